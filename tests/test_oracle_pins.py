@@ -1,0 +1,320 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types the oracle's own formulas: each one compares the oracle
+with a worked example derived by hand, a finite-difference derivative, a
+library least-squares / Cholesky solve of an explicitly formed dense system, a
+closed form of the Neumann partial sum (Proposition 1), the spectral statement
+of Lemma 1, a geometric invariant, or a known zero minimum.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import povar_oracle as O
+from paper_2405_05079_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def tiny(n_cams=5, n_pts=40, seed=7, eta=0.01, track=("uniform", 3, 5), **kw):
+    return synth.make_problem(n_cams, n_pts, track=track, seed=seed, eta=eta, **kw)
+
+
+class _Obs:
+    """A problem with a single observation, for per-observation checks."""
+    def __init__(self, P, X, m, eta):
+        self.n_cams, self.n_pts = 1, 1
+        self.cam_idx = np.zeros(1, np.int32)
+        self.pt_idx = np.zeros(1, np.int32)
+        self.meas = np.asarray(m, float).reshape(1, 2)
+        self.eta = eta
+
+
+# --------------------------------------------------------------------------- residual (6)
+def test_residual_matches_hand_worked_examples():
+    cases = json.load(open(os.path.join(GOLDEN, "pose_residual_worked_example.json")))["cases"]
+    for c in cases:
+        P = np.asarray(c["camera_row_major"], float).reshape(1, 12)
+        X = np.asarray(c["point"], float).reshape(1, 3)
+        p = _Obs(P, X, c["meas"], c["eta"])
+        r = O.pose_residual(P, X, p.cam_idx, p.pt_idx, p.meas, p.eta)[0]
+        np.testing.assert_allclose(r, c["residual"], rtol=1e-14, atol=1e-15)
+        assert abs(O.cost(P, X, p) - c["residual_sq_norm"]) < 1e-12
+
+
+def test_residual_special_cases_eta():
+    """eta = 1: only the affine reprojection error remains; eta = 0: only the OSE rows."""
+    rng = np.random.default_rng(1)
+    P = rng.standard_normal((1, 12)); X = rng.standard_normal((1, 3)); m = rng.standard_normal(2)
+    C = P.reshape(3, 4); xh = np.r_[X[0], 1.0]; y = C @ xh
+    p = _Obs(P, X, m, 1.0)
+    r = O.pose_residual(P, X, p.cam_idx, p.pt_idx, p.meas, 1.0)[0]
+    np.testing.assert_allclose(r, [0, 0, y[0] - m[0], y[1] - m[1]], atol=1e-14)
+    r0 = O.pose_residual(P, X, p.cam_idx, p.pt_idx, p.meas, 0.0)[0]
+    np.testing.assert_allclose(r0, [y[0] - m[0] * y[2], y[1] - m[1] * y[2], 0, 0], atol=1e-14)
+
+
+def test_known_zero_minimum_for_noise_free_affine_cameras():
+    """Affine cameras (third row (0,0,0,1)) and exact measurements: the ground
+    truth is a zero-cost minimum of (6) for every eta, and the closed form (8)
+    recovers the true points."""
+    prob = synth.make_problem(6, 50, track=("uniform", 3, 5), seed=3, sigma=0.0, affine=True)
+    P = prob.cams_gt
+    assert O.cost(P, prob.pts_gt, prob) < 1e-25
+    X, _ = O.solve_landmarks(P, prob)
+    np.testing.assert_allclose(X, prob.pts_gt, atol=1e-10)
+    assert O.reduced_cost(P, prob) < 1e-20
+
+
+# --------------------------------------------------------------------------- Jacobians
+def test_jacobians_match_central_differences():
+    prob = tiny()
+    rng = np.random.default_rng(2)
+    P = rng.standard_normal((prob.n_cams, 12)); X = rng.standard_normal((prob.n_pts, 3))
+    Jp, Jl = O.pose_jacobians(P, X, prob.cam_idx, prob.pt_idx, prob.meas, prob.eta)
+    h = 1e-3   # the residual is affine in every single parameter: central FD is exact
+    res = lambda P_, X_: O.pose_residual(P_, X_, prob.cam_idx, prob.pt_idx, prob.meas, prob.eta)
+    for q in range(12):
+        dP = np.zeros_like(P); dP[:, q] = h
+        fd = (res(P + dP, X) - res(P - dP, X)) / (2 * h)
+        np.testing.assert_allclose(Jp[:, :, q], fd, atol=1e-10)
+    for q in range(3):
+        dX = np.zeros_like(X); dX[:, q] = h
+        fd = (res(P, X + dX) - res(P, X - dX)) / (2 * h)
+        np.testing.assert_allclose(Jl[:, :, q], fd, atol=1e-10)
+
+
+# --------------------------------------------------------------------------- closed form (8)
+def _stacked_landmark_system(P, prob, j):
+    """Rows of the residual of landmark j as an affine map A X - b, found by
+    evaluating the residual at X = 0 and at the unit vectors."""
+    sel = np.nonzero(prob.pt_idx == j)[0]
+    cam, meas = prob.cam_idx[sel], prob.meas[sel]
+    pt = np.zeros(sel.shape[0], np.int32)
+    r = lambda x: O.pose_residual(P, x.reshape(1, 3), cam, pt, meas, prob.eta).ravel()
+    r0 = r(np.zeros(3))
+    A = np.stack([r(e) - r0 for e in np.eye(3)], axis=1)
+    return A, -r0
+
+
+def test_closed_form_landmarks_equal_lstsq_and_zero_gradient():
+    prob = tiny(n_pts=25)
+    P = synth.init_cameras(prob.n_cams, 11)
+    X, _ = O.solve_landmarks(P, prob)
+    for j in range(prob.n_pts):
+        A, b = _stacked_landmark_system(P, prob, j)
+        x_ls = np.linalg.lstsq(A, b, rcond=None)[0]
+        np.testing.assert_allclose(X[j], x_ls, rtol=1e-9, atol=1e-9)
+    lin = O.linearize(P, X, prob)
+    scale = np.abs(lin.V).max() * np.abs(X).max()
+    assert np.abs(lin.bl).max() < 1e-12 * scale
+
+
+def test_singular_landmark_block_gives_minimum_norm_solution():
+    """One observation at m = 0: N = diag(1,1,0) makes V rank 2.  The
+    pseudo-inverse must return the minimum-norm least-squares point."""
+    rng = np.random.default_rng(5)
+    P = rng.standard_normal((1, 12))
+    p = _Obs(P, np.zeros((1, 3)), [0.0, 0.0], 0.01)
+    X, Vp = O.solve_landmarks(P, p)
+    A, b = _stacked_landmark_system(P, p, 0)
+    assert np.linalg.matrix_rank(A) == 2
+    np.testing.assert_allclose(X[0], np.linalg.lstsq(A, b, rcond=None)[0], atol=1e-12)
+    np.testing.assert_allclose(Vp[0], np.linalg.pinv(A.T @ A), atol=1e-10)
+
+
+# --------------------------------------------------------------------------- reduced gradient
+def test_envelope_theorem_reduced_gradient_is_twice_bp():
+    """d f*/d p = 2 J_p^T r at x_l*(p): the landmark term drops out because b_l = 0."""
+    prob = tiny(n_cams=4, n_pts=30)
+    P = synth.init_cameras(prob.n_cams, 12)
+    X, _ = O.solve_landmarks(P, prob)
+    lin = O.linearize(P, X, prob)
+    h = 1e-6
+    for i in range(prob.n_cams):
+        for q in (0, 5, 11):
+            dP = np.zeros_like(P); dP[i, q] = h
+            fd = (O.reduced_cost(P + dP, prob) - O.reduced_cost(P - dP, prob)) / (2 * h)
+            assert abs(fd - 2 * lin.bp[i, q]) <= 1e-6 * max(1.0, abs(fd))
+
+
+# --------------------------------------------------------------------------- dense references
+def _dense_problem(prob, P, lam, manifold="sphere"):
+    """Explicit dense J = [J_p B | J_l] of the whole problem and the damped joint
+    normal equations, built without the oracle's assembly code."""
+    X, _ = O.solve_landmarks(P, prob)
+    Jp, Jl = O.pose_jacobians(P, X, prob.cam_idx, prob.pt_idx, prob.meas, prob.eta)
+    r = O.pose_residual(P, X, prob.cam_idx, prob.pt_idx, prob.meas, prob.eta).ravel()
+    n, nc, npt = prob.n_obs, prob.n_cams, prob.n_pts
+    if manifold == "sphere":
+        Bs = [sla.null_space(P[i][None, :]) for i in range(nc)]       # SVD-based basis
+    else:
+        Bs = [np.eye(12) for _ in range(nc)]
+    k = Bs[0].shape[1]
+    JP = np.zeros((4 * n, k * nc)); JL = np.zeros((4 * n, 3 * npt)); JPa = np.zeros((4 * n, 12 * nc))
+    for o in range(n):
+        i, j = prob.cam_idx[o], prob.pt_idx[o]
+        JPa[4 * o:4 * o + 4, 12 * i:12 * i + 12] = Jp[o]
+        JP[4 * o:4 * o + 4, k * i:k * i + k] = Jp[o] @ Bs[i]
+        JL[4 * o:4 * o + 4, 3 * j:3 * j + 3] = Jl[o]
+    Ua = JPa.T @ JPa
+    damp = np.zeros(12 * nc)
+    for i in range(nc):
+        d = np.diag(Ua)[12 * i:12 * i + 12]
+        damp[12 * i:12 * i + 12] = np.maximum(d, 1e-12 * d.max())
+    Bd = sla.block_diag(*Bs)
+    Ut = JP.T @ JP + lam * Bd.T @ np.diag(damp) @ Bd
+    W = JP.T @ JL
+    V = JL.T @ JL
+    bp, bl = JP.T @ r, JL.T @ r
+    return dict(Ut=Ut, W=W, V=V, bp=bp, bl=bl, Bd=Bd, k=k, JP=JP, JL=JL, r=r)
+
+
+@pytest.mark.parametrize("manifold", ["sphere", "euclidean"])
+def test_series_converges_to_joint_and_schur_cholesky_solves(manifold):
+    prob = tiny(n_cams=4, n_pts=30, seed=21)
+    P = synth.init_cameras(prob.n_cams, 22)
+    lam = 1.0
+    D = _dense_problem(prob, P, lam, manifold)
+    # joint damped system (10) with only the camera block damped, dense least squares
+    K = np.block([[D["Ut"], D["W"]], [D["W"].T, D["V"]]])
+    rhs = -np.r_[D["bp"], D["bl"]]
+    sol = np.linalg.lstsq(K, rhs, rcond=None)[0]
+    dx_joint = D["Bd"] @ sol[:D["Ut"].shape[0]]
+    # explicit Schur complement (14)-(15) solved by Cholesky
+    Vp = np.linalg.pinv(D["V"], rcond=1e-12, hermitian=True)
+    S = D["Ut"] - D["W"] @ Vp @ D["W"].T
+    rhs_s = -(D["bp"] - D["W"] @ Vp @ D["bl"])
+    c = sla.cho_factor(S)
+    dx_schur = D["Bd"] @ sla.cho_solve(c, rhs_s)
+    np.testing.assert_allclose(dx_schur, dx_joint, rtol=1e-8, atol=1e-10)
+    # oracle: series of high order
+    X, _ = O.solve_landmarks(P, prob)
+    lin = O.linearize(P, X, prob)
+    dP = O.camera_step(P, lin, lam, order=600, manifold=manifold)
+    np.testing.assert_allclose(dP.ravel(), dx_schur, rtol=1e-7, atol=1e-9 * np.abs(dx_schur).max())
+
+
+def test_series_partial_sums_match_neumann_closed_form_and_bound():
+    """Proposition 1 with M = U~^-1 W~ V^+ W~^T: the order-m sum equals
+    -(I - M^{m+1}) (I - M)^-1 U~^-1 g, and its U~-norm error is bounded by
+    mu_max^{m+1} ||x*||_U (Lemma 1: M is U~-self-adjoint with spectrum in [0,1))."""
+    prob = tiny(n_cams=4, n_pts=30, seed=31)
+    P = synth.init_cameras(prob.n_cams, 32)
+    lam = 0.3
+    D = _dense_problem(prob, P, lam)
+    Ut, W, V = D["Ut"], D["W"], D["V"]
+    Vp = np.linalg.pinv(V, rcond=1e-12, hermitian=True)
+    M = np.linalg.solve(Ut, W @ Vp @ W.T)
+    g = D["bp"] - W @ Vp @ D["bl"]
+    u0 = np.linalg.solve(Ut, g)
+    I = np.eye(M.shape[0])
+    x_star = -np.linalg.solve(I - M, u0)
+    mu = np.linalg.eigvals(M).real.max()
+    X, _ = O.solve_landmarks(P, prob)
+    lin = O.linearize(P, X, prob)
+    unorm = lambda v: np.sqrt(v @ Ut @ v)
+    q_prev = np.inf
+    for m in (0, 1, 2, 5, 10, 30):
+        closed = -(I - np.linalg.matrix_power(M, m + 1)) @ np.linalg.solve(I - M, u0)
+        dP = O.camera_step(P, lin, lam, order=m).ravel()
+        np.testing.assert_allclose(dP, D["Bd"] @ closed, rtol=1e-8, atol=1e-12 * np.abs(closed).max())
+        assert unorm(closed - x_star) <= mu ** (m + 1) * unorm(x_star) * (1 + 1e-9)
+        # the quadratic model g^T x + x^T S x / 2 never increases with the order
+        S = Ut - W @ Vp @ W.T
+        q = g @ closed + 0.5 * closed @ S @ closed
+        assert q <= q_prev + 1e-12 * abs(q)
+        q_prev = q
+
+
+@pytest.mark.parametrize("manifold,lam", [("sphere", 1e-4), ("sphere", 1.0), ("euclidean", 1e-2)])
+def test_lemma1_spectrum_in_unit_interval(manifold, lam):
+    prob = tiny(n_cams=5, n_pts=40, seed=41)
+    P = synth.init_cameras(prob.n_cams, 42)
+    D = _dense_problem(prob, P, lam, manifold)
+    Vp = np.linalg.pinv(D["V"], rcond=1e-12, hermitian=True)
+    M = np.linalg.solve(D["Ut"], D["W"] @ Vp @ D["W"].T)
+    ev = np.linalg.eigvals(M)
+    assert np.abs(ev.imag).max() < 1e-8
+    assert ev.real.min() > -1e-10 and ev.real.max() < 1.0
+
+
+# --------------------------------------------------------------------------- tangent space
+def test_update_is_tangent_and_retraction_normalises():
+    prob = tiny(seed=51)
+    P = synth.init_cameras(prob.n_cams, 52)
+    X, _ = O.solve_landmarks(P, prob)
+    lin = O.linearize(P, X, prob)
+    dP = O.camera_step(P, lin, 1e-3, order=10)
+    assert np.abs(np.sum(P * dP, axis=1)).max() < 1e-12 * np.abs(dP).max()
+    Pn = O.retract(P, dP)
+    np.testing.assert_allclose(np.linalg.norm(Pn, axis=1), 1.0, atol=1e-14)
+    # |p + dp|^2 = 1 + |dp|^2 because dp is orthogonal to the unit vector p
+    np.testing.assert_allclose(np.linalg.norm(P + dP, axis=1) ** 2,
+                               1 + np.linalg.norm(dP, axis=1) ** 2, rtol=1e-12)
+
+
+def test_update_does_not_depend_on_the_tangent_basis(monkeypatch):
+    prob = tiny(seed=61)
+    P = synth.init_cameras(prob.n_cams, 62)
+    X, _ = O.solve_landmarks(P, prob)
+    lin = O.linearize(P, X, prob)
+    ref = O.camera_step(P, lin, 1e-2, order=7)
+    rng = np.random.default_rng(63)
+    Q = np.linalg.qr(rng.standard_normal((prob.n_cams, 11, 11)))[0]
+    orig = O.tangent_basis
+    monkeypatch.setattr(O, "tangent_basis", lambda P_: orig(P_) @ Q)
+    alt = O.camera_step(P, lin, 1e-2, order=7)
+    np.testing.assert_allclose(alt, ref, rtol=1e-10, atol=1e-13)
+
+
+# --------------------------------------------------------------------------- gauge invariance
+def test_reduced_cost_is_invariant_under_affine_gauge():
+    """P_i -> P_i H with H = [[A, t], [0, 1]] keeps the last landmark coordinate
+    at 1 (x~ -> H^-1 x~), so f* cannot change (Euclidean form)."""
+    prob = tiny(seed=71)
+    P = synth.init_cameras(prob.n_cams, 72)
+    rng = np.random.default_rng(73)
+    H = np.eye(4); H[:3, :3] = rng.standard_normal((3, 3)) + 2 * np.eye(3); H[:3, 3] = rng.standard_normal(3)
+    PH = (P.reshape(-1, 3, 4) @ H).reshape(-1, 12)
+    f0, f1 = O.reduced_cost(P, prob), O.reduced_cost(PH, prob)
+    assert abs(f1 - f0) <= 1e-10 * f0
+    # an orthogonal A keeps every camera on the unit sphere as well
+    R = np.linalg.qr(rng.standard_normal((3, 3)))[0]
+    G = np.eye(4); G[:3, :3] = R
+    PR = (P.reshape(-1, 3, 4) @ G).reshape(-1, 12)
+    np.testing.assert_allclose(np.linalg.norm(PR, axis=1), 1.0, atol=1e-14)
+    assert abs(O.reduced_cost(PR, prob) - f0) <= 1e-12 * f0
+
+
+# --------------------------------------------------------------------------- LM loop
+def test_lm_loop_accepts_only_decreases_and_updates_lambda():
+    prob = synth.workload(1)
+    res = O.lm_solve(prob, opts=O.Options(order=10, max_iters=25, ftol=0.0))
+    f = res.cost0
+    lam = 1e-4
+    for fc, acc, lu in zip(res.trace_cost, res.trace_accept, res.trace_lambda):
+        assert lu == pytest.approx(lam, rel=1e-12)
+        assert acc == (fc < f)
+        if acc:
+            f = fc
+            lam = max(lam / 10, 1e-12)
+        else:
+            lam = min(lam * 10, 1e12)
+    assert res.cost == f
+    assert res.cost < 0.05 * res.cost0
+
+
+def test_lm_reaches_known_zero_minimum_on_noise_free_affine_problem():
+    """From random cameras the Euclidean (paper-literal) update reaches the known
+    zero minimum of exact affine data — a check of the whole loop.  On the unit
+    sphere pOSE is not scale invariant (its affine term is not), so the zero-cost
+    cameras are not on the constraint set; there the check is a large decrease."""
+    prob = synth.make_problem(8, 200, track=("uniform", 4, 6), seed=81, sigma=0.0, affine=True)
+    res = O.lm_solve(prob, opts=O.Options(order=20, max_iters=50, ftol=0.0, manifold="euclidean"))
+    assert res.cost < 1e-12 * res.cost0
+    res = O.lm_solve(prob, opts=O.Options(order=20, max_iters=50, ftol=0.0, manifold="sphere"))
+    assert res.cost < 1e-3 * res.cost0
