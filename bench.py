@@ -1,0 +1,197 @@
+"""Benchmark: PoVar outer iterations per second on one MI355X.
+
+A step is one PoVar outer iteration (linearisation after an accept, damping
+and tangent projection, the order-m power series, retraction, closed-form
+landmark re-solve, LM decision) on the mid-size synthetic workload: 250
+cameras, 60,000 points, ~300k observations, eta = 0.01, series order 20,
+FP32-bulk precision (FP32 Jacobians and series, FP64 landmark blocks, camera
+factorisation and cost).  The line also carries the plain FP64 GPU path on the
+same problem, the matched-final-cost comparison, the roofline of the dominant
+series kernel and the FP64 CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2405_05079_amd import povar, synth  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = 2
+
+
+_hip = None
+
+
+def device_sync():
+    """hipDeviceSynchronize (what torch.cuda.synchronize calls), without
+    paying for a torch import."""
+    global _hip
+    if _hip is None:
+        import ctypes
+        _hip = ctypes.CDLL("libamdhip64.so")
+    rc = _hip.hipDeviceSynchronize()
+    if rc != 0:
+        raise RuntimeError(f"hipDeviceSynchronize failed: {rc}")
+
+
+def series_bytes(n_obs: int, n_l: int, n_p: int, fp32: bool):
+    """Algorithmic bytes of one launch of each series kernel (compulsory
+    traffic: every input read once, every output written once).
+    landmark pass: per observation the camera index (4 B) and the measurement
+      (8 B FP32); per landmark x~_j (12 B), V_j^+ (24 B) and z_j written (12 B);
+      per camera x_i (48 B) and Pbar_i (36 B);
+    camera pass: per observation the landmark index (4 B) and the measurement
+      (8 B); per landmark z_j (12 B) and x~_j (12 B); per camera the 12x12
+      K_i (576 B), Pbar_i (36 B), x_i written (48 B), acc_i read+written (96 B).
+    FP64 doubles every floating-point figure."""
+    s = 1 if fp32 else 2
+    lpass = (4 + 8 * s) * n_obs + 48 * s * n_l + 84 * s * n_p
+    cpass = (4 + 8 * s) * n_obs + 24 * s * n_l + 756 * s * n_p
+    return lpass, cpass
+
+
+def timed_iters(gp, steps: int) -> float:
+    gp.report()
+    device_sync()
+    t0 = time.perf_counter()
+    gp.enqueue(steps)
+    gp.report()          # synchronises the library stream
+    device_sync()
+    return time.perf_counter() - t0
+
+
+def matched_cost(ctx, prob, ref_cost: float, max_iters: int):
+    """Iterations and seconds for FP32-bulk to first reach ref_cost (1 + 1e-6)."""
+    gp = povar.Problem.from_synth(ctx, prob, precision="fp32_bulk", ftol=0.0, max_iters=max_iters)
+    t0 = time.perf_counter()
+    gp.step(max_iters)
+    secs = time.perf_counter() - t0
+    cost, _, acc = gp.trace()
+    best = np.minimum.accumulate(np.where(acc, cost, np.inf))
+    hit = np.nonzero(best <= ref_cost * (1 + 1e-6))[0]
+    it = int(hit[0]) + 1 if hit.size else None
+    out = dict(fp32_cost_at_ref_iters=float(best[min(len(best), prob.iters) - 1]),
+               fp32_iters_to_match=it,
+               fp32_seconds_to_match=(secs * it / max_iters) if it else None)
+    gp.close()
+    return out
+
+
+def cpu_baseline(prob, iters: int):
+    from threadpoolctl import threadpool_limits
+
+    from oracle import povar_oracle as O
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        O.lm_solve(prob, opts=O.Options(order=prob.order, max_iters=iters, ftol=0.0))
+        secs = time.perf_counter() - t0
+    return {"value": iters / secs, "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} LM iterations of the FP64 oracle on the same {prob.n_cams}-camera problem "
+                      f"(incl. its initial landmark solve), {secs:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-matched", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    prob = synth.workload(WORKLOAD)
+    print(f"[bench] workload {prob.name}: {prob.n_cams} cameras, {prob.n_pts} points, "
+          f"{prob.n_obs} observations, order {prob.order}", file=sys.stderr, flush=True)
+    ctx = povar.Context(0)
+    res = {}
+    for prec in ("fp32_bulk", "fp64"):
+        gp = povar.Problem.from_synth(ctx, prob, precision=prec, ftol=0.0, max_iters=10 ** 6)
+        gp.step(args.warmup)
+        secs = timed_iters(gp, args.steps)
+        rep = gp.report()
+        # per-kernel durations of the series passes, HIP events on the library stream
+        gp.kernel_timing(True)
+        gp.step(max(5, args.steps // 10))
+        kt = gp.kernel_times()
+        gp.kernel_timing(False)
+        info = gp.info()
+        res[prec] = dict(secs=secs, iters_per_s=args.steps / secs, rep=rep, kt=kt, info=info)
+        print(f"[bench] {prec}: {args.steps / secs:.1f} iters/s, cost {rep['cost_final']:.6g}",
+              file=sys.stderr, flush=True)
+        gp.close()
+
+    fp32 = res["fp32_bulk"]
+    kt = fp32["kt"]
+    ms_l = kt["ms_landmark_pass"] / max(1, kt["n_landmark_pass"])
+    ms_c = kt["ms_camera_pass"] / max(1, kt["n_camera_pass"])
+    bl, bc = series_bytes(prob.n_obs, prob.n_pts, prob.n_cams, True)
+    if ms_l >= ms_c:
+        name, ms, byt = "k_series_landmark<float>", ms_l, bl
+    else:
+        name, ms, byt = "k_series_camera<float>", ms_c, bc
+    achieved = byt / (ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                "avg_us": round(ms * 1e3, 3), "bytes_per_launch": int(byt),
+                "series_pair_us": round((ms_l + ms_c) * 1e3, 3)}
+
+    out = {
+        "metric": "VarPro iters/s FP32-bulk vs FP64 at matched final cost; p50/p99 solve latency",
+        "value": round(fp32["iters_per_s"], 2),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * fp32["secs"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded; shapes of the paper's BAL workloads)",
+        "config": {"workload": f"{prob.name}: {prob.n_cams} cameras, {prob.n_pts} points, "
+                               f"{prob.n_obs} observations, eta {prob.eta}, series order {prob.order}, "
+                               "FP32-bulk with FP64 V_j / U_i / cost",
+                   "precision": "fp32_bulk"},
+        "fp64_iters_per_s": round(res["fp64"]["iters_per_s"], 2),
+        "fp32_over_fp64": round(fp32["iters_per_s"] / res["fp64"]["iters_per_s"], 3),
+        "roofline": roofline,
+    }
+    if not args.no_matched:
+        # reference: the FP64 GPU path after the workload's iteration count
+        g64 = povar.Problem.from_synth(ctx, prob, precision="fp64", ftol=0.0, max_iters=prob.iters)
+        r64 = g64.solve()
+        g64.close()
+        m = matched_cost(ctx, prob, r64["cost_final"], 2 * prob.iters)
+        m["fp64_cost_final"] = r64["cost_final"]
+        m["ref_iters"] = prob.iters
+        golden = os.path.join(ROOT, "tests", "golden", "oracle_costs.json")
+        if os.path.exists(golden):
+            g = json.load(open(golden)).get(str(WORKLOAD))
+            if g:
+                m["oracle_cost_final"] = g["cost_final"]
+                m["fp64_rel_vs_oracle"] = abs(r64["cost_final"] - g["cost_final"]) / g["cost_final"]
+        out["matched_cost"] = m
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_iters)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

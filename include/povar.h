@@ -1,0 +1,229 @@
+/*
+ * povar.h — C ABI of the PoVar (Power Variable Projection) bundle-adjustment
+ * hot path for AMD Instinct MI355X (gfx950).
+ *
+ * A problem is a set of observations (camera i, point j, 2-D measurement m_ij)
+ * of n_cams projective 3x4 cameras and n_pts points (Sec. 3.2 of the paper).
+ * The library minimises the pOSE objective, Eq. (6),
+ *
+ *   F(P, X) = sum_ij || ( sqrt(1-eta) (P_i^{1:2} x~_j - (P_i^3 x~_j) m_ij) ;
+ *                         sqrt(eta)   (P_i^{1:2} x~_j - m_ij) ) ||^2 ,
+ *   x~_j = (X_j, 1),
+ *
+ * by Variable Projection (Sec. 4.1): every landmark is eliminated in closed
+ * form, Eq. (8); each outer iteration linearises the reduced problem (9) with
+ * the RW2 normal equations (10)-(13), approximates the inverse of the Schur
+ * complement (14)-(15) by the truncated power series (17), takes the camera
+ * update in the tangent space of each camera's unit sphere in R^12 (Sec. 4.3,
+ * (18)-(29)), retracts by normalisation, re-solves the landmarks and accepts
+ * or rejects the step with a Levenberg-Marquardt damping schedule (Sec. 5.2).
+ *
+ * Conventions shared by every call:
+ *  - Every call returns povar_status; 0 (POVAR_OK) is success.  No C++
+ *    exception crosses this boundary.  On failure, povar_last_error(ctx)
+ *    returns a message for the last failing call made on that context.
+ *  - Cameras are row-major 3x4 matrices stored as 12 doubles (p_i), points are
+ *    3 doubles, measurements are 2 doubles, all contiguous and unpadded.
+ *  - Unless a name ends in _device, pointer arguments are HOST pointers.  The
+ *    library copies inputs; the caller keeps ownership of every buffer it
+ *    passes and may free it when the call returns.  Outputs are written into
+ *    caller buffers of the documented size.
+ *  - All device work of a context runs on the HIP stream given to
+ *    povar_ctx_create (NULL = a stream the library creates).  Calls that
+ *    return results to host memory synchronise that stream.
+ *  - A context and the problems created from it are used from one host
+ *    thread at a time.  The server (povar_server_*) is thread-safe.
+ */
+#ifndef POVAR_H
+#define POVAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  POVAR_OK = 0,
+  POVAR_EINVAL = 1,   /* invalid argument (sizes, indices, non-finite values, options) */
+  POVAR_ENOMEM = 2,   /* device allocation failed, or request exceeds a server budget */
+  POVAR_EDEVICE = 3,  /* a HIP runtime error */
+  POVAR_EAGAIN = 4,   /* result not ready yet (server poll) */
+  POVAR_ENUMERIC = 5, /* non-finite cost, or a camera block that is not positive definite */
+  POVAR_ESTATE = 6    /* call not valid in the object's current state */
+} povar_status;
+
+typedef enum {
+  /* every step of the path in FP64 */
+  POVAR_PREC_FP64 = 0,
+  /* Jacobian evaluation and power-series matvecs in FP32 with FP32
+     accumulation; V_j inversion, U_i factorisation and the cost in FP64.
+     U_i and b_p are FP32 products accumulated in FP64. */
+  POVAR_PREC_FP32_BULK = 1
+} povar_precision;
+
+typedef enum {
+  /* camera update in the tangent space of the unit sphere of R^12, then
+     retraction by normalisation (Sec. 4.3) */
+  POVAR_MANIFOLD_SPHERE = 0,
+  /* paper-literal Euclidean camera update of Sec. 4.1-4.2 (no projection) */
+  POVAR_MANIFOLD_EUCLIDEAN = 1
+} povar_manifold;
+
+typedef struct {
+  uint32_t struct_size;  /* = sizeof(povar_options); checked */
+  double eta;            /* pOSE weight in [0,1], Eq. (6); default 0.01 */
+  int32_t series_order;  /* m of Eq. (17): terms i = 0..m; >= 0; default 20 */
+  int32_t max_iters;     /* LM iterations for povar_solve; default 50 */
+  double ftol;           /* stop when an accepted step decreases the cost by
+                            less than ftol relative; 0 disables; default 1e-6 */
+  double lambda0;        /* initial damping (Sec. 5.2); default 1e-4 */
+  double lambda_min;     /* damping bounds; defaults 1e-12, 1e12 */
+  double lambda_max;
+  int32_t precision;     /* povar_precision; default POVAR_PREC_FP64 */
+  int32_t manifold;      /* povar_manifold; default POVAR_MANIFOLD_SPHERE */
+  int32_t use_graph;     /* 1: replay each iteration as a captured HIP graph
+                            (default); 0: launch kernels one by one */
+  int32_t reserved;
+} povar_options;
+
+typedef struct {
+  double cost_initial;   /* f* at the initial cameras */
+  double cost_final;     /* f* at the current cameras */
+  double lambda_final;
+  double seconds;        /* wall time of the call */
+  int32_t iters;         /* LM iterations taken so far (rejected ones count) */
+  int32_t accepted;      /* accepted iterations so far */
+  int32_t stop_reason;   /* 0 running / max_iters, 1 ftol reached */
+  int32_t reserved;
+} povar_report;
+
+typedef struct povar_ctx_s* povar_ctx;
+typedef struct povar_problem_s* povar_problem;
+typedef struct povar_server_s* povar_server;
+
+/* Fill *opts with the defaults listed above. */
+povar_status povar_options_default(povar_options* opts);
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+   (e.g. torch.cuda.current_stream().cuda_stream) or NULL for a private one. */
+povar_status povar_ctx_create(int device, void* hip_stream, povar_ctx* out);
+/* POVAR_ESTATE while problems created on ctx are still alive. */
+povar_status povar_ctx_destroy(povar_ctx ctx);
+/* Message of the last failing call on ctx (never NULL; "" if none).  With
+   ctx == NULL: the last failure of a call that had no context. */
+const char* povar_last_error(povar_ctx ctx);
+
+/* Device bytes a problem of this size needs (all precisions' buffers that
+   the chosen precision uses, plus the layout).  Used for server admission. */
+povar_status povar_problem_footprint(int32_t n_cams, int32_t n_pts, int64_t n_obs,
+                                     int32_t precision, uint64_t* bytes);
+
+/* Create a problem from observations (Sec. 3.2): cam_idx[k] in [0,n_cams),
+   pt_idx[k] in [0,n_pts), meas[2k..2k+1] finite.  Every camera and every
+   point needs at least one observation.  cams0 (n_cams x 12, required) is the
+   initial camera set; on the sphere manifold each camera is normalised to
+   unit norm.  The landmarks are then solved in closed form (8) and the
+   initial cost is evaluated (POVAR_ENUMERIC if it is not finite).
+   Errors: POVAR_EINVAL for any violated precondition, POVAR_ENOMEM,
+   POVAR_EDEVICE. */
+povar_status povar_problem_create(povar_ctx ctx, int32_t n_cams, int32_t n_pts, int64_t n_obs,
+                                  const int32_t* cam_idx, const int32_t* pt_idx,
+                                  const double* meas, const double* cams0,
+                                  const povar_options* opts, povar_problem* out);
+/* Same, with cam_idx, pt_idx, meas and cams0 in device memory of ctx's
+   device (e.g. torch tensors). */
+povar_status povar_problem_create_device(povar_ctx ctx, int32_t n_cams, int32_t n_pts, int64_t n_obs,
+                                         const int32_t* cam_idx, const int32_t* pt_idx,
+                                         const double* meas, const double* cams0,
+                                         const povar_options* opts, povar_problem* out);
+povar_status povar_problem_destroy(povar_problem pb);
+
+/* Run LM iterations until opts.max_iters iterations in total or ftol. */
+povar_status povar_solve(povar_problem pb, povar_report* report);
+/* Run up to n_iters more iterations (fewer if ftol stops the solve). */
+povar_status povar_step(povar_problem pb, int32_t n_iters, povar_report* report);
+/* Enqueue n_iters iterations on the context stream without waiting and
+   without reading anything back (for timing loops); povar_step/povar_report
+   read the state afterwards. */
+povar_status povar_enqueue(povar_problem pb, int32_t n_iters);
+/* Current report (synchronises). */
+povar_status povar_get_report(povar_problem pb, povar_report* report);
+
+/* Current cameras (n_cams x 12) and points (n_pts x 3, caller's point order). */
+povar_status povar_get_cameras(povar_problem pb, double* cams_out);
+povar_status povar_get_points(povar_problem pb, double* pts_out);
+/* Per-iteration trace: trial cost, damping used, accepted flag, for the
+   first min(n, iters) iterations.  Any output pointer may be NULL. */
+povar_status povar_get_trace(povar_problem pb, int32_t n, double* trial_cost,
+                             double* lambda_used, int32_t* accepted);
+
+/* Checkpoint / resume: the state is (cameras, lambda, iteration count); the
+   landmarks follow from the cameras by (8).  set_state re-solves them,
+   re-evaluates the cost and forces a fresh linearisation.  On the sphere it
+   normalises cameras whose squared norm differs from 1 by more than 1e-14
+   and takes the others bit-exactly, so a state read by povar_get_state
+   resumes bit-exactly. */
+povar_status povar_get_state(povar_problem pb, double* cams_out, double* lambda_out,
+                             int32_t* iter_out, double* cost_out);
+povar_status povar_set_state(povar_problem pb, const double* cams, double lambda, int32_t iter);
+
+/* ---- per-step hooks for parity tests ------------------------------------ */
+/* Linearisation at the current cameras (Eq. (10)-(13)): U (n_cams x 144,
+   row-major 12x12), b_p (n_cams x 12), g = b_p - W V^+ b_l (n_cams x 12),
+   V^+ (n_pts x 9), X (n_pts x 3), z0 = V^+ b_l (n_pts x 3), and the cost.
+   Points in the caller's order.  Any output pointer may be NULL. */
+povar_status povar_debug_linearize(povar_problem pb, double* U, double* bp, double* g,
+                                   double* Vpinv, double* X, double* z0, double* cost);
+/* One camera step at the current linearisation with damping `lambda` and
+   series order `order`, without changing the solver state: dp (n_cams x 12)
+   is the ambient update (tangent on the sphere), p_trial the retracted
+   cameras, cost_trial the cost after re-solving the landmarks there. */
+povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, double* dp,
+                              double* p_trial, double* cost_trial);
+
+/* ---- kernel timing for roofline reports --------------------------------- */
+/* enable != 0: subsequent povar_step / povar_enqueue launches bracket every
+   series kernel with HIP events on the context stream (graph replay is
+   bypassed while enabled).  povar_kernel_times returns the summed durations
+   (ms) and launch counts of the two series kernels since timing was enabled
+   and resets them. */
+povar_status povar_kernel_timing(povar_problem pb, int32_t enable);
+povar_status povar_kernel_times(povar_problem pb, double* ms_landmark_pass, int64_t* n_landmark_pass,
+                                double* ms_camera_pass, int64_t* n_camera_pass);
+/* Problem shape after layout: entries of the landmark-major slice layout
+   (observations + padding), number of camera chunks. */
+povar_status povar_problem_info(povar_problem pb, int64_t* n_obs, int64_t* slice_entries,
+                                int32_t* n_chunks, uint64_t* device_bytes);
+
+/* ---- serving: continuous batching of many problems on one GPU ----------- */
+/* A server owns a worker thread and the device state of up to max_slots
+   problems whose summed footprint stays within hbm_budget_bytes.  Requests
+   wait in a FIFO queue until a slot and enough budget are free; admitted
+   problems advance together, one LM iteration per batched launch sequence,
+   and new requests join at the next iteration boundary.  Each result is
+   independent of which other problems shared the launches. */
+povar_status povar_server_create(povar_ctx ctx, uint64_t hbm_budget_bytes, int32_t max_slots,
+                                 povar_server* out);
+/* Copies the request; *ticket identifies it.  POVAR_ENOMEM if the request
+   alone exceeds the budget; POVAR_EINVAL as for povar_problem_create. */
+povar_status povar_server_submit(povar_server sv, int32_t n_cams, int32_t n_pts, int64_t n_obs,
+                                 const int32_t* cam_idx, const int32_t* pt_idx, const double* meas,
+                                 const double* cams0, const povar_options* opts, uint64_t* ticket);
+/* POVAR_EAGAIN until the request has finished; then fills the report, the
+   cameras (n_cams x 12) and points (n_pts x 3) if non-NULL, and releases the
+   ticket.  Timestamps (seconds since server creation) of submit, admission
+   and completion go to times[0..2] if times is non-NULL. */
+povar_status povar_server_poll(povar_server sv, uint64_t ticket, povar_report* report,
+                               double* cams_out, double* pts_out, double* times);
+/* Statistics: requests queued, active, finished; batched iterations run. */
+povar_status povar_server_stats(povar_server sv, int32_t* queued, int32_t* active,
+                                int64_t* finished, int64_t* batch_iters);
+/* Waits for the worker to drain nothing: pending requests are dropped. */
+povar_status povar_server_destroy(povar_server sv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POVAR_H */

@@ -1,0 +1,97 @@
+// Host-side objects of the PoVar library (context, problem, layout).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "povar.h"
+#include "povar_internal.h"
+
+struct povar_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::mutex err_mu;
+  std::string err, err_copy;
+  int live_problems = 0;   // problems created on this context and not destroyed
+};
+
+namespace povar {
+
+// Host image of the observation layout (see DevProblem for the meaning).
+struct HostLayout {
+  int32_t n_p = 0, n_l = 0;
+  int64_t n_obs = 0, n_ent = 0;
+  int32_t n_sl = 0, n_ch = 0;
+  std::vector<int32_t> int2ext;        // internal landmark -> caller's index
+  std::vector<int32_t> sl_off, sl_len, e_cam;
+  std::vector<float> e_m32;
+  std::vector<double> e_m64;
+  std::vector<int32_t> cm_lm;
+  std::vector<float> cm_m32;
+  std::vector<double> cm_m64;
+  std::vector<int32_t> ch_beg, ch_cam, cam_ch;
+};
+
+// Byte offsets of every buffer inside a problem's device arena
+// (SIZE_MAX = not allocated for this precision).
+struct ArenaOffsets {
+  size_t sl_off, sl_len, e_cam, e_m32, e_m64, cm_lm, cm_m32, cm_m64, ch_beg, ch_cam, cam_ch;
+  size_t P64[2], P32[2], X64[2], Vp64[2], z064[2], X32[2], Vp32[2], z032[2];
+  size_t U40, bp, wz, lin_part, K64, K32, x, acc, z, t_part, cam_cnt, cost_part, cost_cnt, ctl;
+  size_t tr_cost, tr_lambda, tr_acc, rec, tables;
+};
+
+size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_ent, int64_t n_sl, int64_t n_ch,
+                   bool fp32, int64_t trace_cap, ArenaOffsets* o);
+povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs, const int32_t* cam,
+                          const int32_t* pt, const double* meas, bool fp32, HostLayout& L);
+povar_status check_options(povar_ctx ctx, const povar_options* o);
+void set_error(povar_ctx ctx, const char* fmt, ...);
+
+struct TimedPair {
+  hipEvent_t start, stop;
+  int kind;   // 0 landmark pass, 1 camera pass
+};
+
+}  // namespace povar
+
+struct povar_problem_s {
+  povar_ctx ctx = nullptr;
+  bool owned_by_ctx = false;   // counted in ctx->live_problems
+  povar_options opt{};
+  bool fp32 = false;
+  hipStream_t stream = nullptr;
+  int trace_cap = 0;
+  povar::HostLayout L;
+  povar::ArenaOffsets off{};
+  size_t bytes = 0;
+  void* arena = nullptr;
+  povar::DevProblem rec{};    // host copy of the device record
+  povar::Batch batch{};       // batch of one
+  hipGraphExec_t graph_exec = nullptr;
+  bool graph_failed = false;
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  size_t event_next = 0;
+  std::vector<povar::TimedPair> pending;
+  double ms_kernel[2] = {0.0, 0.0};
+  int64_t n_kernel[2] = {0, 0};
+
+  hipEvent_t event_pool_get();
+  hipError_t drain_timing();
+};
+
+namespace povar {
+povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, const povar_options* o,
+                          hipStream_t stream, povar_problem_s* pb);
+hipError_t read_ctl(povar_problem_s* pb, Ctl* out);
+hipError_t write_ctl(povar_problem_s* pb, const Ctl* in);
+hipError_t enqueue_iteration(povar_problem_s* pb, bool timed);
+hipError_t enqueue_iterations(povar_problem_s* pb, int n);
+void fill_report(const povar_problem_s* pb, const Ctl& c, double seconds, povar_report* r);
+}  // namespace povar

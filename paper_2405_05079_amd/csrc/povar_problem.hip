@@ -1,0 +1,1029 @@
+// Host side of the PoVar library: validation, observation layout, device
+// state, the LM driver (device-side decisions, graph replay) and the per-step
+// hooks.  Implements the single-problem part of include/povar.h; the server
+// lives in povar_server.hip.
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "povar.h"
+#include "povar_host.h"
+
+namespace povar {
+
+thread_local std::string g_noctx_error;
+
+void set_error(povar_ctx ctx, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (ctx) {
+    std::lock_guard<std::mutex> g(ctx->err_mu);
+    ctx->err = buf;
+  } else {
+    g_noctx_error = buf;
+  }
+}
+
+static inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Byte plan of one problem's device arena.  Used both to allocate and to
+// answer povar_problem_footprint, so admission accounting matches exactly.
+struct ArenaPlan {
+  size_t total = 0;
+  size_t take(size_t bytes) {
+    const size_t off = total;
+    total += align_up(bytes);
+    return off;
+  }
+};
+
+size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_ent, int64_t n_sl, int64_t n_ch,
+                   bool fp32, int64_t trace_cap, ArenaOffsets* o) {
+  ArenaPlan a;
+  ArenaOffsets tmp;
+  ArenaOffsets& r = o ? *o : tmp;
+  const size_t ts = fp32 ? 4 : 8;
+  r.sl_off = a.take((n_sl + 1) * 4);
+  r.sl_len = a.take(n_sl * 4);
+  r.e_cam = a.take(n_ent * 4);
+  r.e_m32 = fp32 ? a.take(n_ent * 8) : SIZE_MAX;
+  r.e_m64 = a.take(n_ent * 16);
+  r.cm_lm = a.take(n_obs * 4);
+  r.cm_m32 = fp32 ? a.take(n_obs * 8) : SIZE_MAX;
+  r.cm_m64 = fp32 ? SIZE_MAX : a.take(n_obs * 16);
+  r.ch_beg = a.take((n_ch + 1) * 4);
+  r.ch_cam = a.take(n_ch * 4);
+  r.cam_ch = a.take((n_p + 1) * 4);
+  for (int b = 0; b < 2; ++b) {
+    r.P64[b] = a.take(n_p * kCam * 8);
+    r.P32[b] = a.take(n_p * kCam * 4);
+    r.X64[b] = a.take(n_l * kLmVec * 8);
+    r.Vp64[b] = a.take(n_l * kLmSym * 8);
+    r.z064[b] = a.take(n_l * kLmVec * 8);
+    r.X32[b] = a.take(n_l * kLmVec * 4);
+    r.Vp32[b] = a.take(n_l * kLmSym * 4);
+    r.z032[b] = a.take(n_l * kLmVec * 4);
+  }
+  r.U40 = a.take(n_p * 40 * 8);
+  r.bp = a.take(n_p * kCam * 8);
+  r.wz = a.take(n_p * kCam * 8);
+  r.lin_part = a.take(n_ch * kLinVals * 8);
+  r.K64 = a.take(n_p * kCamMat * 8);
+  r.K32 = a.take(n_p * kCamMat * 4);
+  r.x = a.take(n_p * kCam * ts);
+  r.acc = a.take(n_p * kCam * ts);
+  r.z = a.take(n_l * kLmVec * ts);
+  r.t_part = a.take(n_ch * kCam * ts);
+  r.cam_cnt = a.take(n_p * 4);
+  r.cost_part = a.take(n_sl * 8);
+  r.cost_cnt = a.take(4);
+  r.ctl = a.take(sizeof(Ctl));
+  r.tr_cost = a.take(trace_cap * 8);
+  r.tr_lambda = a.take(trace_cap * 8);
+  r.tr_acc = a.take(trace_cap * 4);
+  r.rec = a.take(sizeof(DevProblem));
+  r.tables = a.take(kNumUnitKinds * 2 * 4);
+  return a.total;
+}
+
+// ------------------------------------------------------------------ layout
+povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs, const int32_t* cam,
+                          const int32_t* pt, const double* meas, bool fp32, HostLayout& L) {
+  if (n_p <= 0 || n_l <= 0 || n_obs <= 0) {
+    set_error(ctx, "n_cams, n_pts and n_obs must be positive (got %d, %d, %lld)", n_p, n_l, (long long)n_obs);
+    return POVAR_EINVAL;
+  }
+  if (n_obs >= (int64_t)INT_MAX / 2) {
+    set_error(ctx, "n_obs = %lld exceeds the supported maximum", (long long)n_obs);
+    return POVAR_EINVAL;
+  }
+  if (!cam || !pt || !meas) {
+    set_error(ctx, "cam_idx, pt_idx and meas must not be NULL");
+    return POVAR_EINVAL;
+  }
+  L.n_p = n_p;
+  L.n_l = n_l;
+  L.n_obs = n_obs;
+  std::vector<int32_t> cnt_l(n_l, 0), cnt_c(n_p, 0);
+  for (int64_t k = 0; k < n_obs; ++k) {
+    const int32_t c = cam[k], j = pt[k];
+    if (c < 0 || c >= n_p || j < 0 || j >= n_l) {
+      set_error(ctx, "observation %lld has camera %d / point %d out of range", (long long)k, c, j);
+      return POVAR_EINVAL;
+    }
+    if (!std::isfinite(meas[2 * k]) || !std::isfinite(meas[2 * k + 1])) {
+      set_error(ctx, "observation %lld has a non-finite measurement", (long long)k);
+      return POVAR_EINVAL;
+    }
+    ++cnt_l[j];
+    ++cnt_c[c];
+  }
+  for (int32_t i = 0; i < n_p; ++i)
+    if (cnt_c[i] == 0) {
+      set_error(ctx, "camera %d has no observation", i);
+      return POVAR_EINVAL;
+    }
+  for (int32_t j = 0; j < n_l; ++j)
+    if (cnt_l[j] == 0) {
+      set_error(ctx, "point %d has no observation", j);
+      return POVAR_EINVAL;
+    }
+  // internal landmark order: decreasing track length, then caller's index
+  L.int2ext.resize(n_l);
+  std::iota(L.int2ext.begin(), L.int2ext.end(), 0);
+  std::stable_sort(L.int2ext.begin(), L.int2ext.end(),
+                   [&](int32_t a, int32_t b) { return cnt_l[a] > cnt_l[b]; });
+  // observations grouped by caller's landmark, then sorted by camera
+  std::vector<int64_t> lstart(n_l + 1, 0);
+  for (int32_t j = 0; j < n_l; ++j) lstart[j + 1] = lstart[j] + cnt_l[j];
+  std::vector<int64_t> lobs(n_obs);
+  {
+    std::vector<int64_t> fill(lstart.begin(), lstart.end() - 1);
+    for (int64_t k = 0; k < n_obs; ++k) lobs[fill[pt[k]]++] = k;
+  }
+  for (int32_t j = 0; j < n_l; ++j)
+    std::stable_sort(lobs.begin() + lstart[j], lobs.begin() + lstart[j + 1],
+                     [&](int64_t a, int64_t b) { return cam[a] < cam[b]; });
+  // landmark-major slices
+  L.n_sl = (n_l + kWave - 1) / kWave;
+  L.sl_len.resize(L.n_sl);
+  L.sl_off.resize(L.n_sl + 1);
+  L.sl_off[0] = 0;
+  int64_t ent = 0;
+  for (int s = 0; s < L.n_sl; ++s) {
+    L.sl_len[s] = cnt_l[L.int2ext[(size_t)s * kWave]];
+    ent += (int64_t)kWave * L.sl_len[s];
+    if (ent >= (int64_t)INT_MAX) {
+      set_error(ctx, "landmark slice layout exceeds 2^31 entries");
+      return POVAR_EINVAL;
+    }
+    L.sl_off[s + 1] = (int32_t)ent;
+  }
+  L.n_ent = ent;
+  L.e_cam.assign(ent, -1);
+  L.e_m64.assign(2 * ent, 0.0);
+  if (fp32) L.e_m32.assign(2 * ent, 0.0f);
+  for (int32_t jj = 0; jj < n_l; ++jj) {
+    const int32_t j = L.int2ext[jj];
+    const int s = jj / kWave, lane = jj % kWave;
+    int t = 0;
+    for (int64_t q = lstart[j]; q < lstart[j + 1]; ++q, ++t) {
+      const int64_t k = lobs[q];
+      const int64_t e = (int64_t)L.sl_off[s] + (int64_t)t * kWave + lane;
+      L.e_cam[e] = cam[k];
+      L.e_m64[2 * e] = meas[2 * k];
+      L.e_m64[2 * e + 1] = meas[2 * k + 1];
+      if (fp32) {
+        L.e_m32[2 * e] = (float)meas[2 * k];
+        L.e_m32[2 * e + 1] = (float)meas[2 * k + 1];
+      }
+    }
+  }
+  // camera-major order: by camera, then internal landmark
+  std::vector<int64_t> cstart(n_p + 1, 0);
+  for (int32_t i = 0; i < n_p; ++i) cstart[i + 1] = cstart[i] + cnt_c[i];
+  L.cm_lm.resize(n_obs);
+  if (fp32) L.cm_m32.resize(2 * n_obs); else L.cm_m64.resize(2 * n_obs);
+  {
+    std::vector<int64_t> fill(cstart.begin(), cstart.end() - 1);
+    for (int32_t jj = 0; jj < n_l; ++jj) {
+      const int32_t j = L.int2ext[jj];
+      for (int64_t q = lstart[j]; q < lstart[j + 1]; ++q) {
+        const int64_t k = lobs[q];
+        const int64_t pos = fill[cam[k]]++;
+        L.cm_lm[pos] = jj;
+        if (fp32) {
+          L.cm_m32[2 * pos] = (float)meas[2 * k];
+          L.cm_m32[2 * pos + 1] = (float)meas[2 * k + 1];
+        } else {
+          L.cm_m64[2 * pos] = meas[2 * k];
+          L.cm_m64[2 * pos + 1] = meas[2 * k + 1];
+        }
+      }
+    }
+  }
+  // chunks of <= kChunk observations, never spanning two cameras
+  L.cam_ch.resize(n_p + 1);
+  L.cam_ch[0] = 0;
+  for (int32_t i = 0; i < n_p; ++i) L.cam_ch[i + 1] = L.cam_ch[i] + (cnt_c[i] + kChunk - 1) / kChunk;
+  L.n_ch = L.cam_ch[n_p];
+  L.ch_beg.resize(L.n_ch + 1);
+  L.ch_cam.resize(L.n_ch);
+  for (int32_t i = 0; i < n_p; ++i)
+    for (int32_t q = L.cam_ch[i]; q < L.cam_ch[i + 1]; ++q) {
+      L.ch_beg[q] = (int32_t)(cstart[i] + (int64_t)(q - L.cam_ch[i]) * kChunk);
+      L.ch_cam[q] = i;
+    }
+  L.ch_beg[L.n_ch] = (int32_t)n_obs;
+  return POVAR_OK;
+}
+
+}  // namespace povar
+
+using namespace povar;
+
+#define HIP_TRY(ctx, expr)                                                          \
+  do {                                                                              \
+    hipError_t _e = (expr);                                                         \
+    if (_e != hipSuccess) {                                                         \
+      set_error((ctx), "%s failed: %s", #expr, hipGetErrorString(_e));              \
+      return POVAR_EDEVICE;                                                         \
+    }                                                                               \
+  } while (0)
+
+namespace povar {
+
+static const int kTraceCap = 4096;
+
+povar_status check_options(povar_ctx ctx, const povar_options* o) {
+  if (!o) {
+    set_error(ctx, "options must not be NULL");
+    return POVAR_EINVAL;
+  }
+  if (o->struct_size != sizeof(povar_options)) {
+    set_error(ctx, "povar_options.struct_size is %u, expected %zu", o->struct_size, sizeof(povar_options));
+    return POVAR_EINVAL;
+  }
+  if (!(o->eta >= 0.0 && o->eta <= 1.0)) {
+    set_error(ctx, "eta must lie in [0, 1]");
+    return POVAR_EINVAL;
+  }
+  if (o->series_order < 0 || o->series_order > 100000) {
+    set_error(ctx, "series_order must lie in [0, 100000]");
+    return POVAR_EINVAL;
+  }
+  if (o->max_iters < 0) {
+    set_error(ctx, "max_iters must be >= 0");
+    return POVAR_EINVAL;
+  }
+  if (!(o->ftol >= 0.0) || !(o->lambda0 > 0.0) || !(o->lambda_min > 0.0) ||
+      !(o->lambda_max >= o->lambda_min) || !std::isfinite(o->lambda_max)) {
+    set_error(ctx, "need ftol >= 0 and 0 < lambda_min <= lambda_max < inf, lambda0 > 0");
+    return POVAR_EINVAL;
+  }
+  if (o->precision != POVAR_PREC_FP64 && o->precision != POVAR_PREC_FP32_BULK) {
+    set_error(ctx, "unknown precision %d", o->precision);
+    return POVAR_EINVAL;
+  }
+  if (o->manifold != POVAR_MANIFOLD_SPHERE && o->manifold != POVAR_MANIFOLD_EUCLIDEAN) {
+    set_error(ctx, "unknown manifold %d", o->manifold);
+    return POVAR_EINVAL;
+  }
+  return POVAR_OK;
+}
+
+template <typename T>
+static void upload(std::vector<char>& staging, size_t off, const std::vector<T>& v) {
+  if (!v.empty()) std::memcpy(staging.data() + off, v.data(), v.size() * sizeof(T));
+}
+
+// Builds the device state of a problem from a host layout and initial
+// cameras: one arena allocation, filled from a single host staging image.
+povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, const povar_options* o,
+                          hipStream_t stream, povar_problem_s* pb) {
+  pb->ctx = ctx;
+  pb->opt = *o;
+  pb->fp32 = o->precision == POVAR_PREC_FP32_BULK;
+  pb->stream = stream;
+  pb->trace_cap = kTraceCap;
+  pb->L = std::move(L);
+  HostLayout& H = pb->L;
+  ArenaOffsets& A = pb->off;
+  pb->bytes = arena_bytes(H.n_p, H.n_l, H.n_obs, H.n_ent, H.n_sl, H.n_ch, pb->fp32, pb->trace_cap, &A);
+  hipError_t e = hipMalloc(&pb->arena, pb->bytes);
+  if (e != hipSuccess) {
+    pb->arena = nullptr;
+    set_error(ctx, "hipMalloc of %zu bytes failed: %s", pb->bytes, hipGetErrorString(e));
+    return POVAR_ENOMEM;
+  }
+  char* base = static_cast<char*>(pb->arena);
+  auto dp = [&](size_t off) -> void* { return off == SIZE_MAX ? nullptr : base + off; };
+
+  // cameras (normalised on the sphere)
+  std::vector<double> P64((size_t)H.n_p * kCam);
+  std::vector<float> P32((size_t)H.n_p * kCam);
+  for (int32_t i = 0; i < H.n_p; ++i) {
+    double nrm = 0.0;
+    for (int r = 0; r < kCam; ++r) {
+      const double v = cams0[(size_t)i * kCam + r];
+      if (!std::isfinite(v)) {
+        set_error(ctx, "initial camera %d is not finite", i);
+        return POVAR_EINVAL;
+      }
+      nrm += v * v;
+    }
+    if (!(nrm > 0.0)) {
+      set_error(ctx, "initial camera %d is zero", i);
+      return POVAR_EINVAL;
+    }
+    const double s = o->manifold == POVAR_MANIFOLD_SPHERE ? 1.0 / std::sqrt(nrm) : 1.0;
+    for (int r = 0; r < kCam; ++r) {
+      P64[(size_t)i * kCam + r] = cams0[(size_t)i * kCam + r] * s;
+      P32[(size_t)i * kCam + r] = (float)P64[(size_t)i * kCam + r];
+    }
+  }
+
+  DevProblem& R = pb->rec;
+  std::memset(&R, 0, sizeof(R));
+  R.n_p = H.n_p;
+  R.n_l = H.n_l;
+  R.n_sl = H.n_sl;
+  R.n_ch = H.n_ch;
+  R.manifold = o->manifold;
+  R.trace_cap = pb->trace_cap;
+  R.eta = o->eta;
+  R.ftol = o->ftol;
+  R.lambda_min = o->lambda_min;
+  R.lambda_max = o->lambda_max;
+  R.sl_off = (const int32_t*)dp(A.sl_off);
+  R.sl_len = (const int32_t*)dp(A.sl_len);
+  R.e_cam = (const int32_t*)dp(A.e_cam);
+  R.e_m32 = (const float2*)dp(A.e_m32);
+  R.e_m64 = (const double2*)dp(A.e_m64);
+  R.cm_lm = (const int32_t*)dp(A.cm_lm);
+  R.cm_m32 = (const float2*)dp(A.cm_m32);
+  R.cm_m64 = (const double2*)dp(A.cm_m64);
+  R.ch_beg = (const int32_t*)dp(A.ch_beg);
+  R.ch_cam = (const int32_t*)dp(A.ch_cam);
+  R.cam_ch = (const int32_t*)dp(A.cam_ch);
+  for (int b = 0; b < 2; ++b) {
+    R.P64[b] = (double*)dp(A.P64[b]);
+    R.P32[b] = (float*)dp(A.P32[b]);
+    R.X64[b] = (double*)dp(A.X64[b]);
+    R.Vp64[b] = (double*)dp(A.Vp64[b]);
+    R.z064[b] = (double*)dp(A.z064[b]);
+    R.X32[b] = (float*)dp(A.X32[b]);
+    R.Vp32[b] = (float*)dp(A.Vp32[b]);
+    R.z032[b] = (float*)dp(A.z032[b]);
+  }
+  R.U40 = (double*)dp(A.U40);
+  R.bp = (double*)dp(A.bp);
+  R.wz = (double*)dp(A.wz);
+  R.lin_part = (double*)dp(A.lin_part);
+  R.K64 = (double*)dp(A.K64);
+  R.K32 = (float*)dp(A.K32);
+  R.x = dp(A.x);
+  R.acc = dp(A.acc);
+  R.z = dp(A.z);
+  R.t_part = dp(A.t_part);
+  R.cam_cnt = (uint32_t*)dp(A.cam_cnt);
+  R.cost_part = (double*)dp(A.cost_part);
+  R.cost_cnt = (uint32_t*)dp(A.cost_cnt);
+  R.ctl = (Ctl*)dp(A.ctl);
+  R.tr_cost = (double*)dp(A.tr_cost);
+  R.tr_lambda = (double*)dp(A.tr_lambda);
+  R.tr_acc = (int32_t*)dp(A.tr_acc);
+
+  Ctl c;
+  std::memset(&c, 0, sizeof(c));
+  c.lambda = o->lambda0;
+  c.need_lin = 1;
+  c.iter_limit = INT_MAX;
+  c.order = o->series_order;
+
+  // batch of one: prefix tables of waves per unit kind
+  const int32_t units[kNumUnitKinds] = {H.n_sl, H.n_ch, (H.n_p + kWave - 1) / kWave, 1};
+  int32_t tables[kNumUnitKinds * 2];
+  for (int k = 0; k < kNumUnitKinds; ++k) {
+    tables[2 * k] = 0;
+    tables[2 * k + 1] = units[k];
+  }
+
+  // one staging image of everything that has an initial value
+  std::vector<char> img(pb->bytes, 0);
+  upload(img, A.sl_off, H.sl_off);
+  upload(img, A.sl_len, H.sl_len);
+  upload(img, A.e_cam, H.e_cam);
+  if (A.e_m32 != SIZE_MAX) upload(img, A.e_m32, H.e_m32);
+  upload(img, A.e_m64, H.e_m64);
+  upload(img, A.cm_lm, H.cm_lm);
+  if (A.cm_m32 != SIZE_MAX) upload(img, A.cm_m32, H.cm_m32);
+  if (A.cm_m64 != SIZE_MAX) upload(img, A.cm_m64, H.cm_m64);
+  upload(img, A.ch_beg, H.ch_beg);
+  upload(img, A.ch_cam, H.ch_cam);
+  upload(img, A.cam_ch, H.cam_ch);
+  upload(img, A.P64[0], P64);
+  upload(img, A.P32[0], P32);
+  std::memcpy(img.data() + A.ctl, &c, sizeof(c));
+  std::memcpy(img.data() + A.rec, &R, sizeof(R));
+  std::memcpy(img.data() + A.tables, tables, sizeof(tables));
+  HIP_TRY(ctx, hipMemcpyAsync(pb->arena, img.data(), pb->bytes, hipMemcpyHostToDevice, stream));
+
+  Batch& B = pb->batch;
+  B.probs = (const DevProblem*)dp(A.rec);
+  for (int k = 0; k < kNumUnitKinds; ++k) {
+    B.off[k] = (const int32_t*)dp(A.tables) + 2 * k;
+    B.total[k] = units[k];
+  }
+  B.n_prob = 1;
+  // initial landmarks and cost, Eq. (8)-(9)
+  HIP_TRY(ctx, launch_landmark_solve(B, 0, stream));
+  HIP_TRY(ctx, hipStreamSynchronize(stream));
+  // free the host copies of what only the device needs
+  HostLayout keep;
+  keep.n_p = H.n_p;
+  keep.n_l = H.n_l;
+  keep.n_obs = H.n_obs;
+  keep.n_ent = H.n_ent;
+  keep.n_sl = H.n_sl;
+  keep.n_ch = H.n_ch;
+  keep.int2ext = std::move(H.int2ext);
+  H = std::move(keep);
+  Ctl now;
+  HIP_TRY(ctx, read_ctl(pb, &now));
+  if (!std::isfinite(now.cost)) {
+    set_error(ctx, "initial cost is not finite");
+    return POVAR_ENUMERIC;
+  }
+  return POVAR_OK;
+}
+
+hipError_t read_ctl(povar_problem_s* pb, Ctl* out) {
+  hipError_t e = hipMemcpyAsync(out, pb->rec.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, pb->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(pb->stream);
+}
+
+hipError_t write_ctl(povar_problem_s* pb, const Ctl* in) {
+  hipError_t e = hipMemcpyAsync(pb->rec.ctl, in, sizeof(Ctl), hipMemcpyHostToDevice, pb->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(pb->stream);
+}
+
+// Series kernels, optionally bracketed by timing events.
+static hipError_t enqueue_series(povar_problem_s* pb, int order, bool timed) {
+  hipError_t e;
+  for (int t = 1; t <= order; ++t) {
+    hipEvent_t ev[4];
+    if (timed)
+      for (int q = 0; q < 4; ++q) {
+        ev[q] = pb->event_pool_get();
+        if (!ev[q]) return hipErrorOutOfMemory;
+      }
+    if (timed && (e = hipEventRecord(ev[0], pb->stream)) != hipSuccess) return e;
+    if ((e = launch_series_landmark(pb->batch, pb->fp32, t, pb->stream)) != hipSuccess) return e;
+    if (timed && (e = hipEventRecord(ev[1], pb->stream)) != hipSuccess) return e;
+    if (timed && (e = hipEventRecord(ev[2], pb->stream)) != hipSuccess) return e;
+    if ((e = launch_series_camera(pb->batch, pb->fp32, t, pb->stream)) != hipSuccess) return e;
+    if (timed && (e = hipEventRecord(ev[3], pb->stream)) != hipSuccess) return e;
+    if (timed) {
+      pb->pending.push_back({ev[0], ev[1], 0});
+      pb->pending.push_back({ev[2], ev[3], 1});
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t enqueue_iteration(povar_problem_s* pb, bool timed) {
+  hipError_t e;
+  const Batch& B = pb->batch;
+  if ((e = launch_linearize(B, pb->fp32, 0, pb->stream)) != hipSuccess) return e;
+  if ((e = launch_camera_prep(B, pb->fp32, pb->stream)) != hipSuccess) return e;
+  if ((e = enqueue_series(pb, pb->opt.series_order, timed)) != hipSuccess) return e;
+  if ((e = launch_retract(B, pb->fp32, pb->stream)) != hipSuccess) return e;
+  if ((e = launch_landmark_solve(B, 1, pb->stream)) != hipSuccess) return e;
+  return launch_decide(B, pb->stream);
+}
+
+static hipError_t ensure_graph(povar_problem_s* pb) {
+  if (pb->graph_exec) return hipSuccess;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(pb->stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return e;
+  e = enqueue_iteration(pb, false);
+  hipGraph_t captured = nullptr;
+  hipError_t e2 = hipStreamEndCapture(pb->stream, &captured);
+  if (e != hipSuccess) {
+    if (captured) (void)hipGraphDestroy(captured);
+    return e;
+  }
+  if (e2 != hipSuccess) return e2;
+  g = captured;
+  e = hipGraphInstantiate(&pb->graph_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) pb->graph_exec = nullptr;
+  return e;
+}
+
+hipError_t enqueue_iterations(povar_problem_s* pb, int n) {
+  hipError_t e = hipSuccess;
+  const bool timed = pb->timing;
+  if (!timed && pb->opt.use_graph && !pb->graph_failed) {
+    e = ensure_graph(pb);
+    if (e != hipSuccess) {
+      pb->graph_failed = true;   // fall back to direct launches
+      (void)hipGetLastError();
+    }
+  }
+  for (int it = 0; it < n; ++it) {
+    if (!timed && pb->graph_exec) e = hipGraphLaunch(pb->graph_exec, pb->stream);
+    else e = enqueue_iteration(pb, timed);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace povar
+
+hipEvent_t povar_problem_s::event_pool_get() {
+  if (event_next < events.size()) return events[event_next++];
+  hipEvent_t ev;
+  if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+  events.push_back(ev);
+  ++event_next;
+  return ev;
+}
+
+hipError_t povar_problem_s::drain_timing() {
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return e;
+  for (const auto& p : pending) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, p.start, p.stop);
+    if (e != hipSuccess) return e;
+    ms_kernel[p.kind] += ms;
+    n_kernel[p.kind] += 1;
+  }
+  pending.clear();
+  event_next = 0;
+  return hipSuccess;
+}
+
+namespace povar {
+
+void fill_report(const povar_problem_s* pb, const Ctl& c, double seconds, povar_report* r) {
+  if (!r) return;
+  std::memset(r, 0, sizeof(*r));
+  r->cost_initial = c.cost0;
+  r->cost_final = c.cost;
+  r->lambda_final = c.lambda;
+  r->seconds = seconds;
+  r->iters = c.iter;
+  r->accepted = c.n_accept;
+  r->stop_reason = c.stop_reason;
+}
+
+}  // namespace povar
+
+// ==================================================================== C ABI
+extern "C" {
+
+povar_status povar_options_default(povar_options* o) {
+  if (!o) return POVAR_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(povar_options);
+  o->eta = 0.01;
+  o->series_order = 20;
+  o->max_iters = 50;
+  o->ftol = 1e-6;
+  o->lambda0 = 1e-4;
+  o->lambda_min = 1e-12;
+  o->lambda_max = 1e12;
+  o->precision = POVAR_PREC_FP64;
+  o->manifold = POVAR_MANIFOLD_SPHERE;
+  o->use_graph = 1;
+  return POVAR_OK;
+}
+
+povar_status povar_ctx_create(int device, void* hip_stream, povar_ctx* out) {
+  if (!out) return POVAR_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) {
+    set_error(nullptr, "no HIP device available (%s)", hipGetErrorString(e));
+    return POVAR_EDEVICE;
+  }
+  if (device < 0 || device >= n) {
+    set_error(nullptr, "device %d out of range [0, %d)", device, n);
+    return POVAR_EINVAL;
+  }
+  e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    set_error(nullptr, "hipSetDevice(%d): %s", device, hipGetErrorString(e));
+    return POVAR_EDEVICE;
+  }
+  auto* c = new povar_ctx_s();
+  c->device = device;
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->own_stream = false;
+  } else {
+    e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      set_error(nullptr, "hipStreamCreate: %s", hipGetErrorString(e));
+      delete c;
+      return POVAR_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return POVAR_OK;
+}
+
+povar_status povar_ctx_destroy(povar_ctx ctx) {
+  if (!ctx) return POVAR_EINVAL;
+  if (ctx->live_problems > 0) {
+    set_error(ctx, "%d problem(s) of this context are still alive", ctx->live_problems);
+    return POVAR_ESTATE;
+  }
+  (void)hipSetDevice(ctx->device);
+  if (ctx->own_stream) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamDestroy(ctx->stream);
+  }
+  delete ctx;
+  return POVAR_OK;
+}
+
+const char* povar_last_error(povar_ctx ctx) {
+  if (!ctx) return g_noctx_error.c_str();
+  std::lock_guard<std::mutex> g(ctx->err_mu);
+  ctx->err_copy = ctx->err;
+  return ctx->err_copy.c_str();
+}
+
+povar_status povar_problem_footprint(int32_t n_cams, int32_t n_pts, int64_t n_obs, int32_t precision,
+                                     uint64_t* bytes) {
+  if (!bytes || n_cams <= 0 || n_pts <= 0 || n_obs <= 0) return POVAR_EINVAL;
+  if (precision != POVAR_PREC_FP64 && precision != POVAR_PREC_FP32_BULK) return POVAR_EINVAL;
+  // upper bounds for problems without repeated (camera, point) pairs: slice
+  // padding adds at most 64 x the longest track (<= n_cams) entries, chunk
+  // rounding at most one chunk per camera
+  const int64_t n_sl = (n_pts + kWave - 1) / kWave;
+  const int64_t n_ent = n_obs + (int64_t)kWave * std::min<int64_t>(n_cams, n_obs);
+  const int64_t n_ch = n_obs / kChunk + n_cams;
+  *bytes = arena_bytes(n_cams, n_pts, n_obs, n_ent, n_sl, n_ch, precision == POVAR_PREC_FP32_BULK,
+                       kTraceCap, nullptr);
+  return POVAR_OK;
+}
+
+povar_status povar_problem_create(povar_ctx ctx, int32_t n_cams, int32_t n_pts, int64_t n_obs,
+                                  const int32_t* cam_idx, const int32_t* pt_idx, const double* meas,
+                                  const double* cams0, const povar_options* opts, povar_problem* out) {
+  if (!ctx || !out) return POVAR_EINVAL;
+  *out = nullptr;
+  povar_status st = check_options(ctx, opts);
+  if (st != POVAR_OK) return st;
+  if (!cams0) {
+    set_error(ctx, "cams0 must not be NULL");
+    return POVAR_EINVAL;
+  }
+  (void)hipSetDevice(ctx->device);
+  HostLayout L;
+  st = build_layout(ctx, n_cams, n_pts, n_obs, cam_idx, pt_idx, meas,
+                    opts->precision == POVAR_PREC_FP32_BULK, L);
+  if (st != POVAR_OK) return st;
+  auto* pb = new povar_problem_s();
+  pb->ctx = ctx;
+  pb->owned_by_ctx = true;
+  ctx->live_problems += 1;
+  st = problem_init(ctx, std::move(L), cams0, opts, ctx->stream, pb);
+  if (st != POVAR_OK) {
+    povar_problem_destroy(pb);
+    return st;
+  }
+  *out = pb;
+  return POVAR_OK;
+}
+
+povar_status povar_problem_create_device(povar_ctx ctx, int32_t n_cams, int32_t n_pts, int64_t n_obs,
+                                         const int32_t* cam_idx, const int32_t* pt_idx, const double* meas,
+                                         const double* cams0, const povar_options* opts, povar_problem* out) {
+  if (!ctx || !out) return POVAR_EINVAL;
+  if (n_cams <= 0 || n_pts <= 0 || n_obs <= 0 || !cam_idx || !pt_idx || !meas || !cams0) {
+    set_error(ctx, "invalid sizes or NULL device pointers");
+    return POVAR_EINVAL;
+  }
+  (void)hipSetDevice(ctx->device);
+  std::vector<int32_t> c(n_obs), p(n_obs);
+  std::vector<double> m(2 * n_obs), q((size_t)n_cams * kCam);
+  HIP_TRY(ctx, hipMemcpyAsync(c.data(), cam_idx, n_obs * 4, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(p.data(), pt_idx, n_obs * 4, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(m.data(), meas, n_obs * 16, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(q.data(), cams0, q.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return povar_problem_create(ctx, n_cams, n_pts, n_obs, c.data(), p.data(), m.data(), q.data(), opts, out);
+}
+
+povar_status povar_problem_destroy(povar_problem pb) {
+  if (!pb) return POVAR_EINVAL;
+  if (pb->ctx) (void)hipSetDevice(pb->ctx->device);
+  if (pb->stream) (void)hipStreamSynchronize(pb->stream);
+  if (pb->graph_exec) (void)hipGraphExecDestroy(pb->graph_exec);
+  for (auto ev : pb->events) (void)hipEventDestroy(ev);
+  if (pb->arena) (void)hipFree(pb->arena);
+  if (pb->ctx && pb->owned_by_ctx) pb->ctx->live_problems -= 1;
+  delete pb;
+  return POVAR_OK;
+}
+
+static povar_status run_iters(povar_problem pb, int32_t n, bool check_done, povar_report* report) {
+  povar_ctx ctx = pb->ctx;
+  (void)hipSetDevice(ctx->device);
+  const auto t0 = std::chrono::steady_clock::now();
+  Ctl c;
+  HIP_TRY(ctx, read_ctl(pb, &c));
+  int left = n;
+  while (left > 0 && !c.done) {
+    const int batch = check_done ? std::min(left, 4) : left;
+    HIP_TRY(ctx, enqueue_iterations(pb, batch));
+    left -= batch;
+    HIP_TRY(ctx, read_ctl(pb, &c));
+  }
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  fill_report(pb, c, secs, report);
+  if (c.status & 1) {
+    set_error(ctx, "a damped camera block was not positive definite");
+    return POVAR_ENUMERIC;
+  }
+  return POVAR_OK;
+}
+
+povar_status povar_solve(povar_problem pb, povar_report* report) {
+  if (!pb) return POVAR_EINVAL;
+  Ctl c;
+  HIP_TRY(pb->ctx, read_ctl(pb, &c));
+  const int left = std::max(0, pb->opt.max_iters - c.iter);
+  return run_iters(pb, left, pb->opt.ftol > 0.0, report);
+}
+
+povar_status povar_step(povar_problem pb, int32_t n_iters, povar_report* report) {
+  if (!pb || n_iters < 0) return POVAR_EINVAL;
+  return run_iters(pb, n_iters, pb->opt.ftol > 0.0, report);
+}
+
+povar_status povar_enqueue(povar_problem pb, int32_t n_iters) {
+  if (!pb || n_iters < 0) return POVAR_EINVAL;
+  (void)hipSetDevice(pb->ctx->device);
+  HIP_TRY(pb->ctx, enqueue_iterations(pb, n_iters));
+  return POVAR_OK;
+}
+
+povar_status povar_get_report(povar_problem pb, povar_report* report) {
+  if (!pb || !report) return POVAR_EINVAL;
+  Ctl c;
+  HIP_TRY(pb->ctx, read_ctl(pb, &c));
+  fill_report(pb, c, 0.0, report);
+  return POVAR_OK;
+}
+
+povar_status povar_get_cameras(povar_problem pb, double* out) {
+  if (!pb || !out) return POVAR_EINVAL;
+  Ctl c;
+  HIP_TRY(pb->ctx, read_ctl(pb, &c));
+  HIP_TRY(pb->ctx, hipMemcpyAsync(out, pb->rec.P64[c.pcur], (size_t)pb->L.n_p * kCam * 8,
+                                  hipMemcpyDeviceToHost, pb->stream));
+  HIP_TRY(pb->ctx, hipStreamSynchronize(pb->stream));
+  return POVAR_OK;
+}
+
+static povar_status copy_landmark_vec(povar_problem pb, const double* dev, int stride, int width, double* out) {
+  std::vector<double> tmp((size_t)pb->L.n_l * stride);
+  HIP_TRY(pb->ctx, hipMemcpyAsync(tmp.data(), dev, tmp.size() * 8, hipMemcpyDeviceToHost, pb->stream));
+  HIP_TRY(pb->ctx, hipStreamSynchronize(pb->stream));
+  for (int32_t jj = 0; jj < pb->L.n_l; ++jj) {
+    const int32_t j = pb->L.int2ext[jj];
+    for (int k = 0; k < width; ++k) out[(size_t)j * width + k] = tmp[(size_t)jj * stride + k];
+  }
+  return POVAR_OK;
+}
+
+povar_status povar_get_points(povar_problem pb, double* out) {
+  if (!pb || !out) return POVAR_EINVAL;
+  Ctl c;
+  HIP_TRY(pb->ctx, read_ctl(pb, &c));
+  return copy_landmark_vec(pb, pb->rec.X64[c.lcur], kLmVec, 3, out);
+}
+
+povar_status povar_get_trace(povar_problem pb, int32_t n, double* cost, double* lam, int32_t* acc) {
+  if (!pb || n < 0) return POVAR_EINVAL;
+  Ctl c;
+  HIP_TRY(pb->ctx, read_ctl(pb, &c));
+  const int m = std::min(std::min(n, c.iter), pb->trace_cap);
+  if (m == 0) return POVAR_OK;
+  if (cost) HIP_TRY(pb->ctx, hipMemcpyAsync(cost, pb->rec.tr_cost, m * 8, hipMemcpyDeviceToHost, pb->stream));
+  if (lam) HIP_TRY(pb->ctx, hipMemcpyAsync(lam, pb->rec.tr_lambda, m * 8, hipMemcpyDeviceToHost, pb->stream));
+  if (acc) HIP_TRY(pb->ctx, hipMemcpyAsync(acc, pb->rec.tr_acc, m * 4, hipMemcpyDeviceToHost, pb->stream));
+  HIP_TRY(pb->ctx, hipStreamSynchronize(pb->stream));
+  return POVAR_OK;
+}
+
+povar_status povar_get_state(povar_problem pb, double* cams, double* lambda, int32_t* iter, double* cost) {
+  if (!pb) return POVAR_EINVAL;
+  Ctl c;
+  HIP_TRY(pb->ctx, read_ctl(pb, &c));
+  if (cams) {
+    povar_status st = povar_get_cameras(pb, cams);
+    if (st != POVAR_OK) return st;
+  }
+  if (lambda) *lambda = c.lambda;
+  if (iter) *iter = c.iter;
+  if (cost) *cost = c.cost;
+  return POVAR_OK;
+}
+
+povar_status povar_set_state(povar_problem pb, const double* cams, double lambda, int32_t iter) {
+  if (!pb || !cams || !(lambda > 0.0) || iter < 0) return POVAR_EINVAL;
+  povar_ctx ctx = pb->ctx;
+  (void)hipSetDevice(ctx->device);
+  Ctl c;
+  HIP_TRY(ctx, read_ctl(pb, &c));
+  const int32_t n_p = pb->L.n_p;
+  std::vector<double> P64((size_t)n_p * kCam);
+  std::vector<float> P32((size_t)n_p * kCam);
+  for (int32_t i = 0; i < n_p; ++i) {
+    double nrm = 0.0;
+    for (int r = 0; r < kCam; ++r) nrm += cams[(size_t)i * kCam + r] * cams[(size_t)i * kCam + r];
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) {
+      set_error(ctx, "camera %d is zero or not finite", i);
+      return POVAR_EINVAL;
+    }
+    // cameras already on the sphere (to 1e-14) are taken bit-exactly, so a
+    // state read by povar_get_state resumes bit-exactly
+    const bool renorm = pb->opt.manifold == POVAR_MANIFOLD_SPHERE && std::fabs(nrm - 1.0) > 1e-14;
+    const double s = renorm ? 1.0 / std::sqrt(nrm) : 1.0;
+    for (int r = 0; r < kCam; ++r) {
+      P64[(size_t)i * kCam + r] = cams[(size_t)i * kCam + r] * s;
+      P32[(size_t)i * kCam + r] = (float)P64[(size_t)i * kCam + r];
+    }
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(pb->rec.P64[c.pcur], P64.data(), P64.size() * 8, hipMemcpyHostToDevice, pb->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(pb->rec.P32[c.pcur], P32.data(), P32.size() * 4, hipMemcpyHostToDevice, pb->stream));
+  c.lambda = lambda;
+  c.iter = iter;
+  c.need_lin = 1;
+  c.done = 0;
+  c.stop_reason = 0;
+  c.status = 0;
+  HIP_TRY(ctx, write_ctl(pb, &c));
+  HIP_TRY(ctx, launch_landmark_solve(pb->batch, 2, pb->stream));
+  HIP_TRY(ctx, read_ctl(pb, &c));
+  if (!std::isfinite(c.cost)) {
+    set_error(ctx, "cost at the given cameras is not finite");
+    return POVAR_ENUMERIC;
+  }
+  return POVAR_OK;
+}
+
+povar_status povar_debug_linearize(povar_problem pb, double* U, double* bp, double* g, double* Vp, double* X,
+                                   double* z0, double* cost) {
+  if (!pb) return POVAR_EINVAL;
+  povar_ctx ctx = pb->ctx;
+  (void)hipSetDevice(ctx->device);
+  Ctl c;
+  HIP_TRY(ctx, read_ctl(pb, &c));
+  if (c.done) {
+    set_error(ctx, "problem has finished; linearisation hooks need a running problem");
+    return POVAR_ESTATE;
+  }
+  HIP_TRY(ctx, launch_linearize(pb->batch, pb->fp32, 1, pb->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(pb->stream));
+  const int32_t n_p = pb->L.n_p;
+  std::vector<double> u40((size_t)n_p * 40), b((size_t)n_p * kCam), w((size_t)n_p * kCam);
+  HIP_TRY(ctx, hipMemcpyAsync(u40.data(), pb->rec.U40, u40.size() * 8, hipMemcpyDeviceToHost, pb->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(b.data(), pb->rec.bp, b.size() * 8, hipMemcpyDeviceToHost, pb->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(w.data(), pb->rec.wz, w.size() * 8, hipMemcpyDeviceToHost, pb->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(pb->stream));
+  const double a = 1.0 - pb->opt.eta;
+  auto s4 = [](int c0, int d0) {
+    const int lo = std::min(c0, d0), hi = std::max(c0, d0);
+    return (lo * 7 - lo * lo) / 2 + hi;
+  };
+  for (int32_t i = 0; i < n_p; ++i) {
+    const double* q = u40.data() + (size_t)i * 40;
+    if (U)
+      for (int r = 0; r < 12; ++r)
+        for (int cc = 0; cc < 12; ++cc) {
+          const int ar = r / 4, ac = cc / 4, k = s4(r % 4, cc % 4);
+          double v;
+          if (ar < 2 && ac < 2) v = ar == ac ? q[k] : 0.0;
+          else if (ar == 2 && ac == 2) v = a * q[30 + k];
+          else v = -a * q[(ar == 1 || ac == 1) ? 20 + k : 10 + k];
+          U[(size_t)i * 144 + r * 12 + cc] = v;
+        }
+    for (int r = 0; r < kCam; ++r) {
+      if (bp) bp[(size_t)i * kCam + r] = b[(size_t)i * kCam + r];
+      if (g) g[(size_t)i * kCam + r] = b[(size_t)i * kCam + r] - w[(size_t)i * kCam + r];
+    }
+  }
+  if (Vp) {
+    std::vector<double> v((size_t)pb->L.n_l * kLmSym);
+    HIP_TRY(ctx, hipMemcpyAsync(v.data(), pb->rec.Vp64[c.lcur], v.size() * 8, hipMemcpyDeviceToHost, pb->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(pb->stream));
+    static const int map9[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+    for (int32_t jj = 0; jj < pb->L.n_l; ++jj) {
+      const int32_t j = pb->L.int2ext[jj];
+      for (int k = 0; k < 9; ++k) Vp[(size_t)j * 9 + k] = v[(size_t)jj * kLmSym + map9[k]];
+    }
+  }
+  if (X) {
+    povar_status st = copy_landmark_vec(pb, pb->rec.X64[c.lcur], kLmVec, 3, X);
+    if (st != POVAR_OK) return st;
+  }
+  if (z0) {
+    povar_status st = copy_landmark_vec(pb, pb->rec.z064[c.lcur], kLmVec, 3, z0);
+    if (st != POVAR_OK) return st;
+  }
+  if (cost) *cost = c.cost;
+  return POVAR_OK;
+}
+
+povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, double* dp, double* p_trial,
+                              double* cost_trial) {
+  if (!pb || !(lambda > 0.0) || order < 0) return POVAR_EINVAL;
+  povar_ctx ctx = pb->ctx;
+  (void)hipSetDevice(ctx->device);
+  Ctl c;
+  HIP_TRY(ctx, read_ctl(pb, &c));
+  if (c.done) {
+    set_error(ctx, "problem has finished; step hooks need a running problem");
+    return POVAR_ESTATE;
+  }
+  const Ctl saved = c;
+  c.lambda = lambda;
+  c.order = order;
+  c.status = 0;
+  HIP_TRY(ctx, write_ctl(pb, &c));
+  const Batch& B = pb->batch;
+  HIP_TRY(ctx, launch_linearize(B, pb->fp32, 0, pb->stream));
+  HIP_TRY(ctx, launch_camera_prep(B, pb->fp32, pb->stream));
+  for (int t = 1; t <= order; ++t) {
+    HIP_TRY(ctx, launch_series_landmark(B, pb->fp32, t, pb->stream));
+    HIP_TRY(ctx, launch_series_camera(B, pb->fp32, t, pb->stream));
+  }
+  HIP_TRY(ctx, launch_retract(B, pb->fp32, pb->stream));
+  HIP_TRY(ctx, launch_landmark_solve(B, 1, pb->stream));
+  Ctl after;
+  HIP_TRY(ctx, read_ctl(pb, &after));
+  const int32_t n_p = pb->L.n_p;
+  if (dp) {
+    if (pb->fp32) {
+      std::vector<float> t((size_t)n_p * kCam);
+      HIP_TRY(ctx, hipMemcpyAsync(t.data(), pb->rec.acc, t.size() * 4, hipMemcpyDeviceToHost, pb->stream));
+      HIP_TRY(ctx, hipStreamSynchronize(pb->stream));
+      for (size_t k = 0; k < t.size(); ++k) dp[k] = t[k];
+    } else {
+      HIP_TRY(ctx, hipMemcpyAsync(dp, pb->rec.acc, (size_t)n_p * kCam * 8, hipMemcpyDeviceToHost, pb->stream));
+    }
+  }
+  if (p_trial)
+    HIP_TRY(ctx, hipMemcpyAsync(p_trial, pb->rec.P64[c.pcur ^ 1], (size_t)n_p * kCam * 8, hipMemcpyDeviceToHost,
+                                pb->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(pb->stream));
+  if (cost_trial) *cost_trial = after.cost_trial;
+  Ctl restore = saved;
+  restore.need_lin = 0;   // the linearisation at the current cameras is now in place
+  restore.cost_trial = after.cost_trial;
+  restore.status = after.status;
+  HIP_TRY(ctx, write_ctl(pb, &restore));
+  if (after.status & 1) {
+    set_error(ctx, "a damped camera block was not positive definite");
+    return POVAR_ENUMERIC;
+  }
+  return POVAR_OK;
+}
+
+povar_status povar_kernel_timing(povar_problem pb, int32_t enable) {
+  if (!pb) return POVAR_EINVAL;
+  (void)hipSetDevice(pb->ctx->device);
+  if (!enable) HIP_TRY(pb->ctx, pb->drain_timing());
+  pb->timing = enable != 0;
+  return POVAR_OK;
+}
+
+povar_status povar_kernel_times(povar_problem pb, double* ms_l, int64_t* n_l, double* ms_c, int64_t* n_c) {
+  if (!pb) return POVAR_EINVAL;
+  (void)hipSetDevice(pb->ctx->device);
+  HIP_TRY(pb->ctx, pb->drain_timing());
+  if (ms_l) *ms_l = pb->ms_kernel[0];
+  if (n_l) *n_l = pb->n_kernel[0];
+  if (ms_c) *ms_c = pb->ms_kernel[1];
+  if (n_c) *n_c = pb->n_kernel[1];
+  pb->ms_kernel[0] = pb->ms_kernel[1] = 0.0;
+  pb->n_kernel[0] = pb->n_kernel[1] = 0;
+  return POVAR_OK;
+}
+
+povar_status povar_problem_info(povar_problem pb, int64_t* n_obs, int64_t* slice_entries, int32_t* n_chunks,
+                                uint64_t* device_bytes) {
+  if (!pb) return POVAR_EINVAL;
+  if (n_obs) *n_obs = pb->L.n_obs;
+  if (slice_entries) *slice_entries = pb->L.n_ent;
+  if (n_chunks) *n_chunks = pb->L.n_ch;
+  if (device_bytes) *device_bytes = pb->bytes;
+  return POVAR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,357 @@
+"""ctypes binding of ``libpovar.so`` (the C ABI in ``include/povar.h``).
+
+Argument marshalling only: every step of the solve runs in the HIP kernels of
+the library.  The library must have been built (``python -m
+paper_2405_05079_amd.build``); loading fails loudly otherwise.  PyTorch is
+used only to hand over a HIP stream or device tensors when the caller asks.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import weakref
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpovar.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ENUMERIC, ESTATE = range(7)
+STATUS_NAMES = {0: "POVAR_OK", 1: "POVAR_EINVAL", 2: "POVAR_ENOMEM", 3: "POVAR_EDEVICE",
+                4: "POVAR_EAGAIN", 5: "POVAR_ENUMERIC", 6: "POVAR_ESTATE"}
+PRECISION = {"fp64": 0, "fp32_bulk": 1}
+MANIFOLD = {"sphere": 0, "euclidean": 1}
+
+# every symbol include/povar.h declares
+EXPORTS = [
+    "povar_options_default", "povar_ctx_create", "povar_ctx_destroy", "povar_last_error",
+    "povar_problem_footprint", "povar_problem_create", "povar_problem_create_device",
+    "povar_problem_destroy", "povar_solve", "povar_step", "povar_enqueue", "povar_get_report",
+    "povar_get_cameras", "povar_get_points", "povar_get_trace", "povar_get_state", "povar_set_state",
+    "povar_debug_linearize", "povar_debug_step", "povar_kernel_timing", "povar_kernel_times",
+    "povar_problem_info", "povar_server_create", "povar_server_submit", "povar_server_poll",
+    "povar_server_stats", "povar_server_destroy",
+]
+
+
+class PovarError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("eta", C.c_double), ("series_order", C.c_int32),
+                ("max_iters", C.c_int32), ("ftol", C.c_double), ("lambda0", C.c_double),
+                ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("precision", C.c_int32),
+                ("manifold", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Report(C.Structure):
+    _fields_ = [("cost_initial", C.c_double), ("cost_final", C.c_double), ("lambda_final", C.c_double),
+                ("seconds", C.c_double), ("iters", C.c_int32), ("accepted", C.c_int32),
+                ("stop_reason", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib: Optional[C.CDLL] = None
+_P = C.c_void_p
+_I32P = C.POINTER(C.c_int32)
+_I64P = C.POINTER(C.c_int64)
+_DP = C.POINTER(C.c_double)
+_U64P = C.POINTER(C.c_uint64)
+
+
+def lib() -> C.CDLL:
+    """Load the library once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2405_05079_amd.build` "
+                           "(the PoVar path has no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    sig = {
+        "povar_options_default": (C.c_int, [C.POINTER(Options)]),
+        "povar_ctx_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
+        "povar_ctx_destroy": (C.c_int, [_P]),
+        "povar_last_error": (C.c_char_p, [_P]),
+        "povar_problem_footprint": (C.c_int, [C.c_int32, C.c_int32, C.c_int64, C.c_int32, _U64P]),
+        "povar_problem_create": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P,
+                                           C.POINTER(Options), C.POINTER(_P)]),
+        "povar_problem_create_device": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P,
+                                                  C.POINTER(Options), C.POINTER(_P)]),
+        "povar_problem_destroy": (C.c_int, [_P]),
+        "povar_solve": (C.c_int, [_P, C.POINTER(Report)]),
+        "povar_step": (C.c_int, [_P, C.c_int32, C.POINTER(Report)]),
+        "povar_enqueue": (C.c_int, [_P, C.c_int32]),
+        "povar_get_report": (C.c_int, [_P, C.POINTER(Report)]),
+        "povar_get_cameras": (C.c_int, [_P, _P]),
+        "povar_get_points": (C.c_int, [_P, _P]),
+        "povar_get_trace": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
+        "povar_get_state": (C.c_int, [_P, _P, _DP, _I32P, _DP]),
+        "povar_set_state": (C.c_int, [_P, _P, C.c_double, C.c_int32]),
+        "povar_debug_linearize": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _DP]),
+        "povar_debug_step": (C.c_int, [_P, C.c_double, C.c_int32, _P, _P, _DP]),
+        "povar_kernel_timing": (C.c_int, [_P, C.c_int32]),
+        "povar_kernel_times": (C.c_int, [_P, _DP, _I64P, _DP, _I64P]),
+        "povar_problem_info": (C.c_int, [_P, _I64P, _I64P, _I32P, _U64P]),
+        "povar_server_create": (C.c_int, [_P, C.c_uint64, C.c_int32, C.POINTER(_P)]),
+        "povar_server_submit": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P,
+                                          C.POINTER(Options), _U64P]),
+        "povar_server_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(Report), _P, _P, _P]),
+        "povar_server_stats": (C.c_int, [_P, _I32P, _I32P, _I64P, _I64P]),
+        "povar_server_destroy": (C.c_int, [_P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(a: np.ndarray) -> C.c_void_p:
+    return C.c_void_p(a.ctypes.data)
+
+
+def make_options(eta=0.01, order=20, max_iters=50, ftol=1e-6, lambda0=1e-4, lambda_min=1e-12,
+                 lambda_max=1e12, precision="fp64", manifold="sphere", use_graph=True) -> Options:
+    o = Options()
+    lib().povar_options_default(C.byref(o))
+    o.eta, o.series_order, o.max_iters, o.ftol = eta, order, max_iters, ftol
+    o.lambda0, o.lambda_min, o.lambda_max = lambda0, lambda_min, lambda_max
+    o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    o.manifold = MANIFOLD[manifold] if isinstance(manifold, str) else int(manifold)
+    o.use_graph = 1 if use_graph else 0
+    return o
+
+
+def footprint(n_cams: int, n_pts: int, n_obs: int, precision="fp32_bulk") -> int:
+    out = C.c_uint64()
+    st = lib().povar_problem_footprint(n_cams, n_pts, n_obs, PRECISION[precision], C.byref(out))
+    if st != OK:
+        raise PovarError(st, "invalid sizes")
+    return int(out.value)
+
+
+class Context:
+    """A HIP device and the stream all work of its problems runs on.
+    stream: None (library-owned stream), an integer hipStream_t, or "torch"
+    (torch.cuda.current_stream())."""
+
+    def __init__(self, device: int = 0, stream=None):
+        if stream == "torch":
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self.handle = C.c_void_p()
+        st = lib().povar_ctx_create(device, C.c_void_p(stream) if stream else None, C.byref(self.handle))
+        if st != OK:
+            raise PovarError(st, lib().povar_last_error(None).decode())
+        self.device = device
+        self._problems = weakref.WeakSet()
+
+    def check(self, st: int, what: str = ""):
+        if st != OK:
+            raise PovarError(st, (what + ": " if what else "") + lib().povar_last_error(self.handle).decode())
+
+    def close(self):
+        """Destroys every problem still open on this context, then the context."""
+        if self.handle:
+            for p in list(self._problems):
+                p.close()
+            self.check(lib().povar_ctx_destroy(self.handle), "povar_ctx_destroy")
+            self.handle = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Problem:
+    """One bundle-adjustment problem resident on the GPU."""
+
+    def __init__(self, ctx: Context, n_cams: int, n_pts: int, cam_idx, pt_idx, meas, cams0, **opts):
+        self.ctx = ctx
+        self.n_cams, self.n_pts = int(n_cams), int(n_pts)
+        self.options = make_options(**opts)
+        self.handle = C.c_void_p()
+        if _is_torch_cuda(cam_idx):
+            st = lib().povar_problem_create_device(
+                ctx.handle, self.n_cams, self.n_pts, int(cam_idx.shape[0]),
+                C.c_void_p(cam_idx.data_ptr()), C.c_void_p(pt_idx.data_ptr()), C.c_void_p(meas.data_ptr()),
+                C.c_void_p(cams0.data_ptr()), C.byref(self.options), C.byref(self.handle))
+        else:
+            self._cam = np.ascontiguousarray(cam_idx, dtype=np.int32)
+            self._pt = np.ascontiguousarray(pt_idx, dtype=np.int32)
+            self._meas = np.ascontiguousarray(meas, dtype=np.float64).reshape(-1, 2)
+            c0 = np.ascontiguousarray(cams0, dtype=np.float64).reshape(self.n_cams, 12)
+            st = lib().povar_problem_create(ctx.handle, self.n_cams, self.n_pts, int(self._cam.shape[0]),
+                                            _ptr(self._cam), _ptr(self._pt), _ptr(self._meas), _ptr(c0),
+                                            C.byref(self.options), C.byref(self.handle))
+            del self._cam, self._pt, self._meas
+        ctx.check(st, "povar_problem_create")
+        ctx._problems.add(self)
+
+    @classmethod
+    def from_synth(cls, ctx: Context, prob, **opts) -> "Problem":
+        opts.setdefault("eta", prob.eta)
+        opts.setdefault("order", prob.order)
+        return cls(ctx, prob.n_cams, prob.n_pts, prob.cam_idx, prob.pt_idx, prob.meas, prob.cams0, **opts)
+
+    def _chk(self, st, what):
+        self.ctx.check(st, what)
+
+    def solve(self) -> dict:
+        r = Report()
+        self._chk(lib().povar_solve(self.handle, C.byref(r)), "povar_solve")
+        return r.as_dict()
+
+    def step(self, n: int) -> dict:
+        r = Report()
+        self._chk(lib().povar_step(self.handle, int(n), C.byref(r)), "povar_step")
+        return r.as_dict()
+
+    def enqueue(self, n: int):
+        self._chk(lib().povar_enqueue(self.handle, int(n)), "povar_enqueue")
+
+    def report(self) -> dict:
+        r = Report()
+        self._chk(lib().povar_get_report(self.handle, C.byref(r)), "povar_get_report")
+        return r.as_dict()
+
+    def cameras(self) -> np.ndarray:
+        out = np.empty((self.n_cams, 12))
+        self._chk(lib().povar_get_cameras(self.handle, _ptr(out)), "povar_get_cameras")
+        return out
+
+    def points(self) -> np.ndarray:
+        out = np.empty((self.n_pts, 3))
+        self._chk(lib().povar_get_points(self.handle, _ptr(out)), "povar_get_points")
+        return out
+
+    def trace(self, n: int = 4096):
+        it = self.report()["iters"]
+        n = min(n, it)
+        cost, lam, acc = np.empty(n), np.empty(n), np.empty(n, np.int32)
+        if n:
+            self._chk(lib().povar_get_trace(self.handle, n, _ptr(cost), _ptr(lam), _ptr(acc)), "povar_get_trace")
+        return cost, lam, acc.astype(bool)
+
+    def state(self):
+        cams = np.empty((self.n_cams, 12))
+        lam, it, cost = C.c_double(), C.c_int32(), C.c_double()
+        self._chk(lib().povar_get_state(self.handle, _ptr(cams), C.byref(lam), C.byref(it), C.byref(cost)),
+                  "povar_get_state")
+        return cams, lam.value, it.value, cost.value
+
+    def set_state(self, cams, lam: float, it: int):
+        c = np.ascontiguousarray(cams, dtype=np.float64).reshape(self.n_cams, 12)
+        self._chk(lib().povar_set_state(self.handle, _ptr(c), float(lam), int(it)), "povar_set_state")
+
+    def debug_linearize(self) -> dict:
+        nc, npt = self.n_cams, self.n_pts
+        out = dict(U=np.empty((nc, 12, 12)), bp=np.empty((nc, 12)), g=np.empty((nc, 12)),
+                   Vp=np.empty((npt, 3, 3)), X=np.empty((npt, 3)), z0=np.empty((npt, 3)))
+        cost = C.c_double()
+        self._chk(lib().povar_debug_linearize(self.handle, _ptr(out["U"]), _ptr(out["bp"]), _ptr(out["g"]),
+                                              _ptr(out["Vp"]), _ptr(out["X"]), _ptr(out["z0"]),
+                                              C.byref(cost)), "povar_debug_linearize")
+        out["cost"] = cost.value
+        return out
+
+    def debug_step(self, lam: float, order: int):
+        dp, pt = np.empty((self.n_cams, 12)), np.empty((self.n_cams, 12))
+        ct = C.c_double()
+        self._chk(lib().povar_debug_step(self.handle, float(lam), int(order), _ptr(dp), _ptr(pt), C.byref(ct)),
+                  "povar_debug_step")
+        return dp, pt, ct.value
+
+    def kernel_timing(self, enable: bool):
+        self._chk(lib().povar_kernel_timing(self.handle, 1 if enable else 0), "povar_kernel_timing")
+
+    def kernel_times(self) -> dict:
+        ml, mc = C.c_double(), C.c_double()
+        nl, nc = C.c_int64(), C.c_int64()
+        self._chk(lib().povar_kernel_times(self.handle, C.byref(ml), C.byref(nl), C.byref(mc), C.byref(nc)),
+                  "povar_kernel_times")
+        return dict(ms_landmark_pass=ml.value, n_landmark_pass=nl.value,
+                    ms_camera_pass=mc.value, n_camera_pass=nc.value)
+
+    def info(self) -> dict:
+        a, b, d = C.c_int64(), C.c_int64(), C.c_uint64()
+        c = C.c_int32()
+        self._chk(lib().povar_problem_info(self.handle, C.byref(a), C.byref(b), C.byref(c), C.byref(d)),
+                  "povar_problem_info")
+        return dict(n_obs=a.value, slice_entries=b.value, n_chunks=c.value, device_bytes=d.value)
+
+    def close(self):
+        if self.handle:
+            lib().povar_problem_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request loop (povar_server_*)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int):
+        self.ctx = ctx
+        self.handle = C.c_void_p()
+        ctx.check(lib().povar_server_create(ctx.handle, int(hbm_budget_bytes), int(max_slots),
+                                            C.byref(self.handle)), "povar_server_create")
+        self._sizes = {}
+
+    def submit(self, prob, **opts) -> int:
+        opts.setdefault("eta", prob.eta)
+        opts.setdefault("order", prob.order)
+        opts.setdefault("max_iters", prob.iters)
+        o = make_options(**opts)
+        cam = np.ascontiguousarray(prob.cam_idx, np.int32)
+        pt = np.ascontiguousarray(prob.pt_idx, np.int32)
+        meas = np.ascontiguousarray(prob.meas, np.float64)
+        c0 = np.ascontiguousarray(prob.cams0, np.float64)
+        t = C.c_uint64()
+        st = lib().povar_server_submit(self.handle, prob.n_cams, prob.n_pts, cam.shape[0], _ptr(cam), _ptr(pt),
+                                       _ptr(meas), _ptr(c0), C.byref(o), C.byref(t))
+        self.ctx.check(st, "povar_server_submit")
+        self._sizes[t.value] = (prob.n_cams, prob.n_pts)
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while running; else (report, cameras, points, times)."""
+        nc, npt = self._sizes[ticket]
+        cams, pts, times = np.empty((nc, 12)), np.empty((npt, 3)), np.empty(3)
+        r = Report()
+        st = lib().povar_server_poll(self.handle, ticket, C.byref(r), _ptr(cams), _ptr(pts), _ptr(times))
+        if st == EAGAIN:
+            return None
+        self.ctx.check(st, "povar_server_poll")
+        del self._sizes[ticket]
+        return r.as_dict(), cams, pts, times
+
+    def stats(self) -> dict:
+        q, a = C.c_int32(), C.c_int32()
+        f, b = C.c_int64(), C.c_int64()
+        self.ctx.check(lib().povar_server_stats(self.handle, C.byref(q), C.byref(a), C.byref(f), C.byref(b)),
+                       "povar_server_stats")
+        return dict(queued=q.value, active=a.value, finished=f.value, batch_iters=b.value)
+
+    def close(self):
+        if self.handle:
+            lib().povar_server_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+
+def _is_torch_cuda(x) -> bool:
+    return type(x).__module__.startswith("torch") and getattr(x, "is_cuda", False)
