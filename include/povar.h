@@ -192,9 +192,10 @@ povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, do
 povar_status povar_kernel_timing(povar_problem pb, int32_t enable);
 povar_status povar_kernel_times(povar_problem pb, double* ms_landmark_pass, int64_t* n_landmark_pass,
                                 double* ms_camera_pass, int64_t* n_camera_pass);
-/* Problem shape after layout: entries of the landmark-major slice layout
-   (observations + padding), number of camera chunks. */
-povar_status povar_problem_info(povar_problem pb, int64_t* n_obs, int64_t* slice_entries,
+/* Problem shape after layout: landmark-major packets (runs of whole
+   landmarks of at most 64 observations), camera-major chunks (at most 2048
+   observations of one camera), device bytes. */
+povar_status povar_problem_info(povar_problem pb, int64_t* n_obs, int64_t* n_packets,
                                 int32_t* n_chunks, uint64_t* device_bytes);
 
 /* ---- serving: continuous batching of many problems on one GPU ----------- */

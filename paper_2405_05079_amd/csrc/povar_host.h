@@ -24,12 +24,13 @@ namespace povar {
 // Host image of the observation layout (see DevProblem for the meaning).
 struct HostLayout {
   int32_t n_p = 0, n_l = 0;
-  int64_t n_obs = 0, n_ent = 0;
-  int32_t n_sl = 0, n_ch = 0;
+  int64_t n_obs = 0;
+  int32_t n_pk = 0, n_ch = 0;
   std::vector<int32_t> int2ext;        // internal landmark -> caller's index
-  std::vector<int32_t> sl_off, sl_len, e_cam;
-  std::vector<float> e_m32;
-  std::vector<double> e_m64;
+  std::vector<int32_t> pk_off, pk_n, pk_lm0;
+  std::vector<uint32_t> pk_code;
+  std::vector<float> pk_m32;
+  std::vector<double> pk_m64;
   std::vector<int32_t> cm_lm;
   std::vector<float> cm_m32;
   std::vector<double> cm_m64;
@@ -39,14 +40,14 @@ struct HostLayout {
 // Byte offsets of every buffer inside a problem's device arena
 // (SIZE_MAX = not allocated for this precision).
 struct ArenaOffsets {
-  size_t sl_off, sl_len, e_cam, e_m32, e_m64, cm_lm, cm_m32, cm_m64, ch_beg, ch_cam, cam_ch;
-  size_t P64[2], P32[2], X64[2], Vp64[2], z064[2], X32[2], Vp32[2], z032[2];
-  size_t U40, bp, wz, lin_part, K64, K32, x, acc, z, t_part, cam_cnt, cost_part, cost_cnt, ctl;
+  size_t pk_off, pk_n, pk_lm0, pk_code, pk_m32, pk_m64, cm_lm, cm_m32, cm_m64, ch_beg, ch_cam, cam_ch;
+  size_t P64[2], P32[2], rec64[2], rec32[2], Vp64[2], Vp32[2];
+  size_t lin_part, K64, K32, g64, U40, x, acc, zx, t_part, cam_cnt, cost_part;
   size_t tr_cost, tr_lambda, tr_acc, rec, tables;
 };
 
-size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_ent, int64_t n_sl, int64_t n_ch,
-                   bool fp32, int64_t trace_cap, ArenaOffsets* o);
+size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_t n_ch, bool fp32,
+                   int64_t trace_cap, ArenaOffsets* o);
 povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs, const int32_t* cam,
                           const int32_t* pt, const double* meas, bool fp32, HostLayout& L);
 povar_status check_options(povar_ctx ctx, const povar_options* o);

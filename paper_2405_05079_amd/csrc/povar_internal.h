@@ -1,10 +1,10 @@
 // Internal data layout of the PoVar HIP library (device structs and launchers).
 //
 // One problem = one DevProblem record in device memory.  Every kernel is
-// launched over a *batch* of problems: the grid is a flat list of waves,
-// and each wave finds its (problem, unit) pair from a prefix table of units
-// per problem.  A single solve is a batch of one; the server batches every
-// admitted problem into the same launches.
+// launched over a *batch* of problems: the grid is a flat list of work units
+// (a wave or a workgroup each), and each unit finds its (problem, local unit)
+// pair from a prefix table of units per problem.  A single solve is a batch
+// of one; the server batches every admitted problem into the same launches.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -13,19 +13,23 @@
 namespace povar {
 
 constexpr int kWave = 64;                 // CDNA wavefront
-constexpr int kBlock = 256;               // 4 independent waves per workgroup
+constexpr int kBlock = 256;               // workgroup of the streaming passes
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kChunk = 256;               // camera-major observations per wave (4 per lane)
+constexpr int kPerLane = 8;               // camera-major observations per lane
+constexpr int kChunk = kBlock * kPerLane; // camera-major observations per workgroup
 constexpr int kLinVals = 64;              // per-camera linearisation accumulators
+constexpr int kCamBits = 26;              // packet entry: camera index bits
+constexpr uint32_t kCamMask = (1u << kCamBits) - 1u;
 
 // Landmark slot strides (elements) in the per-landmark arrays.
-constexpr int kLmVec = 4;                 // X (x,y,z,1), z0, z: 4 values
+constexpr int kRec = 8;                   // (z0, z1, z2, 0, X0, X1, X2, 1)
 constexpr int kLmSym = 8;                 // V^+ : 6 values (00,01,02,11,12,22) + 2 pad
 constexpr int kCam = 12;                  // one camera / camera vector
 constexpr int kCamMat = 144;              // 12 x 12 camera operator
 
-// Per-problem control block.  Only device kernels write it during a solve;
-// the host reads it after synchronising and writes it only between launches.
+// Per-problem control block (first member of the problem record).  Only
+// kernels write it during a solve; the host reads it after synchronising and
+// writes it only between launches.
 struct Ctl {
   double lambda;        // damping for the next step
   double cost;          // f* at the current cameras
@@ -34,7 +38,7 @@ struct Ctl {
   int32_t lcur;         // landmark buffer holding the current linearisation point
   int32_t pcur;         // camera buffer holding the current cameras
   int32_t need_lin;     // 1: linearise before the next step (after an accept)
-  int32_t done;         // 1: finished (ftol, or iteration limit of a served problem)
+  int32_t done;         // 1: finished (ftol, or iteration limit)
   int32_t iter;         // LM iterations taken
   int32_t n_accept;
   int32_t iter_limit;   // done when iter reaches it
@@ -45,19 +49,23 @@ struct Ctl {
 };
 
 struct DevProblem {
-  int32_t n_p, n_l, n_sl, n_ch;
+  Ctl ctl;
+  int32_t n_p, n_l, n_pk, n_ch;
   int32_t manifold;     // 0 sphere, 1 euclidean
   int32_t trace_cap;
   int32_t pad0, pad1;
   double eta, ftol, lambda_min, lambda_max;
 
-  // landmark-major slices: slice s holds landmarks 64s..64s+63 (internal
-  // order = decreasing track length); entry (t, lane) at sl_off[s]+64t+lane
-  const int32_t* sl_off;
-  const int32_t* sl_len;
-  const int32_t* e_cam;     // camera of each entry, -1 = padding
-  const float2* e_m32;
-  const double2* e_m64;
+  // landmark-major packets: packet q holds whole landmarks lm0 .. (internal
+  // ids), entries pk_off[q] .. pk_off[q] + pk_n[q] - 1, one lane per entry;
+  // pk_n > 64 only for a packet made of a single landmark with more than 64
+  // observations.  Entry code = camera | (landmark - lm0) << 26.
+  const int32_t* pk_off;
+  const int32_t* pk_n;
+  const int32_t* pk_lm0;
+  const uint32_t* pk_code;
+  const float2* pk_m32;
+  const double2* pk_m64;
   // camera-major observations (sorted by camera, then internal landmark)
   const int32_t* cm_lm;     // internal landmark id
   const float2* cm_m32;
@@ -69,43 +77,39 @@ struct DevProblem {
   // cameras, double-buffered (current / trial), n_p x 12
   double* P64[2];
   float* P32[2];
-  // landmarks of the current linearisation / trial point, internal order
-  double* X64[2];           // n_l x 4 (X, 1)
-  double* Vp64[2];          // n_l x 8 (V^+ packed)
-  double* z064[2];          // n_l x 4 (V^+ b_l)
-  float* X32[2];
+  // landmarks of the current linearisation / trial point, internal order:
+  // record (z0 = V^+ b_l, X) per landmark, and V^+
+  double* rec64[2];         // n_l x 8
+  float* rec32[2];
+  double* Vp64[2];          // n_l x 8
   float* Vp32[2];
-  float* z032[2];
 
   // linearisation per camera
-  double* U40;              // n_p x 40: sum x~x~^T, sum m1 x~x~^T, sum m2 x~x~^T, sum |m|^2 x~x~^T
-  double* bp;               // n_p x 12
-  double* wz;               // n_p x 12: sum_k W_k V^+ b_l
-  double* lin_part;         // n_ch x 64 chunk partials
+  double* lin_part;         // n_ch x 64 chunk partials: 40 U values, b_p, sum W z0
   // damped, projected, inverted camera blocks K_i = Pi (Pi U_l Pi + tau p p^T)^-1 Pi
   double* K64;              // n_p x 144
   float* K32;
+  double* g64;              // n_p x 12  b_p - sum W V^+ b_l  (kept for inspection)
+  double* U40;              // n_p x 40  combined U values (kept for inspection)
   // power-series work vectors (series precision)
   void* x;                  // n_p x 12, current term
   void* acc;                // n_p x 12, partial sum x(m)
-  void* z;                  // n_l x 4
+  void* zx;                 // n_l x 8, (z, X) records of the current order
   void* t_part;             // n_ch x 12 chunk partials
-  uint32_t* cam_cnt;        // n_p arrival counters (reset by the last wave)
-  double* cost_part;        // n_sl
-  uint32_t* cost_cnt;       // 1
-  Ctl* ctl;
+  uint32_t* cam_cnt;        // n_p arrival counters (reset by the last workgroup)
+  double* cost_part;        // n_pk
   double* tr_cost;          // trace_cap entries
   double* tr_lambda;
   int32_t* tr_acc;
 };
 
 // Unit kinds of a launch.
-enum UnitKind { kUnitSlice = 0, kUnitChunk = 1, kUnitCamWave = 2, kUnitOne = 3, kNumUnitKinds = 4 };
+enum UnitKind { kUnitPacket = 0, kUnitChunk = 1, kUnitCamWave = 2, kUnitOne = 3, kNumUnitKinds = 4 };
 
 // A batch of problems: device array of records and, per unit kind, the
-// prefix table of waves per problem (n_prob + 1 entries each).
+// prefix table of units per problem (n_prob + 1 entries each).
 struct Batch {
-  const DevProblem* probs;
+  DevProblem* probs;
   const int32_t* off[kNumUnitKinds];
   int32_t n_prob;
   int32_t total[kNumUnitKinds];
@@ -114,12 +118,12 @@ struct Batch {
 // Launchers (defined with the kernels).  `fp32` selects the series /
 // Jacobian precision; the critical kernels are FP64 in both modes.
 hipError_t launch_landmark_solve(const Batch& b, int mode, hipStream_t s);   // mode 0 init, 1 trial, 2 reset
+hipError_t launch_cost_finalize(const Batch& b, int mode, hipStream_t s);    // mode 0 init, 1 trial, 2 reset
 hipError_t launch_linearize(const Batch& b, bool fp32, int force, hipStream_t s);
 hipError_t launch_camera_prep(const Batch& b, bool fp32, hipStream_t s);
 hipError_t launch_series_landmark(const Batch& b, bool fp32, int t, hipStream_t s);
 hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s);
 hipError_t launch_retract(const Batch& b, bool fp32, hipStream_t s);
 hipError_t launch_decide(const Batch& b, hipStream_t s);
-hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 
 }  // namespace povar

@@ -13,18 +13,20 @@
 // observation stream (camera or landmark index + measurement) and the
 // camera / landmark state.
 //
-// Passes (all deterministic, no floating-point atomics):
+// Passes (deterministic: no floating-point atomics, fixed reduction orders):
 //   k_landmark_solve   closed-form landmarks (8), V_j^+, b_l, z0 = V^+ b_l, cost (9)
-//   k_linearize        U_i, b_p, sum_k W_k z0 per camera                  (10)-(13)
+//   k_linearize        U_i, b_p, sum_k W_k z0 per camera chunk             (10)-(13)
 //   k_camera_prep      damping, tangent projection, 12x12 inverse, x_0    (14),(17),(20)-(29)
 //   k_series_landmark  z_j = V_j^+ sum_k W_k^T x_i                        (17)
 //   k_series_camera    x_i = K_i sum_k W_k z_j, acc_i += x_i              (17)
 //   k_retract          p_i <- (p_i + acc_i) / |p_i + acc_i|               (Sec. 4.3)
 //   k_decide           LM accept / reject and damping update              (Sec. 5.2)
-// Landmark-major passes run one lane per landmark over 64-landmark slices
-// whose entries are stored lane-interleaved (coalesced); camera-major passes
-// run one wave per chunk of <= 256 observations of one camera and combine
-// the chunks of a camera in a fixed order in the last-arriving wave.
+// Landmark-major passes run one lane per observation over packets of <= 64
+// observations made of whole landmarks, and sum each landmark's lanes with a
+// segmented scan inside the wave.  Camera-major passes run one workgroup per
+// chunk of <= 2048 observations of one camera (8 independent loads per lane);
+// a camera spanning several chunks is finished by the last-arriving workgroup,
+// which adds the chunk partials in chunk order.
 #include <type_traits>
 
 #include "povar_internal.h"
@@ -34,19 +36,28 @@ namespace povar {
 // ---------------------------------------------------------------- helpers
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
-__device__ __forceinline__ bool map_wave(const Batch& B, int kind, int& p, int& u) {
-  int w = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
-  w = __builtin_amdgcn_readfirstlane(w);
-  if (w >= B.total[kind]) return false;
+__device__ __forceinline__ bool find_unit(const Batch& B, int kind, int ug, int& p, int& u) {
+  if (ug >= B.total[kind]) return false;
   const int32_t* off = B.off[kind];
   int lo = 0, hi = B.n_prob;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (off[mid] <= w) lo = mid; else hi = mid;
+    if (off[mid] <= ug) lo = mid; else hi = mid;
   }
   p = lo;
-  u = w - off[lo];
+  u = ug - off[lo];
   return true;
+}
+
+// one unit per wave
+__device__ __forceinline__ bool map_wave(const Batch& B, int kind, int& p, int& u) {
+  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6));
+  return find_unit(B, kind, w, p, u);
+}
+
+// one unit per workgroup
+__device__ __forceinline__ bool map_block(const Batch& B, int kind, int& p, int& u) {
+  return find_unit(B, kind, (int)blockIdx.x, p, u);
 }
 
 // Butterfly sum: every lane ends with the same, order-fixed value.
@@ -57,48 +68,68 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Segmented inclusive scan over lanes whose keys form contiguous runs: bit s
+// of `links` says that lane - 2^s belongs to the same run.  After seg_sum the
+// last lane of each run holds the run's total.
+__device__ __forceinline__ uint32_t seg_links(int key) {
+  const int lane = lane_id();
+  uint32_t links = 0;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int d = 1 << s;
+    const int kp = __shfl_up(key, d, kWave);
+    if (lane >= d && kp == key) links |= 1u << s;
+  }
+  return links;
+}
+
+template <typename T>
+__device__ __forceinline__ T seg_sum(T v, uint32_t links) {
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const T vp = __shfl_up(v, 1 << s, kWave);
+    if (links & (1u << s)) v += vp;
+  }
+  return v;
+}
+
+// Lane index of the last lane of this lane's run.
+__device__ __forceinline__ int seg_tail_lane(int key, bool tail) {
+  const int lane = lane_id();
+  int t = tail ? lane : kWave;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int d = 1 << s;
+    const int tn = __shfl_down(t, d, kWave);
+    const int kn = __shfl_down(key, d, kWave);
+    if (lane + d < kWave && kn == key) t = min(t, tn);
+  }
+  return t;
+}
+
 template <typename T>
 __device__ __forceinline__ T ld_coherent(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Arrival counter for "last wave combines the partials": every wave of a
-// group publishes its partial, fences, and bumps the counter; the wave that
-// sees count == n-1 owns the combination and resets the counter.
-__device__ __forceinline__ bool arrive_last(uint32_t* cnt, uint32_t n) {
-  __threadfence();
-  uint32_t old = 0;
-  if (lane_id() == 0) old = atomicAdd(cnt, 1u);
-  old = __shfl(old, 0, kWave);
-  if (old != n - 1) return false;
-  __threadfence();
-  return true;
-}
-
-__device__ __forceinline__ void reset_counter(uint32_t* cnt) {
-  if (lane_id() == 0) __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename T> struct Prec;
 template <> struct Prec<float> {
   using T2 = float2;
   __device__ static const float2* cm_m(const DevProblem& D) { return D.cm_m32; }
-  __device__ static const float2* e_m(const DevProblem& D) { return D.e_m32; }
-  __device__ static float* P(const DevProblem& D, int b) { return D.P32[b]; }
-  __device__ static float* X(const DevProblem& D, int b) { return D.X32[b]; }
-  __device__ static float* Vp(const DevProblem& D, int b) { return D.Vp32[b]; }
-  __device__ static float* z0(const DevProblem& D, int b) { return D.z032[b]; }
-  __device__ static float* K(const DevProblem& D) { return D.K32; }
+  __device__ static const float2* pk_m(const DevProblem& D) { return D.pk_m32; }
+  __device__ static const float* P(const DevProblem& D, int b) { return b ? D.P32[1] : D.P32[0]; }
+  __device__ static const float* rec(const DevProblem& D, int b) { return b ? D.rec32[1] : D.rec32[0]; }
+  __device__ static const float* Vp(const DevProblem& D, int b) { return b ? D.Vp32[1] : D.Vp32[0]; }
+  __device__ static const float* K(const DevProblem& D) { return D.K32; }
 };
 template <> struct Prec<double> {
   using T2 = double2;
   __device__ static const double2* cm_m(const DevProblem& D) { return D.cm_m64; }
-  __device__ static const double2* e_m(const DevProblem& D) { return D.e_m64; }
-  __device__ static double* P(const DevProblem& D, int b) { return D.P64[b]; }
-  __device__ static double* X(const DevProblem& D, int b) { return D.X64[b]; }
-  __device__ static double* Vp(const DevProblem& D, int b) { return D.Vp64[b]; }
-  __device__ static double* z0(const DevProblem& D, int b) { return D.z064[b]; }
-  __device__ static double* K(const DevProblem& D) { return D.K64; }
+  __device__ static const double2* pk_m(const DevProblem& D) { return D.pk_m64; }
+  __device__ static const double* P(const DevProblem& D, int b) { return b ? D.P64[1] : D.P64[0]; }
+  __device__ static const double* rec(const DevProblem& D, int b) { return b ? D.rec64[1] : D.rec64[0]; }
+  __device__ static const double* Vp(const DevProblem& D, int b) { return b ? D.Vp64[1] : D.Vp64[0]; }
+  __device__ static const double* K(const DevProblem& D) { return D.K64; }
 };
 
 template <typename T>
@@ -225,136 +256,204 @@ __device__ __forceinline__ void sym3_pinv(const double (&v)[6], double (&out)[6]
 }
 
 // -------------------------------------------------------- k_landmark_solve
-// One lane per landmark, FP64.  V_j = sum J_l^T J_l, h_j = -sum J_l^T r(X=0),
-// X_j = V_j^+ h_j (8); then, at X_j, the cost sum ||r||^2 (9) and
-// b_l = sum J_l^T r, and z0 = V^+ b_l.  J_l rows: sqrt(a)(R0 - m1 R2),
-// sqrt(a)(R1 - m2 R2), sqrt(eta) R0, sqrt(eta) R1 with R_a the rows of Pbar.
-// mode 0: initial state (writes the current buffers, cost and cost0);
-// mode 1: trial point of a step (other buffers, cost_trial);
-// mode 2: re-solve at the current cameras (writes cost).
+// FP64.  Per observation, J_l has rows sqrt(a)(R0 - m1 R2), sqrt(a)(R1 - m2 R2),
+// sqrt(eta) R0, sqrt(eta) R1 (R_a = rows of Pbar), and the residual at X = 0
+// is built from p4.  V_j = sum J_l^T J_l, h_j = -sum J_l^T r(X=0),
+// X_j = V_j^+ h_j (8); then at X_j the cost sum ||r||^2 (9), b_l = sum J_l^T r
+// and z0 = V^+ b_l.
+__device__ __forceinline__ void obs_normal(const double (&Pc)[12], double m1, double m2, double a, double eta,
+                                           double (&v)[6], double (&h)[3]) {
+  const double D0[3] = {Pc[0] - m1 * Pc[8], Pc[1] - m1 * Pc[9], Pc[2] - m1 * Pc[10]};
+  const double D1[3] = {Pc[4] - m2 * Pc[8], Pc[5] - m2 * Pc[9], Pc[6] - m2 * Pc[10]};
+  const double R0[3] = {Pc[0], Pc[1], Pc[2]};
+  const double R1[3] = {Pc[4], Pc[5], Pc[6]};
+  v[0] = a * (D0[0] * D0[0] + D1[0] * D1[0]) + eta * (R0[0] * R0[0] + R1[0] * R1[0]);
+  v[1] = a * (D0[0] * D0[1] + D1[0] * D1[1]) + eta * (R0[0] * R0[1] + R1[0] * R1[1]);
+  v[2] = a * (D0[0] * D0[2] + D1[0] * D1[2]) + eta * (R0[0] * R0[2] + R1[0] * R1[2]);
+  v[3] = a * (D0[1] * D0[1] + D1[1] * D1[1]) + eta * (R0[1] * R0[1] + R1[1] * R1[1]);
+  v[4] = a * (D0[1] * D0[2] + D1[1] * D1[2]) + eta * (R0[1] * R0[2] + R1[1] * R1[2]);
+  v[5] = a * (D0[2] * D0[2] + D1[2] * D1[2]) + eta * (R0[2] * R0[2] + R1[2] * R1[2]);
+  const double o1 = a * (Pc[3] - m1 * Pc[11]), o2 = a * (Pc[7] - m2 * Pc[11]);
+  const double f1 = eta * (Pc[3] - m1), f2 = eta * (Pc[7] - m2);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) h[k] = -(D0[k] * o1 + D1[k] * o2 + R0[k] * f1 + R1[k] * f2);
+}
+
+// residual cost and J_l^T r of one observation at X
+__device__ __forceinline__ double obs_residual(const double (&Pc)[12], double m1, double m2, double a, double eta,
+                                              double X0, double X1, double X2, double (&b)[3]) {
+  const double u = Pc[0] * X0 + Pc[1] * X1 + Pc[2] * X2 + Pc[3];
+  const double v = Pc[4] * X0 + Pc[5] * X1 + Pc[6] * X2 + Pc[7];
+  const double w = Pc[8] * X0 + Pc[9] * X1 + Pc[10] * X2 + Pc[11];
+  const double o1 = u - m1 * w, o2 = v - m2 * w;
+  const double f1 = u - m1, f2 = v - m2;
+  const double ao1 = a * o1, ao2 = a * o2, ef1 = eta * f1, ef2 = eta * f2;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    b[k] = (Pc[k] - m1 * Pc[8 + k]) * ao1 + (Pc[4 + k] - m2 * Pc[8 + k]) * ao2 + Pc[k] * ef1 + Pc[4 + k] * ef2;
+  return a * (o1 * o1 + o2 * o2) + eta * (f1 * f1 + f2 * f2);
+}
+
+__device__ __forceinline__ void store_landmark(DevProblem& D, int lc, int j, const double (&vp)[6], double X0,
+                                               double X1, double X2, const double (&bl)[3]) {
+  const double z0 = vp[0] * bl[0] + vp[1] * bl[1] + vp[2] * bl[2];
+  const double z1 = vp[1] * bl[0] + vp[3] * bl[1] + vp[4] * bl[2];
+  const double z2 = vp[2] * bl[0] + vp[4] * bl[1] + vp[5] * bl[2];
+  double* r64 = (lc ? D.rec64[1] : D.rec64[0]) + (size_t)j * kRec;
+  float* r32 = (lc ? D.rec32[1] : D.rec32[0]) + (size_t)j * kRec;
+  double* v64 = (lc ? D.Vp64[1] : D.Vp64[0]) + (size_t)j * kLmSym;
+  float* v32 = (lc ? D.Vp32[1] : D.Vp32[0]) + (size_t)j * kLmSym;
+  store4(r64, z0, z1, z2, 0.0);
+  store4(r64 + 4, X0, X1, X2, 1.0);
+  store4(r32, (float)z0, (float)z1, (float)z2, 0.0f);
+  store4(r32 + 4, (float)X0, (float)X1, (float)X2, 1.0f);
+  store4(v64, vp[0], vp[1], vp[2], vp[3]);
+  store4(v64 + 4, vp[4], vp[5], 0.0, 0.0);
+  store4(v32, (float)vp[0], (float)vp[1], (float)vp[2], (float)vp[3]);
+  store4(v32 + 4, (float)vp[4], (float)vp[5], 0.0f, 0.0f);
+}
+
+// mode 0: initial state, 1: trial point of a step (other buffers), 2: re-solve
+// at the current cameras.  Writes one cost partial per packet.
 __global__ void __launch_bounds__(kBlock) k_landmark_solve(Batch B, int mode) {
-  int p, s;
-  if (!map_wave(B, kUnitSlice, p, s)) return;
-  const DevProblem& D = B.probs[p];
-  Ctl* ctl = D.ctl;
+  int p, q;
+  if (!map_wave(B, kUnitPacket, p, q)) return;
+  DevProblem& D = B.probs[p];
   const int trial = mode == 1 ? 1 : 0;
-  if (trial && ctl->done) return;
-  const int pc = ctl->pcur ^ trial, lc = ctl->lcur ^ trial;
-  const double* __restrict__ P = D.P64[pc];
+  if (trial && D.ctl.done) return;
+  const int pc = D.ctl.pcur ^ trial, lc = D.ctl.lcur ^ trial;
+  const double* __restrict__ P = pc ? D.P64[1] : D.P64[0];
   const int lane = lane_id();
-  const int j = s * kWave + lane;
   const double eta = D.eta, a = 1.0 - eta;
-  const int len = D.sl_len[s];
-  const int base = D.sl_off[s];
-  const int32_t* __restrict__ ecam = D.e_cam;
-  const double2* __restrict__ em = D.e_m64;
-
-  double v[6] = {0, 0, 0, 0, 0, 0};
-  double h0 = 0, h1 = 0, h2 = 0;
-  for (int t = 0; t < len; ++t) {
-    const int e = base + t * kWave + lane;
-    const int c = ecam[e];
-    if (c < 0) continue;
-    const double2 m = em[e];
+  const int n = D.pk_n[q], off = D.pk_off[q], lm0 = D.pk_lm0[q];
+  double ftot;
+  if (n <= kWave) {
+    const bool act = lane < n;
+    int key = kWave + lane, c = 0;
+    double2 m = make_double2(0.0, 0.0);
+    if (act) {
+      const uint32_t code = D.pk_code[off + lane];
+      c = (int)(code & kCamMask);
+      key = (int)(code >> kCamBits);
+      m = D.pk_m64[off + lane];
+    }
     double Pc[12];
-    load12(P + (size_t)c * kCam, Pc);
-    const double D0[3] = {Pc[0] - m.x * Pc[8], Pc[1] - m.x * Pc[9], Pc[2] - m.x * Pc[10]};
-    const double D1[3] = {Pc[4] - m.y * Pc[8], Pc[5] - m.y * Pc[9], Pc[6] - m.y * Pc[10]};
-    const double R0[3] = {Pc[0], Pc[1], Pc[2]};
-    const double R1[3] = {Pc[4], Pc[5], Pc[6]};
-    v[0] += a * (D0[0] * D0[0] + D1[0] * D1[0]) + eta * (R0[0] * R0[0] + R1[0] * R1[0]);
-    v[1] += a * (D0[0] * D0[1] + D1[0] * D1[1]) + eta * (R0[0] * R0[1] + R1[0] * R1[1]);
-    v[2] += a * (D0[0] * D0[2] + D1[0] * D1[2]) + eta * (R0[0] * R0[2] + R1[0] * R1[2]);
-    v[3] += a * (D0[1] * D0[1] + D1[1] * D1[1]) + eta * (R0[1] * R0[1] + R1[1] * R1[1]);
-    v[4] += a * (D0[1] * D0[2] + D1[1] * D1[2]) + eta * (R0[1] * R0[2] + R1[1] * R1[2]);
-    v[5] += a * (D0[2] * D0[2] + D1[2] * D1[2]) + eta * (R0[2] * R0[2] + R1[2] * R1[2]);
-    // residual at X = 0 is built from p4 = (Pc[3], Pc[7], Pc[11])
-    const double o1 = a * (Pc[3] - m.x * Pc[11]), o2 = a * (Pc[7] - m.y * Pc[11]);
-    const double f1 = eta * (Pc[3] - m.x), f2 = eta * (Pc[7] - m.y);
-    h0 -= D0[0] * o1 + D1[0] * o2 + R0[0] * f1 + R1[0] * f2;
-    h1 -= D0[1] * o1 + D1[1] * o2 + R0[1] * f1 + R1[1] * f2;
-    h2 -= D0[2] * o1 + D1[2] * o2 + R0[2] * f1 + R1[2] * f2;
+    if (act) load12(P + (size_t)c * kCam, Pc);
+    else
+#pragma unroll
+      for (int k = 0; k < 12; ++k) Pc[k] = 0.0;
+    double v[6], h[3];
+    obs_normal(Pc, m.x, m.y, a, eta, v, h);
+    const uint32_t links = seg_links(key);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = seg_sum(v[k], links);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) h[k] = seg_sum(h[k], links);
+    const int kn = __shfl_down(key, 1, kWave);
+    const bool tail = act && (lane == kWave - 1 || kn != key);
+    double vp[6] = {0, 0, 0, 0, 0, 0};
+    double X0 = 0, X1 = 0, X2 = 0;
+    if (tail) {
+      sym3_pinv(v, vp);
+      X0 = vp[0] * h[0] + vp[1] * h[1] + vp[2] * h[2];
+      X1 = vp[1] * h[0] + vp[3] * h[1] + vp[4] * h[2];
+      X2 = vp[2] * h[0] + vp[4] * h[1] + vp[5] * h[2];
+    }
+    const int tl = seg_tail_lane(key, tail);
+    X0 = __shfl(X0, tl, kWave);
+    X1 = __shfl(X1, tl, kWave);
+    X2 = __shfl(X2, tl, kWave);
+    double b[3] = {0, 0, 0}, f = 0.0;
+    if (act) f = obs_residual(Pc, m.x, m.y, a, eta, X0, X1, X2, b);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) b[k] = seg_sum(b[k], links);
+    ftot = wave_sum(f);
+    if (tail) store_landmark(D, lc, lm0 + key, vp, X0, X1, X2, b);
+  } else {
+    // a single landmark with more than 64 observations: lanes stride over it
+    double v[6] = {0, 0, 0, 0, 0, 0}, h[3] = {0, 0, 0};
+    for (int e = off + lane; e < off + n; e += kWave) {
+      const int c = (int)(D.pk_code[e] & kCamMask);
+      const double2 m = D.pk_m64[e];
+      double Pc[12], vv[6], hh[3];
+      load12(P + (size_t)c * kCam, Pc);
+      obs_normal(Pc, m.x, m.y, a, eta, vv, hh);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v[k] += vv[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) h[k] += hh[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) h[k] = wave_sum(h[k]);
+    double vp[6];
+    sym3_pinv(v, vp);
+    const double X0 = vp[0] * h[0] + vp[1] * h[1] + vp[2] * h[2];
+    const double X1 = vp[1] * h[0] + vp[3] * h[1] + vp[4] * h[2];
+    const double X2 = vp[2] * h[0] + vp[4] * h[1] + vp[5] * h[2];
+    double b[3] = {0, 0, 0}, f = 0.0;
+    for (int e = off + lane; e < off + n; e += kWave) {
+      const int c = (int)(D.pk_code[e] & kCamMask);
+      const double2 m = D.pk_m64[e];
+      double Pc[12], bb[3];
+      load12(P + (size_t)c * kCam, Pc);
+      f += obs_residual(Pc, m.x, m.y, a, eta, X0, X1, X2, bb);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) b[k] += bb[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) b[k] = wave_sum(b[k]);
+    ftot = wave_sum(f);
+    if (lane == 0) store_landmark(D, lc, lm0, vp, X0, X1, X2, b);
   }
-  double vp[6];
-  sym3_pinv(v, vp);
-  const double X0 = vp[0] * h0 + vp[1] * h1 + vp[2] * h2;
-  const double X1 = vp[1] * h0 + vp[3] * h1 + vp[4] * h2;
-  const double X2 = vp[2] * h0 + vp[4] * h1 + vp[5] * h2;
+  if (lane == 0) D.cost_part[q] = ftot;
+}
 
-  double f = 0, b0 = 0, b1 = 0, b2 = 0;
-  for (int t = 0; t < len; ++t) {
-    const int e = base + t * kWave + lane;
-    const int c = ecam[e];
-    if (c < 0) continue;
-    const double2 m = em[e];
-    double Pc[12];
-    load12(P + (size_t)c * kCam, Pc);
-    const double u = Pc[0] * X0 + Pc[1] * X1 + Pc[2] * X2 + Pc[3];
-    const double vv = Pc[4] * X0 + Pc[5] * X1 + Pc[6] * X2 + Pc[7];
-    const double w = Pc[8] * X0 + Pc[9] * X1 + Pc[10] * X2 + Pc[11];
-    const double o1 = u - m.x * w, o2 = vv - m.y * w;
-    const double f1 = u - m.x, f2 = vv - m.y;
-    f += a * (o1 * o1 + o2 * o2) + eta * (f1 * f1 + f2 * f2);
-    const double ao1 = a * o1, ao2 = a * o2, ef1 = eta * f1, ef2 = eta * f2;
-    b0 += (Pc[0] - m.x * Pc[8]) * ao1 + (Pc[4] - m.y * Pc[8]) * ao2 + Pc[0] * ef1 + Pc[4] * ef2;
-    b1 += (Pc[1] - m.x * Pc[9]) * ao1 + (Pc[5] - m.y * Pc[9]) * ao2 + Pc[1] * ef1 + Pc[5] * ef2;
-    b2 += (Pc[2] - m.x * Pc[10]) * ao1 + (Pc[6] - m.y * Pc[10]) * ao2 + Pc[2] * ef1 + Pc[6] * ef2;
-  }
-  if (j < D.n_l) {
-    const double z0 = vp[0] * b0 + vp[1] * b1 + vp[2] * b2;
-    const double z1 = vp[1] * b0 + vp[3] * b1 + vp[4] * b2;
-    const double z2 = vp[2] * b0 + vp[4] * b1 + vp[5] * b2;
-    store4(D.X64[lc] + (size_t)j * kLmVec, X0, X1, X2, 1.0);
-    store4(D.z064[lc] + (size_t)j * kLmVec, z0, z1, z2, 0.0);
-    double* vo = D.Vp64[lc] + (size_t)j * kLmSym;
-    store4(vo, vp[0], vp[1], vp[2], vp[3]);
-    store4(vo + 4, vp[4], vp[5], 0.0, 0.0);
-    store4(D.X32[lc] + (size_t)j * kLmVec, (float)X0, (float)X1, (float)X2, 1.0f);
-    store4(D.z032[lc] + (size_t)j * kLmVec, (float)z0, (float)z1, (float)z2, 0.0f);
-    float* vo32 = D.Vp32[lc] + (size_t)j * kLmSym;
-    store4(vo32, (float)vp[0], (float)vp[1], (float)vp[2], (float)vp[3]);
-    store4(vo32 + 4, (float)vp[4], (float)vp[5], 0.0f, 0.0f);
-  }
-  // deterministic cost: lane tree per slice, then slices in order
-  f = wave_sum(f);
-  double total = f;
-  if (D.n_sl > 1) {
-    if (lane == 0) D.cost_part[s] = f;
-    if (!arrive_last(D.cost_cnt, (uint32_t)D.n_sl)) return;
-    double acc = 0;
-    for (int q = lane; q < D.n_sl; q += kWave) acc += ld_coherent(D.cost_part + q);
-    total = wave_sum(acc);
-    reset_counter(D.cost_cnt);
-  }
-  if (lane == 0) {
-    if (mode == 0) { ctl->cost = total; ctl->cost0 = total; }
-    else if (mode == 1) ctl->cost_trial = total;
-    else ctl->cost = total;
+// Sum of the per-packet cost partials in packet order (all lanes get it).
+__device__ __forceinline__ double packet_cost_sum(const DevProblem& D) {
+  double acc = 0.0;
+  for (int q = lane_id(); q < D.n_pk; q += kWave) acc += D.cost_part[q];
+  return wave_sum(acc);
+}
+
+// cost of a landmark solve outside the LM loop, one wave per problem:
+// mode 0 initial (cost, cost0), 1 trial (cost_trial), 2 reset (cost)
+__global__ void __launch_bounds__(kWave) k_cost_finalize(Batch B, int mode) {
+  int p, w;
+  if (!map_wave(B, kUnitOne, p, w)) return;
+  DevProblem& D = B.probs[p];
+  const double f = packet_cost_sum(D);
+  if (lane_id() == 0) {
+    if (mode == 1) {
+      D.ctl.cost_trial = f;
+    } else {
+      D.ctl.cost = f;
+      if (mode == 0) D.ctl.cost0 = f;
+    }
   }
 }
 
 // ------------------------------------------------------------- k_linearize
-// One wave per camera chunk.  Accumulates, in FP64, the 40 distinct values
-// of U_i = sum N_k (x) x~x~^T (N has fixed entries 1 and 0 in its top-left
-// 2x2 block, so U_i is made of sum x~x~^T, sum m1 x~x~^T, sum m2 x~x~^T and
-// sum |m|^2 x~x~^T), b_p = sum vec((N y - eta (m,0)) x~^T) and
-// sum_k W_k z0_j = sum vec((N Pbar z0) x~^T).  Products in T.
+// One workgroup per camera chunk.  Accumulates, in FP64, the 40 distinct
+// values of U_i = sum N_k (x) x~x~^T (N has fixed entries 1 and 0 in its
+// top-left 2x2 block, so U_i is made of sum x~x~^T, sum m1 x~x~^T, sum m2 x~x~^T
+// and sum |m|^2 x~x~^T), b_p = sum vec((N y - eta (m,0)) x~^T) and
+// sum_k W_k z0_j = sum vec((N Pbar z0) x~^T); products in T.  Writes one
+// 64-value partial per chunk; k_camera_prep adds a camera's chunks in order.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
   int p, ch;
-  if (!map_wave(B, kUnitChunk, p, ch)) return;
-  const DevProblem& D = B.probs[p];
-  Ctl* ctl = D.ctl;
-  if (ctl->done) return;
-  if (!force && !ctl->need_lin) return;
-  const int lc = ctl->lcur, pc = ctl->pcur;
-  const int lane = lane_id();
+  if (!map_block(B, kUnitChunk, p, ch)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done) return;
+  if (!force && !D.ctl.need_lin) return;
+  const int lc = D.ctl.lcur, pc = D.ctl.pcur;
   const int cam = D.ch_cam[ch];
   const int beg = D.ch_beg[ch], end = D.ch_beg[ch + 1];
   T Pc[12];
   load12(Prec<T>::P(D, pc) + (size_t)cam * kCam, Pc);
-  const T* __restrict__ X = Prec<T>::X(D, lc);
-  const T* __restrict__ Z0 = Prec<T>::z0(D, lc);
+  const T* __restrict__ rec = Prec<T>::rec(D, lc);
   const typename Prec<T>::T2* __restrict__ M = Prec<T>::cm_m(D);
   const int32_t* __restrict__ lm = D.cm_lm;
   const T eta = (T)D.eta, a = (T)(1.0 - D.eta);
@@ -362,25 +461,27 @@ __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
   double acc[kLinVals];
 #pragma unroll
   for (int k = 0; k < kLinVals; ++k) acc[k] = 0.0;
-  for (int e = beg + lane; e < end; e += kWave) {
+#pragma unroll 2
+  for (int r = 0; r < kPerLane; ++r) {
+    const int e = beg + r * kBlock + (int)threadIdx.x;
+    if (e >= end) break;
     const int j = lm[e];
     const auto m = M[e];
-    T x[4], z[4];
-    load4(X + (size_t)j * kLmVec, x[0], x[1], x[2], x[3]);
-    load4(Z0 + (size_t)j * kLmVec, z[0], z[1], z[2], z[3]);
-    x[3] = (T)1;
+    T z[4], x[4];
+    load4(rec + (size_t)j * kRec, z[0], z[1], z[2], z[3]);
+    load4(rec + (size_t)j * kRec + 4, x[0], x[1], x[2], x[3]);
     const T am1 = a * m.x, am2 = a * m.y, msq = m.x * m.x + m.y * m.y, amsq = a * msq;
     T y[3], q[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      y[r] = Pc[4 * r] * x[0] + Pc[4 * r + 1] * x[1] + Pc[4 * r + 2] * x[2] + Pc[4 * r + 3];
-      q[r] = Pc[4 * r] * z[0] + Pc[4 * r + 1] * z[1] + Pc[4 * r + 2] * z[2];
+    for (int rr = 0; rr < 3; ++rr) {
+      y[rr] = Pc[4 * rr] * x[0] + Pc[4 * rr + 1] * x[1] + Pc[4 * rr + 2] * x[2] + Pc[4 * rr + 3];
+      q[rr] = Pc[4 * rr] * z[0] + Pc[4 * rr + 1] * z[1] + Pc[4 * rr + 2] * z[2];
     }
-    T n[3], vq[3];
-    apply_N(am1, am2, amsq, y[0], y[1], y[2], n[0], n[1], n[2]);
+    T nv[3], vq[3];
+    apply_N(am1, am2, amsq, y[0], y[1], y[2], nv[0], nv[1], nv[2]);
     apply_N(am1, am2, amsq, q[0], q[1], q[2], vq[0], vq[1], vq[2]);
-    n[0] -= eta * m.x;
-    n[1] -= eta * m.y;
+    nv[0] -= eta * m.x;
+    nv[1] -= eta * m.y;
     int o = 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -395,49 +496,31 @@ __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
       }
     }
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
+    for (int rr = 0; rr < 3; ++rr) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        acc[40 + 4 * r + c] += (double)(n[r] * x[c]);
-        acc[52 + 4 * r + c] += (double)(vq[r] * x[c]);
+        acc[40 + 4 * rr + c] += (double)(nv[rr] * x[c]);
+        acc[52 + 4 * rr + c] += (double)(vq[rr] * x[c]);
       }
     }
   }
+  __shared__ double red[kWavesPerBlock][kLinVals];
+  const int wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < kLinVals; ++k) acc[k] = wave_sum(acc[k]);
-
-  const int c0 = D.cam_ch[cam], nch = D.cam_ch[cam + 1] - c0;
-  if (nch > 1) {
-    if (lane == 0) {
-      double* part = D.lin_part + (size_t)ch * kLinVals;
-#pragma unroll
-      for (int k = 0; k < kLinVals; ++k) part[k] = acc[k];
-    }
-    if (!arrive_last(D.cam_cnt + cam, (uint32_t)nch)) return;
-#pragma unroll
-    for (int k = 0; k < kLinVals; ++k) acc[k] = 0.0;
-    for (int q = lane; q < nch; q += kWave) {
-      const double* part = D.lin_part + (size_t)(c0 + q) * kLinVals;
-#pragma unroll
-      for (int k = 0; k < kLinVals; ++k) acc[k] += ld_coherent(part + k);
-    }
-#pragma unroll
-    for (int k = 0; k < kLinVals; ++k) acc[k] = wave_sum(acc[k]);
-    reset_counter(D.cam_cnt + cam);
+  for (int k = 0; k < kLinVals; ++k) {
+    const double s = wave_sum(acc[k]);
+    if (lane_id() == 0) red[wv][k] = s;
   }
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < 40; ++k) D.U40[(size_t)cam * 40 + k] = acc[k];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      D.bp[(size_t)cam * kCam + k] = acc[40 + k];
-      D.wz[(size_t)cam * kCam + k] = acc[52 + k];
-    }
+  __syncthreads();
+  if (threadIdx.x < kLinVals) {
+    const int k = threadIdx.x;
+    D.lin_part[(size_t)ch * kLinVals + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
   }
 }
 
 // ----------------------------------------------------------- k_camera_prep
-// One lane per camera, FP64.  U_l = U + lambda diag(U) (floored), then on the
+// One lane per camera, FP64.  After a linearisation it adds the camera's
+// chunk partials in order.  U_l = U + lambda diag(U) (floored), then on the
 // sphere A = Pi U_l Pi + tau p p^T with Pi = I - p p^T, tau = tr(U_l)/12
 // (A restricted to the tangent space is B^T U_l B for any orthonormal basis
 // B of p^perp, and A p = tau p).  K = Pi A^-1 Pi = B (B^T U_l B)^-1 B^T is
@@ -448,19 +531,41 @@ template <typename T>
 __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
   int p, w;
   if (!map_wave(B, kUnitCamWave, p, w)) return;
-  const DevProblem& D = B.probs[p];
-  Ctl* ctl = D.ctl;
-  if (ctl->done) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done) return;
   const int i = w * kWave + lane_id();
   if (i >= D.n_p) return;
-  const double lam = ctl->lambda;
-  const int pc = ctl->pcur;
+  const double lam = D.ctl.lambda;
+  const int pc = D.ctl.pcur;
   const bool sphere = D.manifold == 0;
   const double a = 1.0 - D.eta;
 
-  double u40[40];
+  double u40[40], g[12];
+  if (D.ctl.need_lin) {
+    double s[kLinVals];
 #pragma unroll
-  for (int k = 0; k < 40; ++k) u40[k] = D.U40[(size_t)i * 40 + k];
+    for (int k = 0; k < kLinVals; ++k) s[k] = 0.0;
+    for (int q = D.cam_ch[i]; q < D.cam_ch[i + 1]; ++q) {
+      const double* part = D.lin_part + (size_t)q * kLinVals;
+#pragma unroll
+      for (int k = 0; k < kLinVals; ++k) s[k] += part[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 40; ++k) {
+      u40[k] = s[k];
+      D.U40[(size_t)i * 40 + k] = s[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      g[k] = s[40 + k] - s[52 + k];
+      D.g64[(size_t)i * kCam + k] = g[k];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 40; ++k) u40[k] = D.U40[(size_t)i * 40 + k];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) g[k] = D.g64[(size_t)i * kCam + k];
+  }
   // 4x4 symmetric packed index of (c, d)
   auto s4 = [](int c, int d) { return c <= d ? (c * 7 - c * c) / 2 + d : (d * 7 - d * d) / 2 + c; };
   double L[78];
@@ -484,7 +589,7 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
   for (int r = 0; r < 12; ++r) L[tri(r, r)] += lam * fmax(L[tri(r, r)], 1e-12 * dmax);
 
   double pv[12];
-  load12(D.P64[pc] + (size_t)i * kCam, pv);
+  load12(pc ? D.P64[1] + (size_t)i * kCam : D.P64[0] + (size_t)i * kCam, pv);
   if (sphere) {
     double w12[12], tr = 0.0, s = 0.0;
 #pragma unroll
@@ -554,12 +659,9 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
       wp[r] = v;
     }
   }
-  double g[12], x0[12];
+  double x0[12];
 #pragma unroll
-  for (int r = 0; r < 12; ++r) {
-    g[r] = D.bp[(size_t)i * kCam + r] - D.wz[(size_t)i * kCam + r];
-    x0[r] = 0.0;
-  }
+  for (int r = 0; r < 12; ++r) x0[r] = 0.0;
   double* K64 = D.K64 + (size_t)i * kCamMat;
   float* K32 = D.K32 + (size_t)i * kCamMat;
 #pragma unroll
@@ -586,138 +688,200 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
     x[r] = (T)x0[r];
     acc[r] = (T)x0[r];
   }
-  if (!ok) atomicOr(&ctl->status, 1);
+  if (!ok) atomicOr(&D.ctl.status, 1);
 }
 
 // ------------------------------------------------------- k_series_landmark
-// z_j = V_j^+ sum_k Pbar_i^T N_k (X_i x~_j), X_i = x_i as a 3x4 matrix.
+// z_j = V_j^+ sum_k Pbar_i^T N_k (X_i x~_j), X_i = x_i as a 3x4 matrix; the
+// (z_j, X_j) record is written for the camera pass.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
-  int p, s;
-  if (!map_wave(B, kUnitSlice, p, s)) return;
-  const DevProblem& D = B.probs[p];
-  const Ctl* ctl = D.ctl;
-  if (ctl->done || t > ctl->order) return;
-  const int lc = ctl->lcur, pc = ctl->pcur;
+  int p, q;
+  if (!map_wave(B, kUnitPacket, p, q)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done || t > D.ctl.order) return;
+  const int lc = D.ctl.lcur, pc = D.ctl.pcur;
   const int lane = lane_id();
-  const int j = s * kWave + lane;
-  const int len = D.sl_len[s];
-  const int base = D.sl_off[s];
-  const int32_t* __restrict__ ecam = D.e_cam;
-  const typename Prec<T>::T2* __restrict__ em = Prec<T>::e_m(D);
+  const int n = D.pk_n[q], off = D.pk_off[q], lm0 = D.pk_lm0[q];
+  const T* __restrict__ rec = Prec<T>::rec(D, lc);
   const T* __restrict__ xs = static_cast<const T*>(D.x);
   const T* __restrict__ Pm = Prec<T>::P(D, pc);
+  const typename Prec<T>::T2* __restrict__ em = Prec<T>::pk_m(D);
   const T a = (T)(1.0 - D.eta);
-  if (j >= D.n_l) return;
-  T X0, X1, X2, X3;
-  load4(Prec<T>::X(D, lc) + (size_t)j * kLmVec, X0, X1, X2, X3);
-  T y0 = 0, y1 = 0, y2 = 0;
-  for (int tt = 0; tt < len; ++tt) {
-    const int e = base + tt * kWave + lane;
-    const int c = ecam[e];
-    if (c < 0) break;   // entries of one landmark are contiguous in t; padding only at its end
-    const auto m = em[e];
-    T xc[12], Pc[12];
-    load12(xs + (size_t)c * kCam, xc);
-    load12(Pm + (size_t)c * kCam, Pc);
-    const T q0 = xc[0] * X0 + xc[1] * X1 + xc[2] * X2 + xc[3];
-    const T q1 = xc[4] * X0 + xc[5] * X1 + xc[6] * X2 + xc[7];
-    const T q2 = xc[8] * X0 + xc[9] * X1 + xc[10] * X2 + xc[11];
-    T v0, v1, v2;
-    apply_N(a * m.x, a * m.y, a * (m.x * m.x + m.y * m.y), q0, q1, q2, v0, v1, v2);
-    y0 += Pc[0] * v0 + Pc[4] * v1 + Pc[8] * v2;
-    y1 += Pc[1] * v0 + Pc[5] * v1 + Pc[9] * v2;
-    y2 += Pc[2] * v0 + Pc[6] * v1 + Pc[10] * v2;
+  T* zx = static_cast<T*>(D.zx);
+  if (n <= kWave) {
+    const bool act = lane < n;
+    int key = kWave + lane;
+    T y0 = 0, y1 = 0, y2 = 0, X0 = 0, X1 = 0, X2 = 0, one;
+    if (act) {
+      const uint32_t code = D.pk_code[off + lane];
+      const int c = (int)(code & kCamMask);
+      key = (int)(code >> kCamBits);
+      const auto m = em[off + lane];
+      load4(rec + (size_t)(lm0 + key) * kRec + 4, X0, X1, X2, one);
+      T xc[12], Pc[12];
+      load12(xs + (size_t)c * kCam, xc);
+      load12(Pm + (size_t)c * kCam, Pc);
+      const T q0 = xc[0] * X0 + xc[1] * X1 + xc[2] * X2 + xc[3];
+      const T q1 = xc[4] * X0 + xc[5] * X1 + xc[6] * X2 + xc[7];
+      const T q2 = xc[8] * X0 + xc[9] * X1 + xc[10] * X2 + xc[11];
+      T v0, v1, v2;
+      apply_N(a * m.x, a * m.y, a * (m.x * m.x + m.y * m.y), q0, q1, q2, v0, v1, v2);
+      y0 = Pc[0] * v0 + Pc[4] * v1 + Pc[8] * v2;
+      y1 = Pc[1] * v0 + Pc[5] * v1 + Pc[9] * v2;
+      y2 = Pc[2] * v0 + Pc[6] * v1 + Pc[10] * v2;
+    }
+    const uint32_t links = seg_links(key);
+    y0 = seg_sum(y0, links);
+    y1 = seg_sum(y1, links);
+    y2 = seg_sum(y2, links);
+    const int kn = __shfl_down(key, 1, kWave);
+    const bool tail = act && (lane == kWave - 1 || kn != key);
+    if (tail) {
+      const int j = lm0 + key;
+      T v[8];
+      const T* vp = Prec<T>::Vp(D, lc) + (size_t)j * kLmSym;
+      load4(vp, v[0], v[1], v[2], v[3]);
+      load4(vp + 4, v[4], v[5], v[6], v[7]);
+      const T z0 = v[0] * y0 + v[1] * y1 + v[2] * y2;
+      const T z1 = v[1] * y0 + v[3] * y1 + v[4] * y2;
+      const T z2 = v[2] * y0 + v[4] * y1 + v[5] * y2;
+      store4(zx + (size_t)j * kRec, z0, z1, z2, (T)0);
+      store4(zx + (size_t)j * kRec + 4, X0, X1, X2, (T)1);
+    }
+  } else {
+    T X0, X1, X2, one;
+    load4(rec + (size_t)lm0 * kRec + 4, X0, X1, X2, one);
+    T y0 = 0, y1 = 0, y2 = 0;
+    for (int e = off + lane; e < off + n; e += kWave) {
+      const int c = (int)(D.pk_code[e] & kCamMask);
+      const auto m = em[e];
+      T xc[12], Pc[12];
+      load12(xs + (size_t)c * kCam, xc);
+      load12(Pm + (size_t)c * kCam, Pc);
+      const T q0 = xc[0] * X0 + xc[1] * X1 + xc[2] * X2 + xc[3];
+      const T q1 = xc[4] * X0 + xc[5] * X1 + xc[6] * X2 + xc[7];
+      const T q2 = xc[8] * X0 + xc[9] * X1 + xc[10] * X2 + xc[11];
+      T v0, v1, v2;
+      apply_N(a * m.x, a * m.y, a * (m.x * m.x + m.y * m.y), q0, q1, q2, v0, v1, v2);
+      y0 += Pc[0] * v0 + Pc[4] * v1 + Pc[8] * v2;
+      y1 += Pc[1] * v0 + Pc[5] * v1 + Pc[9] * v2;
+      y2 += Pc[2] * v0 + Pc[6] * v1 + Pc[10] * v2;
+    }
+    y0 = wave_sum(y0);
+    y1 = wave_sum(y1);
+    y2 = wave_sum(y2);
+    if (lane == 0) {
+      T v[8];
+      const T* vp = Prec<T>::Vp(D, lc) + (size_t)lm0 * kLmSym;
+      load4(vp, v[0], v[1], v[2], v[3]);
+      load4(vp + 4, v[4], v[5], v[6], v[7]);
+      const T z0 = v[0] * y0 + v[1] * y1 + v[2] * y2;
+      const T z1 = v[1] * y0 + v[3] * y1 + v[4] * y2;
+      const T z2 = v[2] * y0 + v[4] * y1 + v[5] * y2;
+      store4(zx + (size_t)lm0 * kRec, z0, z1, z2, (T)0);
+      store4(zx + (size_t)lm0 * kRec + 4, X0, X1, X2, (T)1);
+    }
   }
-  T v[8];
-  const T* vp = Prec<T>::Vp(D, lc) + (size_t)j * kLmSym;
-  load4(vp, v[0], v[1], v[2], v[3]);
-  load4(vp + 4, v[4], v[5], v[6], v[7]);
-  const T z0 = v[0] * y0 + v[1] * y1 + v[2] * y2;
-  const T z1 = v[1] * y0 + v[3] * y1 + v[4] * y2;
-  const T z2 = v[2] * y0 + v[4] * y1 + v[5] * y2;
-  store4(static_cast<T*>(D.z) + (size_t)j * kLmVec, z0, z1, z2, (T)0);
 }
 
 // --------------------------------------------------------- k_series_camera
 // t_i = sum_k vec((N_k Pbar_i z_j) x~_j^T); x_i = K_i t_i; acc_i += x_i.
 template <typename T>
-__device__ __forceinline__ void camera_finalize(const DevProblem& D, int cam, const T (&tv)[12]) {
-  const int r = lane_id();
-  if (r >= 12) return;
-  const T* K = Prec<T>::K(D) + (size_t)cam * kCamMat + r * 12;
-  T kr[12];
-  load12(K, kr);
-  T xr = 0;
-#pragma unroll
-  for (int c = 0; c < 12; ++c) xr += kr[c] * tv[c];
-  static_cast<T*>(D.x)[(size_t)cam * kCam + r] = xr;
-  static_cast<T*>(D.acc)[(size_t)cam * kCam + r] += xr;
-}
-
-template <typename T>
 __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
   int p, ch;
-  if (!map_wave(B, kUnitChunk, p, ch)) return;
-  const DevProblem& D = B.probs[p];
-  const Ctl* ctl = D.ctl;
-  if (ctl->done || t > ctl->order) return;
-  const int lc = ctl->lcur, pc = ctl->pcur;
-  const int lane = lane_id();
+  if (!map_block(B, kUnitChunk, p, ch)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done || t > D.ctl.order) return;
+  const int pc = D.ctl.pcur;
   const int cam = D.ch_cam[ch];
   const int beg = D.ch_beg[ch], end = D.ch_beg[ch + 1];
   T Pc[12];
   load12(Prec<T>::P(D, pc) + (size_t)cam * kCam, Pc);
-  const T* __restrict__ X = Prec<T>::X(D, lc);
-  const T* __restrict__ Z = static_cast<const T*>(D.z);
+  const T* __restrict__ zx = static_cast<const T*>(D.zx);
   const typename Prec<T>::T2* __restrict__ M = Prec<T>::cm_m(D);
   const int32_t* __restrict__ lm = D.cm_lm;
   const T a = (T)(1.0 - D.eta);
   T acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = 0;
-  for (int e = beg + lane; e < end; e += kWave) {
-    const int j = lm[e];
-    const auto m = M[e];
-    T x[4], z[4];
-    load4(X + (size_t)j * kLmVec, x[0], x[1], x[2], x[3]);
-    load4(Z + (size_t)j * kLmVec, z[0], z[1], z[2], z[3]);
-    const T q0 = Pc[0] * z[0] + Pc[1] * z[1] + Pc[2] * z[2];
-    const T q1 = Pc[4] * z[0] + Pc[5] * z[1] + Pc[6] * z[2];
-    const T q2 = Pc[8] * z[0] + Pc[9] * z[1] + Pc[10] * z[2];
-    T v[3];
-    apply_N(a * m.x, a * m.y, a * (m.x * m.x + m.y * m.y), q0, q1, q2, v[0], v[1], v[2]);
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      acc[4 * r + 0] += v[r] * x[0];
-      acc[4 * r + 1] += v[r] * x[1];
-      acc[4 * r + 2] += v[r] * x[2];
-      acc[4 * r + 3] += v[r];
+  for (int r = 0; r < kPerLane; ++r) {
+    const int e = beg + r * kBlock + (int)threadIdx.x;
+    if (e < end) {
+      const int j = lm[e];
+      const auto m = M[e];
+      T z[4], x[4];
+      load4(zx + (size_t)j * kRec, z[0], z[1], z[2], z[3]);
+      load4(zx + (size_t)j * kRec + 4, x[0], x[1], x[2], x[3]);
+      const T q0 = Pc[0] * z[0] + Pc[1] * z[1] + Pc[2] * z[2];
+      const T q1 = Pc[4] * z[0] + Pc[5] * z[1] + Pc[6] * z[2];
+      const T q2 = Pc[8] * z[0] + Pc[9] * z[1] + Pc[10] * z[2];
+      T v[3];
+      apply_N(a * m.x, a * m.y, a * (m.x * m.x + m.y * m.y), q0, q1, q2, v[0], v[1], v[2]);
+#pragma unroll
+      for (int rr = 0; rr < 3; ++rr) {
+        acc[4 * rr + 0] += v[rr] * x[0];
+        acc[4 * rr + 1] += v[rr] * x[1];
+        acc[4 * rr + 2] += v[rr] * x[2];
+        acc[4 * rr + 3] += v[rr];
+      }
     }
   }
+  __shared__ T red[kWavesPerBlock][12];
+  __shared__ T tv[12];
+  __shared__ uint32_t last;
+  const int wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = wave_sum(acc[k]);
+  for (int k = 0; k < 12; ++k) {
+    const T s = wave_sum(acc[k]);
+    if (lane_id() == 0) red[wv][k] = s;
+  }
+  __syncthreads();
   const int c0 = D.cam_ch[cam], nch = D.cam_ch[cam + 1] - c0;
-  if (nch > 1) {
-    if (lane == 0) {
-      T* part = static_cast<T*>(D.t_part) + (size_t)ch * kCam;
-      store4(part, acc[0], acc[1], acc[2], acc[3]);
-      store4(part + 4, acc[4], acc[5], acc[6], acc[7]);
-      store4(part + 8, acc[8], acc[9], acc[10], acc[11]);
+  const int k = threadIdx.x;
+  if (nch == 1) {
+    if (k < 12) tv[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  } else {
+    if (k < 12) {
+      static_cast<T*>(D.t_part)[(size_t)ch * kCam + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+      __threadfence();   // release the partial at device scope
     }
-    if (!arrive_last(D.cam_cnt + cam, (uint32_t)nch)) return;
+    __syncthreads();
+    if (k == 0) last = atomicAdd(D.cam_cnt + cam, 1u) == (uint32_t)(nch - 1) ? 1u : 0u;
+    __syncthreads();
+    if (!last) return;
+    if (wv != 0) return;
+    __threadfence();     // acquire the other chunks' partials
+    T s[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = 0;
-    for (int q = lane; q < nch; q += kWave) {
-      const T* part = static_cast<const T*>(D.t_part) + (size_t)(c0 + q) * kCam;
+    for (int kk = 0; kk < 12; ++kk) s[kk] = 0;
+    for (int qq = lane_id(); qq < nch; qq += kWave) {
+      const T* part = static_cast<const T*>(D.t_part) + (size_t)(c0 + qq) * kCam;
 #pragma unroll
-      for (int k = 0; k < 12; ++k) acc[k] += ld_coherent(part + k);
+      for (int kk = 0; kk < 12; ++kk) s[kk] += ld_coherent(part + kk);
     }
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = wave_sum(acc[k]);
-    reset_counter(D.cam_cnt + cam);
+    for (int kk = 0; kk < 12; ++kk) s[kk] = wave_sum(s[kk]);
+    if (k == 0) {
+#pragma unroll
+      for (int kk = 0; kk < 12; ++kk) tv[kk] = s[kk];
+      __hip_atomic_store(D.cam_cnt + cam, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
-  camera_finalize<T>(D, cam, acc);
+  // single chunk: the whole workgroup is here; several: only wave 0 is left
+  if (nch == 1) __syncthreads();
+  else __builtin_amdgcn_wave_barrier();
+  if (k < 12) {
+    const T* Kr = Prec<T>::K(D) + (size_t)cam * kCamMat + k * 12;
+    T kr[12];
+    load12(Kr, kr);
+    T xr = 0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) xr += kr[c] * tv[c];
+    static_cast<T*>(D.x)[(size_t)cam * kCam + k] = xr;
+    static_cast<T*>(D.acc)[(size_t)cam * kCam + k] += xr;
+  }
 }
 
 // --------------------------------------------------------------- k_retract
@@ -725,14 +889,13 @@ template <typename T>
 __global__ void __launch_bounds__(kWave) k_retract(Batch B) {
   int p, w;
   if (!map_wave(B, kUnitCamWave, p, w)) return;
-  const DevProblem& D = B.probs[p];
-  const Ctl* ctl = D.ctl;
-  if (ctl->done) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done) return;
   const int i = w * kWave + lane_id();
   if (i >= D.n_p) return;
-  const int pc = ctl->pcur;
+  const int pc = D.ctl.pcur;
   double q[12];
-  load12(D.P64[pc] + (size_t)i * kCam, q);
+  load12((pc ? D.P64[1] : D.P64[0]) + (size_t)i * kCam, q);
   const T* acc = static_cast<const T*>(D.acc) + (size_t)i * kCam;
   double nrm = 0.0;
 #pragma unroll
@@ -745,8 +908,8 @@ __global__ void __launch_bounds__(kWave) k_retract(Batch B) {
 #pragma unroll
     for (int r = 0; r < 12; ++r) q[r] *= inv;
   }
-  double* o64 = D.P64[pc ^ 1] + (size_t)i * kCam;
-  float* o32 = D.P32[pc ^ 1] + (size_t)i * kCam;
+  double* o64 = (pc ? D.P64[0] : D.P64[1]) + (size_t)i * kCam;
+  float* o32 = (pc ? D.P32[0] : D.P32[1]) + (size_t)i * kCam;
 #pragma unroll
   for (int r = 0; r < 12; r += 4) {
     store4(o64 + r, q[r], q[r + 1], q[r + 2], q[r + 3]);
@@ -755,58 +918,63 @@ __global__ void __launch_bounds__(kWave) k_retract(Batch B) {
 }
 
 // ---------------------------------------------------------------- k_decide
-// Strict decrease accepts (NaN rejects); lambda /10 on accept, x10 on reject,
-// clamped; relinearise only after an accept; ftol on accepted steps.
+// Adds the trial cost partials (packet order), then: strict decrease accepts
+// (NaN rejects); lambda /10 on accept, x10 on reject, clamped; relinearise
+// only after an accept; ftol on accepted steps.  One wave per problem.
 __global__ void __launch_bounds__(kWave) k_decide(Batch B) {
   int p, w;
   if (!map_wave(B, kUnitOne, p, w)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done) return;
+  const double fn = packet_cost_sum(D);
   if (lane_id() != 0) return;
-  const DevProblem& D = B.probs[p];
-  Ctl* ctl = D.ctl;
-  if (ctl->done) return;
-  const double fn = ctl->cost_trial, f = ctl->cost;
+  Ctl& c = D.ctl;
+  const double f = c.cost;
+  c.cost_trial = fn;
   const bool accept = (fn < f) && (fn - fn == 0.0);
-  const int it = ctl->iter;
+  const int it = c.iter;
   if (it < D.trace_cap) {
     D.tr_cost[it] = fn;
-    D.tr_lambda[it] = ctl->lambda;
+    D.tr_lambda[it] = c.lambda;
     D.tr_acc[it] = accept ? 1 : 0;
   }
   if (accept) {
     const double rel = (f - fn) / f;
-    ctl->cost = fn;
-    ctl->lcur ^= 1;
-    ctl->pcur ^= 1;
-    ctl->lambda = fmax(ctl->lambda / 10.0, D.lambda_min);
-    ctl->n_accept += 1;
-    if (rel < D.ftol) { ctl->done = 1; ctl->stop_reason = 1; }
+    c.cost = fn;
+    c.lcur ^= 1;
+    c.pcur ^= 1;
+    c.lambda = fmax(c.lambda / 10.0, D.lambda_min);
+    c.n_accept += 1;
+    if (rel < D.ftol) { c.done = 1; c.stop_reason = 1; }
   } else {
-    ctl->lambda = fmin(ctl->lambda * 10.0, D.lambda_max);
+    c.lambda = fmin(c.lambda * 10.0, D.lambda_max);
   }
-  ctl->need_lin = accept ? 1 : 0;
-  ctl->iter = it + 1;
-  if (ctl->iter >= ctl->iter_limit) ctl->done = 1;
-}
-
-__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  c.need_lin = accept ? 1 : 0;
+  c.iter = it + 1;
+  if (c.iter >= c.iter_limit) c.done = 1;
 }
 
 // ---------------------------------------------------------------- launchers
-static inline dim3 grid_for(int waves, int waves_per_block) {
-  return dim3((unsigned)((waves + waves_per_block - 1) / waves_per_block));
+static inline dim3 blocks_for(int units, int units_per_block) {
+  return dim3((unsigned)((units + units_per_block - 1) / units_per_block));
 }
 
 hipError_t launch_landmark_solve(const Batch& b, int mode, hipStream_t s) {
-  if (b.total[kUnitSlice] == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_landmark_solve, grid_for(b.total[kUnitSlice], kWavesPerBlock), dim3(kBlock), 0, s, b, mode);
+  if (b.total[kUnitPacket] == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_landmark_solve, blocks_for(b.total[kUnitPacket], kWavesPerBlock), dim3(kBlock), 0, s, b,
+                     mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_cost_finalize(const Batch& b, int mode, hipStream_t s) {
+  if (b.total[kUnitOne] == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cost_finalize, blocks_for(b.total[kUnitOne], 1), dim3(kWave), 0, s, b, mode);
   return hipGetLastError();
 }
 
 hipError_t launch_linearize(const Batch& b, bool fp32, int force, hipStream_t s) {
   if (b.total[kUnitChunk] == 0) return hipSuccess;
-  const dim3 g = grid_for(b.total[kUnitChunk], kWavesPerBlock);
+  const dim3 g = blocks_for(b.total[kUnitChunk], 1);
   if (fp32) hipLaunchKernelGGL(k_linearize<float>, g, dim3(kBlock), 0, s, b, force);
   else hipLaunchKernelGGL(k_linearize<double>, g, dim3(kBlock), 0, s, b, force);
   return hipGetLastError();
@@ -814,15 +982,15 @@ hipError_t launch_linearize(const Batch& b, bool fp32, int force, hipStream_t s)
 
 hipError_t launch_camera_prep(const Batch& b, bool fp32, hipStream_t s) {
   if (b.total[kUnitCamWave] == 0) return hipSuccess;
-  const dim3 g = grid_for(b.total[kUnitCamWave], 1);
+  const dim3 g = blocks_for(b.total[kUnitCamWave], 1);
   if (fp32) hipLaunchKernelGGL(k_camera_prep<float>, g, dim3(kWave), 0, s, b);
   else hipLaunchKernelGGL(k_camera_prep<double>, g, dim3(kWave), 0, s, b);
   return hipGetLastError();
 }
 
 hipError_t launch_series_landmark(const Batch& b, bool fp32, int t, hipStream_t s) {
-  if (b.total[kUnitSlice] == 0) return hipSuccess;
-  const dim3 g = grid_for(b.total[kUnitSlice], kWavesPerBlock);
+  if (b.total[kUnitPacket] == 0) return hipSuccess;
+  const dim3 g = blocks_for(b.total[kUnitPacket], kWavesPerBlock);
   if (fp32) hipLaunchKernelGGL(k_series_landmark<float>, g, dim3(kBlock), 0, s, b, t);
   else hipLaunchKernelGGL(k_series_landmark<double>, g, dim3(kBlock), 0, s, b, t);
   return hipGetLastError();
@@ -830,7 +998,7 @@ hipError_t launch_series_landmark(const Batch& b, bool fp32, int t, hipStream_t 
 
 hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s) {
   if (b.total[kUnitChunk] == 0) return hipSuccess;
-  const dim3 g = grid_for(b.total[kUnitChunk], kWavesPerBlock);
+  const dim3 g = blocks_for(b.total[kUnitChunk], 1);
   if (fp32) hipLaunchKernelGGL(k_series_camera<float>, g, dim3(kBlock), 0, s, b, t);
   else hipLaunchKernelGGL(k_series_camera<double>, g, dim3(kBlock), 0, s, b, t);
   return hipGetLastError();
@@ -838,7 +1006,7 @@ hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s)
 
 hipError_t launch_retract(const Batch& b, bool fp32, hipStream_t s) {
   if (b.total[kUnitCamWave] == 0) return hipSuccess;
-  const dim3 g = grid_for(b.total[kUnitCamWave], 1);
+  const dim3 g = blocks_for(b.total[kUnitCamWave], 1);
   if (fp32) hipLaunchKernelGGL(k_retract<float>, g, dim3(kWave), 0, s, b);
   else hipLaunchKernelGGL(k_retract<double>, g, dim3(kWave), 0, s, b);
   return hipGetLastError();
@@ -846,13 +1014,7 @@ hipError_t launch_retract(const Batch& b, bool fp32, hipStream_t s) {
 
 hipError_t launch_decide(const Batch& b, hipStream_t s) {
   if (b.total[kUnitOne] == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_decide, grid_for(b.total[kUnitOne], 1), dim3(kWave), 0, s, b);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  hipLaunchKernelGGL(k_decide, blocks_for(b.total[kUnitOne], 1), dim3(kWave), 0, s, b);
   return hipGetLastError();
 }
 

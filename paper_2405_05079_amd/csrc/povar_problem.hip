@@ -48,17 +48,18 @@ struct ArenaPlan {
   }
 };
 
-size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_ent, int64_t n_sl, int64_t n_ch,
-                   bool fp32, int64_t trace_cap, ArenaOffsets* o) {
+size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_t n_ch, bool fp32,
+                   int64_t trace_cap, ArenaOffsets* o) {
   ArenaPlan a;
   ArenaOffsets tmp;
   ArenaOffsets& r = o ? *o : tmp;
   const size_t ts = fp32 ? 4 : 8;
-  r.sl_off = a.take((n_sl + 1) * 4);
-  r.sl_len = a.take(n_sl * 4);
-  r.e_cam = a.take(n_ent * 4);
-  r.e_m32 = fp32 ? a.take(n_ent * 8) : SIZE_MAX;
-  r.e_m64 = a.take(n_ent * 16);
+  r.pk_off = a.take(n_pk * 4);
+  r.pk_n = a.take(n_pk * 4);
+  r.pk_lm0 = a.take(n_pk * 4);
+  r.pk_code = a.take(n_obs * 4);
+  r.pk_m32 = fp32 ? a.take(n_obs * 8) : SIZE_MAX;
+  r.pk_m64 = a.take(n_obs * 16);
   r.cm_lm = a.take(n_obs * 4);
   r.cm_m32 = fp32 ? a.take(n_obs * 8) : SIZE_MAX;
   r.cm_m64 = fp32 ? SIZE_MAX : a.take(n_obs * 16);
@@ -68,27 +69,22 @@ size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_ent, int64
   for (int b = 0; b < 2; ++b) {
     r.P64[b] = a.take(n_p * kCam * 8);
     r.P32[b] = a.take(n_p * kCam * 4);
-    r.X64[b] = a.take(n_l * kLmVec * 8);
+    r.rec64[b] = a.take(n_l * kRec * 8);
+    r.rec32[b] = a.take(n_l * kRec * 4);
     r.Vp64[b] = a.take(n_l * kLmSym * 8);
-    r.z064[b] = a.take(n_l * kLmVec * 8);
-    r.X32[b] = a.take(n_l * kLmVec * 4);
     r.Vp32[b] = a.take(n_l * kLmSym * 4);
-    r.z032[b] = a.take(n_l * kLmVec * 4);
   }
-  r.U40 = a.take(n_p * 40 * 8);
-  r.bp = a.take(n_p * kCam * 8);
-  r.wz = a.take(n_p * kCam * 8);
   r.lin_part = a.take(n_ch * kLinVals * 8);
   r.K64 = a.take(n_p * kCamMat * 8);
   r.K32 = a.take(n_p * kCamMat * 4);
+  r.g64 = a.take(n_p * kCam * 8);
+  r.U40 = a.take(n_p * 40 * 8);
   r.x = a.take(n_p * kCam * ts);
   r.acc = a.take(n_p * kCam * ts);
-  r.z = a.take(n_l * kLmVec * ts);
+  r.zx = a.take(n_l * kRec * ts);
   r.t_part = a.take(n_ch * kCam * ts);
   r.cam_cnt = a.take(n_p * 4);
-  r.cost_part = a.take(n_sl * 8);
-  r.cost_cnt = a.take(4);
-  r.ctl = a.take(sizeof(Ctl));
+  r.cost_part = a.take(n_pk * 8);
   r.tr_cost = a.take(trace_cap * 8);
   r.tr_lambda = a.take(trace_cap * 8);
   r.tr_acc = a.take(trace_cap * 4);
@@ -139,11 +135,15 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
       set_error(ctx, "point %d has no observation", j);
       return POVAR_EINVAL;
     }
-  // internal landmark order: decreasing track length, then caller's index
+  // internal landmark order: by the smallest camera that sees the landmark,
+  // then caller's index (landmarks sharing a camera sit close together, which
+  // helps the camera-major gathers)
+  std::vector<int32_t> minc(n_l, INT_MAX);
+  for (int64_t k = 0; k < n_obs; ++k) minc[pt[k]] = std::min(minc[pt[k]], cam[k]);
   L.int2ext.resize(n_l);
   std::iota(L.int2ext.begin(), L.int2ext.end(), 0);
   std::stable_sort(L.int2ext.begin(), L.int2ext.end(),
-                   [&](int32_t a, int32_t b) { return cnt_l[a] > cnt_l[b]; });
+                   [&](int32_t a, int32_t b) { return minc[a] < minc[b]; });
   // observations grouped by caller's landmark, then sorted by camera
   std::vector<int64_t> lstart(n_l + 1, 0);
   for (int32_t j = 0; j < n_l; ++j) lstart[j + 1] = lstart[j] + cnt_l[j];
@@ -155,41 +155,41 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
   for (int32_t j = 0; j < n_l; ++j)
     std::stable_sort(lobs.begin() + lstart[j], lobs.begin() + lstart[j + 1],
                      [&](int64_t a, int64_t b) { return cam[a] < cam[b]; });
-  // landmark-major slices
-  L.n_sl = (n_l + kWave - 1) / kWave;
-  L.sl_len.resize(L.n_sl);
-  L.sl_off.resize(L.n_sl + 1);
-  L.sl_off[0] = 0;
-  int64_t ent = 0;
-  for (int s = 0; s < L.n_sl; ++s) {
-    L.sl_len[s] = cnt_l[L.int2ext[(size_t)s * kWave]];
-    ent += (int64_t)kWave * L.sl_len[s];
-    if (ent >= (int64_t)INT_MAX) {
-      set_error(ctx, "landmark slice layout exceeds 2^31 entries");
-      return POVAR_EINVAL;
-    }
-    L.sl_off[s + 1] = (int32_t)ent;
+  if (n_p > (int32_t)kCamMask) {
+    set_error(ctx, "n_cams exceeds the supported maximum");
+    return POVAR_EINVAL;
   }
-  L.n_ent = ent;
-  L.e_cam.assign(ent, -1);
-  L.e_m64.assign(2 * ent, 0.0);
-  if (fp32) L.e_m32.assign(2 * ent, 0.0f);
+  // landmark-major packets: greedy runs of whole landmarks with <= 64
+  // observations; a landmark with more than 64 observations is a packet alone
+  L.pk_code.resize(n_obs);
+  L.pk_m64.resize(2 * n_obs);
+  if (fp32) L.pk_m32.resize(2 * n_obs);
+  int64_t ent = 0;
+  int32_t open_n = 0;
   for (int32_t jj = 0; jj < n_l; ++jj) {
     const int32_t j = L.int2ext[jj];
-    const int s = jj / kWave, lane = jj % kWave;
-    int t = 0;
-    for (int64_t q = lstart[j]; q < lstart[j + 1]; ++q, ++t) {
+    const int32_t len = cnt_l[j];
+    if (len > kWave || open_n + len > kWave || open_n == 0) {
+      L.pk_off.push_back((int32_t)ent);
+      L.pk_n.push_back(0);
+      L.pk_lm0.push_back(jj);
+      open_n = 0;
+    }
+    const int32_t local = jj - L.pk_lm0.back();
+    for (int64_t q = lstart[j]; q < lstart[j + 1]; ++q, ++ent) {
       const int64_t k = lobs[q];
-      const int64_t e = (int64_t)L.sl_off[s] + (int64_t)t * kWave + lane;
-      L.e_cam[e] = cam[k];
-      L.e_m64[2 * e] = meas[2 * k];
-      L.e_m64[2 * e + 1] = meas[2 * k + 1];
+      L.pk_code[ent] = (uint32_t)cam[k] | ((uint32_t)local << kCamBits);
+      L.pk_m64[2 * ent] = meas[2 * k];
+      L.pk_m64[2 * ent + 1] = meas[2 * k + 1];
       if (fp32) {
-        L.e_m32[2 * e] = (float)meas[2 * k];
-        L.e_m32[2 * e + 1] = (float)meas[2 * k + 1];
+        L.pk_m32[2 * ent] = (float)meas[2 * k];
+        L.pk_m32[2 * ent + 1] = (float)meas[2 * k + 1];
       }
     }
+    L.pk_n.back() += len;
+    open_n = len > kWave ? kWave : open_n + len;   // a long landmark closes its packet
   }
+  L.n_pk = (int32_t)L.pk_off.size();
   // camera-major order: by camera, then internal landmark
   std::vector<int64_t> cstart(n_p + 1, 0);
   for (int32_t i = 0; i < n_p; ++i) cstart[i + 1] = cstart[i] + cnt_c[i];
@@ -300,7 +300,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   pb->L = std::move(L);
   HostLayout& H = pb->L;
   ArenaOffsets& A = pb->off;
-  pb->bytes = arena_bytes(H.n_p, H.n_l, H.n_obs, H.n_ent, H.n_sl, H.n_ch, pb->fp32, pb->trace_cap, &A);
+  pb->bytes = arena_bytes(H.n_p, H.n_l, H.n_obs, H.n_pk, H.n_ch, pb->fp32, pb->trace_cap, &A);
   hipError_t e = hipMalloc(&pb->arena, pb->bytes);
   if (e != hipSuccess) {
     pb->arena = nullptr;
@@ -338,7 +338,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   std::memset(&R, 0, sizeof(R));
   R.n_p = H.n_p;
   R.n_l = H.n_l;
-  R.n_sl = H.n_sl;
+  R.n_pk = H.n_pk;
   R.n_ch = H.n_ch;
   R.manifold = o->manifold;
   R.trace_cap = pb->trace_cap;
@@ -346,11 +346,12 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.ftol = o->ftol;
   R.lambda_min = o->lambda_min;
   R.lambda_max = o->lambda_max;
-  R.sl_off = (const int32_t*)dp(A.sl_off);
-  R.sl_len = (const int32_t*)dp(A.sl_len);
-  R.e_cam = (const int32_t*)dp(A.e_cam);
-  R.e_m32 = (const float2*)dp(A.e_m32);
-  R.e_m64 = (const double2*)dp(A.e_m64);
+  R.pk_off = (const int32_t*)dp(A.pk_off);
+  R.pk_n = (const int32_t*)dp(A.pk_n);
+  R.pk_lm0 = (const int32_t*)dp(A.pk_lm0);
+  R.pk_code = (const uint32_t*)dp(A.pk_code);
+  R.pk_m32 = (const float2*)dp(A.pk_m32);
+  R.pk_m64 = (const double2*)dp(A.pk_m64);
   R.cm_lm = (const int32_t*)dp(A.cm_lm);
   R.cm_m32 = (const float2*)dp(A.cm_m32);
   R.cm_m64 = (const double2*)dp(A.cm_m64);
@@ -360,40 +361,34 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   for (int b = 0; b < 2; ++b) {
     R.P64[b] = (double*)dp(A.P64[b]);
     R.P32[b] = (float*)dp(A.P32[b]);
-    R.X64[b] = (double*)dp(A.X64[b]);
+    R.rec64[b] = (double*)dp(A.rec64[b]);
+    R.rec32[b] = (float*)dp(A.rec32[b]);
     R.Vp64[b] = (double*)dp(A.Vp64[b]);
-    R.z064[b] = (double*)dp(A.z064[b]);
-    R.X32[b] = (float*)dp(A.X32[b]);
     R.Vp32[b] = (float*)dp(A.Vp32[b]);
-    R.z032[b] = (float*)dp(A.z032[b]);
   }
-  R.U40 = (double*)dp(A.U40);
-  R.bp = (double*)dp(A.bp);
-  R.wz = (double*)dp(A.wz);
   R.lin_part = (double*)dp(A.lin_part);
   R.K64 = (double*)dp(A.K64);
   R.K32 = (float*)dp(A.K32);
+  R.g64 = (double*)dp(A.g64);
+  R.U40 = (double*)dp(A.U40);
   R.x = dp(A.x);
   R.acc = dp(A.acc);
-  R.z = dp(A.z);
+  R.zx = dp(A.zx);
   R.t_part = dp(A.t_part);
   R.cam_cnt = (uint32_t*)dp(A.cam_cnt);
   R.cost_part = (double*)dp(A.cost_part);
-  R.cost_cnt = (uint32_t*)dp(A.cost_cnt);
-  R.ctl = (Ctl*)dp(A.ctl);
   R.tr_cost = (double*)dp(A.tr_cost);
   R.tr_lambda = (double*)dp(A.tr_lambda);
   R.tr_acc = (int32_t*)dp(A.tr_acc);
 
-  Ctl c;
-  std::memset(&c, 0, sizeof(c));
+  Ctl& c = R.ctl;
   c.lambda = o->lambda0;
   c.need_lin = 1;
   c.iter_limit = INT_MAX;
   c.order = o->series_order;
 
   // batch of one: prefix tables of waves per unit kind
-  const int32_t units[kNumUnitKinds] = {H.n_sl, H.n_ch, (H.n_p + kWave - 1) / kWave, 1};
+  const int32_t units[kNumUnitKinds] = {H.n_pk, H.n_ch, (H.n_p + kWave - 1) / kWave, 1};
   int32_t tables[kNumUnitKinds * 2];
   for (int k = 0; k < kNumUnitKinds; ++k) {
     tables[2 * k] = 0;
@@ -402,11 +397,12 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
 
   // one staging image of everything that has an initial value
   std::vector<char> img(pb->bytes, 0);
-  upload(img, A.sl_off, H.sl_off);
-  upload(img, A.sl_len, H.sl_len);
-  upload(img, A.e_cam, H.e_cam);
-  if (A.e_m32 != SIZE_MAX) upload(img, A.e_m32, H.e_m32);
-  upload(img, A.e_m64, H.e_m64);
+  upload(img, A.pk_off, H.pk_off);
+  upload(img, A.pk_n, H.pk_n);
+  upload(img, A.pk_lm0, H.pk_lm0);
+  upload(img, A.pk_code, H.pk_code);
+  if (A.pk_m32 != SIZE_MAX) upload(img, A.pk_m32, H.pk_m32);
+  upload(img, A.pk_m64, H.pk_m64);
   upload(img, A.cm_lm, H.cm_lm);
   if (A.cm_m32 != SIZE_MAX) upload(img, A.cm_m32, H.cm_m32);
   if (A.cm_m64 != SIZE_MAX) upload(img, A.cm_m64, H.cm_m64);
@@ -415,13 +411,12 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   upload(img, A.cam_ch, H.cam_ch);
   upload(img, A.P64[0], P64);
   upload(img, A.P32[0], P32);
-  std::memcpy(img.data() + A.ctl, &c, sizeof(c));
   std::memcpy(img.data() + A.rec, &R, sizeof(R));
   std::memcpy(img.data() + A.tables, tables, sizeof(tables));
   HIP_TRY(ctx, hipMemcpyAsync(pb->arena, img.data(), pb->bytes, hipMemcpyHostToDevice, stream));
 
   Batch& B = pb->batch;
-  B.probs = (const DevProblem*)dp(A.rec);
+  B.probs = (DevProblem*)dp(A.rec);
   for (int k = 0; k < kNumUnitKinds; ++k) {
     B.off[k] = (const int32_t*)dp(A.tables) + 2 * k;
     B.total[k] = units[k];
@@ -429,16 +424,17 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   B.n_prob = 1;
   // initial landmarks and cost, Eq. (8)-(9)
   HIP_TRY(ctx, launch_landmark_solve(B, 0, stream));
+  HIP_TRY(ctx, launch_cost_finalize(B, 0, stream));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
   // free the host copies of what only the device needs
   HostLayout keep;
   keep.n_p = H.n_p;
   keep.n_l = H.n_l;
   keep.n_obs = H.n_obs;
-  keep.n_ent = H.n_ent;
-  keep.n_sl = H.n_sl;
+  keep.n_pk = H.n_pk;
   keep.n_ch = H.n_ch;
   keep.int2ext = std::move(H.int2ext);
+  keep.cam_ch = std::move(H.cam_ch);
   H = std::move(keep);
   Ctl now;
   HIP_TRY(ctx, read_ctl(pb, &now));
@@ -450,13 +446,13 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
 }
 
 hipError_t read_ctl(povar_problem_s* pb, Ctl* out) {
-  hipError_t e = hipMemcpyAsync(out, pb->rec.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, pb->stream);
+  hipError_t e = hipMemcpyAsync(out, pb->batch.probs, sizeof(Ctl), hipMemcpyDeviceToHost, pb->stream);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(pb->stream);
 }
 
 hipError_t write_ctl(povar_problem_s* pb, const Ctl* in) {
-  hipError_t e = hipMemcpyAsync(pb->rec.ctl, in, sizeof(Ctl), hipMemcpyHostToDevice, pb->stream);
+  hipError_t e = hipMemcpyAsync(pb->batch.probs, in, sizeof(Ctl), hipMemcpyHostToDevice, pb->stream);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(pb->stream);
 }
@@ -658,13 +654,11 @@ povar_status povar_problem_footprint(int32_t n_cams, int32_t n_pts, int64_t n_ob
                                      uint64_t* bytes) {
   if (!bytes || n_cams <= 0 || n_pts <= 0 || n_obs <= 0) return POVAR_EINVAL;
   if (precision != POVAR_PREC_FP64 && precision != POVAR_PREC_FP32_BULK) return POVAR_EINVAL;
-  // upper bounds for problems without repeated (camera, point) pairs: slice
-  // padding adds at most 64 x the longest track (<= n_cams) entries, chunk
-  // rounding at most one chunk per camera
-  const int64_t n_sl = (n_pts + kWave - 1) / kWave;
-  const int64_t n_ent = n_obs + (int64_t)kWave * std::min<int64_t>(n_cams, n_obs);
+  // upper bounds: a packet holds at least one landmark; chunk rounding adds
+  // at most one chunk per camera
+  const int64_t n_pk = n_pts;
   const int64_t n_ch = n_obs / kChunk + n_cams;
-  *bytes = arena_bytes(n_cams, n_pts, n_obs, n_ent, n_sl, n_ch, precision == POVAR_PREC_FP32_BULK,
+  *bytes = arena_bytes(n_cams, n_pts, n_obs, n_pk, n_ch, precision == POVAR_PREC_FP32_BULK,
                        kTraceCap, nullptr);
   return POVAR_OK;
 }
@@ -789,13 +783,14 @@ povar_status povar_get_cameras(povar_problem pb, double* out) {
   return POVAR_OK;
 }
 
-static povar_status copy_landmark_vec(povar_problem pb, const double* dev, int stride, int width, double* out) {
+static povar_status copy_landmark_vec(povar_problem pb, const double* dev, int stride, int offset, int width,
+                                      double* out) {
   std::vector<double> tmp((size_t)pb->L.n_l * stride);
   HIP_TRY(pb->ctx, hipMemcpyAsync(tmp.data(), dev, tmp.size() * 8, hipMemcpyDeviceToHost, pb->stream));
   HIP_TRY(pb->ctx, hipStreamSynchronize(pb->stream));
   for (int32_t jj = 0; jj < pb->L.n_l; ++jj) {
     const int32_t j = pb->L.int2ext[jj];
-    for (int k = 0; k < width; ++k) out[(size_t)j * width + k] = tmp[(size_t)jj * stride + k];
+    for (int k = 0; k < width; ++k) out[(size_t)j * width + k] = tmp[(size_t)jj * stride + offset + k];
   }
   return POVAR_OK;
 }
@@ -804,7 +799,7 @@ povar_status povar_get_points(povar_problem pb, double* out) {
   if (!pb || !out) return POVAR_EINVAL;
   Ctl c;
   HIP_TRY(pb->ctx, read_ctl(pb, &c));
-  return copy_landmark_vec(pb, pb->rec.X64[c.lcur], kLmVec, 3, out);
+  return copy_landmark_vec(pb, pb->rec.rec64[c.lcur], kRec, 4, 3, out);
 }
 
 povar_status povar_get_trace(povar_problem pb, int32_t n, double* cost, double* lam, int32_t* acc) {
@@ -869,6 +864,7 @@ povar_status povar_set_state(povar_problem pb, const double* cams, double lambda
   c.status = 0;
   HIP_TRY(ctx, write_ctl(pb, &c));
   HIP_TRY(ctx, launch_landmark_solve(pb->batch, 2, pb->stream));
+  HIP_TRY(ctx, launch_cost_finalize(pb->batch, 2, pb->stream));
   HIP_TRY(ctx, read_ctl(pb, &c));
   if (!std::isfinite(c.cost)) {
     set_error(ctx, "cost at the given cameras is not finite");
@@ -891,10 +887,8 @@ povar_status povar_debug_linearize(povar_problem pb, double* U, double* bp, doub
   HIP_TRY(ctx, launch_linearize(pb->batch, pb->fp32, 1, pb->stream));
   HIP_TRY(ctx, hipStreamSynchronize(pb->stream));
   const int32_t n_p = pb->L.n_p;
-  std::vector<double> u40((size_t)n_p * 40), b((size_t)n_p * kCam), w((size_t)n_p * kCam);
-  HIP_TRY(ctx, hipMemcpyAsync(u40.data(), pb->rec.U40, u40.size() * 8, hipMemcpyDeviceToHost, pb->stream));
-  HIP_TRY(ctx, hipMemcpyAsync(b.data(), pb->rec.bp, b.size() * 8, hipMemcpyDeviceToHost, pb->stream));
-  HIP_TRY(ctx, hipMemcpyAsync(w.data(), pb->rec.wz, w.size() * 8, hipMemcpyDeviceToHost, pb->stream));
+  std::vector<double> part((size_t)pb->L.n_ch * kLinVals);
+  HIP_TRY(ctx, hipMemcpyAsync(part.data(), pb->rec.lin_part, part.size() * 8, hipMemcpyDeviceToHost, pb->stream));
   HIP_TRY(ctx, hipStreamSynchronize(pb->stream));
   const double a = 1.0 - pb->opt.eta;
   auto s4 = [](int c0, int d0) {
@@ -902,7 +896,10 @@ povar_status povar_debug_linearize(povar_problem pb, double* U, double* bp, doub
     return (lo * 7 - lo * lo) / 2 + hi;
   };
   for (int32_t i = 0; i < n_p; ++i) {
-    const double* q = u40.data() + (size_t)i * 40;
+    // chunk partials of camera i added in chunk order, as the kernels do
+    double q[kLinVals] = {0};
+    for (int32_t ch = pb->L.cam_ch[i]; ch < pb->L.cam_ch[i + 1]; ++ch)
+      for (int k = 0; k < kLinVals; ++k) q[k] += part[(size_t)ch * kLinVals + k];
     if (U)
       for (int r = 0; r < 12; ++r)
         for (int cc = 0; cc < 12; ++cc) {
@@ -914,8 +911,8 @@ povar_status povar_debug_linearize(povar_problem pb, double* U, double* bp, doub
           U[(size_t)i * 144 + r * 12 + cc] = v;
         }
     for (int r = 0; r < kCam; ++r) {
-      if (bp) bp[(size_t)i * kCam + r] = b[(size_t)i * kCam + r];
-      if (g) g[(size_t)i * kCam + r] = b[(size_t)i * kCam + r] - w[(size_t)i * kCam + r];
+      if (bp) bp[(size_t)i * kCam + r] = q[40 + r];
+      if (g) g[(size_t)i * kCam + r] = q[40 + r] - q[52 + r];
     }
   }
   if (Vp) {
@@ -929,11 +926,11 @@ povar_status povar_debug_linearize(povar_problem pb, double* U, double* bp, doub
     }
   }
   if (X) {
-    povar_status st = copy_landmark_vec(pb, pb->rec.X64[c.lcur], kLmVec, 3, X);
+    povar_status st = copy_landmark_vec(pb, pb->rec.rec64[c.lcur], kRec, 4, 3, X);
     if (st != POVAR_OK) return st;
   }
   if (z0) {
-    povar_status st = copy_landmark_vec(pb, pb->rec.z064[c.lcur], kLmVec, 3, z0);
+    povar_status st = copy_landmark_vec(pb, pb->rec.rec64[c.lcur], kRec, 0, 3, z0);
     if (st != POVAR_OK) return st;
   }
   if (cost) *cost = c.cost;
@@ -965,6 +962,7 @@ povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, do
   }
   HIP_TRY(ctx, launch_retract(B, pb->fp32, pb->stream));
   HIP_TRY(ctx, launch_landmark_solve(B, 1, pb->stream));
+  HIP_TRY(ctx, launch_cost_finalize(B, 1, pb->stream));
   Ctl after;
   HIP_TRY(ctx, read_ctl(pb, &after));
   const int32_t n_p = pb->L.n_p;
@@ -1016,11 +1014,11 @@ povar_status povar_kernel_times(povar_problem pb, double* ms_l, int64_t* n_l, do
   return POVAR_OK;
 }
 
-povar_status povar_problem_info(povar_problem pb, int64_t* n_obs, int64_t* slice_entries, int32_t* n_chunks,
+povar_status povar_problem_info(povar_problem pb, int64_t* n_obs, int64_t* n_packets, int32_t* n_chunks,
                                 uint64_t* device_bytes) {
   if (!pb) return POVAR_EINVAL;
   if (n_obs) *n_obs = pb->L.n_obs;
-  if (slice_entries) *slice_entries = pb->L.n_ent;
+  if (n_packets) *n_packets = pb->L.n_pk;
   if (n_chunks) *n_chunks = pb->L.n_ch;
   if (device_bytes) *device_bytes = pb->bytes;
   return POVAR_OK;

@@ -288,7 +288,7 @@ class Problem:
         c = C.c_int32()
         self._chk(lib().povar_problem_info(self.handle, C.byref(a), C.byref(b), C.byref(c), C.byref(d)),
                   "povar_problem_info")
-        return dict(n_obs=a.value, slice_entries=b.value, n_chunks=c.value, device_bytes=d.value)
+        return dict(n_obs=a.value, n_packets=b.value, n_chunks=c.value, device_bytes=d.value)
 
     def close(self):
         if self.handle:

@@ -114,8 +114,11 @@ def test_camera_step_fp32_bulk(ctx, lam, order):
 
 def test_many_cameras_and_many_chunks_per_camera(ctx):
     """More than one wave of cameras (per-camera kernels span several
-    workgroups) and cameras whose observations span tens of chunks."""
-    for n_cams, n_pts, track in ((150, 3000, ("uniform", 3, 6)), (3, 4000, ("uniform", 3, 3))):
+    workgroups), cameras whose observations span many chunks, and landmarks
+    seen by more than 64 cameras (a packet of their own)."""
+    for n_cams, n_pts, track in ((150, 3000, ("uniform", 3, 6)),      # 3 waves of cameras
+                                 (2, 20000, ("uniform", 2, 2)),       # 10 chunks per camera
+                                 (100, 50, ("uniform", 60, 90))):     # landmarks with > 64 observations
         prob = synth.make_problem(n_cams, n_pts, track=track, seed=21)
         say("many", n_cams, n_pts)
         gp = povar.Problem.from_synth(ctx, prob, precision="fp64")
