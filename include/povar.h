@@ -58,7 +58,9 @@ typedef enum {
   /* every step of the path in FP64 */
   POVAR_PREC_FP64 = 0,
   /* Jacobian evaluation and power-series matvecs in FP32 with FP32
-     accumulation; V_j inversion, U_i factorisation and the cost in FP64.
+     accumulation (the per-observation products and their per-landmark and
+     per-camera sums); the V_j pseudo-inverse, the U_i factorisation (and
+     their application to those sums inside the series) and the cost in FP64.
      U_i and b_p are FP32 products accumulated in FP64. */
   POVAR_PREC_FP32_BULK = 1
 } povar_precision;

@@ -41,8 +41,8 @@ struct HostLayout {
 // (SIZE_MAX = not allocated for this precision).
 struct ArenaOffsets {
   size_t pk_off, pk_n, pk_lm0, pk_code, pk_m32, pk_m64, cm_lm, cm_m32, cm_m64, ch_beg, ch_cam, cam_ch;
-  size_t P64[2], P32[2], rec64[2], rec32[2], Vp64[2], Vp32[2];
-  size_t lin_part, K64, K32, g64, U40, x, acc, zx, t_part, cam_cnt, cost_part;
+  size_t P64[2], P32[2], rec64[2], rec32[2], Vp64[2];
+  size_t lin_part, K64, g64, U40, x, acc, zx, t_part, cam_cnt, cost_part;
   size_t tr_cost, tr_lambda, tr_acc, rec, tables;
 };
 
@@ -88,8 +88,12 @@ struct povar_problem_s {
 };
 
 namespace povar {
+// Allocates and fills the device state of a problem and solves its initial
+// landmarks.  rec_dev: where the problem record lives (NULL: in its arena).
 povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, const povar_options* o,
-                          hipStream_t stream, povar_problem_s* pb);
+                          hipStream_t stream, povar_problem_s* pb, DevProblem* rec_dev, int32_t iter_limit);
+size_t layout_footprint(const HostLayout& L, bool fp32);
+povar_status copy_points(povar_problem_s* pb, int lcur, double* out);
 hipError_t read_ctl(povar_problem_s* pb, Ctl* out);
 hipError_t write_ctl(povar_problem_s* pb, const Ctl* in);
 hipError_t enqueue_iteration(povar_problem_s* pb, bool timed);

@@ -82,18 +82,16 @@ struct DevProblem {
   double* rec64[2];         // n_l x 8
   float* rec32[2];
   double* Vp64[2];          // n_l x 8
-  float* Vp32[2];
 
   // linearisation per camera
   double* lin_part;         // n_ch x 64 chunk partials: 40 U values, b_p, sum W z0
   // damped, projected, inverted camera blocks K_i = Pi (Pi U_l Pi + tau p p^T)^-1 Pi
   double* K64;              // n_p x 144
-  float* K32;
   double* g64;              // n_p x 12  b_p - sum W V^+ b_l  (kept for inspection)
   double* U40;              // n_p x 40  combined U values (kept for inspection)
-  // power-series work vectors (series precision)
-  void* x;                  // n_p x 12, current term
-  void* acc;                // n_p x 12, partial sum x(m)
+  // power-series work vectors
+  void* x;                  // n_p x 12, current term (series precision)
+  double* acc;              // n_p x 12, partial sum x(m) (FP64)
   void* zx;                 // n_l x 8, (z, X) records of the current order
   void* t_part;             // n_ch x 12 chunk partials
   uint32_t* cam_cnt;        // n_p arrival counters (reset by the last workgroup)

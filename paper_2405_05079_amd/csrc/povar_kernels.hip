@@ -119,8 +119,6 @@ template <> struct Prec<float> {
   __device__ static const float2* pk_m(const DevProblem& D) { return D.pk_m32; }
   __device__ static const float* P(const DevProblem& D, int b) { return b ? D.P32[1] : D.P32[0]; }
   __device__ static const float* rec(const DevProblem& D, int b) { return b ? D.rec32[1] : D.rec32[0]; }
-  __device__ static const float* Vp(const DevProblem& D, int b) { return b ? D.Vp32[1] : D.Vp32[0]; }
-  __device__ static const float* K(const DevProblem& D) { return D.K32; }
 };
 template <> struct Prec<double> {
   using T2 = double2;
@@ -128,8 +126,6 @@ template <> struct Prec<double> {
   __device__ static const double2* pk_m(const DevProblem& D) { return D.pk_m64; }
   __device__ static const double* P(const DevProblem& D, int b) { return b ? D.P64[1] : D.P64[0]; }
   __device__ static const double* rec(const DevProblem& D, int b) { return b ? D.rec64[1] : D.rec64[0]; }
-  __device__ static const double* Vp(const DevProblem& D, int b) { return b ? D.Vp64[1] : D.Vp64[0]; }
-  __device__ static const double* K(const DevProblem& D) { return D.K64; }
 };
 
 template <typename T>
@@ -302,15 +298,12 @@ __device__ __forceinline__ void store_landmark(DevProblem& D, int lc, int j, con
   double* r64 = (lc ? D.rec64[1] : D.rec64[0]) + (size_t)j * kRec;
   float* r32 = (lc ? D.rec32[1] : D.rec32[0]) + (size_t)j * kRec;
   double* v64 = (lc ? D.Vp64[1] : D.Vp64[0]) + (size_t)j * kLmSym;
-  float* v32 = (lc ? D.Vp32[1] : D.Vp32[0]) + (size_t)j * kLmSym;
   store4(r64, z0, z1, z2, 0.0);
   store4(r64 + 4, X0, X1, X2, 1.0);
   store4(r32, (float)z0, (float)z1, (float)z2, 0.0f);
   store4(r32 + 4, (float)X0, (float)X1, (float)X2, 1.0f);
   store4(v64, vp[0], vp[1], vp[2], vp[3]);
   store4(v64 + 4, vp[4], vp[5], 0.0, 0.0);
-  store4(v32, (float)vp[0], (float)vp[1], (float)vp[2], (float)vp[3]);
-  store4(v32 + 4, (float)vp[4], (float)vp[5], 0.0f, 0.0f);
 }
 
 // mode 0: initial state, 1: trial point of a step (other buffers), 2: re-solve
@@ -410,21 +403,36 @@ __global__ void __launch_bounds__(kBlock) k_landmark_solve(Batch B, int mode) {
   if (lane == 0) D.cost_part[q] = ftot;
 }
 
-// Sum of the per-packet cost partials in packet order (all lanes get it).
+// Sum of the per-packet cost partials by one workgroup: thread t adds
+// packets t, t+256, ... in order (four independent accumulators interleaved
+// by stride 1024), then a fixed tree.  Thread 0 gets the total.
 __device__ __forceinline__ double packet_cost_sum(const DevProblem& D) {
-  double acc = 0.0;
-  for (int q = lane_id(); q < D.n_pk; q += kWave) acc += D.cost_part[q];
-  return wave_sum(acc);
+  __shared__ double red[kWavesPerBlock];
+  const int t = threadIdx.x;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  const int n = D.n_pk;
+  int q = t;
+  for (; q + 3 * kBlock < n; q += 4 * kBlock) {
+    a0 += D.cost_part[q];
+    a1 += D.cost_part[q + kBlock];
+    a2 += D.cost_part[q + 2 * kBlock];
+    a3 += D.cost_part[q + 3 * kBlock];
+  }
+  for (; q < n; q += kBlock) a0 += D.cost_part[q];
+  const double s = wave_sum((a0 + a1) + (a2 + a3));
+  if (lane_id() == 0) red[t >> 6] = s;
+  __syncthreads();
+  return ((red[0] + red[1]) + red[2]) + red[3];
 }
 
-// cost of a landmark solve outside the LM loop, one wave per problem:
+// cost of a landmark solve outside the LM loop, one workgroup per problem:
 // mode 0 initial (cost, cost0), 1 trial (cost_trial), 2 reset (cost)
-__global__ void __launch_bounds__(kWave) k_cost_finalize(Batch B, int mode) {
+__global__ void __launch_bounds__(kBlock) k_cost_finalize(Batch B, int mode) {
   int p, w;
-  if (!map_wave(B, kUnitOne, p, w)) return;
+  if (!map_block(B, kUnitOne, p, w)) return;
   DevProblem& D = B.probs[p];
   const double f = packet_cost_sum(D);
-  if (lane_id() == 0) {
+  if (threadIdx.x == 0) {
     if (mode == 1) {
       D.ctl.cost_trial = f;
     } else {
@@ -663,7 +671,6 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
 #pragma unroll
   for (int r = 0; r < 12; ++r) x0[r] = 0.0;
   double* K64 = D.K64 + (size_t)i * kCamMat;
-  float* K32 = D.K32 + (size_t)i * kCamMat;
 #pragma unroll
   for (int r = 0; r < 12; ++r) {
 #pragma unroll
@@ -675,23 +682,40 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
       if (!ok) v = 0.0;
       K64[r * 12 + c] = v;
       K64[c * 12 + r] = v;
-      K32[r * 12 + c] = (float)v;
-      K32[c * 12 + r] = (float)v;
       x0[r] -= v * g[c];
       if (c != r) x0[c] -= v * g[r];
     }
   }
   T* x = static_cast<T*>(D.x) + (size_t)i * kCam;
-  T* acc = static_cast<T*>(D.acc) + (size_t)i * kCam;
+  double* acc = D.acc + (size_t)i * kCam;
 #pragma unroll
   for (int r = 0; r < 12; ++r) {
     x[r] = (T)x0[r];
-    acc[r] = (T)x0[r];
+    acc[r] = x0[r];
   }
   if (!ok) atomicOr(&D.ctl.status, 1);
 }
 
 // ------------------------------------------------------- k_series_landmark
+// z_j = V_j^+ y_j with the FP64 pseudo-inverse in both precisions: rounding
+// V^+ itself to FP32 would perturb W V^+ W^T by ~eps * cond(V_j) and can push
+// the spectrum of M past 1 for the near-singular blocks of random starts;
+// applied in FP64 to the FP32 sum y_j the error stays ~eps * sqrt(cond(V_j)).
+template <typename T>
+__device__ __forceinline__ void store_z(const DevProblem& D, int lc, int j, T y0, T y1, T y2, T X0, T X1, T X2,
+                                        T* zx) {
+  double v[8];
+  const double* vp = (lc ? D.Vp64[1] : D.Vp64[0]) + (size_t)j * kLmSym;
+  load4(vp, v[0], v[1], v[2], v[3]);
+  load4(vp + 4, v[4], v[5], v[6], v[7]);
+  const double d0 = y0, d1 = y1, d2 = y2;
+  const double z0 = v[0] * d0 + v[1] * d1 + v[2] * d2;
+  const double z1 = v[1] * d0 + v[3] * d1 + v[4] * d2;
+  const double z2 = v[2] * d0 + v[4] * d1 + v[5] * d2;
+  store4(zx + (size_t)j * kRec, (T)z0, (T)z1, (T)z2, (T)0);
+  store4(zx + (size_t)j * kRec + 4, X0, X1, X2, (T)1);
+}
+
 // z_j = V_j^+ sum_k Pbar_i^T N_k (X_i x~_j), X_i = x_i as a 3x4 matrix; the
 // (z_j, X_j) record is written for the camera pass.
 template <typename T>
@@ -737,18 +761,7 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
     y2 = seg_sum(y2, links);
     const int kn = __shfl_down(key, 1, kWave);
     const bool tail = act && (lane == kWave - 1 || kn != key);
-    if (tail) {
-      const int j = lm0 + key;
-      T v[8];
-      const T* vp = Prec<T>::Vp(D, lc) + (size_t)j * kLmSym;
-      load4(vp, v[0], v[1], v[2], v[3]);
-      load4(vp + 4, v[4], v[5], v[6], v[7]);
-      const T z0 = v[0] * y0 + v[1] * y1 + v[2] * y2;
-      const T z1 = v[1] * y0 + v[3] * y1 + v[4] * y2;
-      const T z2 = v[2] * y0 + v[4] * y1 + v[5] * y2;
-      store4(zx + (size_t)j * kRec, z0, z1, z2, (T)0);
-      store4(zx + (size_t)j * kRec + 4, X0, X1, X2, (T)1);
-    }
+    if (tail) store_z<T>(D, lc, lm0 + key, y0, y1, y2, X0, X1, X2, zx);
   } else {
     T X0, X1, X2, one;
     load4(rec + (size_t)lm0 * kRec + 4, X0, X1, X2, one);
@@ -771,17 +784,7 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
     y0 = wave_sum(y0);
     y1 = wave_sum(y1);
     y2 = wave_sum(y2);
-    if (lane == 0) {
-      T v[8];
-      const T* vp = Prec<T>::Vp(D, lc) + (size_t)lm0 * kLmSym;
-      load4(vp, v[0], v[1], v[2], v[3]);
-      load4(vp + 4, v[4], v[5], v[6], v[7]);
-      const T z0 = v[0] * y0 + v[1] * y1 + v[2] * y2;
-      const T z1 = v[1] * y0 + v[3] * y1 + v[4] * y2;
-      const T z2 = v[2] * y0 + v[4] * y1 + v[5] * y2;
-      store4(zx + (size_t)lm0 * kRec, z0, z1, z2, (T)0);
-      store4(zx + (size_t)lm0 * kRec + 4, X0, X1, X2, (T)1);
-    }
+    if (lane == 0) store_z<T>(D, lc, lm0, y0, y1, y2, X0, X1, X2, zx);
   }
 }
 
@@ -872,15 +875,15 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
   // single chunk: the whole workgroup is here; several: only wave 0 is left
   if (nch == 1) __syncthreads();
   else __builtin_amdgcn_wave_barrier();
+  // x_i = K_i t_i with the FP64 camera block in both precisions
   if (k < 12) {
-    const T* Kr = Prec<T>::K(D) + (size_t)cam * kCamMat + k * 12;
-    T kr[12];
-    load12(Kr, kr);
-    T xr = 0;
+    double kr[12];
+    load12(D.K64 + (size_t)cam * kCamMat + k * 12, kr);
+    double xr = 0.0;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) xr += kr[c] * tv[c];
-    static_cast<T*>(D.x)[(size_t)cam * kCam + k] = xr;
-    static_cast<T*>(D.acc)[(size_t)cam * kCam + k] += xr;
+    for (int c = 0; c < 12; ++c) xr += kr[c] * (double)tv[c];
+    static_cast<T*>(D.x)[(size_t)cam * kCam + k] = (T)xr;
+    D.acc[(size_t)cam * kCam + k] += xr;
   }
 }
 
@@ -896,11 +899,11 @@ __global__ void __launch_bounds__(kWave) k_retract(Batch B) {
   const int pc = D.ctl.pcur;
   double q[12];
   load12((pc ? D.P64[1] : D.P64[0]) + (size_t)i * kCam, q);
-  const T* acc = static_cast<const T*>(D.acc) + (size_t)i * kCam;
+  const double* acc = D.acc + (size_t)i * kCam;
   double nrm = 0.0;
 #pragma unroll
   for (int r = 0; r < 12; ++r) {
-    q[r] += (double)acc[r];
+    q[r] += acc[r];
     nrm += q[r] * q[r];
   }
   if (D.manifold == 0) {
@@ -920,14 +923,14 @@ __global__ void __launch_bounds__(kWave) k_retract(Batch B) {
 // ---------------------------------------------------------------- k_decide
 // Adds the trial cost partials (packet order), then: strict decrease accepts
 // (NaN rejects); lambda /10 on accept, x10 on reject, clamped; relinearise
-// only after an accept; ftol on accepted steps.  One wave per problem.
-__global__ void __launch_bounds__(kWave) k_decide(Batch B) {
+// only after an accept; ftol on accepted steps.  One workgroup per problem.
+__global__ void __launch_bounds__(kBlock) k_decide(Batch B) {
   int p, w;
-  if (!map_wave(B, kUnitOne, p, w)) return;
+  if (!map_block(B, kUnitOne, p, w)) return;
   DevProblem& D = B.probs[p];
   if (D.ctl.done) return;
   const double fn = packet_cost_sum(D);
-  if (lane_id() != 0) return;
+  if (threadIdx.x != 0) return;
   Ctl& c = D.ctl;
   const double f = c.cost;
   c.cost_trial = fn;
@@ -968,7 +971,7 @@ hipError_t launch_landmark_solve(const Batch& b, int mode, hipStream_t s) {
 
 hipError_t launch_cost_finalize(const Batch& b, int mode, hipStream_t s) {
   if (b.total[kUnitOne] == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cost_finalize, blocks_for(b.total[kUnitOne], 1), dim3(kWave), 0, s, b, mode);
+  hipLaunchKernelGGL(k_cost_finalize, blocks_for(b.total[kUnitOne], 1), dim3(kBlock), 0, s, b, mode);
   return hipGetLastError();
 }
 
@@ -1014,7 +1017,7 @@ hipError_t launch_retract(const Batch& b, bool fp32, hipStream_t s) {
 
 hipError_t launch_decide(const Batch& b, hipStream_t s) {
   if (b.total[kUnitOne] == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_decide, blocks_for(b.total[kUnitOne], 1), dim3(kWave), 0, s, b);
+  hipLaunchKernelGGL(k_decide, blocks_for(b.total[kUnitOne], 1), dim3(kBlock), 0, s, b);
   return hipGetLastError();
 }
 

@@ -19,6 +19,8 @@
 
 namespace povar {
 
+constexpr int kTraceCapacity = 4096;   // per-iteration trace entries kept per problem
+
 thread_local std::string g_noctx_error;
 
 void set_error(povar_ctx ctx, const char* fmt, ...) {
@@ -72,15 +74,13 @@ size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_
     r.rec64[b] = a.take(n_l * kRec * 8);
     r.rec32[b] = a.take(n_l * kRec * 4);
     r.Vp64[b] = a.take(n_l * kLmSym * 8);
-    r.Vp32[b] = a.take(n_l * kLmSym * 4);
   }
   r.lin_part = a.take(n_ch * kLinVals * 8);
   r.K64 = a.take(n_p * kCamMat * 8);
-  r.K32 = a.take(n_p * kCamMat * 4);
   r.g64 = a.take(n_p * kCam * 8);
   r.U40 = a.take(n_p * 40 * 8);
   r.x = a.take(n_p * kCam * ts);
-  r.acc = a.take(n_p * kCam * ts);
+  r.acc = a.take(n_p * kCam * 8);
   r.zx = a.take(n_l * kRec * ts);
   r.t_part = a.take(n_ch * kCam * ts);
   r.cam_cnt = a.take(n_p * 4);
@@ -91,6 +91,10 @@ size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_
   r.rec = a.take(sizeof(DevProblem));
   r.tables = a.take(kNumUnitKinds * 2 * 4);
   return a.total;
+}
+
+size_t layout_footprint(const HostLayout& L, bool fp32) {
+  return arena_bytes(L.n_p, L.n_l, L.n_obs, L.n_pk, L.n_ch, fp32, kTraceCapacity, nullptr);
 }
 
 // ------------------------------------------------------------------ layout
@@ -244,7 +248,6 @@ using namespace povar;
 
 namespace povar {
 
-static const int kTraceCap = 4096;
 
 povar_status check_options(povar_ctx ctx, const povar_options* o) {
   if (!o) {
@@ -291,12 +294,12 @@ static void upload(std::vector<char>& staging, size_t off, const std::vector<T>&
 // Builds the device state of a problem from a host layout and initial
 // cameras: one arena allocation, filled from a single host staging image.
 povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, const povar_options* o,
-                          hipStream_t stream, povar_problem_s* pb) {
+                          hipStream_t stream, povar_problem_s* pb, DevProblem* rec_dev, int32_t iter_limit) {
   pb->ctx = ctx;
   pb->opt = *o;
   pb->fp32 = o->precision == POVAR_PREC_FP32_BULK;
   pb->stream = stream;
-  pb->trace_cap = kTraceCap;
+  pb->trace_cap = kTraceCapacity;
   pb->L = std::move(L);
   HostLayout& H = pb->L;
   ArenaOffsets& A = pb->off;
@@ -364,15 +367,13 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
     R.rec64[b] = (double*)dp(A.rec64[b]);
     R.rec32[b] = (float*)dp(A.rec32[b]);
     R.Vp64[b] = (double*)dp(A.Vp64[b]);
-    R.Vp32[b] = (float*)dp(A.Vp32[b]);
   }
   R.lin_part = (double*)dp(A.lin_part);
   R.K64 = (double*)dp(A.K64);
-  R.K32 = (float*)dp(A.K32);
   R.g64 = (double*)dp(A.g64);
   R.U40 = (double*)dp(A.U40);
   R.x = dp(A.x);
-  R.acc = dp(A.acc);
+  R.acc = (double*)dp(A.acc);
   R.zx = dp(A.zx);
   R.t_part = dp(A.t_part);
   R.cam_cnt = (uint32_t*)dp(A.cam_cnt);
@@ -384,7 +385,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   Ctl& c = R.ctl;
   c.lambda = o->lambda0;
   c.need_lin = 1;
-  c.iter_limit = INT_MAX;
+  c.iter_limit = iter_limit;
   c.order = o->series_order;
 
   // batch of one: prefix tables of waves per unit kind
@@ -414,9 +415,14 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   std::memcpy(img.data() + A.rec, &R, sizeof(R));
   std::memcpy(img.data() + A.tables, tables, sizeof(tables));
   HIP_TRY(ctx, hipMemcpyAsync(pb->arena, img.data(), pb->bytes, hipMemcpyHostToDevice, stream));
+  HIP_TRY(ctx, hipStreamSynchronize(stream));   // the staging image is freed on return
 
   Batch& B = pb->batch;
   B.probs = (DevProblem*)dp(A.rec);
+  if (rec_dev) {   // the record lives in a caller-owned array (server slots)
+    HIP_TRY(ctx, hipMemcpyAsync(rec_dev, &R, sizeof(R), hipMemcpyHostToDevice, stream));
+    B.probs = rec_dev;
+  }
   for (int k = 0; k < kNumUnitKinds; ++k) {
     B.off[k] = (const int32_t*)dp(A.tables) + 2 * k;
     B.total[k] = units[k];
@@ -572,6 +578,24 @@ void fill_report(const povar_problem_s* pb, const Ctl& c, double seconds, povar_
 
 }  // namespace povar
 
+static povar_status copy_landmark_vec(povar_problem_s* pb, const double* dev, int stride, int offset, int width,
+                                      double* out) {
+  std::vector<double> tmp((size_t)pb->L.n_l * stride);
+  HIP_TRY(pb->ctx, hipMemcpyAsync(tmp.data(), dev, tmp.size() * 8, hipMemcpyDeviceToHost, pb->stream));
+  HIP_TRY(pb->ctx, hipStreamSynchronize(pb->stream));
+  for (int32_t jj = 0; jj < pb->L.n_l; ++jj) {
+    const int32_t j = pb->L.int2ext[jj];
+    for (int k = 0; k < width; ++k) out[(size_t)j * width + k] = tmp[(size_t)jj * stride + offset + k];
+  }
+  return POVAR_OK;
+}
+
+namespace povar {
+povar_status copy_points(povar_problem_s* pb, int lcur, double* out) {
+  return copy_landmark_vec(pb, pb->rec.rec64[lcur], kRec, 4, 3, out);
+}
+}  // namespace povar
+
 // ==================================================================== C ABI
 extern "C" {
 
@@ -659,7 +683,7 @@ povar_status povar_problem_footprint(int32_t n_cams, int32_t n_pts, int64_t n_ob
   const int64_t n_pk = n_pts;
   const int64_t n_ch = n_obs / kChunk + n_cams;
   *bytes = arena_bytes(n_cams, n_pts, n_obs, n_pk, n_ch, precision == POVAR_PREC_FP32_BULK,
-                       kTraceCap, nullptr);
+                       kTraceCapacity, nullptr);
   return POVAR_OK;
 }
 
@@ -683,7 +707,7 @@ povar_status povar_problem_create(povar_ctx ctx, int32_t n_cams, int32_t n_pts, 
   pb->ctx = ctx;
   pb->owned_by_ctx = true;
   ctx->live_problems += 1;
-  st = problem_init(ctx, std::move(L), cams0, opts, ctx->stream, pb);
+  st = problem_init(ctx, std::move(L), cams0, opts, ctx->stream, pb, nullptr, INT_MAX);
   if (st != POVAR_OK) {
     povar_problem_destroy(pb);
     return st;
@@ -783,24 +807,14 @@ povar_status povar_get_cameras(povar_problem pb, double* out) {
   return POVAR_OK;
 }
 
-static povar_status copy_landmark_vec(povar_problem pb, const double* dev, int stride, int offset, int width,
-                                      double* out) {
-  std::vector<double> tmp((size_t)pb->L.n_l * stride);
-  HIP_TRY(pb->ctx, hipMemcpyAsync(tmp.data(), dev, tmp.size() * 8, hipMemcpyDeviceToHost, pb->stream));
-  HIP_TRY(pb->ctx, hipStreamSynchronize(pb->stream));
-  for (int32_t jj = 0; jj < pb->L.n_l; ++jj) {
-    const int32_t j = pb->L.int2ext[jj];
-    for (int k = 0; k < width; ++k) out[(size_t)j * width + k] = tmp[(size_t)jj * stride + offset + k];
-  }
-  return POVAR_OK;
-}
-
 povar_status povar_get_points(povar_problem pb, double* out) {
   if (!pb || !out) return POVAR_EINVAL;
   Ctl c;
   HIP_TRY(pb->ctx, read_ctl(pb, &c));
   return copy_landmark_vec(pb, pb->rec.rec64[c.lcur], kRec, 4, 3, out);
 }
+
+
 
 povar_status povar_get_trace(povar_problem pb, int32_t n, double* cost, double* lam, int32_t* acc) {
   if (!pb || n < 0) return POVAR_EINVAL;
@@ -966,16 +980,7 @@ povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, do
   Ctl after;
   HIP_TRY(ctx, read_ctl(pb, &after));
   const int32_t n_p = pb->L.n_p;
-  if (dp) {
-    if (pb->fp32) {
-      std::vector<float> t((size_t)n_p * kCam);
-      HIP_TRY(ctx, hipMemcpyAsync(t.data(), pb->rec.acc, t.size() * 4, hipMemcpyDeviceToHost, pb->stream));
-      HIP_TRY(ctx, hipStreamSynchronize(pb->stream));
-      for (size_t k = 0; k < t.size(); ++k) dp[k] = t[k];
-    } else {
-      HIP_TRY(ctx, hipMemcpyAsync(dp, pb->rec.acc, (size_t)n_p * kCam * 8, hipMemcpyDeviceToHost, pb->stream));
-    }
-  }
+  if (dp) HIP_TRY(ctx, hipMemcpyAsync(dp, pb->rec.acc, (size_t)n_p * kCam * 8, hipMemcpyDeviceToHost, pb->stream));
   if (p_trial)
     HIP_TRY(ctx, hipMemcpyAsync(p_trial, pb->rec.P64[c.pcur ^ 1], (size_t)n_p * kCam * 8, hipMemcpyDeviceToHost,
                                 pb->stream));

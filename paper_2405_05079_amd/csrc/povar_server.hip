@@ -1,22 +1,403 @@
-// Continuous-batching server (placeholder until the batched driver lands).
+// Continuous-batching server: many bundle-adjustment problems resident on one
+// GPU, advanced together.
+//
+// submit() validates a request and builds its observation layout on the
+// caller's thread, so its exact device footprint is known before admission.
+// One worker thread owns the device: it admits queued requests in FIFO order
+// whenever a slot is free and the summed footprint of resident problems stays
+// within the budget, then runs one LM iteration for every resident problem
+// with a single batched launch sequence per precision (each kernel's grid
+// covers the work units of all problems), reads back the control blocks, and
+// retires finished problems (results copied to host, device memory freed).
+// New requests therefore join at iteration boundaries while others are
+// mid-solve.  Every reduction stays inside one problem's own units in a fixed
+// order, so a problem's result does not depend on which others shared the
+// launches.
+#include <chrono>
+#include <climits>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
 #include "povar.h"
 #include "povar_host.h"
 
+namespace povar {
+
+struct Request {
+  uint64_t ticket = 0;
+  HostLayout layout;
+  std::vector<double> cams0;
+  povar_options opt{};
+  bool fp32 = false;
+  size_t footprint = 0;
+  int32_t n_p = 0, n_l = 0;
+  double t_submit = 0.0, t_admit = -1.0, t_finish = -1.0;
+  bool finished = false;
+  povar_status status = POVAR_OK;
+  std::string error;
+  povar_report report{};
+  std::vector<double> cams, pts;
+};
+
+struct Resident {
+  std::shared_ptr<Request> req;
+  povar_problem_s* pb = nullptr;
+};
+
+// Problems of one precision share one batch: their records sit contiguously
+// in `recs`, in the order of `res`.
+struct Group {
+  bool fp32 = false;
+  DevProblem* recs = nullptr;          // device, max_slots records
+  int32_t* tables = nullptr;           // device, kNumUnitKinds x (max_slots + 1)
+  std::vector<Resident> res;
+  std::vector<DevProblem> host_recs;   // read-back buffer
+  Batch batch{};
+  int max_order = 0;
+  bool dirty = true;
+};
+
+}  // namespace povar
+
 using namespace povar;
 
+struct povar_server_s {
+  povar_ctx ctx = nullptr;
+  hipStream_t stream = nullptr;
+  uint64_t budget = 0;
+  int32_t max_slots = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::map<uint64_t, std::shared_ptr<Request>> tickets;   // submitted and not yet collected
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  uint64_t used = 0;
+  int32_t n_resident = 0;
+  int64_t n_finished = 0, batch_iters = 0;
+  Group groups[2];
+  std::thread worker;
+  std::chrono::steady_clock::time_point t0;
+
+  double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+namespace {
+
+void fail_request(povar_server_s* sv, const std::shared_ptr<Request>& r, povar_status st, const std::string& msg) {
+  std::lock_guard<std::mutex> g(sv->mu);
+  r->status = st;
+  r->error = msg;
+  r->finished = true;
+  r->t_finish = sv->now();
+  sv->n_finished += 1;
+}
+
+hipError_t upload_tables(povar_server_s* sv, Group& G) {
+  const int n = (int)G.res.size();
+  const int stride = sv->max_slots + 1;
+  std::vector<int32_t> tab((size_t)kNumUnitKinds * stride, 0);
+  G.max_order = 0;
+  for (int p = 0; p < n; ++p) {
+    const HostLayout& L = G.res[p].pb->L;
+    const int32_t units[kNumUnitKinds] = {L.n_pk, L.n_ch, (L.n_p + kWave - 1) / kWave, 1};
+    for (int k = 0; k < kNumUnitKinds; ++k) tab[(size_t)k * stride + p + 1] = tab[(size_t)k * stride + p] + units[k];
+    G.max_order = std::max(G.max_order, G.res[p].pb->opt.series_order);
+  }
+  hipError_t e = hipMemcpyAsync(G.tables, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, sv->stream);
+  if (e != hipSuccess) return e;
+  G.batch.probs = G.recs;
+  G.batch.n_prob = n;
+  for (int k = 0; k < kNumUnitKinds; ++k) {
+    G.batch.off[k] = G.tables + (size_t)k * stride;
+    G.batch.total[k] = tab[(size_t)k * stride + n];
+  }
+  G.dirty = false;
+  // the host table must outlive the asynchronous copy
+  return hipStreamSynchronize(sv->stream);
+}
+
+hipError_t launch_iteration(povar_server_s* sv, Group& G) {
+  hipError_t e;
+  const Batch& B = G.batch;
+  hipStream_t s = sv->stream;
+  if ((e = launch_linearize(B, G.fp32, 0, s)) != hipSuccess) return e;
+  if ((e = launch_camera_prep(B, G.fp32, s)) != hipSuccess) return e;
+  for (int t = 1; t <= G.max_order; ++t) {
+    if ((e = launch_series_landmark(B, G.fp32, t, s)) != hipSuccess) return e;
+    if ((e = launch_series_camera(B, G.fp32, t, s)) != hipSuccess) return e;
+  }
+  if ((e = launch_retract(B, G.fp32, s)) != hipSuccess) return e;
+  if ((e = launch_landmark_solve(B, 1, s)) != hipSuccess) return e;
+  return launch_decide(B, s);
+}
+
+void admit(povar_server_s* sv, const std::shared_ptr<Request>& r) {
+  Group& G = sv->groups[r->fp32 ? 0 : 1];
+  auto* pb = new povar_problem_s();
+  const int pos = (int)G.res.size();
+  const int32_t limit = r->opt.max_iters;
+  povar_status st = problem_init(sv->ctx, std::move(r->layout), r->cams0.data(), &r->opt, sv->stream, pb,
+                                 G.recs + pos, limit);
+  r->cams0.clear();
+  r->cams0.shrink_to_fit();
+  if (st != POVAR_OK) {
+    std::string msg = povar_last_error(sv->ctx);
+    povar_problem_destroy(pb);
+    {
+      std::lock_guard<std::mutex> g(sv->mu);
+      sv->used -= r->footprint;
+      sv->n_resident -= 1;
+    }
+    fail_request(sv, r, st, msg);
+    return;
+  }
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    r->t_admit = sv->now();
+  }
+  G.res.push_back({r, pb});
+  G.dirty = true;
+}
+
+// Copies the result of resident problem `idx` out, frees it, and moves the
+// last record into its place.
+hipError_t retire(povar_server_s* sv, Group& G, int idx, const Ctl& c) {
+  Resident R = G.res[idx];
+  auto& r = R.req;
+  povar_problem_s* pb = R.pb;
+  std::vector<double> cams((size_t)r->n_p * kCam), pts((size_t)r->n_l * 3);
+  hipError_t e = hipMemcpyAsync(cams.data(), pb->rec.P64[c.pcur], cams.size() * 8, hipMemcpyDeviceToHost,
+                                sv->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
+  povar_status st = e == hipSuccess ? copy_points(pb, c.lcur, pts.data()) : POVAR_EDEVICE;
+  povar_report rep;
+  fill_report(pb, c, 0.0, &rep);
+  povar_problem_destroy(pb);
+  const int last = (int)G.res.size() - 1;
+  if (idx != last) {
+    hipError_t e2 = hipMemcpyAsync(G.recs + idx, G.recs + last, sizeof(DevProblem), hipMemcpyDeviceToDevice,
+                                   sv->stream);
+    if (e2 != hipSuccess && e == hipSuccess) e = e2;
+    G.res[idx] = G.res[last];
+    G.res[idx].pb->batch.probs = G.recs + idx;
+  }
+  G.res.pop_back();
+  G.dirty = true;
+  std::lock_guard<std::mutex> g(sv->mu);
+  rep.seconds = sv->now() - r->t_admit;
+  r->report = rep;
+  r->cams = std::move(cams);
+  r->pts = std::move(pts);
+  r->status = (e != hipSuccess || st != POVAR_OK) ? POVAR_EDEVICE : ((c.status & 1) ? POVAR_ENUMERIC : POVAR_OK);
+  if (r->status != POVAR_OK) r->error = e != hipSuccess ? hipGetErrorString(e) : "camera block not positive definite";
+  r->finished = true;
+  r->t_finish = sv->now();
+  sv->used -= r->footprint;
+  sv->n_resident -= 1;
+  sv->n_finished += 1;
+  return e;
+}
+
+void worker_loop(povar_server_s* sv) {
+  (void)hipSetDevice(sv->ctx->device);
+  for (;;) {
+    std::vector<std::shared_ptr<Request>> admitted;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      if (sv->n_resident == 0)
+        sv->cv.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
+      if (sv->stop) return;
+      // FIFO admission by slot and footprint
+      while (!sv->queue.empty()) {
+        auto& r = sv->queue.front();
+        if (sv->n_resident >= sv->max_slots || sv->used + r->footprint > sv->budget) break;
+        sv->used += r->footprint;
+        sv->n_resident += 1;
+        admitted.push_back(r);
+        sv->queue.pop_front();
+      }
+    }
+    for (auto& r : admitted) admit(sv, r);
+    bool any = false;
+    for (Group& G : sv->groups) {
+      if (G.res.empty()) continue;
+      hipError_t e = G.dirty ? upload_tables(sv, G) : hipSuccess;
+      if (e == hipSuccess) e = launch_iteration(sv, G);
+      if (e != hipSuccess) {
+        for (auto& R : G.res) {
+          povar_problem_destroy(R.pb);
+          {
+            std::lock_guard<std::mutex> g(sv->mu);
+            sv->used -= R.req->footprint;
+            sv->n_resident -= 1;
+          }
+          fail_request(sv, R.req, POVAR_EDEVICE, hipGetErrorString(e));
+        }
+        G.res.clear();
+        G.dirty = true;
+        continue;
+      }
+      any = true;
+    }
+    if (!any) continue;
+    for (Group& G : sv->groups) {
+      if (G.res.empty()) continue;
+      const size_t n = G.res.size();
+      G.host_recs.resize(n);
+      hipError_t e = hipMemcpyAsync(G.host_recs.data(), G.recs, n * sizeof(DevProblem), hipMemcpyDeviceToHost,
+                                    sv->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
+      if (e != hipSuccess) continue;
+      for (int idx = (int)n - 1; idx >= 0; --idx)
+        if (G.host_recs[idx].ctl.done) (void)retire(sv, G, idx, G.host_recs[idx].ctl);
+    }
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->batch_iters += 1;
+  }
+}
+
+void free_server(povar_server_s* sv) {
+  for (Group& G : sv->groups) {
+    for (auto& R : G.res) povar_problem_destroy(R.pb);
+    G.res.clear();
+    if (G.recs) (void)hipFree(G.recs);
+    if (G.tables) (void)hipFree(G.tables);
+  }
+  if (sv->stream) (void)hipStreamDestroy(sv->stream);
+}
+
+}  // namespace
+
 extern "C" {
-povar_status povar_server_create(povar_ctx ctx, uint64_t, int32_t, povar_server* out) {
-  if (out) *out = nullptr;
-  set_error(ctx, "server not available in this build");
-  return POVAR_ESTATE;
+
+povar_status povar_server_create(povar_ctx ctx, uint64_t hbm_budget_bytes, int32_t max_slots, povar_server* out) {
+  if (!out) return POVAR_EINVAL;
+  *out = nullptr;
+  if (!ctx || max_slots <= 0 || hbm_budget_bytes == 0) {
+    set_error(ctx, "server needs a context, max_slots > 0 and a positive budget");
+    return POVAR_EINVAL;
+  }
+  (void)hipSetDevice(ctx->device);
+  auto* sv = new povar_server_s();
+  sv->ctx = ctx;
+  sv->budget = hbm_budget_bytes;
+  sv->max_slots = max_slots;
+  sv->t0 = std::chrono::steady_clock::now();
+  hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+  for (int g = 0; g < 2 && e == hipSuccess; ++g) {
+    sv->groups[g].fp32 = g == 0;
+    e = hipMalloc(&sv->groups[g].recs, sizeof(DevProblem) * max_slots);
+    if (e == hipSuccess) e = hipMalloc(&sv->groups[g].tables, sizeof(int32_t) * kNumUnitKinds * (max_slots + 1));
+  }
+  if (e != hipSuccess) {
+    set_error(ctx, "server allocation failed: %s", hipGetErrorString(e));
+    free_server(sv);
+    delete sv;
+    return POVAR_ENOMEM;
+  }
+  ctx->live_problems += 1;
+  sv->worker = std::thread(worker_loop, sv);
+  *out = sv;
+  return POVAR_OK;
 }
-povar_status povar_server_submit(povar_server, int32_t, int32_t, int64_t, const int32_t*, const int32_t*,
-                                 const double*, const double*, const povar_options*, uint64_t*) {
-  return POVAR_ESTATE;
+
+povar_status povar_server_submit(povar_server sv, int32_t n_cams, int32_t n_pts, int64_t n_obs,
+                                 const int32_t* cam_idx, const int32_t* pt_idx, const double* meas,
+                                 const double* cams0, const povar_options* opts, uint64_t* ticket) {
+  if (!sv || !ticket) return POVAR_EINVAL;
+  povar_ctx ctx = sv->ctx;
+  povar_status st = check_options(ctx, opts);
+  if (st != POVAR_OK) return st;
+  if (!cams0) {
+    set_error(ctx, "cams0 must not be NULL");
+    return POVAR_EINVAL;
+  }
+  auto r = std::make_shared<Request>();
+  r->opt = *opts;
+  r->fp32 = opts->precision == POVAR_PREC_FP32_BULK;
+  st = build_layout(ctx, n_cams, n_pts, n_obs, cam_idx, pt_idx, meas, r->fp32, r->layout);
+  if (st != POVAR_OK) return st;
+  r->footprint = layout_footprint(r->layout, r->fp32);
+  if (r->footprint > sv->budget) {
+    set_error(ctx, "request needs %zu device bytes, more than the server budget %llu", r->footprint,
+              (unsigned long long)sv->budget);
+    return POVAR_ENOMEM;
+  }
+  r->n_p = n_cams;
+  r->n_l = n_pts;
+  r->cams0.assign(cams0, cams0 + (size_t)n_cams * kCam);
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    r->ticket = sv->next_ticket++;
+    r->t_submit = sv->now();
+    sv->tickets[r->ticket] = r;
+    sv->queue.push_back(r);
+    *ticket = r->ticket;
+  }
+  sv->cv.notify_one();
+  return POVAR_OK;
 }
-povar_status povar_server_poll(povar_server, uint64_t, povar_report*, double*, double*, double*) {
-  return POVAR_ESTATE;
+
+povar_status povar_server_poll(povar_server sv, uint64_t ticket, povar_report* report, double* cams_out,
+                               double* pts_out, double* times) {
+  if (!sv) return POVAR_EINVAL;
+  std::lock_guard<std::mutex> g(sv->mu);
+  auto it = sv->tickets.find(ticket);
+  if (it == sv->tickets.end()) {
+    set_error(sv->ctx, "unknown ticket %llu", (unsigned long long)ticket);
+    return POVAR_EINVAL;
+  }
+  auto r = it->second;
+  if (!r->finished) return POVAR_EAGAIN;
+  if (times) {
+    times[0] = r->t_submit;
+    times[1] = r->t_admit;
+    times[2] = r->t_finish;
+  }
+  if (report) *report = r->report;
+  if (r->status == POVAR_OK) {
+    if (cams_out) std::memcpy(cams_out, r->cams.data(), r->cams.size() * 8);
+    if (pts_out) std::memcpy(pts_out, r->pts.data(), r->pts.size() * 8);
+  } else {
+    set_error(sv->ctx, "request %llu failed: %s", (unsigned long long)ticket, r->error.c_str());
+  }
+  const povar_status st = r->status;
+  sv->tickets.erase(it);
+  return st;
 }
-povar_status povar_server_stats(povar_server, int32_t*, int32_t*, int64_t*, int64_t*) { return POVAR_ESTATE; }
-povar_status povar_server_destroy(povar_server) { return POVAR_ESTATE; }
+
+povar_status povar_server_stats(povar_server sv, int32_t* queued, int32_t* active, int64_t* finished,
+                                int64_t* batch_iters) {
+  if (!sv) return POVAR_EINVAL;
+  std::lock_guard<std::mutex> g(sv->mu);
+  if (queued) *queued = (int32_t)sv->queue.size();
+  if (active) *active = sv->n_resident;
+  if (finished) *finished = sv->n_finished;
+  if (batch_iters) *batch_iters = sv->batch_iters;
+  return POVAR_OK;
 }
+
+povar_status povar_server_destroy(povar_server sv) {
+  if (!sv) return POVAR_EINVAL;
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv.notify_all();
+  if (sv->worker.joinable()) sv->worker.join();
+  (void)hipSetDevice(sv->ctx->device);
+  free_server(sv);
+  sv->ctx->live_problems -= 1;
+  delete sv;
+  return POVAR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+"""Continuous-batching server: each result equals the problem solved alone,
+admission respects the slot cap and the device-memory budget, and requests
+arriving while others run are admitted as capacity frees up (needs a GPU)."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2405_05079_amd import povar, synth
+
+pytestmark = pytest.mark.gpu
+
+OPTS = dict(precision="fp32_bulk", order=10, max_iters=8, ftol=0.0)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = povar.Context(0)
+    yield c
+    c.close()
+
+
+def requests():
+    sizes = [(20, 2500), (45, 6000), (12, 900), (80, 9000), (30, 4000), (60, 7000), (25, 3000)]
+    return [synth.make_problem(n_c, n_p, track=("geom", 0.25), seed=700 + i) for i, (n_c, n_p) in enumerate(sizes)]
+
+
+def solve_alone(ctx, prob):
+    gp = povar.Problem.from_synth(ctx, prob, **OPTS)
+    rep = gp.solve()
+    out = (rep, gp.cameras(), gp.points())
+    gp.close()
+    return out
+
+
+def drain(sv, tickets, timeout=120.0):
+    out, t0, max_active = {}, time.time(), 0
+    while len(out) < len(tickets):
+        max_active = max(max_active, sv.stats()["active"])
+        for t in tickets:
+            if t not in out:
+                r = sv.poll(t)
+                if r is not None:
+                    out[t] = r
+        assert time.time() - t0 < timeout, "server did not finish"
+        time.sleep(0.002)
+    return out, max_active
+
+
+def test_results_equal_single_solves_and_mix_is_bitwise_independent(ctx):
+    probs = requests()
+    print("[case] server mix of", len(probs), flush=True)
+    alone = [solve_alone(ctx, p) for p in probs]
+    sv = povar.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=3)
+    tickets = [sv.submit(p, **OPTS) for p in probs]
+    res, max_active = drain(sv, tickets)
+    assert max_active <= 3
+    for p, t, (rep_a, cams_a, pts_a) in zip(probs, tickets, alone):
+        rep, cams, pts, times = res[t]
+        np.testing.assert_array_equal(cams, cams_a)
+        np.testing.assert_array_equal(pts, pts_a)
+        assert rep["cost_final"] == rep_a["cost_final"] and rep["iters"] == OPTS["max_iters"]
+        assert times[0] <= times[1] <= times[2]
+    # a request solved alone by the server equals the same request in the mix
+    sv2 = povar.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=3)
+    t_alone = sv2.submit(probs[3], **OPTS)
+    r_alone, _ = drain(sv2, [t_alone])
+    np.testing.assert_array_equal(r_alone[t_alone][1], res[tickets[3]][1])
+    st = sv.stats()
+    assert st["finished"] == len(probs) and st["active"] == 0 and st["queued"] == 0
+    sv.close()
+    sv2.close()
+
+
+def test_admission_respects_budget_and_late_arrivals_join(ctx):
+    probs = requests()
+    print("[case] server budget", flush=True)
+    fps = [povar.footprint(p.n_cams, p.n_pts, p.n_obs, "fp32_bulk") for p in probs]
+    budget = int(max(fps) * 1.6)     # at most ~one large problem plus small ones
+    sv = povar.Server(ctx, hbm_budget_bytes=budget, max_slots=8)
+    first = [sv.submit(p, **OPTS) for p in probs[:3]]
+    time.sleep(0.05)                 # later arrivals while the first ones run
+    later = [sv.submit(p, **OPTS) for p in probs[3:]]
+    res, _ = drain(sv, first + later)
+    admits = {t: res[t][3][1] for t in first + later}
+    finishes = {t: res[t][3][2] for t in first + later}
+    # some request was admitted only after another one had finished
+    assert any(admits[t] >= min(finishes.values()) for t in later)
+    for t, p in zip(first + later, probs):
+        assert res[t][0]["iters"] == OPTS["max_iters"]
+    sv.close()
+
+
+def test_oversized_and_invalid_requests_are_rejected(ctx):
+    prob = requests()[0]
+    print("[case] server rejects", flush=True)
+    sv = povar.Server(ctx, hbm_budget_bytes=1 << 20, max_slots=2)
+    with pytest.raises(povar.PovarError) as e:
+        sv.submit(prob, **OPTS)
+    assert e.value.status == povar.ENOMEM
+    sv.close()
+    sv = povar.Server(ctx, hbm_budget_bytes=1 << 30, max_slots=2)
+    bad = synth.Problem(prob.n_cams, prob.n_pts, prob.cam_idx.copy(), prob.pt_idx, prob.meas, prob.cams0)
+    bad.cam_idx[0] = -1
+    with pytest.raises(povar.PovarError) as e:
+        sv.submit(bad, **OPTS)
+    assert e.value.status == povar.EINVAL
+    sv.close()
