@@ -50,7 +50,9 @@ typedef enum {
   POVAR_ENOMEM = 2,   /* device allocation failed, or request exceeds a server budget */
   POVAR_EDEVICE = 3,  /* a HIP runtime error */
   POVAR_EAGAIN = 4,   /* result not ready yet (server poll) */
-  POVAR_ENUMERIC = 5, /* non-finite cost, or a camera block that is not positive definite */
+  POVAR_ENUMERIC = 5, /* non-finite initial cost; from povar_debug_step: a damped camera
+                         block that could not be factored (inside the LM loop such a
+                         step is simply rejected) */
   POVAR_ESTATE = 6    /* call not valid in the object's current state */
 } povar_status;
 

@@ -34,7 +34,9 @@ notes of the repository):
   R8  LM: accept iff f_new < f (NaN rejects); lambda /= 10 (>= lambda_min) on
       accept, *= 10 (<= lambda_max) on reject; relinearise only after accept;
       stop when the relative decrease of an accepted step is below ftol;
-  R11 V_j^+ with eigenvalues below 1e-12 * lambda_max(V_j) dropped.
+  R11 V_j^+ with eigenvalues below 1e-12 * lambda_max(V_j) dropped;
+  R12 a step whose damped camera block has no Cholesky factor is rejected
+      (lambda x10), as any failed LM step.
 
 parity pinned: see tests/test_oracle_pins.py (finite differences, lstsq,
 envelope theorem, dense joint solve, Neumann closed form and bound, Lemma 1,
@@ -272,6 +274,15 @@ def retract(P: np.ndarray, dP: np.ndarray, manifold: str = "sphere") -> np.ndarr
     return Q
 
 
+def factorizable(rs: ReducedSystem) -> bool:
+    """True if every damped tangent camera block has a Cholesky factor."""
+    try:
+        np.linalg.cholesky(rs.Ut)
+        return True
+    except np.linalg.LinAlgError:
+        return False
+
+
 def camera_step(P, lin, lam, order, manifold="sphere", rtol=0.0):
     """One PoVar camera update (ambient, (n_cams, 12)) for a linearisation."""
     rs = reduced_system(P, lin, lam, manifold)
@@ -330,13 +341,18 @@ def lm_solve(prob, cams0=None, opts: Options | None = None, lam=None, P=None) ->
     for it in range(opts.max_iters):
         if lin is None:
             lin = linearize(P, X, prob)
-        dP = camera_step(P, lin, lam, opts.order, opts.manifold, opts.rtol)
-        Pn = retract(P, dP, opts.manifold)
-        Xn, _ = solve_landmarks(Pn, prob)
-        fn = cost(Pn, Xn, prob)
+        rs = reduced_system(P, lin, lam, opts.manifold)
         res.trace_lambda.append(lam)
+        if not factorizable(rs):
+            # R12: a step whose damped camera block has no Cholesky factor is rejected
+            fn, accepted = np.inf, False
+        else:
+            xt, _ = power_series(rs, opts.order, opts.rtol)
+            Pn = retract(P, back_project(rs, xt), opts.manifold)
+            Xn, _ = solve_landmarks(Pn, prob)
+            fn = cost(Pn, Xn, prob)
+            accepted = bool(np.isfinite(fn) and fn < f)
         res.trace_cost.append(fn)
-        accepted = bool(np.isfinite(fn) and fn < f)
         res.trace_accept.append(accepted)
         res.iters = it + 1
         if accepted:

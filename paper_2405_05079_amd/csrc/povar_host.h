@@ -35,18 +35,20 @@ struct HostLayout {
   std::vector<float> cm_m32;
   std::vector<double> cm_m64;
   std::vector<int32_t> ch_beg, ch_cam, cam_ch;
+  std::vector<int32_t> mc_cam;         // cameras spanning more than one chunk
+  int32_t n_mc = 0, n_cg = 0;
 };
 
 // Byte offsets of every buffer inside a problem's device arena
 // (SIZE_MAX = not allocated for this precision).
 struct ArenaOffsets {
-  size_t pk_off, pk_n, pk_lm0, pk_code, pk_m32, pk_m64, cm_lm, cm_m32, cm_m64, ch_beg, ch_cam, cam_ch;
+  size_t pk_off, pk_n, pk_lm0, pk_code, pk_m32, pk_m64, cm_lm, cm_m32, cm_m64, ch_beg, ch_cam, cam_ch, mc_cam;
   size_t P64[2], P32[2], rec64[2], rec32[2], Vp64[2];
-  size_t lin_part, K64, g64, U40, x, acc, zx, t_part, cam_cnt, cost_part;
+  size_t lin_part, K64, g64, U40, x, acc, zx, t_part, cost_part, cost_group;
   size_t tr_cost, tr_lambda, tr_acc, rec, tables;
 };
 
-size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_t n_ch, bool fp32,
+size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_t n_ch, int64_t n_mc, bool fp32,
                    int64_t trace_cap, ArenaOffsets* o);
 povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs, const int32_t* cam,
                           const int32_t* pt, const double* meas, bool fp32, HostLayout& L);

@@ -44,7 +44,7 @@ struct Ctl {
   int32_t iter_limit;   // done when iter reaches it
   int32_t order;        // series order m of the next steps
   int32_t stop_reason;  // 1: ftol
-  int32_t status;       // bit 0: a damped camera block was not positive definite
+  int32_t status;       // bit 0: a damped camera block of this step could not be factored
   int32_t pad0, pad1;
 };
 
@@ -73,6 +73,8 @@ struct DevProblem {
   const int32_t* ch_beg;    // n_ch + 1: chunk c covers [ch_beg[c], ch_beg[c+1])
   const int32_t* ch_cam;    // camera of chunk c (a chunk never spans two cameras)
   const int32_t* cam_ch;    // n_p + 1: chunks of camera i are cam_ch[i]..cam_ch[i+1]-1
+  const int32_t* mc_cam;    // n_mc cameras whose observations span more than one chunk
+  int32_t n_mc, n_cg;       // multi-chunk cameras; cost groups (kCostGroup packets each)
 
   // cameras, double-buffered (current / trial), n_p x 12
   double* P64[2];
@@ -94,15 +96,24 @@ struct DevProblem {
   double* acc;              // n_p x 12, partial sum x(m) (FP64)
   void* zx;                 // n_l x 8, (z, X) records of the current order
   void* t_part;             // n_ch x 12 chunk partials
-  uint32_t* cam_cnt;        // n_p arrival counters (reset by the last workgroup)
-  double* cost_part;        // n_pk
+  double* cost_part;        // n_pk landmark-solve cost partials (one per packet)
+  double* cost_group;       // n_cg sums of kCostGroup consecutive packet partials
   double* tr_cost;          // trace_cap entries
   double* tr_lambda;
   int32_t* tr_acc;
 };
 
 // Unit kinds of a launch.
-enum UnitKind { kUnitPacket = 0, kUnitChunk = 1, kUnitCamWave = 2, kUnitOne = 3, kNumUnitKinds = 4 };
+enum UnitKind {
+  kUnitPacket = 0,     // one wave per landmark packet
+  kUnitChunk = 1,      // one workgroup per camera chunk
+  kUnitCamWave = 2,    // one wave per 64 cameras
+  kUnitOne = 3,        // one workgroup per problem
+  kUnitMultiCam = 4,   // one wave per camera spanning several chunks
+  kUnitCostGroup = 5,  // one workgroup per kCostGroup packets
+  kNumUnitKinds = 6
+};
+constexpr int kCostGroup = 2048;
 
 // A batch of problems: device array of records and, per unit kind, the
 // prefix table of units per problem (n_prob + 1 entries each).
@@ -120,7 +131,8 @@ hipError_t launch_cost_finalize(const Batch& b, int mode, hipStream_t s);    // 
 hipError_t launch_linearize(const Batch& b, bool fp32, int force, hipStream_t s);
 hipError_t launch_camera_prep(const Batch& b, bool fp32, hipStream_t s);
 hipError_t launch_series_landmark(const Batch& b, bool fp32, int t, hipStream_t s);
-hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s);
+hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s);   // + multi-chunk combine
+hipError_t launch_cost_groups(const Batch& b, int trial, hipStream_t s);
 hipError_t launch_retract(const Batch& b, bool fp32, hipStream_t s);
 hipError_t launch_decide(const Batch& b, hipStream_t s);
 

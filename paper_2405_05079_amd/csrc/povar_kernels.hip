@@ -403,26 +403,37 @@ __global__ void __launch_bounds__(kBlock) k_landmark_solve(Batch B, int mode) {
   if (lane == 0) D.cost_part[q] = ftot;
 }
 
-// Sum of the per-packet cost partials by one workgroup: thread t adds
-// packets t, t+256, ... in order (four independent accumulators interleaved
-// by stride 1024), then a fixed tree.  Thread 0 gets the total.
-__device__ __forceinline__ double packet_cost_sum(const DevProblem& D) {
+// Cost reduction in two fixed-order levels: k_cost_groups adds kCostGroup
+// consecutive packet partials per workgroup, then one workgroup adds the
+// groups (thread t adds groups t, t+256, ... in order, then a fixed tree).
+__device__ __forceinline__ double block_sum(double v) {
   __shared__ double red[kWavesPerBlock];
-  const int t = threadIdx.x;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  const int n = D.n_pk;
-  int q = t;
-  for (; q + 3 * kBlock < n; q += 4 * kBlock) {
-    a0 += D.cost_part[q];
-    a1 += D.cost_part[q + kBlock];
-    a2 += D.cost_part[q + 2 * kBlock];
-    a3 += D.cost_part[q + 3 * kBlock];
-  }
-  for (; q < n; q += kBlock) a0 += D.cost_part[q];
-  const double s = wave_sum((a0 + a1) + (a2 + a3));
-  if (lane_id() == 0) red[t >> 6] = s;
+  const double s = wave_sum(v);
+  if (lane_id() == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   return ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ void __launch_bounds__(kBlock) k_cost_groups(Batch B, int trial) {
+  int p, g;
+  if (!map_block(B, kUnitCostGroup, p, g)) return;
+  DevProblem& D = B.probs[p];
+  if (trial && D.ctl.done) return;
+  const int q0 = g * kCostGroup, q1 = min(q0 + kCostGroup, D.n_pk);
+  double a = 0.0;
+#pragma unroll
+  for (int r = 0; r < kCostGroup / kBlock; ++r) {
+    const int q = q0 + r * kBlock + (int)threadIdx.x;
+    if (q < q1) a += D.cost_part[q];
+  }
+  const double s = block_sum(a);
+  if (threadIdx.x == 0) D.cost_group[g] = s;
+}
+
+__device__ __forceinline__ double packet_cost_sum(const DevProblem& D) {
+  double a = 0.0;
+  for (int q = threadIdx.x; q < D.n_cg; q += kBlock) a += D.cost_group[q];
+  return block_sum(a);
 }
 
 // cost of a landmark solve outside the LM loop, one workgroup per problem:
@@ -528,11 +539,12 @@ __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
 
 // ----------------------------------------------------------- k_camera_prep
 // One lane per camera, FP64.  After a linearisation it adds the camera's
-// chunk partials in order.  U_l = U + lambda diag(U) (floored), then on the
-// sphere A = Pi U_l Pi + tau p p^T with Pi = I - p p^T, tau = tr(U_l)/12
-// (A restricted to the tangent space is B^T U_l B for any orthonormal basis
-// B of p^perp, and A p = tau p).  K = Pi A^-1 Pi = B (B^T U_l B)^-1 B^T is
-// stored; x_0 = acc = -K g with g = b_p - sum W_k V^+ b_l.  Euclidean: K = U_l^-1.
+// chunk partials in order.  U_l = U + lambda diag(U) (floored).  On the
+// sphere the tangent-space inverse B (B^T U_l B)^-1 B^T (B any orthonormal
+// basis of p^perp) equals the constrained (KKT) form
+//   K = U_l^-1 - w w^T / (p^T w),   w = U_l^-1 p ,
+// which needs only the Cholesky factor of U_l.  Euclidean: K = U_l^-1.
+// x_0 = acc = -K g with g = b_p - sum W_k V^+ b_l.
 __host__ __device__ constexpr int tri(int r, int c) { return r * (r + 1) / 2 + c; }
 
 template <typename T>
@@ -598,26 +610,8 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
 
   double pv[12];
   load12(pc ? D.P64[1] + (size_t)i * kCam : D.P64[0] + (size_t)i * kCam, pv);
-  if (sphere) {
-    double w12[12], tr = 0.0, s = 0.0;
-#pragma unroll
-    for (int r = 0; r < 12; ++r) {
-      double acc = 0.0;
-#pragma unroll
-      for (int c = 0; c < 12; ++c) acc += L[r >= c ? tri(r, c) : tri(c, r)] * pv[c];
-      w12[r] = acc;
-      tr += L[tri(r, r)];
-    }
-#pragma unroll
-    for (int r = 0; r < 12; ++r) s += pv[r] * w12[r];
-    const double st = s + tr / 12.0;
-#pragma unroll
-    for (int r = 0; r < 12; ++r) {
-#pragma unroll
-      for (int c = 0; c <= r; ++c) L[tri(r, c)] += -pv[r] * w12[c] - w12[r] * pv[c] + st * pv[r] * pv[c];
-    }
-  }
-  // Cholesky A = L L^T in place
+  // Cholesky U_l = L L^T in place (Marquardt damping keeps the diagonally
+  // scaled block well conditioned; Cholesky is insensitive to that scaling)
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < 12; ++j) {
@@ -648,16 +642,17 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
       L[tri(r, j)] = -v / L[tri(r, r)];
     }
   }
-  double wp[12], sp = 0.0;
+  // sphere: w = U_l^-1 p, h = p^T U_l^-1 p
+  double wp[12], ih = 0.0;
   if (sphere) {
-    double u[12];
+    double u[12], h = 0.0;
 #pragma unroll
     for (int r = 0; r < 12; ++r) {
       double v = 0.0;
 #pragma unroll
       for (int k = 0; k <= r; ++k) v += L[tri(r, k)] * pv[k];
       u[r] = v;
-      sp += v * v;
+      h += v * v;
     }
 #pragma unroll
     for (int r = 0; r < 12; ++r) {
@@ -666,6 +661,7 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
       for (int k = r; k < 12; ++k) v += L[tri(k, r)] * u[k];
       wp[r] = v;
     }
+    ih = 1.0 / h;
   }
   double x0[12];
 #pragma unroll
@@ -678,7 +674,7 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
       double v = 0.0;
 #pragma unroll
       for (int k = r; k < 12; ++k) v += L[tri(k, r)] * L[tri(k, c)];
-      if (sphere) v += -pv[r] * wp[c] - wp[r] * pv[c] + sp * pv[r] * pv[c];
+      if (sphere) v -= wp[r] * wp[c] * ih;
       if (!ok) v = 0.0;
       K64[r * 12 + c] = v;
       K64[c * 12 + r] = v;
@@ -790,6 +786,20 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
 
 // --------------------------------------------------------- k_series_camera
 // t_i = sum_k vec((N_k Pbar_i z_j) x~_j^T); x_i = K_i t_i; acc_i += x_i.
+// The camera block is applied in FP64 in both precisions.
+template <typename T>
+__device__ __forceinline__ void camera_solve(DevProblem& D, int cam, const T* tv) {
+  const int k = threadIdx.x;
+  if (k >= 12) return;
+  double kr[12];
+  load12(D.K64 + (size_t)cam * kCamMat + k * 12, kr);
+  double xr = 0.0;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) xr += kr[c] * (double)tv[c];
+  static_cast<T*>(D.x)[(size_t)cam * kCam + k] = (T)xr;
+  D.acc[(size_t)cam * kCam + k] += xr;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
   int p, ch;
@@ -833,7 +843,6 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
   }
   __shared__ T red[kWavesPerBlock][12];
   __shared__ T tv[12];
-  __shared__ uint32_t last;
   const int wv = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
@@ -841,50 +850,46 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
     if (lane_id() == 0) red[wv][k] = s;
   }
   __syncthreads();
-  const int c0 = D.cam_ch[cam], nch = D.cam_ch[cam + 1] - c0;
   const int k = threadIdx.x;
-  if (nch == 1) {
-    if (k < 12) tv[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
-  } else {
-    if (k < 12) {
-      static_cast<T*>(D.t_part)[(size_t)ch * kCam + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
-      __threadfence();   // release the partial at device scope
-    }
-    __syncthreads();
-    if (k == 0) last = atomicAdd(D.cam_cnt + cam, 1u) == (uint32_t)(nch - 1) ? 1u : 0u;
-    __syncthreads();
-    if (!last) return;
-    if (wv != 0) return;
-    __threadfence();     // acquire the other chunks' partials
-    T s[12];
-#pragma unroll
-    for (int kk = 0; kk < 12; ++kk) s[kk] = 0;
-    for (int qq = lane_id(); qq < nch; qq += kWave) {
-      const T* part = static_cast<const T*>(D.t_part) + (size_t)(c0 + qq) * kCam;
-#pragma unroll
-      for (int kk = 0; kk < 12; ++kk) s[kk] += ld_coherent(part + kk);
-    }
-#pragma unroll
-    for (int kk = 0; kk < 12; ++kk) s[kk] = wave_sum(s[kk]);
-    if (k == 0) {
-#pragma unroll
-      for (int kk = 0; kk < 12; ++kk) tv[kk] = s[kk];
-      __hip_atomic_store(D.cam_cnt + cam, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+  const int nch = D.cam_ch[cam + 1] - D.cam_ch[cam];
+  if (nch > 1) {
+    // finished by k_series_camera_combine after all chunks are written
+    if (k < 12) static_cast<T*>(D.t_part)[(size_t)ch * kCam + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    return;
   }
-  // single chunk: the whole workgroup is here; several: only wave 0 is left
-  if (nch == 1) __syncthreads();
-  else __builtin_amdgcn_wave_barrier();
-  // x_i = K_i t_i with the FP64 camera block in both precisions
-  if (k < 12) {
-    double kr[12];
-    load12(D.K64 + (size_t)cam * kCamMat + k * 12, kr);
-    double xr = 0.0;
+  if (k < 12) tv[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  __syncthreads();
+  camera_solve<T>(D, cam, tv);
+}
+
+// One wave per camera whose observations span several chunks: adds the
+// chunk partials in chunk order (lane-strided, then a fixed tree) and
+// applies the camera block.
+template <typename T>
+__global__ void __launch_bounds__(kWave) k_series_camera_combine(Batch B, int t) {
+  int p, u;
+  if (!map_wave(B, kUnitMultiCam, p, u)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done || t > D.ctl.order) return;
+  const int cam = D.mc_cam[u];
+  const int c0 = D.cam_ch[cam], nch = D.cam_ch[cam + 1] - c0;
+  T s[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) xr += kr[c] * (double)tv[c];
-    static_cast<T*>(D.x)[(size_t)cam * kCam + k] = (T)xr;
-    D.acc[(size_t)cam * kCam + k] += xr;
+  for (int kk = 0; kk < 12; ++kk) s[kk] = 0;
+  for (int q = lane_id(); q < nch; q += kWave) {
+    T v[12];
+    load12(static_cast<const T*>(D.t_part) + (size_t)(c0 + q) * kCam, v);
+#pragma unroll
+    for (int kk = 0; kk < 12; ++kk) s[kk] += v[kk];
   }
+  __shared__ T tv[12];
+#pragma unroll
+  for (int kk = 0; kk < 12; ++kk) {
+    const T r = wave_sum(s[kk]);
+    if (lane_id() == 0) tv[kk] = r;
+  }
+  __syncthreads();
+  camera_solve<T>(D, cam, tv);
 }
 
 // --------------------------------------------------------------- k_retract
@@ -922,8 +927,10 @@ __global__ void __launch_bounds__(kWave) k_retract(Batch B) {
 
 // ---------------------------------------------------------------- k_decide
 // Adds the trial cost partials (packet order), then: strict decrease accepts
-// (NaN rejects); lambda /10 on accept, x10 on reject, clamped; relinearise
-// only after an accept; ftol on accepted steps.  One workgroup per problem.
+// (NaN rejects, and so does a step whose damped camera block could not be
+// Cholesky-factored); lambda /10 on accept, x10 on reject, clamped;
+// relinearise only after an accept; ftol on accepted steps.  One workgroup
+// per problem.
 __global__ void __launch_bounds__(kBlock) k_decide(Batch B) {
   int p, w;
   if (!map_block(B, kUnitOne, p, w)) return;
@@ -933,11 +940,14 @@ __global__ void __launch_bounds__(kBlock) k_decide(Batch B) {
   if (threadIdx.x != 0) return;
   Ctl& c = D.ctl;
   const double f = c.cost;
-  c.cost_trial = fn;
-  const bool accept = (fn < f) && (fn - fn == 0.0);
+  // a step whose damped camera block could not be factored is rejected
+  const bool factored = (c.status & 1) == 0;
+  c.status &= ~1;
+  c.cost_trial = factored ? fn : INFINITY;
+  const bool accept = factored && (fn < f) && (fn - fn == 0.0);
   const int it = c.iter;
   if (it < D.trace_cap) {
-    D.tr_cost[it] = fn;
+    D.tr_cost[it] = c.cost_trial;
     D.tr_lambda[it] = c.lambda;
     D.tr_acc[it] = accept ? 1 : 0;
   }
@@ -1004,6 +1014,17 @@ hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s)
   const dim3 g = blocks_for(b.total[kUnitChunk], 1);
   if (fp32) hipLaunchKernelGGL(k_series_camera<float>, g, dim3(kBlock), 0, s, b, t);
   else hipLaunchKernelGGL(k_series_camera<double>, g, dim3(kBlock), 0, s, b, t);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || b.total[kUnitMultiCam] == 0) return e;
+  const dim3 gm = blocks_for(b.total[kUnitMultiCam], 1);
+  if (fp32) hipLaunchKernelGGL(k_series_camera_combine<float>, gm, dim3(kWave), 0, s, b, t);
+  else hipLaunchKernelGGL(k_series_camera_combine<double>, gm, dim3(kWave), 0, s, b, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_cost_groups(const Batch& b, int trial, hipStream_t s) {
+  if (b.total[kUnitCostGroup] == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cost_groups, blocks_for(b.total[kUnitCostGroup], 1), dim3(kBlock), 0, s, b, trial);
   return hipGetLastError();
 }
 

@@ -50,7 +50,7 @@ struct ArenaPlan {
   }
 };
 
-size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_t n_ch, bool fp32,
+size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_t n_ch, int64_t n_mc, bool fp32,
                    int64_t trace_cap, ArenaOffsets* o) {
   ArenaPlan a;
   ArenaOffsets tmp;
@@ -68,6 +68,7 @@ size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_
   r.ch_beg = a.take((n_ch + 1) * 4);
   r.ch_cam = a.take(n_ch * 4);
   r.cam_ch = a.take((n_p + 1) * 4);
+  r.mc_cam = a.take(n_mc * 4);
   for (int b = 0; b < 2; ++b) {
     r.P64[b] = a.take(n_p * kCam * 8);
     r.P32[b] = a.take(n_p * kCam * 4);
@@ -83,8 +84,8 @@ size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_
   r.acc = a.take(n_p * kCam * 8);
   r.zx = a.take(n_l * kRec * ts);
   r.t_part = a.take(n_ch * kCam * ts);
-  r.cam_cnt = a.take(n_p * 4);
   r.cost_part = a.take(n_pk * 8);
+  r.cost_group = a.take((n_pk + kCostGroup - 1) / kCostGroup * 8);
   r.tr_cost = a.take(trace_cap * 8);
   r.tr_lambda = a.take(trace_cap * 8);
   r.tr_acc = a.take(trace_cap * 4);
@@ -94,7 +95,7 @@ size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_
 }
 
 size_t layout_footprint(const HostLayout& L, bool fp32) {
-  return arena_bytes(L.n_p, L.n_l, L.n_obs, L.n_pk, L.n_ch, fp32, kTraceCapacity, nullptr);
+  return arena_bytes(L.n_p, L.n_l, L.n_obs, L.n_pk, L.n_ch, L.n_mc, fp32, kTraceCapacity, nullptr);
 }
 
 // ------------------------------------------------------------------ layout
@@ -230,6 +231,10 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
       L.ch_cam[q] = i;
     }
   L.ch_beg[L.n_ch] = (int32_t)n_obs;
+  for (int32_t i = 0; i < n_p; ++i)
+    if (L.cam_ch[i + 1] - L.cam_ch[i] > 1) L.mc_cam.push_back(i);
+  L.n_mc = (int32_t)L.mc_cam.size();
+  L.n_cg = (L.n_pk + kCostGroup - 1) / kCostGroup;
   return POVAR_OK;
 }
 
@@ -303,7 +308,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   pb->L = std::move(L);
   HostLayout& H = pb->L;
   ArenaOffsets& A = pb->off;
-  pb->bytes = arena_bytes(H.n_p, H.n_l, H.n_obs, H.n_pk, H.n_ch, pb->fp32, pb->trace_cap, &A);
+  pb->bytes = arena_bytes(H.n_p, H.n_l, H.n_obs, H.n_pk, H.n_ch, H.n_mc, pb->fp32, pb->trace_cap, &A);
   hipError_t e = hipMalloc(&pb->arena, pb->bytes);
   if (e != hipSuccess) {
     pb->arena = nullptr;
@@ -342,6 +347,8 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.n_p = H.n_p;
   R.n_l = H.n_l;
   R.n_pk = H.n_pk;
+  R.n_mc = H.n_mc;
+  R.n_cg = H.n_cg;
   R.n_ch = H.n_ch;
   R.manifold = o->manifold;
   R.trace_cap = pb->trace_cap;
@@ -361,6 +368,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.ch_beg = (const int32_t*)dp(A.ch_beg);
   R.ch_cam = (const int32_t*)dp(A.ch_cam);
   R.cam_ch = (const int32_t*)dp(A.cam_ch);
+  R.mc_cam = (const int32_t*)dp(A.mc_cam);
   for (int b = 0; b < 2; ++b) {
     R.P64[b] = (double*)dp(A.P64[b]);
     R.P32[b] = (float*)dp(A.P32[b]);
@@ -376,8 +384,8 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.acc = (double*)dp(A.acc);
   R.zx = dp(A.zx);
   R.t_part = dp(A.t_part);
-  R.cam_cnt = (uint32_t*)dp(A.cam_cnt);
   R.cost_part = (double*)dp(A.cost_part);
+  R.cost_group = (double*)dp(A.cost_group);
   R.tr_cost = (double*)dp(A.tr_cost);
   R.tr_lambda = (double*)dp(A.tr_lambda);
   R.tr_acc = (int32_t*)dp(A.tr_acc);
@@ -389,7 +397,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   c.order = o->series_order;
 
   // batch of one: prefix tables of waves per unit kind
-  const int32_t units[kNumUnitKinds] = {H.n_pk, H.n_ch, (H.n_p + kWave - 1) / kWave, 1};
+  const int32_t units[kNumUnitKinds] = {H.n_pk, H.n_ch, (H.n_p + kWave - 1) / kWave, 1, H.n_mc, H.n_cg};
   int32_t tables[kNumUnitKinds * 2];
   for (int k = 0; k < kNumUnitKinds; ++k) {
     tables[2 * k] = 0;
@@ -410,6 +418,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   upload(img, A.ch_beg, H.ch_beg);
   upload(img, A.ch_cam, H.ch_cam);
   upload(img, A.cam_ch, H.cam_ch);
+  upload(img, A.mc_cam, H.mc_cam);
   upload(img, A.P64[0], P64);
   upload(img, A.P32[0], P32);
   std::memcpy(img.data() + A.rec, &R, sizeof(R));
@@ -430,6 +439,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   B.n_prob = 1;
   // initial landmarks and cost, Eq. (8)-(9)
   HIP_TRY(ctx, launch_landmark_solve(B, 0, stream));
+  HIP_TRY(ctx, launch_cost_groups(B, 0, stream));
   HIP_TRY(ctx, launch_cost_finalize(B, 0, stream));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
   // free the host copies of what only the device needs
@@ -439,6 +449,8 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   keep.n_obs = H.n_obs;
   keep.n_pk = H.n_pk;
   keep.n_ch = H.n_ch;
+  keep.n_mc = H.n_mc;
+  keep.n_cg = H.n_cg;
   keep.int2ext = std::move(H.int2ext);
   keep.cam_ch = std::move(H.cam_ch);
   H = std::move(keep);
@@ -495,6 +507,7 @@ hipError_t enqueue_iteration(povar_problem_s* pb, bool timed) {
   if ((e = enqueue_series(pb, pb->opt.series_order, timed)) != hipSuccess) return e;
   if ((e = launch_retract(B, pb->fp32, pb->stream)) != hipSuccess) return e;
   if ((e = launch_landmark_solve(B, 1, pb->stream)) != hipSuccess) return e;
+  if ((e = launch_cost_groups(B, 1, pb->stream)) != hipSuccess) return e;
   return launch_decide(B, pb->stream);
 }
 
@@ -682,7 +695,7 @@ povar_status povar_problem_footprint(int32_t n_cams, int32_t n_pts, int64_t n_ob
   // at most one chunk per camera
   const int64_t n_pk = n_pts;
   const int64_t n_ch = n_obs / kChunk + n_cams;
-  *bytes = arena_bytes(n_cams, n_pts, n_obs, n_pk, n_ch, precision == POVAR_PREC_FP32_BULK,
+  *bytes = arena_bytes(n_cams, n_pts, n_obs, n_pk, n_ch, n_cams, precision == POVAR_PREC_FP32_BULK,
                        kTraceCapacity, nullptr);
   return POVAR_OK;
 }
@@ -762,10 +775,6 @@ static povar_status run_iters(povar_problem pb, int32_t n, bool check_done, pova
   }
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   fill_report(pb, c, secs, report);
-  if (c.status & 1) {
-    set_error(ctx, "a damped camera block was not positive definite");
-    return POVAR_ENUMERIC;
-  }
   return POVAR_OK;
 }
 
@@ -878,6 +887,7 @@ povar_status povar_set_state(povar_problem pb, const double* cams, double lambda
   c.status = 0;
   HIP_TRY(ctx, write_ctl(pb, &c));
   HIP_TRY(ctx, launch_landmark_solve(pb->batch, 2, pb->stream));
+  HIP_TRY(ctx, launch_cost_groups(pb->batch, 0, pb->stream));
   HIP_TRY(ctx, launch_cost_finalize(pb->batch, 2, pb->stream));
   HIP_TRY(ctx, read_ctl(pb, &c));
   if (!std::isfinite(c.cost)) {
@@ -976,6 +986,7 @@ povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, do
   }
   HIP_TRY(ctx, launch_retract(B, pb->fp32, pb->stream));
   HIP_TRY(ctx, launch_landmark_solve(B, 1, pb->stream));
+  HIP_TRY(ctx, launch_cost_groups(B, 1, pb->stream));
   HIP_TRY(ctx, launch_cost_finalize(B, 1, pb->stream));
   Ctl after;
   HIP_TRY(ctx, read_ctl(pb, &after));
@@ -992,7 +1003,7 @@ povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, do
   restore.status = after.status;
   HIP_TRY(ctx, write_ctl(pb, &restore));
   if (after.status & 1) {
-    set_error(ctx, "a damped camera block was not positive definite");
+    set_error(ctx, "a damped camera block could not be factored at this damping");
     return POVAR_ENUMERIC;
   }
   return POVAR_OK;

@@ -107,7 +107,7 @@ hipError_t upload_tables(povar_server_s* sv, Group& G) {
   G.max_order = 0;
   for (int p = 0; p < n; ++p) {
     const HostLayout& L = G.res[p].pb->L;
-    const int32_t units[kNumUnitKinds] = {L.n_pk, L.n_ch, (L.n_p + kWave - 1) / kWave, 1};
+    const int32_t units[kNumUnitKinds] = {L.n_pk, L.n_ch, (L.n_p + kWave - 1) / kWave, 1, L.n_mc, L.n_cg};
     for (int k = 0; k < kNumUnitKinds; ++k) tab[(size_t)k * stride + p + 1] = tab[(size_t)k * stride + p] + units[k];
     G.max_order = std::max(G.max_order, G.res[p].pb->opt.series_order);
   }
@@ -136,6 +136,7 @@ hipError_t launch_iteration(povar_server_s* sv, Group& G) {
   }
   if ((e = launch_retract(B, G.fp32, s)) != hipSuccess) return e;
   if ((e = launch_landmark_solve(B, 1, s)) != hipSuccess) return e;
+  if ((e = launch_cost_groups(B, 1, s)) != hipSuccess) return e;
   return launch_decide(B, s);
 }
 
@@ -196,8 +197,8 @@ hipError_t retire(povar_server_s* sv, Group& G, int idx, const Ctl& c) {
   r->report = rep;
   r->cams = std::move(cams);
   r->pts = std::move(pts);
-  r->status = (e != hipSuccess || st != POVAR_OK) ? POVAR_EDEVICE : ((c.status & 1) ? POVAR_ENUMERIC : POVAR_OK);
-  if (r->status != POVAR_OK) r->error = e != hipSuccess ? hipGetErrorString(e) : "camera block not positive definite";
+  r->status = (e != hipSuccess || st != POVAR_OK) ? POVAR_EDEVICE : POVAR_OK;
+  if (r->status != POVAR_OK) r->error = e != hipSuccess ? hipGetErrorString(e) : "result copy failed";
   r->finished = true;
   r->t_finish = sv->now();
   sv->used -= r->footprint;

@@ -247,6 +247,23 @@ def test_edge_cases(ctx):
     gp.close()
 
 
+def test_outlier_measurements(ctx):
+    """Gross outliers pull some landmarks far away, spreading the diagonal of
+    the camera blocks over many orders of magnitude; the damped camera
+    inverse must stay well defined down to the smallest damping."""
+    prob = case(n_cams=20, n_pts=600, seed=13, outlier_frac=0.05)
+    say("outliers")
+    gp = povar.Problem.from_synth(ctx, prob, precision="fp64")
+    P, X, f = O.initial_state(prob, prob.cams0)
+    lin = O.linearize(P, X, prob)
+    dp, _, _ = gp.debug_step(1e-2, 5)
+    assert rel(dp, O.camera_step(P, lin, 1e-2, 5)) < 1e-8
+    dp, _, ct = gp.debug_step(1e-12, 5)
+    assert np.isfinite(dp).all() and np.isfinite(ct)
+    assert np.abs(np.sum(dp * P, axis=1)).max() <= 1e-9 * np.abs(dp).max()
+    gp.close()
+
+
 def test_invalid_inputs_are_rejected(ctx):
     prob = case(**CASES[0])
     say("invalid inputs")
