@@ -47,17 +47,18 @@ def device_sync():
 
 def series_bytes(n_obs: int, n_l: int, n_p: int, fp32: bool):
     """Algorithmic bytes of one launch of each series kernel (compulsory
-    traffic: every input read once, every output written once).
-    landmark pass: per observation the camera index (4 B) and the measurement
-      (8 B FP32); per landmark x~_j (12 B), V_j^+ (24 B) and z_j written (12 B);
-      per camera x_i (48 B) and Pbar_i (36 B);
+    traffic: every input read once, every output written once; s = 4 for
+    FP32-bulk, 8 for FP64):
+    landmark pass: per observation the packed camera index (4 B) and the
+      measurement (2s); per landmark X_j (3s), V_j^+ (6 FP64 = 48 B) and z_j
+      written (3s); per camera x_i (12s) and Pbar_i (9s);
     camera pass: per observation the landmark index (4 B) and the measurement
-      (8 B); per landmark z_j (12 B) and x~_j (12 B); per camera the 12x12
-      K_i (576 B), Pbar_i (36 B), x_i written (48 B), acc_i read+written (96 B).
-    FP64 doubles every floating-point figure."""
-    s = 1 if fp32 else 2
-    lpass = (4 + 8 * s) * n_obs + 48 * s * n_l + 84 * s * n_p
-    cpass = (4 + 8 * s) * n_obs + 24 * s * n_l + 756 * s * n_p
+      (2s); per landmark z_j and X_j (6s); per camera the FP64 12x12 block K_i
+      (1152 B), Pbar_i (9s), x_i written (12s) and the FP64 partial sum acc_i
+      read and written (192 B)."""
+    s = 4 if fp32 else 8
+    lpass = (4 + 2 * s) * n_obs + (6 * s + 48) * n_l + 21 * s * n_p
+    cpass = (4 + 2 * s) * n_obs + 6 * s * n_l + (1344 + 21 * s) * n_p
     return lpass, cpass
 
 
@@ -88,6 +89,141 @@ def matched_cost(ctx, prob, ref_cost: float, max_iters: int):
     return out
 
 
+BUCKETS = [(20, 40), (40, 80), (80, 160), (160, 320), (320, 401)]
+
+
+def run_stream(ctx, probs, arrivals, budget, slots, opts):
+    """Submit probs at the given arrival offsets (seconds; None = all at once)
+    to a fresh server and wait for every result.  Returns (latencies,
+    wall seconds, max resident)."""
+    sv = povar.Server(ctx, hbm_budget_bytes=budget, max_slots=slots)
+    t0 = time.perf_counter()
+    tickets, done, lat = [], {}, {}
+    nxt = 0
+    max_res = 0
+    while len(done) < len(probs):
+        now = time.perf_counter() - t0
+        while nxt < len(probs) and (arrivals is None or arrivals[nxt] <= now):
+            tickets.append(sv.submit(probs[nxt], **opts))
+            nxt += 1
+        max_res = max(max_res, sv.stats()["active"])
+        for i, t in enumerate(tickets):
+            if i in done:
+                continue
+            r = sv.poll(t)
+            if r is not None:
+                done[i] = r
+                lat[i] = r[3][2] - r[3][0]
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t0
+    sv.close()
+    return [lat[i] for i in range(len(probs))], wall, max_res
+
+
+def serving(ctx, n_requests: int, budget: int, slots: int):
+    """Continuous-batching leg: a seeded sample of the serving stream
+    (cameras log-uniform in [20, 400], points = 250 x cameras, mean track 5,
+    series order 20, 50 iterations, FP32-bulk).  A closed-loop run (all
+    requests queued at once) calibrates the throughput; the open-loop run
+    then submits with Poisson arrivals at 0.8 x that rate."""
+    sizes = synth.serving_stream(512)[:n_requests]
+    probs = [synth.serving_problem(nc, npt, seed) for nc, npt, seed in sizes]
+    opts = dict(precision="fp32_bulk", order=20, max_iters=50, ftol=0.0)
+    _, closed_wall, _ = run_stream(ctx, probs, None, budget, slots, opts)
+    rate = 0.8 * len(probs) / closed_wall
+    rng = np.random.default_rng(4999)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(probs))) - 0.0
+    lat, wall, max_res = run_stream(ctx, probs, arrivals, budget, slots, opts)
+    lat = np.asarray(lat)
+    ncam = np.array([p.n_cams for p in probs])
+    per_bucket = {}
+    for lo, hi in BUCKETS:
+        sel = (ncam >= lo) & (ncam < hi)
+        if sel.any():
+            per_bucket[f"{lo}-{hi - 1}"] = {"n": int(sel.sum()),
+                                            "p50_s": round(float(np.percentile(lat[sel], 50)), 4),
+                                            "p99_s": round(float(np.percentile(lat[sel], 99)), 4)}
+    return {"requests": len(probs), "of_stream": 512, "iters_per_request": 50, "order": 20,
+            "precision": "fp32_bulk", "hbm_budget_bytes": budget, "max_slots": slots,
+            "closed_loop_problems_per_s": round(len(probs) / closed_wall, 3),
+            "arrival_rate_per_s": round(rate, 3), "open_loop_problems_per_s": round(len(probs) / wall, 3),
+            "p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4),
+            "max_resident": max_res, "obs_total": int(sum(p.n_obs for p in probs)),
+            "per_bucket_cameras": per_bucket}
+
+
+def copy_calibration(nbytes: int):
+    """A plain device-to-device copy of known size (HIP runs it as a blit
+    kernel), for scaling the HBM byte counters."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(a), ctypes.c_size_t(nbytes)) == 0
+    assert hip.hipMalloc(ctypes.byref(b), ctypes.c_size_t(nbytes)) == 0
+    for _ in range(3):
+        assert hip.hipMemcpy(b, a, ctypes.c_size_t(nbytes), 3) == 0   # device to device
+    assert hip.hipDeviceSynchronize() == 0
+    hip.hipFree(a)
+    hip.hipFree(b)
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}))
+
+
+def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, workload, out_path):
+    """Per-launch HBM bytes of the series kernels from rocprofv3 counter CSVs:
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) averaged over the kernel's
+    dispatches, each scaled by bytes / counter of a plain copy of copy_bytes."""
+    import csv
+
+    def per_kernel(path):
+        acc = {}
+        for row in csv.DictReader(open(path)):
+            k = row["Kernel_Name"]
+            acc.setdefault(k, []).append(float(row["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    def copy_value(path):
+        vals = [v for k, v in per_kernel(path).items() if "copyBuffer" in k or "copy" in k.lower()]
+        return max(vals)
+
+    f, w = per_kernel(fetch_csv), per_kernel(write_csv)
+    fs = copy_bytes / copy_value(copy_fetch_csv)     # bytes per FETCH_SIZE unit
+    ws = copy_bytes / copy_value(copy_write_csv)
+    data = json.load(open(out_path)) if os.path.exists(out_path) else {}
+    entry = data.setdefault(workload, {})
+    for k in f:
+        if "k_series_" not in k:
+            continue
+        short = k.split("(")[0].replace("void povar::", "").replace("povar::", "")
+        entry[short] = {"fetch_bytes_per_launch": f[k] * fs, "write_bytes_per_launch": w.get(k, 0.0) * ws,
+                        "hbm_bytes_per_launch": f[k] * fs + w.get(k, 0.0) * ws,
+                        "fetch_counter_kib": f[k], "write_counter_kib": w.get(k, 0.0),
+                        "copy_scale_fetch": fs, "copy_scale_write": ws,
+                        "kernel_source_sha256": kernel_source_hash()}
+    json.dump(data, open(out_path, "w"), indent=1)
+    print(json.dumps(entry))
+
+
+def traffic_from_profiles(kernel: str, workload: str, kernel_hash: str):
+    """HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy), if the committed summary matches this
+    kernel build and workload; None otherwise."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path)).get(workload, {}).get(kernel)
+    if not d or d.get("kernel_source_sha256") != kernel_hash:
+        return None
+    return d["hbm_bytes_per_launch"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("povar_kernels.hip", "povar_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2405_05079_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def cpu_baseline(prob, iters: int):
     from threadpoolctl import threadpool_limits
 
@@ -111,7 +247,24 @@ def main():
     ap.add_argument("--no-matched", action="store_true")
     ap.add_argument("--workload", type=int, default=WORKLOAD,
                     help="2: 250 cameras (default); 3: 1,800 cameras / 5M obs; 5: 13,700 cameras / 29M obs")
+    ap.add_argument("--serve", type=int, default=128,
+                    help="requests of the 512-request serving stream to run (0: skip)")
+    ap.add_argument("--serve-budget", type=int, default=2 << 30)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--summarize-counters", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+                                                               "COPY_WRITE_CSV", "COPY_BYTES"),
+                    help="write profiles/hbm_traffic.json from rocprofv3 counter CSVs")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.summarize_counters:
+        a = args.summarize_counters
+        summarize_counters(a[0], a[1], a[2], a[3], int(a[4]), f"workload{args.workload}",
+                           os.path.join(ROOT, "profiles", "hbm_traffic.json"))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -119,7 +272,8 @@ def main():
 
     prob = synth.workload(args.workload)
     if args.workload != WORKLOAD:
-        args.no_matched = True   # the matched-cost comparison is defined on the default workload
+        args.no_matched = True   # the matched-cost comparison and serving leg run with the default workload
+        args.serve = 0
     print(f"[bench] workload {prob.name}: {prob.n_cams} cameras, {prob.n_pts} points, "
           f"{prob.n_obs} observations, order {prob.order}", file=sys.stderr, flush=True)
     ctx = povar.Context(0)
@@ -150,9 +304,11 @@ def main():
     else:
         name, ms, byt = "k_series_camera<float>", ms_c, bc
     achieved = byt / (ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(name, f"workload{args.workload}", kernel_source_hash())
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": name,
                 "avg_us": round(ms * 1e3, 3), "bytes_per_launch": int(byt),
+                "traffic_over_algorithmic": round(traffic / byt, 3) if traffic else None,
                 "series_pair_us": round((ms_l + ms_c) * 1e3, 3)}
 
     out = {
@@ -191,6 +347,10 @@ def main():
                 m["oracle_cost_final"] = g["cost_final"]
                 m["fp64_rel_vs_oracle"] = abs(r64["cost_final"] - g["cost_final"]) / g["cost_final"]
         out["matched_cost"] = m
+    if args.serve > 0:
+        out["serving"] = serving(ctx, args.serve, args.serve_budget, args.serve_slots)
+        print(f"[bench] serving: p50 {out['serving']['p50_s']} s, p99 {out['serving']['p99_s']} s",
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_iters)
     ctx.close()

@@ -130,8 +130,10 @@ hipError_t launch_landmark_solve(const Batch& b, int mode, hipStream_t s);   // 
 hipError_t launch_cost_finalize(const Batch& b, int mode, hipStream_t s);    // mode 0 init, 1 trial, 2 reset
 hipError_t launch_linearize(const Batch& b, bool fp32, int force, hipStream_t s);
 hipError_t launch_camera_prep(const Batch& b, bool fp32, hipStream_t s);
-hipError_t launch_series_landmark(const Batch& b, bool fp32, int t, hipStream_t s);
-hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s);   // + multi-chunk combine
+hipError_t launch_series_landmark(const Batch& b, bool fp32, int t, hipStream_t s, hipEvent_t ev0 = nullptr,
+                                  hipEvent_t ev1 = nullptr);
+hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s, hipEvent_t ev0 = nullptr,
+                                hipEvent_t ev1 = nullptr);   // + multi-chunk combine (not timed)
 hipError_t launch_cost_groups(const Batch& b, int trial, hipStream_t s);
 hipError_t launch_retract(const Batch& b, bool fp32, hipStream_t s);
 hipError_t launch_decide(const Batch& b, hipStream_t s);

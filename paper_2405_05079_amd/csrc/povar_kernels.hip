@@ -27,6 +27,8 @@
 // chunk of <= 2048 observations of one camera (8 independent loads per lane);
 // a camera spanning several chunks is finished by the last-arriving workgroup,
 // which adds the chunk partials in chunk order.
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "povar_internal.h"
@@ -1001,19 +1003,21 @@ hipError_t launch_camera_prep(const Batch& b, bool fp32, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_series_landmark(const Batch& b, bool fp32, int t, hipStream_t s) {
+// With ev0/ev1 set, the events are recorded by the dispatch itself
+// (hipExtLaunchKernelGGL), so their interval is the kernel's execution.
+hipError_t launch_series_landmark(const Batch& b, bool fp32, int t, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (b.total[kUnitPacket] == 0) return hipSuccess;
   const dim3 g = blocks_for(b.total[kUnitPacket], kWavesPerBlock);
-  if (fp32) hipLaunchKernelGGL(k_series_landmark<float>, g, dim3(kBlock), 0, s, b, t);
-  else hipLaunchKernelGGL(k_series_landmark<double>, g, dim3(kBlock), 0, s, b, t);
+  if (fp32) hipExtLaunchKernelGGL(k_series_landmark<float>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
+  else hipExtLaunchKernelGGL(k_series_landmark<double>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
   return hipGetLastError();
 }
 
-hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s) {
+hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (b.total[kUnitChunk] == 0) return hipSuccess;
   const dim3 g = blocks_for(b.total[kUnitChunk], 1);
-  if (fp32) hipLaunchKernelGGL(k_series_camera<float>, g, dim3(kBlock), 0, s, b, t);
-  else hipLaunchKernelGGL(k_series_camera<double>, g, dim3(kBlock), 0, s, b, t);
+  if (fp32) hipExtLaunchKernelGGL(k_series_camera<float>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
+  else hipExtLaunchKernelGGL(k_series_camera<double>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || b.total[kUnitMultiCam] == 0) return e;
   const dim3 gm = blocks_for(b.total[kUnitMultiCam], 1);

@@ -475,22 +475,19 @@ hipError_t write_ctl(povar_problem_s* pb, const Ctl* in) {
   return hipStreamSynchronize(pb->stream);
 }
 
-// Series kernels, optionally bracketed by timing events.
+// Series kernels; when timed, each series kernel carries a start/stop event
+// pair recorded by its own dispatch.
 static hipError_t enqueue_series(povar_problem_s* pb, int order, bool timed) {
   hipError_t e;
   for (int t = 1; t <= order; ++t) {
-    hipEvent_t ev[4];
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (timed)
       for (int q = 0; q < 4; ++q) {
         ev[q] = pb->event_pool_get();
         if (!ev[q]) return hipErrorOutOfMemory;
       }
-    if (timed && (e = hipEventRecord(ev[0], pb->stream)) != hipSuccess) return e;
-    if ((e = launch_series_landmark(pb->batch, pb->fp32, t, pb->stream)) != hipSuccess) return e;
-    if (timed && (e = hipEventRecord(ev[1], pb->stream)) != hipSuccess) return e;
-    if (timed && (e = hipEventRecord(ev[2], pb->stream)) != hipSuccess) return e;
-    if ((e = launch_series_camera(pb->batch, pb->fp32, t, pb->stream)) != hipSuccess) return e;
-    if (timed && (e = hipEventRecord(ev[3], pb->stream)) != hipSuccess) return e;
+    if ((e = launch_series_landmark(pb->batch, pb->fp32, t, pb->stream, ev[0], ev[1])) != hipSuccess) return e;
+    if ((e = launch_series_camera(pb->batch, pb->fp32, t, pb->stream, ev[2], ev[3])) != hipSuccess) return e;
     if (timed) {
       pb->pending.push_back({ev[0], ev[1], 0});
       pb->pending.push_back({ev[2], ev[3], 1});
