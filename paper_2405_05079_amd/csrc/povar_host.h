@@ -27,14 +27,14 @@ struct HostLayout {
   int64_t n_obs = 0;
   int32_t n_pk = 0, n_ch = 0;
   std::vector<int32_t> int2ext;        // internal landmark -> caller's index
-  std::vector<int32_t> pk_off, pk_n, pk_lm0;
+  std::vector<int32_t> pk_hdr;         // 2 per slot: (n, lm0)
   std::vector<uint32_t> pk_code;
   std::vector<float> pk_m32;
   std::vector<double> pk_m64;
   std::vector<int32_t> cm_lm;
   std::vector<float> cm_m32;
   std::vector<double> cm_m64;
-  std::vector<int32_t> ch_beg, ch_cam, cam_ch;
+  std::vector<int32_t> ch_meta, cam_ch;   // ch_meta: 4 per chunk
   std::vector<int32_t> mc_cam;         // cameras spanning more than one chunk
   int32_t n_mc = 0, n_cg = 0;
 };
@@ -42,7 +42,7 @@ struct HostLayout {
 // Byte offsets of every buffer inside a problem's device arena
 // (SIZE_MAX = not allocated for this precision).
 struct ArenaOffsets {
-  size_t pk_off, pk_n, pk_lm0, pk_code, pk_m32, pk_m64, cm_lm, cm_m32, cm_m64, ch_beg, ch_cam, cam_ch, mc_cam;
+  size_t pk_hdr, pk_code, pk_m32, pk_m64, cm_lm, cm_m32, cm_m64, ch_meta, cam_ch, mc_cam;
   size_t P64[2], P32[2], rec64[2], rec32[2], Vp64[2];
   size_t lin_part, K64, g64, U40, x, acc, zx, t_part, cost_part, cost_group;
   size_t tr_cost, tr_lambda, tr_acc, rec, tables;

@@ -50,19 +50,18 @@ struct Ctl {
 
 struct DevProblem {
   Ctl ctl;
-  int32_t n_p, n_l, n_pk, n_ch;
+  int32_t n_p, n_l, n_pk, n_ch;   // n_pk: packet slots
   int32_t manifold;     // 0 sphere, 1 euclidean
   int32_t trace_cap;
   int32_t pad0, pad1;
   double eta, ftol, lambda_min, lambda_max;
 
-  // landmark-major packets: packet q holds whole landmarks lm0 .. (internal
-  // ids), entries pk_off[q] .. pk_off[q] + pk_n[q] - 1, one lane per entry;
-  // pk_n > 64 only for a packet made of a single landmark with more than 64
-  // observations.  Entry code = camera | (landmark - lm0) << 26.
-  const int32_t* pk_off;
-  const int32_t* pk_n;
-  const int32_t* pk_lm0;
+  // landmark-major packets on 64-entry slots: slot q holds whole landmarks
+  // lm0, lm0+1, ... (internal ids) in entries 64q .. 64q + n - 1 (one lane
+  // per entry), with pk_hdr[q] = (n, lm0).  A landmark with more than 64
+  // observations fills consecutive slots; its first slot has n = its count
+  // and the following ones n = 0.  Entry code = camera | (landmark - lm0) << 26.
+  const int2* pk_hdr;
   const uint32_t* pk_code;
   const float2* pk_m32;
   const double2* pk_m64;
@@ -70,8 +69,8 @@ struct DevProblem {
   const int32_t* cm_lm;     // internal landmark id
   const float2* cm_m32;
   const double2* cm_m64;
-  const int32_t* ch_beg;    // n_ch + 1: chunk c covers [ch_beg[c], ch_beg[c+1])
-  const int32_t* ch_cam;    // camera of chunk c (a chunk never spans two cameras)
+  const int4* ch_meta;      // chunk c: (camera, first obs, end obs, chunks of that camera);
+                            // a chunk never spans two cameras
   const int32_t* cam_ch;    // n_p + 1: chunks of camera i are cam_ch[i]..cam_ch[i+1]-1
   const int32_t* mc_cam;    // n_mc cameras whose observations span more than one chunk
   int32_t n_mc, n_cg;       // multi-chunk cameras; cost groups (kCostGroup packets each)

@@ -51,9 +51,10 @@ __device__ __forceinline__ bool find_unit(const Batch& B, int kind, int ug, int&
   return true;
 }
 
-// one unit per wave
+// one unit per wave of a WG-thread workgroup
+template <int WG = kBlock>
 __device__ __forceinline__ bool map_wave(const Batch& B, int kind, int& p, int& u) {
-  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6));
+  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * (WG / kWave) + (threadIdx.x >> 6));
   return find_unit(B, kind, w, p, u);
 }
 
@@ -320,17 +321,23 @@ __global__ void __launch_bounds__(kBlock) k_landmark_solve(Batch B, int mode) {
   const double* __restrict__ P = pc ? D.P64[1] : D.P64[0];
   const int lane = lane_id();
   const double eta = D.eta, a = 1.0 - eta;
-  const int n = D.pk_n[q], off = D.pk_off[q], lm0 = D.pk_lm0[q];
-  double ftot;
-  if (n <= kWave) {
+  const int off = q * kWave;
+  // entry loads do not wait for the slot header
+  const uint32_t code = D.pk_code[off + lane];
+  const double2 mraw = D.pk_m64[off + lane];
+  const int2 hdr = D.pk_hdr[q];
+  const int n = hdr.x, lm0 = hdr.y;
+  double ftot = 0.0;
+  if (n == 0) {
+    // continuation slot of a landmark with more than 64 observations
+  } else if (n <= kWave) {
     const bool act = lane < n;
     int key = kWave + lane, c = 0;
     double2 m = make_double2(0.0, 0.0);
     if (act) {
-      const uint32_t code = D.pk_code[off + lane];
       c = (int)(code & kCamMask);
       key = (int)(code >> kCamBits);
-      m = D.pk_m64[off + lane];
+      m = mraw;
     }
     double Pc[12];
     if (act) load12(P + (size_t)c * kCam, Pc);
@@ -470,8 +477,8 @@ __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
   if (D.ctl.done) return;
   if (!force && !D.ctl.need_lin) return;
   const int lc = D.ctl.lcur, pc = D.ctl.pcur;
-  const int cam = D.ch_cam[ch];
-  const int beg = D.ch_beg[ch], end = D.ch_beg[ch + 1];
+  const int4 meta = D.ch_meta[ch];
+  const int cam = meta.x, beg = meta.y, end = meta.z;
   T Pc[12];
   load12(Prec<T>::P(D, pc) + (size_t)cam * kCam, Pc);
   const T* __restrict__ rec = Prec<T>::rec(D, lc);
@@ -552,7 +559,7 @@ __host__ __device__ constexpr int tri(int r, int c) { return r * (r + 1) / 2 + c
 template <typename T>
 __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
   int p, w;
-  if (!map_wave(B, kUnitCamWave, p, w)) return;
+  if (!map_wave<kWave>(B, kUnitCamWave, p, w)) return;
   DevProblem& D = B.probs[p];
   if (D.ctl.done) return;
   const int i = w * kWave + lane_id();
@@ -700,12 +707,7 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
 // the spectrum of M past 1 for the near-singular blocks of random starts;
 // applied in FP64 to the FP32 sum y_j the error stays ~eps * sqrt(cond(V_j)).
 template <typename T>
-__device__ __forceinline__ void store_z(const DevProblem& D, int lc, int j, T y0, T y1, T y2, T X0, T X1, T X2,
-                                        T* zx) {
-  double v[8];
-  const double* vp = (lc ? D.Vp64[1] : D.Vp64[0]) + (size_t)j * kLmSym;
-  load4(vp, v[0], v[1], v[2], v[3]);
-  load4(vp + 4, v[4], v[5], v[6], v[7]);
+__device__ __forceinline__ void store_z(const double (&v)[8], int j, T y0, T y1, T y2, T X0, T X1, T X2, T* zx) {
   const double d0 = y0, d1 = y1, d2 = y2;
   const double z0 = v[0] * d0 + v[1] * d1 + v[2] * d2;
   const double z1 = v[1] * d0 + v[3] * d1 + v[4] * d2;
@@ -724,22 +726,37 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
   if (D.ctl.done || t > D.ctl.order) return;
   const int lc = D.ctl.lcur, pc = D.ctl.pcur;
   const int lane = lane_id();
-  const int n = D.pk_n[q], off = D.pk_off[q], lm0 = D.pk_lm0[q];
+  const int off = q * kWave;
   const T* __restrict__ rec = Prec<T>::rec(D, lc);
   const T* __restrict__ xs = static_cast<const T*>(D.x);
   const T* __restrict__ Pm = Prec<T>::P(D, pc);
   const typename Prec<T>::T2* __restrict__ em = Prec<T>::pk_m(D);
   const T a = (T)(1.0 - D.eta);
   T* zx = static_cast<T*>(D.zx);
+  // entry loads do not wait for the slot header
+  const uint32_t code = D.pk_code[off + lane];
+  const auto mraw = em[off + lane];
+  const int2 hdr = D.pk_hdr[q];
+  const int n = hdr.x, lm0 = hdr.y;
+  if (n == 0) return;   // continuation slot of a long landmark
   if (n <= kWave) {
     const bool act = lane < n;
+    const uint32_t next = __shfl_down(code, 1, kWave);   // all lanes take part
     int key = kWave + lane;
     T y0 = 0, y1 = 0, y2 = 0, X0 = 0, X1 = 0, X2 = 0, one;
+    bool tail = false;
+    double v[8];
     if (act) {
-      const uint32_t code = D.pk_code[off + lane];
       const int c = (int)(code & kCamMask);
       key = (int)(code >> kCamBits);
-      const auto m = em[off + lane];
+      tail = lane == n - 1 || (int)(next >> kCamBits) != key;
+      // the tail lane fetches V^+ together with the gathers
+      if (tail) {
+        const double* vp = (lc ? D.Vp64[1] : D.Vp64[0]) + (size_t)(lm0 + key) * kLmSym;
+        load4(vp, v[0], v[1], v[2], v[3]);
+        load4(vp + 4, v[4], v[5], v[6], v[7]);
+      }
+      const auto m = mraw;
       load4(rec + (size_t)(lm0 + key) * kRec + 4, X0, X1, X2, one);
       T xc[12], Pc[12];
       load12(xs + (size_t)c * kCam, xc);
@@ -757,13 +774,15 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
     y0 = seg_sum(y0, links);
     y1 = seg_sum(y1, links);
     y2 = seg_sum(y2, links);
-    const int kn = __shfl_down(key, 1, kWave);
-    const bool tail = act && (lane == kWave - 1 || kn != key);
-    if (tail) store_z<T>(D, lc, lm0 + key, y0, y1, y2, X0, X1, X2, zx);
+    if (tail) store_z<T>(v, lm0 + key, y0, y1, y2, X0, X1, X2, zx);
   } else {
     T X0, X1, X2, one;
     load4(rec + (size_t)lm0 * kRec + 4, X0, X1, X2, one);
     T y0 = 0, y1 = 0, y2 = 0;
+    double v[8];
+    const double* vp = (lc ? D.Vp64[1] : D.Vp64[0]) + (size_t)lm0 * kLmSym;
+    load4(vp, v[0], v[1], v[2], v[3]);
+    load4(vp + 4, v[4], v[5], v[6], v[7]);
     for (int e = off + lane; e < off + n; e += kWave) {
       const int c = (int)(D.pk_code[e] & kCamMask);
       const auto m = em[e];
@@ -782,7 +801,7 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
     y0 = wave_sum(y0);
     y1 = wave_sum(y1);
     y2 = wave_sum(y2);
-    if (lane == 0) store_z<T>(D, lc, lm0, y0, y1, y2, X0, X1, X2, zx);
+    if (lane == 0) store_z<T>(v, lm0, y0, y1, y2, X0, X1, X2, zx);
   }
 }
 
@@ -790,11 +809,9 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
 // t_i = sum_k vec((N_k Pbar_i z_j) x~_j^T); x_i = K_i t_i; acc_i += x_i.
 // The camera block is applied in FP64 in both precisions.
 template <typename T>
-__device__ __forceinline__ void camera_solve(DevProblem& D, int cam, const T* tv) {
+__device__ __forceinline__ void camera_solve(DevProblem& D, int cam, const T* tv, const double (&kr)[12]) {
   const int k = threadIdx.x;
   if (k >= 12) return;
-  double kr[12];
-  load12(D.K64 + (size_t)cam * kCamMat + k * 12, kr);
   double xr = 0.0;
 #pragma unroll
   for (int c = 0; c < 12; ++c) xr += kr[c] * (double)tv[c];
@@ -809,10 +826,13 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
   DevProblem& D = B.probs[p];
   if (D.ctl.done || t > D.ctl.order) return;
   const int pc = D.ctl.pcur;
-  const int cam = D.ch_cam[ch];
-  const int beg = D.ch_beg[ch], end = D.ch_beg[ch + 1];
+  const int4 meta = D.ch_meta[ch];
+  const int cam = meta.x, beg = meta.y, end = meta.z, nch = meta.w;
   T Pc[12];
   load12(Prec<T>::P(D, pc) + (size_t)cam * kCam, Pc);
+  // the camera-block row of this thread, fetched before the reduction needs it
+  double kr[12];
+  if (nch == 1 && threadIdx.x < 12) load12(D.K64 + (size_t)cam * kCamMat + threadIdx.x * 12, kr);
   const T* __restrict__ zx = static_cast<const T*>(D.zx);
   const typename Prec<T>::T2* __restrict__ M = Prec<T>::cm_m(D);
   const int32_t* __restrict__ lm = D.cm_lm;
@@ -853,7 +873,6 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
   }
   __syncthreads();
   const int k = threadIdx.x;
-  const int nch = D.cam_ch[cam + 1] - D.cam_ch[cam];
   if (nch > 1) {
     // finished by k_series_camera_combine after all chunks are written
     if (k < 12) static_cast<T*>(D.t_part)[(size_t)ch * kCam + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
@@ -861,7 +880,7 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
   }
   if (k < 12) tv[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
   __syncthreads();
-  camera_solve<T>(D, cam, tv);
+  camera_solve<T>(D, cam, tv, kr);
 }
 
 // One wave per camera whose observations span several chunks: adds the
@@ -870,7 +889,7 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
 template <typename T>
 __global__ void __launch_bounds__(kWave) k_series_camera_combine(Batch B, int t) {
   int p, u;
-  if (!map_wave(B, kUnitMultiCam, p, u)) return;
+  if (!map_wave<kWave>(B, kUnitMultiCam, p, u)) return;
   DevProblem& D = B.probs[p];
   if (D.ctl.done || t > D.ctl.order) return;
   const int cam = D.mc_cam[u];
@@ -891,14 +910,16 @@ __global__ void __launch_bounds__(kWave) k_series_camera_combine(Batch B, int t)
     if (lane_id() == 0) tv[kk] = r;
   }
   __syncthreads();
-  camera_solve<T>(D, cam, tv);
+  double kr[12];
+  if (threadIdx.x < 12) load12(D.K64 + (size_t)cam * kCamMat + threadIdx.x * 12, kr);
+  camera_solve<T>(D, cam, tv, kr);
 }
 
 // --------------------------------------------------------------- k_retract
 template <typename T>
 __global__ void __launch_bounds__(kWave) k_retract(Batch B) {
   int p, w;
-  if (!map_wave(B, kUnitCamWave, p, w)) return;
+  if (!map_wave<kWave>(B, kUnitCamWave, p, w)) return;
   DevProblem& D = B.probs[p];
   if (D.ctl.done) return;
   const int i = w * kWave + lane_id();

@@ -56,17 +56,15 @@ size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_
   ArenaOffsets tmp;
   ArenaOffsets& r = o ? *o : tmp;
   const size_t ts = fp32 ? 4 : 8;
-  r.pk_off = a.take(n_pk * 4);
-  r.pk_n = a.take(n_pk * 4);
-  r.pk_lm0 = a.take(n_pk * 4);
-  r.pk_code = a.take(n_obs * 4);
-  r.pk_m32 = fp32 ? a.take(n_obs * 8) : SIZE_MAX;
-  r.pk_m64 = a.take(n_obs * 16);
+  const int64_t n_ent = n_pk * kWave;   // packet slots of 64 entries
+  r.pk_hdr = a.take(n_pk * 8);
+  r.pk_code = a.take(n_ent * 4);
+  r.pk_m32 = fp32 ? a.take(n_ent * 8) : SIZE_MAX;
+  r.pk_m64 = a.take(n_ent * 16);
   r.cm_lm = a.take(n_obs * 4);
   r.cm_m32 = fp32 ? a.take(n_obs * 8) : SIZE_MAX;
   r.cm_m64 = fp32 ? SIZE_MAX : a.take(n_obs * 16);
-  r.ch_beg = a.take((n_ch + 1) * 4);
-  r.ch_cam = a.take(n_ch * 4);
+  r.ch_meta = a.take(n_ch * 16);
   r.cam_ch = a.take((n_p + 1) * 4);
   r.mc_cam = a.take(n_mc * 4);
   for (int b = 0; b < 2; ++b) {
@@ -164,37 +162,66 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
     set_error(ctx, "n_cams exceeds the supported maximum");
     return POVAR_EINVAL;
   }
-  // landmark-major packets: greedy runs of whole landmarks with <= 64
-  // observations; a landmark with more than 64 observations is a packet alone
-  L.pk_code.resize(n_obs);
-  L.pk_m64.resize(2 * n_obs);
-  if (fp32) L.pk_m32.resize(2 * n_obs);
-  int64_t ent = 0;
-  int32_t open_n = 0;
-  for (int32_t jj = 0; jj < n_l; ++jj) {
-    const int32_t j = L.int2ext[jj];
-    const int32_t len = cnt_l[j];
-    if (len > kWave || open_n + len > kWave || open_n == 0) {
-      L.pk_off.push_back((int32_t)ent);
-      L.pk_n.push_back(0);
-      L.pk_lm0.push_back(jj);
-      open_n = 0;
-    }
-    const int32_t local = jj - L.pk_lm0.back();
-    for (int64_t q = lstart[j]; q < lstart[j + 1]; ++q, ++ent) {
-      const int64_t k = lobs[q];
-      L.pk_code[ent] = (uint32_t)cam[k] | ((uint32_t)local << kCamBits);
-      L.pk_m64[2 * ent] = meas[2 * k];
-      L.pk_m64[2 * ent + 1] = meas[2 * k + 1];
-      if (fp32) {
-        L.pk_m32[2 * ent] = (float)meas[2 * k];
-        L.pk_m32[2 * ent + 1] = (float)meas[2 * k + 1];
+  // landmark-major packets on 64-entry slots: greedy runs of whole landmarks
+  // with <= 64 observations; a landmark with more than 64 observations fills
+  // consecutive slots of its own
+  std::vector<int32_t> slot_of(n_l), pos_in_slot(n_l);
+  {
+    int32_t slot = -1, used = kWave;
+    for (int32_t jj = 0; jj < n_l; ++jj) {
+      const int32_t len = cnt_l[L.int2ext[jj]];
+      if (len > kWave) {
+        slot += 1;
+        slot_of[jj] = slot;
+        pos_in_slot[jj] = 0;
+        L.pk_hdr.push_back(len);
+        L.pk_hdr.push_back(jj);
+        const int32_t extra = (len + kWave - 1) / kWave - 1;
+        for (int32_t x = 0; x < extra; ++x) {
+          L.pk_hdr.push_back(0);
+          L.pk_hdr.push_back(jj);
+        }
+        slot += extra;
+        used = kWave;   // closed
+      } else {
+        if (used + len > kWave) {
+          slot += 1;
+          used = 0;
+          L.pk_hdr.push_back(0);
+          L.pk_hdr.push_back(jj);
+        }
+        slot_of[jj] = slot;
+        pos_in_slot[jj] = used;
+        used += len;
+        L.pk_hdr[2 * slot] = used;
       }
     }
-    L.pk_n.back() += len;
-    open_n = len > kWave ? kWave : open_n + len;   // a long landmark closes its packet
+    L.n_pk = slot + 1;
   }
-  L.n_pk = (int32_t)L.pk_off.size();
+  const int64_t n_ent = (int64_t)L.n_pk * kWave;
+  if (n_ent >= (int64_t)INT_MAX) {
+    set_error(ctx, "packet layout exceeds 2^31 entries");
+    return POVAR_EINVAL;
+  }
+  L.pk_code.assign(n_ent, 0u);
+  L.pk_m64.assign(2 * n_ent, 0.0);
+  if (fp32) L.pk_m32.assign(2 * n_ent, 0.0f);
+  for (int32_t jj = 0; jj < n_l; ++jj) {
+    const int32_t j = L.int2ext[jj];
+    const int32_t slot = slot_of[jj];
+    const int32_t local = jj - L.pk_hdr[2 * slot + 1];
+    int64_t e = (int64_t)slot * kWave + pos_in_slot[jj];
+    for (int64_t q = lstart[j]; q < lstart[j + 1]; ++q, ++e) {
+      const int64_t k = lobs[q];
+      L.pk_code[e] = (uint32_t)cam[k] | ((uint32_t)local << kCamBits);
+      L.pk_m64[2 * e] = meas[2 * k];
+      L.pk_m64[2 * e + 1] = meas[2 * k + 1];
+      if (fp32) {
+        L.pk_m32[2 * e] = (float)meas[2 * k];
+        L.pk_m32[2 * e + 1] = (float)meas[2 * k + 1];
+      }
+    }
+  }
   // camera-major order: by camera, then internal landmark
   std::vector<int64_t> cstart(n_p + 1, 0);
   for (int32_t i = 0; i < n_p; ++i) cstart[i + 1] = cstart[i] + cnt_c[i];
@@ -223,14 +250,17 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
   L.cam_ch[0] = 0;
   for (int32_t i = 0; i < n_p; ++i) L.cam_ch[i + 1] = L.cam_ch[i] + (cnt_c[i] + kChunk - 1) / kChunk;
   L.n_ch = L.cam_ch[n_p];
-  L.ch_beg.resize(L.n_ch + 1);
-  L.ch_cam.resize(L.n_ch);
-  for (int32_t i = 0; i < n_p; ++i)
+  L.ch_meta.resize((size_t)4 * L.n_ch);
+  for (int32_t i = 0; i < n_p; ++i) {
+    const int32_t nch = L.cam_ch[i + 1] - L.cam_ch[i];
     for (int32_t q = L.cam_ch[i]; q < L.cam_ch[i + 1]; ++q) {
-      L.ch_beg[q] = (int32_t)(cstart[i] + (int64_t)(q - L.cam_ch[i]) * kChunk);
-      L.ch_cam[q] = i;
+      const int64_t b = cstart[i] + (int64_t)(q - L.cam_ch[i]) * kChunk;
+      L.ch_meta[4 * (size_t)q + 0] = i;
+      L.ch_meta[4 * (size_t)q + 1] = (int32_t)b;
+      L.ch_meta[4 * (size_t)q + 2] = (int32_t)std::min<int64_t>(b + kChunk, cstart[i + 1]);
+      L.ch_meta[4 * (size_t)q + 3] = nch;
     }
-  L.ch_beg[L.n_ch] = (int32_t)n_obs;
+  }
   for (int32_t i = 0; i < n_p; ++i)
     if (L.cam_ch[i + 1] - L.cam_ch[i] > 1) L.mc_cam.push_back(i);
   L.n_mc = (int32_t)L.mc_cam.size();
@@ -356,17 +386,14 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.ftol = o->ftol;
   R.lambda_min = o->lambda_min;
   R.lambda_max = o->lambda_max;
-  R.pk_off = (const int32_t*)dp(A.pk_off);
-  R.pk_n = (const int32_t*)dp(A.pk_n);
-  R.pk_lm0 = (const int32_t*)dp(A.pk_lm0);
+  R.pk_hdr = (const int2*)dp(A.pk_hdr);
   R.pk_code = (const uint32_t*)dp(A.pk_code);
   R.pk_m32 = (const float2*)dp(A.pk_m32);
   R.pk_m64 = (const double2*)dp(A.pk_m64);
   R.cm_lm = (const int32_t*)dp(A.cm_lm);
   R.cm_m32 = (const float2*)dp(A.cm_m32);
   R.cm_m64 = (const double2*)dp(A.cm_m64);
-  R.ch_beg = (const int32_t*)dp(A.ch_beg);
-  R.ch_cam = (const int32_t*)dp(A.ch_cam);
+  R.ch_meta = (const int4*)dp(A.ch_meta);
   R.cam_ch = (const int32_t*)dp(A.cam_ch);
   R.mc_cam = (const int32_t*)dp(A.mc_cam);
   for (int b = 0; b < 2; ++b) {
@@ -406,17 +433,14 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
 
   // one staging image of everything that has an initial value
   std::vector<char> img(pb->bytes, 0);
-  upload(img, A.pk_off, H.pk_off);
-  upload(img, A.pk_n, H.pk_n);
-  upload(img, A.pk_lm0, H.pk_lm0);
+  upload(img, A.pk_hdr, H.pk_hdr);
   upload(img, A.pk_code, H.pk_code);
   if (A.pk_m32 != SIZE_MAX) upload(img, A.pk_m32, H.pk_m32);
   upload(img, A.pk_m64, H.pk_m64);
   upload(img, A.cm_lm, H.cm_lm);
   if (A.cm_m32 != SIZE_MAX) upload(img, A.cm_m32, H.cm_m32);
   if (A.cm_m64 != SIZE_MAX) upload(img, A.cm_m64, H.cm_m64);
-  upload(img, A.ch_beg, H.ch_beg);
-  upload(img, A.ch_cam, H.ch_cam);
+  upload(img, A.ch_meta, H.ch_meta);
   upload(img, A.cam_ch, H.cam_ch);
   upload(img, A.mc_cam, H.mc_cam);
   upload(img, A.P64[0], P64);
@@ -688,9 +712,12 @@ povar_status povar_problem_footprint(int32_t n_cams, int32_t n_pts, int64_t n_ob
                                      uint64_t* bytes) {
   if (!bytes || n_cams <= 0 || n_pts <= 0 || n_obs <= 0) return POVAR_EINVAL;
   if (precision != POVAR_PREC_FP64 && precision != POVAR_PREC_FP32_BULK) return POVAR_EINVAL;
-  // upper bounds: a packet holds at least one landmark; chunk rounding adds
-  // at most one chunk per camera
-  const int64_t n_pk = n_pts;
+  // upper bounds on the packet slots: (a) every slot starts a landmark or
+  // continues one with more than 64 observations; (b) two consecutive slots of
+  // short landmarks hold more than 64 observations together, a run of them
+  // starts after each long landmark, and a long landmark of L observations
+  // takes ceil(L/64) slots.  Chunk rounding adds at most one chunk per camera.
+  const int64_t n_pk = std::min<int64_t>(n_pts + n_obs / kWave + 1, n_obs / kWave + 2 * n_obs / (kWave + 1) + 3);
   const int64_t n_ch = n_obs / kChunk + n_cams;
   *bytes = arena_bytes(n_cams, n_pts, n_obs, n_pk, n_ch, n_cams, precision == POVAR_PREC_FP32_BULK,
                        kTraceCapacity, nullptr);

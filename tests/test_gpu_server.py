@@ -75,7 +75,12 @@ def test_results_equal_single_solves_and_mix_is_bitwise_independent(ctx):
 def test_admission_respects_budget_and_late_arrivals_join(ctx):
     probs = requests()
     print("[case] server budget", flush=True)
-    fps = [povar.footprint(p.n_cams, p.n_pts, p.n_obs, "fp32_bulk") for p in probs]
+    fps = []
+    for p in probs:                  # exact device bytes after layout
+        gp = povar.Problem.from_synth(ctx, p, **OPTS)
+        fps.append(gp.info()["device_bytes"])
+        gp.close()
+    assert all(f <= povar.footprint(p.n_cams, p.n_pts, p.n_obs, "fp32_bulk") for f, p in zip(fps, probs))
     budget = int(max(fps) * 1.6)     # at most ~one large problem plus small ones
     sv = povar.Server(ctx, hbm_budget_bytes=budget, max_slots=8)
     first = [sv.submit(p, **OPTS) for p in probs[:3]]
