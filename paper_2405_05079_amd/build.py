@@ -12,6 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpovar.so")
 SOURCES = ["povar_kernels.hip", "povar_problem.hip", "povar_server.hip"]
+DEVICE_SOURCES = {"povar_kernels.hip"}   # the others hold host code only
 ARCH = os.environ.get("POVAR_OFFLOAD_ARCH", "gfx950")
 
 
@@ -40,6 +41,8 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(tmp, src.replace(".hip", ".o"))
         cmd = [cc, *flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+        if src not in DEVICE_SOURCES:
+            cmd.append("--offload-host-only")   # host runtime: no device code
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

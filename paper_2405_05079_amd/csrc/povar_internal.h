@@ -12,6 +12,16 @@
 
 namespace povar {
 
+// Every pointer of a problem record and a batch addresses global device
+// memory.  Device code sees them in the global address space, so loads and
+// stores through them compile to global (not flat) memory instructions; the
+// host sees plain pointers of the same size and value.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define POVAR_GMEM __attribute__((address_space(1)))
+#else
+#define POVAR_GMEM
+#endif
+
 constexpr int kWave = 64;                 // CDNA wavefront
 constexpr int kBlock = 256;               // workgroup of the streaming passes
 constexpr int kWavesPerBlock = kBlock / kWave;
@@ -61,45 +71,45 @@ struct DevProblem {
   // per entry), with pk_hdr[q] = (n, lm0).  A landmark with more than 64
   // observations fills consecutive slots; its first slot has n = its count
   // and the following ones n = 0.  Entry code = camera | (landmark - lm0) << 26.
-  const int2* pk_hdr;
-  const uint32_t* pk_code;
-  const float2* pk_m32;
-  const double2* pk_m64;
+  const int2 POVAR_GMEM* pk_hdr;
+  const uint32_t POVAR_GMEM* pk_code;
+  const float2 POVAR_GMEM* pk_m32;
+  const double2 POVAR_GMEM* pk_m64;
   // camera-major observations (sorted by camera, then internal landmark)
-  const int32_t* cm_lm;     // internal landmark id
-  const float2* cm_m32;
-  const double2* cm_m64;
-  const int4* ch_meta;      // chunk c: (camera, first obs, end obs, chunks of that camera);
+  const int32_t POVAR_GMEM* cm_lm;     // internal landmark id
+  const float2 POVAR_GMEM* cm_m32;
+  const double2 POVAR_GMEM* cm_m64;
+  const int4 POVAR_GMEM* ch_meta;      // chunk c: (camera, first obs, end obs, chunks of that camera);
                             // a chunk never spans two cameras
-  const int32_t* cam_ch;    // n_p + 1: chunks of camera i are cam_ch[i]..cam_ch[i+1]-1
-  const int32_t* mc_cam;    // n_mc cameras whose observations span more than one chunk
+  const int32_t POVAR_GMEM* cam_ch;    // n_p + 1: chunks of camera i are cam_ch[i]..cam_ch[i+1]-1
+  const int32_t POVAR_GMEM* mc_cam;    // n_mc cameras whose observations span more than one chunk
   int32_t n_mc, n_cg;       // multi-chunk cameras; cost groups (kCostGroup packets each)
 
   // cameras, double-buffered (current / trial), n_p x 12
-  double* P64[2];
-  float* P32[2];
+  double POVAR_GMEM* P64[2];
+  float POVAR_GMEM* P32[2];
   // landmarks of the current linearisation / trial point, internal order:
   // record (z0 = V^+ b_l, X) per landmark, and V^+
-  double* rec64[2];         // n_l x 8
-  float* rec32[2];
-  double* Vp64[2];          // n_l x 8
+  double POVAR_GMEM* rec64[2];         // n_l x 8
+  float POVAR_GMEM* rec32[2];
+  double POVAR_GMEM* Vp64[2];          // n_l x 8
 
   // linearisation per camera
-  double* lin_part;         // n_ch x 64 chunk partials: 40 U values, b_p, sum W z0
+  double POVAR_GMEM* lin_part;         // n_ch x 64 chunk partials: 40 U values, b_p, sum W z0
   // damped, projected, inverted camera blocks K_i = Pi (Pi U_l Pi + tau p p^T)^-1 Pi
-  double* K64;              // n_p x 144
-  double* g64;              // n_p x 12  b_p - sum W V^+ b_l  (kept for inspection)
-  double* U40;              // n_p x 40  combined U values (kept for inspection)
+  double POVAR_GMEM* K64;              // n_p x 144
+  double POVAR_GMEM* g64;              // n_p x 12  b_p - sum W V^+ b_l  (kept for inspection)
+  double POVAR_GMEM* U40;              // n_p x 40  combined U values (kept for inspection)
   // power-series work vectors
-  void* x;                  // n_p x 12, current term (series precision)
-  double* acc;              // n_p x 12, partial sum x(m) (FP64)
-  void* zx;                 // n_l x 8, (z, X) records of the current order
-  void* t_part;             // n_ch x 12 chunk partials
-  double* cost_part;        // n_pk landmark-solve cost partials (one per packet)
-  double* cost_group;       // n_cg sums of kCostGroup consecutive packet partials
-  double* tr_cost;          // trace_cap entries
-  double* tr_lambda;
-  int32_t* tr_acc;
+  void POVAR_GMEM* x;                  // n_p x 12, current term (series precision)
+  double POVAR_GMEM* acc;              // n_p x 12, partial sum x(m) (FP64)
+  void POVAR_GMEM* zx;                 // n_l x 8, (z, X) records of the current order
+  void POVAR_GMEM* t_part;             // n_ch x 12 chunk partials
+  double POVAR_GMEM* cost_part;        // n_pk landmark-solve cost partials (one per packet)
+  double POVAR_GMEM* cost_group;       // n_cg sums of kCostGroup consecutive packet partials
+  double POVAR_GMEM* tr_cost;          // trace_cap entries
+  double POVAR_GMEM* tr_lambda;
+  int32_t POVAR_GMEM* tr_acc;
 };
 
 // Unit kinds of a launch.
@@ -117,8 +127,8 @@ constexpr int kCostGroup = 2048;
 // A batch of problems: device array of records and, per unit kind, the
 // prefix table of units per problem (n_prob + 1 entries each).
 struct Batch {
-  DevProblem* probs;
-  const int32_t* off[kNumUnitKinds];
+  DevProblem POVAR_GMEM* probs;
+  const int32_t POVAR_GMEM* off[kNumUnitKinds];
   int32_t n_prob;
   int32_t total[kNumUnitKinds];
 };

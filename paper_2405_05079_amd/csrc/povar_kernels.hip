@@ -63,52 +63,100 @@ __device__ __forceinline__ bool map_block(const Batch& B, int kind, int& p, int&
   return find_unit(B, kind, (int)blockIdx.x, p, u);
 }
 
-// Butterfly sum: every lane ends with the same, order-fixed value.
+// ------------------------------------------------- cross-lane primitives
+// Built on DPP lane moves (VALU operands, no LDS round trip).  GFX9 DPP
+// controls: quad permutes, row (16-lane) shifts and mirrors, and the two row
+// broadcasts used by wave-wide scans.  Callers run them with all 64 lanes of
+// the wave active.
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]: lane i <- i^1
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]: lane i <- i^2
+constexpr int kDppMirror = 0x140;     // lane i <- 15-i within each row
+constexpr int kDppHalfMirror = 0x141; // lane i <- 7-i within each half row
+constexpr int kDppBcast15 = 0x142;    // rows 1, 3 <- lane 15 of the previous row
+constexpr int kDppBcast31 = 0x143;    // rows 2, 3 <- lane 31
+constexpr int kDppWaveShl1 = 0x130;   // lane i <- lane i+1 across the wave
+constexpr int kDppRowShr = 0x110;     // + d: lane i <- lane i-d within its row
+
+// Lane move: lanes whose source is outside the row (or whose row is not in
+// RowMask) keep `old`.
+template <int Ctrl, int RowMask = 0xF, typename T>
+__device__ __forceinline__ T dpp(T old, T v) {
+  return __builtin_amdgcn_update_dpp(old, v, Ctrl, RowMask, 0xF, false);
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Value of lane l (a uniform result); the builtin moves 32-bit words.
+template <typename T>
+__device__ __forceinline__ T read_lane(T v, int l) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+  } else {
+    const int2 w = __builtin_bit_cast(int2, v);
+    int2 r;
+    r.x = __builtin_amdgcn_readlane(w.x, l);
+    r.y = __builtin_amdgcn_readlane(w.y, l);
+    return __builtin_bit_cast(T, r);
+  }
+}
+
+// Wave sum in a fixed order, the same value in every lane: pairs, quads,
+// half rows and rows by lane moves (a + b and b + a are the same number), then
+// the four row totals as ((r0 + r1) + (r2 + r3)).
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += dpp<kDppXor1>(v, v);
+  v += dpp<kDppXor2>(v, v);
+  v += dpp<kDppHalfMirror>(v, v);
+  v += dpp<kDppMirror>(v, v);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
-// Segmented inclusive scan over lanes whose keys form contiguous runs: bit s
-// of `links` says that lane - 2^s belongs to the same run.  After seg_sum the
-// last lane of each run holds the run's total.
+// Segmented inclusive scan over lanes whose keys form contiguous runs (each
+// key one run).  A scan inside each 16-lane row by shifts of 1, 2, 4, 8, then
+// the carries between rows: rows 1 and 3 take lane 15 of the row before,
+// rows 2 and 3 take lane 31.  Bit s of `links` (s < 4) says that lane - 2^s is
+// in this lane's row and run; bit 4 that the row broadcast source of the
+// first carry is in this lane's run, bit 5 the same for lane 31.  After
+// seg_sum the last lane of each run holds the run's total.
 __device__ __forceinline__ uint32_t seg_links(int key) {
-  const int lane = lane_id();
-  uint32_t links = 0;
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const int d = 1 << s;
-    const int kp = __shfl_up(key, d, kWave);
-    if (lane >= d && kp == key) links |= 1u << s;
-  }
-  return links;
+  const int nk = ~key;   // never equal to key
+  uint32_t l = 0;
+  l |= dpp<kDppRowShr + 1>(nk, key) == key ? 1u : 0u;
+  l |= dpp<kDppRowShr + 2>(nk, key) == key ? 2u : 0u;
+  l |= dpp<kDppRowShr + 4>(nk, key) == key ? 4u : 0u;
+  l |= dpp<kDppRowShr + 8>(nk, key) == key ? 8u : 0u;
+  l |= dpp<kDppBcast15, 0xA>(nk, key) == key ? 16u : 0u;
+  l |= dpp<kDppBcast31, 0xC>(nk, key) == key ? 32u : 0u;
+  return l;
 }
 
-template <typename T>
-__device__ __forceinline__ T seg_sum(T v, uint32_t links) {
+template <int Ctrl, int RowMask, int N, typename T>
+__device__ __forceinline__ void seg_step(T (&v)[N], bool take) {
+  T t[N];
 #pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const T vp = __shfl_up(v, 1 << s, kWave);
-    if (links & (1u << s)) v += vp;
-  }
-  return v;
+  for (int k = 0; k < N; ++k) t[k] = dpp<Ctrl, RowMask>(T(0), v[k]);
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = take ? v[k] + t[k] : v[k];
 }
 
-// Lane index of the last lane of this lane's run.
-__device__ __forceinline__ int seg_tail_lane(int key, bool tail) {
-  const int lane = lane_id();
-  int t = tail ? lane : kWave;
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const int d = 1 << s;
-    const int tn = __shfl_down(t, d, kWave);
-    const int kn = __shfl_down(key, d, kWave);
-    if (lane + d < kWave && kn == key) t = min(t, tn);
-  }
-  return t;
+template <int N, typename T>
+__device__ __forceinline__ void seg_sum(T (&v)[N], uint32_t links) {
+  seg_step<kDppRowShr + 1, 0xF>(v, links & 1u);
+  seg_step<kDppRowShr + 2, 0xF>(v, links & 2u);
+  seg_step<kDppRowShr + 4, 0xF>(v, links & 4u);
+  seg_step<kDppRowShr + 8, 0xF>(v, links & 8u);
+  seg_step<kDppBcast15, 0xA>(v, links & 16u);
+  seg_step<kDppBcast31, 0xC>(v, links & 32u);
 }
+
+// true in the last lane of each run (and in lane 63)
+__device__ __forceinline__ bool run_tail(int key) { return dpp<kDppWaveShl1>(~key, key) != key; }
 
 template <typename T>
 __device__ __forceinline__ T ld_coherent(const T* p) {
@@ -118,43 +166,46 @@ __device__ __forceinline__ T ld_coherent(const T* p) {
 template <typename T> struct Prec;
 template <> struct Prec<float> {
   using T2 = float2;
-  __device__ static const float2* cm_m(const DevProblem& D) { return D.cm_m32; }
-  __device__ static const float2* pk_m(const DevProblem& D) { return D.pk_m32; }
-  __device__ static const float* P(const DevProblem& D, int b) { return b ? D.P32[1] : D.P32[0]; }
-  __device__ static const float* rec(const DevProblem& D, int b) { return b ? D.rec32[1] : D.rec32[0]; }
+  __device__ static const float2 POVAR_GMEM* cm_m(const DevProblem& D) { return D.cm_m32; }
+  __device__ static const float2 POVAR_GMEM* pk_m(const DevProblem& D) { return D.pk_m32; }
+  __device__ static const float POVAR_GMEM* P(const DevProblem& D, int b) { return b ? D.P32[1] : D.P32[0]; }
+  __device__ static const float POVAR_GMEM* rec(const DevProblem& D, int b) { return b ? D.rec32[1] : D.rec32[0]; }
 };
 template <> struct Prec<double> {
   using T2 = double2;
-  __device__ static const double2* cm_m(const DevProblem& D) { return D.cm_m64; }
-  __device__ static const double2* pk_m(const DevProblem& D) { return D.pk_m64; }
-  __device__ static const double* P(const DevProblem& D, int b) { return b ? D.P64[1] : D.P64[0]; }
-  __device__ static const double* rec(const DevProblem& D, int b) { return b ? D.rec64[1] : D.rec64[0]; }
+  __device__ static const double2 POVAR_GMEM* cm_m(const DevProblem& D) { return D.cm_m64; }
+  __device__ static const double2 POVAR_GMEM* pk_m(const DevProblem& D) { return D.pk_m64; }
+  __device__ static const double POVAR_GMEM* P(const DevProblem& D, int b) { return b ? D.P64[1] : D.P64[0]; }
+  __device__ static const double POVAR_GMEM* rec(const DevProblem& D, int b) { return b ? D.rec64[1] : D.rec64[0]; }
 };
 
-template <typename T>
-__device__ __forceinline__ void load4(const T* p, T& a, T& b, T& c, T& d) {
+// Vector loads and stores of 4 / 12 consecutive elements of device memory
+// (16 B aligned), through global-address-space pointers.
+template <typename T, typename Ptr>
+__device__ __forceinline__ void load4(Ptr p, T& a, T& b, T& c, T& d) {
   if constexpr (std::is_same<T, float>::value) {
-    const float4 v = *reinterpret_cast<const float4*>(p);
+    const float4 v = *(const float4 POVAR_GMEM*)(p);
     a = v.x; b = v.y; c = v.z; d = v.w;
   } else {
-    const double2 v0 = reinterpret_cast<const double2*>(p)[0];
-    const double2 v1 = reinterpret_cast<const double2*>(p)[1];
+    const double2 POVAR_GMEM* q = (const double2 POVAR_GMEM*)(p);
+    const double2 v0 = q[0], v1 = q[1];
     a = v0.x; b = v0.y; c = v1.x; d = v1.y;
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void store4(T* p, T a, T b, T c, T d) {
+template <typename T, typename Ptr>
+__device__ __forceinline__ void store4(Ptr p, T a, T b, T c, T d) {
   if constexpr (std::is_same<T, float>::value) {
-    *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
+    *(float4 POVAR_GMEM*)(p) = make_float4(a, b, c, d);
   } else {
-    reinterpret_cast<double2*>(p)[0] = make_double2(a, b);
-    reinterpret_cast<double2*>(p)[1] = make_double2(c, d);
+    double2 POVAR_GMEM* q = (double2 POVAR_GMEM*)(p);
+    q[0] = make_double2(a, b);
+    q[1] = make_double2(c, d);
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void load12(const T* p, T (&v)[12]) {
+template <typename T, typename Ptr>
+__device__ __forceinline__ void load12(Ptr p, T (&v)[12]) {
   load4(p, v[0], v[1], v[2], v[3]);
   load4(p + 4, v[4], v[5], v[6], v[7]);
   load4(p + 8, v[8], v[9], v[10], v[11]);
@@ -191,7 +242,7 @@ __device__ __forceinline__ void jacobi_rotate(double (&A)[3][3], double (&Q)[3][
   }
 }
 
-__device__ __noinline__ void sym3_pinv_jacobi(const double (&v)[6], double (&out)[6]) {
+__device__ __forceinline__ void sym3_pinv_jacobi(const double (&v)[6], double (&out)[6]) {
   double A[3][3] = {{v[0], v[1], v[2]}, {v[1], v[3], v[4]}, {v[2], v[4], v[5]}};
   double Q[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
   for (int sweep = 0; sweep < 32; ++sweep) {
@@ -347,28 +398,33 @@ __global__ void __launch_bounds__(kBlock) k_landmark_solve(Batch B, int mode) {
     double v[6], h[3];
     obs_normal(Pc, m.x, m.y, a, eta, v, h);
     const uint32_t links = seg_links(key);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) v[k] = seg_sum(v[k], links);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) h[k] = seg_sum(h[k], links);
-    const int kn = __shfl_down(key, 1, kWave);
-    const bool tail = act && (lane == kWave - 1 || kn != key);
+    double vh[9] = {v[0], v[1], v[2], v[3], v[4], v[5], h[0], h[1], h[2]};
+    seg_sum(vh, links);
+    const bool tail = act && run_tail(key);
     double vp[6] = {0, 0, 0, 0, 0, 0};
     double X0 = 0, X1 = 0, X2 = 0;
+    // the tail lane solves its landmark and hands X to the run through LDS
+    __shared__ double bx[kWavesPerBlock][3][kWave];
+    const int wv = threadIdx.x >> 6;
     if (tail) {
-      sym3_pinv(v, vp);
-      X0 = vp[0] * h[0] + vp[1] * h[1] + vp[2] * h[2];
-      X1 = vp[1] * h[0] + vp[3] * h[1] + vp[4] * h[2];
-      X2 = vp[2] * h[0] + vp[4] * h[1] + vp[5] * h[2];
+      const double vs[6] = {vh[0], vh[1], vh[2], vh[3], vh[4], vh[5]};
+      sym3_pinv(vs, vp);
+      X0 = vp[0] * vh[6] + vp[1] * vh[7] + vp[2] * vh[8];
+      X1 = vp[1] * vh[6] + vp[3] * vh[7] + vp[4] * vh[8];
+      X2 = vp[2] * vh[6] + vp[4] * vh[7] + vp[5] * vh[8];
+      bx[wv][0][key] = X0;
+      bx[wv][1][key] = X1;
+      bx[wv][2][key] = X2;
     }
-    const int tl = seg_tail_lane(key, tail);
-    X0 = __shfl(X0, tl, kWave);
-    X1 = __shfl(X1, tl, kWave);
-    X2 = __shfl(X2, tl, kWave);
+    wave_sync();
     double b[3] = {0, 0, 0}, f = 0.0;
-    if (act) f = obs_residual(Pc, m.x, m.y, a, eta, X0, X1, X2, b);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) b[k] = seg_sum(b[k], links);
+    if (act) {
+      X0 = bx[wv][0][key];
+      X1 = bx[wv][1][key];
+      X2 = bx[wv][2][key];
+      f = obs_residual(Pc, m.x, m.y, a, eta, X0, X1, X2, b);
+    }
+    seg_sum(b, links);
     ftot = wave_sum(f);
     if (tail) store_landmark(D, lc, lm0 + key, vp, X0, X1, X2, b);
   } else {
@@ -741,15 +797,12 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
   if (n == 0) return;   // continuation slot of a long landmark
   if (n <= kWave) {
     const bool act = lane < n;
-    const uint32_t next = __shfl_down(code, 1, kWave);   // all lanes take part
-    int key = kWave + lane;
+    const int key = act ? (int)(code >> kCamBits) : kWave + lane;
+    const bool tail = act && run_tail(key);
     T y0 = 0, y1 = 0, y2 = 0, X0 = 0, X1 = 0, X2 = 0, one;
-    bool tail = false;
     double v[8];
     if (act) {
       const int c = (int)(code & kCamMask);
-      key = (int)(code >> kCamBits);
-      tail = lane == n - 1 || (int)(next >> kCamBits) != key;
       // the tail lane fetches V^+ together with the gathers
       if (tail) {
         const double* vp = (lc ? D.Vp64[1] : D.Vp64[0]) + (size_t)(lm0 + key) * kLmSym;
@@ -770,11 +823,9 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
       y1 = Pc[1] * v0 + Pc[5] * v1 + Pc[9] * v2;
       y2 = Pc[2] * v0 + Pc[6] * v1 + Pc[10] * v2;
     }
-    const uint32_t links = seg_links(key);
-    y0 = seg_sum(y0, links);
-    y1 = seg_sum(y1, links);
-    y2 = seg_sum(y2, links);
-    if (tail) store_z<T>(v, lm0 + key, y0, y1, y2, X0, X1, X2, zx);
+    T y[3] = {y0, y1, y2};
+    seg_sum(y, seg_links(key));
+    if (tail) store_z<T>(v, lm0 + key, y[0], y[1], y[2], X0, X1, X2, zx);
   } else {
     T X0, X1, X2, one;
     load4(rec + (size_t)lm0 * kRec + 4, X0, X1, X2, one);
@@ -837,28 +888,46 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
   const typename Prec<T>::T2* __restrict__ M = Prec<T>::cm_m(D);
   const int32_t* __restrict__ lm = D.cm_lm;
   const T a = (T)(1.0 - D.eta);
+  // all index and measurement loads, then all record gathers, then the
+  // arithmetic: two memory round trips per lane instead of two per
+  // observation.  The trip count is uniform over the workgroup.
+  const int nr = (end - beg + kBlock - 1) / kBlock;
+  const int tid = (int)threadIdx.x;
+  int jr[kPerLane];
+  typename Prec<T>::T2 mr[kPerLane];
+#pragma unroll
+  for (int r = 0; r < kPerLane; ++r) {
+    if (r < nr) {
+      const int e = min(beg + r * kBlock + tid, end - 1);
+      jr[r] = lm[e];
+      mr[r] = M[e];
+    }
+  }
+  T z[kPerLane][4], x[kPerLane][4];
+#pragma unroll
+  for (int r = 0; r < kPerLane; ++r) {
+    if (r < nr) {
+      load4(zx + (size_t)jr[r] * kRec, z[r][0], z[r][1], z[r][2], z[r][3]);
+      load4(zx + (size_t)jr[r] * kRec + 4, x[r][0], x[r][1], x[r][2], x[r][3]);
+    }
+  }
   T acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = 0;
 #pragma unroll
   for (int r = 0; r < kPerLane; ++r) {
-    const int e = beg + r * kBlock + (int)threadIdx.x;
-    if (e < end) {
-      const int j = lm[e];
-      const auto m = M[e];
-      T z[4], x[4];
-      load4(zx + (size_t)j * kRec, z[0], z[1], z[2], z[3]);
-      load4(zx + (size_t)j * kRec + 4, x[0], x[1], x[2], x[3]);
-      const T q0 = Pc[0] * z[0] + Pc[1] * z[1] + Pc[2] * z[2];
-      const T q1 = Pc[4] * z[0] + Pc[5] * z[1] + Pc[6] * z[2];
-      const T q2 = Pc[8] * z[0] + Pc[9] * z[1] + Pc[10] * z[2];
+    if (r < nr && beg + r * kBlock + tid < end) {
+      const auto m = mr[r];
+      const T q0 = Pc[0] * z[r][0] + Pc[1] * z[r][1] + Pc[2] * z[r][2];
+      const T q1 = Pc[4] * z[r][0] + Pc[5] * z[r][1] + Pc[6] * z[r][2];
+      const T q2 = Pc[8] * z[r][0] + Pc[9] * z[r][1] + Pc[10] * z[r][2];
       T v[3];
       apply_N(a * m.x, a * m.y, a * (m.x * m.x + m.y * m.y), q0, q1, q2, v[0], v[1], v[2]);
 #pragma unroll
       for (int rr = 0; rr < 3; ++rr) {
-        acc[4 * rr + 0] += v[rr] * x[0];
-        acc[4 * rr + 1] += v[rr] * x[1];
-        acc[4 * rr + 2] += v[rr] * x[2];
+        acc[4 * rr + 0] += v[rr] * x[r][0];
+        acc[4 * rr + 1] += v[rr] * x[r][1];
+        acc[4 * rr + 2] += v[rr] * x[r][2];
         acc[4 * rr + 3] += v[rr];
       }
     }
