@@ -36,6 +36,16 @@ constexpr int kRec = 8;                   // (z0, z1, z2, 0, X0, X1, X2, 1)
 constexpr int kLmSym = 8;                 // V^+ : 6 values (00,01,02,11,12,22) + 2 pad
 constexpr int kCam = 12;                  // one camera / camera vector
 constexpr int kCamMat = 144;              // 12 x 12 camera operator
+// Series camera record: P (12 values) then x (12 values).  Packed (stride 24)
+// while the records of all cameras fit a 32 KB L1 in FP32; otherwise padded to
+// stride 32, one 128-byte line per camera in FP32, so that a gather of a
+// camera's P and x touches a single line.
+constexpr int kSerX = 12;                 // offset of x in the series record
+constexpr int kSerPacked = 24;
+constexpr int kSerLine = 32;
+__host__ __device__ constexpr int ser_stride(int n_p) {
+  return (long long)n_p * kSerPacked * 4 <= 32768 ? kSerPacked : kSerLine;
+}
 
 // Per-problem control block (first member of the problem record).  Only
 // kernels write it during a solve; the host reads it after synchronising and
@@ -63,7 +73,8 @@ struct DevProblem {
   int32_t n_p, n_l, n_pk, n_ch;   // n_pk: packet slots
   int32_t manifold;     // 0 sphere, 1 euclidean
   int32_t trace_cap;
-  int32_t pad0, pad1;
+  int32_t s_stride;     // series record stride, ser_stride(n_p)
+  int32_t pad1;
   double eta, ftol, lambda_min, lambda_max;
 
   // landmark-major packets on 64-entry slots: slot q holds whole landmarks
@@ -85,9 +96,12 @@ struct DevProblem {
   const int32_t POVAR_GMEM* mc_cam;    // n_mc cameras whose observations span more than one chunk
   int32_t n_mc, n_cg;       // multi-chunk cameras; cost groups (kCostGroup packets each)
 
-  // cameras, double-buffered (current / trial), n_p x 12
+  // cameras, double-buffered (current / trial): FP64 n_p x 12, and the
+  // series record of each camera in the series precision, n_p x s_stride,
+  // holding P and the current series term x
   double POVAR_GMEM* P64[2];
-  float POVAR_GMEM* P32[2];
+  float POVAR_GMEM* S32[2];    // FP32-bulk problems only
+  double POVAR_GMEM* S64[2];   // FP64 problems only
   // landmarks of the current linearisation / trial point, internal order:
   // record (z0 = V^+ b_l, X) per landmark, and V^+
   double POVAR_GMEM* rec64[2];         // n_l x 8
@@ -101,7 +115,6 @@ struct DevProblem {
   double POVAR_GMEM* g64;              // n_p x 12  b_p - sum W V^+ b_l  (kept for inspection)
   double POVAR_GMEM* U40;              // n_p x 40  combined U values (kept for inspection)
   // power-series work vectors
-  void POVAR_GMEM* x;                  // n_p x 12, current term (series precision)
   double POVAR_GMEM* acc;              // n_p x 12, partial sum x(m) (FP64)
   void POVAR_GMEM* zx;                 // n_l x 8, (z, X) records of the current order
   void POVAR_GMEM* t_part;             // n_ch x 12 chunk partials

@@ -168,14 +168,15 @@ template <> struct Prec<float> {
   using T2 = float2;
   __device__ static const float2 POVAR_GMEM* cm_m(const DevProblem& D) { return D.cm_m32; }
   __device__ static const float2 POVAR_GMEM* pk_m(const DevProblem& D) { return D.pk_m32; }
-  __device__ static const float POVAR_GMEM* P(const DevProblem& D, int b) { return b ? D.P32[1] : D.P32[0]; }
+  // series record of buffer b: P at 0, x at kSerX (stride s_stride)
+  __device__ static float POVAR_GMEM* S(const DevProblem& D, int b) { return b ? D.S32[1] : D.S32[0]; }
   __device__ static const float POVAR_GMEM* rec(const DevProblem& D, int b) { return b ? D.rec32[1] : D.rec32[0]; }
 };
 template <> struct Prec<double> {
   using T2 = double2;
   __device__ static const double2 POVAR_GMEM* cm_m(const DevProblem& D) { return D.cm_m64; }
   __device__ static const double2 POVAR_GMEM* pk_m(const DevProblem& D) { return D.pk_m64; }
-  __device__ static const double POVAR_GMEM* P(const DevProblem& D, int b) { return b ? D.P64[1] : D.P64[0]; }
+  __device__ static double POVAR_GMEM* S(const DevProblem& D, int b) { return b ? D.S64[1] : D.S64[0]; }
   __device__ static const double POVAR_GMEM* rec(const DevProblem& D, int b) { return b ? D.rec64[1] : D.rec64[0]; }
 };
 
@@ -536,7 +537,7 @@ __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
   const int4 meta = D.ch_meta[ch];
   const int cam = meta.x, beg = meta.y, end = meta.z;
   T Pc[12];
-  load12(Prec<T>::P(D, pc) + (size_t)cam * kCam, Pc);
+  load12(Prec<T>::S(D, pc) + (size_t)cam * D.s_stride, Pc);
   const T* __restrict__ rec = Prec<T>::rec(D, lc);
   const typename Prec<T>::T2* __restrict__ M = Prec<T>::cm_m(D);
   const int32_t* __restrict__ lm = D.cm_lm;
@@ -747,7 +748,7 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
       if (c != r) x0[c] -= v * g[r];
     }
   }
-  T* x = static_cast<T*>(D.x) + (size_t)i * kCam;
+  T POVAR_GMEM* x = Prec<T>::S(D, D.ctl.pcur) + (size_t)i * D.s_stride + kSerX;
   double* acc = D.acc + (size_t)i * kCam;
 #pragma unroll
   for (int r = 0; r < 12; ++r) {
@@ -784,8 +785,8 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
   const int lane = lane_id();
   const int off = q * kWave;
   const T* __restrict__ rec = Prec<T>::rec(D, lc);
-  const T* __restrict__ xs = static_cast<const T*>(D.x);
-  const T* __restrict__ Pm = Prec<T>::P(D, pc);
+  // P and x of a camera share one series record (one line in FP32)
+  const T* __restrict__ Sr = Prec<T>::S(D, pc);
   const typename Prec<T>::T2* __restrict__ em = Prec<T>::pk_m(D);
   const T a = (T)(1.0 - D.eta);
   T* zx = static_cast<T*>(D.zx);
@@ -812,8 +813,8 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
       const auto m = mraw;
       load4(rec + (size_t)(lm0 + key) * kRec + 4, X0, X1, X2, one);
       T xc[12], Pc[12];
-      load12(xs + (size_t)c * kCam, xc);
-      load12(Pm + (size_t)c * kCam, Pc);
+      load12(Sr + (size_t)c * D.s_stride + kSerX, xc);
+      load12(Sr + (size_t)c * D.s_stride, Pc);
       const T q0 = xc[0] * X0 + xc[1] * X1 + xc[2] * X2 + xc[3];
       const T q1 = xc[4] * X0 + xc[5] * X1 + xc[6] * X2 + xc[7];
       const T q2 = xc[8] * X0 + xc[9] * X1 + xc[10] * X2 + xc[11];
@@ -838,8 +839,8 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
       const int c = (int)(D.pk_code[e] & kCamMask);
       const auto m = em[e];
       T xc[12], Pc[12];
-      load12(xs + (size_t)c * kCam, xc);
-      load12(Pm + (size_t)c * kCam, Pc);
+      load12(Sr + (size_t)c * D.s_stride + kSerX, xc);
+      load12(Sr + (size_t)c * D.s_stride, Pc);
       const T q0 = xc[0] * X0 + xc[1] * X1 + xc[2] * X2 + xc[3];
       const T q1 = xc[4] * X0 + xc[5] * X1 + xc[6] * X2 + xc[7];
       const T q2 = xc[8] * X0 + xc[9] * X1 + xc[10] * X2 + xc[11];
@@ -866,7 +867,7 @@ __device__ __forceinline__ void camera_solve(DevProblem& D, int cam, const T* tv
   double xr = 0.0;
 #pragma unroll
   for (int c = 0; c < 12; ++c) xr += kr[c] * (double)tv[c];
-  static_cast<T*>(D.x)[(size_t)cam * kCam + k] = (T)xr;
+  Prec<T>::S(D, D.ctl.pcur)[(size_t)cam * D.s_stride + kSerX + k] = (T)xr;
   D.acc[(size_t)cam * kCam + k] += xr;
 }
 
@@ -880,7 +881,7 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
   const int4 meta = D.ch_meta[ch];
   const int cam = meta.x, beg = meta.y, end = meta.z, nch = meta.w;
   T Pc[12];
-  load12(Prec<T>::P(D, pc) + (size_t)cam * kCam, Pc);
+  load12(Prec<T>::S(D, pc) + (size_t)cam * D.s_stride, Pc);
   // the camera-block row of this thread, fetched before the reduction needs it
   double kr[12];
   if (nch == 1 && threadIdx.x < 12) load12(D.K64 + (size_t)cam * kCamMat + threadIdx.x * 12, kr);
@@ -1009,11 +1010,11 @@ __global__ void __launch_bounds__(kWave) k_retract(Batch B) {
     for (int r = 0; r < 12; ++r) q[r] *= inv;
   }
   double* o64 = (pc ? D.P64[0] : D.P64[1]) + (size_t)i * kCam;
-  float* o32 = (pc ? D.P32[0] : D.P32[1]) + (size_t)i * kCam;
+  T POVAR_GMEM* os = Prec<T>::S(D, pc ^ 1) + (size_t)i * D.s_stride;
 #pragma unroll
   for (int r = 0; r < 12; r += 4) {
     store4(o64 + r, q[r], q[r + 1], q[r + 2], q[r + 3]);
-    store4(o32 + r, (float)q[r], (float)q[r + 1], (float)q[r + 2], (float)q[r + 3]);
+    store4(os + r, (T)q[r], (T)q[r + 1], (T)q[r + 2], (T)q[r + 3]);
   }
 }
 

@@ -69,7 +69,8 @@ size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_
   r.mc_cam = a.take(n_mc * 4);
   for (int b = 0; b < 2; ++b) {
     r.P64[b] = a.take(n_p * kCam * 8);
-    r.P32[b] = a.take(n_p * kCam * 4);
+    r.S32[b] = fp32 ? a.take(n_p * ser_stride((int)n_p) * 4) : SIZE_MAX;
+    r.S64[b] = fp32 ? SIZE_MAX : a.take(n_p * ser_stride((int)n_p) * 8);
     r.rec64[b] = a.take(n_l * kRec * 8);
     r.rec32[b] = a.take(n_l * kRec * 4);
     r.Vp64[b] = a.take(n_l * kLmSym * 8);
@@ -78,7 +79,6 @@ size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_
   r.K64 = a.take(n_p * kCamMat * 8);
   r.g64 = a.take(n_p * kCam * 8);
   r.U40 = a.take(n_p * 40 * 8);
-  r.x = a.take(n_p * kCam * ts);
   r.acc = a.take(n_p * kCam * 8);
   r.zx = a.take(n_l * kRec * ts);
   r.t_part = a.take(n_ch * kCam * ts);
@@ -350,7 +350,9 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
 
   // cameras (normalised on the sphere)
   std::vector<double> P64((size_t)H.n_p * kCam);
-  std::vector<float> P32((size_t)H.n_p * kCam);
+  const int ss = ser_stride(H.n_p);
+  std::vector<float> S32(pb->fp32 ? (size_t)H.n_p * ss : 0, 0.0f);
+  std::vector<double> S64(pb->fp32 ? 0 : (size_t)H.n_p * ss, 0.0);
   for (int32_t i = 0; i < H.n_p; ++i) {
     double nrm = 0.0;
     for (int r = 0; r < kCam; ++r) {
@@ -367,8 +369,10 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
     }
     const double s = o->manifold == POVAR_MANIFOLD_SPHERE ? 1.0 / std::sqrt(nrm) : 1.0;
     for (int r = 0; r < kCam; ++r) {
-      P64[(size_t)i * kCam + r] = cams0[(size_t)i * kCam + r] * s;
-      P32[(size_t)i * kCam + r] = (float)P64[(size_t)i * kCam + r];
+      const double v = cams0[(size_t)i * kCam + r] * s;
+      P64[(size_t)i * kCam + r] = v;
+      if (pb->fp32) S32[(size_t)i * ss + r] = (float)v;
+      else S64[(size_t)i * ss + r] = v;
     }
   }
 
@@ -381,6 +385,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.n_cg = H.n_cg;
   R.n_ch = H.n_ch;
   R.manifold = o->manifold;
+  R.s_stride = ser_stride(H.n_p);
   R.trace_cap = pb->trace_cap;
   R.eta = o->eta;
   R.ftol = o->ftol;
@@ -398,7 +403,8 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.mc_cam = (const int32_t*)dp(A.mc_cam);
   for (int b = 0; b < 2; ++b) {
     R.P64[b] = (double*)dp(A.P64[b]);
-    R.P32[b] = (float*)dp(A.P32[b]);
+    R.S32[b] = (float*)dp(A.S32[b]);
+    R.S64[b] = (double*)dp(A.S64[b]);
     R.rec64[b] = (double*)dp(A.rec64[b]);
     R.rec32[b] = (float*)dp(A.rec32[b]);
     R.Vp64[b] = (double*)dp(A.Vp64[b]);
@@ -407,7 +413,6 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.K64 = (double*)dp(A.K64);
   R.g64 = (double*)dp(A.g64);
   R.U40 = (double*)dp(A.U40);
-  R.x = dp(A.x);
   R.acc = (double*)dp(A.acc);
   R.zx = dp(A.zx);
   R.t_part = dp(A.t_part);
@@ -444,7 +449,8 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   upload(img, A.cam_ch, H.cam_ch);
   upload(img, A.mc_cam, H.mc_cam);
   upload(img, A.P64[0], P64);
-  upload(img, A.P32[0], P32);
+  if (pb->fp32) upload(img, A.S32[0], S32);
+  else upload(img, A.S64[0], S64);
   std::memcpy(img.data() + A.rec, &R, sizeof(R));
   std::memcpy(img.data() + A.tables, tables, sizeof(tables));
   HIP_TRY(ctx, hipMemcpyAsync(pb->arena, img.data(), pb->bytes, hipMemcpyHostToDevice, stream));
@@ -884,7 +890,9 @@ povar_status povar_set_state(povar_problem pb, const double* cams, double lambda
   HIP_TRY(ctx, read_ctl(pb, &c));
   const int32_t n_p = pb->L.n_p;
   std::vector<double> P64((size_t)n_p * kCam);
-  std::vector<float> P32((size_t)n_p * kCam);
+  const int ss = ser_stride(n_p);
+  std::vector<float> S32(pb->fp32 ? (size_t)n_p * ss : 0, 0.0f);
+  std::vector<double> S64(pb->fp32 ? 0 : (size_t)n_p * ss, 0.0);
   for (int32_t i = 0; i < n_p; ++i) {
     double nrm = 0.0;
     for (int r = 0; r < kCam; ++r) nrm += cams[(size_t)i * kCam + r] * cams[(size_t)i * kCam + r];
@@ -897,12 +905,18 @@ povar_status povar_set_state(povar_problem pb, const double* cams, double lambda
     const bool renorm = pb->opt.manifold == POVAR_MANIFOLD_SPHERE && std::fabs(nrm - 1.0) > 1e-14;
     const double s = renorm ? 1.0 / std::sqrt(nrm) : 1.0;
     for (int r = 0; r < kCam; ++r) {
-      P64[(size_t)i * kCam + r] = cams[(size_t)i * kCam + r] * s;
-      P32[(size_t)i * kCam + r] = (float)P64[(size_t)i * kCam + r];
+      const double v = cams[(size_t)i * kCam + r] * s;
+      P64[(size_t)i * kCam + r] = v;
+      if (pb->fp32) S32[(size_t)i * ss + r] = (float)v;
+      else S64[(size_t)i * ss + r] = v;
     }
   }
   HIP_TRY(ctx, hipMemcpyAsync(pb->rec.P64[c.pcur], P64.data(), P64.size() * 8, hipMemcpyHostToDevice, pb->stream));
-  HIP_TRY(ctx, hipMemcpyAsync(pb->rec.P32[c.pcur], P32.data(), P32.size() * 4, hipMemcpyHostToDevice, pb->stream));
+  if (pb->fp32)
+    HIP_TRY(ctx, hipMemcpyAsync(pb->rec.S32[c.pcur], S32.data(), S32.size() * 4, hipMemcpyHostToDevice, pb->stream));
+  else
+    HIP_TRY(ctx, hipMemcpyAsync(pb->rec.S64[c.pcur], S64.data(), S64.size() * 8, hipMemcpyHostToDevice, pb->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(pb->stream));   // host buffers are freed on return
   c.lambda = lambda;
   c.iter = iter;
   c.need_lin = 1;
