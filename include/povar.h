@@ -201,6 +201,14 @@ povar_status povar_kernel_times(povar_problem pb, double* ms_landmark_pass, int6
    observations of one camera), device bytes. */
 povar_status povar_problem_info(povar_problem pb, int64_t* n_obs, int64_t* n_packets,
                                 int32_t* n_chunks, uint64_t* device_bytes);
+/* Series camera pass of the problem.  *blocked = 0: one workgroup per camera
+   chunk, landmark records gathered from anywhere (the records fit in L2).
+   *blocked = 1 (records of the series precision above 4 MiB): landmarks in
+   blocks of *lm_block internal ids (2 MiB of records), *n_slots 64-lane slots of 4 observations
+   per lane, each block's slots run on one XCD, and *n_runs per-(camera, block
+   part) partial sums added per camera afterwards.  NULL outputs are skipped. */
+povar_status povar_problem_layout(povar_problem pb, int32_t* blocked, int32_t* lm_block, int64_t* n_slots,
+                                  int64_t* n_runs);
 
 /* ---- serving: continuous batching of many problems on one GPU ----------- */
 /* A server owns a worker thread and the device state of up to max_slots

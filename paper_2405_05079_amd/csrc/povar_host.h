@@ -37,19 +37,35 @@ struct HostLayout {
   std::vector<int32_t> ch_meta, cam_ch;   // ch_meta: 4 per chunk
   std::vector<int32_t> mc_cam;         // cameras spanning more than one chunk
   int32_t n_mc = 0, n_cg = 0;
+  // blocked series camera pass (DevProblem::blocked)
+  int32_t blocked = 0, lm_block = 0, n_cs = 0, n_runs = 0;
+  std::vector<int32_t> cs_hdr, cs_lane, cs_lm;   // cs_lane: 2 per lane
+  std::vector<float> cs_m32;
+  std::vector<double> cs_m64;
+  std::vector<int32_t> run_off;        // n_p + 1, runs of each camera
+  std::vector<int32_t> smc;            // cameras whose series partials are combined
 };
+
+// Array sizes that fix a problem's device arena.
+struct LayoutSizes {
+  int64_t n_p, n_l, n_obs, n_pk, n_ch, n_mc, n_cs, n_runs;
+  bool blocked;
+};
+inline LayoutSizes sizes_of(const HostLayout& L) {
+  return LayoutSizes{L.n_p, L.n_l, L.n_obs, L.n_pk, L.n_ch, L.n_mc, L.n_cs, L.n_runs, L.blocked != 0};
+}
 
 // Byte offsets of every buffer inside a problem's device arena
 // (SIZE_MAX = not allocated for this precision).
 struct ArenaOffsets {
   size_t pk_hdr, pk_code, pk_m32, pk_m64, cm_lm, cm_m32, cm_m64, ch_meta, cam_ch, mc_cam;
+  size_t cs_hdr, cs_lane, cs_lm, cs_m32, cs_m64, run_off, smc, t_run;
   size_t P64[2], S32[2], S64[2], rec64[2], rec32[2], Vp64[2];
   size_t lin_part, K64, g64, U40, acc, zx, t_part, cost_part, cost_group;
   size_t tr_cost, tr_lambda, tr_acc, rec, tables;
 };
 
-size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_t n_ch, int64_t n_mc, bool fp32,
-                   int64_t trace_cap, ArenaOffsets* o);
+size_t arena_bytes(const LayoutSizes& z, bool fp32, int64_t trace_cap, ArenaOffsets* o);
 povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs, const int32_t* cam,
                           const int32_t* pt, const double* meas, bool fp32, HostLayout& L);
 povar_status check_options(povar_ctx ctx, const povar_options* o);
@@ -95,6 +111,7 @@ namespace povar {
 povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, const povar_options* o,
                           hipStream_t stream, povar_problem_s* pb, DevProblem* rec_dev, int32_t iter_limit);
 size_t layout_footprint(const HostLayout& L, bool fp32);
+void unit_counts(const HostLayout& L, int32_t* units);   // kNumUnitKinds units per kind
 povar_status copy_points(povar_problem_s* pb, int lcur, double* out);
 hipError_t read_ctl(povar_problem_s* pb, Ctl* out);
 hipError_t write_ctl(povar_problem_s* pb, const Ctl* in);

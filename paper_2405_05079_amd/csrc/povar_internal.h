@@ -118,6 +118,26 @@ struct DevProblem {
   double POVAR_GMEM* acc;              // n_p x 12, partial sum x(m) (FP64)
   void POVAR_GMEM* zx;                 // n_l x 8, (z, X) records of the current order
   void POVAR_GMEM* t_part;             // n_ch x 12 chunk partials
+  // Series camera pass of blocked problems (landmark records of the series
+  // precision larger than one XCD's L2): landmarks fall in blocks of lm_block
+  // consecutive internal ids, and each block's observations, by camera then
+  // landmark, fill 64-lane slots with kCsPerLane observations per lane.  A run
+  // is the part of one camera's observations of one block that lies in one
+  // slot; each run gives one partial sum.  Workgroup g (4 slots) runs on XCD
+  // g % 8, and the slots are ordered so that all slots of a block go to the
+  // XCD that block is assigned to, in block order.
+  int32_t blocked, n_cs, n_runs, n_smc;
+  const int32_t POVAR_GMEM* cs_hdr;    // n_cs: lanes used (0: empty slot)
+  const int2 POVAR_GMEM* cs_lane;      // n_cs x 64: (camera | run key << 26, run id)
+  const int32_t POVAR_GMEM* cs_lm;     // entry (q, r, lane) at (q * kCsPerLane + r) * 64 + lane:
+                                       // internal landmark, -1 for padding
+  const float2 POVAR_GMEM* cs_m32;
+  const double2 POVAR_GMEM* cs_m64;
+  // partial camera sums of the series camera pass (per chunk, or per run of a
+  // blocked problem) and the cameras whose partials are combined
+  const int32_t POVAR_GMEM* ser_off;   // n_p + 1: partials of camera i are ser_off[i] .. ser_off[i+1]-1
+  const int32_t POVAR_GMEM* ser_mc;    // n_smc cameras
+  void POVAR_GMEM* ser_part;           // 12 values per partial, series precision
   double POVAR_GMEM* cost_part;        // n_pk landmark-solve cost partials (one per packet)
   double POVAR_GMEM* cost_group;       // n_cg sums of kCostGroup consecutive packet partials
   double POVAR_GMEM* tr_cost;          // trace_cap entries
@@ -128,14 +148,27 @@ struct DevProblem {
 // Unit kinds of a launch.
 enum UnitKind {
   kUnitPacket = 0,     // one wave per landmark packet
-  kUnitChunk = 1,      // one workgroup per camera chunk
+  kUnitChunk = 1,      // one workgroup per camera chunk (linearisation)
   kUnitCamWave = 2,    // one wave per 64 cameras
   kUnitOne = 3,        // one workgroup per problem
-  kUnitMultiCam = 4,   // one wave per camera spanning several chunks
+  kUnitMultiCam = 4,   // one wave per camera whose series partials are combined
   kUnitCostGroup = 5,  // one workgroup per kCostGroup packets
-  kNumUnitKinds = 6
+  kUnitSerChunk = 6,   // one workgroup per camera chunk, series pass (problems not blocked)
+  kUnitCSlot = 7,      // one wave per camera slot, series pass (blocked problems)
+  kNumUnitKinds = 8
 };
 constexpr int kCostGroup = 2048;
+
+// Blocked series camera pass.
+constexpr int kCsPerLane = 4;                    // observations per lane of a camera slot
+constexpr int kCsObs = kWave * kCsPerLane;       // observations per slot
+constexpr long long kLmBlockBytes = 2ll << 20;   // landmark records per block (half of one XCD's L2)
+constexpr long long kL2Bytes = 4ll << 20;        // L2 of one XCD
+constexpr int kXcds = 8;
+// landmark records of the series precision do not fit one XCD's L2
+__host__ __device__ constexpr bool blocked_layout(long long n_l, bool fp32) {
+  return n_l * kRec * (fp32 ? 4 : 8) > kL2Bytes;
+}
 
 // A batch of problems: device array of records and, per unit kind, the
 // prefix table of units per problem (n_prob + 1 entries each).
@@ -155,7 +188,7 @@ hipError_t launch_camera_prep(const Batch& b, bool fp32, hipStream_t s);
 hipError_t launch_series_landmark(const Batch& b, bool fp32, int t, hipStream_t s, hipEvent_t ev0 = nullptr,
                                   hipEvent_t ev1 = nullptr);
 hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s, hipEvent_t ev0 = nullptr,
-                                hipEvent_t ev1 = nullptr);   // + multi-chunk combine (not timed)
+                                hipEvent_t ev1 = nullptr);   // chunk or slot pass, + combine (not timed)
 hipError_t launch_cost_groups(const Batch& b, int trial, hipStream_t s);
 hipError_t launch_retract(const Batch& b, bool fp32, hipStream_t s);
 hipError_t launch_decide(const Batch& b, hipStream_t s);

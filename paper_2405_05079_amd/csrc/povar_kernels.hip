@@ -168,6 +168,7 @@ template <> struct Prec<float> {
   using T2 = float2;
   __device__ static const float2 POVAR_GMEM* cm_m(const DevProblem& D) { return D.cm_m32; }
   __device__ static const float2 POVAR_GMEM* pk_m(const DevProblem& D) { return D.pk_m32; }
+  __device__ static const float2 POVAR_GMEM* cs_m(const DevProblem& D) { return D.cs_m32; }
   // series record of buffer b: P at 0, x at kSerX (stride s_stride)
   __device__ static float POVAR_GMEM* S(const DevProblem& D, int b) { return b ? D.S32[1] : D.S32[0]; }
   __device__ static const float POVAR_GMEM* rec(const DevProblem& D, int b) { return b ? D.rec32[1] : D.rec32[0]; }
@@ -176,6 +177,7 @@ template <> struct Prec<double> {
   using T2 = double2;
   __device__ static const double2 POVAR_GMEM* cm_m(const DevProblem& D) { return D.cm_m64; }
   __device__ static const double2 POVAR_GMEM* pk_m(const DevProblem& D) { return D.pk_m64; }
+  __device__ static const double2 POVAR_GMEM* cs_m(const DevProblem& D) { return D.cs_m64; }
   __device__ static double POVAR_GMEM* S(const DevProblem& D, int b) { return b ? D.S64[1] : D.S64[0]; }
   __device__ static const double POVAR_GMEM* rec(const DevProblem& D, int b) { return b ? D.rec64[1] : D.rec64[0]; }
 };
@@ -874,7 +876,7 @@ __device__ __forceinline__ void camera_solve(DevProblem& D, int cam, const T* tv
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
   int p, ch;
-  if (!map_block(B, kUnitChunk, p, ch)) return;
+  if (!map_block(B, kUnitSerChunk, p, ch)) return;
   DevProblem& D = B.probs[p];
   if (D.ctl.done || t > D.ctl.order) return;
   const int pc = D.ctl.pcur;
@@ -953,23 +955,27 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
   camera_solve<T>(D, cam, tv, kr);
 }
 
-// One wave per camera whose observations span several chunks: adds the
-// chunk partials in chunk order (lane-strided, then a fixed tree) and
-// applies the camera block.
+// One wave per camera whose series partials need adding (chunks of a camera
+// spanning several chunks, or the runs of a blocked problem): adds the
+// camera's partials in order (lane-strided, then a fixed tree) and applies
+// the camera block.
 template <typename T>
 __global__ void __launch_bounds__(kWave) k_series_camera_combine(Batch B, int t) {
   int p, u;
   if (!map_wave<kWave>(B, kUnitMultiCam, p, u)) return;
   DevProblem& D = B.probs[p];
   if (D.ctl.done || t > D.ctl.order) return;
-  const int cam = D.mc_cam[u];
-  const int c0 = D.cam_ch[cam], nch = D.cam_ch[cam + 1] - c0;
+  const int cam = D.ser_mc[u];
+  const int c0 = D.ser_off[cam], np = D.ser_off[cam + 1] - c0;
+  double kr[12];
+  if (threadIdx.x < 12) load12(D.K64 + (size_t)cam * kCamMat + threadIdx.x * 12, kr);
+  const T* __restrict__ part = static_cast<const T*>(D.ser_part);
   T s[12];
 #pragma unroll
   for (int kk = 0; kk < 12; ++kk) s[kk] = 0;
-  for (int q = lane_id(); q < nch; q += kWave) {
+  for (int q = lane_id(); q < np; q += kWave) {
     T v[12];
-    load12(static_cast<const T*>(D.t_part) + (size_t)(c0 + q) * kCam, v);
+    load12(part + (size_t)(c0 + q) * kCam, v);
 #pragma unroll
     for (int kk = 0; kk < 12; ++kk) s[kk] += v[kk];
   }
@@ -980,9 +986,79 @@ __global__ void __launch_bounds__(kWave) k_series_camera_combine(Batch B, int t)
     if (lane_id() == 0) tv[kk] = r;
   }
   __syncthreads();
-  double kr[12];
-  if (threadIdx.x < 12) load12(D.K64 + (size_t)cam * kCamMat + threadIdx.x * 12, kr);
   camera_solve<T>(D, cam, tv, kr);
+}
+
+// --------------------------------------------------- k_series_camera_slots
+// Blocked problems: one wave per camera slot, kCsPerLane observations per
+// lane, all of one run.  t_run = sum_k vec((N_k Pbar_i z_j) x~_j^T) over the
+// run's observations; the (z, X) records gathered here belong to the slot's
+// landmark block, which the slot order keeps in one XCD's L2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_series_camera_slots(Batch B, int t) {
+  int p, q;
+  if (!map_wave(B, kUnitCSlot, p, q)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done || t > D.ctl.order) return;
+  const int lane = lane_id();
+  const int pc = D.ctl.pcur;
+  // entry loads do not wait for the slot header
+  const int2 li = D.cs_lane[(size_t)q * kWave + lane];
+  int jr[kCsPerLane];
+  typename Prec<T>::T2 mr[kCsPerLane];
+#pragma unroll
+  for (int r = 0; r < kCsPerLane; ++r) {
+    const size_t e = ((size_t)q * kCsPerLane + r) * kWave + lane;
+    jr[r] = D.cs_lm[e];
+    mr[r] = Prec<T>::cs_m(D)[e];
+  }
+  const int nl = D.cs_hdr[q];
+  if (nl == 0) return;   // empty slot (keeps the XCD order)
+  const bool act = lane < nl;
+  const int cam = li.x & (int)kCamMask;
+  const int key = act ? (int)((uint32_t)li.x >> kCamBits) : kWave + lane;
+  T Pc[12];
+  if (act) load12(Prec<T>::S(D, pc) + (size_t)cam * D.s_stride, Pc);
+  else
+#pragma unroll
+    for (int k = 0; k < 12; ++k) Pc[k] = 0;
+  const T* __restrict__ zx = static_cast<const T*>(D.zx);
+  T z[kCsPerLane][4], x[kCsPerLane][4];
+#pragma unroll
+  for (int r = 0; r < kCsPerLane; ++r) {
+    if (jr[r] >= 0) {
+      load4(zx + (size_t)jr[r] * kRec, z[r][0], z[r][1], z[r][2], z[r][3]);
+      load4(zx + (size_t)jr[r] * kRec + 4, x[r][0], x[r][1], x[r][2], x[r][3]);
+    }
+  }
+  const T a = (T)(1.0 - D.eta);
+  T acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0;
+#pragma unroll
+  for (int r = 0; r < kCsPerLane; ++r) {
+    if (jr[r] >= 0) {
+      const auto m = mr[r];
+      const T q0 = Pc[0] * z[r][0] + Pc[1] * z[r][1] + Pc[2] * z[r][2];
+      const T q1 = Pc[4] * z[r][0] + Pc[5] * z[r][1] + Pc[6] * z[r][2];
+      const T q2 = Pc[8] * z[r][0] + Pc[9] * z[r][1] + Pc[10] * z[r][2];
+      T v[3];
+      apply_N(a * m.x, a * m.y, a * (m.x * m.x + m.y * m.y), q0, q1, q2, v[0], v[1], v[2]);
+#pragma unroll
+      for (int rr = 0; rr < 3; ++rr) {
+        acc[4 * rr + 0] += v[rr] * x[r][0];
+        acc[4 * rr + 1] += v[rr] * x[r][1];
+        acc[4 * rr + 2] += v[rr] * x[r][2];
+        acc[4 * rr + 3] += v[rr];
+      }
+    }
+  }
+  seg_sum(acc, seg_links(key));
+  if (act && run_tail(key)) {
+    T* out = static_cast<T*>(D.ser_part) + (size_t)li.y * kCam;
+#pragma unroll
+    for (int k = 0; k < 12; k += 4) store4(out + k, acc[k], acc[k + 1], acc[k + 2], acc[k + 3]);
+  }
 }
 
 // --------------------------------------------------------------- k_retract
@@ -1104,13 +1180,25 @@ hipError_t launch_series_landmark(const Batch& b, bool fp32, int t, hipStream_t 
   return hipGetLastError();
 }
 
+// The timing events bracket the chunk pass, or the slot pass when no
+// problem of the batch has chunk units.
 hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  if (b.total[kUnitChunk] == 0) return hipSuccess;
-  const dim3 g = blocks_for(b.total[kUnitChunk], 1);
-  if (fp32) hipExtLaunchKernelGGL(k_series_camera<float>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
-  else hipExtLaunchKernelGGL(k_series_camera<double>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || b.total[kUnitMultiCam] == 0) return e;
+  hipError_t e = hipSuccess;
+  const bool chunks = b.total[kUnitSerChunk] > 0;
+  if (chunks) {
+    const dim3 g = blocks_for(b.total[kUnitSerChunk], 1);
+    if (fp32) hipExtLaunchKernelGGL(k_series_camera<float>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
+    else hipExtLaunchKernelGGL(k_series_camera<double>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (b.total[kUnitCSlot] > 0) {
+    const dim3 g = blocks_for(b.total[kUnitCSlot], kWavesPerBlock);
+    hipEvent_t e0 = chunks ? nullptr : ev0, e1 = chunks ? nullptr : ev1;
+    if (fp32) hipExtLaunchKernelGGL(k_series_camera_slots<float>, g, dim3(kBlock), 0, s, e0, e1, 0, b, t);
+    else hipExtLaunchKernelGGL(k_series_camera_slots<double>, g, dim3(kBlock), 0, s, e0, e1, 0, b, t);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (b.total[kUnitMultiCam] == 0) return e;
   const dim3 gm = blocks_for(b.total[kUnitMultiCam], 1);
   if (fp32) hipLaunchKernelGGL(k_series_camera_combine<float>, gm, dim3(kWave), 0, s, b, t);
   else hipLaunchKernelGGL(k_series_camera_combine<double>, gm, dim3(kWave), 0, s, b, t);

@@ -50,8 +50,8 @@ struct ArenaPlan {
   }
 };
 
-size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_t n_ch, int64_t n_mc, bool fp32,
-                   int64_t trace_cap, ArenaOffsets* o) {
+size_t arena_bytes(const LayoutSizes& z, bool fp32, int64_t trace_cap, ArenaOffsets* o) {
+  const int64_t n_p = z.n_p, n_l = z.n_l, n_obs = z.n_obs, n_pk = z.n_pk, n_ch = z.n_ch, n_mc = z.n_mc;
   ArenaPlan a;
   ArenaOffsets tmp;
   ArenaOffsets& r = o ? *o : tmp;
@@ -67,6 +67,15 @@ size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_
   r.ch_meta = a.take(n_ch * 16);
   r.cam_ch = a.take((n_p + 1) * 4);
   r.mc_cam = a.take(n_mc * 4);
+  const int64_t n_cs = z.blocked ? z.n_cs : 0, n_runs = z.blocked ? z.n_runs : 0;
+  r.cs_hdr = a.take(n_cs * 4);
+  r.cs_lane = a.take(n_cs * kWave * 8);
+  r.cs_lm = a.take(n_cs * kCsObs * 4);
+  r.cs_m32 = fp32 ? a.take(n_cs * kCsObs * 8) : SIZE_MAX;
+  r.cs_m64 = fp32 ? SIZE_MAX : a.take(n_cs * kCsObs * 16);
+  r.run_off = a.take((n_p + 1) * 4);
+  r.smc = a.take((z.blocked ? n_p : n_mc) * 4);
+  r.t_run = a.take(n_runs * kCam * ts);
   for (int b = 0; b < 2; ++b) {
     r.P64[b] = a.take(n_p * kCam * 8);
     r.S32[b] = fp32 ? a.take(n_p * ser_stride((int)n_p) * 4) : SIZE_MAX;
@@ -92,11 +101,164 @@ size_t arena_bytes(int64_t n_p, int64_t n_l, int64_t n_obs, int64_t n_pk, int64_
   return a.total;
 }
 
+void unit_counts(const HostLayout& L, int32_t* units) {
+  units[kUnitPacket] = L.n_pk;
+  units[kUnitChunk] = L.n_ch;
+  units[kUnitCamWave] = (L.n_p + kWave - 1) / kWave;
+  units[kUnitOne] = 1;
+  units[kUnitMultiCam] = (int32_t)L.smc.size();
+  units[kUnitCostGroup] = L.n_cg;
+  units[kUnitSerChunk] = L.blocked ? 0 : L.n_ch;
+  units[kUnitCSlot] = L.blocked ? L.n_cs : 0;
+}
+
 size_t layout_footprint(const HostLayout& L, bool fp32) {
-  return arena_bytes(L.n_p, L.n_l, L.n_obs, L.n_pk, L.n_ch, L.n_mc, fp32, kTraceCapacity, nullptr);
+  return arena_bytes(sizes_of(L), fp32, kTraceCapacity, nullptr);
 }
 
 // ------------------------------------------------------------------ layout
+// Number of landmark blocks of a blocked problem: records of at most
+// kLmBlockBytes per block, a multiple of kXcds blocks of equal size.
+static int64_t landmark_blocks(int64_t n_l, bool fp32) {
+  const int64_t lb_max = kLmBlockBytes / (kRec * (fp32 ? 4 : 8));
+  const int64_t nb = (n_l + lb_max - 1) / lb_max;
+  return (nb + kXcds - 1) / kXcds * kXcds;
+}
+
+// XCD of landmark block b: blocks go round the XCDs forwards, then
+// backwards, so that each XCD receives a mix of early (denser) and later
+// blocks of the min-camera landmark order.
+static int xcd_of_block(int64_t b) {
+  const int64_t g = b / kXcds, r = b % kXcds;
+  return (int)((g & 1) ? kXcds - 1 - r : r);
+}
+
+// Slots of the blocked series camera pass, from the camera-major order
+// (camera, then internal landmark) already in L.cm_lm / L.cm_m*.
+static povar_status build_camera_slots(povar_ctx ctx, HostLayout& L, const std::vector<int64_t>& cstart,
+                                       bool fp32) {
+  const int32_t n_p = L.n_p, n_l = L.n_l;
+  const int64_t nb = landmark_blocks(n_l, fp32);
+  const int64_t lb = (n_l + nb - 1) / nb;
+  L.blocked = 1;
+  L.lm_block = (int32_t)lb;
+  // one run per (block, camera) segment part that lies in one slot
+  struct Run {
+    int32_t cam, lslot, lane0, nlanes, key;
+    int64_t beg, cnt;   // camera-major observation range
+  };
+  std::vector<std::vector<std::pair<int64_t, int64_t>>> segs_cam(nb);   // (camera, begin) per block
+  std::vector<std::vector<int64_t>> segs_end(nb);
+  for (int32_t c = 0; c < n_p; ++c) {
+    int64_t pos = cstart[c];
+    while (pos < cstart[c + 1]) {
+      const int64_t b = L.cm_lm[pos] / lb;
+      int64_t end = pos;
+      while (end < cstart[c + 1] && L.cm_lm[end] / lb == b) ++end;
+      segs_cam[b].push_back({c, pos});
+      segs_end[b].push_back(end);
+      pos = end;
+    }
+  }
+  std::vector<std::vector<Run>> runs(nb);
+  std::vector<int32_t> nslots(nb, 0);
+  std::vector<std::vector<int32_t>> slot_lanes(nb);
+  for (int64_t b = 0; b < nb; ++b) {
+    int32_t used = kWave, key = 0;
+    for (size_t k = 0; k < segs_cam[b].size(); ++k) {
+      int64_t beg = segs_cam[b][k].second;
+      const int64_t end = segs_end[b][k];
+      while (beg < end) {
+        if (used == kWave) {
+          slot_lanes[b].push_back(0);
+          ++nslots[b];
+          used = 0;
+          key = 0;
+        }
+        const int64_t want = (end - beg + kCsPerLane - 1) / kCsPerLane;
+        const int32_t nl = (int32_t)std::min<int64_t>(kWave - used, want);
+        const int64_t cnt = std::min<int64_t>(end - beg, (int64_t)nl * kCsPerLane);
+        runs[b].push_back(Run{(int32_t)segs_cam[b][k].first, nslots[b] - 1, used, nl, key, beg, cnt});
+        used += nl;
+        ++key;
+        slot_lanes[b].back() = used;
+        beg += cnt;
+      }
+    }
+  }
+  // dispatch order: rounds of one workgroup (4 slots) per XCD while every
+  // XCD has slots left, then the remaining slots in block order
+  std::vector<std::vector<std::pair<int64_t, int32_t>>> xl(kXcds);   // (block, local slot)
+  for (int64_t b = 0; b < nb; ++b)
+    for (int32_t q = 0; q < nslots[b]; ++q) xl[xcd_of_block(b)].push_back({b, q});
+  std::vector<std::vector<int64_t>> gslot(nb);
+  for (int64_t b = 0; b < nb; ++b) gslot[b].assign(nslots[b], -1);
+  int64_t g = 0;
+  std::vector<size_t> next(kXcds, 0);
+  auto all_left = [&]() {
+    for (int x = 0; x < kXcds; ++x)
+      if (next[x] >= xl[x].size()) return false;
+    return true;
+  };
+  while (all_left()) {
+    for (int x = 0; x < kXcds; ++x) {
+      for (int w = 0; w < kWavesPerBlock; ++w, ++g) {
+        if (next[x] < xl[x].size()) {
+          const auto bq = xl[x][next[x]++];
+          gslot[bq.first][bq.second] = g;
+        }   // else: empty slot keeps the XCD alignment
+      }
+    }
+  }
+  for (int x = 0; x < kXcds; ++x)
+    for (; next[x] < xl[x].size(); ++next[x], ++g) gslot[xl[x][next[x]].first][xl[x][next[x]].second] = g;
+  g = (g + kXcds * kWavesPerBlock - 1) / (kXcds * kWavesPerBlock) * (kXcds * kWavesPerBlock);
+  if (g * (int64_t)kCsObs >= (int64_t)INT_MAX) {
+    set_error(ctx, "camera slot layout exceeds 2^31 entries");
+    return POVAR_EINVAL;
+  }
+  L.n_cs = (int32_t)g;
+  // run ids camera-major (each camera's runs in block order)
+  L.run_off.assign(n_p + 1, 0);
+  for (int64_t b = 0; b < nb; ++b)
+    for (const Run& r : runs[b]) ++L.run_off[r.cam + 1];
+  for (int32_t c = 0; c < n_p; ++c) L.run_off[c + 1] += L.run_off[c];
+  L.n_runs = L.run_off[n_p];
+  std::vector<int32_t> fill(L.run_off.begin(), L.run_off.end() - 1);
+  L.cs_hdr.assign(L.n_cs, 0);
+  L.cs_lane.assign((size_t)L.n_cs * kWave * 2, 0);
+  L.cs_lm.assign((size_t)L.n_cs * kCsObs, -1);
+  if (fp32) L.cs_m32.assign((size_t)L.n_cs * kCsObs * 2, 0.0f);
+  else L.cs_m64.assign((size_t)L.n_cs * kCsObs * 2, 0.0);
+  for (int64_t b = 0; b < nb; ++b) {
+    for (int32_t q = 0; q < nslots[b]; ++q) L.cs_hdr[gslot[b][q]] = slot_lanes[b][q];
+    for (const Run& r : runs[b]) {
+      const int64_t gs = gslot[b][r.lslot];
+      const int32_t id = fill[r.cam]++;
+      for (int32_t l = r.lane0; l < r.lane0 + r.nlanes; ++l) {
+        L.cs_lane[2 * ((size_t)gs * kWave + l)] = r.cam | (r.key << kCamBits);
+        L.cs_lane[2 * ((size_t)gs * kWave + l) + 1] = id;
+      }
+      for (int64_t o = 0; o < r.cnt; ++o) {
+        const int32_t lane = r.lane0 + (int32_t)(o / kCsPerLane), rr = (int32_t)(o % kCsPerLane);
+        const size_t e = ((size_t)gs * kCsPerLane + rr) * kWave + lane;
+        const int64_t src = r.beg + o;
+        L.cs_lm[e] = L.cm_lm[src];
+        if (fp32) {
+          L.cs_m32[2 * e] = L.cm_m32[2 * src];
+          L.cs_m32[2 * e + 1] = L.cm_m32[2 * src + 1];
+        } else {
+          L.cs_m64[2 * e] = L.cm_m64[2 * src];
+          L.cs_m64[2 * e + 1] = L.cm_m64[2 * src + 1];
+        }
+      }
+    }
+  }
+  L.smc.resize(n_p);
+  for (int32_t c = 0; c < n_p; ++c) L.smc[c] = c;
+  return POVAR_OK;
+}
+
 povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs, const int32_t* cam,
                           const int32_t* pt, const double* meas, bool fp32, HostLayout& L) {
   if (n_p <= 0 || n_l <= 0 || n_obs <= 0) {
@@ -265,7 +427,11 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
     if (L.cam_ch[i + 1] - L.cam_ch[i] > 1) L.mc_cam.push_back(i);
   L.n_mc = (int32_t)L.mc_cam.size();
   L.n_cg = (L.n_pk + kCostGroup - 1) / kCostGroup;
-  return POVAR_OK;
+  if (!blocked_layout(n_l, fp32)) {
+    L.smc = L.mc_cam;
+    return POVAR_OK;
+  }
+  return build_camera_slots(ctx, L, cstart, fp32);
 }
 
 }  // namespace povar
@@ -338,7 +504,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   pb->L = std::move(L);
   HostLayout& H = pb->L;
   ArenaOffsets& A = pb->off;
-  pb->bytes = arena_bytes(H.n_p, H.n_l, H.n_obs, H.n_pk, H.n_ch, H.n_mc, pb->fp32, pb->trace_cap, &A);
+  pb->bytes = arena_bytes(sizes_of(H), pb->fp32, pb->trace_cap, &A);
   hipError_t e = hipMalloc(&pb->arena, pb->bytes);
   if (e != hipSuccess) {
     pb->arena = nullptr;
@@ -401,6 +567,17 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.ch_meta = (const int4*)dp(A.ch_meta);
   R.cam_ch = (const int32_t*)dp(A.cam_ch);
   R.mc_cam = (const int32_t*)dp(A.mc_cam);
+  R.blocked = H.blocked;
+  R.n_cs = H.blocked ? H.n_cs : 0;
+  R.n_runs = H.blocked ? H.n_runs : 0;
+  R.n_smc = (int32_t)H.smc.size();
+  R.cs_hdr = (const int32_t*)dp(A.cs_hdr);
+  R.cs_lane = (const int2*)dp(A.cs_lane);
+  R.cs_lm = (const int32_t*)dp(A.cs_lm);
+  R.cs_m32 = (const float2*)dp(A.cs_m32);
+  R.cs_m64 = (const double2*)dp(A.cs_m64);
+  R.ser_off = H.blocked ? (const int32_t*)dp(A.run_off) : (const int32_t*)dp(A.cam_ch);
+  R.ser_mc = (const int32_t*)dp(A.smc);
   for (int b = 0; b < 2; ++b) {
     R.P64[b] = (double*)dp(A.P64[b]);
     R.S32[b] = (float*)dp(A.S32[b]);
@@ -416,6 +593,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.acc = (double*)dp(A.acc);
   R.zx = dp(A.zx);
   R.t_part = dp(A.t_part);
+  R.ser_part = H.blocked ? dp(A.t_run) : dp(A.t_part);
   R.cost_part = (double*)dp(A.cost_part);
   R.cost_group = (double*)dp(A.cost_group);
   R.tr_cost = (double*)dp(A.tr_cost);
@@ -429,7 +607,8 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   c.order = o->series_order;
 
   // batch of one: prefix tables of waves per unit kind
-  const int32_t units[kNumUnitKinds] = {H.n_pk, H.n_ch, (H.n_p + kWave - 1) / kWave, 1, H.n_mc, H.n_cg};
+  int32_t units[kNumUnitKinds];
+  unit_counts(H, units);
   int32_t tables[kNumUnitKinds * 2];
   for (int k = 0; k < kNumUnitKinds; ++k) {
     tables[2 * k] = 0;
@@ -448,6 +627,15 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   upload(img, A.ch_meta, H.ch_meta);
   upload(img, A.cam_ch, H.cam_ch);
   upload(img, A.mc_cam, H.mc_cam);
+  upload(img, A.smc, H.smc);
+  if (H.blocked) {
+    upload(img, A.cs_hdr, H.cs_hdr);
+    upload(img, A.cs_lane, H.cs_lane);
+    upload(img, A.cs_lm, H.cs_lm);
+    if (A.cs_m32 != SIZE_MAX) upload(img, A.cs_m32, H.cs_m32);
+    if (A.cs_m64 != SIZE_MAX) upload(img, A.cs_m64, H.cs_m64);
+    upload(img, A.run_off, H.run_off);
+  }
   upload(img, A.P64[0], P64);
   if (pb->fp32) upload(img, A.S32[0], S32);
   else upload(img, A.S64[0], S64);
@@ -481,6 +669,11 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   keep.n_ch = H.n_ch;
   keep.n_mc = H.n_mc;
   keep.n_cg = H.n_cg;
+  keep.blocked = H.blocked;
+  keep.lm_block = H.lm_block;
+  keep.n_cs = H.n_cs;
+  keep.n_runs = H.n_runs;
+  keep.smc = std::move(H.smc);
   keep.int2ext = std::move(H.int2ext);
   keep.cam_ch = std::move(H.cam_ch);
   H = std::move(keep);
@@ -725,8 +918,18 @@ povar_status povar_problem_footprint(int32_t n_cams, int32_t n_pts, int64_t n_ob
   // takes ceil(L/64) slots.  Chunk rounding adds at most one chunk per camera.
   const int64_t n_pk = std::min<int64_t>(n_pts + n_obs / kWave + 1, n_obs / kWave + 2 * n_obs / (kWave + 1) + 3);
   const int64_t n_ch = n_obs / kChunk + n_cams;
-  *bytes = arena_bytes(n_cams, n_pts, n_obs, n_pk, n_ch, n_cams, precision == POVAR_PREC_FP32_BULK,
-                       kTraceCapacity, nullptr);
+  const bool fp32 = precision == POVAR_PREC_FP32_BULK;
+  LayoutSizes z{n_cams, n_pts, n_obs, n_pk, n_ch, n_cams, 0, 0, blocked_layout(n_pts, fp32)};
+  if (z.blocked) {
+    // segments (block, camera) <= min(n_obs, n_cams * blocks); a slot holds
+    // 64 lanes, a run wastes less than one lane, and a slot boundary splits
+    // at most one run; plus one partial slot per block and the dispatch padding
+    const int64_t nb = landmark_blocks(n_pts, fp32);
+    const int64_t segs = std::min<int64_t>(n_obs, (int64_t)n_cams * nb);
+    z.n_cs = (n_obs / kCsPerLane + segs) / (kWave - 1) + 2 * nb + 2 * kXcds * kWavesPerBlock;
+    z.n_runs = segs + z.n_cs;
+  }
+  *bytes = arena_bytes(z, fp32, kTraceCapacity, nullptr);
   return POVAR_OK;
 }
 
@@ -1075,6 +1278,16 @@ povar_status povar_problem_info(povar_problem pb, int64_t* n_obs, int64_t* n_pac
   if (n_packets) *n_packets = pb->L.n_pk;
   if (n_chunks) *n_chunks = pb->L.n_ch;
   if (device_bytes) *device_bytes = pb->bytes;
+  return POVAR_OK;
+}
+
+povar_status povar_problem_layout(povar_problem pb, int32_t* blocked, int32_t* lm_block, int64_t* n_slots,
+                                  int64_t* n_runs) {
+  if (!pb) return POVAR_EINVAL;
+  if (blocked) *blocked = pb->L.blocked;
+  if (lm_block) *lm_block = pb->L.lm_block;
+  if (n_slots) *n_slots = pb->L.blocked ? pb->L.n_cs : 0;
+  if (n_runs) *n_runs = pb->L.blocked ? pb->L.n_runs : 0;
   return POVAR_OK;
 }
 

@@ -107,7 +107,8 @@ hipError_t upload_tables(povar_server_s* sv, Group& G) {
   G.max_order = 0;
   for (int p = 0; p < n; ++p) {
     const HostLayout& L = G.res[p].pb->L;
-    const int32_t units[kNumUnitKinds] = {L.n_pk, L.n_ch, (L.n_p + kWave - 1) / kWave, 1, L.n_mc, L.n_cg};
+    int32_t units[kNumUnitKinds];
+    unit_counts(L, units);
     for (int k = 0; k < kNumUnitKinds; ++k) tab[(size_t)k * stride + p + 1] = tab[(size_t)k * stride + p] + units[k];
     G.max_order = std::max(G.max_order, G.res[p].pb->opt.series_order);
   }

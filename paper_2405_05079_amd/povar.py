@@ -30,7 +30,7 @@ EXPORTS = [
     "povar_problem_destroy", "povar_solve", "povar_step", "povar_enqueue", "povar_get_report",
     "povar_get_cameras", "povar_get_points", "povar_get_trace", "povar_get_state", "povar_set_state",
     "povar_debug_linearize", "povar_debug_step", "povar_kernel_timing", "povar_kernel_times",
-    "povar_problem_info", "povar_server_create", "povar_server_submit", "povar_server_poll",
+    "povar_problem_info", "povar_problem_layout", "povar_server_create", "povar_server_submit", "povar_server_poll",
     "povar_server_stats", "povar_server_destroy",
 ]
 
@@ -99,6 +99,7 @@ def lib() -> C.CDLL:
         "povar_kernel_timing": (C.c_int, [_P, C.c_int32]),
         "povar_kernel_times": (C.c_int, [_P, _DP, _I64P, _DP, _I64P]),
         "povar_problem_info": (C.c_int, [_P, _I64P, _I64P, _I32P, _U64P]),
+        "povar_problem_layout": (C.c_int, [_P, _I32P, _I32P, _I64P, _I64P]),
         "povar_server_create": (C.c_int, [_P, C.c_uint64, C.c_int32, C.POINTER(_P)]),
         "povar_server_submit": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P,
                                           C.POINTER(Options), _U64P]),
@@ -289,6 +290,13 @@ class Problem:
         self._chk(lib().povar_problem_info(self.handle, C.byref(a), C.byref(b), C.byref(c), C.byref(d)),
                   "povar_problem_info")
         return dict(n_obs=a.value, n_packets=b.value, n_chunks=c.value, device_bytes=d.value)
+
+    def layout(self) -> dict:
+        b, lb = C.c_int32(), C.c_int32()
+        ns, nr = C.c_int64(), C.c_int64()
+        self._chk(lib().povar_problem_layout(self.handle, C.byref(b), C.byref(lb), C.byref(ns), C.byref(nr)),
+                  "povar_problem_layout")
+        return dict(blocked=bool(b.value), lm_block=lb.value, n_slots=ns.value, n_runs=nr.value)
 
     def close(self):
         if self.handle:

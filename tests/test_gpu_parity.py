@@ -130,6 +130,32 @@ def test_many_cameras_and_many_chunks_per_camera(ctx):
         gp.close()
 
 
+# landmark records above 4 MiB: the slot camera pass (landmark blocks, runs
+# per camera and block, partials added per camera)
+BLOCKED = [
+    ("fp64", dict(n_cams=40, n_pts=70000, track=("uniform", 2, 4), seed=31), 1e-9),
+    # ~38k observations per camera: many runs per camera and block, runs split at slot ends
+    ("fp32_bulk", dict(n_cams=6, n_pts=140000, track=("uniform", 2, 2), seed=32), 2e-3),
+    # heavy-tailed views per camera
+    ("fp32_bulk", dict(n_cams=300, n_pts=140000, track=("uniform", 2, 3), cam_choice="zipf", seed=33), 2e-3),
+]
+
+
+@pytest.mark.parametrize("prec,kw,tol", BLOCKED)
+def test_blocked_camera_pass(ctx, prec, kw, tol):
+    prob = synth.make_problem(**kw)
+    say("blocked", prec, kw)
+    gp = povar.Problem.from_synth(ctx, prob, precision=prec)
+    lay = gp.layout()
+    assert lay["blocked"] and lay["n_slots"] > 0 and lay["n_runs"] >= prob.n_cams
+    P, X, f = O.initial_state(prob, prob.cams0)
+    lin = O.linearize(P, X, prob)
+    for lam, order in ((1e-3, 1), (1e-3, 8)):
+        dp, pt, ct = gp.debug_step(lam, order)
+        assert rel(dp, O.camera_step(P, lin, lam, order)) < tol
+    gp.close()
+
+
 def test_trajectory_fp64_matches_oracle(ctx):
     prob = synth.workload(1)
     say("trajectory fp64 workload 1")
