@@ -55,7 +55,8 @@ def series_bytes(n_obs: int, n_l: int, n_p: int, fp32: bool):
     camera pass: per observation the landmark index (4 B) and the measurement
       (2s); per landmark z_j and X_j (6s); per camera the FP64 12x12 block K_i
       (1152 B), Pbar_i (9s), x_i written (12s) and the FP64 partial sum acc_i
-      read and written (192 B)."""
+      read and written (192 B).  The per-camera part is done by the combine
+      kernel when a problem's camera pass is blocked; the figure is the pass's."""
     s = 4 if fp32 else 8
     lpass = (4 + 2 * s) * n_obs + (6 * s + 48) * n_l + 21 * s * n_p
     cpass = (4 + 2 * s) * n_obs + 6 * s * n_l + (1344 + 21 * s) * n_p
@@ -289,7 +290,7 @@ def main():
         kt = gp.kernel_times()
         gp.kernel_timing(False)
         info = gp.info()
-        res[prec] = dict(secs=secs, iters_per_s=args.steps / secs, rep=rep, kt=kt, info=info)
+        res[prec] = dict(secs=secs, iters_per_s=args.steps / secs, rep=rep, kt=kt, info=info, layout=gp.layout())
         print(f"[bench] {prec}: {args.steps / secs:.1f} iters/s, cost {rep['cost_final']:.6g}",
               file=sys.stderr, flush=True)
         gp.close()
@@ -301,6 +302,8 @@ def main():
     bl, bc = series_bytes(prob.n_obs, prob.n_pts, prob.n_cams, True)
     if ms_l >= ms_c:
         name, ms, byt = "k_series_landmark<float>", ms_l, bl
+    elif fp32["layout"]["blocked"]:
+        name, ms, byt = "k_series_camera_slots<float>", ms_c, bc
     else:
         name, ms, byt = "k_series_camera<float>", ms_c, bc
     achieved = byt / (ms * 1e-3) / 1e9
