@@ -27,6 +27,7 @@ struct HostLayout {
   int64_t n_obs = 0;
   int32_t n_pk = 0, n_ch = 0;
   std::vector<int32_t> int2ext;        // internal landmark -> caller's index
+  std::vector<int32_t> cam_int2ext;    // internal camera -> caller's index
   std::vector<int32_t> pk_hdr;         // 2 per slot: (n, lm0)
   std::vector<uint32_t> pk_code;
   std::vector<float> pk_m32;
@@ -111,7 +112,9 @@ namespace povar {
 povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, const povar_options* o,
                           hipStream_t stream, povar_problem_s* pb, DevProblem* rec_dev, int32_t iter_limit);
 size_t layout_footprint(const HostLayout& L, bool fp32);
-void unit_counts(const HostLayout& L, int32_t* units);   // kNumUnitKinds units per kind
+void unit_counts(const HostLayout& L, int32_t* units);
+// width values per camera, internal order -> caller's order
+void cams_to_caller(const HostLayout& L, const double* in, double* out, int width);   // kNumUnitKinds units per kind
 povar_status copy_points(povar_problem_s* pb, int lcur, double* out);
 hipError_t read_ctl(povar_problem_s* pb, Ctl* out);
 hipError_t write_ctl(povar_problem_s* pb, const Ctl* in);

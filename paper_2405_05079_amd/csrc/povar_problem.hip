@@ -101,6 +101,11 @@ size_t arena_bytes(const LayoutSizes& z, bool fp32, int64_t trace_cap, ArenaOffs
   return a.total;
 }
 
+void cams_to_caller(const HostLayout& L, const double* in, double* out, int width) {
+  for (int32_t i = 0; i < L.n_p; ++i)
+    std::memcpy(out + (size_t)L.cam_int2ext[i] * width, in + (size_t)i * width, sizeof(double) * width);
+}
+
 void unit_counts(const HostLayout& L, int32_t* units) {
   units[kUnitPacket] = L.n_pk;
   units[kUnitChunk] = L.n_ch;
@@ -300,6 +305,23 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
       set_error(ctx, "point %d has no observation", j);
       return POVAR_EINVAL;
     }
+  // internal camera order: most observed first (the landmark pass of large
+  // problems keeps the first cameras' series data in LDS), then caller's index;
+  // everything below works on internal camera ids
+  L.cam_int2ext.resize(n_p);
+  std::iota(L.cam_int2ext.begin(), L.cam_int2ext.end(), 0);
+  std::stable_sort(L.cam_int2ext.begin(), L.cam_int2ext.end(),
+                   [&](int32_t a, int32_t b) { return cnt_c[a] > cnt_c[b]; });
+  std::vector<int32_t> cam_ext2int(n_p);
+  for (int32_t i = 0; i < n_p; ++i) cam_ext2int[L.cam_int2ext[i]] = i;
+  std::vector<int32_t> cam_in(n_obs);
+  for (int64_t k = 0; k < n_obs; ++k) cam_in[k] = cam_ext2int[cam[k]];
+  {
+    std::vector<int32_t> cnt(n_p);
+    for (int32_t i = 0; i < n_p; ++i) cnt[i] = cnt_c[L.cam_int2ext[i]];
+    cnt_c.swap(cnt);
+  }
+  cam = cam_in.data();
   // internal landmark order: by the smallest camera that sees the landmark,
   // then caller's index (landmarks sharing a camera sit close together, which
   // helps the camera-major gathers)
@@ -520,22 +542,23 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   std::vector<float> S32(pb->fp32 ? (size_t)H.n_p * ss : 0, 0.0f);
   std::vector<double> S64(pb->fp32 ? 0 : (size_t)H.n_p * ss, 0.0);
   for (int32_t i = 0; i < H.n_p; ++i) {
+    const int32_t e = H.cam_int2ext[i];
     double nrm = 0.0;
     for (int r = 0; r < kCam; ++r) {
-      const double v = cams0[(size_t)i * kCam + r];
+      const double v = cams0[(size_t)e * kCam + r];
       if (!std::isfinite(v)) {
-        set_error(ctx, "initial camera %d is not finite", i);
+        set_error(ctx, "initial camera %d is not finite", e);
         return POVAR_EINVAL;
       }
       nrm += v * v;
     }
     if (!(nrm > 0.0)) {
-      set_error(ctx, "initial camera %d is zero", i);
+      set_error(ctx, "initial camera %d is zero", e);
       return POVAR_EINVAL;
     }
     const double s = o->manifold == POVAR_MANIFOLD_SPHERE ? 1.0 / std::sqrt(nrm) : 1.0;
     for (int r = 0; r < kCam; ++r) {
-      const double v = cams0[(size_t)i * kCam + r] * s;
+      const double v = cams0[(size_t)e * kCam + r] * s;
       P64[(size_t)i * kCam + r] = v;
       if (pb->fp32) S32[(size_t)i * ss + r] = (float)v;
       else S64[(size_t)i * ss + r] = v;
@@ -675,6 +698,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   keep.n_runs = H.n_runs;
   keep.smc = std::move(H.smc);
   keep.int2ext = std::move(H.int2ext);
+  keep.cam_int2ext = std::move(H.cam_int2ext);
   keep.cam_ch = std::move(H.cam_ch);
   H = std::move(keep);
   Ctl now;
@@ -1043,9 +1067,11 @@ povar_status povar_get_cameras(povar_problem pb, double* out) {
   if (!pb || !out) return POVAR_EINVAL;
   Ctl c;
   HIP_TRY(pb->ctx, read_ctl(pb, &c));
-  HIP_TRY(pb->ctx, hipMemcpyAsync(out, pb->rec.P64[c.pcur], (size_t)pb->L.n_p * kCam * 8,
-                                  hipMemcpyDeviceToHost, pb->stream));
+  std::vector<double> tmp((size_t)pb->L.n_p * kCam);
+  HIP_TRY(pb->ctx, hipMemcpyAsync(tmp.data(), pb->rec.P64[c.pcur], tmp.size() * 8, hipMemcpyDeviceToHost,
+                                  pb->stream));
   HIP_TRY(pb->ctx, hipStreamSynchronize(pb->stream));
+  cams_to_caller(pb->L, tmp.data(), out, kCam);
   return POVAR_OK;
 }
 
@@ -1097,10 +1123,11 @@ povar_status povar_set_state(povar_problem pb, const double* cams, double lambda
   std::vector<float> S32(pb->fp32 ? (size_t)n_p * ss : 0, 0.0f);
   std::vector<double> S64(pb->fp32 ? 0 : (size_t)n_p * ss, 0.0);
   for (int32_t i = 0; i < n_p; ++i) {
+    const double* ci = cams + (size_t)pb->L.cam_int2ext[i] * kCam;   // caller's order
     double nrm = 0.0;
-    for (int r = 0; r < kCam; ++r) nrm += cams[(size_t)i * kCam + r] * cams[(size_t)i * kCam + r];
+    for (int r = 0; r < kCam; ++r) nrm += ci[r] * ci[r];
     if (!(nrm > 0.0) || !std::isfinite(nrm)) {
-      set_error(ctx, "camera %d is zero or not finite", i);
+      set_error(ctx, "camera %d is zero or not finite", pb->L.cam_int2ext[i]);
       return POVAR_EINVAL;
     }
     // cameras already on the sphere (to 1e-14) are taken bit-exactly, so a
@@ -1108,7 +1135,7 @@ povar_status povar_set_state(povar_problem pb, const double* cams, double lambda
     const bool renorm = pb->opt.manifold == POVAR_MANIFOLD_SPHERE && std::fabs(nrm - 1.0) > 1e-14;
     const double s = renorm ? 1.0 / std::sqrt(nrm) : 1.0;
     for (int r = 0; r < kCam; ++r) {
-      const double v = cams[(size_t)i * kCam + r] * s;
+      const double v = ci[r] * s;
       P64[(size_t)i * kCam + r] = v;
       if (pb->fp32) S32[(size_t)i * ss + r] = (float)v;
       else S64[(size_t)i * ss + r] = v;
@@ -1161,6 +1188,7 @@ povar_status povar_debug_linearize(povar_problem pb, double* U, double* bp, doub
     return (lo * 7 - lo * lo) / 2 + hi;
   };
   for (int32_t i = 0; i < n_p; ++i) {
+    const size_t e = (size_t)pb->L.cam_int2ext[i];   // caller's index of internal camera i
     // chunk partials of camera i added in chunk order, as the kernels do
     double q[kLinVals] = {0};
     for (int32_t ch = pb->L.cam_ch[i]; ch < pb->L.cam_ch[i + 1]; ++ch)
@@ -1173,11 +1201,11 @@ povar_status povar_debug_linearize(povar_problem pb, double* U, double* bp, doub
           if (ar < 2 && ac < 2) v = ar == ac ? q[k] : 0.0;
           else if (ar == 2 && ac == 2) v = a * q[30 + k];
           else v = -a * q[(ar == 1 || ac == 1) ? 20 + k : 10 + k];
-          U[(size_t)i * 144 + r * 12 + cc] = v;
+          U[e * 144 + r * 12 + cc] = v;
         }
     for (int r = 0; r < kCam; ++r) {
-      if (bp) bp[(size_t)i * kCam + r] = q[40 + r];
-      if (g) g[(size_t)i * kCam + r] = q[40 + r] - q[52 + r];
+      if (bp) bp[e * kCam + r] = q[40 + r];
+      if (g) g[e * kCam + r] = q[40 + r] - q[52 + r];
     }
   }
   if (Vp) {
@@ -1232,11 +1260,13 @@ povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, do
   Ctl after;
   HIP_TRY(ctx, read_ctl(pb, &after));
   const int32_t n_p = pb->L.n_p;
-  if (dp) HIP_TRY(ctx, hipMemcpyAsync(dp, pb->rec.acc, (size_t)n_p * kCam * 8, hipMemcpyDeviceToHost, pb->stream));
-  if (p_trial)
-    HIP_TRY(ctx, hipMemcpyAsync(p_trial, pb->rec.P64[c.pcur ^ 1], (size_t)n_p * kCam * 8, hipMemcpyDeviceToHost,
-                                pb->stream));
+  std::vector<double> tdp((size_t)n_p * kCam), tpt((size_t)n_p * kCam);
+  HIP_TRY(ctx, hipMemcpyAsync(tdp.data(), pb->rec.acc, tdp.size() * 8, hipMemcpyDeviceToHost, pb->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(tpt.data(), pb->rec.P64[c.pcur ^ 1], tpt.size() * 8, hipMemcpyDeviceToHost,
+                              pb->stream));
   HIP_TRY(ctx, hipStreamSynchronize(pb->stream));
+  if (dp) cams_to_caller(pb->L, tdp.data(), dp, kCam);
+  if (p_trial) cams_to_caller(pb->L, tpt.data(), p_trial, kCam);
   if (cost_trial) *cost_trial = after.cost_trial;
   Ctl restore = saved;
   restore.need_lin = 0;   // the linearisation at the current cameras is now in place

@@ -175,10 +175,11 @@ hipError_t retire(povar_server_s* sv, Group& G, int idx, const Ctl& c) {
   Resident R = G.res[idx];
   auto& r = R.req;
   povar_problem_s* pb = R.pb;
-  std::vector<double> cams((size_t)r->n_p * kCam), pts((size_t)r->n_l * 3);
-  hipError_t e = hipMemcpyAsync(cams.data(), pb->rec.P64[c.pcur], cams.size() * 8, hipMemcpyDeviceToHost,
+  std::vector<double> cams((size_t)r->n_p * kCam), pts((size_t)r->n_l * 3), cin((size_t)r->n_p * kCam);
+  hipError_t e = hipMemcpyAsync(cin.data(), pb->rec.P64[c.pcur], cin.size() * 8, hipMemcpyDeviceToHost,
                                 sv->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
+  if (e == hipSuccess) cams_to_caller(pb->L, cin.data(), cams.data(), kCam);
   povar_status st = e == hipSuccess ? copy_points(pb, c.lcur, pts.data()) : POVAR_EDEVICE;
   povar_report rep;
   fill_report(pb, c, 0.0, &rep);
