@@ -127,6 +127,8 @@ struct DevProblem {
   // g % 8, and the slots are ordered so that all slots of a block go to the
   // XCD that block is assigned to, in block order.
   int32_t blocked, n_cs, n_runs, n_smc;
+  int32_t n_hot;        // cameras whose series data the LDS landmark pass stages (0: not used)
+  int32_t pad2;
   const int32_t POVAR_GMEM* cs_hdr;    // n_cs: lanes used (0: empty slot)
   const int2 POVAR_GMEM* cs_lane;      // n_cs x 64: (camera | run key << 26, run id)
   const int32_t POVAR_GMEM* cs_lm;     // entry (q, r, lane) at (q * kCsPerLane + r) * 64 + lane:
@@ -177,7 +179,17 @@ struct Batch {
   const int32_t POVAR_GMEM* off[kNumUnitKinds];
   int32_t n_prob;
   int32_t total[kNumUnitKinds];
+  // single large problem: the landmark pass runs as lds_grid persistent
+  // workgroups with lds_bytes of staged camera data (0: the plain pass)
+  int32_t lds_bytes, lds_grid;
 };
+
+constexpr int kLdsCamVals = 21;   // staged camera values: x (12), Pbar (9)
+constexpr int kLdsBlock = 1024;   // threads of a staged landmark-pass workgroup
+
+// Enables dynamic LDS of `bytes` for the staged landmark pass (host, once
+// per size increase; not while a stream is being captured).
+hipError_t prepare_landmark_lds(int bytes);
 
 // Launchers (defined with the kernels).  `fp32` selects the series /
 // Jacobian precision; the critical kernels are FP64 in both modes.

@@ -29,6 +29,7 @@
 // which adds the chunk partials in chunk order.
 #include <hip/hip_ext.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "povar_internal.h"
@@ -775,28 +776,74 @@ __device__ __forceinline__ void store_z(const double (&v)[8], int j, T y0, T y1,
   store4(zx + (size_t)j * kRec + 4, X0, X1, X2, (T)1);
 }
 
-// z_j = V_j^+ sum_k Pbar_i^T N_k (X_i x~_j), X_i = x_i as a 3x4 matrix; the
-// (z_j, X_j) record is written for the camera pass.
+// Camera series data of the landmark pass: x_i (12 values) and the rows of
+// Pbar_i, from the series records in global memory ...
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
-  int p, q;
-  if (!map_wave(B, kUnitPacket, p, q)) return;
-  DevProblem& D = B.probs[p];
-  if (D.ctl.done || t > D.ctl.order) return;
-  const int lc = D.ctl.lcur, pc = D.ctl.pcur;
+struct CamFromRecords {
+  const T* __restrict__ S;
+  int stride;
+  __device__ __forceinline__ void operator()(int c, T (&xc)[12], T (&Pc)[12]) const {
+    load12(S + (size_t)c * stride + kSerX, xc);
+    load12(S + (size_t)c * stride, Pc);
+  }
+};
+
+// ... or, for the n_hot most observed cameras, from a table in LDS
+// (kLdsCamVals values per camera: x, then Pbar row-major).
+#define POVAR_LDS __attribute__((address_space(3)))
+template <typename T>
+struct CamFromLds {
+  const T POVAR_LDS* tab;
+  CamFromRecords<T> g;
+  int n_hot;
+  __device__ __forceinline__ void operator()(int c, T (&xc)[12], T (&Pc)[12]) const {
+    if (c < n_hot) {
+      const T POVAR_LDS* e = tab + c * kLdsCamVals;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) xc[k] = e[k];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        Pc[4 * r] = e[12 + 3 * r];
+        Pc[4 * r + 1] = e[13 + 3 * r];
+        Pc[4 * r + 2] = e[14 + 3 * r];
+        Pc[4 * r + 3] = 0;
+      }
+    } else {
+      g(c, xc, Pc);
+    }
+  }
+};
+
+// The first loads of a packet slot (this lane's entry and the slot header),
+// which depend on nothing else.
+template <typename T>
+struct SlotHead {
+  uint32_t code;
+  typename Prec<T>::T2 m;
+  int2 hdr;
+};
+
+template <typename T>
+__device__ __forceinline__ SlotHead<T> slot_head(const DevProblem& D, int q) {
+  const int e = q * kWave + lane_id();
+  return SlotHead<T>{D.pk_code[e], Prec<T>::pk_m(D)[e], D.pk_hdr[q]};
+}
+
+// One packet slot of the landmark pass: z_j = V_j^+ sum_k Pbar_i^T N_k (X_i x~_j),
+// X_i = x_i as a 3x4 matrix; the (z_j, X_j) record is written for the camera
+// pass.  Wave-uniform; all 64 lanes call it.
+template <typename T, typename Cam>
+__device__ __forceinline__ void landmark_slot(const DevProblem& D, int q, const SlotHead<T>& head, int lc,
+                                              const Cam& cam) {
   const int lane = lane_id();
   const int off = q * kWave;
   const T* __restrict__ rec = Prec<T>::rec(D, lc);
-  // P and x of a camera share one series record (one line in FP32)
-  const T* __restrict__ Sr = Prec<T>::S(D, pc);
   const typename Prec<T>::T2* __restrict__ em = Prec<T>::pk_m(D);
   const T a = (T)(1.0 - D.eta);
   T* zx = static_cast<T*>(D.zx);
-  // entry loads do not wait for the slot header
-  const uint32_t code = D.pk_code[off + lane];
-  const auto mraw = em[off + lane];
-  const int2 hdr = D.pk_hdr[q];
-  const int n = hdr.x, lm0 = hdr.y;
+  const uint32_t code = head.code;
+  const auto mraw = head.m;
+  const int n = head.hdr.x, lm0 = head.hdr.y;
   if (n == 0) return;   // continuation slot of a long landmark
   if (n <= kWave) {
     const bool act = lane < n;
@@ -815,8 +862,7 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
       const auto m = mraw;
       load4(rec + (size_t)(lm0 + key) * kRec + 4, X0, X1, X2, one);
       T xc[12], Pc[12];
-      load12(Sr + (size_t)c * D.s_stride + kSerX, xc);
-      load12(Sr + (size_t)c * D.s_stride, Pc);
+      cam(c, xc, Pc);
       const T q0 = xc[0] * X0 + xc[1] * X1 + xc[2] * X2 + xc[3];
       const T q1 = xc[4] * X0 + xc[5] * X1 + xc[6] * X2 + xc[7];
       const T q2 = xc[8] * X0 + xc[9] * X1 + xc[10] * X2 + xc[11];
@@ -841,8 +887,7 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
       const int c = (int)(D.pk_code[e] & kCamMask);
       const auto m = em[e];
       T xc[12], Pc[12];
-      load12(Sr + (size_t)c * D.s_stride + kSerX, xc);
-      load12(Sr + (size_t)c * D.s_stride, Pc);
+      cam(c, xc, Pc);
       const T q0 = xc[0] * X0 + xc[1] * X1 + xc[2] * X2 + xc[3];
       const T q1 = xc[4] * X0 + xc[5] * X1 + xc[6] * X2 + xc[7];
       const T q2 = xc[8] * X0 + xc[9] * X1 + xc[10] * X2 + xc[11];
@@ -856,6 +901,54 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
     y1 = wave_sum(y1);
     y2 = wave_sum(y2);
     if (lane == 0) store_z<T>(v, lm0, y0, y1, y2, X0, X1, X2, zx);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
+  int p, q;
+  if (!map_wave(B, kUnitPacket, p, q)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done || t > D.ctl.order) return;
+  const CamFromRecords<T> cam{Prec<T>::S(D, D.ctl.pcur), D.s_stride};
+  landmark_slot<T>(D, q, slot_head<T>(D, q), D.ctl.lcur, cam);
+}
+
+// Landmark pass of a single large problem: one persistent workgroup of
+// kLdsBlock threads per CU first copies x_i and Pbar_i of the n_hot most
+// observed cameras (internal ids below n_hot) into LDS, then its waves walk
+// the packet slots; the other cameras are read from the series records.
+template <typename T>
+__global__ void __launch_bounds__(kLdsBlock) k_series_landmark_lds(Batch B, int t) {
+  const DevProblem& D = B.probs[0];
+  if (D.ctl.done || t > D.ctl.order) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T POVAR_LDS* tab = (T POVAR_LDS*)lds_raw;
+  const int n_hot = D.n_hot, ss = D.s_stride;
+  const T* __restrict__ S = Prec<T>::S(D, D.ctl.pcur);
+  for (int idx = threadIdx.x; idx < n_hot * kLdsCamVals; idx += kLdsBlock) {
+    const int h = idx / kLdsCamVals, k = idx - h * kLdsCamVals;
+    const int src = k < 12 ? kSerX + k : (k - 12) / 3 * 4 + (k - 12) % 3;
+    tab[idx] = S[(size_t)h * ss + src];
+  }
+  __syncthreads();
+  const CamFromLds<T> cam{tab, CamFromRecords<T>{S, ss}, n_hot};
+  const int lc = D.ctl.lcur;
+  const int waves = kLdsBlock / kWave;
+  const int stride = (int)gridDim.x * waves;
+  // the next slot's entry and header loads are issued before this slot's work
+  int q = (int)blockIdx.x * waves + (int)(threadIdx.x >> 6);
+  if (q >= D.n_pk) return;
+  SlotHead<T> head = slot_head<T>(D, q);
+  for (;;) {
+    const int qn = q + stride;
+    const bool more = qn < D.n_pk;
+    SlotHead<T> next = head;
+    if (more) next = slot_head<T>(D, qn);
+    landmark_slot<T>(D, q, head, lc, cam);
+    if (!more) break;
+    q = qn;
+    head = next;
   }
 }
 
@@ -1172,8 +1265,29 @@ hipError_t launch_camera_prep(const Batch& b, bool fp32, hipStream_t s) {
 
 // With ev0/ev1 set, the events are recorded by the dispatch itself
 // (hipExtLaunchKernelGGL), so their interval is the kernel's execution.
+hipError_t prepare_landmark_lds(int bytes) {
+  static std::mutex mu;
+  static int enabled = 0;
+  std::lock_guard<std::mutex> g(mu);
+  if (bytes <= enabled) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_series_landmark_lds<float>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_series_landmark_lds<double>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) enabled = bytes;
+  return e;
+}
+
 hipError_t launch_series_landmark(const Batch& b, bool fp32, int t, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (b.total[kUnitPacket] == 0) return hipSuccess;
+  if (b.lds_bytes > 0 && b.n_prob == 1) {
+    const dim3 g((unsigned)b.lds_grid);
+    const size_t sh = (size_t)b.lds_bytes;
+    if (fp32) hipExtLaunchKernelGGL(k_series_landmark_lds<float>, g, dim3(kLdsBlock), sh, s, ev0, ev1, 0, b, t);
+    else hipExtLaunchKernelGGL(k_series_landmark_lds<double>, g, dim3(kLdsBlock), sh, s, ev0, ev1, 0, b, t);
+    return hipGetLastError();
+  }
   const dim3 g = blocks_for(b.total[kUnitPacket], kWavesPerBlock);
   if (fp32) hipExtLaunchKernelGGL(k_series_landmark<float>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
   else hipExtLaunchKernelGGL(k_series_landmark<double>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);

@@ -601,6 +601,23 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.cs_m64 = (const double2*)dp(A.cs_m64);
   R.ser_off = H.blocked ? (const int32_t*)dp(A.run_off) : (const int32_t*)dp(A.cam_ch);
   R.ser_mc = (const int32_t*)dp(A.smc);
+  // a single large FP64 problem stages the series data of its most observed
+  // cameras in LDS for the landmark pass (measured faster than gathering them
+  // from L2 in FP64; in FP32 the plain pass with more resident waves is faster)
+  int lds_bytes = 0, lds_grid = 0;
+  if (H.blocked && !rec_dev && !pb->fp32) {
+    int max_lds = 0, n_cu = 0;
+    HIP_TRY(ctx, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    HIP_TRY(ctx, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    const int per = kLdsCamVals * 8;
+    const int n_hot = std::min<int>(H.n_p, max_lds / per);
+    if (n_hot > 0 && n_cu > 0) {
+      R.n_hot = n_hot;
+      lds_bytes = n_hot * per;
+      lds_grid = n_cu;
+      HIP_TRY(ctx, prepare_landmark_lds(lds_bytes));
+    }
+  }
   for (int b = 0; b < 2; ++b) {
     R.P64[b] = (double*)dp(A.P64[b]);
     R.S32[b] = (float*)dp(A.S32[b]);
@@ -678,6 +695,8 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
     B.total[k] = units[k];
   }
   B.n_prob = 1;
+  B.lds_bytes = lds_bytes;
+  B.lds_grid = lds_grid;
   // initial landmarks and cost, Eq. (8)-(9)
   HIP_TRY(ctx, launch_landmark_solve(B, 0, stream));
   HIP_TRY(ctx, launch_cost_groups(B, 0, stream));
@@ -1312,8 +1331,9 @@ povar_status povar_problem_info(povar_problem pb, int64_t* n_obs, int64_t* n_pac
 }
 
 povar_status povar_problem_layout(povar_problem pb, int32_t* blocked, int32_t* lm_block, int64_t* n_slots,
-                                  int64_t* n_runs) {
+                                  int64_t* n_runs, int32_t* n_lds_cams) {
   if (!pb) return POVAR_EINVAL;
+  if (n_lds_cams) *n_lds_cams = pb->batch.lds_bytes > 0 ? pb->rec.n_hot : 0;
   if (blocked) *blocked = pb->L.blocked;
   if (lm_block) *lm_block = pb->L.lm_block;
   if (n_slots) *n_slots = pb->L.blocked ? pb->L.n_cs : 0;

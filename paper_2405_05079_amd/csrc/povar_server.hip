@@ -116,6 +116,8 @@ hipError_t upload_tables(povar_server_s* sv, Group& G) {
   if (e != hipSuccess) return e;
   G.batch.probs = G.recs;
   G.batch.n_prob = n;
+  G.batch.lds_bytes = 0;   // batches use the plain landmark pass
+  G.batch.lds_grid = 0;
   for (int k = 0; k < kNumUnitKinds; ++k) {
     G.batch.off[k] = G.tables + (size_t)k * stride;
     G.batch.total[k] = tab[(size_t)k * stride + n];

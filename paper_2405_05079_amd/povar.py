@@ -99,7 +99,7 @@ def lib() -> C.CDLL:
         "povar_kernel_timing": (C.c_int, [_P, C.c_int32]),
         "povar_kernel_times": (C.c_int, [_P, _DP, _I64P, _DP, _I64P]),
         "povar_problem_info": (C.c_int, [_P, _I64P, _I64P, _I32P, _U64P]),
-        "povar_problem_layout": (C.c_int, [_P, _I32P, _I32P, _I64P, _I64P]),
+        "povar_problem_layout": (C.c_int, [_P, _I32P, _I32P, _I64P, _I64P, _I32P]),
         "povar_server_create": (C.c_int, [_P, C.c_uint64, C.c_int32, C.POINTER(_P)]),
         "povar_server_submit": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P,
                                           C.POINTER(Options), _U64P]),
@@ -292,11 +292,12 @@ class Problem:
         return dict(n_obs=a.value, n_packets=b.value, n_chunks=c.value, device_bytes=d.value)
 
     def layout(self) -> dict:
-        b, lb = C.c_int32(), C.c_int32()
+        b, lb, nh = C.c_int32(), C.c_int32(), C.c_int32()
         ns, nr = C.c_int64(), C.c_int64()
-        self._chk(lib().povar_problem_layout(self.handle, C.byref(b), C.byref(lb), C.byref(ns), C.byref(nr)),
-                  "povar_problem_layout")
-        return dict(blocked=bool(b.value), lm_block=lb.value, n_slots=ns.value, n_runs=nr.value)
+        self._chk(lib().povar_problem_layout(self.handle, C.byref(b), C.byref(lb), C.byref(ns), C.byref(nr),
+                                             C.byref(nh)), "povar_problem_layout")
+        return dict(blocked=bool(b.value), lm_block=lb.value, n_slots=ns.value, n_runs=nr.value,
+                    n_lds_cams=nh.value)
 
     def close(self):
         if self.handle:

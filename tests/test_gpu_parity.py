@@ -134,6 +134,8 @@ def test_many_cameras_and_many_chunks_per_camera(ctx):
 # per camera and block, partials added per camera)
 BLOCKED = [
     ("fp64", dict(n_cams=40, n_pts=70000, track=("uniform", 2, 4), seed=31), 1e-9),
+    # more cameras than the landmark pass stages in LDS: staged and global camera reads
+    ("fp64", dict(n_cams=1200, n_pts=70000, track=("uniform", 2, 4), cam_choice="zipf", seed=34), 1e-9),
     # ~38k observations per camera: many runs per camera and block, runs split at slot ends
     ("fp32_bulk", dict(n_cams=6, n_pts=140000, track=("uniform", 2, 2), seed=32), 2e-3),
     # heavy-tailed views per camera
@@ -148,6 +150,13 @@ def test_blocked_camera_pass(ctx, prec, kw, tol):
     gp = povar.Problem.from_synth(ctx, prob, precision=prec)
     lay = gp.layout()
     assert lay["blocked"] and lay["n_slots"] > 0 and lay["n_runs"] >= prob.n_cams
+    # FP64 problems stage their most observed cameras in LDS for the landmark pass
+    if prec == "fp64":
+        assert 0 < lay["n_lds_cams"] <= prob.n_cams
+        if prob.n_cams == 1200:
+            assert lay["n_lds_cams"] < prob.n_cams
+    else:
+        assert lay["n_lds_cams"] == 0
     P, X, f = O.initial_state(prob, prob.cams0)
     lin = O.linearize(P, X, prob)
     for lam, order in ((1e-3, 1), (1e-3, 8)):
