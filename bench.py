@@ -217,11 +217,22 @@ def traffic_from_profiles(kernel: str, workload: str, kernel_hash: str):
     return d["hbm_bytes_per_launch"]
 
 
+def strip_comments(src: str) -> str:
+    """C++ source without comments and with whitespace collapsed (string
+    literals in the kernel sources hold no comment markers)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def kernel_source_hash() -> str:
+    """Hash of the kernel code the counters were taken on (comments and
+    layout of the text do not count)."""
     import hashlib
     h = hashlib.sha256()
     for name in ("povar_kernels.hip", "povar_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2405_05079_amd", "csrc", name), "rb").read())
+        h.update(strip_comments(open(os.path.join(ROOT, "paper_2405_05079_amd", "csrc", name)).read()).encode())
     return h.hexdigest()
 
 

@@ -14,19 +14,23 @@
 // camera / landmark state.
 //
 // Passes (deterministic: no floating-point atomics, fixed reduction orders):
-//   k_landmark_solve   closed-form landmarks (8), V_j^+, b_l, z0 = V^+ b_l, cost (9)
-//   k_linearize        U_i, b_p, sum_k W_k z0 per camera chunk             (10)-(13)
-//   k_camera_prep      damping, tangent projection, 12x12 inverse, x_0    (14),(17),(20)-(29)
-//   k_series_landmark  z_j = V_j^+ sum_k W_k^T x_i                        (17)
-//   k_series_camera    x_i = K_i sum_k W_k z_j, acc_i += x_i              (17)
-//   k_retract          p_i <- (p_i + acc_i) / |p_i + acc_i|               (Sec. 4.3)
-//   k_decide           LM accept / reject and damping update              (Sec. 5.2)
-// Landmark-major passes run one lane per observation over packets of <= 64
-// observations made of whole landmarks, and sum each landmark's lanes with a
-// segmented scan inside the wave.  Camera-major passes run one workgroup per
-// chunk of <= 2048 observations of one camera (8 independent loads per lane);
-// a camera spanning several chunks is finished by the last-arriving workgroup,
-// which adds the chunk partials in chunk order.
+//   k_landmark_solve       closed-form landmarks (8), V_j^+, b_l, z0 = V^+ b_l, cost (9)
+//   k_linearize            U_i, b_p, sum_k W_k z0_j per camera chunk         (10)-(13)
+//   k_camera_prep          damping, tangent projection, 12x12 inverse, x_0  (14),(17),(20)-(29)
+//   k_series_landmark      z_j = V_j^+ sum_k W_k^T x_i                      (17)
+//   k_series_landmark_lds  the same, large FP64 problems, cameras staged in LDS
+//   k_series_camera        x_i = K_i sum_k W_k z_j, acc_i += x_i             (17)
+//   k_series_camera_slots  the same sums for landmark-blocked problems, per run
+//   k_series_camera_combine  adds a camera's partial sums, applies K_i
+//   k_retract              p_i <- (p_i + acc_i) / |p_i + acc_i|             (Sec. 4.3)
+//   k_decide               LM accept / reject and damping update            (Sec. 5.2)
+// Landmark-major passes run one lane per observation over 64-entry packet
+// slots of whole landmarks and sum each landmark's lanes with a segmented
+// scan of DPP lane moves.  The camera-major pass runs one workgroup per chunk
+// of <= 2048 observations of one camera while the landmark records fit one
+// XCD's L2; larger problems use landmark blocks pinned to XCDs, with 64-lane
+// slots of 4 observations per lane and one partial per (camera, block part),
+// which the combine kernel adds per camera in a fixed order.
 #include <hip/hip_ext.h>
 
 #include <mutex>
