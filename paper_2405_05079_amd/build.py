@@ -26,6 +26,9 @@ def hipcc() -> str:
 def flags() -> list[str]:
     return [
         f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+        # multiply-adds fused where the source expression allows, the same way in
+        # every kernel that shares a code path (bitwise-equal results across them)
+        "-ffp-contract=on",
         # packed FP32 instructions stay off (the compiler may not form them)
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", INCLUDE, "-I", CSRC,

@@ -111,3 +111,34 @@ def test_oversized_and_invalid_requests_are_rejected(ctx):
         sv.submit(bad, **OPTS)
     assert e.value.status == povar.EINVAL
     sv.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32_bulk", "fp64"])
+def test_blocked_problems_in_a_mix_equal_single_solves(ctx, prec):
+    """Problems whose camera pass is landmark-blocked (camera slots per XCD,
+    partials per run) batched with small chunked problems: each result is
+    bitwise the same as the problem solved alone (alone, a large FP64 problem
+    also stages cameras in LDS for its landmark pass)."""
+    opts = dict(OPTS, precision=prec, max_iters=4)
+    probs = [synth.make_problem(30, 140000, track=("uniform", 2, 3), seed=801),
+             synth.make_problem(20, 2500, track=("geom", 0.25), seed=802),
+             synth.make_problem(300, 140000, track=("uniform", 2, 3), cam_choice="zipf", seed=803),
+             synth.make_problem(45, 6000, track=("geom", 0.25), seed=804)]
+    print("[case] blocked mix", prec, flush=True)
+    alone = []
+    for p in probs:
+        gp = povar.Problem.from_synth(ctx, p, **opts)
+        alone.append((gp.solve(), gp.cameras(), gp.points(), gp.layout()["blocked"]))
+        gp.close()
+    assert [a[3] for a in alone] == [True, False, True, False]
+    sv = povar.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=4)
+    try:
+        tickets = [sv.submit(p, **opts) for p in probs]
+        res, _ = drain(sv, tickets)
+    finally:
+        sv.close()
+    for t, (rep_a, cams_a, pts_a, _) in zip(tickets, alone):
+        rep, cams, pts, _ = res[t]
+        np.testing.assert_array_equal(cams, cams_a)
+        np.testing.assert_array_equal(pts, pts_a)
+        assert rep["cost_final"] == rep_a["cost_final"]
