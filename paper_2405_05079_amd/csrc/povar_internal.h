@@ -94,7 +94,7 @@ struct DevProblem {
                             // a chunk never spans two cameras
   const int32_t POVAR_GMEM* cam_ch;    // n_p + 1: chunks of camera i are cam_ch[i]..cam_ch[i+1]-1
   const int32_t POVAR_GMEM* mc_cam;    // n_mc cameras whose observations span more than one chunk
-  int32_t n_mc, n_cg;       // multi-chunk cameras; cost groups (kCostGroup packets each)
+  int32_t n_mc, n_cg;       // multi-chunk cameras; cost groups (kCostGroup packets each; 0 up to kCostDirect packets)
 
   // cameras, double-buffered (current / trial): FP64 n_p x 12, and the
   // series record of each camera in the series precision, n_p x s_stride,
@@ -160,6 +160,7 @@ enum UnitKind {
   kNumUnitKinds = 8
 };
 constexpr int kCostGroup = 2048;
+constexpr int kCostDirect = 16384;   // up to this many packets, k_decide adds the packet partials itself
 
 // Blocked series camera pass.
 constexpr int kCsPerLane = 4;                    // observations per lane of a camera slot

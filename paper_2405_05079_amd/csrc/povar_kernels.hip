@@ -23,6 +23,7 @@
 //   k_series_camera_slots  the same sums for landmark-blocked problems, per run
 //   k_series_camera_combine  adds a camera's partial sums, applies K_i
 //   k_retract              p_i <- (p_i + acc_i) / |p_i + acc_i|             (Sec. 4.3)
+//                          (series order 0 only; otherwise in the last camera pass)
 //   k_decide               LM accept / reject and damping update            (Sec. 5.2)
 // Landmark-major passes run one lane per observation over 64-entry packet
 // slots of whole landmarks and sum each landmark's lanes with a segmented
@@ -45,6 +46,11 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
 __device__ __forceinline__ bool find_unit(const Batch& B, int kind, int ug, int& p, int& u) {
   if (ug >= B.total[kind]) return false;
+  if (B.n_prob == 1) {   // a single problem: no table lookup before the first real load
+    p = 0;
+    u = ug;
+    return true;
+  }
   const int32_t* off = B.off[kind];
   int lo = 0, hi = B.n_prob;
   while (hi - lo > 1) {
@@ -503,9 +509,14 @@ __global__ void __launch_bounds__(kBlock) k_cost_groups(Batch B, int trial) {
   if (threadIdx.x == 0) D.cost_group[g] = s;
 }
 
+// Cost of all packets: from the group sums, or, for problems with few
+// packets (no groups), from the packet partials directly.
 __device__ __forceinline__ double packet_cost_sum(const DevProblem& D) {
   double a = 0.0;
-  for (int q = threadIdx.x; q < D.n_cg; q += kBlock) a += D.cost_group[q];
+  if (D.n_cg > 0)
+    for (int q = threadIdx.x; q < D.n_cg; q += kBlock) a += D.cost_group[q];
+  else
+    for (int q = threadIdx.x; q < D.n_pk; q += kBlock) a += D.cost_part[q];
   return block_sum(a);
 }
 
@@ -959,15 +970,37 @@ __global__ void __launch_bounds__(kLdsBlock) k_series_landmark_lds(Batch B, int 
 // --------------------------------------------------------- k_series_camera
 // t_i = sum_k vec((N_k Pbar_i z_j) x~_j^T); x_i = K_i t_i; acc_i += x_i.
 // The camera block is applied in FP64 in both precisions.
+// Retraction of one camera (Sec. 4.3): q = p + acc, p_trial = q / |q| on the
+// sphere (q in Euclidean mode), FP64, into the other camera buffer and the
+// series record.  Value k of the camera in thread k of 12 consecutive lanes.
 template <typename T>
-__device__ __forceinline__ void camera_solve(DevProblem& D, int cam, const T* tv, const double (&kr)[12]) {
+__device__ __forceinline__ void retract_value(DevProblem& D, int cam, int k, double q, double (&qs)[12]) {
+  qs[k] = q;
+  wave_sync();
+  double nrm = 0.0;
+#pragma unroll
+  for (int r = 0; r < 12; ++r) nrm += qs[r] * qs[r];
+  if (D.manifold == 0) q *= 1.0 / sqrt(nrm);
+  const int pc = D.ctl.pcur;
+  (pc ? D.P64[0] : D.P64[1])[(size_t)cam * kCam + k] = q;
+  Prec<T>::S(D, pc ^ 1)[(size_t)cam * D.s_stride + k] = (T)q;
+}
+
+// x_i = K_i t_i in FP64, acc_i += x_i (threads 0..11); after the last order
+// the same threads retract the camera, so no separate pass is needed.
+template <typename T>
+__device__ __forceinline__ void camera_solve(DevProblem& D, int cam, const T* tv, const double (&kr)[12], bool last) {
+  __shared__ double qs[12];
   const int k = threadIdx.x;
   if (k >= 12) return;
   double xr = 0.0;
 #pragma unroll
   for (int c = 0; c < 12; ++c) xr += kr[c] * (double)tv[c];
-  Prec<T>::S(D, D.ctl.pcur)[(size_t)cam * D.s_stride + kSerX + k] = (T)xr;
-  D.acc[(size_t)cam * kCam + k] += xr;
+  const int pc = D.ctl.pcur;
+  Prec<T>::S(D, pc)[(size_t)cam * D.s_stride + kSerX + k] = (T)xr;
+  const double a = D.acc[(size_t)cam * kCam + k] + xr;
+  D.acc[(size_t)cam * kCam + k] = a;
+  if (last) retract_value<T>(D, cam, k, (pc ? D.P64[1] : D.P64[0])[(size_t)cam * kCam + k] + a, qs);
 }
 
 template <typename T>
@@ -1049,7 +1082,7 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
   }
   if (k < 12) tv[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
   __syncthreads();
-  camera_solve<T>(D, cam, tv, kr);
+  camera_solve<T>(D, cam, tv, kr, t == D.ctl.order);
 }
 
 // One wave per camera whose series partials need adding (chunks of a camera
@@ -1083,7 +1116,7 @@ __global__ void __launch_bounds__(kWave) k_series_camera_combine(Batch B, int t)
     if (lane_id() == 0) tv[kk] = r;
   }
   __syncthreads();
-  camera_solve<T>(D, cam, tv, kr);
+  camera_solve<T>(D, cam, tv, kr, t == D.ctl.order);
 }
 
 // --------------------------------------------------- k_series_camera_slots
@@ -1164,7 +1197,7 @@ __global__ void __launch_bounds__(kWave) k_retract(Batch B) {
   int p, w;
   if (!map_wave<kWave>(B, kUnitCamWave, p, w)) return;
   DevProblem& D = B.probs[p];
-  if (D.ctl.done) return;
+  if (D.ctl.done || D.ctl.order > 0) return;   // order >= 1: retracted by the last camera pass
   const int i = w * kWave + lane_id();
   if (i >= D.n_p) return;
   const int pc = D.ctl.pcur;

@@ -448,7 +448,7 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
   for (int32_t i = 0; i < n_p; ++i)
     if (L.cam_ch[i + 1] - L.cam_ch[i] > 1) L.mc_cam.push_back(i);
   L.n_mc = (int32_t)L.mc_cam.size();
-  L.n_cg = (L.n_pk + kCostGroup - 1) / kCostGroup;
+  L.n_cg = L.n_pk > kCostDirect ? (L.n_pk + kCostGroup - 1) / kCostGroup : 0;
   if (!blocked_layout(n_l, fp32)) {
     L.smc = L.mc_cam;
     return POVAR_OK;
@@ -768,7 +768,7 @@ hipError_t enqueue_iteration(povar_problem_s* pb, bool timed) {
   if ((e = launch_linearize(B, pb->fp32, 0, pb->stream)) != hipSuccess) return e;
   if ((e = launch_camera_prep(B, pb->fp32, pb->stream)) != hipSuccess) return e;
   if ((e = enqueue_series(pb, pb->opt.series_order, timed)) != hipSuccess) return e;
-  if ((e = launch_retract(B, pb->fp32, pb->stream)) != hipSuccess) return e;
+  if (pb->opt.series_order == 0 && (e = launch_retract(B, pb->fp32, pb->stream)) != hipSuccess) return e;
   if ((e = launch_landmark_solve(B, 1, pb->stream)) != hipSuccess) return e;
   if ((e = launch_cost_groups(B, 1, pb->stream)) != hipSuccess) return e;
   return launch_decide(B, pb->stream);
@@ -1272,7 +1272,7 @@ povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, do
     HIP_TRY(ctx, launch_series_landmark(B, pb->fp32, t, pb->stream));
     HIP_TRY(ctx, launch_series_camera(B, pb->fp32, t, pb->stream));
   }
-  HIP_TRY(ctx, launch_retract(B, pb->fp32, pb->stream));
+  if (order == 0) HIP_TRY(ctx, launch_retract(B, pb->fp32, pb->stream));
   HIP_TRY(ctx, launch_landmark_solve(B, 1, pb->stream));
   HIP_TRY(ctx, launch_cost_groups(B, 1, pb->stream));
   HIP_TRY(ctx, launch_cost_finalize(B, 1, pb->stream));
