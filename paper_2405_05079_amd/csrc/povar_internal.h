@@ -160,7 +160,7 @@ enum UnitKind {
   kNumUnitKinds = 8
 };
 constexpr int kCostGroup = 2048;
-constexpr int kCostDirect = 16384;   // up to this many packets, k_decide adds the packet partials itself
+constexpr int kCostDirect = 8192;    // up to this many packets, k_decide adds the packet partials itself
 
 // Blocked series camera pass.
 constexpr int kCsPerLane = 4;                    // observations per lane of a camera slot

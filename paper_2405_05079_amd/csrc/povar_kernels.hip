@@ -513,10 +513,21 @@ __global__ void __launch_bounds__(kBlock) k_cost_groups(Batch B, int trial) {
 // packets (no groups), from the packet partials directly.
 __device__ __forceinline__ double packet_cost_sum(const DevProblem& D) {
   double a = 0.0;
-  if (D.n_cg > 0)
+  if (D.n_cg > 0) {
     for (int q = threadIdx.x; q < D.n_cg; q += kBlock) a += D.cost_group[q];
-  else
-    for (int q = threadIdx.x; q < D.n_pk; q += kBlock) a += D.cost_part[q];
+  } else {
+    // eight independent loads per thread per round, added in a fixed order
+    for (int q0 = 0; q0 < D.n_pk; q0 += kBlock * 8) {
+      double v[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int q = q0 + r * kBlock + (int)threadIdx.x;
+        v[r] = q < D.n_pk ? D.cost_part[q] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) a += v[r];
+    }
+  }
   return block_sum(a);
 }
 

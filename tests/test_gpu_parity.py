@@ -150,6 +150,8 @@ def test_blocked_camera_pass(ctx, prec, kw, tol):
     gp = povar.Problem.from_synth(ctx, prob, precision=prec)
     lay = gp.layout()
     assert lay["blocked"] and lay["n_slots"] > 0 and lay["n_runs"] >= prob.n_cams
+    # the footprint from sizes alone bounds the built layout's device bytes
+    assert gp.info()["device_bytes"] <= povar.footprint(prob.n_cams, prob.n_pts, prob.n_obs, prec)
     # FP64 problems stage their most observed cameras in LDS for the landmark pass
     if prec == "fp64":
         assert 0 < lay["n_lds_cams"] <= prob.n_cams
