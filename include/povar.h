@@ -186,6 +186,20 @@ povar_status povar_debug_linearize(povar_problem pb, double* U, double* bp, doub
    cameras, cost_trial the cost after re-solving the landmarks there. */
 povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, double* dp,
                               double* p_trial, double* cost_trial);
+/* Host only, no device needed: builds the device layout of a problem (same
+   arguments as povar_problem_create) and checks it — every observation in
+   exactly one packet entry, one camera-major position and, when the camera
+   pass is landmark-blocked, one camera-slot entry; packet, chunk and slot
+   headers consistent with their entries; run keys contiguous in each slot
+   and run ids inside their camera's range; while every XCD has camera slots
+   left, each slot's landmark block assigned to the XCD its workgroup runs
+   on; the footprint from sizes alone at least the built layout's.  out[0..7] (if non-NULL): blocked, packet slots, chunks, camera
+   slots, runs, landmarks per block, exact device bytes, footprint bound.
+   POVAR_EINVAL with the reason in povar_last_error(NULL) on the first
+   violated property or invalid input. */
+povar_status povar_debug_layout_check(int32_t n_cams, int32_t n_pts, int64_t n_obs, const int32_t* cam_idx,
+                                      const int32_t* pt_idx, const double* meas, int32_t precision,
+                                      int64_t* out);
 
 /* ---- kernel timing for roofline reports --------------------------------- */
 /* enable != 0: subsequent povar_step / povar_enqueue launches bracket every

@@ -12,6 +12,7 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "povar.h"
@@ -454,6 +455,167 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
     return POVAR_OK;
   }
   return build_camera_slots(ctx, L, cstart, fp32);
+}
+
+// Checks the invariants of a built layout that the kernels rely on (the
+// properties are listed with povar_debug_layout_check).
+static povar_status check_layout(const HostLayout& L, const int32_t* cam, const int32_t* pt, const double* meas,
+                                 bool fp32, int64_t* out) {
+  auto fail = [](const char* what, long long a, long long b) {
+    set_error(nullptr, "layout check: %s (%lld, %lld)", what, a, b);
+    return POVAR_EINVAL;
+  };
+  const int32_t n_p = L.n_p, n_l = L.n_l;
+  const int64_t n_obs = L.n_obs;
+  std::vector<int32_t> cam_ext2int(n_p), lm_ext2int(n_l);
+  for (int32_t i = 0; i < n_p; ++i) cam_ext2int[L.cam_int2ext[i]] = i;
+  for (int32_t j = 0; j < n_l; ++j) lm_ext2int[L.int2ext[j]] = j;
+  // each observation as (internal camera, internal landmark, u, v), the
+  // measurement in FP64 and in the bulk precision
+  using Obs = std::tuple<int32_t, int32_t, double, double>;
+  std::vector<Obs> want64(n_obs), want(n_obs);
+  for (int64_t k = 0; k < n_obs; ++k) {
+    const int32_t c = cam_ext2int[cam[k]], j = lm_ext2int[pt[k]];
+    want64[k] = Obs(c, j, meas[2 * k], meas[2 * k + 1]);
+    want[k] = fp32 ? Obs(c, j, (double)(float)meas[2 * k], (double)(float)meas[2 * k + 1]) : want64[k];
+  }
+  std::sort(want64.begin(), want64.end());
+  std::sort(want.begin(), want.end());
+  // landmark-major packets: a slot holds whole landmarks in internal order, or
+  // starts a landmark of more than 64 observations whose continuation slots
+  // carry n = 0 and the same first landmark
+  {
+    if ((int64_t)L.pk_hdr.size() != 2LL * L.n_pk) return fail("packet header count", L.pk_hdr.size(), L.n_pk);
+    std::vector<Obs> got;
+    int32_t next_lm = 0;
+    for (int32_t q = 0; q < L.n_pk;) {
+      const int32_t n = L.pk_hdr[2 * q], lm0 = L.pk_hdr[2 * q + 1];
+      if (n <= 0 || lm0 != next_lm) return fail("packet header", q, n);
+      const int32_t slots = n > kWave ? (n + kWave - 1) / kWave : 1;
+      if (q + slots > L.n_pk) return fail("long landmark past the last slot", q, n);
+      for (int32_t x = 1; x < slots; ++x)
+        if (L.pk_hdr[2 * (q + x)] != 0 || L.pk_hdr[2 * (q + x) + 1] != lm0) return fail("continuation slot", q + x, n);
+      int32_t prev = 0;
+      for (int32_t e = 0; e < n; ++e) {
+        const size_t idx = (size_t)q * kWave + e;
+        const int32_t c = (int32_t)(L.pk_code[idx] & kCamMask), key = (int32_t)(L.pk_code[idx] >> kCamBits);
+        if (key < prev || key > prev + 1 || (e == 0 && key != 0) || (n > kWave && key != 0) || c >= n_p)
+          return fail("packet entry", q, e);
+        prev = key;
+        if (fp32 && (double)L.pk_m32[2 * idx] != (double)(float)L.pk_m64[2 * idx]) return fail("packet FP32 copy", q, e);
+        got.push_back(Obs(c, lm0 + key, L.pk_m64[2 * idx], L.pk_m64[2 * idx + 1]));
+      }
+      next_lm = lm0 + prev + 1;
+      q += slots;
+    }
+    if (next_lm != n_l) return fail("packets do not cover every landmark", next_lm, n_l);
+    std::sort(got.begin(), got.end());
+    if (got != want64) return fail("packets do not hold every observation once", (long long)got.size(), n_obs);
+  }
+  // camera-major chunks: consecutive, at most kChunk observations, one camera each
+  {
+    if ((int64_t)L.cm_lm.size() != n_obs) return fail("camera-major size", L.cm_lm.size(), n_obs);
+    std::vector<Obs> got;
+    int64_t pos = 0;
+    for (int32_t i = 0; i < n_p; ++i) {
+      if (L.cam_ch[i + 1] <= L.cam_ch[i]) return fail("camera without a chunk", i, L.cam_ch[i]);
+      for (int32_t ch = L.cam_ch[i]; ch < L.cam_ch[i + 1]; ++ch) {
+        const int32_t* m = &L.ch_meta[4 * (size_t)ch];
+        if (m[0] != i || m[1] != pos || m[2] <= m[1] || m[2] - m[1] > kChunk || m[3] != L.cam_ch[i + 1] - L.cam_ch[i])
+          return fail("chunk metadata", ch, m[0]);
+        int32_t prev = -1;
+        for (int64_t e = m[1]; e < m[2]; ++e) {
+          if (L.cm_lm[e] < prev) return fail("camera-major landmarks out of order", i, e);
+          prev = L.cm_lm[e];
+          got.push_back(Obs(i, L.cm_lm[e], fp32 ? L.cm_m32[2 * e] : L.cm_m64[2 * e],
+                            fp32 ? L.cm_m32[2 * e + 1] : L.cm_m64[2 * e + 1]));
+        }
+        pos = m[2];
+      }
+    }
+    if (pos != n_obs) return fail("chunks end early", pos, n_obs);
+    std::sort(got.begin(), got.end());
+    if (got != want) return fail("chunks do not hold every observation once", (long long)got.size(), n_obs);
+    int32_t n_mc = 0;
+    for (int32_t i = 0; i < n_p; ++i)
+      if (L.cam_ch[i + 1] - L.cam_ch[i] > 1 && (n_mc >= L.n_mc || L.mc_cam[n_mc++] != i))
+        return fail("multi-chunk camera list", i, n_mc);
+    if (n_mc != L.n_mc) return fail("multi-chunk camera count", n_mc, L.n_mc);
+  }
+  // camera slots of a landmark-blocked problem
+  if (L.blocked) {
+    const int64_t nb = landmark_blocks(n_l, fp32), lb = L.lm_block;
+    if (lb <= 0 || lb * nb < n_l || (int64_t)L.lm_block * kRec * (fp32 ? 4 : 8) > kLmBlockBytes)
+      return fail("landmark block size", lb, nb);
+    if (L.n_cs % (kXcds * kWavesPerBlock) != 0) return fail("camera slots not a multiple of 32", L.n_cs, 0);
+    if ((int32_t)L.run_off.size() != n_p + 1 || L.run_off[0] != 0 || L.run_off[n_p] != L.n_runs)
+      return fail("run offsets", L.run_off.size(), L.n_runs);
+    std::vector<Obs> got;
+    std::vector<int32_t> run_tails(L.n_runs, 0);
+    std::vector<int64_t> slot_block(L.n_cs, -1), per_xcd(kXcds, 0);
+    for (int32_t q = 0; q < L.n_cs; ++q) {
+      const int32_t nl = L.cs_hdr[q];
+      if (nl < 0 || nl > kWave) return fail("slot header", q, nl);
+      int32_t prev_key = -1, prev_code = -1, prev_id = -1;
+      for (int32_t lane = 0; lane < kWave; ++lane) {
+        const size_t li = (size_t)q * kWave + lane;
+        const int32_t code = L.cs_lane[2 * li], id = L.cs_lane[2 * li + 1];
+        if (lane >= nl) {
+          for (int32_t r = 0; r < kCsPerLane; ++r)
+            if (L.cs_lm[((size_t)q * kCsPerLane + r) * kWave + lane] != -1) return fail("entry in an unused lane", q, lane);
+          continue;
+        }
+        const int32_t c = code & (int32_t)kCamMask, key = (int32_t)((uint32_t)code >> kCamBits);
+        if (c >= n_p || id < L.run_off[c] || id >= L.run_off[c + 1]) return fail("run id outside its camera", q, lane);
+        if (code == prev_code ? id != prev_id : key != prev_key + 1) return fail("run keys", q, lane);
+        prev_key = key;
+        prev_code = code;
+        prev_id = id;
+        if (lane == nl - 1 || L.cs_lane[2 * (li + 1)] != code) run_tails[id] += 1;
+        for (int32_t r = 0; r < kCsPerLane; ++r) {
+          const size_t e = ((size_t)q * kCsPerLane + r) * kWave + lane;
+          const int32_t j = L.cs_lm[e];
+          if (j == -1) {
+            if (r == 0) return fail("empty lane inside a run", q, lane);
+            continue;
+          }
+          if (j < 0 || j >= n_l) return fail("slot landmark", q, j);
+          if (slot_block[q] < 0) slot_block[q] = j / lb;
+          if (j / lb != slot_block[q]) return fail("slot spans two landmark blocks", q, j);
+          got.push_back(Obs(c, j, fp32 ? L.cs_m32[2 * e] : L.cs_m64[2 * e], fp32 ? L.cs_m32[2 * e + 1] : L.cs_m64[2 * e + 1]));
+        }
+      }
+      if ((nl > 0) != (slot_block[q] >= 0)) return fail("slot header and entries disagree", q, nl);
+      if (slot_block[q] >= 0) ++per_xcd[xcd_of_block(slot_block[q])];
+    }
+    for (int32_t id = 0; id < L.n_runs; ++id)
+      if (run_tails[id] != 1) return fail("run without exactly one tail lane", id, run_tails[id]);
+    std::sort(got.begin(), got.end());
+    if (got != want) return fail("camera slots do not hold every observation once", (long long)got.size(), n_obs);
+    // workgroup g (slots 4g..4g+3) runs on XCD g % 8: while every XCD has
+    // slots left, rounds of 32 slots give each XCD four slots of its blocks
+    const int64_t rounds = (*std::min_element(per_xcd.begin(), per_xcd.end()) + kWavesPerBlock - 1) / kWavesPerBlock;
+    for (int64_t q = 0; q < rounds * kXcds * kWavesPerBlock; ++q)
+      if (slot_block[q] >= 0 && xcd_of_block(slot_block[q]) != (int)((q / kWavesPerBlock) % kXcds))
+        return fail("slot off its XCD in an aligned round", q, slot_block[q]);
+  }
+  // footprint from sizes alone
+  const size_t exact = layout_footprint(L, fp32);
+  uint64_t bound = 0;
+  if (povar_problem_footprint(n_p, n_l, n_obs, fp32 ? POVAR_PREC_FP32_BULK : POVAR_PREC_FP64, &bound) != POVAR_OK ||
+      exact > bound)
+    return fail("footprint bound below the built layout", (long long)exact, (long long)bound);
+  if (out) {
+    out[0] = L.blocked;
+    out[1] = L.n_pk;
+    out[2] = L.n_ch;
+    out[3] = L.n_cs;
+    out[4] = L.n_runs;
+    out[5] = L.lm_block;
+    out[6] = (int64_t)exact;
+    out[7] = (int64_t)bound;
+  }
+  return POVAR_OK;
 }
 
 }  // namespace povar
@@ -1328,6 +1490,20 @@ povar_status povar_problem_info(povar_problem pb, int64_t* n_obs, int64_t* n_pac
   if (n_chunks) *n_chunks = pb->L.n_ch;
   if (device_bytes) *device_bytes = pb->bytes;
   return POVAR_OK;
+}
+
+povar_status povar_debug_layout_check(int32_t n_cams, int32_t n_pts, int64_t n_obs, const int32_t* cam_idx,
+                                      const int32_t* pt_idx, const double* meas, int32_t precision,
+                                      int64_t* out) {
+  if (precision != POVAR_PREC_FP64 && precision != POVAR_PREC_FP32_BULK) {
+    set_error(nullptr, "precision must be POVAR_PREC_FP64 or POVAR_PREC_FP32_BULK");
+    return POVAR_EINVAL;
+  }
+  const bool fp32 = precision == POVAR_PREC_FP32_BULK;
+  HostLayout L;
+  const povar_status st = build_layout(nullptr, n_cams, n_pts, n_obs, cam_idx, pt_idx, meas, fp32, L);
+  if (st != POVAR_OK) return st;
+  return check_layout(L, cam_idx, pt_idx, meas, fp32, out);
 }
 
 povar_status povar_problem_layout(povar_problem pb, int32_t* blocked, int32_t* lm_block, int64_t* n_slots,

@@ -29,7 +29,7 @@ EXPORTS = [
     "povar_problem_footprint", "povar_problem_create", "povar_problem_create_device",
     "povar_problem_destroy", "povar_solve", "povar_step", "povar_enqueue", "povar_get_report",
     "povar_get_cameras", "povar_get_points", "povar_get_trace", "povar_get_state", "povar_set_state",
-    "povar_debug_linearize", "povar_debug_step", "povar_kernel_timing", "povar_kernel_times",
+    "povar_debug_linearize", "povar_debug_step", "povar_debug_layout_check", "povar_kernel_timing", "povar_kernel_times",
     "povar_problem_info", "povar_problem_layout", "povar_server_create", "povar_server_submit", "povar_server_poll",
     "povar_server_stats", "povar_server_destroy",
 ]
@@ -96,6 +96,7 @@ def lib() -> C.CDLL:
         "povar_set_state": (C.c_int, [_P, _P, C.c_double, C.c_int32]),
         "povar_debug_linearize": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _DP]),
         "povar_debug_step": (C.c_int, [_P, C.c_double, C.c_int32, _P, _P, _DP]),
+        "povar_debug_layout_check": (C.c_int, [C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, C.c_int32, _I64P]),
         "povar_kernel_timing": (C.c_int, [_P, C.c_int32]),
         "povar_kernel_times": (C.c_int, [_P, _DP, _I64P, _DP, _I64P]),
         "povar_problem_info": (C.c_int, [_P, _I64P, _I64P, _I32P, _U64P]),
@@ -129,6 +130,24 @@ def make_options(eta=0.01, order=20, max_iters=50, ftol=1e-6, lambda0=1e-4, lamb
     o.manifold = MANIFOLD[manifold] if isinstance(manifold, str) else int(manifold)
     o.use_graph = 1 if use_graph else 0
     return o
+
+
+def layout_check(cam_idx: np.ndarray, pt_idx: np.ndarray, meas: np.ndarray, n_cams: int, n_pts: int,
+                 precision="fp32_bulk") -> dict:
+    """Build a problem's device layout on the host and check its invariants
+    (``povar_debug_layout_check``; no device needed).  Raises PovarError with
+    the violated property."""
+    cam = np.ascontiguousarray(cam_idx, dtype=np.int32)
+    pt = np.ascontiguousarray(pt_idx, dtype=np.int32)
+    m = np.ascontiguousarray(meas, dtype=np.float64).reshape(-1, 2)
+    assert cam.shape[0] == pt.shape[0] == m.shape[0]
+    out = (C.c_int64 * 8)()
+    st = lib().povar_debug_layout_check(n_cams, n_pts, cam.shape[0], _ptr(cam), _ptr(pt), _ptr(m),
+                                        PRECISION[precision], out)
+    if st != OK:
+        raise PovarError(st, lib().povar_last_error(None).decode())
+    keys = ("blocked", "n_packets", "n_chunks", "n_slots", "n_runs", "lm_block", "device_bytes", "footprint")
+    return dict(zip(keys, (int(v) for v in out)))
 
 
 def footprint(n_cams: int, n_pts: int, n_obs: int, precision="fp32_bulk") -> int:

@@ -64,3 +64,57 @@ def test_context_without_gpu_reports_device_error():
     st = povar.lib().povar_ctx_create(0, None, C.byref(h))
     assert st == povar.EDEVICE
     assert b"device" in povar.lib().povar_last_error(None).lower()
+
+
+# Layout shapes for the host-side layout check: small problems, landmarks with
+# more than 64 observations (continuation packet slots), cameras with more than
+# one chunk, and landmark-blocked camera passes in both precisions, with uniform
+# and Zipf-weighted camera choice.
+LAYOUT_CASES = [
+    ("small", dict(n_cams=20, n_pts=500, track=("uniform", 4, 8)), "fp64", 0),
+    ("long-tracks", dict(n_cams=150, n_pts=300, track=("uniform", 70, 140)), "fp64", 0),
+    ("two-cameras", dict(n_cams=2, n_pts=3000, track=("uniform", 1, 2)), "fp32_bulk", 0),
+    ("blocked-fp64", dict(n_cams=40, n_pts=70_000, track=("geom", 0.25)), "fp64", 1),
+    ("blocked-fp64-zipf", dict(n_cams=1200, n_pts=70_000, track=("geom", 0.25), cam_choice="zipf"), "fp64", 1),
+    ("blocked-fp32-6cam", dict(n_cams=6, n_pts=140_000, track=("uniform", 2, 3)), "fp32_bulk", 1),
+    ("blocked-fp32-zipf", dict(n_cams=300, n_pts=140_000, track=("uniform", 2, 3), cam_choice="zipf"),
+     "fp32_bulk", 1),
+]
+
+
+@pytest.mark.parametrize("name,kw,prec,blocked", LAYOUT_CASES, ids=[c[0] for c in LAYOUT_CASES])
+def test_layout_invariants(name, kw, prec, blocked):
+    from paper_2405_05079_amd import synth
+    p = synth.make_problem(seed=7, **kw)
+    r = povar.layout_check(p.cam_idx, p.pt_idx, p.meas, p.n_cams, p.n_pts, prec)
+    assert r["blocked"] == blocked
+    assert 0 < r["device_bytes"] <= r["footprint"]
+    if blocked:
+        assert r["n_slots"] % 32 == 0 and r["n_runs"] >= p.n_cams
+        rec_bytes = 8 * (4 if prec == "fp32_bulk" else 8)
+        assert r["lm_block"] * rec_bytes <= 2 << 20
+
+
+@pytest.mark.parametrize("prec,limit", [("fp64", 65_536), ("fp32_bulk", 131_072)])
+def test_blocking_starts_where_the_records_outgrow_half_the_l2(prec, limit):
+    # landmark records of 8 values: the camera pass is blocked once they pass 4 MiB
+    from paper_2405_05079_amd import synth
+    for n_pts, want in ((limit, 0), (limit + 1, 1)):
+        p = synth.make_problem(n_cams=8, n_pts=n_pts, track=("uniform", 2, 2), seed=3)
+        assert povar.layout_check(p.cam_idx, p.pt_idx, p.meas, p.n_cams, p.n_pts, prec)["blocked"] == want
+
+
+def test_layout_check_rejects_invalid_problems():
+    import numpy as np
+    cam = np.array([0, 1, 0], np.int32)
+    pt = np.array([0, 0, 1], np.int32)
+    meas = np.zeros((3, 2))
+    with pytest.raises(povar.PovarError, match="camera 2 has no observation"):
+        povar.layout_check(cam, pt, meas, 3, 2, "fp64")
+    with pytest.raises(povar.PovarError, match="out of range"):
+        povar.layout_check(cam, pt, meas, 2, 1, "fp64")
+    bad = meas.copy()
+    bad[1, 0] = np.nan
+    with pytest.raises(povar.PovarError, match="non-finite"):
+        povar.layout_check(cam, pt, bad, 2, 2, "fp64")
+    assert povar.layout_check(cam, pt, meas, 2, 2, "fp64")["n_packets"] == 1
