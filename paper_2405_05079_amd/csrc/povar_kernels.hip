@@ -708,6 +708,7 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
   // Cholesky U_l = L L^T in place (Marquardt damping keeps the diagonally
   // scaled block well conditioned; Cholesky is insensitive to that scaling)
   bool ok = true;
+  double rd[12];   // reciprocals of the diagonal of L
 #pragma unroll
   for (int j = 0; j < 12; ++j) {
     double d = L[tri(j, j)];
@@ -716,25 +717,26 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
     if (!(d > 0.0)) { ok = false; d = 1.0; }
     d = sqrt(d);
     L[tri(j, j)] = d;
-    const double inv = 1.0 / d;
+    rd[j] = 1.0 / d;
 #pragma unroll
     for (int r = j + 1; r < 12; ++r) {
       double v = L[tri(r, j)];
 #pragma unroll
       for (int k = 0; k < j; ++k) v -= L[tri(r, k)] * L[tri(j, k)];
-      L[tri(r, j)] = v * inv;
+      L[tri(r, j)] = v * rd[j];
     }
   }
-  // L^-1 in place, column by column, rows ascending
+  // L^-1 in place, column by column, rows ascending; the one reciprocal per
+  // row replaces a division per entry (which dominates this lane's chain)
 #pragma unroll
   for (int j = 0; j < 12; ++j) {
-    L[tri(j, j)] = 1.0 / L[tri(j, j)];
+    L[tri(j, j)] = rd[j];
 #pragma unroll
     for (int r = j + 1; r < 12; ++r) {
       double v = 0.0;
 #pragma unroll
       for (int k = j; k < r; ++k) v += L[tri(r, k)] * L[tri(k, j)];
-      L[tri(r, j)] = -v / L[tri(r, r)];
+      L[tri(r, j)] = -v * rd[r];
     }
   }
   // sphere: w = U_l^-1 p, h = p^T U_l^-1 p
