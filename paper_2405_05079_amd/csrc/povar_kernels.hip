@@ -147,13 +147,22 @@ __device__ __forceinline__ uint32_t seg_links(int key) {
   return l;
 }
 
+// 32-bit values: an add with the lane move folded in, and a select.  64-bit
+// values: v += f * t with f = 1 (take) or 0, one multiply-add instead of an
+// add and two 32-bit selects; for finite t the result is v + t or v exactly.
 template <int Ctrl, int RowMask, int N, typename T>
 __device__ __forceinline__ void seg_step(T (&v)[N], bool take) {
   T t[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) t[k] = dpp<Ctrl, RowMask>(T(0), v[k]);
+  if constexpr (sizeof(T) == 4) {
 #pragma unroll
-  for (int k = 0; k < N; ++k) v[k] = take ? v[k] + t[k] : v[k];
+    for (int k = 0; k < N; ++k) v[k] = take ? v[k] + t[k] : v[k];
+  } else {
+    const T f = take ? T(1) : T(0);
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = __builtin_fma(t[k], f, v[k]);
+  }
 }
 
 template <int N, typename T>
@@ -296,15 +305,17 @@ __device__ __forceinline__ void sym3_pinv(const double (&v)[6], double (&out)[6]
     const double thr = 1e-3 * maxd;
     const double d0 = v[0];
     if (d0 > thr) {
-      const double l10 = v[1] / d0, l20 = v[2] / d0;
+      const double i0 = 1.0 / d0;
+      const double l10 = v[1] * i0, l20 = v[2] * i0;
       const double d1 = v[3] - l10 * v[1];
       if (d1 > thr) {
+        const double i1 = 1.0 / d1;
         const double e12 = v[4] - l20 * v[1];
-        const double l21 = e12 / d1;
+        const double l21 = e12 * i1;
         const double d2 = v[5] - l20 * v[2] - l21 * e12;
         if (d2 > thr) {
           const double a10 = -l10, a21 = -l21, a20 = l10 * l21 - l20;
-          const double i0 = 1.0 / d0, i1 = 1.0 / d1, i2 = 1.0 / d2;
+          const double i2 = 1.0 / d2;
           out[0] = i0 + a10 * a10 * i1 + a20 * a20 * i2;
           out[1] = a10 * i1 + a20 * a21 * i2;
           out[2] = a20 * i2;
