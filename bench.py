@@ -346,7 +346,10 @@ def main():
     ms_c = kt["ms_camera_pass"] / max(1, kt["n_camera_pass"])
     bl, bc = series_bytes(prob.n_obs, prob.n_pts, prob.n_cams, True)
     if ms_l >= ms_c:
-        name, ms, byt = "k_series_landmark<float>", ms_l, bl
+        # FP32 camera records of 128 bytes (more than 341 cameras) go through the
+        # cooperative landmark pass
+        coop = prob.n_cams * 96 > 32768
+        name, ms, byt = ("k_series_landmark_coop" if coop else "k_series_landmark<float>"), ms_l, bl
     elif fp32["layout"]["blocked"]:
         name, ms, byt = "k_series_camera_slots<float>", ms_c, bc
     else:

@@ -18,8 +18,10 @@ namespace povar {
 // host sees plain pointers of the same size and value.
 #if defined(__HIP_DEVICE_COMPILE__)
 #define POVAR_GMEM __attribute__((address_space(1)))
+#define POVAR_LDS __attribute__((address_space(3)))
 #else
 #define POVAR_GMEM
+#define POVAR_LDS
 #endif
 
 constexpr int kWave = 64;                 // CDNA wavefront
@@ -177,13 +179,19 @@ __host__ __device__ constexpr bool blocked_layout(long long n_l, bool fp32) {
 // prefix table of units per problem (n_prob + 1 entries each).
 struct Batch {
   DevProblem POVAR_GMEM* probs;
-  const int32_t POVAR_GMEM* off[kNumUnitKinds];
-  int32_t n_prob;
+  // prefix table of unit kind k: tables + k * tab_stride (n_prob + 1 entries)
+  const int32_t POVAR_GMEM* tables;
+  int32_t n_prob, tab_stride;
   int32_t total[kNumUnitKinds];
   // single large problem: the landmark pass runs as lds_grid persistent
   // workgroups with lds_bytes of staged camera data (0: the plain pass)
   int32_t lds_bytes, lds_grid;
+  // 1: FP32 problems of the batch with 128-byte camera records gather them
+  // cooperatively in the landmark pass (which then has kCoopLdsBytes of LDS)
+  int32_t coop_cams, pad;
 };
+constexpr int kCoopPieces = 6;   // 16-byte pieces of an FP32 camera series record read by the landmark pass
+constexpr int kCoopLdsBytes = kBlock / kWave * kCoopPieces * kWave * 16;
 
 constexpr int kLdsCamVals = 21;   // staged camera values: x (12), Pbar (9)
 constexpr int kLdsBlock = 1024;   // threads of a staged landmark-pass workgroup

@@ -19,6 +19,8 @@
 //   k_camera_prep          damping, tangent projection, 12x12 inverse, x_0  (14),(17),(20)-(29)
 //   k_series_landmark      z_j = V_j^+ sum_k W_k^T x_i                      (17)
 //   k_series_landmark_lds  the same, large FP64 problems, cameras staged in LDS
+//   k_series_landmark_coop the same, FP32 problems with many cameras, camera
+//                          records fetched by whole waves
 //   k_series_camera        x_i = K_i sum_k W_k z_j, acc_i += x_i             (17)
 //   k_series_camera_slots  the same sums for landmark-blocked problems, per run
 //   k_series_camera_combine  adds a camera's partial sums, applies K_i
@@ -51,7 +53,7 @@ __device__ __forceinline__ bool find_unit(const Batch& B, int kind, int ug, int&
     u = ug;
     return true;
   }
-  const int32_t* off = B.off[kind];
+  const int32_t* off = B.tables + (size_t)kind * B.tab_stride;
   int lo = 0, hi = B.n_prob;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
@@ -99,6 +101,37 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 16 bytes as a native vector (plain loads and stores in any address space)
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Wave-cooperative gather of one record of NP 16-byte pieces per lane (record
+// src of `base`, stride in bytes; a lane with src < 0 receives record 0, which
+// it must not use).  Piece k of the wave's
+// 64 NP pieces is loaded by lane k % 64 in instruction k / 64 and belongs to
+// lane k / NP, so the lanes of one load instruction read consecutive pieces
+// of a few records (a cache line serves several lanes) instead of one piece
+// of 64 records (up to 64 lines, each one lookup in the vector L1); the
+// pieces then go to their lanes through `buf` (64 NP pieces of this wave).
+// All 64 lanes call it.
+template <int NP>
+__device__ __forceinline__ void coop_fetch(const char POVAR_GMEM* base, size_t stride, int src,
+                                           f4v POVAR_LDS* buf, f4v (&out)[NP]) {
+  const int lane = lane_id();
+  f4v piece[NP];
+#pragma unroll
+  for (int r = 0; r < NP; ++r) {
+    const int k = r * kWave + lane, o = k / NP, part = k - o * NP;
+    const int so = max(__shfl(src, o), 0);
+    piece[r] = *(const f4v POVAR_GMEM*)(base + (size_t)so * stride + (size_t)part * 16);
+  }
+#pragma unroll
+  for (int r = 0; r < NP; ++r) buf[r * kWave + lane] = piece[r];
+  wave_sync();
+#pragma unroll
+  for (int k = 0; k < NP; ++k) out[k] = buf[lane * NP + k];
+  wave_sync();
 }
 
 // Value of lane l (a uniform result); the builtin moves 32-bit words.
@@ -829,7 +862,6 @@ struct CamFromRecords {
 
 // ... or, for the n_hot most observed cameras, from a table in LDS
 // (kLdsCamVals values per camera: x, then Pbar row-major).
-#define POVAR_LDS __attribute__((address_space(3)))
 template <typename T>
 struct CamFromLds {
   const T POVAR_LDS* tab;
@@ -871,9 +903,9 @@ __device__ __forceinline__ SlotHead<T> slot_head(const DevProblem& D, int q) {
 // One packet slot of the landmark pass: z_j = V_j^+ sum_k Pbar_i^T N_k (X_i x~_j),
 // X_i = x_i as a 3x4 matrix; the (z_j, X_j) record is written for the camera
 // pass.  Wave-uniform; all 64 lanes call it.
-template <typename T, typename Cam>
+template <typename T, typename Cam, bool Coop = false>
 __device__ __forceinline__ void landmark_slot(const DevProblem& D, int q, const SlotHead<T>& head, int lc,
-                                              const Cam& cam) {
+                                              const Cam& cam, f4v POVAR_LDS* cbuf = nullptr) {
   const int lane = lane_id();
   const int off = q * kWave;
   const T* __restrict__ rec = Prec<T>::rec(D, lc);
@@ -890,18 +922,41 @@ __device__ __forceinline__ void landmark_slot(const DevProblem& D, int q, const 
     const bool tail = act && run_tail(key);
     T y0 = 0, y1 = 0, y2 = 0, X0 = 0, X1 = 0, X2 = 0, one;
     double v[8];
+    T xc[12], Pc[12];
+    if constexpr (Coop) {
+      // V^+ and X are requested before the cooperative camera gather
+      if (act) {
+        if (tail) {
+          const double* vp = (lc ? D.Vp64[1] : D.Vp64[0]) + (size_t)(lm0 + key) * kLmSym;
+          load4(vp, v[0], v[1], v[2], v[3]);
+          load4(vp + 4, v[4], v[5], v[6], v[7]);
+        }
+        load4(rec + (size_t)(lm0 + key) * kRec + 4, X0, X1, X2, one);
+      }
+      f4v pc[kCoopPieces];
+      coop_fetch<kCoopPieces>((const char POVAR_GMEM*)cam.S, (size_t)cam.stride * sizeof(T),
+                    act ? (int)(code & kCamMask) : -1, cbuf, pc);
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          Pc[4 * r + k] = pc[r][k];
+          xc[4 * r + k] = pc[3 + r][k];
+        }
+    }
     if (act) {
       const int c = (int)(code & kCamMask);
-      // the tail lane fetches V^+ together with the gathers
-      if (tail) {
-        const double* vp = (lc ? D.Vp64[1] : D.Vp64[0]) + (size_t)(lm0 + key) * kLmSym;
-        load4(vp, v[0], v[1], v[2], v[3]);
-        load4(vp + 4, v[4], v[5], v[6], v[7]);
+      if constexpr (!Coop) {
+        // the tail lane fetches V^+ together with the gathers
+        if (tail) {
+          const double* vp = (lc ? D.Vp64[1] : D.Vp64[0]) + (size_t)(lm0 + key) * kLmSym;
+          load4(vp, v[0], v[1], v[2], v[3]);
+          load4(vp + 4, v[4], v[5], v[6], v[7]);
+        }
+        load4(rec + (size_t)(lm0 + key) * kRec + 4, X0, X1, X2, one);
+        cam(c, xc, Pc);
       }
       const auto m = mraw;
-      load4(rec + (size_t)(lm0 + key) * kRec + 4, X0, X1, X2, one);
-      T xc[12], Pc[12];
-      cam(c, xc, Pc);
       const T q0 = xc[0] * X0 + xc[1] * X1 + xc[2] * X2 + xc[3];
       const T q1 = xc[4] * X0 + xc[5] * X1 + xc[6] * X2 + xc[7];
       const T q2 = xc[8] * X0 + xc[9] * X1 + xc[10] * X2 + xc[11];
@@ -951,6 +1006,24 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
   if (D.ctl.done || t > D.ctl.order) return;
   const CamFromRecords<T> cam{Prec<T>::S(D, D.ctl.pcur), D.s_stride};
   landmark_slot<T>(D, q, slot_head<T>(D, q), D.ctl.lcur, cam);
+}
+
+// FP32 landmark pass of batches holding problems with 128-byte camera records
+// (too many cameras for the vector L1): those problems fetch the records
+// cooperatively, through kCoopLdsBytes of dynamic LDS; the others per lane.
+__global__ void __launch_bounds__(kBlock) k_series_landmark_coop(Batch B, int t) {
+  int p, q;
+  if (!map_wave(B, kUnitPacket, p, q)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done || t > D.ctl.order) return;
+  const CamFromRecords<float> cam{Prec<float>::S(D, D.ctl.pcur), D.s_stride};
+  if (D.s_stride == kSerLine) {
+    extern __shared__ f4v coop_lds[];
+    f4v POVAR_LDS* buf = (f4v POVAR_LDS*)coop_lds + (threadIdx.x >> 6) * (kCoopPieces * kWave);
+    landmark_slot<float, CamFromRecords<float>, true>(D, q, slot_head<float>(D, q), D.ctl.lcur, cam, buf);
+  } else {
+    landmark_slot<float>(D, q, slot_head<float>(D, q), D.ctl.lcur, cam);
+  }
 }
 
 // Landmark pass of a single large problem: one persistent workgroup of
@@ -1350,7 +1423,9 @@ hipError_t launch_series_landmark(const Batch& b, bool fp32, int t, hipStream_t 
     return hipGetLastError();
   }
   const dim3 g = blocks_for(b.total[kUnitPacket], kWavesPerBlock);
-  if (fp32) hipExtLaunchKernelGGL(k_series_landmark<float>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
+  if (fp32 && b.coop_cams)
+    hipExtLaunchKernelGGL(k_series_landmark_coop, g, dim3(kBlock), kCoopLdsBytes, s, ev0, ev1, 0, b, t);
+  else if (fp32) hipExtLaunchKernelGGL(k_series_landmark<float>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
   else hipExtLaunchKernelGGL(k_series_landmark<double>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
   return hipGetLastError();
 }

@@ -872,13 +872,14 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
     HIP_TRY(ctx, hipMemcpyAsync(rec_dev, &R, sizeof(R), hipMemcpyHostToDevice, stream));
     B.probs = rec_dev;
   }
-  for (int k = 0; k < kNumUnitKinds; ++k) {
-    B.off[k] = (const int32_t*)dp(A.tables) + 2 * k;
-    B.total[k] = units[k];
-  }
+  B.tables = (const int32_t*)dp(A.tables);
+  B.tab_stride = 2;
+  for (int k = 0; k < kNumUnitKinds; ++k) B.total[k] = units[k];
   B.n_prob = 1;
   B.lds_bytes = lds_bytes;
   B.lds_grid = lds_grid;
+  B.coop_cams = pb->fp32 && R.s_stride == kSerLine ? 1 : 0;
+  B.pad = 0;
   // initial landmarks and cost, Eq. (8)-(9)
   HIP_TRY(ctx, launch_landmark_solve(B, 0, stream));
   HIP_TRY(ctx, launch_cost_groups(B, 0, stream));

@@ -100,9 +100,15 @@ def test_camera_step_fp64(ctx, kw, lam, order, manifold):
     gp.close()
 
 
+# 400 cameras: camera records of 128 bytes (more than the vector L1 holds
+# packed), which the landmark pass gathers cooperatively
+FP32_STEP = [CASES[1], dict(n_cams=400, n_pts=8000, track=("uniform", 3, 6), seed=36)]
+
+
+@pytest.mark.parametrize("kw", FP32_STEP)
 @pytest.mark.parametrize("lam,order", [(1e-4, 10), (1.0, 20)])
-def test_camera_step_fp32_bulk(ctx, lam, order):
-    prob = case(**CASES[1])
+def test_camera_step_fp32_bulk(ctx, lam, order, kw):
+    prob = case(**kw)
     say("step fp32", lam, order)
     gp = povar.Problem.from_synth(ctx, prob, precision="fp32_bulk")
     dp, pt, ct = gp.debug_step(lam, order)
@@ -140,6 +146,8 @@ BLOCKED = [
     ("fp32_bulk", dict(n_cams=6, n_pts=140000, track=("uniform", 2, 2), seed=32), 2e-3),
     # heavy-tailed views per camera
     ("fp32_bulk", dict(n_cams=300, n_pts=140000, track=("uniform", 2, 3), cam_choice="zipf", seed=33), 2e-3),
+    # 128-byte camera records, gathered cooperatively by the landmark pass
+    ("fp32_bulk", dict(n_cams=400, n_pts=140000, track=("uniform", 2, 3), seed=35), 2e-3),
 ]
 
 

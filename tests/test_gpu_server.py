@@ -118,11 +118,12 @@ def test_blocked_problems_in_a_mix_equal_single_solves(ctx, prec):
     """Problems whose camera pass is landmark-blocked (camera slots per XCD,
     partials per run) batched with small chunked problems: each result is
     bitwise the same as the problem solved alone (alone, a large FP64 problem
-    also stages cameras in LDS for its landmark pass)."""
+    also stages cameras in LDS for its landmark pass; the 400-camera problem
+    has 128-byte camera records, gathered cooperatively in FP32)."""
     opts = dict(OPTS, precision=prec, max_iters=4)
     probs = [synth.make_problem(30, 140000, track=("uniform", 2, 3), seed=801),
              synth.make_problem(20, 2500, track=("geom", 0.25), seed=802),
-             synth.make_problem(300, 140000, track=("uniform", 2, 3), cam_choice="zipf", seed=803),
+             synth.make_problem(400, 140000, track=("uniform", 2, 3), cam_choice="zipf", seed=803),
              synth.make_problem(45, 6000, track=("geom", 0.25), seed=804)]
     print("[case] blocked mix", prec, flush=True)
     alone = []
