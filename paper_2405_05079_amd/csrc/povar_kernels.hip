@@ -106,32 +106,37 @@ __device__ __forceinline__ void wave_sync() {
 // 16 bytes as a native vector (plain loads and stores in any address space)
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-// Wave-cooperative gather of one record of NP 16-byte pieces per lane (record
-// src of `base`, stride in bytes; a lane with src < 0 receives record 0, which
-// it must not use).  Piece k of the wave's
-// 64 NP pieces is loaded by lane k % 64 in instruction k / 64 and belongs to
-// lane k / NP, so the lanes of one load instruction read consecutive pieces
-// of a few records (a cache line serves several lanes) instead of one piece
-// of 64 records (up to 64 lines, each one lookup in the vector L1); the
-// pieces then go to their lanes through `buf` (64 NP pieces of this wave).
-// All 64 lanes call it.
-template <int NP>
-__device__ __forceinline__ void coop_fetch(const char POVAR_GMEM* base, size_t stride, int src,
-                                           f4v POVAR_LDS* buf, f4v (&out)[NP]) {
+// Wave-cooperative gather of R records of NP 16-byte pieces per lane (record
+// src[r] of `base`, stride in bytes; a lane with src[r] < 0 receives record 0
+// there, which it must not use).  For each r, piece k of the wave's 64 NP
+// pieces is loaded by lane k % 64 and belongs to lane k / NP, so the lanes of
+// one load instruction read consecutive pieces of a few records (a cache line
+// serves several lanes) instead of one piece of 64 records (up to 64 lines,
+// each one lookup in the vector L1).  All loads are issued first; the pieces
+// then go to their lanes through `buf` (64 NP pieces of this wave), one r at
+// a time.  All 64 lanes call it.
+template <int NP, int R = 1>
+__device__ __forceinline__ void coop_fetch(const char POVAR_GMEM* base, size_t stride, const int (&src)[R],
+                                           f4v POVAR_LDS* buf, f4v (&out)[R][NP]) {
   const int lane = lane_id();
-  f4v piece[NP];
+  f4v piece[R][NP];
 #pragma unroll
-  for (int r = 0; r < NP; ++r) {
-    const int k = r * kWave + lane, o = k / NP, part = k - o * NP;
-    const int so = max(__shfl(src, o), 0);
-    piece[r] = *(const f4v POVAR_GMEM*)(base + (size_t)so * stride + (size_t)part * 16);
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int k = i * kWave + lane, o = k / NP, part = k - o * NP;
+      const int so = max(__shfl(src[r], o), 0);
+      piece[r][i] = *(const f4v POVAR_GMEM*)(base + (size_t)so * stride + (size_t)part * 16);
+    }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) buf[i * kWave + lane] = piece[r][i];
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < NP; ++k) out[r][k] = buf[lane * NP + k];
+    wave_sync();
   }
-#pragma unroll
-  for (int r = 0; r < NP; ++r) buf[r * kWave + lane] = piece[r];
-  wave_sync();
-#pragma unroll
-  for (int k = 0; k < NP; ++k) out[k] = buf[lane * NP + k];
-  wave_sync();
 }
 
 // Value of lane l (a uniform result); the builtin moves 32-bit words.
@@ -933,15 +938,15 @@ __device__ __forceinline__ void landmark_slot(const DevProblem& D, int q, const 
         }
         load4(rec + (size_t)(lm0 + key) * kRec + 4, X0, X1, X2, one);
       }
-      f4v pc[kCoopPieces];
-      coop_fetch<kCoopPieces>((const char POVAR_GMEM*)cam.S, (size_t)cam.stride * sizeof(T),
-                    act ? (int)(code & kCamMask) : -1, cbuf, pc);
+      f4v pc[1][kCoopPieces];
+      const int src[1] = {act ? (int)(code & kCamMask) : -1};
+      coop_fetch<kCoopPieces>((const char POVAR_GMEM*)cam.S, (size_t)cam.stride * sizeof(T), src, cbuf, pc);
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          Pc[4 * r + k] = pc[r][k];
-          xc[4 * r + k] = pc[3 + r][k];
+          Pc[4 * r + k] = pc[0][r][k];
+          xc[4 * r + k] = pc[0][3 + r][k];
         }
     }
     if (act) {
@@ -1251,11 +1256,26 @@ __global__ void __launch_bounds__(kBlock) k_series_camera_slots(Batch B, int t) 
     for (int k = 0; k < 12; ++k) Pc[k] = 0;
   const T* __restrict__ zx = static_cast<const T*>(D.zx);
   T z[kCsPerLane][4], x[kCsPerLane][4];
+  if constexpr (sizeof(T) == 4) {
+    // the 32-byte records fetched by pairs of lanes (half the L1 lookups)
+    __shared__ f4v cbuf[kWavesPerBlock][2 * kWave];
+    f4v rz[kCsPerLane][2];
+    coop_fetch<2, kCsPerLane>((const char POVAR_GMEM*)zx, kRec * sizeof(T), jr,
+                              (f4v POVAR_LDS*)cbuf[threadIdx.x >> 6], rz);
 #pragma unroll
-  for (int r = 0; r < kCsPerLane; ++r) {
-    if (jr[r] >= 0) {
-      load4(zx + (size_t)jr[r] * kRec, z[r][0], z[r][1], z[r][2], z[r][3]);
-      load4(zx + (size_t)jr[r] * kRec + 4, x[r][0], x[r][1], x[r][2], x[r][3]);
+    for (int r = 0; r < kCsPerLane; ++r)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        z[r][k] = rz[r][0][k];
+        x[r][k] = rz[r][1][k];
+      }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kCsPerLane; ++r) {
+      if (jr[r] >= 0) {
+        load4(zx + (size_t)jr[r] * kRec, z[r][0], z[r][1], z[r][2], z[r][3]);
+        load4(zx + (size_t)jr[r] * kRec + 4, x[r][0], x[r][1], x[r][2], x[r][3]);
+      }
     }
   }
   const T a = (T)(1.0 - D.eta);
