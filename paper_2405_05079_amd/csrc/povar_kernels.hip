@@ -166,6 +166,77 @@ __device__ __forceinline__ T wave_sum(T v) {
   return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
+// Reduce-scatter of N values (N a power of two, 2 <= N <= 64) over the wave:
+// afterwards lane l holds the wave total of value rs_index<N>(l), each value
+// in 64 / N lanes, for about N lane moves per lane instead of the 8 N of N
+// separate wave sums.  Step s pairs the lanes that differ in lane bit s (bits
+// 0..3 by lane moves: xor 1, xor 2, the half-row and the row mirror; bits 4, 5
+// by ds_bpermute: xor 16, xor 32); while values remain to be split, each lane
+// keeps one half and adds its partner's copy of it.  The half kept at step s
+// is chosen by k_s = b0^b2, b1^b2, b2^b3, b3, b4, b5 (b = lane bits): the two
+// lanes of a pair differ in it, and the partners of every later step (the
+// mirrors flip all lower bits) agree on it, so they hold the same values.
+// Once one value is left, the remaining steps add the partners' copies.  The
+// order is fixed: bitwise repeatable.
+__device__ __forceinline__ int rs_keep(int lane, int s) {
+  const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+  switch (s) {
+    case 0: return b0 ^ b2;
+    case 1: return b1 ^ b2;
+    case 2: return b2 ^ b3;
+    case 3: return b3;
+    default: return (lane >> s) & 1;
+  }
+}
+
+template <int N>
+__device__ __forceinline__ int rs_index(int lane) {
+  int idx = 0;
+#pragma unroll
+  for (int s = 0, w = N >> 1; w > 0; ++s, w >>= 1) idx += rs_keep(lane, s) * w;
+  return idx;
+}
+
+template <int S, typename T>
+__device__ __forceinline__ T rs_partner(T v) {
+  if constexpr (S == 0) return dpp<kDppXor1>(v, v);
+  else if constexpr (S == 1) return dpp<kDppXor2>(v, v);
+  else if constexpr (S == 2) return dpp<kDppHalfMirror>(v, v);
+  else if constexpr (S == 3) return dpp<kDppMirror>(v, v);
+  else return __shfl_xor(v, 1 << S);
+}
+
+template <int S, int N, typename T>
+__device__ __forceinline__ void rs_step(T (&v)[N], int n, int lane) {
+  if (n > 1) {
+    const bool up = rs_keep(lane, S);
+    const int h = n >> 1;
+#pragma unroll
+    for (int i = 0; i < N / 2; ++i) {
+      if (i < h) {
+        const T send = up ? v[i] : v[i + h];
+        const T keep = up ? v[i + h] : v[i];
+        v[i] = keep + rs_partner<S>(send);
+      }
+    }
+  } else {
+    v[0] += rs_partner<S>(v[0]);
+  }
+}
+
+template <int N, typename T>
+__device__ __forceinline__ T reduce_scatter(T (&v)[N]) {
+  static_assert(N >= 2 && N <= 64 && (N & (N - 1)) == 0, "N a power of two up to 64");
+  const int lane = lane_id();
+  rs_step<0>(v, N, lane);
+  rs_step<1>(v, N >> 1, lane);
+  rs_step<2>(v, N >> 2, lane);
+  rs_step<3>(v, N >> 3, lane);
+  rs_step<4>(v, N >> 4, lane);
+  rs_step<5>(v, N >> 5, lane);
+  return v[0];
+}
+
 // Segmented inclusive scan over lanes whose keys form contiguous runs (each
 // key one run).  A scan inside each 16-lane row by shifts of 1, 2, 4, 8, then
 // the carries between rows: rows 1 and 3 take lane 15 of the row before,
@@ -624,7 +695,10 @@ __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
   double acc[kLinVals];
 #pragma unroll
   for (int k = 0; k < kLinVals; ++k) acc[k] = 0.0;
-#pragma unroll 2
+  // two observations at a time in FP32; in FP64 that would spill the
+  // reduction's registers
+  constexpr int kUnroll = sizeof(T) == 4 ? 2 : 1;
+#pragma unroll kUnroll
   for (int r = 0; r < kPerLane; ++r) {
     const int e = beg + r * kBlock + (int)threadIdx.x;
     if (e >= end) break;
@@ -669,10 +743,9 @@ __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
   }
   __shared__ double red[kWavesPerBlock][kLinVals];
   const int wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < kLinVals; ++k) {
-    const double s = wave_sum(acc[k]);
-    if (lane_id() == 0) red[wv][k] = s;
+  {
+    const double s = reduce_scatter<kLinVals>(acc);
+    red[wv][rs_index<kLinVals>(lane_id())] = s;
   }
   __syncthreads();
   if (threadIdx.x < kLinVals) {
@@ -1170,10 +1243,13 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
   __shared__ T red[kWavesPerBlock][12];
   __shared__ T tv[12];
   const int wv = threadIdx.x >> 6;
+  {
+    T v16[16];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) {
-    const T s = wave_sum(acc[k]);
-    if (lane_id() == 0) red[wv][k] = s;
+    for (int k = 0; k < 16; ++k) v16[k] = k < 12 ? acc[k] : T(0);
+    const T s = reduce_scatter<16>(v16);
+    const int idx = rs_index<16>(lane_id());
+    if (lane_id() < 16 && idx < 12) red[wv][idx] = s;
   }
   __syncthreads();
   const int k = threadIdx.x;
