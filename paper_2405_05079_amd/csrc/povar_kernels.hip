@@ -1288,10 +1288,13 @@ __global__ void __launch_bounds__(kWave) k_series_camera_combine(Batch B, int t)
     for (int kk = 0; kk < 12; ++kk) s[kk] += v[kk];
   }
   __shared__ T tv[12];
+  {
+    T v16[16];
 #pragma unroll
-  for (int kk = 0; kk < 12; ++kk) {
-    const T r = wave_sum(s[kk]);
-    if (lane_id() == 0) tv[kk] = r;
+    for (int k = 0; k < 16; ++k) v16[k] = k < 12 ? s[k] : T(0);
+    const T r = reduce_scatter<16>(v16);
+    const int idx = rs_index<16>(lane_id());
+    if (lane_id() < 16 && idx < 12) tv[idx] = r;
   }
   __syncthreads();
   camera_solve<T>(D, cam, tv, kr, t == D.ctl.order);
