@@ -92,7 +92,8 @@ struct povar_problem_s {
   void* arena = nullptr;
   povar::DevProblem rec{};    // host copy of the device record
   povar::Batch batch{};       // batch of one
-  hipGraphExec_t graph_exec = nullptr;
+  hipGraphExec_t graph_exec = nullptr;     // one iteration
+  hipGraphExec_t graph_exec_k = nullptr;   // kGraphIters iterations
   bool graph_failed = false;
   // kernel timing
   bool timing = false;

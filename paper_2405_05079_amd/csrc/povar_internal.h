@@ -161,6 +161,7 @@ enum UnitKind {
   kUnitCSlot = 7,      // one wave per camera slot, series pass (blocked problems)
   kNumUnitKinds = 8
 };
+constexpr int kGraphIters = 4;       // iterations per replay of the longer graph
 constexpr int kCostGroup = 2048;
 constexpr int kCostDirect = 8192;    // up to this many packets, k_decide adds the packet partials itself
 

@@ -957,23 +957,30 @@ hipError_t enqueue_iteration(povar_problem_s* pb, bool timed) {
   return launch_decide(B, pb->stream);
 }
 
-static hipError_t ensure_graph(povar_problem_s* pb) {
-  if (pb->graph_exec) return hipSuccess;
-  hipGraph_t g = nullptr;
+// Graphs of one and of kGraphIters iterations: replaying a graph costs a few
+// microseconds between graphs, which the longer graph pays once per
+// kGraphIters iterations.
+static hipError_t capture_iterations(povar_problem_s* pb, int iters, hipGraphExec_t* out) {
   hipError_t e = hipStreamBeginCapture(pb->stream, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return e;
-  e = enqueue_iteration(pb, false);
+  for (int i = 0; i < iters && e == hipSuccess; ++i) e = enqueue_iteration(pb, false);
   hipGraph_t captured = nullptr;
-  hipError_t e2 = hipStreamEndCapture(pb->stream, &captured);
-  if (e != hipSuccess) {
+  const hipError_t e2 = hipStreamEndCapture(pb->stream, &captured);
+  if (e != hipSuccess || e2 != hipSuccess) {
     if (captured) (void)hipGraphDestroy(captured);
-    return e;
+    return e != hipSuccess ? e : e2;
   }
-  if (e2 != hipSuccess) return e2;
-  g = captured;
-  e = hipGraphInstantiate(&pb->graph_exec, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (e != hipSuccess) pb->graph_exec = nullptr;
+  e = hipGraphInstantiate(out, captured, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(captured);
+  if (e != hipSuccess) *out = nullptr;
+  return e;
+}
+
+static hipError_t ensure_graph(povar_problem_s* pb) {
+  if (pb->graph_exec && pb->graph_exec_k) return hipSuccess;
+  hipError_t e = hipSuccess;
+  if (!pb->graph_exec) e = capture_iterations(pb, 1, &pb->graph_exec);
+  if (e == hipSuccess && !pb->graph_exec_k) e = capture_iterations(pb, kGraphIters, &pb->graph_exec_k);
   return e;
 }
 
@@ -987,8 +994,13 @@ hipError_t enqueue_iterations(povar_problem_s* pb, int n) {
       (void)hipGetLastError();
     }
   }
-  for (int it = 0; it < n; ++it) {
-    if (!timed && pb->graph_exec) e = hipGraphLaunch(pb->graph_exec, pb->stream);
+  const bool graphs = !timed && !pb->graph_failed && pb->graph_exec && pb->graph_exec_k;
+  int it = 0;
+  if (graphs)
+    for (; it + kGraphIters <= n; it += kGraphIters)
+      if ((e = hipGraphLaunch(pb->graph_exec_k, pb->stream)) != hipSuccess) return e;
+  for (; it < n; ++it) {
+    if (graphs) e = hipGraphLaunch(pb->graph_exec, pb->stream);
     else e = enqueue_iteration(pb, timed);
     if (e != hipSuccess) return e;
   }
@@ -1212,6 +1224,7 @@ povar_status povar_problem_destroy(povar_problem pb) {
   if (pb->ctx) (void)hipSetDevice(pb->ctx->device);
   if (pb->stream) (void)hipStreamSynchronize(pb->stream);
   if (pb->graph_exec) (void)hipGraphExecDestroy(pb->graph_exec);
+  if (pb->graph_exec_k) (void)hipGraphExecDestroy(pb->graph_exec_k);
   for (auto ev : pb->events) (void)hipEventDestroy(ev);
   if (pb->arena) (void)hipFree(pb->arena);
   if (pb->ctx && pb->owned_by_ctx) pb->ctx->live_problems -= 1;
