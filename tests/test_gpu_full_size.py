@@ -1,0 +1,132 @@
+"""Parity at the benchmark's full sizes, in the configuration bench.py times
+(one problem per context, the same layout and kernels, graph replays).
+
+* 250 cameras / 60,000 points / 300,731 observations (the benchmark
+  workload): every landmark's V^+ and X, every camera's U_i, the cost and one
+  damped order-20 camera step against the oracle, in both precisions.
+* 1,800 cameras / 1M points / 5.0M observations (landmark-blocked camera
+  pass, cooperative camera gathers): V^+ and X on sampled landmarks and U_i on
+  sampled cameras, each of which the oracle computes exactly from a
+  sub-problem holding all the observations it depends on; then properties
+  that hold at any size (steps tangent to the sphere, unit-norm trial
+  cameras, LM iterations that never raise the cost).
+"""
+import numpy as np
+import pytest
+
+from oracle import povar_oracle as O
+from paper_2405_05079_amd import povar, synth
+
+pytestmark = pytest.mark.gpu
+
+# (V^+, U, cost, step, trial cost) relative-error bounds: FP64 at rounding
+# level; FP32-bulk with FP32 products in U and an FP32 series
+TOL = {"fp64": (1e-9, 1e-9, 1e-12, 1e-8, 1e-10), "fp32_bulk": (1e-9, 1e-5, 1e-12, 1e-4, 1e-6)}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = povar.Context(0)
+    yield c
+    c.close()
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def rel_rows(a, b):
+    a, b = a.reshape(len(a), -1), b.reshape(len(b), -1)
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def w2():
+    prob = synth.workload(2)
+    P, X, f = O.initial_state(prob, prob.cams0)
+    lin = O.linearize(P, X, prob)
+    step = O.camera_step(P, lin, 1e-3, prob.order)
+    Pn = O.retract(P, step)
+    Xn, _ = O.solve_landmarks(Pn, prob)
+    return prob, X, lin, step, O.cost(Pn, Xn, prob)
+
+
+@pytest.mark.parametrize("prec", ["fp32_bulk", "fp64"])
+def test_full_size_250_cameras(ctx, w2, prec):
+    prob, X, lin, step, f_trial = w2
+    t_vp, t_u, t_f, t_step, t_trial = TOL[prec]
+    say("full 250 cameras", prec, prob.n_obs)
+    gp = povar.Problem.from_synth(ctx, prob, precision=prec)
+    try:
+        d = gp.debug_linearize()
+        assert rel_rows(d["Vp"], lin.Vp).max() < t_vp
+        assert rel_rows(d["X"], X).max() < t_vp
+        assert rel_rows(d["U"], lin.U).max() < t_u
+        assert abs(d["cost"] - lin.cost) / lin.cost < t_f
+        dp, pt, ct = gp.debug_step(1e-3, prob.order)
+        assert rel_rows(dp, step).max() < t_step
+        assert abs(ct - f_trial) / f_trial < t_trial
+        # LM iterations replayed from the graphs: the accepted cost never rises
+        c0 = gp.report()["cost_final"]
+        gp.step(9)
+        rep = gp.report()
+        assert rep["iters"] == 9 and rep["cost_final"] <= c0
+        np.testing.assert_allclose(np.linalg.norm(gp.cameras(), axis=1), 1.0, rtol=1e-12)
+    finally:
+        gp.close()
+
+
+def sub_problem(prob, keep):
+    """The observations `keep` (boolean mask) with their points renumbered."""
+    pts, inv = np.unique(prob.pt_idx[keep], return_inverse=True)
+    sub = synth.Problem(n_cams=prob.n_cams, n_pts=len(pts), cam_idx=prob.cam_idx[keep],
+                        pt_idx=inv.astype(np.int32), meas=prob.meas[keep], cams0=prob.cams0,
+                        eta=prob.eta, order=prob.order, iters=prob.iters)
+    return sub, pts
+
+
+@pytest.fixture(scope="module")
+def w3():
+    return synth.workload(3)
+
+
+@pytest.mark.parametrize("prec", ["fp32_bulk", "fp64"])
+def test_full_size_1800_cameras_sampled(ctx, w3, prec):
+    prob = w3
+    t_vp, t_u = TOL[prec][0], TOL[prec][1]
+    say("full 1800 cameras", prec, prob.n_obs)
+    rng = np.random.default_rng(77)
+    gp = povar.Problem.from_synth(ctx, prob, precision=prec)
+    try:
+        lay = gp.layout()
+        assert lay["blocked"] and prob.n_cams * 96 > 32768   # camera slots; 128-byte camera records
+        d = gp.debug_linearize()
+        P = prob.cams0 / np.linalg.norm(prob.cams0, axis=1, keepdims=True)   # the initial cameras
+        # landmarks: each one's V^+ and X depend only on its own observations
+        lm = rng.choice(prob.n_pts, size=3000, replace=False)
+        sub, pts = sub_problem(prob, np.isin(prob.pt_idx, lm))
+        Xs, _ = O.solve_landmarks(P, sub)
+        lin_s = O.linearize(P, Xs, sub)
+        assert rel_rows(d["Vp"][pts], lin_s.Vp).max() < t_vp
+        assert rel_rows(d["X"][pts], Xs).max() < t_vp
+        # cameras: U_i needs all of camera i's observations and, for each of
+        # their landmarks, all of that landmark's observations
+        cams = rng.choice(prob.n_cams, size=12, replace=False)
+        seen = np.unique(prob.pt_idx[np.isin(prob.cam_idx, cams)])
+        sub, pts = sub_problem(prob, np.isin(prob.pt_idx, seen))
+        Xs, _ = O.solve_landmarks(P, sub)
+        lin_s = O.linearize(P, Xs, sub)
+        assert rel_rows(d["U"][cams], lin_s.U[cams]).max() < t_u
+        # properties at any size: the step lies in each camera's tangent space
+        # and the trial cameras have unit norm; iterations never raise the cost
+        dp, pt, ct = gp.debug_step(1e-3, prob.order)
+        tang = np.abs(np.sum(P * dp, axis=1)) / np.maximum(np.linalg.norm(dp, axis=1), 1e-300)
+        assert tang.max() < 1e-6
+        np.testing.assert_allclose(np.linalg.norm(pt, axis=1), 1.0, rtol=1e-12)
+        assert np.isfinite(ct)
+        c0 = gp.report()["cost_final"]
+        gp.step(4)
+        rep = gp.report()
+        assert rep["iters"] == 4 and rep["cost_final"] <= c0
+    finally:
+        gp.close()
