@@ -90,6 +90,13 @@ typedef struct {
   int32_t use_graph;     /* 1: replay each iteration as a captured HIP graph
                             (default); 0: launch kernels one by one */
   int32_t reserved;
+  double series_rtol;    /* optional early stop of the series, in [0, 1).
+                            Sec. 5.2 gives the expansion methods a "threshold"
+                            of 0.01 without defining it; read here as: after
+                            term t >= 1, stop once ||x_t|| <= series_rtol *
+                            ||x_0 + ... + x_t|| (2-norms over all cameras,
+                            FP64 sums of the stored terms).  0 (default) runs
+                            all series_order terms. */
 } povar_options;
 
 typedef struct {

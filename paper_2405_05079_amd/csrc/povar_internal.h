@@ -67,7 +67,8 @@ struct Ctl {
   int32_t order;        // series order m of the next steps
   int32_t stop_reason;  // 1: ftol
   int32_t status;       // bit 0: a damped camera block of this step could not be factored
-  int32_t pad0, pad1;
+  int32_t stop_at;      // last series term of the current step (order, or earlier on an early stop)
+  int32_t stopped;      // 1: the series of the current step stopped early (retraction still to do)
 };
 
 struct DevProblem {
@@ -78,6 +79,7 @@ struct DevProblem {
   int32_t s_stride;     // series record stride, ser_stride(n_p)
   int32_t pad1;
   double eta, ftol, lambda_min, lambda_max;
+  double series_rtol;   // early stop of the series (0: off)
 
   // landmark-major packets on 64-entry slots: slot q holds whole landmarks
   // lm0, lm0+1, ... (internal ids) in entries 64q .. 64q + n - 1 (one lane
@@ -212,6 +214,7 @@ hipError_t launch_series_landmark(const Batch& b, bool fp32, int t, hipStream_t 
 hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s, hipEvent_t ev0 = nullptr,
                                 hipEvent_t ev1 = nullptr);   // chunk or slot pass, + combine (not timed)
 hipError_t launch_cost_groups(const Batch& b, int trial, hipStream_t s);
+hipError_t launch_series_check(const Batch& b, bool fp32, int t, hipStream_t s);
 hipError_t launch_retract(const Batch& b, bool fp32, hipStream_t s);
 hipError_t launch_decide(const Batch& b, hipStream_t s);
 

@@ -24,6 +24,7 @@
 //   k_series_camera        x_i = K_i sum_k W_k z_j, acc_i += x_i             (17)
 //   k_series_camera_slots  the same sums for landmark-blocked problems, per run
 //   k_series_camera_combine  adds a camera's partial sums, applies K_i
+//   k_series_check         optional early stop of the series (Sec. 5.2)
 //   k_retract              p_i <- (p_i + acc_i) / |p_i + acc_i|             (Sec. 4.3)
 //                          (series order 0 only; otherwise in the last camera pass)
 //   k_decide               LM accept / reject and damping update            (Sec. 5.2)
@@ -771,6 +772,11 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
   DevProblem& D = B.probs[p];
   if (D.ctl.done) return;
   const int i = w * kWave + lane_id();
+  // a new step: all series terms until an early stop says otherwise
+  if (i == 0) {
+    D.ctl.stop_at = D.ctl.order;
+    D.ctl.stopped = 0;
+  }
   if (i >= D.n_p) return;
   const double lam = D.ctl.lambda;
   const int pc = D.ctl.pcur;
@@ -1081,7 +1087,7 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
   int p, q;
   if (!map_wave(B, kUnitPacket, p, q)) return;
   DevProblem& D = B.probs[p];
-  if (D.ctl.done || t > D.ctl.order) return;
+  if (D.ctl.done || t > D.ctl.stop_at) return;
   const CamFromRecords<T> cam{Prec<T>::S(D, D.ctl.pcur), D.s_stride};
   landmark_slot<T>(D, q, slot_head<T>(D, q), D.ctl.lcur, cam);
 }
@@ -1093,7 +1099,7 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark_coop(Batch B, int t)
   int p, q;
   if (!map_wave(B, kUnitPacket, p, q)) return;
   DevProblem& D = B.probs[p];
-  if (D.ctl.done || t > D.ctl.order) return;
+  if (D.ctl.done || t > D.ctl.stop_at) return;
   const CamFromRecords<float> cam{Prec<float>::S(D, D.ctl.pcur), D.s_stride};
   if (D.s_stride == kSerLine) {
     extern __shared__ f4v coop_lds[];
@@ -1111,7 +1117,7 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark_coop(Batch B, int t)
 template <typename T>
 __global__ void __launch_bounds__(kLdsBlock) k_series_landmark_lds(Batch B, int t) {
   const DevProblem& D = B.probs[0];
-  if (D.ctl.done || t > D.ctl.order) return;
+  if (D.ctl.done || t > D.ctl.stop_at) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T POVAR_LDS* tab = (T POVAR_LDS*)lds_raw;
   const int n_hot = D.n_hot, ss = D.s_stride;
@@ -1183,7 +1189,7 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
   int p, ch;
   if (!map_block(B, kUnitSerChunk, p, ch)) return;
   DevProblem& D = B.probs[p];
-  if (D.ctl.done || t > D.ctl.order) return;
+  if (D.ctl.done || t > D.ctl.stop_at) return;
   const int pc = D.ctl.pcur;
   const int4 meta = D.ch_meta[ch];
   const int cam = meta.x, beg = meta.y, end = meta.z, nch = meta.w;
@@ -1272,7 +1278,7 @@ __global__ void __launch_bounds__(kWave) k_series_camera_combine(Batch B, int t)
   int p, u;
   if (!map_wave<kWave>(B, kUnitMultiCam, p, u)) return;
   DevProblem& D = B.probs[p];
-  if (D.ctl.done || t > D.ctl.order) return;
+  if (D.ctl.done || t > D.ctl.stop_at) return;
   const int cam = D.ser_mc[u];
   const int c0 = D.ser_off[cam], np = D.ser_off[cam + 1] - c0;
   double kr[12];
@@ -1310,7 +1316,7 @@ __global__ void __launch_bounds__(kBlock) k_series_camera_slots(Batch B, int t) 
   int p, q;
   if (!map_wave(B, kUnitCSlot, p, q)) return;
   DevProblem& D = B.probs[p];
-  if (D.ctl.done || t > D.ctl.order) return;
+  if (D.ctl.done || t > D.ctl.stop_at) return;
   const int lane = lane_id();
   const int pc = D.ctl.pcur;
   // entry loads do not wait for the slot header
@@ -1387,13 +1393,56 @@ __global__ void __launch_bounds__(kBlock) k_series_camera_slots(Batch B, int t) 
   }
 }
 
+// ---------------------------------------------------------- k_series_check
+// Optional early stop of the series (series_rtol > 0): after term t (1 <= t <
+// order), the 2-norms over all cameras of x_t (the stored series term) and of
+// acc = x_0 + ... + x_t, summed in FP64 in a fixed order; if ||x_t|| <=
+// series_rtol ||acc||, the later terms are skipped and k_retract applies acc.
+// One workgroup per problem.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_series_check(Batch B, int t) {
+  int p, w;
+  if (!map_block(B, kUnitOne, p, w)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done || !(D.series_rtol > 0.0) || t > D.ctl.stop_at || t >= D.ctl.order) return;
+  const T POVAR_GMEM* S = Prec<T>::S(D, D.ctl.pcur);
+  double sx = 0.0, sa = 0.0;
+  for (int i = (int)threadIdx.x; i < D.n_p; i += kBlock) {
+#pragma unroll
+    for (int k = 0; k < kCam; ++k) {
+      const double x = (double)S[(size_t)i * D.s_stride + kSerX + k];
+      const double a = D.acc[(size_t)i * kCam + k];
+      sx += x * x;
+      sa += a * a;
+    }
+  }
+  sx = wave_sum(sx);
+  sa = wave_sum(sa);
+  __shared__ double red[kWavesPerBlock][2];
+  const int wv = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    red[wv][0] = sx;
+    red[wv][1] = sa;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double nx = ((red[0][0] + red[1][0]) + red[2][0]) + red[3][0];
+  const double na = ((red[0][1] + red[1][1]) + red[2][1]) + red[3][1];
+  if (sqrt(nx) <= D.series_rtol * sqrt(na)) {
+    D.ctl.stop_at = t;
+    D.ctl.stopped = 1;
+  }
+}
+
 // --------------------------------------------------------------- k_retract
 template <typename T>
 __global__ void __launch_bounds__(kWave) k_retract(Batch B) {
   int p, w;
   if (!map_wave<kWave>(B, kUnitCamWave, p, w)) return;
   DevProblem& D = B.probs[p];
-  if (D.ctl.done || D.ctl.order > 0) return;   // order >= 1: retracted by the last camera pass
+  // order >= 1: retracted by the camera pass of the last term, unless the
+  // series stopped early
+  if (D.ctl.done || (D.ctl.order > 0 && !D.ctl.stopped)) return;
   const int i = w * kWave + lane_id();
   if (i >= D.n_p) return;
   const int pc = D.ctl.pcur;
@@ -1557,6 +1606,14 @@ hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s,
 hipError_t launch_cost_groups(const Batch& b, int trial, hipStream_t s) {
   if (b.total[kUnitCostGroup] == 0) return hipSuccess;
   hipLaunchKernelGGL(k_cost_groups, blocks_for(b.total[kUnitCostGroup], 1), dim3(kBlock), 0, s, b, trial);
+  return hipGetLastError();
+}
+
+hipError_t launch_series_check(const Batch& b, bool fp32, int t, hipStream_t s) {
+  if (b.total[kUnitOne] == 0) return hipSuccess;
+  const dim3 g = blocks_for(b.total[kUnitOne], 1);
+  if (fp32) hipLaunchKernelGGL(k_series_check<float>, g, dim3(kBlock), 0, s, b, t);
+  else hipLaunchKernelGGL(k_series_check<double>, g, dim3(kBlock), 0, s, b, t);
   return hipGetLastError();
 }
 

@@ -688,6 +688,10 @@ povar_status check_options(povar_ctx ctx, const povar_options* o) {
     set_error(ctx, "unknown manifold %d", o->manifold);
     return POVAR_EINVAL;
   }
+  if (!(o->series_rtol >= 0.0 && o->series_rtol < 1.0)) {
+    set_error(ctx, "series_rtol must lie in [0, 1)");
+    return POVAR_EINVAL;
+  }
   return POVAR_OK;
 }
 
@@ -762,6 +766,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.ftol = o->ftol;
   R.lambda_min = o->lambda_min;
   R.lambda_max = o->lambda_max;
+  R.series_rtol = o->series_rtol;
   R.pk_hdr = (const int2*)dp(A.pk_hdr);
   R.pk_code = (const uint32_t*)dp(A.pk_code);
   R.pk_m32 = (const float2*)dp(A.pk_m32);
@@ -827,6 +832,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   c.need_lin = 1;
   c.iter_limit = iter_limit;
   c.order = o->series_order;
+  c.stop_at = o->series_order;
 
   // batch of one: prefix tables of waves per unit kind
   int32_t units[kNumUnitKinds];
@@ -937,6 +943,9 @@ static hipError_t enqueue_series(povar_problem_s* pb, int order, bool timed) {
       }
     if ((e = launch_series_landmark(pb->batch, pb->fp32, t, pb->stream, ev[0], ev[1])) != hipSuccess) return e;
     if ((e = launch_series_camera(pb->batch, pb->fp32, t, pb->stream, ev[2], ev[3])) != hipSuccess) return e;
+    if (pb->opt.series_rtol > 0.0 && t < order &&
+        (e = launch_series_check(pb->batch, pb->fp32, t, pb->stream)) != hipSuccess)
+      return e;
     if (timed) {
       pb->pending.push_back({ev[0], ev[1], 0});
       pb->pending.push_back({ev[2], ev[3], 1});
@@ -951,7 +960,10 @@ hipError_t enqueue_iteration(povar_problem_s* pb, bool timed) {
   if ((e = launch_linearize(B, pb->fp32, 0, pb->stream)) != hipSuccess) return e;
   if ((e = launch_camera_prep(B, pb->fp32, pb->stream)) != hipSuccess) return e;
   if ((e = enqueue_series(pb, pb->opt.series_order, timed)) != hipSuccess) return e;
-  if (pb->opt.series_order == 0 && (e = launch_retract(B, pb->fp32, pb->stream)) != hipSuccess) return e;
+  // order 0, or a series that may stop early: the retraction is a kernel of its own
+  if ((pb->opt.series_order == 0 || pb->opt.series_rtol > 0.0) &&
+      (e = launch_retract(B, pb->fp32, pb->stream)) != hipSuccess)
+    return e;
   if ((e = launch_landmark_solve(B, 1, pb->stream)) != hipSuccess) return e;
   if ((e = launch_cost_groups(B, 1, pb->stream)) != hipSuccess) return e;
   return launch_decide(B, pb->stream);
@@ -1467,8 +1479,9 @@ povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, do
   for (int t = 1; t <= order; ++t) {
     HIP_TRY(ctx, launch_series_landmark(B, pb->fp32, t, pb->stream));
     HIP_TRY(ctx, launch_series_camera(B, pb->fp32, t, pb->stream));
+    if (pb->opt.series_rtol > 0.0 && t < order) HIP_TRY(ctx, launch_series_check(B, pb->fp32, t, pb->stream));
   }
-  if (order == 0) HIP_TRY(ctx, launch_retract(B, pb->fp32, pb->stream));
+  if (order == 0 || pb->opt.series_rtol > 0.0) HIP_TRY(ctx, launch_retract(B, pb->fp32, pb->stream));
   HIP_TRY(ctx, launch_landmark_solve(B, 1, pb->stream));
   HIP_TRY(ctx, launch_cost_groups(B, 1, pb->stream));
   HIP_TRY(ctx, launch_cost_finalize(B, 1, pb->stream));

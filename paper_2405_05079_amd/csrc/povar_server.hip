@@ -61,6 +61,7 @@ struct Group {
   std::vector<DevProblem> host_recs;   // read-back buffer
   Batch batch{};
   int max_order = 0, min_order = 0;
+  bool any_rtol = false;               // a problem of the group may stop its series early
   bool dirty = true;
 };
 
@@ -106,6 +107,7 @@ hipError_t upload_tables(povar_server_s* sv, Group& G) {
   std::vector<int32_t> tab((size_t)kNumUnitKinds * stride, 0);
   G.max_order = 0;
   G.min_order = INT_MAX;
+  G.any_rtol = false;
   for (int p = 0; p < n; ++p) {
     const HostLayout& L = G.res[p].pb->L;
     int32_t units[kNumUnitKinds];
@@ -113,6 +115,7 @@ hipError_t upload_tables(povar_server_s* sv, Group& G) {
     for (int k = 0; k < kNumUnitKinds; ++k) tab[(size_t)k * stride + p + 1] = tab[(size_t)k * stride + p] + units[k];
     G.max_order = std::max(G.max_order, G.res[p].pb->opt.series_order);
     G.min_order = std::min(G.min_order, G.res[p].pb->opt.series_order);
+    if (G.res[p].pb->opt.series_rtol > 0.0) G.any_rtol = true;
   }
   hipError_t e = hipMemcpyAsync(G.tables, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, sv->stream);
   if (e != hipSuccess) return e;
@@ -141,8 +144,9 @@ hipError_t launch_iteration(povar_server_s* sv, Group& G) {
   for (int t = 1; t <= G.max_order; ++t) {
     if ((e = launch_series_landmark(B, G.fp32, t, s)) != hipSuccess) return e;
     if ((e = launch_series_camera(B, G.fp32, t, s)) != hipSuccess) return e;
+    if (G.any_rtol && t < G.max_order && (e = launch_series_check(B, G.fp32, t, s)) != hipSuccess) return e;
   }
-  if (G.min_order == 0 && (e = launch_retract(B, G.fp32, s)) != hipSuccess) return e;
+  if ((G.min_order == 0 || G.any_rtol) && (e = launch_retract(B, G.fp32, s)) != hipSuccess) return e;
   if ((e = launch_landmark_solve(B, 1, s)) != hipSuccess) return e;
   if ((e = launch_cost_groups(B, 1, s)) != hipSuccess) return e;
   return launch_decide(B, s);

@@ -45,7 +45,8 @@ class Options(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("eta", C.c_double), ("series_order", C.c_int32),
                 ("max_iters", C.c_int32), ("ftol", C.c_double), ("lambda0", C.c_double),
                 ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("precision", C.c_int32),
-                ("manifold", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32)]
+                ("manifold", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32),
+                ("series_rtol", C.c_double)]
 
 
 class Report(C.Structure):
@@ -121,7 +122,8 @@ def _ptr(a: np.ndarray) -> C.c_void_p:
 
 
 def make_options(eta=0.01, order=20, max_iters=50, ftol=1e-6, lambda0=1e-4, lambda_min=1e-12,
-                 lambda_max=1e12, precision="fp64", manifold="sphere", use_graph=True) -> Options:
+                 lambda_max=1e12, precision="fp64", manifold="sphere", use_graph=True,
+                 series_rtol=0.0) -> Options:
     o = Options()
     lib().povar_options_default(C.byref(o))
     o.eta, o.series_order, o.max_iters, o.ftol = eta, order, max_iters, ftol
@@ -129,6 +131,7 @@ def make_options(eta=0.01, order=20, max_iters=50, ftol=1e-6, lambda0=1e-4, lamb
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     o.manifold = MANIFOLD[manifold] if isinstance(manifold, str) else int(manifold)
     o.use_graph = 1 if use_graph else 0
+    o.series_rtol = series_rtol
     return o
 
 

@@ -35,6 +35,7 @@ def test_options_default_values():
     assert (o.eta, o.series_order, o.max_iters, o.ftol) == (0.01, 20, 50, 1e-6)
     assert (o.lambda0, o.lambda_min, o.lambda_max) == (1e-4, 1e-12, 1e12)
     assert (o.precision, o.manifold, o.use_graph) == (0, 0, 1)
+    assert o.series_rtol == 0.0   # the series runs all its terms unless asked to stop early
     assert povar.lib().povar_options_default(None) == povar.EINVAL
 
 

@@ -118,6 +118,46 @@ def test_camera_step_fp32_bulk(ctx, lam, order, kw):
     gp.close()
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32_bulk", 2e-3)])
+def test_series_early_stop(ctx, prec, tol):
+    """series_rtol = 0.01: the series stops after the first term t >= 1 with
+    ||x_t|| <= 0.01 ||x_0 + ... + x_t|| and the step is retracted from there.
+    Dampings chosen so that the ratios at each decision sit >= 2% from the
+    threshold (FP32 rounding cannot flip it): the oracle stops after 3 and 7
+    terms at lambda 10 and 1 and runs all 20 at 1e-4."""
+    prob = case(**CASES[1])
+    say("early stop", prec)
+    gp = povar.Problem.from_synth(ctx, prob, precision=prec, series_rtol=0.01)
+    P, X, f = O.initial_state(prob, prob.cams0)
+    lin = O.linearize(P, X, prob)
+    used = []
+    for lam in (10.0, 1.0, 1e-4):
+        used.append(O.power_series(O.reduced_system(P, lin, lam), 20, 0.01)[1])
+        dp, pt, ct = gp.debug_step(lam, 20)
+        ref = O.camera_step(P, lin, lam, 20, rtol=0.01)
+        assert rel(dp, ref) < tol
+        np.testing.assert_allclose(np.linalg.norm(pt, axis=1), 1.0, rtol=1e-12)
+        Pn = O.retract(P, ref)
+        Xn, _ = O.solve_landmarks(Pn, prob)
+        assert abs(ct - O.cost(Pn, Xn, prob)) / O.cost(Pn, Xn, prob) < (1e-10 if prec == "fp64" else 1e-4)
+    assert used == [3, 7, 20]
+    gp.close()
+
+
+def test_trajectory_with_series_early_stop_matches_oracle(ctx):
+    prob = synth.workload(1)
+    say("trajectory fp64 workload 1, series early stop")
+    gp = povar.Problem.from_synth(ctx, prob, precision="fp64", max_iters=15, ftol=0.0, series_rtol=0.01)
+    rep = gp.solve()
+    cost, lam, acc = gp.trace()
+    ref = O.lm_solve(prob, opts=O.Options(order=prob.order, max_iters=15, ftol=0.0, rtol=0.01))
+    assert list(acc) == ref.trace_accept
+    np.testing.assert_allclose(lam, ref.trace_lambda, rtol=1e-12)
+    np.testing.assert_allclose(cost, ref.trace_cost, rtol=1e-8)
+    assert abs(rep["cost_final"] - ref.cost) <= 1e-8 * ref.cost
+    gp.close()
+
+
 def test_many_cameras_and_many_chunks_per_camera(ctx):
     """More than one wave of cameras (per-camera kernels span several
     workgroups), cameras whose observations span many chunks, and landmarks
@@ -326,3 +366,6 @@ def test_invalid_inputs_are_rejected(ctx):
                       np.r_[prob.cams0, prob.cams0[:1]])
     with pytest.raises(povar.PovarError):
         povar.Problem.from_synth(ctx, prob, eta=1.5)
+    for r in (-0.1, 1.0, float("nan")):
+        with pytest.raises(povar.PovarError):
+            povar.Problem.from_synth(ctx, prob, series_rtol=r)

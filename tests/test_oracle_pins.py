@@ -230,6 +230,40 @@ def test_series_partial_sums_match_neumann_closed_form_and_bound():
         q_prev = q
 
 
+def test_series_early_stop_is_the_first_small_term():
+    """The optional early stop of the series (reading of the undefined
+    "threshold" of Sec. 5.2): the sum ends after the first term t >= 1 with
+    ||x_t|| <= rtol ||x_0 + ... + x_t||.  The stopping order is found here from
+    dense powers of M, and the oracle's step equals the Neumann closed form at
+    that order."""
+    prob = tiny(n_cams=4, n_pts=30, seed=31)
+    P = synth.init_cameras(prob.n_cams, 32)
+    X, _ = O.solve_landmarks(P, prob)
+    lin = O.linearize(P, X, prob)
+    stops = []
+    for lam, rtol in ((0.3, 0.05), (0.3, 0.01), (3.0, 0.01), (1e-3, 0.01)):
+        D = _dense_problem(prob, P, lam)
+        Ut, W, V = D["Ut"], D["W"], D["V"]
+        Vp = np.linalg.pinv(V, rcond=1e-12, hermitian=True)
+        M = np.linalg.solve(Ut, W @ Vp @ W.T)
+        u0 = np.linalg.solve(Ut, D["bp"] - W @ Vp @ D["bl"])
+        x, acc, t_stop = -u0, -u0, 20
+        for t in range(1, 21):
+            x = M @ x
+            acc = acc + x
+            if np.linalg.norm(x) <= rtol * np.linalg.norm(acc):
+                t_stop = t
+                break
+        _, used = O.power_series(O.reduced_system(P, lin, lam), 20, rtol)
+        assert used == t_stop
+        I = np.eye(M.shape[0])
+        closed = -(I - np.linalg.matrix_power(M, t_stop + 1)) @ np.linalg.solve(I - M, u0)
+        dP = O.camera_step(P, lin, lam, 20, rtol=rtol).ravel()
+        np.testing.assert_allclose(dP, D["Bd"] @ closed, rtol=1e-8, atol=1e-12 * np.abs(closed).max())
+        stops.append(t_stop)
+    assert min(stops) < 20       # the stop is exercised
+
+
 @pytest.mark.parametrize("manifold,lam", [("sphere", 1e-4), ("sphere", 1.0), ("euclidean", 1e-2)])
 def test_lemma1_spectrum_in_unit_interval(manifold, lam):
     prob = tiny(n_cams=5, n_pts=40, seed=41)
