@@ -208,6 +208,48 @@ povar_status povar_debug_layout_check(int32_t n_cams, int32_t n_pts, int64_t n_o
                                       const int32_t* pt_idx, const double* meas, int32_t precision,
                                       int64_t* out);
 
+/* ---- second stage: projective refinement (RiPoBA) ----------------------- */
+/* Objective (7) of Sec. 3 with the method of Sec. 4.3: the cameras (unit
+   sphere of R^12) and the homogeneous landmarks (unit sphere of R^4) refined
+   jointly by LM; each step solves the damped Riemannian normal equations
+   (20)-(26) with the power series (29) of the inverse Riemannian Schur
+   complement (27) for the cameras and back-substitution for the landmarks,
+   then retracts both by normalisation.  Damping: Marquardt on the diagonal of
+   each ambient camera / landmark block, then projected.
+   cams0: n_cams x 12 (row-major 3x4), pts0: n_pts x 4 homogeneous, both in
+   the caller's order (each row is normalised; host memory).  opts: precision
+   POVAR_PREC_FP64, manifold POVAR_MANIFOLD_SPHERE, series_rtol 0; the other
+   fields as for povar_problem_create.  The handle works with povar_solve,
+   povar_step, povar_enqueue, povar_get_report, povar_get_cameras,
+   povar_get_trace, povar_get_state, povar_kernel_timing / _times,
+   povar_problem_info / _layout and povar_problem_destroy; povar_get_points
+   returns X / w per landmark, povar_get_points_h the unit 4-vectors.  The
+   server does not take second-stage problems.  Errors: POVAR_EINVAL for
+   invalid sizes, indices, options or non-finite / zero inputs, POVAR_ENOMEM,
+   POVAR_EDEVICE, POVAR_ENUMERIC for a non-finite initial cost. */
+povar_status povar_refine_create(povar_ctx ctx, int32_t n_cams, int32_t n_pts, int64_t n_obs,
+                                 const int32_t* cam_idx, const int32_t* pt_idx, const double* meas,
+                                 const double* cams0, const double* pts0, const povar_options* opts,
+                                 povar_problem* out);
+/* Homogeneous landmarks at the current point, n_pts x 4 in the caller's
+   order: the unit 4-vectors of a second-stage problem, (X, 1) for a first-
+   stage one. */
+povar_status povar_get_points_h(povar_problem pb, double* out);
+/* Test hooks of the second stage (each may be NULL; host arrays, caller's
+   order).  povar_refine_debug_blocks: at the current point, U (n_cams x 144,
+   undamped J_p^T J_p), b_p (n_cams x 12, J_p^T r), G (n_pts x 16, the ambient
+   form B (B^T V_l B)^-1 B^T of the damped landmark block V_l at damping
+   `lambda`, B a basis of the landmark's tangent space), b_l (n_pts x 4) and
+   the cost (7).  povar_refine_debug_step: one step at `lambda` with series
+   order `order` (the problem's state is kept): dp the ambient camera update
+   (n_cams x 12), p_trial and x_trial (n_pts x 4) the retracted trial cameras
+   and landmarks, cost_trial the cost there.  POVAR_ESTATE on a first-stage or
+   finished problem; POVAR_ENUMERIC if a damped block could not be factored. */
+povar_status povar_refine_debug_blocks(povar_problem pb, double lambda, double* U, double* bp, double* G,
+                                       double* bl, double* cost);
+povar_status povar_refine_debug_step(povar_problem pb, double lambda, int32_t order, double* dp, double* p_trial,
+                                     double* x_trial, double* cost_trial);
+
 /* ---- kernel timing for roofline reports --------------------------------- */
 /* enable != 0: subsequent povar_step / povar_enqueue launches bracket every
    series kernel with HIP events on the context stream (graph replay is

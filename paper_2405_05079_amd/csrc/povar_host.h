@@ -90,6 +90,7 @@ struct povar_problem_s {
   povar::ArenaOffsets off{};
   size_t bytes = 0;
   void* arena = nullptr;
+  void* arena2 = nullptr;      // second-stage buffers (RiPoBA problems only)
   povar::DevProblem rec{};    // host copy of the device record
   povar::Batch batch{};       // batch of one
   hipGraphExec_t graph_exec = nullptr;     // one iteration
@@ -111,7 +112,7 @@ namespace povar {
 // Allocates and fills the device state of a problem and solves its initial
 // landmarks.  rec_dev: where the problem record lives (NULL: in its arena).
 povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, const povar_options* o,
-                          hipStream_t stream, povar_problem_s* pb, DevProblem* rec_dev, int32_t iter_limit);
+                          hipStream_t stream, povar_problem_s* pb, DevProblem* rec_dev, int32_t iter_limit, const double* pts0 = nullptr);
 size_t layout_footprint(const HostLayout& L, bool fp32);
 void unit_counts(const HostLayout& L, int32_t* units);
 // width values per camera, internal order -> caller's order

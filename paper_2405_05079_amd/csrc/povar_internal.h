@@ -149,7 +149,18 @@ struct DevProblem {
   double POVAR_GMEM* tr_cost;          // trace_cap entries
   double POVAR_GMEM* tr_lambda;
   int32_t POVAR_GMEM* tr_acc;
+
+  // Second stage (projective refinement, Eq. (7), RiPoBA of Sec. 4.3), FP64:
+  // landmarks are unit 4-vectors in rec64[b] (first 4 of each record).
+  int32_t stage;                       // 1: PoVar on Eq. (6); 2: RiPoBA on Eq. (7)
+  int32_t pad3;
+  double POVAR_GMEM* lm2;              // n_l x kLm2: G_j (10, sym4 order), b_l (4), z0 = G_j b_l (4)
+  double POVAR_GMEM* lin2;             // n_ch x kLin2 chunk partials: 40 sums of g (x) X X^T, b_p, sum W z0
+  double POVAR_GMEM* x2;               // n_p x 12 series term
+  double POVAR_GMEM* z2;               // n_l x 4 series landmark term
 };
+constexpr int kLm2 = 20;
+constexpr int kLin2 = 64;
 
 // Unit kinds of a launch.
 enum UnitKind {
@@ -215,6 +226,12 @@ hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s,
                                 hipEvent_t ev1 = nullptr);   // chunk or slot pass, + combine (not timed)
 hipError_t launch_cost_groups(const Batch& b, int trial, hipStream_t s);
 hipError_t launch_series_check(const Batch& b, bool fp32, int t, hipStream_t s);
+// second stage (RiPoBA): one LM iteration, and the landmark linearisation with
+// the cost at the current point (initial state)
+hipError_t launch_refine_iteration(const Batch& b, int order, hipStream_t s);
+hipError_t launch_refine_landmarks(const Batch& b, hipStream_t s);
+hipError_t launch_refine_cameras(const Batch& b, hipStream_t s);
+hipError_t launch_refine_step(const Batch& b, int order, hipStream_t s);
 hipError_t launch_retract(const Batch& b, bool fp32, hipStream_t s);
 hipError_t launch_decide(const Batch& b, hipStream_t s);
 

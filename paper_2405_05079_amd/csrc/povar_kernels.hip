@@ -1511,6 +1511,606 @@ __global__ void __launch_bounds__(kBlock) k_decide(Batch B) {
   if (c.iter >= c.iter_limit) c.done = 1;
 }
 
+// ============================================================ second stage
+// Projective refinement (RiPoBA): objective (7), r = pi(P_i X_j) - m with
+// pi(y) = (y0 / y2, y1 / y2), P_i on the unit sphere of R^12 and X_j on the
+// unit sphere of R^4; the camera update by the power series of the inverse
+// Riemannian Schur complement (27)-(29), the landmarks by back-substitution,
+// both retracted (Sec. 4.3).  FP64.  With y = P X, iw = 1 / y2 and
+// u = (y0 iw, y1 iw):  d pi / d y = iw [[1, 0, -u0], [0, 1, -u1]],
+// J_l = (d pi / d y) P (2 x 4) and J_p[r][4a + c] = (d pi / d y)[r][a] X_c.
+// Tangent projections are applied in the KKT form (ambient coordinates):
+// K_i = U_l^-1 - w w^T / (p^T w), w = U_l^-1 p, and likewise
+// G_j = V_l^-1 - v v^T / (x^T v), v = V_l^-1 x, for the landmark blocks.
+struct Proj2 {
+  double iw, u0, u1;
+  double jl0[4], jl1[4];   // rows of J_l
+};
+
+__device__ __forceinline__ Proj2 project2(const double (&P)[12], const double (&X)[4]) {
+  Proj2 g;
+  const double y0 = P[0] * X[0] + P[1] * X[1] + P[2] * X[2] + P[3] * X[3];
+  const double y1 = P[4] * X[0] + P[5] * X[1] + P[6] * X[2] + P[7] * X[3];
+  const double y2 = P[8] * X[0] + P[9] * X[1] + P[10] * X[2] + P[11] * X[3];
+  g.iw = 1.0 / y2;
+  g.u0 = y0 * g.iw;
+  g.u1 = y1 * g.iw;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    g.jl0[c] = g.iw * (P[c] - g.u0 * P[8 + c]);
+    g.jl1[c] = g.iw * (P[4 + c] - g.u1 * P[8 + c]);
+  }
+  return g;
+}
+
+// (d pi / d y)^T s
+__device__ __forceinline__ void dpi_t(const Proj2& g, double s0, double s1, double (&h)[3]) {
+  h[0] = g.iw * s0;
+  h[1] = g.iw * s1;
+  h[2] = -g.iw * (g.u0 * s0 + g.u1 * s1);
+}
+
+// J_p x for a camera-space vector x (12 values, row-major 3 x 4)
+__device__ __forceinline__ void jp_apply(const Proj2& g, const double (&x)[12], const double (&X)[4], double& s0,
+                                         double& s1) {
+  const double a0 = x[0] * X[0] + x[1] * X[1] + x[2] * X[2] + x[3] * X[3];
+  const double a1 = x[4] * X[0] + x[5] * X[1] + x[6] * X[2] + x[7] * X[3];
+  const double a2 = x[8] * X[0] + x[9] * X[1] + x[10] * X[2] + x[11] * X[3];
+  s0 = g.iw * (a0 - g.u0 * a2);
+  s1 = g.iw * (a1 - g.u1 * a2);
+}
+
+__host__ __device__ constexpr int sym4(int a, int b) { return a <= b ? (a * 7 - a * a) / 2 + b : (b * 7 - b * b) / 2 + a; }
+
+// Inverse of a symmetric positive-definite 4x4 block (10 values, sym4 order)
+// by Cholesky; false if a pivot is not positive.
+__device__ __forceinline__ bool sym4_inv(const double (&v)[10], double (&out)[10]) {
+  double L[4][4], Li[4][4], rd[4];
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double d = v[sym4(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+    if (!(d > 0.0)) { ok = false; d = 1.0; }
+    d = sqrt(d);
+    L[j][j] = d;
+    rd[j] = 1.0 / d;
+#pragma unroll
+    for (int r = j + 1; r < 4; ++r) {
+      double t = v[sym4(r, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= L[r][k] * L[j][k];
+      L[r][j] = t * rd[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    Li[j][j] = rd[j];
+#pragma unroll
+    for (int r = j + 1; r < 4; ++r) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = j; k < r; ++k) t += L[r][k] * Li[k][j];
+      Li[r][j] = -t * rd[r];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = a; b < 4; ++b) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = b; k < 4; ++k) t += Li[k][a] * Li[k][b];
+      out[sym4(a, b)] = t;
+    }
+  return ok;
+}
+
+// V (10) and b_l (4) contributions of one observation
+__device__ __forceinline__ void refine_lm_terms(const Proj2& g, double r0, double r1, double (&vb)[14]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int b = a; b < 4; ++b) vb[sym4(a, b)] = g.jl0[a] * g.jl0[b] + g.jl1[a] * g.jl1[b];
+    vb[10 + a] = g.jl0[a] * r0 + g.jl1[a] * r1;
+  }
+}
+
+// The damped, projected, inverted landmark block G_j, b_l and z0 = G_j b_l.
+__device__ __forceinline__ void refine_lm_finish(DevProblem& D, int j, const double (&vb)[14], const double (&X)[4],
+                                                 double lam) {
+  double v[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) v[k] = vb[k];
+  const double dmax = fmax(fmax(v[0], v[4]), fmax(v[7], v[9]));
+  v[0] += lam * fmax(v[0], 1e-12 * dmax);
+  v[4] += lam * fmax(v[4], 1e-12 * dmax);
+  v[7] += lam * fmax(v[7], 1e-12 * dmax);
+  v[9] += lam * fmax(v[9], 1e-12 * dmax);
+  double vi[10];
+  const bool ok = sym4_inv(v, vi);
+  double w[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+    w[a] = vi[sym4(a, 0)] * X[0] + vi[sym4(a, 1)] * X[1] + vi[sym4(a, 2)] * X[2] + vi[sym4(a, 3)] * X[3];
+  const double xw = X[0] * w[0] + X[1] * w[1] + X[2] * w[2] + X[3] * w[3];
+  const double ixw = 1.0 / xw;
+  double G[10];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = a; b < 4; ++b) G[sym4(a, b)] = vi[sym4(a, b)] - w[a] * w[b] * ixw;
+  double* o = D.lm2 + (size_t)j * kLm2;
+#pragma unroll
+  for (int k = 0; k < 10; ++k) o[k] = G[k];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    o[10 + a] = vb[10 + a];
+    o[14 + a] = G[sym4(a, 0)] * vb[10] + G[sym4(a, 1)] * vb[11] + G[sym4(a, 2)] * vb[12] + G[sym4(a, 3)] * vb[13];
+  }
+  o[18] = 0.0;
+  o[19] = 0.0;
+  if (!(ok && xw > 0.0)) atomicOr(&D.ctl.status, 1);
+}
+
+// k_refine_landmarks: per landmark V_j, b_l, G_j and z0 at the current point,
+// and the cost partial of each packet (Eq. (7)).
+__global__ void __launch_bounds__(kBlock) k_refine_landmarks(Batch B) {
+  int p, q;
+  if (!map_wave(B, kUnitPacket, p, q)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done) return;
+  const double* __restrict__ P = D.ctl.pcur ? D.P64[1] : D.P64[0];
+  const double* __restrict__ Xr = D.ctl.lcur ? D.rec64[1] : D.rec64[0];
+  const double lam = D.ctl.lambda;
+  const int lane = lane_id(), off = q * kWave;
+  const uint32_t code = D.pk_code[off + lane];
+  const double2 mraw = D.pk_m64[off + lane];
+  const int2 hdr = D.pk_hdr[q];
+  const int n = hdr.x, lm0 = hdr.y;
+  double ftot = 0.0;
+  if (n == 0) {
+    // continuation slot of a landmark with more than 64 observations
+  } else if (n <= kWave) {
+    const bool act = lane < n;
+    const int key = act ? (int)(code >> kCamBits) : kWave + lane;
+    double vb[14], X[4] = {0.0, 0.0, 0.0, 1.0}, f = 0.0;
+#pragma unroll
+    for (int k = 0; k < 14; ++k) vb[k] = 0.0;
+    if (act) {
+      double Pc[12];
+      load12(P + (size_t)(code & kCamMask) * kCam, Pc);
+      load4(Xr + (size_t)(lm0 + key) * kRec, X[0], X[1], X[2], X[3]);
+      const Proj2 g = project2(Pc, X);
+      const double r0 = g.u0 - mraw.x, r1 = g.u1 - mraw.y;
+      refine_lm_terms(g, r0, r1, vb);
+      f = r0 * r0 + r1 * r1;
+    }
+    seg_sum(vb, seg_links(key));
+    ftot = wave_sum(f);
+    if (act && run_tail(key)) refine_lm_finish(D, lm0 + key, vb, X, lam);
+  } else {
+    double vb[14], X[4], f = 0.0;
+#pragma unroll
+    for (int k = 0; k < 14; ++k) vb[k] = 0.0;
+    load4(Xr + (size_t)lm0 * kRec, X[0], X[1], X[2], X[3]);
+    for (int e = off + lane; e < off + n; e += kWave) {
+      double Pc[12], t[14];
+      load12(P + (size_t)(D.pk_code[e] & kCamMask) * kCam, Pc);
+      const double2 m = D.pk_m64[e];
+      const Proj2 g = project2(Pc, X);
+      const double r0 = g.u0 - m.x, r1 = g.u1 - m.y;
+      refine_lm_terms(g, r0, r1, t);
+#pragma unroll
+      for (int k = 0; k < 14; ++k) vb[k] += t[k];
+      f += r0 * r0 + r1 * r1;
+    }
+#pragma unroll
+    for (int k = 0; k < 14; ++k) vb[k] = wave_sum(vb[k]);
+    ftot = wave_sum(f);
+    if (lane == 0) refine_lm_finish(D, lm0, vb, X, lam);
+  }
+  if (lane == 0) D.cost_part[q] = ftot;
+}
+
+// k_refine_cameras: per camera chunk, 64 FP64 sums: U_i as 40 sums of
+// g (x) X X^T (d pi^T d pi = iw^2 [[1,0,-u0],[0,1,-u1],[-u0,-u1,|u|^2]] has
+// the four distinct entries g), b_p = sum J_p^T r and sum W z0 = sum J_p^T J_l z0.
+__global__ void __launch_bounds__(kBlock) k_refine_cameras(Batch B) {
+  int p, ch;
+  if (!map_block(B, kUnitChunk, p, ch)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done) return;
+  const int4 meta = D.ch_meta[ch];
+  const int cam = meta.x, beg = meta.y, end = meta.z;
+  double Pc[12];
+  load12((D.ctl.pcur ? D.P64[1] : D.P64[0]) + (size_t)cam * kCam, Pc);
+  const double* __restrict__ Xr = D.ctl.lcur ? D.rec64[1] : D.rec64[0];
+  double acc[kLin2];
+#pragma unroll
+  for (int k = 0; k < kLin2; ++k) acc[k] = 0.0;
+#pragma unroll 1
+  for (int r = 0; r < kPerLane; ++r) {
+    const int e = beg + r * kBlock + (int)threadIdx.x;
+    if (e >= end) break;
+    const int j = D.cm_lm[e];
+    const double2 m = D.cm_m64[e];
+    double X[4], z[4];
+    load4(Xr + (size_t)j * kRec, X[0], X[1], X[2], X[3]);
+    load4(D.lm2 + (size_t)j * kLm2 + 14, z[0], z[1], z[2], z[3]);
+    const Proj2 g = project2(Pc, X);
+    const double r0 = g.u0 - m.x, r1 = g.u1 - m.y;
+    const double w2 = g.iw * g.iw;
+    const double gg[4] = {w2, -g.u0 * w2, -g.u1 * w2, (g.u0 * g.u0 + g.u1 * g.u1) * w2};
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = a; b < 4; ++b) {
+        const double xx = X[a] * X[b];
+#pragma unroll
+        for (int gi = 0; gi < 4; ++gi) acc[gi * 10 + sym4(a, b)] += gg[gi] * xx;
+      }
+    double hb[3], hz[3];
+    dpi_t(g, r0, r1, hb);
+    const double v0 = g.jl0[0] * z[0] + g.jl0[1] * z[1] + g.jl0[2] * z[2] + g.jl0[3] * z[3];
+    const double v1 = g.jl1[0] * z[0] + g.jl1[1] * z[1] + g.jl1[2] * z[2] + g.jl1[3] * z[3];
+    dpi_t(g, v0, v1, hz);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        acc[40 + 4 * a + c] += hb[a] * X[c];
+        acc[52 + 4 * a + c] += hz[a] * X[c];
+      }
+  }
+  __shared__ double red[kWavesPerBlock][kLin2];
+  const int wv = threadIdx.x >> 6;
+  {
+    const double sv = reduce_scatter<kLin2>(acc);
+    red[wv][rs_index<kLin2>(lane_id())] = sv;
+  }
+  __syncthreads();
+  if (threadIdx.x < kLin2) {
+    const int k = threadIdx.x;
+    D.lin2[(size_t)ch * kLin2 + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  }
+}
+
+// which of the four g sums feeds U[(a, c), (a2, c2)] (rows a, a2 of
+// d pi^T d pi); -1 for the zero entries (0, 1)
+__device__ __forceinline__ int refine_gsel(int a, int a2) {
+  const int lo = a < a2 ? a : a2, hi = a < a2 ? a2 : a;
+  if (lo == hi) return lo == 2 ? 3 : 0;
+  if (lo == 0 && hi == 1) return -1;
+  return hi == 2 ? (lo == 0 ? 1 : 2) : -1;
+}
+
+// k_refine_prep: one lane per camera.  U_i from the chunk sums, Marquardt
+// damping, Cholesky, the tangent inverse K_i (KKT form), g_i = b_p - sum W z0,
+// x0 = acc = -K_i g_i.
+__global__ void __launch_bounds__(kWave) k_refine_prep(Batch B) {
+  int p, w;
+  if (!map_wave<kWave>(B, kUnitCamWave, p, w)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done) return;
+  const int i = w * kWave + lane_id();
+  if (i >= D.n_p) return;
+  const double lam = D.ctl.lambda;
+  double s[kLin2];
+#pragma unroll
+  for (int k = 0; k < kLin2; ++k) s[k] = 0.0;
+  for (int q = D.cam_ch[i]; q < D.cam_ch[i + 1]; ++q) {
+    const double* part = D.lin2 + (size_t)q * kLin2;
+#pragma unroll
+    for (int k = 0; k < kLin2; ++k) s[k] += part[k];
+  }
+  double L[78];
+#pragma unroll
+  for (int r = 0; r < 12; ++r)
+#pragma unroll
+    for (int c = 0; c <= r; ++c) {
+      const int gs = refine_gsel(r >> 2, c >> 2);
+      L[tri(r, c)] = gs < 0 ? 0.0 : s[gs * 10 + sym4(r & 3, c & 3)];
+    }
+  double dmax = 0.0;
+#pragma unroll
+  for (int r = 0; r < 12; ++r) dmax = fmax(dmax, L[tri(r, r)]);
+#pragma unroll
+  for (int r = 0; r < 12; ++r) L[tri(r, r)] += lam * fmax(L[tri(r, r)], 1e-12 * dmax);
+  double pv[12];
+  load12((D.ctl.pcur ? D.P64[1] : D.P64[0]) + (size_t)i * kCam, pv);
+  bool ok = true;
+  double rd[12];
+#pragma unroll
+  for (int j = 0; j < 12; ++j) {
+    double d = L[tri(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= L[tri(j, k)] * L[tri(j, k)];
+    if (!(d > 0.0)) { ok = false; d = 1.0; }
+    d = sqrt(d);
+    L[tri(j, j)] = d;
+    rd[j] = 1.0 / d;
+#pragma unroll
+    for (int r = j + 1; r < 12; ++r) {
+      double v = L[tri(r, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= L[tri(r, k)] * L[tri(j, k)];
+      L[tri(r, j)] = v * rd[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 12; ++j) {
+    L[tri(j, j)] = rd[j];
+#pragma unroll
+    for (int r = j + 1; r < 12; ++r) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = j; k < r; ++k) v += L[tri(r, k)] * L[tri(k, j)];
+      L[tri(r, j)] = -v * rd[r];
+    }
+  }
+  double wp[12], h = 0.0;
+  {
+    double u[12];
+#pragma unroll
+    for (int r = 0; r < 12; ++r) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k <= r; ++k) v += L[tri(r, k)] * pv[k];
+      u[r] = v;
+      h += v * v;
+    }
+#pragma unroll
+    for (int r = 0; r < 12; ++r) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = r; k < 12; ++k) v += L[tri(k, r)] * u[k];
+      wp[r] = v;
+    }
+  }
+  const double ih = 1.0 / h;
+  double gv[12], x0[12];
+#pragma unroll
+  for (int r = 0; r < 12; ++r) {
+    gv[r] = s[40 + r] - s[52 + r];
+    D.g64[(size_t)i * kCam + r] = gv[r];
+    x0[r] = 0.0;
+  }
+  double* K64 = D.K64 + (size_t)i * kCamMat;
+#pragma unroll
+  for (int r = 0; r < 12; ++r) {
+#pragma unroll
+    for (int c = 0; c <= r; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = r; k < 12; ++k) v += L[tri(k, r)] * L[tri(k, c)];
+      v -= wp[r] * wp[c] * ih;
+      if (!ok) v = 0.0;
+      K64[r * 12 + c] = v;
+      K64[c * 12 + r] = v;
+      x0[r] -= v * gv[c];
+      if (c != r) x0[c] -= v * gv[r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 12; ++r) {
+    D.x2[(size_t)i * kCam + r] = x0[r];
+    D.acc[(size_t)i * kCam + r] = x0[r];
+  }
+  if (!ok) atomicOr(&D.ctl.status, 1);
+}
+
+// W^T y for one observation of camera vector y (12): J_l^T J_p y
+__device__ __forceinline__ void refine_wt(const Proj2& g, const double (&y)[12], const double (&X)[4],
+                                          double (&o)[4]) {
+  double s0, s1;
+  jp_apply(g, y, X, s0, s1);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) o[c] = g.jl0[c] * s0 + g.jl1[c] * s1;
+}
+
+// Landmark pass over packets shared by the series (z_j = G_j sum W^T x_i) and
+// the back-substitution (dl_j = -G_j (b_l + sum W^T dp_i), then the landmark
+// is retracted into the other buffer).
+template <bool Update>
+__device__ __forceinline__ void refine_landmark_slot(DevProblem& D, int q) {
+  const double* __restrict__ P = D.ctl.pcur ? D.P64[1] : D.P64[0];
+  const int lc = D.ctl.lcur;
+  const double* __restrict__ Xr = lc ? D.rec64[1] : D.rec64[0];
+  const double* __restrict__ Y = Update ? D.acc : D.x2;
+  const int lane = lane_id(), off = q * kWave;
+  const uint32_t code = D.pk_code[off + lane];
+  const int2 hdr = D.pk_hdr[q];
+  const int n = hdr.x, lm0 = hdr.y;
+  if (n == 0) return;
+  double wt[4] = {0.0, 0.0, 0.0, 0.0}, X[4] = {0.0, 0.0, 0.0, 1.0};
+  int j = lm0;
+  bool tail;
+  if (n <= kWave) {
+    const bool act = lane < n;
+    const int key = act ? (int)(code >> kCamBits) : kWave + lane;
+    j = lm0 + (act ? key : 0);
+    if (act) {
+      const int c = (int)(code & kCamMask);
+      double Pc[12], y[12];
+      load12(P + (size_t)c * kCam, Pc);
+      load12(Y + (size_t)c * kCam, y);
+      load4(Xr + (size_t)j * kRec, X[0], X[1], X[2], X[3]);
+      const Proj2 g = project2(Pc, X);
+      refine_wt(g, y, X, wt);
+    }
+    seg_sum(wt, seg_links(key));
+    tail = act && run_tail(key);
+  } else {
+    load4(Xr + (size_t)lm0 * kRec, X[0], X[1], X[2], X[3]);
+    for (int e = off + lane; e < off + n; e += kWave) {
+      const int c = (int)(D.pk_code[e] & kCamMask);
+      double Pc[12], y[12], t[4];
+      load12(P + (size_t)c * kCam, Pc);
+      load12(Y + (size_t)c * kCam, y);
+      const Proj2 g = project2(Pc, X);
+      refine_wt(g, y, X, t);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wt[k] += t[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) wt[k] = wave_sum(wt[k]);
+    tail = lane == 0;
+  }
+  if (!tail) return;
+  const double* G = D.lm2 + (size_t)j * kLm2;
+  double v[4];
+  if (Update) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) v[a] = G[10 + a] + wt[a];
+  } else {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) v[a] = wt[a];
+  }
+  double z[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+    z[a] = G[sym4(a, 0)] * v[0] + G[sym4(a, 1)] * v[1] + G[sym4(a, 2)] * v[2] + G[sym4(a, 3)] * v[3];
+  if (Update) {
+    double xn[4], nrm = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      xn[a] = X[a] - z[a];
+      nrm += xn[a] * xn[a];
+    }
+    const double inv = 1.0 / sqrt(nrm);
+    double* o = (lc ? D.rec64[0] : D.rec64[1]) + (size_t)j * kRec;
+    store4(o, xn[0] * inv, xn[1] * inv, xn[2] * inv, xn[3] * inv);
+    store4(o + 4, 0.0, 0.0, 0.0, 0.0);
+  } else {
+    store4(D.z2 + (size_t)j * 4, z[0], z[1], z[2], z[3]);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_refine_series_landmark(Batch B, int t) {
+  int p, q;
+  if (!map_wave(B, kUnitPacket, p, q)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done || t > D.ctl.order) return;
+  refine_landmark_slot<false>(D, q);
+}
+
+__global__ void __launch_bounds__(kBlock) k_refine_landmark_update(Batch B) {
+  int p, q;
+  if (!map_wave(B, kUnitPacket, p, q)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done) return;
+  refine_landmark_slot<true>(D, q);
+}
+
+// Camera pass of the series: t_i = sum_k W_k z_j, x_i = K_i t_i, acc_i += x_i.
+// The workgroup of a camera's first chunk walks all of its observations.
+__global__ void __launch_bounds__(kBlock) k_refine_series_camera(Batch B, int t) {
+  int p, ch;
+  if (!map_block(B, kUnitChunk, p, ch)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done || t > D.ctl.order) return;
+  const int4 meta = D.ch_meta[ch];
+  const int cam = meta.x;
+  if (D.cam_ch[cam] != ch) return;
+  const int beg = meta.y, end = D.ch_meta[D.cam_ch[cam + 1] - 1].z;
+  double Pc[12];
+  load12((D.ctl.pcur ? D.P64[1] : D.P64[0]) + (size_t)cam * kCam, Pc);
+  double kr[12];
+  if (threadIdx.x < 12) load12(D.K64 + (size_t)cam * kCamMat + threadIdx.x * 12, kr);
+  const double* __restrict__ Xr = D.ctl.lcur ? D.rec64[1] : D.rec64[0];
+  double acc[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+  for (int e = beg + (int)threadIdx.x; e < end; e += kBlock) {
+    const int j = D.cm_lm[e];
+    double X[4], z[4];
+    load4(Xr + (size_t)j * kRec, X[0], X[1], X[2], X[3]);
+    load4(D.z2 + (size_t)j * 4, z[0], z[1], z[2], z[3]);
+    const Proj2 g = project2(Pc, X);
+    const double v0 = g.jl0[0] * z[0] + g.jl0[1] * z[1] + g.jl0[2] * z[2] + g.jl0[3] * z[3];
+    const double v1 = g.jl1[0] * z[0] + g.jl1[1] * z[1] + g.jl1[2] * z[2] + g.jl1[3] * z[3];
+    double h[3];
+    dpi_t(g, v0, v1, h);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[4 * a + c] += h[a] * X[c];
+  }
+  __shared__ double red[kWavesPerBlock][12];
+  __shared__ double tv[12];
+  const int wv = threadIdx.x >> 6;
+  {
+    const double sv = reduce_scatter<16>(acc);
+    const int idx = rs_index<16>(lane_id());
+    if (lane_id() < 16 && idx < 12) red[wv][idx] = sv;
+  }
+  __syncthreads();
+  if (threadIdx.x < 12) tv[threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
+                                          red[3][threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x < 12) {
+    double x = 0.0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) x += kr[c] * tv[c];
+    D.x2[(size_t)cam * kCam + threadIdx.x] = x;
+    D.acc[(size_t)cam * kCam + threadIdx.x] += x;
+  }
+}
+
+// Camera retraction of the second stage: p <- (p + acc) / |p + acc|.
+__global__ void __launch_bounds__(kWave) k_refine_retract(Batch B) {
+  int p, w;
+  if (!map_wave<kWave>(B, kUnitCamWave, p, w)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done) return;
+  const int i = w * kWave + lane_id();
+  if (i >= D.n_p) return;
+  const int pc = D.ctl.pcur;
+  double q[12], nrm = 0.0;
+  load12((pc ? D.P64[1] : D.P64[0]) + (size_t)i * kCam, q);
+#pragma unroll
+  for (int r = 0; r < 12; ++r) {
+    q[r] += D.acc[(size_t)i * kCam + r];
+    nrm += q[r] * q[r];
+  }
+  const double inv = 1.0 / sqrt(nrm);
+  double* o = (pc ? D.P64[0] : D.P64[1]) + (size_t)i * kCam;
+#pragma unroll
+  for (int r = 0; r < 12; r += 4) store4(o + r, q[r] * inv, q[r + 1] * inv, q[r + 2] * inv, q[r + 3] * inv);
+}
+
+// Cost (7) at the trial cameras and landmarks, one partial per packet.
+__global__ void __launch_bounds__(kBlock) k_refine_cost(Batch B) {
+  int p, q;
+  if (!map_wave(B, kUnitPacket, p, q)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done) return;
+  const double* __restrict__ P = D.ctl.pcur ? D.P64[0] : D.P64[1];
+  const double* __restrict__ Xr = D.ctl.lcur ? D.rec64[0] : D.rec64[1];
+  const int lane = lane_id(), off = q * kWave;
+  const int2 hdr = D.pk_hdr[q];
+  const int n = hdr.x, lm0 = hdr.y;
+  double f = 0.0;
+  if (n > 0) {
+    // a landmark with more than 64 observations runs over its continuation slots
+    for (int e = off + lane; e < off + n; e += kWave) {
+      const uint32_t code = D.pk_code[e];
+      const int j = n <= kWave ? lm0 + (int)(code >> kCamBits) : lm0;
+      double Pc[12], X[4];
+      load12(P + (size_t)(code & kCamMask) * kCam, Pc);
+      load4(Xr + (size_t)j * kRec, X[0], X[1], X[2], X[3]);
+      const double2 m = D.pk_m64[e];
+      const Proj2 g = project2(Pc, X);
+      const double r0 = g.u0 - m.x, r1 = g.u1 - m.y;
+      f += r0 * r0 + r1 * r1;
+    }
+  }
+  f = wave_sum(f);
+  if (lane == 0) D.cost_part[q] = f;
+}
+
 // ---------------------------------------------------------------- launchers
 static inline dim3 blocks_for(int units, int units_per_block) {
   return dim3((unsigned)((units + units_per_block - 1) / units_per_block));
@@ -1623,6 +2223,44 @@ hipError_t launch_retract(const Batch& b, bool fp32, hipStream_t s) {
   if (fp32) hipLaunchKernelGGL(k_retract<float>, g, dim3(kWave), 0, s, b);
   else hipLaunchKernelGGL(k_retract<double>, g, dim3(kWave), 0, s, b);
   return hipGetLastError();
+}
+
+hipError_t launch_refine_landmarks(const Batch& b, hipStream_t s) {
+  if (b.total[kUnitPacket] == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_refine_landmarks, blocks_for(b.total[kUnitPacket], kWavesPerBlock), dim3(kBlock), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_cameras(const Batch& b, hipStream_t s) {
+  if (b.total[kUnitChunk] == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_refine_cameras, blocks_for(b.total[kUnitChunk], 1), dim3(kBlock), 0, s, b);
+  return hipGetLastError();
+}
+
+// camera blocks through the trial cost (the landmark blocks and the camera
+// chunk sums of the current point must be in place)
+hipError_t launch_refine_step(const Batch& b, int order, hipStream_t s) {
+  const dim3 gp = blocks_for(b.total[kUnitPacket], kWavesPerBlock);
+  const dim3 gc = blocks_for(b.total[kUnitChunk], 1);
+  const dim3 gw = blocks_for(b.total[kUnitCamWave], 1);
+  hipLaunchKernelGGL(k_refine_prep, gw, dim3(kWave), 0, s, b);
+  for (int t = 1; t <= order; ++t) {
+    hipLaunchKernelGGL(k_refine_series_landmark, gp, dim3(kBlock), 0, s, b, t);
+    hipLaunchKernelGGL(k_refine_series_camera, gc, dim3(kBlock), 0, s, b, t);
+  }
+  hipLaunchKernelGGL(k_refine_landmark_update, gp, dim3(kBlock), 0, s, b);
+  hipLaunchKernelGGL(k_refine_retract, gw, dim3(kWave), 0, s, b);
+  hipLaunchKernelGGL(k_refine_cost, gp, dim3(kBlock), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_iteration(const Batch& b, int order, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_refine_landmarks(b, s)) != hipSuccess) return e;
+  if ((e = launch_refine_cameras(b, s)) != hipSuccess) return e;
+  if ((e = launch_refine_step(b, order, s)) != hipSuccess) return e;
+  if ((e = launch_cost_groups(b, 1, s)) != hipSuccess) return e;
+  return launch_decide(b, s);
 }
 
 hipError_t launch_decide(const Batch& b, hipStream_t s) {

@@ -703,7 +703,8 @@ static void upload(std::vector<char>& staging, size_t off, const std::vector<T>&
 // Builds the device state of a problem from a host layout and initial
 // cameras: one arena allocation, filled from a single host staging image.
 povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, const povar_options* o,
-                          hipStream_t stream, povar_problem_s* pb, DevProblem* rec_dev, int32_t iter_limit) {
+                          hipStream_t stream, povar_problem_s* pb, DevProblem* rec_dev, int32_t iter_limit,
+                          const double* pts0) {
   pb->ctx = ctx;
   pb->opt = *o;
   pb->fp32 = o->precision == POVAR_PREC_FP32_BULK;
@@ -827,6 +828,43 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.tr_lambda = (double*)dp(A.tr_lambda);
   R.tr_acc = (int32_t*)dp(A.tr_acc);
 
+  // second stage: initial landmarks (unit 4-vectors) and its own buffers
+  R.stage = pts0 ? 2 : 1;
+  std::vector<double> X4;
+  if (pts0) {
+    X4.assign((size_t)H.n_l * kRec, 0.0);
+    for (int32_t jj = 0; jj < H.n_l; ++jj) {
+      const int32_t e = H.int2ext[jj];
+      double nrm = 0.0;
+      for (int k = 0; k < 4; ++k) {
+        const double v = pts0[(size_t)e * 4 + k];
+        if (!std::isfinite(v)) {
+          set_error(ctx, "initial point %d is not finite", e);
+          return POVAR_EINVAL;
+        }
+        nrm += v * v;
+      }
+      if (!(nrm > 0.0)) {
+        set_error(ctx, "initial point %d is zero", e);
+        return POVAR_EINVAL;
+      }
+      for (int k = 0; k < 4; ++k) X4[(size_t)jj * kRec + k] = pts0[(size_t)e * 4 + k] / std::sqrt(nrm);
+    }
+    const size_t b_lm2 = align_up((size_t)H.n_l * kLm2 * 8), b_lin2 = align_up((size_t)H.n_ch * kLin2 * 8);
+    const size_t b_x2 = align_up((size_t)H.n_p * kCam * 8), b_z2 = align_up((size_t)H.n_l * 4 * 8);
+    e = hipMalloc(&pb->arena2, b_lm2 + b_lin2 + b_x2 + b_z2);
+    if (e != hipSuccess) {
+      pb->arena2 = nullptr;
+      set_error(ctx, "hipMalloc of the second-stage buffers failed: %s", hipGetErrorString(e));
+      return POVAR_ENOMEM;
+    }
+    char* b2 = static_cast<char*>(pb->arena2);
+    R.lm2 = (double*)b2;
+    R.lin2 = (double*)(b2 + b_lm2);
+    R.x2 = (double*)(b2 + b_lm2 + b_lin2);
+    R.z2 = (double*)(b2 + b_lm2 + b_lin2 + b_x2);
+  }
+
   Ctl& c = R.ctl;
   c.lambda = o->lambda0;
   c.need_lin = 1;
@@ -865,6 +903,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
     upload(img, A.run_off, H.run_off);
   }
   upload(img, A.P64[0], P64);
+  if (pts0) upload(img, A.rec64[0], X4);
   if (pb->fp32) upload(img, A.S32[0], S32);
   else upload(img, A.S64[0], S64);
   std::memcpy(img.data() + A.rec, &R, sizeof(R));
@@ -886,8 +925,13 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   B.lds_grid = lds_grid;
   B.coop_cams = pb->fp32 && R.s_stride == kSerLine ? 1 : 0;
   B.pad = 0;
-  // initial landmarks and cost, Eq. (8)-(9)
-  HIP_TRY(ctx, launch_landmark_solve(B, 0, stream));
+  if (pts0) {
+    // second stage: the cost (7) at the given cameras and landmarks
+    HIP_TRY(ctx, launch_refine_landmarks(B, stream));
+  } else {
+    // initial landmarks and cost, Eq. (8)-(9)
+    HIP_TRY(ctx, launch_landmark_solve(B, 0, stream));
+  }
   HIP_TRY(ctx, launch_cost_groups(B, 0, stream));
   HIP_TRY(ctx, launch_cost_finalize(B, 0, stream));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
@@ -957,6 +1001,7 @@ static hipError_t enqueue_series(povar_problem_s* pb, int order, bool timed) {
 hipError_t enqueue_iteration(povar_problem_s* pb, bool timed) {
   hipError_t e;
   const Batch& B = pb->batch;
+  if (pb->rec.stage == 2) return launch_refine_iteration(B, pb->opt.series_order, pb->stream);
   if ((e = launch_linearize(B, pb->fp32, 0, pb->stream)) != hipSuccess) return e;
   if ((e = launch_camera_prep(B, pb->fp32, pb->stream)) != hipSuccess) return e;
   if ((e = enqueue_series(pb, pb->opt.series_order, timed)) != hipSuccess) return e;
@@ -1239,6 +1284,7 @@ povar_status povar_problem_destroy(povar_problem pb) {
   if (pb->graph_exec_k) (void)hipGraphExecDestroy(pb->graph_exec_k);
   for (auto ev : pb->events) (void)hipEventDestroy(ev);
   if (pb->arena) (void)hipFree(pb->arena);
+  if (pb->arena2) (void)hipFree(pb->arena2);
   if (pb->ctx && pb->owned_by_ctx) pb->ctx->live_problems -= 1;
   delete pb;
   return POVAR_OK;
@@ -1306,7 +1352,53 @@ povar_status povar_get_points(povar_problem pb, double* out) {
   if (!pb || !out) return POVAR_EINVAL;
   Ctl c;
   HIP_TRY(pb->ctx, read_ctl(pb, &c));
-  return copy_landmark_vec(pb, pb->rec.rec64[c.lcur], kRec, 4, 3, out);
+  if (pb->rec.stage != 2) return copy_landmark_vec(pb, pb->rec.rec64[c.lcur], kRec, 4, 3, out);
+  std::vector<double> h((size_t)pb->L.n_l * 4);
+  const povar_status st = copy_landmark_vec(pb, pb->rec.rec64[c.lcur], kRec, 0, 4, h.data());
+  if (st != POVAR_OK) return st;
+  for (int32_t j = 0; j < pb->L.n_l; ++j)
+    for (int k = 0; k < 3; ++k) out[(size_t)j * 3 + k] = h[(size_t)j * 4 + k] / h[(size_t)j * 4 + 3];
+  return POVAR_OK;
+}
+
+povar_status povar_get_points_h(povar_problem pb, double* out) {
+  if (!pb || !out) return POVAR_EINVAL;
+  Ctl c;
+  HIP_TRY(pb->ctx, read_ctl(pb, &c));
+  return copy_landmark_vec(pb, pb->rec.rec64[c.lcur], kRec, pb->rec.stage == 2 ? 0 : 4, 4, out);
+}
+
+povar_status povar_refine_create(povar_ctx ctx, int32_t n_cams, int32_t n_pts, int64_t n_obs,
+                                 const int32_t* cam_idx, const int32_t* pt_idx, const double* meas,
+                                 const double* cams0, const double* pts0, const povar_options* opts,
+                                 povar_problem* out) {
+  if (!ctx || !out) return POVAR_EINVAL;
+  *out = nullptr;
+  povar_status st = check_options(ctx, opts);
+  if (st != POVAR_OK) return st;
+  if (!cams0 || !pts0) {
+    set_error(ctx, "cams0 and pts0 must not be NULL");
+    return POVAR_EINVAL;
+  }
+  if (opts->precision != POVAR_PREC_FP64 || opts->manifold != POVAR_MANIFOLD_SPHERE || opts->series_rtol != 0.0) {
+    set_error(ctx, "the second stage runs in FP64 on the spheres with a fixed series order");
+    return POVAR_EINVAL;
+  }
+  (void)hipSetDevice(ctx->device);
+  HostLayout L;
+  st = build_layout(ctx, n_cams, n_pts, n_obs, cam_idx, pt_idx, meas, false, L);
+  if (st != POVAR_OK) return st;
+  auto* pb = new povar_problem_s();
+  pb->ctx = ctx;
+  pb->owned_by_ctx = true;
+  ctx->live_problems += 1;
+  st = problem_init(ctx, std::move(L), cams0, opts, ctx->stream, pb, nullptr, INT_MAX, pts0);
+  if (st != POVAR_OK) {
+    povar_problem_destroy(pb);
+    return st;
+  }
+  *out = pb;
+  return POVAR_OK;
 }
 
 
@@ -1340,6 +1432,10 @@ povar_status povar_get_state(povar_problem pb, double* cams, double* lambda, int
 
 povar_status povar_set_state(povar_problem pb, const double* cams, double lambda, int32_t iter) {
   if (!pb || !cams || !(lambda > 0.0) || iter < 0) return POVAR_EINVAL;
+  if (pb->rec.stage == 2) {
+    set_error(pb->ctx, "povar_set_state restores first-stage problems (their landmarks follow from the cameras)");
+    return POVAR_ESTATE;
+  }
   povar_ctx ctx = pb->ctx;
   (void)hipSetDevice(ctx->device);
   Ctl c;
@@ -1395,6 +1491,10 @@ povar_status povar_set_state(povar_problem pb, const double* cams, double lambda
 povar_status povar_debug_linearize(povar_problem pb, double* U, double* bp, double* g, double* Vp, double* X,
                                    double* z0, double* cost) {
   if (!pb) return POVAR_EINVAL;
+  if (pb->rec.stage == 2) {
+    set_error(pb->ctx, "povar_debug_linearize is for first-stage problems; use povar_refine_debug_blocks");
+    return POVAR_ESTATE;
+  }
   povar_ctx ctx = pb->ctx;
   (void)hipSetDevice(ctx->device);
   Ctl c;
@@ -1460,6 +1560,10 @@ povar_status povar_debug_linearize(povar_problem pb, double* U, double* bp, doub
 povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, double* dp, double* p_trial,
                               double* cost_trial) {
   if (!pb || !(lambda > 0.0) || order < 0) return POVAR_EINVAL;
+  if (pb->rec.stage == 2) {
+    set_error(pb->ctx, "povar_debug_step is for first-stage problems; use povar_refine_debug_step");
+    return POVAR_ESTATE;
+  }
   povar_ctx ctx = pb->ctx;
   (void)hipSetDevice(ctx->device);
   Ctl c;
@@ -1503,6 +1607,130 @@ povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, do
   HIP_TRY(ctx, write_ctl(pb, &restore));
   if (after.status & 1) {
     set_error(ctx, "a damped camera block could not be factored at this damping");
+    return POVAR_ENUMERIC;
+  }
+  return POVAR_OK;
+}
+
+// Second stage: the blocks at the current point for damping lambda.
+povar_status povar_refine_debug_blocks(povar_problem pb, double lambda, double* U, double* bp, double* G,
+                                       double* bl, double* cost) {
+  if (!pb || !(lambda > 0.0)) return POVAR_EINVAL;
+  if (pb->rec.stage != 2) {
+    set_error(pb->ctx, "povar_refine_debug_blocks needs a second-stage problem");
+    return POVAR_ESTATE;
+  }
+  povar_ctx ctx = pb->ctx;
+  (void)hipSetDevice(ctx->device);
+  Ctl c;
+  HIP_TRY(ctx, read_ctl(pb, &c));
+  if (c.done) {
+    set_error(ctx, "problem has finished; debug hooks need a running problem");
+    return POVAR_ESTATE;
+  }
+  Ctl t = c;
+  t.lambda = lambda;
+  t.status = 0;
+  HIP_TRY(ctx, write_ctl(pb, &t));
+  const Batch& B = pb->batch;
+  HIP_TRY(ctx, launch_refine_landmarks(B, pb->stream));
+  HIP_TRY(ctx, launch_refine_cameras(B, pb->stream));
+  HIP_TRY(ctx, launch_cost_groups(B, 0, pb->stream));
+  HIP_TRY(ctx, launch_cost_finalize(B, 2, pb->stream));
+  const int32_t n_p = pb->L.n_p, n_l = pb->L.n_l, n_ch = pb->L.n_ch;
+  std::vector<double> lin((size_t)n_ch * kLin2), lm((size_t)n_l * kLm2);
+  HIP_TRY(ctx, hipMemcpyAsync(lin.data(), pb->rec.lin2, lin.size() * 8, hipMemcpyDeviceToHost, pb->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(lm.data(), pb->rec.lm2, lm.size() * 8, hipMemcpyDeviceToHost, pb->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(pb->stream));
+  Ctl after;
+  HIP_TRY(ctx, read_ctl(pb, &after));
+  // U_i (undamped) and b_p from the chunk sums: U[(a, c), (a2, c2)] is the
+  // sum for the entry of d pi^T d pi in rows a, a2 times X_c X_c2
+  auto sym = [](int a, int b) { return a <= b ? (a * 7 - a * a) / 2 + b : (b * 7 - b * b) / 2 + a; };
+  auto gsel = [](int a, int b) {
+    const int lo = std::min(a, b), hi = std::max(a, b);
+    if (lo == hi) return lo == 2 ? 3 : 0;
+    if (lo == 0 && hi == 1) return -1;
+    return lo == 0 ? 1 : 2;
+  };
+  std::vector<double> Ui((size_t)n_p * kCamMat), bpi((size_t)n_p * kCam);
+  for (int32_t i = 0; i < n_p; ++i) {
+    double sum[kLin2] = {0};
+    for (int32_t q = pb->L.cam_ch[i]; q < pb->L.cam_ch[i + 1]; ++q)
+      for (int k = 0; k < kLin2; ++k) sum[k] += lin[(size_t)q * kLin2 + k];
+    for (int r = 0; r < 12; ++r) {
+      for (int cc = 0; cc < 12; ++cc) {
+        const int gs = gsel(r >> 2, cc >> 2);
+        Ui[(size_t)i * kCamMat + r * 12 + cc] = gs < 0 ? 0.0 : sum[gs * 10 + sym(r & 3, cc & 3)];
+      }
+      bpi[(size_t)i * kCam + r] = sum[40 + r];
+    }
+  }
+  if (U) cams_to_caller(pb->L, Ui.data(), U, kCamMat);
+  if (bp) cams_to_caller(pb->L, bpi.data(), bp, kCam);
+  for (int32_t jj = 0; jj < n_l; ++jj) {
+    const int32_t j = pb->L.int2ext[jj];
+    const double* o = lm.data() + (size_t)jj * kLm2;
+    for (int a = 0; a < 4; ++a) {
+      for (int b = 0; b < 4; ++b)
+        if (G) G[(size_t)j * 16 + a * 4 + b] = o[sym(a, b)];
+      if (bl) bl[(size_t)j * 4 + a] = o[10 + a];
+    }
+  }
+  if (cost) *cost = after.cost;
+  Ctl restore = c;
+  HIP_TRY(ctx, write_ctl(pb, &restore));
+  return POVAR_OK;
+}
+
+// Second stage: one step at damping lambda and series order `order`.
+povar_status povar_refine_debug_step(povar_problem pb, double lambda, int32_t order, double* dp, double* p_trial,
+                                     double* x_trial, double* cost_trial) {
+  if (!pb || !(lambda > 0.0) || order < 0) return POVAR_EINVAL;
+  if (pb->rec.stage != 2) {
+    set_error(pb->ctx, "povar_refine_debug_step needs a second-stage problem");
+    return POVAR_ESTATE;
+  }
+  povar_ctx ctx = pb->ctx;
+  (void)hipSetDevice(ctx->device);
+  Ctl c;
+  HIP_TRY(ctx, read_ctl(pb, &c));
+  if (c.done) {
+    set_error(ctx, "problem has finished; debug hooks need a running problem");
+    return POVAR_ESTATE;
+  }
+  Ctl t = c;
+  t.lambda = lambda;
+  t.order = order;
+  t.status = 0;
+  HIP_TRY(ctx, write_ctl(pb, &t));
+  const Batch& B = pb->batch;
+  HIP_TRY(ctx, launch_refine_landmarks(B, pb->stream));
+  HIP_TRY(ctx, launch_refine_cameras(B, pb->stream));
+  HIP_TRY(ctx, launch_refine_step(B, order, pb->stream));
+  HIP_TRY(ctx, launch_cost_groups(B, 1, pb->stream));
+  HIP_TRY(ctx, launch_cost_finalize(B, 1, pb->stream));
+  Ctl after;
+  HIP_TRY(ctx, read_ctl(pb, &after));
+  const int32_t n_p = pb->L.n_p;
+  std::vector<double> tdp((size_t)n_p * kCam), tpt((size_t)n_p * kCam);
+  HIP_TRY(ctx, hipMemcpyAsync(tdp.data(), pb->rec.acc, tdp.size() * 8, hipMemcpyDeviceToHost, pb->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(tpt.data(), pb->rec.P64[c.pcur ^ 1], tpt.size() * 8, hipMemcpyDeviceToHost,
+                              pb->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(pb->stream));
+  if (dp) cams_to_caller(pb->L, tdp.data(), dp, kCam);
+  if (p_trial) cams_to_caller(pb->L, tpt.data(), p_trial, kCam);
+  if (x_trial) {
+    const povar_status st = copy_landmark_vec(pb, pb->rec.rec64[c.lcur ^ 1], kRec, 0, 4, x_trial);
+    if (st != POVAR_OK) return st;
+  }
+  if (cost_trial) *cost_trial = after.cost_trial;
+  Ctl restore = c;
+  restore.cost_trial = after.cost_trial;
+  restore.status = after.status;
+  HIP_TRY(ctx, write_ctl(pb, &restore));
+  if (after.status & 1) {
+    set_error(ctx, "a damped block could not be factored at this damping");
     return POVAR_ENUMERIC;
   }
   return POVAR_OK;

@@ -31,7 +31,8 @@ EXPORTS = [
     "povar_get_cameras", "povar_get_points", "povar_get_trace", "povar_get_state", "povar_set_state",
     "povar_debug_linearize", "povar_debug_step", "povar_debug_layout_check", "povar_kernel_timing", "povar_kernel_times",
     "povar_problem_info", "povar_problem_layout", "povar_server_create", "povar_server_submit", "povar_server_poll",
-    "povar_server_stats", "povar_server_destroy",
+    "povar_server_stats", "povar_server_destroy", "povar_refine_create", "povar_get_points_h",
+    "povar_refine_debug_blocks", "povar_refine_debug_step",
 ]
 
 
@@ -108,6 +109,11 @@ def lib() -> C.CDLL:
         "povar_server_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(Report), _P, _P, _P]),
         "povar_server_stats": (C.c_int, [_P, _I32P, _I32P, _I64P, _I64P]),
         "povar_server_destroy": (C.c_int, [_P]),
+        "povar_refine_create": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P, _P,
+                                          C.POINTER(Options), C.POINTER(_P)]),
+        "povar_get_points_h": (C.c_int, [_P, _P]),
+        "povar_refine_debug_blocks": (C.c_int, [_P, C.c_double, _P, _P, _P, _P, _DP]),
+        "povar_refine_debug_step": (C.c_int, [_P, C.c_double, C.c_int32, _P, _P, _P, _DP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -247,6 +253,50 @@ class Problem:
         r = Report()
         self._chk(lib().povar_get_report(self.handle, C.byref(r)), "povar_get_report")
         return r.as_dict()
+
+    @classmethod
+    def refine(cls, ctx: Context, n_cams: int, n_pts: int, cam_idx, pt_idx, meas, cams0, pts0,
+               **opts) -> "Problem":
+        """A second-stage problem (projective refinement, RiPoBA): cameras and
+        homogeneous landmarks (n_pts x 4) refined jointly (povar_refine_create)."""
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self.n_cams, self.n_pts = int(n_cams), int(n_pts)
+        self.options = make_options(**opts)
+        self.handle = C.c_void_p()
+        cam = np.ascontiguousarray(cam_idx, dtype=np.int32)
+        pt = np.ascontiguousarray(pt_idx, dtype=np.int32)
+        m = np.ascontiguousarray(meas, dtype=np.float64).reshape(-1, 2)
+        c0 = np.ascontiguousarray(cams0, dtype=np.float64).reshape(self.n_cams, 12)
+        x0 = np.ascontiguousarray(pts0, dtype=np.float64).reshape(self.n_pts, 4)
+        st = lib().povar_refine_create(ctx.handle, self.n_cams, self.n_pts, int(cam.shape[0]), _ptr(cam), _ptr(pt),
+                                       _ptr(m), _ptr(c0), _ptr(x0), C.byref(self.options), C.byref(self.handle))
+        ctx.check(st, "povar_refine_create")
+        ctx._problems.add(self)
+        return self
+
+    def points_h(self) -> np.ndarray:
+        out = np.empty((self.n_pts, 4))
+        self._chk(lib().povar_get_points_h(self.handle, _ptr(out)), "povar_get_points_h")
+        return out
+
+    def refine_blocks(self, lam: float) -> dict:
+        nc, npt = self.n_cams, self.n_pts
+        out = dict(U=np.empty((nc, 12, 12)), bp=np.empty((nc, 12)), G=np.empty((npt, 4, 4)), bl=np.empty((npt, 4)))
+        cost = C.c_double()
+        self._chk(lib().povar_refine_debug_blocks(self.handle, float(lam), _ptr(out["U"]), _ptr(out["bp"]),
+                                                  _ptr(out["G"]), _ptr(out["bl"]), C.byref(cost)),
+                  "povar_refine_debug_blocks")
+        out["cost"] = cost.value
+        return out
+
+    def refine_step(self, lam: float, order: int):
+        dp, pt = np.empty((self.n_cams, 12)), np.empty((self.n_cams, 12))
+        xt = np.empty((self.n_pts, 4))
+        ct = C.c_double()
+        self._chk(lib().povar_refine_debug_step(self.handle, float(lam), int(order), _ptr(dp), _ptr(pt), _ptr(xt),
+                                                C.byref(ct)), "povar_refine_debug_step")
+        return dp, pt, xt, ct.value
 
     def cameras(self) -> np.ndarray:
         out = np.empty((self.n_cams, 12))
