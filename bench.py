@@ -117,6 +117,43 @@ def run_stream(ctx, probs, arrivals, budget, slots, opts):
     return [lat[i] for i in range(len(probs))], wall, max_res
 
 
+def refine_leg(ctx, prob, P1, X1, steps: int):
+    """The second stage (projective refinement, RiPoBA, FP64) on the same
+    problem.  The rate: `steps` graph-replayed LM iterations from the first
+    stage's FP64 solution (the stratified pipeline).  The costs: before and
+    after, against the noise floor of the measurements, from that solution and
+    from the ground truth perturbed by N(0, 0.02^2) per coordinate (cameras
+    and homogeneous landmarks, each then put back on its sphere).  From random
+    cameras the first stage can stop in a poor basin of its own objective, and
+    the refinement then only improves the start it was given."""
+    def unit(a):
+        return a / np.linalg.norm(a, axis=1, keepdims=True)
+
+    def make(P, Xh):
+        return povar.Problem.refine(ctx, prob.n_cams, prob.n_pts, prob.cam_idx, prob.pt_idx, prob.meas,
+                                    unit(P), unit(Xh), order=prob.order, ftol=0.0, max_iters=10 ** 6)
+
+    gp = make(P1, np.concatenate([X1, np.ones((X1.shape[0], 1))], axis=1))
+    c0 = gp.report()["cost_initial"]
+    gp.step(5)
+    secs = timed_iters(gp, steps)
+    rep = gp.report()
+    gp.close()
+    rng = np.random.default_rng(77)
+    Pg = prob.cams_gt.reshape(prob.n_cams, 12)
+    Xg = np.concatenate([prob.pts_gt, np.ones((prob.n_pts, 1))], axis=1)
+    gp = make(unit(Pg) + 0.02 * rng.standard_normal(Pg.shape), unit(Xg) + 0.02 * rng.standard_normal(Xg.shape))
+    g0 = gp.report()["cost_initial"]
+    gp.step(steps)
+    grep_ = gp.report()
+    gp.close()
+    return {"iters_per_s": round(steps / secs, 2), "steps": steps, "precision": "fp64", "order": prob.order,
+            "noise_floor": synth.SIGMA ** 2 * 2 * prob.n_obs,
+            "from_first_stage": {"cost_initial": c0, "cost_after": rep["cost_final"], "iters": rep["iters"]},
+            "from_perturbed_truth": {"sigma": 0.02, "cost_initial": g0, "cost_after": grep_["cost_final"],
+                                     "iters": grep_["iters"]}}
+
+
 def serving(ctx, n_requests: int, budget: int, slots: int):
     """Continuous-batching leg: a seeded sample of the serving stream
     (cameras log-uniform in [20, 400], points = 250 x cameras, mean track 5,
@@ -290,6 +327,8 @@ def main():
                     help="seeds of the workload for the matched-final-cost comparison")
     ap.add_argument("--workload", type=int, default=WORKLOAD,
                     help="2: 250 cameras (default); 3: 1,800 cameras / 5M obs; 5: 13,700 cameras / 29M obs")
+    ap.add_argument("--no-refine", action="store_true",
+                    help="skip the second-stage (projective refinement) leg")
     ap.add_argument("--serve", type=int, default=128,
                     help="requests of the 512-request serving stream to run (0: skip)")
     ap.add_argument("--serve-budget", type=int, default=2 << 30)
@@ -320,6 +359,7 @@ def main():
         args.no_matched = True
         args.serve = 0
         args.no_cpu_baseline = True
+        args.no_refine = True
     print(f"[bench] workload {prob.name}: {prob.n_cams} cameras, {prob.n_pts} points, "
           f"{prob.n_obs} observations, order {prob.order}", file=sys.stderr, flush=True)
     ctx = povar.Context(0)
@@ -338,6 +378,8 @@ def main():
         res[prec] = dict(secs=secs, iters_per_s=args.steps / secs, rep=rep, kt=kt, info=info, layout=gp.layout())
         print(f"[bench] {prec}: {args.steps / secs:.1f} iters/s, cost {rep['cost_final']:.6g}",
               file=sys.stderr, flush=True)
+        if prec == "fp64":
+            stage1 = (gp.cameras(), gp.points())
         gp.close()
 
     fp32 = res["fp32_bulk"]
@@ -414,6 +456,9 @@ def main():
             "fp64_seconds_ref": prob.iters / r64,
             "fp32_seconds_to_match_median": (med / r32) if med else None,
             "speedup_at_matched_cost": (prob.iters / r64) / (med / r32) if med else None}
+    if not args.no_refine:
+        out["refine"] = refine_leg(ctx, prob, *stage1, min(args.steps, 50))
+        print(f"[bench] refinement: {out['refine']['iters_per_s']} iters/s", file=sys.stderr, flush=True)
     if args.serve > 0:
         out["serving"] = serving(ctx, args.serve, args.serve_budget, args.serve_slots)
         print(f"[bench] serving: p50 {out['serving']['p50_s']} s, p99 {out['serving']['p99_s']} s",
