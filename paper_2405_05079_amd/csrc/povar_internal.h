@@ -156,8 +156,7 @@ struct DevProblem {
   int32_t pad3;
   double POVAR_GMEM* lm2;              // n_l x kLm2: G_j (10, sym4 order), b_l (4), z0 = G_j b_l (4)
   double POVAR_GMEM* lin2;             // n_ch x kLin2 chunk partials: 40 sums of g (x) X X^T, b_p, sum W z0
-  double POVAR_GMEM* x2;               // n_p x 12 series term
-  double POVAR_GMEM* z2;               // n_l x 4 series landmark term
+  double POVAR_GMEM* x2;               // n_p x 12 series term (the landmark term goes to zx as (z, X))
 };
 constexpr int kLm2 = 20;
 constexpr int kLin2 = 64;

@@ -1984,7 +1984,10 @@ __device__ __forceinline__ void refine_landmark_slot(DevProblem& D, int q) {
     store4(o, xn[0] * inv, xn[1] * inv, xn[2] * inv, xn[3] * inv);
     store4(o + 4, 0.0, 0.0, 0.0, 0.0);
   } else {
-    store4(D.z2 + (size_t)j * 4, z[0], z[1], z[2], z[3]);
+    // the (z, X) record the camera pass gathers, one 64-byte line per landmark
+    double* o = static_cast<double*>(D.zx) + (size_t)j * kRec;
+    store4(o, z[0], z[1], z[2], z[3]);
+    store4(o + 4, X[0], X[1], X[2], X[3]);
   }
 }
 
@@ -2004,59 +2007,165 @@ __global__ void __launch_bounds__(kBlock) k_refine_landmark_update(Batch B) {
   refine_landmark_slot<true>(D, q);
 }
 
-// Camera pass of the series: t_i = sum_k W_k z_j, x_i = K_i t_i, acc_i += x_i.
-// The workgroup of a camera's first chunk walks all of its observations.
+// W z for one observation, added to the camera's 12 sums:
+// J_p^T J_l z = vec((d pi / d y)^T J_l z) X^T (row-major 3 x 4).
+__device__ __forceinline__ void refine_w_add(const double (&Pc)[12], const double (&z)[4], const double (&X)[4],
+                                             double (&acc)[12]) {
+  const Proj2 g = project2(Pc, X);
+  const double v0 = g.jl0[0] * z[0] + g.jl0[1] * z[1] + g.jl0[2] * z[2] + g.jl0[3] * z[3];
+  const double v1 = g.jl1[0] * z[0] + g.jl1[1] * z[1] + g.jl1[2] * z[2] + g.jl1[3] * z[3];
+  double h[3];
+  dpi_t(g, v0, v1, h);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[4 * a + c] += h[a] * X[c];
+}
+
+// x_i = K_i t_i (rows of K_i in kr, one per thread 0..11), acc_i += x_i.
+__device__ __forceinline__ void refine_camera_solve(DevProblem& D, int cam, const double* tv, const double (&kr)[12]) {
+  const int k = (int)threadIdx.x;
+  if (k >= 12) return;
+  double x = 0.0;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) x += kr[c] * tv[c];
+  D.x2[(size_t)cam * kCam + k] = x;
+  D.acc[(size_t)cam * kCam + k] += x;
+}
+
+// Camera pass of the series over camera-major chunks: t_i = sum_k W_k z_j,
+// x_i = K_i t_i, acc_i += x_i.  Index loads, then the (z, X) record gathers,
+// then the arithmetic; a camera spanning several chunks leaves one partial
+// per chunk for k_refine_series_combine.
 __global__ void __launch_bounds__(kBlock) k_refine_series_camera(Batch B, int t) {
   int p, ch;
-  if (!map_block(B, kUnitChunk, p, ch)) return;
+  if (!map_block(B, kUnitSerChunk, p, ch)) return;
   DevProblem& D = B.probs[p];
   if (D.ctl.done || t > D.ctl.order) return;
   const int4 meta = D.ch_meta[ch];
-  const int cam = meta.x;
-  if (D.cam_ch[cam] != ch) return;
-  const int beg = meta.y, end = D.ch_meta[D.cam_ch[cam + 1] - 1].z;
+  const int cam = meta.x, beg = meta.y, end = meta.z, nch = meta.w;
   double Pc[12];
   load12((D.ctl.pcur ? D.P64[1] : D.P64[0]) + (size_t)cam * kCam, Pc);
   double kr[12];
-  if (threadIdx.x < 12) load12(D.K64 + (size_t)cam * kCamMat + threadIdx.x * 12, kr);
-  const double* __restrict__ Xr = D.ctl.lcur ? D.rec64[1] : D.rec64[0];
-  double acc[16];
+  if (nch == 1 && threadIdx.x < 12) load12(D.K64 + (size_t)cam * kCamMat + threadIdx.x * 12, kr);
+  const double* __restrict__ zx = static_cast<const double*>(D.zx);
+  const int nr = (end - beg + kBlock - 1) / kBlock;
+  const int tid = (int)threadIdx.x;
+  int jr[kPerLane];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) acc[k] = 0.0;
-  for (int e = beg + (int)threadIdx.x; e < end; e += kBlock) {
-    const int j = D.cm_lm[e];
-    double X[4], z[4];
-    load4(Xr + (size_t)j * kRec, X[0], X[1], X[2], X[3]);
-    load4(D.z2 + (size_t)j * 4, z[0], z[1], z[2], z[3]);
-    const Proj2 g = project2(Pc, X);
-    const double v0 = g.jl0[0] * z[0] + g.jl0[1] * z[1] + g.jl0[2] * z[2] + g.jl0[3] * z[3];
-    const double v1 = g.jl1[0] * z[0] + g.jl1[1] * z[1] + g.jl1[2] * z[2] + g.jl1[3] * z[3];
-    double h[3];
-    dpi_t(g, v0, v1, h);
+  for (int r = 0; r < kPerLane; ++r)
+    if (r < nr) jr[r] = D.cm_lm[min(beg + r * kBlock + tid, end - 1)];
+  double z[kPerLane][4], X[kPerLane][4];
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[4 * a + c] += h[a] * X[c];
+  for (int r = 0; r < kPerLane; ++r) {
+    if (r < nr) {
+      load4(zx + (size_t)jr[r] * kRec, z[r][0], z[r][1], z[r][2], z[r][3]);
+      load4(zx + (size_t)jr[r] * kRec + 4, X[r][0], X[r][1], X[r][2], X[r][3]);
+    }
   }
+  double acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int r = 0; r < kPerLane; ++r)
+    if (r < nr && beg + r * kBlock + tid < end) refine_w_add(Pc, z[r], X[r], acc);
   __shared__ double red[kWavesPerBlock][12];
   __shared__ double tv[12];
   const int wv = threadIdx.x >> 6;
   {
-    const double sv = reduce_scatter<16>(acc);
+    double v16[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v16[k] = k < 12 ? acc[k] : 0.0;
+    const double sv = reduce_scatter<16>(v16);
     const int idx = rs_index<16>(lane_id());
     if (lane_id() < 16 && idx < 12) red[wv][idx] = sv;
   }
   __syncthreads();
-  if (threadIdx.x < 12) tv[threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
-                                          red[3][threadIdx.x];
-  __syncthreads();
-  if (threadIdx.x < 12) {
-    double x = 0.0;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) x += kr[c] * tv[c];
-    D.x2[(size_t)cam * kCam + threadIdx.x] = x;
-    D.acc[(size_t)cam * kCam + threadIdx.x] += x;
+  const int k = threadIdx.x;
+  if (nch > 1) {
+    if (k < 12) static_cast<double*>(D.t_part)[(size_t)ch * kCam + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    return;
   }
+  if (k < 12) tv[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  __syncthreads();
+  refine_camera_solve(D, cam, tv, kr);
+}
+
+// Camera pass of landmark-blocked problems: one wave per camera slot,
+// kCsPerLane observations of one run per lane, a partial sum per run; the
+// (z, X) records of the slot's landmark block stay in one XCD's L2.
+__global__ void __launch_bounds__(kBlock) k_refine_series_camera_slots(Batch B, int t) {
+  int p, q;
+  if (!map_wave(B, kUnitCSlot, p, q)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done || t > D.ctl.order) return;
+  const int lane = lane_id();
+  const int2 li = D.cs_lane[(size_t)q * kWave + lane];
+  int jr[kCsPerLane];
+#pragma unroll
+  for (int r = 0; r < kCsPerLane; ++r) jr[r] = D.cs_lm[((size_t)q * kCsPerLane + r) * kWave + lane];
+  const int nl = D.cs_hdr[q];
+  if (nl == 0) return;
+  const bool act = lane < nl;
+  const int cam = li.x & (int)kCamMask;
+  const int key = act ? (int)((uint32_t)li.x >> kCamBits) : kWave + lane;
+  double Pc[12];
+  if (act) load12((D.ctl.pcur ? D.P64[1] : D.P64[0]) + (size_t)cam * kCam, Pc);
+  else
+#pragma unroll
+    for (int k = 0; k < 12; ++k) Pc[k] = 0.0;
+  const double* __restrict__ zx = static_cast<const double*>(D.zx);
+  double z[kCsPerLane][4], X[kCsPerLane][4];
+#pragma unroll
+  for (int r = 0; r < kCsPerLane; ++r) {
+    if (jr[r] >= 0) {
+      load4(zx + (size_t)jr[r] * kRec, z[r][0], z[r][1], z[r][2], z[r][3]);
+      load4(zx + (size_t)jr[r] * kRec + 4, X[r][0], X[r][1], X[r][2], X[r][3]);
+    }
+  }
+  double acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int r = 0; r < kCsPerLane; ++r)
+    if (jr[r] >= 0) refine_w_add(Pc, z[r], X[r], acc);
+  seg_sum(acc, seg_links(key));
+  if (act && run_tail(key)) {
+    double* out = static_cast<double*>(D.ser_part) + (size_t)li.y * kCam;
+#pragma unroll
+    for (int k = 0; k < 12; k += 4) store4(out + k, acc[k], acc[k + 1], acc[k + 2], acc[k + 3]);
+  }
+}
+
+// One wave per camera with several partial sums (chunks or runs): adds them
+// in order (lane-strided, then a fixed tree) and applies K_i.
+__global__ void __launch_bounds__(kWave) k_refine_series_combine(Batch B, int t) {
+  int p, u;
+  if (!map_wave<kWave>(B, kUnitMultiCam, p, u)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done || t > D.ctl.order) return;
+  const int cam = D.ser_mc[u];
+  const int c0 = D.ser_off[cam], np = D.ser_off[cam + 1] - c0;
+  double kr[12];
+  if (threadIdx.x < 12) load12(D.K64 + (size_t)cam * kCamMat + threadIdx.x * 12, kr);
+  const double* __restrict__ part = static_cast<const double*>(D.ser_part);
+  double s[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) s[k] = 0.0;
+  for (int q = lane_id(); q < np; q += kWave) {
+    double v[12];
+    load12(part + (size_t)(c0 + q) * kCam, v);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) s[k] += v[k];
+  }
+  __shared__ double tv[12];
+  {
+    const double r = reduce_scatter<16>(s);
+    const int idx = rs_index<16>(lane_id());
+    if (lane_id() < 16 && idx < 12) tv[idx] = r;
+  }
+  __syncthreads();
+  refine_camera_solve(D, cam, tv, kr);
 }
 
 // Camera retraction of the second stage: p <- (p + acc) / |p + acc|.
@@ -2241,12 +2350,17 @@ hipError_t launch_refine_cameras(const Batch& b, hipStream_t s) {
 // chunk sums of the current point must be in place)
 hipError_t launch_refine_step(const Batch& b, int order, hipStream_t s) {
   const dim3 gp = blocks_for(b.total[kUnitPacket], kWavesPerBlock);
-  const dim3 gc = blocks_for(b.total[kUnitChunk], 1);
   const dim3 gw = blocks_for(b.total[kUnitCamWave], 1);
   hipLaunchKernelGGL(k_refine_prep, gw, dim3(kWave), 0, s, b);
   for (int t = 1; t <= order; ++t) {
     hipLaunchKernelGGL(k_refine_series_landmark, gp, dim3(kBlock), 0, s, b, t);
-    hipLaunchKernelGGL(k_refine_series_camera, gc, dim3(kBlock), 0, s, b, t);
+    if (b.total[kUnitSerChunk] > 0)
+      hipLaunchKernelGGL(k_refine_series_camera, blocks_for(b.total[kUnitSerChunk], 1), dim3(kBlock), 0, s, b, t);
+    if (b.total[kUnitCSlot] > 0)
+      hipLaunchKernelGGL(k_refine_series_camera_slots, blocks_for(b.total[kUnitCSlot], kWavesPerBlock), dim3(kBlock),
+                         0, s, b, t);
+    if (b.total[kUnitMultiCam] > 0)
+      hipLaunchKernelGGL(k_refine_series_combine, blocks_for(b.total[kUnitMultiCam], 1), dim3(kWave), 0, s, b, t);
   }
   hipLaunchKernelGGL(k_refine_landmark_update, gp, dim3(kBlock), 0, s, b);
   hipLaunchKernelGGL(k_refine_retract, gw, dim3(kWave), 0, s, b);

@@ -851,8 +851,8 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
       for (int k = 0; k < 4; ++k) X4[(size_t)jj * kRec + k] = pts0[(size_t)e * 4 + k] / std::sqrt(nrm);
     }
     const size_t b_lm2 = align_up((size_t)H.n_l * kLm2 * 8), b_lin2 = align_up((size_t)H.n_ch * kLin2 * 8);
-    const size_t b_x2 = align_up((size_t)H.n_p * kCam * 8), b_z2 = align_up((size_t)H.n_l * 4 * 8);
-    e = hipMalloc(&pb->arena2, b_lm2 + b_lin2 + b_x2 + b_z2);
+    const size_t b_x2 = align_up((size_t)H.n_p * kCam * 8);
+    e = hipMalloc(&pb->arena2, b_lm2 + b_lin2 + b_x2);
     if (e != hipSuccess) {
       pb->arena2 = nullptr;
       set_error(ctx, "hipMalloc of the second-stage buffers failed: %s", hipGetErrorString(e));
@@ -862,7 +862,6 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
     R.lm2 = (double*)b2;
     R.lin2 = (double*)(b2 + b_lm2);
     R.x2 = (double*)(b2 + b_lm2 + b_lin2);
-    R.z2 = (double*)(b2 + b_lm2 + b_lin2 + b_x2);
   }
 
   Ctl& c = R.ctl;

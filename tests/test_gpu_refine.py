@@ -50,8 +50,11 @@ CASES = [
     dict(n_cams=30, n_pts=129, seed=7, track=("geom", 0.25)),
     dict(n_cams=100, n_pts=50, seed=21, track=("uniform", 60, 90)),
     dict(n_cams=2, n_pts=5000, seed=22, track=("uniform", 2, 2)),
+    # 70,000 landmarks: 64-byte (z, X) records above 4 MB, so the camera pass
+    # runs over landmark-blocked camera slots and adds each camera's runs
+    dict(n_cams=40, n_pts=70000, seed=23, track=("uniform", 2, 3)),
 ]
-IDS = ["small", "3-chunks", "ragged", "long-tracks", "5-chunks"]
+IDS = ["small", "7-cameras", "ragged", "long-tracks", "3-chunk-cameras", "blocked"]
 
 
 @pytest.mark.parametrize("lam", [1e-3, 1.0])
@@ -62,6 +65,7 @@ def test_refine_blocks(ctx, kw, lam):
     say("refine blocks", kw, lam)
     gp = refine(ctx, prob, P, X)
     try:
+        assert gp.layout()["blocked"] == (prob.n_pts >= 70000)
         d = gp.refine_blocks(lam)
         lin = R.linearize(P, X, prob)
         rs = R.riemannian_system(P, X, lin, lam)
