@@ -359,7 +359,6 @@ def main():
         args.no_matched = True
         args.serve = 0
         args.no_cpu_baseline = True
-        args.no_refine = True
     print(f"[bench] workload {prob.name}: {prob.n_cams} cameras, {prob.n_pts} points, "
           f"{prob.n_obs} observations, order {prob.order}", file=sys.stderr, flush=True)
     ctx = povar.Context(0)
