@@ -154,11 +154,13 @@ struct DevProblem {
   // landmarks are unit 4-vectors in rec64[b] (first 4 of each record).
   int32_t stage;                       // 1: PoVar on Eq. (6); 2: RiPoBA on Eq. (7)
   int32_t pad3;
-  double POVAR_GMEM* lm2;              // n_l x kLm2: G_j (10, sym4 order), b_l (4), z0 = G_j b_l (4)
+  double POVAR_GMEM* g2;               // n_l x kG2: G_j (sym4 order)
+  double POVAR_GMEM* bl2;              // n_l x 4: b_l
   double POVAR_GMEM* lin2;             // n_ch x kLin2 chunk partials: 40 sums of g (x) X X^T, b_p, sum W z0
   double POVAR_GMEM* x2;               // n_p x 12 series term (the landmark term goes to zx as (z, X))
 };
-constexpr int kLm2 = 20;
+constexpr int kG2 = 10;
+constexpr int kX2 = 4;   // second stage: X_j (unit 4-vector) at stride 4 in rec64
 constexpr int kLin2 = 64;
 
 // Unit kinds of a launch.

@@ -1641,16 +1641,18 @@ __device__ __forceinline__ void refine_lm_finish(DevProblem& D, int j, const dou
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = a; b < 4; ++b) G[sym4(a, b)] = vi[sym4(a, b)] - w[a] * w[b] * ixw;
-  double* o = D.lm2 + (size_t)j * kLm2;
+  double* go = D.g2 + (size_t)j * kG2;
 #pragma unroll
-  for (int k = 0; k < 10; ++k) o[k] = G[k];
+  for (int k = 0; k < 10; ++k) go[k] = G[k];
+  store4(D.bl2 + (size_t)j * 4, vb[10], vb[11], vb[12], vb[13]);
+  // z0 = G_j b_l with X_j: the (z, X) record k_refine_cameras gathers
+  double z0[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    o[10 + a] = vb[10 + a];
-    o[14 + a] = G[sym4(a, 0)] * vb[10] + G[sym4(a, 1)] * vb[11] + G[sym4(a, 2)] * vb[12] + G[sym4(a, 3)] * vb[13];
-  }
-  o[18] = 0.0;
-  o[19] = 0.0;
+  for (int a = 0; a < 4; ++a)
+    z0[a] = G[sym4(a, 0)] * vb[10] + G[sym4(a, 1)] * vb[11] + G[sym4(a, 2)] * vb[12] + G[sym4(a, 3)] * vb[13];
+  double* zo = static_cast<double*>(D.zx) + (size_t)j * kRec;
+  store4(zo, z0[0], z0[1], z0[2], z0[3]);
+  store4(zo + 4, X[0], X[1], X[2], X[3]);
   if (!(ok && xw > 0.0)) atomicOr(&D.ctl.status, 1);
 }
 
@@ -1681,7 +1683,7 @@ __global__ void __launch_bounds__(kBlock) k_refine_landmarks(Batch B) {
     if (act) {
       double Pc[12];
       load12(P + (size_t)(code & kCamMask) * kCam, Pc);
-      load4(Xr + (size_t)(lm0 + key) * kRec, X[0], X[1], X[2], X[3]);
+      load4(Xr + (size_t)(lm0 + key) * kX2, X[0], X[1], X[2], X[3]);
       const Proj2 g = project2(Pc, X);
       const double r0 = g.u0 - mraw.x, r1 = g.u1 - mraw.y;
       refine_lm_terms(g, r0, r1, vb);
@@ -1694,7 +1696,7 @@ __global__ void __launch_bounds__(kBlock) k_refine_landmarks(Batch B) {
     double vb[14], X[4], f = 0.0;
 #pragma unroll
     for (int k = 0; k < 14; ++k) vb[k] = 0.0;
-    load4(Xr + (size_t)lm0 * kRec, X[0], X[1], X[2], X[3]);
+    load4(Xr + (size_t)lm0 * kX2, X[0], X[1], X[2], X[3]);
     for (int e = off + lane; e < off + n; e += kWave) {
       double Pc[12], t[14];
       load12(P + (size_t)(D.pk_code[e] & kCamMask) * kCam, Pc);
@@ -1726,7 +1728,7 @@ __global__ void __launch_bounds__(kBlock) k_refine_cameras(Batch B) {
   const int cam = meta.x, beg = meta.y, end = meta.z;
   double Pc[12];
   load12((D.ctl.pcur ? D.P64[1] : D.P64[0]) + (size_t)cam * kCam, Pc);
-  const double* __restrict__ Xr = D.ctl.lcur ? D.rec64[1] : D.rec64[0];
+  const double* __restrict__ zx = static_cast<const double*>(D.zx);
   double acc[kLin2];
 #pragma unroll
   for (int k = 0; k < kLin2; ++k) acc[k] = 0.0;
@@ -1737,8 +1739,8 @@ __global__ void __launch_bounds__(kBlock) k_refine_cameras(Batch B) {
     const int j = D.cm_lm[e];
     const double2 m = D.cm_m64[e];
     double X[4], z[4];
-    load4(Xr + (size_t)j * kRec, X[0], X[1], X[2], X[3]);
-    load4(D.lm2 + (size_t)j * kLm2 + 14, z[0], z[1], z[2], z[3]);
+    load4(zx + (size_t)j * kRec, z[0], z[1], z[2], z[3]);
+    load4(zx + (size_t)j * kRec + 4, X[0], X[1], X[2], X[3]);
     const Proj2 g = project2(Pc, X);
     const double r0 = g.u0 - m.x, r1 = g.u1 - m.y;
     const double w2 = g.iw * g.iw;
@@ -1939,7 +1941,7 @@ __device__ __forceinline__ void refine_landmark_slot(DevProblem& D, int q, f4v P
     const bool act = lane < n;
     const int key = act ? (int)(code >> kCamBits) : kWave + lane;
     j = lm0 + (act ? key : 0);
-    if (act) load4(Xr + (size_t)j * kRec, X[0], X[1], X[2], X[3]);
+    if (act) load4(Xr + (size_t)j * kX2, X[0], X[1], X[2], X[3]);
     // P_i and y_i (96 bytes each) fetched cooperatively: each load
     // instruction covers about eleven consecutive records instead of 64
     // scattered ones, which cuts the vector L1's tag lookups fourfold
@@ -1960,7 +1962,7 @@ __device__ __forceinline__ void refine_landmark_slot(DevProblem& D, int q, f4v P
     seg_sum(wt, seg_links(key));
     tail = act && run_tail(key);
   } else {
-    load4(Xr + (size_t)lm0 * kRec, X[0], X[1], X[2], X[3]);
+    load4(Xr + (size_t)lm0 * kX2, X[0], X[1], X[2], X[3]);
     for (int e = off + lane; e < off + n; e += kWave) {
       const int c = (int)(D.pk_code[e] & kCamMask);
       double Pc[12], y[12], t[4];
@@ -1976,11 +1978,12 @@ __device__ __forceinline__ void refine_landmark_slot(DevProblem& D, int q, f4v P
     tail = lane == 0;
   }
   if (!tail) return;
-  const double* G = D.lm2 + (size_t)j * kLm2;
+  const double* G = D.g2 + (size_t)j * kG2;
   double v[4];
   if (Update) {
+    const double* bl = D.bl2 + (size_t)j * 4;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) v[a] = G[10 + a] + wt[a];
+    for (int a = 0; a < 4; ++a) v[a] = bl[a] + wt[a];
   } else {
 #pragma unroll
     for (int a = 0; a < 4; ++a) v[a] = wt[a];
@@ -1997,9 +2000,8 @@ __device__ __forceinline__ void refine_landmark_slot(DevProblem& D, int q, f4v P
       nrm += xn[a] * xn[a];
     }
     const double inv = 1.0 / sqrt(nrm);
-    double* o = (lc ? D.rec64[0] : D.rec64[1]) + (size_t)j * kRec;
+    double* o = (lc ? D.rec64[0] : D.rec64[1]) + (size_t)j * kX2;
     store4(o, xn[0] * inv, xn[1] * inv, xn[2] * inv, xn[3] * inv);
-    store4(o + 4, 0.0, 0.0, 0.0, 0.0);
   } else {
     // the (z, X) record the camera pass gathers, one 64-byte line per landmark
     double* o = static_cast<double*>(D.zx) + (size_t)j * kRec;
@@ -2228,7 +2230,7 @@ __global__ void __launch_bounds__(kBlock) k_refine_cost(Batch B) {
       const int j = n <= kWave ? lm0 + (int)(code >> kCamBits) : lm0;
       double Pc[12], X[4];
       load12(P + (size_t)(code & kCamMask) * kCam, Pc);
-      load4(Xr + (size_t)j * kRec, X[0], X[1], X[2], X[3]);
+      load4(Xr + (size_t)j * kX2, X[0], X[1], X[2], X[3]);
       const double2 m = D.pk_m64[e];
       const Proj2 g = project2(Pc, X);
       const double r0 = g.u0 - m.x, r1 = g.u1 - m.y;

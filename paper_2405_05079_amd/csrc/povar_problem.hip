@@ -832,7 +832,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.stage = pts0 ? 2 : 1;
   std::vector<double> X4;
   if (pts0) {
-    X4.assign((size_t)H.n_l * kRec, 0.0);
+    X4.assign((size_t)H.n_l * kX2, 0.0);
     for (int32_t jj = 0; jj < H.n_l; ++jj) {
       const int32_t e = H.int2ext[jj];
       double nrm = 0.0;
@@ -848,20 +848,21 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
         set_error(ctx, "initial point %d is zero", e);
         return POVAR_EINVAL;
       }
-      for (int k = 0; k < 4; ++k) X4[(size_t)jj * kRec + k] = pts0[(size_t)e * 4 + k] / std::sqrt(nrm);
+      for (int k = 0; k < 4; ++k) X4[(size_t)jj * kX2 + k] = pts0[(size_t)e * 4 + k] / std::sqrt(nrm);
     }
-    const size_t b_lm2 = align_up((size_t)H.n_l * kLm2 * 8), b_lin2 = align_up((size_t)H.n_ch * kLin2 * 8);
-    const size_t b_x2 = align_up((size_t)H.n_p * kCam * 8);
-    e = hipMalloc(&pb->arena2, b_lm2 + b_lin2 + b_x2);
+    const size_t b_g2 = align_up((size_t)H.n_l * kG2 * 8), b_bl2 = align_up((size_t)H.n_l * 4 * 8);
+    const size_t b_lin2 = align_up((size_t)H.n_ch * kLin2 * 8), b_x2 = align_up((size_t)H.n_p * kCam * 8);
+    e = hipMalloc(&pb->arena2, b_g2 + b_bl2 + b_lin2 + b_x2);
     if (e != hipSuccess) {
       pb->arena2 = nullptr;
       set_error(ctx, "hipMalloc of the second-stage buffers failed: %s", hipGetErrorString(e));
       return POVAR_ENOMEM;
     }
     char* b2 = static_cast<char*>(pb->arena2);
-    R.lm2 = (double*)b2;
-    R.lin2 = (double*)(b2 + b_lm2);
-    R.x2 = (double*)(b2 + b_lm2 + b_lin2);
+    R.g2 = (double*)b2;
+    R.bl2 = (double*)(b2 + b_g2);
+    R.lin2 = (double*)(b2 + b_g2 + b_bl2);
+    R.x2 = (double*)(b2 + b_g2 + b_bl2 + b_lin2);
   }
 
   Ctl& c = R.ctl;
@@ -1353,7 +1354,7 @@ povar_status povar_get_points(povar_problem pb, double* out) {
   HIP_TRY(pb->ctx, read_ctl(pb, &c));
   if (pb->rec.stage != 2) return copy_landmark_vec(pb, pb->rec.rec64[c.lcur], kRec, 4, 3, out);
   std::vector<double> h((size_t)pb->L.n_l * 4);
-  const povar_status st = copy_landmark_vec(pb, pb->rec.rec64[c.lcur], kRec, 0, 4, h.data());
+  const povar_status st = copy_landmark_vec(pb, pb->rec.rec64[c.lcur], kX2, 0, 4, h.data());
   if (st != POVAR_OK) return st;
   for (int32_t j = 0; j < pb->L.n_l; ++j)
     for (int k = 0; k < 3; ++k) out[(size_t)j * 3 + k] = h[(size_t)j * 4 + k] / h[(size_t)j * 4 + 3];
@@ -1364,7 +1365,8 @@ povar_status povar_get_points_h(povar_problem pb, double* out) {
   if (!pb || !out) return POVAR_EINVAL;
   Ctl c;
   HIP_TRY(pb->ctx, read_ctl(pb, &c));
-  return copy_landmark_vec(pb, pb->rec.rec64[c.lcur], kRec, pb->rec.stage == 2 ? 0 : 4, 4, out);
+  if (pb->rec.stage == 2) return copy_landmark_vec(pb, pb->rec.rec64[c.lcur], kX2, 0, 4, out);
+  return copy_landmark_vec(pb, pb->rec.rec64[c.lcur], kRec, 4, 4, out);
 }
 
 povar_status povar_refine_create(povar_ctx ctx, int32_t n_cams, int32_t n_pts, int64_t n_obs,
@@ -1637,9 +1639,10 @@ povar_status povar_refine_debug_blocks(povar_problem pb, double lambda, double* 
   HIP_TRY(ctx, launch_cost_groups(B, 0, pb->stream));
   HIP_TRY(ctx, launch_cost_finalize(B, 2, pb->stream));
   const int32_t n_p = pb->L.n_p, n_l = pb->L.n_l, n_ch = pb->L.n_ch;
-  std::vector<double> lin((size_t)n_ch * kLin2), lm((size_t)n_l * kLm2);
+  std::vector<double> lin((size_t)n_ch * kLin2), g2((size_t)n_l * kG2), bl2((size_t)n_l * 4);
   HIP_TRY(ctx, hipMemcpyAsync(lin.data(), pb->rec.lin2, lin.size() * 8, hipMemcpyDeviceToHost, pb->stream));
-  HIP_TRY(ctx, hipMemcpyAsync(lm.data(), pb->rec.lm2, lm.size() * 8, hipMemcpyDeviceToHost, pb->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(g2.data(), pb->rec.g2, g2.size() * 8, hipMemcpyDeviceToHost, pb->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(bl2.data(), pb->rec.bl2, bl2.size() * 8, hipMemcpyDeviceToHost, pb->stream));
   HIP_TRY(ctx, hipStreamSynchronize(pb->stream));
   Ctl after;
   HIP_TRY(ctx, read_ctl(pb, &after));
@@ -1669,11 +1672,11 @@ povar_status povar_refine_debug_blocks(povar_problem pb, double lambda, double* 
   if (bp) cams_to_caller(pb->L, bpi.data(), bp, kCam);
   for (int32_t jj = 0; jj < n_l; ++jj) {
     const int32_t j = pb->L.int2ext[jj];
-    const double* o = lm.data() + (size_t)jj * kLm2;
+    const double* o = g2.data() + (size_t)jj * kG2;
     for (int a = 0; a < 4; ++a) {
       for (int b = 0; b < 4; ++b)
         if (G) G[(size_t)j * 16 + a * 4 + b] = o[sym(a, b)];
-      if (bl) bl[(size_t)j * 4 + a] = o[10 + a];
+      if (bl) bl[(size_t)j * 4 + a] = bl2[(size_t)jj * 4 + a];
     }
   }
   if (cost) *cost = after.cost;
@@ -1720,7 +1723,7 @@ povar_status povar_refine_debug_step(povar_problem pb, double lambda, int32_t or
   if (dp) cams_to_caller(pb->L, tdp.data(), dp, kCam);
   if (p_trial) cams_to_caller(pb->L, tpt.data(), p_trial, kCam);
   if (x_trial) {
-    const povar_status st = copy_landmark_vec(pb, pb->rec.rec64[c.lcur ^ 1], kRec, 0, 4, x_trial);
+    const povar_status st = copy_landmark_vec(pb, pb->rec.rec64[c.lcur ^ 1], kX2, 0, 4, x_trial);
     if (st != POVAR_OK) return st;
   }
   if (cost_trial) *cost_trial = after.cost_trial;
