@@ -148,7 +148,10 @@ def refine_leg(ctx, prob, P1, X1, steps: int):
     grep_ = gp.report()
     gp.close()
     return {"iters_per_s": round(steps / secs, 2), "steps": steps, "precision": "fp64", "order": prob.order,
+            # sigma^2 per coordinate of every observation: reachable only
+            # without outliers (the 1,800-camera workload holds 1%)
             "noise_floor": synth.SIGMA ** 2 * 2 * prob.n_obs,
+            "outlier_frac": next(w["outlier_frac"] for w in synth.WORKLOADS.values() if w["name"] == prob.name),
             "from_first_stage": {"cost_initial": c0, "cost_after": rep["cost_final"], "iters": rep["iters"]},
             "from_perturbed_truth": {"sigma": 0.02, "cost_initial": g0, "cost_after": grep_["cost_final"],
                                      "iters": grep_["iters"]}}
