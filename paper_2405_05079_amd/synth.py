@@ -23,6 +23,11 @@ Recipe (identical on every machine for a given numpy version):
   * initial cameras: unit-norm Gaussian 12-vectors from a separate seed stream
     (Sec. 5 draws cameras from an isotropic Gaussian; they are normalised here
     because the solver keeps every camera on the unit sphere of R^12).
+  * calibrated scenes (for the metric upgrade, which needs known intrinsics):
+    camera centres at distance 5 from the origin in uniformly random
+    directions, optical axis through the origin, random roll; intrinsics
+    K = [[f, 0, u], [0, f, v], [0, 0, 1]] with f ~ U(0.8, 1.2) and
+    u, v ~ U(-0.05, 0.05); G = K [R | t] scaled to unit Frobenius norm.
 """
 from __future__ import annotations
 
@@ -64,6 +69,7 @@ class Problem:
     iters: int = 50
     cams_gt: np.ndarray | None = None   # diagnostics only
     pts_gt: np.ndarray | None = None
+    K_gt: np.ndarray | None = None      # (n_cams, 3, 3) intrinsics of calibrated scenes
     seeds: dict = field(default_factory=dict)
     name: str = ""
 
@@ -78,6 +84,31 @@ def _gt_cameras(rng: np.random.Generator, n_cams: int) -> np.ndarray:
     G[:, 2, 3] = 5.0
     G /= np.linalg.norm(G.reshape(n_cams, 12), axis=1)[:, None, None]
     return G
+
+
+def _calibrated_cameras(rng: np.random.Generator, n_cams: int):
+    """Cameras K [R | t] looking at the origin from distance 5; returns
+    (G unit-norm 3x4, K 3x3)."""
+    d = rng.standard_normal((n_cams, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    C = 5.0 * d
+    z = -d
+    a = rng.standard_normal((n_cams, 3))
+    x = a - np.sum(a * z, axis=1, keepdims=True) * z
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    y = np.cross(z, x)
+    R = np.stack([x, y, z], axis=1)                       # rows: camera axes
+    t = -np.einsum("nab,nb->na", R, C)
+    K = np.zeros((n_cams, 3, 3))
+    f = rng.uniform(0.8, 1.2, size=n_cams)
+    K[:, 0, 0] = f
+    K[:, 1, 1] = f
+    K[:, 0, 2] = rng.uniform(-0.05, 0.05, size=n_cams)
+    K[:, 1, 2] = rng.uniform(-0.05, 0.05, size=n_cams)
+    K[:, 2, 2] = 1.0
+    G = np.einsum("nab,nbc->nac", K, np.concatenate([R, t[:, :, None]], axis=2))
+    G /= np.linalg.norm(G.reshape(n_cams, 12), axis=1)[:, None, None]
+    return G, K
 
 
 def _track_lengths(rng, n_pts, n_cams, track):
@@ -123,14 +154,19 @@ def _draw_distinct(rng, L, n_cams, weights):
 
 def make_problem(n_cams: int, n_pts: int, *, track=("geom", 0.25), cam_choice="uniform",
                  outlier_frac=0.0, eta=0.01, order=20, iters=50, seed=0, init_seed=None,
-                 sigma=SIGMA, affine=False, name="") -> Problem:
+                 sigma=SIGMA, affine=False, calibrated=False, name="") -> Problem:
     """Draw one problem.  `affine=True` gives cameras with third row (0,0,0,1)
-    (depth 1 everywhere), used by checks that need a known zero-cost minimum."""
+    (depth 1 everywhere), used by checks that need a known zero-cost minimum;
+    `calibrated=True` gives cameras K [R | t] with known intrinsics (K_gt)."""
     if init_seed is None:
         init_seed = seed + 1
     for attempt in range(64):
         rng = np.random.default_rng([seed, attempt]) if attempt else np.random.default_rng(seed)
-        G = _gt_cameras(rng, n_cams)
+        K = None
+        if calibrated:
+            G, K = _calibrated_cameras(rng, n_cams)
+        else:
+            G = _gt_cameras(rng, n_cams)
         if affine:
             G[:, 2, :] = 0.0
             G[:, 2, 3] = 1.0
@@ -161,7 +197,7 @@ def make_problem(n_cams: int, n_pts: int, *, track=("geom", 0.25), cam_choice="u
     cams0 = init_cameras(n_cams, init_seed)
     return Problem(n_cams=n_cams, n_pts=n_pts, cam_idx=cam_idx, pt_idx=pt_idx, meas=meas,
                    cams0=cams0, eta=eta, order=order, iters=iters,
-                   cams_gt=G.reshape(n_cams, 12), pts_gt=X,
+                   cams_gt=G.reshape(n_cams, 12), pts_gt=X, K_gt=K,
                    seeds=dict(data=seed, init=init_seed), name=name)
 
 
