@@ -250,6 +250,50 @@ povar_status povar_refine_debug_blocks(povar_problem pb, double lambda, double* 
 povar_status povar_refine_debug_step(povar_problem pb, double lambda, int32_t order, double* dp, double* p_trial,
                                      double* x_trial, double* cost_trial);
 
+/* ---- metric upgrade (autocalibration, supplement App. D) ----------------- */
+/* From a projective reconstruction (for instance the refined cameras) and the
+   cameras' known intrinsics, find H = [[A, 0], [c^T, 1]] such that every
+   P_i H is a scaled K_i [R_i | t_i].  With Q_i = K_i^-1 P_i and H~ the three
+   left columns of H, the plane at infinity c and the scales alpha_i minimise
+   sum_i || alpha_i Q_i H~ H~^T Q_i^T - I ||_F^2: each alpha_i in closed form
+   (variable projection), c by Levenberg-Marquardt on the reduced residual,
+   in FP64 on the device.  The frame is first moved so that camera 0 is
+   [I | 0], and A = K_0: camera 0 becomes K_0 [I | 0] and the metric frame is
+   camera 0's, up to a global scale.  LM: Marquardt damping on diag(J^T J)
+   (floored at 1e-12 of its largest entry), lambda0 = 1e-4, accept iff the
+   cost decreases, lambda / 10 (>= 1e-12) on accept and x 10 on reject; stop
+   when an accepted step lowers the cost by at most ftol (relative), when
+   lambda reaches 1e12, or after max_iters iterations (attempted steps).
+
+   cams: n_cams x 12 (row-major 3 x 4, any scale and sign per camera); K:
+   n_cams x 9 (row-major, upper triangular, nonzero diagonal).  Outputs (each
+   may be NULL): H (16, row-major 4 x 4; a projective point X maps to the
+   metric frame as H^-1 X), c (3), alpha (n_cams), R (n_cams x 9, rotations:
+   the orthogonal polar factor of K_i^-1 P_i H~ / s_i), t (n_cams x 3), with
+   P_i H = s_i K_i [R_i | t_i], s_i = +-1/sqrt(alpha_i) of the sign that makes
+   det R_i positive; trace_cost and trace_accept (max_iters each; the first
+   report.iters entries are written) the trial cost and decision of every
+   iteration.  Errors: POVAR_EINVAL (n_cams < 2, non-finite entries, a K that
+   is not upper triangular with a nonzero diagonal, camera 0 with a singular
+   left 3 x 3 block, max_iters outside [0, 2^20], ftol outside [0, 1)),
+   POVAR_ENOMEM, POVAR_EDEVICE.  Device memory is allocated per call. */
+typedef struct {
+  double cost_initial; /* at c = 0 */
+  double cost_final;
+  double lambda;
+  int32_t iters;
+  int32_t stop;        /* 1: ftol, 2: lambda at its cap, 3: max_iters, 0: max_iters = 0 */
+} povar_metric_report;
+
+povar_status povar_metric_upgrade(povar_ctx ctx, int32_t n_cams, const double* cams, const double* K,
+                                  int32_t max_iters, double ftol, double* H, double* c, double* alpha,
+                                  double* R, double* t, double* trace_cost, int32_t* trace_accept,
+                                  povar_metric_report* report);
+/* Test hook: the reduced problem at a given c (3 values): alpha (n_cams),
+   J^T J (9, row-major 3 x 3), J^T r (3) and the cost. */
+povar_status povar_metric_debug_reduced(povar_ctx ctx, int32_t n_cams, const double* cams, const double* K,
+                                        const double* c, double* alpha, double* JtJ, double* Jtr, double* cost);
+
 /* ---- kernel timing for roofline reports --------------------------------- */
 /* enable != 0: subsequent povar_step / povar_enqueue launches bracket every
    series kernel with HIP events on the context stream (graph replay is

@@ -11,8 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpovar.so")
-SOURCES = ["povar_kernels.hip", "povar_problem.hip", "povar_server.hip"]
-DEVICE_SOURCES = {"povar_kernels.hip"}   # the others hold host code only
+SOURCES = ["povar_kernels.hip", "povar_problem.hip", "povar_server.hip", "povar_metric.hip"]
+DEVICE_SOURCES = {"povar_kernels.hip", "povar_metric.hip"}   # the others hold host code only
 ARCH = os.environ.get("POVAR_OFFLOAD_ARCH", "gfx950")
 
 

@@ -32,7 +32,7 @@ EXPORTS = [
     "povar_debug_linearize", "povar_debug_step", "povar_debug_layout_check", "povar_kernel_timing", "povar_kernel_times",
     "povar_problem_info", "povar_problem_layout", "povar_server_create", "povar_server_submit", "povar_server_poll",
     "povar_server_stats", "povar_server_destroy", "povar_refine_create", "povar_get_points_h",
-    "povar_refine_debug_blocks", "povar_refine_debug_step",
+    "povar_refine_debug_blocks", "povar_refine_debug_step", "povar_metric_upgrade", "povar_metric_debug_reduced",
 ]
 
 
@@ -40,6 +40,11 @@ class PovarError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
         self.status = status
+
+
+class MetricReport(C.Structure):
+    _fields_ = [("cost_initial", C.c_double), ("cost_final", C.c_double), ("lambda_", C.c_double),
+                ("iters", C.c_int32), ("stop", C.c_int32)]
 
 
 class Options(C.Structure):
@@ -114,6 +119,9 @@ def lib() -> C.CDLL:
         "povar_get_points_h": (C.c_int, [_P, _P]),
         "povar_refine_debug_blocks": (C.c_int, [_P, C.c_double, _P, _P, _P, _P, _DP]),
         "povar_refine_debug_step": (C.c_int, [_P, C.c_double, C.c_int32, _P, _P, _P, _DP]),
+        "povar_metric_upgrade": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int32, C.c_double, _P, _P, _P, _P, _P, _P, _P,
+                                           C.POINTER(MetricReport)]),
+        "povar_metric_debug_reduced": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, _P, _DP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -165,6 +173,46 @@ def footprint(n_cams: int, n_pts: int, n_obs: int, precision="fp32_bulk") -> int
     if st != OK:
         raise PovarError(st, "invalid sizes")
     return int(out.value)
+
+
+def _metric_inputs(cams, K):
+    P = np.ascontiguousarray(cams, dtype=np.float64).reshape(-1, 12)
+    Km = np.ascontiguousarray(K, dtype=np.float64).reshape(-1, 9)
+    if P.shape[0] != Km.shape[0]:
+        raise ValueError("cams and K must have one entry per camera")
+    return P, Km
+
+
+def metric_upgrade(ctx: "Context", cams: np.ndarray, K: np.ndarray, max_iters: int = 100,
+                   ftol: float = 1e-14) -> dict:
+    """Metric upgrade (``povar_metric_upgrade``): cams (n, 12) or (n, 3, 4)
+    projective cameras, K (n, 3, 3) intrinsics.  Returns H (4, 4), c, alpha,
+    R (n, 3, 3), t (n, 3), the trace and the report."""
+    P, Km = _metric_inputs(cams, K)
+    n = P.shape[0]
+    out = dict(H=np.empty(16), c=np.empty(3), alpha=np.empty(n), R=np.empty((n, 9)), t=np.empty((n, 3)))
+    tc, ta = np.empty(max(max_iters, 1)), np.empty(max(max_iters, 1), dtype=np.int32)
+    rep = MetricReport()
+    ctx.check(lib().povar_metric_upgrade(ctx.handle, n, _ptr(P), _ptr(Km), int(max_iters), float(ftol),
+                                         _ptr(out["H"]), _ptr(out["c"]), _ptr(out["alpha"]), _ptr(out["R"]),
+                                         _ptr(out["t"]), _ptr(tc), _ptr(ta), C.byref(rep)),
+              "povar_metric_upgrade")
+    out["H"] = out["H"].reshape(4, 4)
+    out["R"] = out["R"].reshape(n, 3, 3)
+    out.update(trace_cost=tc[:rep.iters].copy(), trace_accept=ta[:rep.iters].astype(bool), iters=rep.iters,
+               cost_initial=rep.cost_initial, cost_final=rep.cost_final, lambda_=rep.lambda_, stop=rep.stop)
+    return out
+
+
+def metric_debug_reduced(ctx: "Context", cams: np.ndarray, K: np.ndarray, c) -> dict:
+    """The reduced metric-upgrade problem at c: alpha, J^T J, J^T r, cost."""
+    P, Km = _metric_inputs(cams, K)
+    n = P.shape[0]
+    cv = np.ascontiguousarray(c, dtype=np.float64).reshape(3)
+    alpha, JtJ, Jtr, cost = np.empty(n), np.empty(9), np.empty(3), C.c_double()
+    ctx.check(lib().povar_metric_debug_reduced(ctx.handle, n, _ptr(P), _ptr(Km), _ptr(cv), _ptr(alpha),
+                                               _ptr(JtJ), _ptr(Jtr), C.byref(cost)), "povar_metric_debug_reduced")
+    return dict(alpha=alpha, JtJ=JtJ.reshape(3, 3), Jtr=Jtr, cost=cost.value)
 
 
 class Context:

@@ -111,6 +111,12 @@ def _calibrated_cameras(rng: np.random.Generator, n_cams: int):
     return G, K
 
 
+def calibrated_cameras(n_cams: int, seed: int):
+    """Only the cameras of a calibrated scene (no points): (G (n, 3, 4) unit
+    norm, K (n, 3, 3)), for checks of the metric upgrade at any size."""
+    return _calibrated_cameras(np.random.default_rng(seed), n_cams)
+
+
 def _track_lengths(rng, n_pts, n_cams, track):
     kind = track[0]
     if kind == "uniform":
