@@ -157,6 +157,36 @@ def refine_leg(ctx, prob, P1, X1, steps: int):
                                      "iters": grep_["iters"]}}
 
 
+def metric_leg(ctx, reps: int = 5):
+    """The metric upgrade (App. D) at 250 and 13,700 cameras: calibrated
+    cameras seen through a random projective frame, each with a random scale
+    and sign and 1e-3 relative noise on every entry.  Wall time of the whole
+    call (host inputs to host outputs, device allocation included), median of
+    `reps`; the largest rotation error against the ground truth."""
+    out = {}
+    for n in (250, 13700):
+        G, K = synth.calibrated_cameras(n, 7000 + n)
+        rng = np.random.default_rng(7100 + n)
+        Hp = np.eye(4) + 0.3 * rng.standard_normal((4, 4))
+        s = rng.uniform(0.5, 2.0, n) * rng.choice([-1.0, 1.0], n)
+        P = s[:, None, None] * (G @ Hp) * (1.0 + 1e-3 * rng.standard_normal((n, 3, 4)))
+        povar.metric_upgrade(ctx, P, K, ftol=1e-10)
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            g = povar.metric_upgrade(ctx, P, K, ftol=1e-10)
+            times.append(time.perf_counter() - t0)
+        B = np.linalg.solve(K, G)
+        Rg = B[:, :, :3] / np.cbrt(np.linalg.det(B[:, :, :3]))[:, None, None]
+        cosang = (np.einsum("nab,nab->n", g["R"], Rg @ Rg[0].T) - 1.0) / 2.0
+        ms = 1e3 * float(np.median(times))
+        out[str(n)] = {"ms_per_call": round(ms, 3), "iters": int(g["iters"]),
+                       "ms_per_iter": round(ms / max(1, g["iters"]), 4),
+                       "cost_initial": g["cost_initial"], "cost_final": g["cost_final"],
+                       "max_rotation_error_deg": float(np.degrees(np.arccos(np.clip(cosang, -1, 1))).max())}
+    return out
+
+
 def serving(ctx, n_requests: int, budget: int, slots: int):
     """Continuous-batching leg: a seeded sample of the serving stream
     (cameras log-uniform in [20, 400], points = 250 x cameras, mean track 5,
@@ -332,6 +362,7 @@ def main():
                     help="2: 250 cameras (default); 3: 1,800 cameras / 5M obs; 5: 13,700 cameras / 29M obs")
     ap.add_argument("--no-refine", action="store_true",
                     help="skip the second-stage (projective refinement) leg")
+    ap.add_argument("--no-metric", action="store_true", help="skip the metric-upgrade leg")
     ap.add_argument("--serve", type=int, default=128,
                     help="requests of the 512-request serving stream to run (0: skip)")
     ap.add_argument("--serve-budget", type=int, default=2 << 30)
@@ -362,6 +393,7 @@ def main():
         args.no_matched = True
         args.serve = 0
         args.no_cpu_baseline = True
+        args.no_metric = True
     print(f"[bench] workload {prob.name}: {prob.n_cams} cameras, {prob.n_pts} points, "
           f"{prob.n_obs} observations, order {prob.order}", file=sys.stderr, flush=True)
     ctx = povar.Context(0)
@@ -461,6 +493,9 @@ def main():
     if not args.no_refine:
         out["refine"] = refine_leg(ctx, prob, *stage1, min(args.steps, 50))
         print(f"[bench] refinement: {out['refine']['iters_per_s']} iters/s", file=sys.stderr, flush=True)
+    if not args.no_metric:
+        out["metric"] = metric_leg(ctx)
+        print(f"[bench] metric upgrade: {out['metric']}", file=sys.stderr, flush=True)
     if args.serve > 0:
         out["serving"] = serving(ctx, args.serve, args.serve_budget, args.serve_slots)
         print(f"[bench] serving: p50 {out['serving']['p50_s']} s, p99 {out['serving']['p99_s']} s",
