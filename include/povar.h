@@ -313,13 +313,13 @@ povar_status povar_problem_info(povar_problem pb, int64_t* n_obs, int64_t* n_pac
    *blocked = 1 (records of the series precision above 4 MiB): landmarks in
    blocks of *lm_block internal ids (2 MiB of records), *n_slots 64-lane slots of 4 observations
    per lane, each block's slots run on one XCD, and *n_runs per-(camera, block
-   part) partial sums added per camera afterwards.  *n_lds_cams: cameras (the
-   most observed ones) whose series data the landmark pass of a large FP64
-   problem keeps in LDS, 0 when that pass reads every camera from global
-   memory.
+   part) partial sums added per camera afterwards.  *coop_gather = 1 when the
+   cameras' series records are a full stride apart (more than 341 cameras:
+   128 bytes in FP32, 256 in FP64) and the landmark pass gathers them
+   cooperatively, whole waves reading consecutive pieces of a few records.
    NULL outputs are skipped. */
 povar_status povar_problem_layout(povar_problem pb, int32_t* blocked, int32_t* lm_block, int64_t* n_slots,
-                                  int64_t* n_runs, int32_t* n_lds_cams);
+                                  int64_t* n_runs, int32_t* coop_gather);
 
 /* ---- serving: continuous batching of many problems on one GPU ----------- */
 /* A server owns a worker thread and the device state of up to max_slots

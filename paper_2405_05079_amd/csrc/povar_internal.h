@@ -131,8 +131,7 @@ struct DevProblem {
   // g % 8, and the slots are ordered so that all slots of a block go to the
   // XCD that block is assigned to, in block order.
   int32_t blocked, n_cs, n_runs, n_smc;
-  int32_t n_hot;        // cameras whose series data the LDS landmark pass stages (0: not used)
-  int32_t pad2;
+  int32_t pad2[2];
   const int32_t POVAR_GMEM* cs_hdr;    // n_cs: lanes used (0: empty slot)
   const int2 POVAR_GMEM* cs_lane;      // n_cs x 64: (camera | run key << 26, run id)
   const int32_t POVAR_GMEM* cs_lm;     // entry (q, r, lane) at (q * kCsPerLane + r) * 64 + lane:
@@ -198,22 +197,13 @@ struct Batch {
   const int32_t POVAR_GMEM* tables;
   int32_t n_prob, tab_stride;
   int32_t total[kNumUnitKinds];
-  // single large problem: the landmark pass runs as lds_grid persistent
-  // workgroups with lds_bytes of staged camera data (0: the plain pass)
-  int32_t lds_bytes, lds_grid;
-  // 1: FP32 problems of the batch with 128-byte camera records gather them
-  // cooperatively in the landmark pass (which then has kCoopLdsBytes of LDS)
+  // 1: problems of the batch whose camera series records are kSerLine
+  // values apart (128 bytes in FP32, 256 in FP64) gather them cooperatively in
+  // the landmark pass (kCoopLdsBytes of LDS per workgroup)
   int32_t coop_cams, pad;
 };
-constexpr int kCoopPieces = 6;   // 16-byte pieces of an FP32 camera series record read by the landmark pass
+constexpr int kCoopPieces = 6;   // 16-byte pieces of P and x (FP32), or of each of them (FP64)
 constexpr int kCoopLdsBytes = kBlock / kWave * kCoopPieces * kWave * 16;
-
-constexpr int kLdsCamVals = 21;   // staged camera values: x (12), Pbar (9)
-constexpr int kLdsBlock = 1024;   // threads of a staged landmark-pass workgroup
-
-// Enables dynamic LDS of `bytes` for the staged landmark pass (host, once
-// per size increase; not while a stream is being captured).
-hipError_t prepare_landmark_lds(int bytes);
 
 // Launchers (defined with the kernels).  `fp32` selects the series /
 // Jacobian precision; the critical kernels are FP64 in both modes.

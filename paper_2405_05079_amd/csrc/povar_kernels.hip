@@ -18,9 +18,9 @@
 //   k_linearize            U_i, b_p, sum_k W_k z0_j per camera chunk         (10)-(13)
 //   k_camera_prep          damping, tangent projection, 12x12 inverse, x_0  (14),(17),(20)-(29)
 //   k_series_landmark      z_j = V_j^+ sum_k W_k^T x_i                      (17)
-//   k_series_landmark_lds  the same, large FP64 problems, cameras staged in LDS
 //   k_series_landmark_coop the same, FP32 problems with many cameras, camera
 //                          records fetched by whole waves
+//   k_series_landmark_coop64  the same in FP64 (two gathers per record)
 //   k_series_camera        x_i = K_i sum_k W_k z_j, acc_i += x_i             (17)
 //   k_series_camera_slots  the same sums for landmark-blocked problems, per run
 //   k_series_camera_combine  adds a camera's partial sums, applies K_i
@@ -138,6 +138,14 @@ __device__ __forceinline__ void coop_fetch(const char POVAR_GMEM* base, size_t s
     for (int k = 0; k < NP; ++k) out[r][k] = buf[lane * NP + k];
     wave_sync();
   }
+}
+
+// A 16-byte piece of a cooperative gather as two doubles.
+__device__ __forceinline__ void piece_d2(f4v v, double& a, double& b) {
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  const d2v d = __builtin_bit_cast(d2v, v);
+  a = d[0];
+  b = d[1];
 }
 
 // Value of lane l (a uniform result); the builtin moves 32-bit words.
@@ -944,31 +952,6 @@ struct CamFromRecords {
   }
 };
 
-// ... or, for the n_hot most observed cameras, from a table in LDS
-// (kLdsCamVals values per camera: x, then Pbar row-major).
-template <typename T>
-struct CamFromLds {
-  const T POVAR_LDS* tab;
-  CamFromRecords<T> g;
-  int n_hot;
-  __device__ __forceinline__ void operator()(int c, T (&xc)[12], T (&Pc)[12]) const {
-    if (c < n_hot) {
-      const T POVAR_LDS* e = tab + c * kLdsCamVals;
-#pragma unroll
-      for (int k = 0; k < 12; ++k) xc[k] = e[k];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        Pc[4 * r] = e[12 + 3 * r];
-        Pc[4 * r + 1] = e[13 + 3 * r];
-        Pc[4 * r + 2] = e[14 + 3 * r];
-        Pc[4 * r + 3] = 0;
-      }
-    } else {
-      g(c, xc, Pc);
-    }
-  }
-};
-
 // The first loads of a packet slot (this lane's entry and the slot header),
 // which depend on nothing else.
 template <typename T>
@@ -1017,16 +1000,29 @@ __device__ __forceinline__ void landmark_slot(const DevProblem& D, int q, const 
         }
         load4(rec + (size_t)(lm0 + key) * kRec + 4, X0, X1, X2, one);
       }
-      f4v pc[1][kCoopPieces];
       const int src[1] = {act ? (int)(code & kCamMask) : -1};
-      coop_fetch<kCoopPieces>((const char POVAR_GMEM*)cam.S, (size_t)cam.stride * sizeof(T), src, cbuf, pc);
+      if constexpr (sizeof(T) == 4) {
+        f4v pc[1][kCoopPieces];
+        coop_fetch<kCoopPieces>((const char POVAR_GMEM*)cam.S, (size_t)cam.stride * sizeof(T), src, cbuf, pc);
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
+        for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          Pc[4 * r + k] = pc[0][r][k];
-          xc[4 * r + k] = pc[0][3 + r][k];
+          for (int k = 0; k < 4; ++k) {
+            Pc[4 * r + k] = pc[0][r][k];
+            xc[4 * r + k] = pc[0][3 + r][k];
+          }
+      } else {
+        // P and x (96 bytes each) in two gathers through the same buffer
+        f4v pp[1][kCoopPieces], px[1][kCoopPieces];
+        const char POVAR_GMEM* base = (const char POVAR_GMEM*)cam.S;
+        coop_fetch<kCoopPieces>(base, (size_t)cam.stride * sizeof(T), src, cbuf, pp);
+        coop_fetch<kCoopPieces>(base + kSerX * sizeof(T), (size_t)cam.stride * sizeof(T), src, cbuf, px);
+#pragma unroll
+        for (int i = 0; i < kCoopPieces; ++i) {
+          piece_d2(pp[0][i], Pc[2 * i], Pc[2 * i + 1]);
+          piece_d2(px[0][i], xc[2 * i], xc[2 * i + 1]);
         }
+      }
     }
     if (act) {
       const int c = (int)(code & kCamMask);
@@ -1110,41 +1106,21 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark_coop(Batch B, int t)
   }
 }
 
-// Landmark pass of a single large problem: one persistent workgroup of
-// kLdsBlock threads per CU first copies x_i and Pbar_i of the n_hot most
-// observed cameras (internal ids below n_hot) into LDS, then its waves walk
-// the packet slots; the other cameras are read from the series records.
-template <typename T>
-__global__ void __launch_bounds__(kLdsBlock) k_series_landmark_lds(Batch B, int t) {
-  const DevProblem& D = B.probs[0];
+// FP64 landmark pass of batches holding problems with 256-byte camera
+// records (stride kSerLine): P and x gathered cooperatively, through a 6 KB
+// LDS buffer per wave; the other problems per lane.
+__global__ void __launch_bounds__(kBlock) k_series_landmark_coop64(Batch B, int t) {
+  int p, q;
+  if (!map_wave(B, kUnitPacket, p, q)) return;
+  DevProblem& D = B.probs[p];
   if (D.ctl.done || t > D.ctl.stop_at) return;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  T POVAR_LDS* tab = (T POVAR_LDS*)lds_raw;
-  const int n_hot = D.n_hot, ss = D.s_stride;
-  const T* __restrict__ S = Prec<T>::S(D, D.ctl.pcur);
-  for (int idx = threadIdx.x; idx < n_hot * kLdsCamVals; idx += kLdsBlock) {
-    const int h = idx / kLdsCamVals, k = idx - h * kLdsCamVals;
-    const int src = k < 12 ? kSerX + k : (k - 12) / 3 * 4 + (k - 12) % 3;
-    tab[idx] = S[(size_t)h * ss + src];
-  }
-  __syncthreads();
-  const CamFromLds<T> cam{tab, CamFromRecords<T>{S, ss}, n_hot};
-  const int lc = D.ctl.lcur;
-  const int waves = kLdsBlock / kWave;
-  const int stride = (int)gridDim.x * waves;
-  // the next slot's entry and header loads are issued before this slot's work
-  int q = (int)blockIdx.x * waves + (int)(threadIdx.x >> 6);
-  if (q >= D.n_pk) return;
-  SlotHead<T> head = slot_head<T>(D, q);
-  for (;;) {
-    const int qn = q + stride;
-    const bool more = qn < D.n_pk;
-    SlotHead<T> next = head;
-    if (more) next = slot_head<T>(D, qn);
-    landmark_slot<T>(D, q, head, lc, cam);
-    if (!more) break;
-    q = qn;
-    head = next;
+  const CamFromRecords<double> cam{Prec<double>::S(D, D.ctl.pcur), D.s_stride};
+  if (D.s_stride == kSerLine) {
+    __shared__ f4v cbuf[kWavesPerBlock][kCoopPieces * kWave];
+    landmark_slot<double, CamFromRecords<double>, true>(D, q, slot_head<double>(D, q), D.ctl.lcur, cam,
+                                                        (f4v POVAR_LDS*)cbuf[threadIdx.x >> 6]);
+  } else {
+    landmark_slot<double>(D, q, slot_head<double>(D, q), D.ctl.lcur, cam);
   }
 }
 
@@ -1915,14 +1891,6 @@ __device__ __forceinline__ void refine_wt(const Proj2& g, const double (&y)[12],
 // Landmark pass over packets shared by the series (z_j = G_j sum W^T x_i) and
 // the back-substitution (dl_j = -G_j (b_l + sum W^T dp_i), then the landmark
 // is retracted into the other buffer).
-// A 16-byte piece of a cooperative gather as two doubles.
-__device__ __forceinline__ void piece_d2(f4v v, double& a, double& b) {
-  typedef double d2v __attribute__((ext_vector_type(2)));
-  const d2v d = __builtin_bit_cast(d2v, v);
-  a = d[0];
-  b = d[1];
-}
-
 template <bool Update>
 __device__ __forceinline__ void refine_landmark_slot(DevProblem& D, int q, f4v POVAR_LDS* cbuf) {
   const double* __restrict__ P = D.ctl.pcur ? D.P64[1] : D.P64[0];
@@ -2277,32 +2245,13 @@ hipError_t launch_camera_prep(const Batch& b, bool fp32, hipStream_t s) {
 
 // With ev0/ev1 set, the events are recorded by the dispatch itself
 // (hipExtLaunchKernelGGL), so their interval is the kernel's execution.
-hipError_t prepare_landmark_lds(int bytes) {
-  static std::mutex mu;
-  static int enabled = 0;
-  std::lock_guard<std::mutex> g(mu);
-  if (bytes <= enabled) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_series_landmark_lds<float>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_series_landmark_lds<double>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess) enabled = bytes;
-  return e;
-}
-
 hipError_t launch_series_landmark(const Batch& b, bool fp32, int t, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (b.total[kUnitPacket] == 0) return hipSuccess;
-  if (b.lds_bytes > 0 && b.n_prob == 1) {
-    const dim3 g((unsigned)b.lds_grid);
-    const size_t sh = (size_t)b.lds_bytes;
-    if (fp32) hipExtLaunchKernelGGL(k_series_landmark_lds<float>, g, dim3(kLdsBlock), sh, s, ev0, ev1, 0, b, t);
-    else hipExtLaunchKernelGGL(k_series_landmark_lds<double>, g, dim3(kLdsBlock), sh, s, ev0, ev1, 0, b, t);
-    return hipGetLastError();
-  }
   const dim3 g = blocks_for(b.total[kUnitPacket], kWavesPerBlock);
   if (fp32 && b.coop_cams)
     hipExtLaunchKernelGGL(k_series_landmark_coop, g, dim3(kBlock), kCoopLdsBytes, s, ev0, ev1, 0, b, t);
+  else if (b.coop_cams)
+    hipExtLaunchKernelGGL(k_series_landmark_coop64, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
   else if (fp32) hipExtLaunchKernelGGL(k_series_landmark<float>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
   else hipExtLaunchKernelGGL(k_series_landmark<double>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
   return hipGetLastError();

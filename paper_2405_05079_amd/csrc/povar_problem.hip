@@ -789,23 +789,6 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.cs_m64 = (const double2*)dp(A.cs_m64);
   R.ser_off = H.blocked ? (const int32_t*)dp(A.run_off) : (const int32_t*)dp(A.cam_ch);
   R.ser_mc = (const int32_t*)dp(A.smc);
-  // a single large FP64 problem stages the series data of its most observed
-  // cameras in LDS for the landmark pass (measured faster than gathering them
-  // from L2 in FP64; in FP32 the plain pass with more resident waves is faster)
-  int lds_bytes = 0, lds_grid = 0;
-  if (H.blocked && !rec_dev && !pb->fp32) {
-    int max_lds = 0, n_cu = 0;
-    HIP_TRY(ctx, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
-    HIP_TRY(ctx, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
-    const int per = kLdsCamVals * 8;
-    const int n_hot = std::min<int>(H.n_p, max_lds / per);
-    if (n_hot > 0 && n_cu > 0) {
-      R.n_hot = n_hot;
-      lds_bytes = n_hot * per;
-      lds_grid = n_cu;
-      HIP_TRY(ctx, prepare_landmark_lds(lds_bytes));
-    }
-  }
   for (int b = 0; b < 2; ++b) {
     R.P64[b] = (double*)dp(A.P64[b]);
     R.S32[b] = (float*)dp(A.S32[b]);
@@ -921,9 +904,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   B.tab_stride = 2;
   for (int k = 0; k < kNumUnitKinds; ++k) B.total[k] = units[k];
   B.n_prob = 1;
-  B.lds_bytes = lds_bytes;
-  B.lds_grid = lds_grid;
-  B.coop_cams = pb->fp32 && R.s_stride == kSerLine ? 1 : 0;
+  B.coop_cams = R.s_stride == kSerLine ? 1 : 0;
   B.pad = 0;
   if (pts0) {
     // second stage: the cost (7) at the given cameras and landmarks
@@ -1784,9 +1765,9 @@ povar_status povar_debug_layout_check(int32_t n_cams, int32_t n_pts, int64_t n_o
 }
 
 povar_status povar_problem_layout(povar_problem pb, int32_t* blocked, int32_t* lm_block, int64_t* n_slots,
-                                  int64_t* n_runs, int32_t* n_lds_cams) {
+                                  int64_t* n_runs, int32_t* coop_gather) {
   if (!pb) return POVAR_EINVAL;
-  if (n_lds_cams) *n_lds_cams = pb->batch.lds_bytes > 0 ? pb->rec.n_hot : 0;
+  if (coop_gather) *coop_gather = pb->batch.coop_cams;
   if (blocked) *blocked = pb->L.blocked;
   if (lm_block) *lm_block = pb->L.lm_block;
   if (n_slots) *n_slots = pb->L.blocked ? pb->L.n_cs : 0;

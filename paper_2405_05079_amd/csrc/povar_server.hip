@@ -121,12 +121,10 @@ hipError_t upload_tables(povar_server_s* sv, Group& G) {
   if (e != hipSuccess) return e;
   G.batch.probs = G.recs;
   G.batch.n_prob = n;
-  G.batch.lds_bytes = 0;   // batches use the plain landmark pass
-  G.batch.lds_grid = 0;
   G.batch.coop_cams = 0;
   G.batch.pad = 0;
   for (int p = 0; p < n; ++p)
-    if (G.res[p].pb->fp32 && G.res[p].pb->rec.s_stride == kSerLine) G.batch.coop_cams = 1;
+    if (G.res[p].pb->rec.s_stride == kSerLine) G.batch.coop_cams = 1;
   G.batch.tables = G.tables;
   G.batch.tab_stride = stride;
   for (int k = 0; k < kNumUnitKinds; ++k) G.batch.total[k] = tab[(size_t)k * stride + n];

@@ -417,7 +417,7 @@ class Problem:
         self._chk(lib().povar_problem_layout(self.handle, C.byref(b), C.byref(lb), C.byref(ns), C.byref(nr),
                                              C.byref(nh)), "povar_problem_layout")
         return dict(blocked=bool(b.value), lm_block=lb.value, n_slots=ns.value, n_runs=nr.value,
-                    n_lds_cams=nh.value)
+                    coop_gather=bool(nh.value))
 
     def close(self):
         if self.handle:

@@ -118,6 +118,24 @@ def test_camera_step_fp32_bulk(ctx, lam, order, kw):
     gp.close()
 
 
+@pytest.mark.parametrize("lam,order", [(1e-4, 10), (1.0, 20)])
+def test_camera_step_fp64_cooperative(ctx, lam, order):
+    """400 cameras in FP64: 256-byte series records, whose P and x the
+    landmark pass gathers cooperatively (two 96-byte gathers per record)."""
+    prob = case(**FP32_STEP[1])
+    say("step fp64 400 cameras", lam, order)
+    gp = povar.Problem.from_synth(ctx, prob, precision="fp64")
+    dp, pt, ct = gp.debug_step(lam, order)
+    P, X, f = O.initial_state(prob, prob.cams0)
+    ref = O.camera_step(P, O.linearize(P, X, prob), lam, order)
+    assert rel(dp, ref) < 1e-9
+    Pn = O.retract(P, ref)
+    assert rel(pt, Pn) < 1e-9
+    Xn, _ = O.solve_landmarks(Pn, prob)
+    assert abs(ct - O.cost(Pn, Xn, prob)) <= 1e-8 * O.cost(Pn, Xn, prob)
+    gp.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32_bulk", 2e-3)])
 def test_series_early_stop(ctx, prec, tol):
     """series_rtol = 0.01: the series stops after the first term t >= 1 with
@@ -200,13 +218,7 @@ def test_blocked_camera_pass(ctx, prec, kw, tol):
     assert lay["blocked"] and lay["n_slots"] > 0 and lay["n_runs"] >= prob.n_cams
     # the footprint from sizes alone bounds the built layout's device bytes
     assert gp.info()["device_bytes"] <= povar.footprint(prob.n_cams, prob.n_pts, prob.n_obs, prec)
-    # FP64 problems stage their most observed cameras in LDS for the landmark pass
-    if prec == "fp64":
-        assert 0 < lay["n_lds_cams"] <= prob.n_cams
-        if prob.n_cams == 1200:
-            assert lay["n_lds_cams"] < prob.n_cams
-    else:
-        assert lay["n_lds_cams"] == 0
+    assert lay["coop_gather"] == (prob.n_cams > 341)
     P, X, f = O.initial_state(prob, prob.cams0)
     lin = O.linearize(P, X, prob)
     for lam, order in ((1e-3, 1), (1e-3, 8)):
