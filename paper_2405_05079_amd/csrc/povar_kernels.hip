@@ -1331,12 +1331,17 @@ __global__ void __launch_bounds__(kBlock) k_series_camera_slots(Batch B, int t) 
         x[r][k] = rz[r][1][k];
       }
   } else {
+    // the 64-byte records fetched by groups of four lanes (a quarter of the L1 lookups)
+    __shared__ f4v cbuf[kWavesPerBlock][4 * kWave];
+    f4v rz[kCsPerLane][4];
+    coop_fetch<4, kCsPerLane>((const char POVAR_GMEM*)zx, kRec * sizeof(T), jr,
+                              (f4v POVAR_LDS*)cbuf[threadIdx.x >> 6], rz);
 #pragma unroll
     for (int r = 0; r < kCsPerLane; ++r) {
-      if (jr[r] >= 0) {
-        load4(zx + (size_t)jr[r] * kRec, z[r][0], z[r][1], z[r][2], z[r][3]);
-        load4(zx + (size_t)jr[r] * kRec + 4, x[r][0], x[r][1], x[r][2], x[r][3]);
-      }
+      piece_d2(rz[r][0], z[r][0], z[r][1]);
+      piece_d2(rz[r][1], z[r][2], z[r][3]);
+      piece_d2(rz[r][2], x[r][0], x[r][1]);
+      piece_d2(rz[r][3], x[r][2], x[r][3]);
     }
   }
   const T a = (T)(1.0 - D.eta);
@@ -2105,11 +2110,18 @@ __global__ void __launch_bounds__(kBlock) k_refine_series_camera_slots(Batch B, 
     for (int k = 0; k < 12; ++k) Pc[k] = 0.0;
   const double* __restrict__ zx = static_cast<const double*>(D.zx);
   double z[kCsPerLane][4], X[kCsPerLane][4];
+  {
+    // (z, X) records fetched by groups of four lanes
+    __shared__ f4v cbuf[kWavesPerBlock][4 * kWave];
+    f4v rz[kCsPerLane][4];
+    coop_fetch<4, kCsPerLane>((const char POVAR_GMEM*)zx, kRec * sizeof(double), jr,
+                              (f4v POVAR_LDS*)cbuf[threadIdx.x >> 6], rz);
 #pragma unroll
-  for (int r = 0; r < kCsPerLane; ++r) {
-    if (jr[r] >= 0) {
-      load4(zx + (size_t)jr[r] * kRec, z[r][0], z[r][1], z[r][2], z[r][3]);
-      load4(zx + (size_t)jr[r] * kRec + 4, X[r][0], X[r][1], X[r][2], X[r][3]);
+    for (int r = 0; r < kCsPerLane; ++r) {
+      piece_d2(rz[r][0], z[r][0], z[r][1]);
+      piece_d2(rz[r][1], z[r][2], z[r][3]);
+      piece_d2(rz[r][2], X[r][0], X[r][1]);
+      piece_d2(rz[r][3], X[r][2], X[r][3]);
     }
   }
   double acc[12];
