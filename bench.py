@@ -494,8 +494,8 @@ def main():
         out["refine"] = refine_leg(ctx, prob, *stage1, min(args.steps, 50))
         print(f"[bench] refinement: {out['refine']['iters_per_s']} iters/s", file=sys.stderr, flush=True)
     if not args.no_metric:
-        out["metric"] = metric_leg(ctx)
-        print(f"[bench] metric upgrade: {out['metric']}", file=sys.stderr, flush=True)
+        out["metric_upgrade"] = metric_leg(ctx)
+        print(f"[bench] metric upgrade: {out['metric_upgrade']}", file=sys.stderr, flush=True)
     if args.serve > 0:
         out["serving"] = serving(ctx, args.serve, args.serve_budget, args.serve_slots)
         print(f"[bench] serving: p50 {out['serving']['p50_s']} s, p99 {out['serving']['p99_s']} s",
