@@ -18,6 +18,12 @@
  * (18)-(29)), retracts by normalisation, re-solves the landmarks and accepts
  * or rejects the step with a Levenberg-Marquardt damping schedule (Sec. 5.2).
  *
+ * The stratified pipeline of Sec. 3 continues with two more calls: the
+ * projective refinement of objective (7) with the Riemannian power-series
+ * solver on both blocks (povar_refine_create, then the same solve/step
+ * calls), and the metric upgrade with known intrinsics (povar_metric_upgrade,
+ * the supplement's App. D).
+ *
  * Conventions shared by every call:
  *  - Every call returns povar_status; 0 (POVAR_OK) is success.  No C++
  *    exception crosses this boundary.  On failure, povar_last_error(ctx)
