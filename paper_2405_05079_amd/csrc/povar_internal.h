@@ -35,7 +35,7 @@ constexpr uint32_t kCamMask = (1u << kCamBits) - 1u;
 
 // Landmark slot strides (elements) in the per-landmark arrays.
 constexpr int kRec = 8;                   // (z0, z1, z2, 0, X0, X1, X2, 1)
-constexpr int kLmSym = 8;                 // V^+ : 6 values (00,01,02,11,12,22) + 2 pad
+constexpr int kLmSym = 6;                 // V^+ : 6 values (00,01,02,11,12,22), 48 bytes
 constexpr int kCam = 12;                  // one camera / camera vector
 constexpr int kCamMat = 144;              // 12 x 12 camera operator
 // Series camera record: P (12 values) then x (12 values).  Packed (stride 24)
@@ -110,6 +110,10 @@ struct DevProblem {
   // record (z0 = V^+ b_l, X) per landmark, and V^+
   double POVAR_GMEM* rec64[2];         // n_l x 8
   float POVAR_GMEM* rec32[2];
+  // (X, 1) of the same records, compact (n_l x 4): what the landmark series
+  // pass reads, half the bytes of the full records
+  double POVAR_GMEM* xs64[2];
+  float POVAR_GMEM* xs32[2];
   double POVAR_GMEM* Vp64[2];          // n_l x 8
 
   // linearisation per camera

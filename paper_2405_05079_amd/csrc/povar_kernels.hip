@@ -310,6 +310,7 @@ template <> struct Prec<float> {
   // series record of buffer b: P at 0, x at kSerX (stride s_stride)
   __device__ static float POVAR_GMEM* S(const DevProblem& D, int b) { return b ? D.S32[1] : D.S32[0]; }
   __device__ static const float POVAR_GMEM* rec(const DevProblem& D, int b) { return b ? D.rec32[1] : D.rec32[0]; }
+  __device__ static const float POVAR_GMEM* xs(const DevProblem& D, int b) { return b ? D.xs32[1] : D.xs32[0]; }
 };
 template <> struct Prec<double> {
   using T2 = double2;
@@ -318,7 +319,16 @@ template <> struct Prec<double> {
   __device__ static const double2 POVAR_GMEM* cs_m(const DevProblem& D) { return D.cs_m64; }
   __device__ static double POVAR_GMEM* S(const DevProblem& D, int b) { return b ? D.S64[1] : D.S64[0]; }
   __device__ static const double POVAR_GMEM* rec(const DevProblem& D, int b) { return b ? D.rec64[1] : D.rec64[0]; }
+  __device__ static const double POVAR_GMEM* xs(const DevProblem& D, int b) { return b ? D.xs64[1] : D.xs64[0]; }
 };
+
+// Two consecutive doubles (16 B aligned).
+template <typename Ptr>
+__device__ __forceinline__ void load_d2(Ptr p, double& a, double& b) {
+  const double2 v = *(const double2 POVAR_GMEM*)(p);
+  a = v.x;
+  b = v.y;
+}
 
 // Vector loads and stores of 4 / 12 consecutive elements of device memory
 // (16 B aligned), through global-address-space pointers.
@@ -499,8 +509,10 @@ __device__ __forceinline__ void store_landmark(DevProblem& D, int lc, int j, con
   store4(r64 + 4, X0, X1, X2, 1.0);
   store4(r32, (float)z0, (float)z1, (float)z2, 0.0f);
   store4(r32 + 4, (float)X0, (float)X1, (float)X2, 1.0f);
+  store4((lc ? D.xs64[1] : D.xs64[0]) + (size_t)j * 4, X0, X1, X2, 1.0);
+  store4((lc ? D.xs32[1] : D.xs32[0]) + (size_t)j * 4, (float)X0, (float)X1, (float)X2, 1.0f);
   store4(v64, vp[0], vp[1], vp[2], vp[3]);
-  store4(v64 + 4, vp[4], vp[5], 0.0, 0.0);
+  *(double2 POVAR_GMEM*)(v64 + 4) = make_double2(vp[4], vp[5]);
 }
 
 // mode 0: initial state, 1: trial point of a step (other buffers), 2: re-solve
@@ -975,7 +987,7 @@ __device__ __forceinline__ void landmark_slot(const DevProblem& D, int q, const 
                                               const Cam& cam, f4v POVAR_LDS* cbuf = nullptr) {
   const int lane = lane_id();
   const int off = q * kWave;
-  const T* __restrict__ rec = Prec<T>::rec(D, lc);
+  const T* __restrict__ xs = Prec<T>::xs(D, lc);
   const typename Prec<T>::T2* __restrict__ em = Prec<T>::pk_m(D);
   const T a = (T)(1.0 - D.eta);
   T* zx = static_cast<T*>(D.zx);
@@ -996,9 +1008,9 @@ __device__ __forceinline__ void landmark_slot(const DevProblem& D, int q, const 
         if (tail) {
           const double* vp = (lc ? D.Vp64[1] : D.Vp64[0]) + (size_t)(lm0 + key) * kLmSym;
           load4(vp, v[0], v[1], v[2], v[3]);
-          load4(vp + 4, v[4], v[5], v[6], v[7]);
+          load_d2(vp + 4, v[4], v[5]);
         }
-        load4(rec + (size_t)(lm0 + key) * kRec + 4, X0, X1, X2, one);
+        load4(xs + (size_t)(lm0 + key) * 4, X0, X1, X2, one);
       }
       const int src[1] = {act ? (int)(code & kCamMask) : -1};
       if constexpr (sizeof(T) == 4) {
@@ -1031,9 +1043,9 @@ __device__ __forceinline__ void landmark_slot(const DevProblem& D, int q, const 
         if (tail) {
           const double* vp = (lc ? D.Vp64[1] : D.Vp64[0]) + (size_t)(lm0 + key) * kLmSym;
           load4(vp, v[0], v[1], v[2], v[3]);
-          load4(vp + 4, v[4], v[5], v[6], v[7]);
+          load_d2(vp + 4, v[4], v[5]);
         }
-        load4(rec + (size_t)(lm0 + key) * kRec + 4, X0, X1, X2, one);
+        load4(xs + (size_t)(lm0 + key) * 4, X0, X1, X2, one);
         cam(c, xc, Pc);
       }
       const auto m = mraw;
@@ -1051,12 +1063,12 @@ __device__ __forceinline__ void landmark_slot(const DevProblem& D, int q, const 
     if (tail) store_z<T>(v, lm0 + key, y[0], y[1], y[2], X0, X1, X2, zx);
   } else {
     T X0, X1, X2, one;
-    load4(rec + (size_t)lm0 * kRec + 4, X0, X1, X2, one);
+    load4(xs + (size_t)lm0 * 4, X0, X1, X2, one);
     T y0 = 0, y1 = 0, y2 = 0;
     double v[8];
     const double* vp = (lc ? D.Vp64[1] : D.Vp64[0]) + (size_t)lm0 * kLmSym;
     load4(vp, v[0], v[1], v[2], v[3]);
-    load4(vp + 4, v[4], v[5], v[6], v[7]);
+    load_d2(vp + 4, v[4], v[5]);
     for (int e = off + lane; e < off + n; e += kWave) {
       const int c = (int)(D.pk_code[e] & kCamMask);
       const auto m = em[e];
