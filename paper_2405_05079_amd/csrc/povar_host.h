@@ -64,6 +64,7 @@ struct ArenaOffsets {
   size_t P64[2], S32[2], S64[2], rec64[2], rec32[2], xs64[2], xs32[2], Vp64[2];
   size_t lin_part, K64, g64, U40, acc, zx, t_part, cost_part, cost_group;
   size_t tr_cost, tr_lambda, tr_acc, rec, tables;
+  size_t init_end;   // buffers with initial values lie below this offset
 };
 
 size_t arena_bytes(const LayoutSizes& z, bool fp32, int64_t trace_cap, ArenaOffsets* o);

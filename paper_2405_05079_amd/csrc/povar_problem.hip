@@ -76,12 +76,25 @@ size_t arena_bytes(const LayoutSizes& z, bool fp32, int64_t trace_cap, ArenaOffs
   r.cs_m64 = fp32 ? SIZE_MAX : a.take(n_cs * kCsObs * 16);
   r.run_off = a.take((n_p + 1) * 4);
   r.smc = a.take((z.blocked ? n_p : n_mc) * 4);
+  // the other buffers with initial values (current cameras and series
+  // records, second-stage landmarks, the problem record, unit tables) end the
+  // prefix that problem creation copies from the host; the rest is cleared
+  // on the device
+  r.P64[0] = a.take(n_p * kCam * 8);
+  r.S32[0] = fp32 ? a.take(n_p * ser_stride((int)n_p) * 4) : SIZE_MAX;
+  r.S64[0] = fp32 ? SIZE_MAX : a.take(n_p * ser_stride((int)n_p) * 8);
+  r.rec64[0] = a.take(n_l * kRec * 8);
+  r.rec = a.take(sizeof(DevProblem));
+  r.tables = a.take(kNumUnitKinds * 2 * 4);
+  r.init_end = a.total;
   r.t_run = a.take(n_runs * kCam * ts);
   for (int b = 0; b < 2; ++b) {
-    r.P64[b] = a.take(n_p * kCam * 8);
-    r.S32[b] = fp32 ? a.take(n_p * ser_stride((int)n_p) * 4) : SIZE_MAX;
-    r.S64[b] = fp32 ? SIZE_MAX : a.take(n_p * ser_stride((int)n_p) * 8);
-    r.rec64[b] = a.take(n_l * kRec * 8);
+    if (b == 1) {
+      r.P64[b] = a.take(n_p * kCam * 8);
+      r.S32[b] = fp32 ? a.take(n_p * ser_stride((int)n_p) * 4) : SIZE_MAX;
+      r.S64[b] = fp32 ? SIZE_MAX : a.take(n_p * ser_stride((int)n_p) * 8);
+      r.rec64[b] = a.take(n_l * kRec * 8);
+    }
     r.rec32[b] = a.take(n_l * kRec * 4);
     r.xs64[b] = a.take(n_l * 4 * 8);
     r.xs32[b] = a.take(n_l * 4 * 4);
@@ -99,8 +112,6 @@ size_t arena_bytes(const LayoutSizes& z, bool fp32, int64_t trace_cap, ArenaOffs
   r.tr_cost = a.take(trace_cap * 8);
   r.tr_lambda = a.take(trace_cap * 8);
   r.tr_acc = a.take(trace_cap * 4);
-  r.rec = a.take(sizeof(DevProblem));
-  r.tables = a.take(kNumUnitKinds * 2 * 4);
   return a.total;
 }
 
@@ -698,8 +709,12 @@ povar_status check_options(povar_ctx ctx, const povar_options* o) {
 }
 
 template <typename T>
-static void upload(std::vector<char>& staging, size_t off, const std::vector<T>& v) {
-  if (!v.empty()) std::memcpy(staging.data() + off, v.data(), v.size() * sizeof(T));
+static bool upload(std::vector<char>& staging, size_t off, const std::vector<T>& v) {
+  // every buffer with an initial value lies in the staged prefix
+  if (v.empty()) return true;
+  if (off > staging.size() || v.size() * sizeof(T) > staging.size() - off) return false;
+  std::memcpy(staging.data() + off, v.data(), v.size() * sizeof(T));
+  return true;
 }
 
 // Builds the device state of a problem from a host layout and initial
@@ -868,34 +883,41 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
     tables[2 * k + 1] = units[k];
   }
 
-  // one staging image of everything that has an initial value
-  std::vector<char> img(pb->bytes, 0);
-  upload(img, A.pk_hdr, H.pk_hdr);
-  upload(img, A.pk_code, H.pk_code);
-  if (A.pk_m32 != SIZE_MAX) upload(img, A.pk_m32, H.pk_m32);
-  upload(img, A.pk_m64, H.pk_m64);
-  upload(img, A.cm_lm, H.cm_lm);
-  if (A.cm_m32 != SIZE_MAX) upload(img, A.cm_m32, H.cm_m32);
-  if (A.cm_m64 != SIZE_MAX) upload(img, A.cm_m64, H.cm_m64);
-  upload(img, A.ch_meta, H.ch_meta);
-  upload(img, A.cam_ch, H.cam_ch);
-  upload(img, A.mc_cam, H.mc_cam);
-  upload(img, A.smc, H.smc);
+  // one staging image of the arena's prefix with initial values; the rest is
+  // cleared on the device
+  std::vector<char> img(A.init_end, 0);
+  bool staged = true;
+  staged &= upload(img, A.pk_hdr, H.pk_hdr);
+  staged &= upload(img, A.pk_code, H.pk_code);
+  if (A.pk_m32 != SIZE_MAX) staged &= upload(img, A.pk_m32, H.pk_m32);
+  staged &= upload(img, A.pk_m64, H.pk_m64);
+  staged &= upload(img, A.cm_lm, H.cm_lm);
+  if (A.cm_m32 != SIZE_MAX) staged &= upload(img, A.cm_m32, H.cm_m32);
+  if (A.cm_m64 != SIZE_MAX) staged &= upload(img, A.cm_m64, H.cm_m64);
+  staged &= upload(img, A.ch_meta, H.ch_meta);
+  staged &= upload(img, A.cam_ch, H.cam_ch);
+  staged &= upload(img, A.mc_cam, H.mc_cam);
+  staged &= upload(img, A.smc, H.smc);
   if (H.blocked) {
-    upload(img, A.cs_hdr, H.cs_hdr);
-    upload(img, A.cs_lane, H.cs_lane);
-    upload(img, A.cs_lm, H.cs_lm);
-    if (A.cs_m32 != SIZE_MAX) upload(img, A.cs_m32, H.cs_m32);
-    if (A.cs_m64 != SIZE_MAX) upload(img, A.cs_m64, H.cs_m64);
-    upload(img, A.run_off, H.run_off);
+    staged &= upload(img, A.cs_hdr, H.cs_hdr);
+    staged &= upload(img, A.cs_lane, H.cs_lane);
+    staged &= upload(img, A.cs_lm, H.cs_lm);
+    if (A.cs_m32 != SIZE_MAX) staged &= upload(img, A.cs_m32, H.cs_m32);
+    if (A.cs_m64 != SIZE_MAX) staged &= upload(img, A.cs_m64, H.cs_m64);
+    staged &= upload(img, A.run_off, H.run_off);
   }
-  upload(img, A.P64[0], P64);
-  if (pts0) upload(img, A.rec64[0], X4);
-  if (pb->fp32) upload(img, A.S32[0], S32);
-  else upload(img, A.S64[0], S64);
+  staged &= upload(img, A.P64[0], P64);
+  if (pts0) staged &= upload(img, A.rec64[0], X4);
+  if (pb->fp32) staged &= upload(img, A.S32[0], S32);
+  else staged &= upload(img, A.S64[0], S64);
+  if (!staged || A.rec + sizeof(R) > A.init_end || A.tables + sizeof(int32_t) * kNumUnitKinds * 2 > A.init_end) {
+    set_error(ctx, "internal: a buffer with an initial value lies outside the staged prefix");
+    return POVAR_EDEVICE;
+  }
   std::memcpy(img.data() + A.rec, &R, sizeof(R));
   std::memcpy(img.data() + A.tables, tables, sizeof(tables));
-  HIP_TRY(ctx, hipMemcpyAsync(pb->arena, img.data(), pb->bytes, hipMemcpyHostToDevice, stream));
+  HIP_TRY(ctx, hipMemcpyAsync(pb->arena, img.data(), A.init_end, hipMemcpyHostToDevice, stream));
+  HIP_TRY(ctx, hipMemsetAsync(static_cast<char*>(pb->arena) + A.init_end, 0, pb->bytes - A.init_end, stream));
   HIP_TRY(ctx, hipStreamSynchronize(stream));   // the staging image is freed on return
 
   Batch& B = pb->batch;
