@@ -157,6 +157,23 @@ def refine_leg(ctx, prob, P1, X1, steps: int):
                                      "iters": grep_["iters"]}}
 
 
+def eta_sweep(ctx, prob, iters: int):
+    """The pOSE weight eta at the paper's main value (0.1) and its ablation
+    values (0.2-0.4) on the same problem and kernels: FP32-bulk iterations
+    per second and the cost after `iters` iterations from the same random
+    cameras.  Costs of different eta are different objectives."""
+    out = {}
+    for eta in (0.1, 0.2, 0.3, 0.4):
+        gp = povar.Problem.from_synth(ctx, prob, precision="fp32_bulk", eta=eta, ftol=0.0, max_iters=10 ** 6)
+        gp.step(5)
+        secs = timed_iters(gp, iters)
+        rep = gp.report()
+        gp.close()
+        out[str(eta)] = {"iters_per_s": round(iters / secs, 1), "cost_initial": rep["cost_initial"],
+                         "cost_after": rep["cost_final"], "iters": rep["iters"]}
+    return out
+
+
 def metric_leg(ctx, reps: int = 5):
     """The metric upgrade (App. D) at 250 and 13,700 cameras: calibrated
     cameras seen through a random projective frame, each with a random scale
@@ -363,6 +380,7 @@ def main():
     ap.add_argument("--no-refine", action="store_true",
                     help="skip the second-stage (projective refinement) leg")
     ap.add_argument("--no-metric", action="store_true", help="skip the metric-upgrade leg")
+    ap.add_argument("--no-eta-sweep", action="store_true", help="skip the eta sweep (0.1-0.4)")
     ap.add_argument("--serve", type=int, default=128,
                     help="requests of the 512-request serving stream to run (0: skip)")
     ap.add_argument("--serve-budget", type=int, default=2 << 30)
@@ -394,6 +412,7 @@ def main():
         args.serve = 0
         args.no_cpu_baseline = True
         args.no_metric = True
+        args.no_eta_sweep = True
     print(f"[bench] workload {prob.name}: {prob.n_cams} cameras, {prob.n_pts} points, "
           f"{prob.n_obs} observations, order {prob.order}", file=sys.stderr, flush=True)
     ctx = povar.Context(0)
@@ -493,6 +512,9 @@ def main():
     if not args.no_refine:
         out["refine"] = refine_leg(ctx, prob, *stage1, min(args.steps, 50))
         print(f"[bench] refinement: {out['refine']['iters_per_s']} iters/s", file=sys.stderr, flush=True)
+    if not args.no_eta_sweep:
+        out["eta_sweep"] = eta_sweep(ctx, prob, min(args.steps, prob.iters))
+        print(f"[bench] eta sweep: {out['eta_sweep']}", file=sys.stderr, flush=True)
     if not args.no_metric:
         out["metric_upgrade"] = metric_leg(ctx)
         print(f"[bench] metric upgrade: {out['metric_upgrade']}", file=sys.stderr, flush=True)

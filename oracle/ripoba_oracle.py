@@ -160,17 +160,26 @@ def riemannian_system(P: np.ndarray, Xh: np.ndarray, lin: Linearization, lam: fl
     return RiemannianSystem(Bp=Bp, Bl=Bl, Ut=Ut, Vt=Vt, Wt=Wt, bpt=bpt, blt=blt)
 
 
-def series_solve(rs: RiemannianSystem, order: int):
+def series_solve(rs: RiemannianSystem, order: int, rtol: float = 0.0, info: dict | None = None):
     """Camera update by the truncated power series of the inverse Riemannian
     Schur complement (27)-(29), dx_p = -sum_{i=0..m} M^i U~^-1 g with
     g = b~_p - W~ V~^-1 b~_l; then the landmarks by back-substitution,
-    dx_l = -V~^-1 (b~_l + W~^T dx_p).  Tangent coordinates."""
+    dx_l = -V~^-1 (b~_l + W~^T dx_p).  Tangent coordinates.  rtol > 0: the
+    early stop of Sec. 5.2 as in the first stage (reading R6): after the first
+    term t >= 1 with ||x_t|| <= rtol ||x_0 + ... + x_t||, norms over all
+    cameras; info["terms"] receives the number of terms after the first."""
     g = rs.bpt - rs.Wt @ rs.apply_Vinv(rs.blt)
     x = -rs.apply_Uinv(g)
     acc = x.copy()
+    used = 0
     for _ in range(order):
         x = rs.apply_M(x)
         acc = acc + x
+        used += 1
+        if rtol > 0 and np.linalg.norm(x) <= rtol * np.linalg.norm(acc):
+            break
+    if info is not None:
+        info["terms"] = used
     dxl = -rs.apply_Vinv(rs.blt + rs.Wt.T @ acc)
     return acc, dxl
 
@@ -189,10 +198,11 @@ def retract(x: np.ndarray, dx: np.ndarray) -> np.ndarray:
     return y / np.linalg.norm(y, axis=1, keepdims=True)
 
 
-def step(P: np.ndarray, Xh: np.ndarray, lin: Linearization, lam: float, order: int):
+def step(P: np.ndarray, Xh: np.ndarray, lin: Linearization, lam: float, order: int, rtol: float = 0.0,
+         info: dict | None = None):
     """One RiPoBA update: ambient (dP, dX) in the tangent spaces."""
     rs = riemannian_system(P, Xh, lin, lam)
-    return back_project(rs, *series_solve(rs, order))
+    return back_project(rs, *series_solve(rs, order, rtol, info))
 
 
 # ----------------------------------------------------------------------------
@@ -206,6 +216,7 @@ class Options:
     lambda0: float = 1e-4
     lambda_min: float = 1e-12
     lambda_max: float = 1e12
+    series_rtol: float = 0.0
 
 
 @dataclass
@@ -239,7 +250,7 @@ def lm_solve(prob, P0: np.ndarray, Xh0: np.ndarray, opts: Options | None = None)
     lam = opts.lambda0
     lin = linearize(P, Xh, prob)
     for it in range(opts.max_iters):
-        dP, dX = step(P, Xh, lin, lam, opts.order)
+        dP, dX = step(P, Xh, lin, lam, opts.order, opts.series_rtol)
         Pn, Xn = retract(P, dP), retract(Xh, dX)
         fn = cost(Pn, Xn, prob)
         res.trace_cost.append(fn)

@@ -309,6 +309,21 @@ def test_checkpoint_resume_is_bitwise(ctx):
         g.close()
 
 
+@pytest.mark.parametrize("eta", [0.1, 0.2, 0.3, 0.4])
+def test_paper_eta_values(ctx, eta):
+    """The paper's main setting (eta = 0.1) and its ablation (0.2-0.4) as the
+    runtime option on the same kernels: one order-10 step in both precisions."""
+    prob = case(n_cams=10, n_pts=400, seed=13, eta=eta)
+    say("eta", eta)
+    P, X, f = O.initial_state(prob, prob.cams0)
+    ref = O.camera_step(P, O.linearize(P, X, prob), 1e-3, 10)
+    for prec, tol in (("fp64", 1e-9), ("fp32_bulk", 2e-3)):
+        gp = povar.Problem.from_synth(ctx, prob, precision=prec, eta=eta)
+        dp, _, _ = gp.debug_step(1e-3, 10)
+        gp.close()
+        assert rel(dp, ref) < tol
+
+
 def test_edge_cases(ctx):
     say("edge: eta 0 and 1, singular landmark, repeated observation")
     # eta = 1 drops the OSE rows, so nothing depends on the third camera row:

@@ -187,3 +187,33 @@ def test_first_stage_solution_hands_over_to_the_refinement():
     floor = synth.SIGMA ** 2 * 2 * prob.n_obs
     assert res.cost <= res.cost0
     assert res.cost < 3.0 * floor
+
+
+@pytest.mark.parametrize("lam", [1e-2, 1.0])
+def test_series_early_stop_against_dense_partial_sums(lam):
+    """The early stop of Sec. 5.2 (reading R6) on the second stage: the
+    stopping term is the first t >= 1 where the t-th Neumann term of the dense
+    joint system is at most rtol times the partial sum, and the update equals
+    that partial sum."""
+    prob = problem(n_cams=5, n_pts=40, seed=11)
+    P, Xh = random_state(prob, 12)
+    A, rhs, B = dense_tangent_system(prob, P, Xh, lam)
+    k = 11 * prob.n_cams
+    Ut, Wt, Vt = A[:k, :k], A[:k, k:], A[k:, k:]
+    M = np.linalg.solve(Ut, Wt @ np.linalg.solve(Vt, Wt.T))
+    g = -rhs[:k] - Wt @ np.linalg.solve(Vt, -rhs[k:])
+    x = -np.linalg.solve(Ut, g)
+    acc = x.copy()
+    rtol = 0.05
+    t_ref = 20
+    for t in range(1, 21):
+        x = M @ x
+        acc = acc + x
+        if np.linalg.norm(x) <= rtol * np.linalg.norm(acc):
+            t_ref = t
+            break
+    rs = R.riemannian_system(P, Xh, R.linearize(P, Xh, prob), lam)
+    info = {}
+    dxp, _ = R.series_solve(rs, 20, rtol, info)
+    assert info["terms"] == t_ref
+    np.testing.assert_allclose(dxp, acc, rtol=1e-8, atol=1e-10 * np.abs(acc).max())
