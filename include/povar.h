@@ -224,8 +224,10 @@ povar_status povar_debug_layout_check(int32_t n_cams, int32_t n_pts, int64_t n_o
    each ambient camera / landmark block, then projected.
    cams0: n_cams x 12 (row-major 3x4), pts0: n_pts x 4 homogeneous, both in
    the caller's order (each row is normalised; host memory).  opts: precision
-   POVAR_PREC_FP64, manifold POVAR_MANIFOLD_SPHERE, series_rtol 0; the other
-   fields as for povar_problem_create.  The handle works with povar_solve,
+   POVAR_PREC_FP64, manifold POVAR_MANIFOLD_SPHERE; series_rtol as for the
+   first stage (the early stop ends the camera series; the landmark update
+   follows from the terms taken); the other fields as for
+   povar_problem_create.  The handle works with povar_solve,
    povar_step, povar_enqueue, povar_get_report, povar_get_cameras,
    povar_get_trace, povar_get_state, povar_kernel_timing / _times,
    povar_problem_info / _layout and povar_problem_destroy; povar_get_points

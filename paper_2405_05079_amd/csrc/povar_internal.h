@@ -223,10 +223,10 @@ hipError_t launch_cost_groups(const Batch& b, int trial, hipStream_t s);
 hipError_t launch_series_check(const Batch& b, bool fp32, int t, hipStream_t s);
 // second stage (RiPoBA): one LM iteration, and the landmark linearisation with
 // the cost at the current point (initial state)
-hipError_t launch_refine_iteration(const Batch& b, int order, hipStream_t s);
+hipError_t launch_refine_iteration(const Batch& b, int order, bool check, hipStream_t s);
 hipError_t launch_refine_landmarks(const Batch& b, hipStream_t s);
 hipError_t launch_refine_cameras(const Batch& b, hipStream_t s);
-hipError_t launch_refine_step(const Batch& b, int order, hipStream_t s);
+hipError_t launch_refine_step(const Batch& b, int order, bool check, hipStream_t s);
 hipError_t launch_retract(const Batch& b, bool fp32, hipStream_t s);
 hipError_t launch_decide(const Batch& b, hipStream_t s);
 

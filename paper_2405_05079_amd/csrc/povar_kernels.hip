@@ -1392,20 +1392,18 @@ __global__ void __launch_bounds__(kBlock) k_series_camera_slots(Batch B, int t) 
 // acc = x_0 + ... + x_t, summed in FP64 in a fixed order; if ||x_t|| <=
 // series_rtol ||acc||, the later terms are skipped and k_retract applies acc.
 // One workgroup per problem.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_series_check(Batch B, int t) {
-  int p, w;
-  if (!map_block(B, kUnitOne, p, w)) return;
-  DevProblem& D = B.probs[p];
-  if (D.ctl.done || !(D.series_rtol > 0.0) || t > D.ctl.stop_at || t >= D.ctl.order) return;
-  const T POVAR_GMEM* S = Prec<T>::S(D, D.ctl.pcur);
+// After term t: ||x_t|| and ||acc|| over all cameras (FP64 sums in a fixed
+// order, one workgroup); stop_at = t if ||x_t|| <= series_rtol ||acc||.
+// x(i, k) returns value k of camera i's term.
+template <typename X>
+__device__ __forceinline__ void series_check(DevProblem& D, int t, const X& x) {
   double sx = 0.0, sa = 0.0;
   for (int i = (int)threadIdx.x; i < D.n_p; i += kBlock) {
 #pragma unroll
     for (int k = 0; k < kCam; ++k) {
-      const double x = (double)S[(size_t)i * D.s_stride + kSerX + k];
+      const double v = x(i, k);
       const double a = D.acc[(size_t)i * kCam + k];
-      sx += x * x;
+      sx += v * v;
       sa += a * a;
     }
   }
@@ -1425,6 +1423,17 @@ __global__ void __launch_bounds__(kBlock) k_series_check(Batch B, int t) {
     D.ctl.stop_at = t;
     D.ctl.stopped = 1;
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_series_check(Batch B, int t) {
+  int p, w;
+  if (!map_block(B, kUnitOne, p, w)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done || !(D.series_rtol > 0.0) || t > D.ctl.stop_at || t >= D.ctl.order) return;
+  const T POVAR_GMEM* S = Prec<T>::S(D, D.ctl.pcur);
+  const int ss = D.s_stride;
+  series_check(D, t, [&](int i, int k) { return (double)S[(size_t)i * ss + kSerX + k]; });
 }
 
 // --------------------------------------------------------------- k_retract
@@ -1790,6 +1799,11 @@ __global__ void __launch_bounds__(kWave) k_refine_prep(Batch B) {
   DevProblem& D = B.probs[p];
   if (D.ctl.done) return;
   const int i = w * kWave + lane_id();
+  // a new step: all series terms until an early stop says otherwise
+  if (i == 0) {
+    D.ctl.stop_at = D.ctl.order;
+    D.ctl.stopped = 0;
+  }
   if (i >= D.n_p) return;
   const double lam = D.ctl.lambda;
   double s[kLin2];
@@ -1999,7 +2013,7 @@ __global__ void __launch_bounds__(kBlock) k_refine_series_landmark(Batch B, int 
   int p, q;
   if (!map_wave(B, kUnitPacket, p, q)) return;
   DevProblem& D = B.probs[p];
-  if (D.ctl.done || t > D.ctl.order) return;
+  if (D.ctl.done || t > D.ctl.stop_at) return;
   __shared__ f4v cbuf[kWavesPerBlock][6 * kWave];
   refine_landmark_slot<false>(D, q, (f4v POVAR_LDS*)cbuf[threadIdx.x >> 6]);
 }
@@ -2047,7 +2061,7 @@ __global__ void __launch_bounds__(kBlock) k_refine_series_camera(Batch B, int t)
   int p, ch;
   if (!map_block(B, kUnitSerChunk, p, ch)) return;
   DevProblem& D = B.probs[p];
-  if (D.ctl.done || t > D.ctl.order) return;
+  if (D.ctl.done || t > D.ctl.stop_at) return;
   const int4 meta = D.ch_meta[ch];
   const int cam = meta.x, beg = meta.y, end = meta.z, nch = meta.w;
   double Pc[12];
@@ -2104,7 +2118,7 @@ __global__ void __launch_bounds__(kBlock) k_refine_series_camera_slots(Batch B, 
   int p, q;
   if (!map_wave(B, kUnitCSlot, p, q)) return;
   DevProblem& D = B.probs[p];
-  if (D.ctl.done || t > D.ctl.order) return;
+  if (D.ctl.done || t > D.ctl.stop_at) return;
   const int lane = lane_id();
   const int2 li = D.cs_lane[(size_t)q * kWave + lane];
   int jr[kCsPerLane];
@@ -2156,7 +2170,7 @@ __global__ void __launch_bounds__(kWave) k_refine_series_combine(Batch B, int t)
   int p, u;
   if (!map_wave<kWave>(B, kUnitMultiCam, p, u)) return;
   DevProblem& D = B.probs[p];
-  if (D.ctl.done || t > D.ctl.order) return;
+  if (D.ctl.done || t > D.ctl.stop_at) return;
   const int cam = D.ser_mc[u];
   const int c0 = D.ser_off[cam], np = D.ser_off[cam + 1] - c0;
   double kr[12];
@@ -2179,6 +2193,17 @@ __global__ void __launch_bounds__(kWave) k_refine_series_combine(Batch B, int t)
   }
   __syncthreads();
   refine_camera_solve(D, cam, tv, kr);
+}
+
+// Optional early stop of the second stage's series (series_rtol > 0), on
+// the ambient terms x_t (whose norms equal the tangent ones).
+__global__ void __launch_bounds__(kBlock) k_refine_series_check(Batch B, int t) {
+  int p, w;
+  if (!map_block(B, kUnitOne, p, w)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done || !(D.series_rtol > 0.0) || t > D.ctl.stop_at || t >= D.ctl.order) return;
+  const double* __restrict__ x2 = D.x2;
+  series_check(D, t, [&](int i, int k) { return x2[(size_t)i * kCam + k]; });
 }
 
 // Camera retraction of the second stage: p <- (p + acc) / |p + acc|.
@@ -2342,7 +2367,7 @@ hipError_t launch_refine_cameras(const Batch& b, hipStream_t s) {
 
 // camera blocks through the trial cost (the landmark blocks and the camera
 // chunk sums of the current point must be in place)
-hipError_t launch_refine_step(const Batch& b, int order, hipStream_t s) {
+hipError_t launch_refine_step(const Batch& b, int order, bool check, hipStream_t s) {
   const dim3 gp = blocks_for(b.total[kUnitPacket], kWavesPerBlock);
   const dim3 gw = blocks_for(b.total[kUnitCamWave], 1);
   hipLaunchKernelGGL(k_refine_prep, gw, dim3(kWave), 0, s, b);
@@ -2355,6 +2380,8 @@ hipError_t launch_refine_step(const Batch& b, int order, hipStream_t s) {
                          0, s, b, t);
     if (b.total[kUnitMultiCam] > 0)
       hipLaunchKernelGGL(k_refine_series_combine, blocks_for(b.total[kUnitMultiCam], 1), dim3(kWave), 0, s, b, t);
+    if (check && t < order)
+      hipLaunchKernelGGL(k_refine_series_check, blocks_for(b.total[kUnitOne], 1), dim3(kBlock), 0, s, b, t);
   }
   hipLaunchKernelGGL(k_refine_landmark_update, gp, dim3(kBlock), 0, s, b);
   hipLaunchKernelGGL(k_refine_retract, gw, dim3(kWave), 0, s, b);
@@ -2362,11 +2389,11 @@ hipError_t launch_refine_step(const Batch& b, int order, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_refine_iteration(const Batch& b, int order, hipStream_t s) {
+hipError_t launch_refine_iteration(const Batch& b, int order, bool check, hipStream_t s) {
   hipError_t e;
   if ((e = launch_refine_landmarks(b, s)) != hipSuccess) return e;
   if ((e = launch_refine_cameras(b, s)) != hipSuccess) return e;
-  if ((e = launch_refine_step(b, order, s)) != hipSuccess) return e;
+  if ((e = launch_refine_step(b, order, check, s)) != hipSuccess) return e;
   if ((e = launch_cost_groups(b, 1, s)) != hipSuccess) return e;
   return launch_decide(b, s);
 }

@@ -1008,7 +1008,8 @@ static hipError_t enqueue_series(povar_problem_s* pb, int order, bool timed) {
 hipError_t enqueue_iteration(povar_problem_s* pb, bool timed) {
   hipError_t e;
   const Batch& B = pb->batch;
-  if (pb->rec.stage == 2) return launch_refine_iteration(B, pb->opt.series_order, pb->stream);
+  if (pb->rec.stage == 2)
+    return launch_refine_iteration(B, pb->opt.series_order, pb->opt.series_rtol > 0.0, pb->stream);
   if ((e = launch_linearize(B, pb->fp32, 0, pb->stream)) != hipSuccess) return e;
   if ((e = launch_camera_prep(B, pb->fp32, pb->stream)) != hipSuccess) return e;
   if ((e = enqueue_series(pb, pb->opt.series_order, timed)) != hipSuccess) return e;
@@ -1388,8 +1389,8 @@ povar_status povar_refine_create(povar_ctx ctx, int32_t n_cams, int32_t n_pts, i
     set_error(ctx, "cams0 and pts0 must not be NULL");
     return POVAR_EINVAL;
   }
-  if (opts->precision != POVAR_PREC_FP64 || opts->manifold != POVAR_MANIFOLD_SPHERE || opts->series_rtol != 0.0) {
-    set_error(ctx, "the second stage runs in FP64 on the spheres with a fixed series order");
+  if (opts->precision != POVAR_PREC_FP64 || opts->manifold != POVAR_MANIFOLD_SPHERE) {
+    set_error(ctx, "the second stage runs in FP64 on the spheres");
     return POVAR_EINVAL;
   }
   (void)hipSetDevice(ctx->device);
@@ -1716,7 +1717,7 @@ povar_status povar_refine_debug_step(povar_problem pb, double lambda, int32_t or
   const Batch& B = pb->batch;
   HIP_TRY(ctx, launch_refine_landmarks(B, pb->stream));
   HIP_TRY(ctx, launch_refine_cameras(B, pb->stream));
-  HIP_TRY(ctx, launch_refine_step(B, order, pb->stream));
+  HIP_TRY(ctx, launch_refine_step(B, order, pb->opt.series_rtol > 0.0, pb->stream));
   HIP_TRY(ctx, launch_cost_groups(B, 1, pb->stream));
   HIP_TRY(ctx, launch_cost_finalize(B, 1, pb->stream));
   Ctl after;

@@ -100,6 +100,28 @@ def test_refine_step(ctx, kw, lam, order):
         gp.close()
 
 
+@pytest.mark.parametrize("lam", [10.0, 1.0, 1e-2])
+def test_refine_series_early_stop(ctx, lam):
+    """series_rtol = 0.01 on the second stage: the oracle stops after 2, 4 and
+    all 20 terms at these dampings, each decision at least 30% away from the
+    threshold (ratios 0.0149 -> 0.0005, 0.0151 -> 0.0067, >= 0.0134 to the
+    end), so rounding cannot flip one; the step taken must be the same."""
+    prob = synth.make_problem(**CASES[4])
+    P, X = start(prob, 8)
+    say("refine early stop", lam)
+    gp = refine(ctx, prob, P, X, series_rtol=0.01)
+    try:
+        dp, pt, xt, ct = gp.refine_step(lam, 20)
+        lin = R.linearize(P, X, prob)
+        info = {}
+        dP, dX = R.step(P, X, lin, lam, 20, 0.01, info)
+        assert info["terms"] == {10.0: 2, 1.0: 4, 1e-2: 20}[lam]
+        assert rel(dp, dP) < 1e-8
+        assert rel(xt, R.retract(X, dX)) < 1e-9
+    finally:
+        gp.close()
+
+
 def test_refine_trajectory_matches_oracle(ctx):
     prob = synth.make_problem(**CASES[2])
     P, X = start(prob, 9)
@@ -159,7 +181,7 @@ def test_refine_rejects_invalid_use(ctx):
     prob = synth.make_problem(**CASES[0])
     P, X = start(prob, 10)
     say("refine invalid")
-    for opts in (dict(precision="fp32_bulk"), dict(manifold="euclidean"), dict(series_rtol=0.01)):
+    for opts in (dict(precision="fp32_bulk"), dict(manifold="euclidean"), dict(series_rtol=1.5)):
         with pytest.raises(povar.PovarError) as e:
             refine(ctx, prob, P, X, **opts)
         assert e.value.status == povar.EINVAL
