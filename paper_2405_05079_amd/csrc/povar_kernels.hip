@@ -1172,8 +1172,28 @@ __device__ __forceinline__ void camera_solve(DevProblem& D, int cam, const T* tv
   if (last) retract_value<T>(D, cam, k, (pc ? D.P64[1] : D.P64[0])[(size_t)cam * kCam + k] + a, qs);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
+constexpr int kCamWG = 1024;   // threads of a camera-chunk workgroup
+
+// Sum of the per-wave partials of value k, in a fixed pairwise order.
+template <typename T, int NW>
+__device__ __forceinline__ T wg_sum(const T (&red)[NW][12], int k) {
+  if constexpr (NW == 4) {
+    return ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  } else {
+    T v[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) v[w] = red[w][k];
+#pragma unroll
+    for (int h = NW / 2; h > 0; h >>= 1)
+#pragma unroll
+      for (int w = 0; w < h; ++w) v[w] = v[w] + v[w + h];
+    return v[0];
+  }
+}
+
+template <typename T, int WG>
+__global__ void __launch_bounds__(WG) k_series_camera(Batch B, int t) {
+  constexpr int kPL = kChunk / WG;   // observations per lane
   int p, ch;
   if (!map_block(B, kUnitSerChunk, p, ch)) return;
   DevProblem& D = B.probs[p];
@@ -1193,21 +1213,21 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
   // all index and measurement loads, then all record gathers, then the
   // arithmetic: two memory round trips per lane instead of two per
   // observation.  The trip count is uniform over the workgroup.
-  const int nr = (end - beg + kBlock - 1) / kBlock;
+  const int nr = (end - beg + WG - 1) / WG;
   const int tid = (int)threadIdx.x;
-  int jr[kPerLane];
-  typename Prec<T>::T2 mr[kPerLane];
+  int jr[kPL];
+  typename Prec<T>::T2 mr[kPL];
 #pragma unroll
-  for (int r = 0; r < kPerLane; ++r) {
+  for (int r = 0; r < kPL; ++r) {
     if (r < nr) {
-      const int e = min(beg + r * kBlock + tid, end - 1);
+      const int e = min(beg + r * WG + tid, end - 1);
       jr[r] = lm[e];
       mr[r] = M[e];
     }
   }
-  T z[kPerLane][4], x[kPerLane][4];
+  T z[kPL][4], x[kPL][4];
 #pragma unroll
-  for (int r = 0; r < kPerLane; ++r) {
+  for (int r = 0; r < kPL; ++r) {
     if (r < nr) {
       load4(zx + (size_t)jr[r] * kRec, z[r][0], z[r][1], z[r][2], z[r][3]);
       load4(zx + (size_t)jr[r] * kRec + 4, x[r][0], x[r][1], x[r][2], x[r][3]);
@@ -1217,8 +1237,8 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = 0;
 #pragma unroll
-  for (int r = 0; r < kPerLane; ++r) {
-    if (r < nr && beg + r * kBlock + tid < end) {
+  for (int r = 0; r < kPL; ++r) {
+    if (r < nr && beg + r * WG + tid < end) {
       const auto m = mr[r];
       const T q0 = Pc[0] * z[r][0] + Pc[1] * z[r][1] + Pc[2] * z[r][2];
       const T q1 = Pc[4] * z[r][0] + Pc[5] * z[r][1] + Pc[6] * z[r][2];
@@ -1234,7 +1254,7 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
       }
     }
   }
-  __shared__ T red[kWavesPerBlock][12];
+  __shared__ T red[WG / kWave][12];
   __shared__ T tv[12];
   const int wv = threadIdx.x >> 6;
   {
@@ -1249,10 +1269,10 @@ __global__ void __launch_bounds__(kBlock) k_series_camera(Batch B, int t) {
   const int k = threadIdx.x;
   if (nch > 1) {
     // finished by k_series_camera_combine after all chunks are written
-    if (k < 12) static_cast<T*>(D.t_part)[(size_t)ch * kCam + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    if (k < 12) static_cast<T*>(D.t_part)[(size_t)ch * kCam + k] = wg_sum<T, WG / kWave>(red, k);
     return;
   }
-  if (k < 12) tv[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  if (k < 12) tv[k] = wg_sum<T, WG / kWave>(red, k);
   __syncthreads();
   camera_solve<T>(D, cam, tv, kr, t == D.ctl.order);
 }
@@ -2313,8 +2333,8 @@ hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s,
   const bool chunks = b.total[kUnitSerChunk] > 0;
   if (chunks) {
     const dim3 g = blocks_for(b.total[kUnitSerChunk], 1);
-    if (fp32) hipExtLaunchKernelGGL(k_series_camera<float>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
-    else hipExtLaunchKernelGGL(k_series_camera<double>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
+    if (fp32) hipExtLaunchKernelGGL((k_series_camera<float, kCamWG>), g, dim3(kCamWG), 0, s, ev0, ev1, 0, b, t);
+    else hipExtLaunchKernelGGL((k_series_camera<double, kCamWG>), g, dim3(kCamWG), 0, s, ev0, ev1, 0, b, t);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (b.total[kUnitCSlot] > 0) {
