@@ -2077,7 +2077,8 @@ __device__ __forceinline__ void refine_camera_solve(DevProblem& D, int cam, cons
 // x_i = K_i t_i, acc_i += x_i.  Index loads, then the (z, X) record gathers,
 // then the arithmetic; a camera spanning several chunks leaves one partial
 // per chunk for k_refine_series_combine.
-__global__ void __launch_bounds__(kBlock) k_refine_series_camera(Batch B, int t) {
+__global__ void __launch_bounds__(kCamWG) k_refine_series_camera(Batch B, int t) {
+  constexpr int kPL = kChunk / kCamWG;   // observations per lane
   int p, ch;
   if (!map_block(B, kUnitSerChunk, p, ch)) return;
   DevProblem& D = B.probs[p];
@@ -2089,15 +2090,15 @@ __global__ void __launch_bounds__(kBlock) k_refine_series_camera(Batch B, int t)
   double kr[12];
   if (nch == 1 && threadIdx.x < 12) load12(D.K64 + (size_t)cam * kCamMat + threadIdx.x * 12, kr);
   const double* __restrict__ zx = static_cast<const double*>(D.zx);
-  const int nr = (end - beg + kBlock - 1) / kBlock;
+  const int nr = (end - beg + kCamWG - 1) / kCamWG;
   const int tid = (int)threadIdx.x;
-  int jr[kPerLane];
+  int jr[kPL];
 #pragma unroll
-  for (int r = 0; r < kPerLane; ++r)
-    if (r < nr) jr[r] = D.cm_lm[min(beg + r * kBlock + tid, end - 1)];
-  double z[kPerLane][4], X[kPerLane][4];
+  for (int r = 0; r < kPL; ++r)
+    if (r < nr) jr[r] = D.cm_lm[min(beg + r * kCamWG + tid, end - 1)];
+  double z[kPL][4], X[kPL][4];
 #pragma unroll
-  for (int r = 0; r < kPerLane; ++r) {
+  for (int r = 0; r < kPL; ++r) {
     if (r < nr) {
       load4(zx + (size_t)jr[r] * kRec, z[r][0], z[r][1], z[r][2], z[r][3]);
       load4(zx + (size_t)jr[r] * kRec + 4, X[r][0], X[r][1], X[r][2], X[r][3]);
@@ -2107,9 +2108,9 @@ __global__ void __launch_bounds__(kBlock) k_refine_series_camera(Batch B, int t)
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = 0.0;
 #pragma unroll
-  for (int r = 0; r < kPerLane; ++r)
-    if (r < nr && beg + r * kBlock + tid < end) refine_w_add(Pc, z[r], X[r], acc);
-  __shared__ double red[kWavesPerBlock][12];
+  for (int r = 0; r < kPL; ++r)
+    if (r < nr && beg + r * kCamWG + tid < end) refine_w_add(Pc, z[r], X[r], acc);
+  __shared__ double red[kCamWG / kWave][12];
   __shared__ double tv[12];
   const int wv = threadIdx.x >> 6;
   {
@@ -2123,10 +2124,10 @@ __global__ void __launch_bounds__(kBlock) k_refine_series_camera(Batch B, int t)
   __syncthreads();
   const int k = threadIdx.x;
   if (nch > 1) {
-    if (k < 12) static_cast<double*>(D.t_part)[(size_t)ch * kCam + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    if (k < 12) static_cast<double*>(D.t_part)[(size_t)ch * kCam + k] = wg_sum<double, kCamWG / kWave>(red, k);
     return;
   }
-  if (k < 12) tv[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  if (k < 12) tv[k] = wg_sum<double, kCamWG / kWave>(red, k);
   __syncthreads();
   refine_camera_solve(D, cam, tv, kr);
 }
@@ -2394,7 +2395,7 @@ hipError_t launch_refine_step(const Batch& b, int order, bool check, hipStream_t
   for (int t = 1; t <= order; ++t) {
     hipLaunchKernelGGL(k_refine_series_landmark, gp, dim3(kBlock), 0, s, b, t);
     if (b.total[kUnitSerChunk] > 0)
-      hipLaunchKernelGGL(k_refine_series_camera, blocks_for(b.total[kUnitSerChunk], 1), dim3(kBlock), 0, s, b, t);
+      hipLaunchKernelGGL(k_refine_series_camera, blocks_for(b.total[kUnitSerChunk], 1), dim3(kCamWG), 0, s, b, t);
     if (b.total[kUnitCSlot] > 0)
       hipLaunchKernelGGL(k_refine_series_camera_slots, blocks_for(b.total[kUnitCSlot], kWavesPerBlock), dim3(kBlock),
                          0, s, b, t);
