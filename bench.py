@@ -448,7 +448,7 @@ def main():
     elif fp32["layout"]["blocked"]:
         name, ms, byt = "k_series_camera_slots<float>", ms_c, bc
     else:
-        name, ms, byt = "k_series_camera<float>", ms_c, bc
+        name, ms, byt = "k_series_camera<float, 1024>", ms_c, bc
     achieved = byt / (ms * 1e-3) / 1e9
     traffic = traffic_from_profiles(name, f"workload{args.workload}", kernel_source_hash())
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
