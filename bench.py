@@ -373,7 +373,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-matched", action="store_true")
-    ap.add_argument("--matched-seeds", type=int, default=9,
+    ap.add_argument("--matched-seeds", type=int, default=15,
                     help="seeds of the workload for the matched-final-cost comparison")
     ap.add_argument("--workload", type=int, default=WORKLOAD,
                     help="2: 250 cameras (default); 3: 1,800 cameras / 5M obs; 5: 13,700 cameras / 29M obs")
