@@ -28,6 +28,14 @@
 //   k_retract              p_i <- (p_i + acc_i) / |p_i + acc_i|             (Sec. 4.3)
 //                          (series order 0 only; otherwise in the last camera pass)
 //   k_decide               LM accept / reject and damping update            (Sec. 5.2)
+// Second stage, objective (7) with both blocks on their spheres (Sec. 4.3):
+//   k_refine_landmarks     V_j, b_l, G_j (projected damped inverse), z0, cost
+//   k_refine_cameras       U_i, b_p, sum W z0 per camera chunk
+//   k_refine_prep          damping, Cholesky, K_i (KKT form), x_0
+//   k_refine_series_landmark / _camera / _camera_slots / _combine / _check
+//                          the series (29) and its optional early stop
+//   k_refine_landmark_update  back-substitution and landmark retraction
+//   k_refine_retract, k_refine_cost  camera retraction, trial cost
 // Landmark-major passes run one lane per observation over 64-entry packet
 // slots of whole landmarks and sum each landmark's lanes with a segmented
 // scan of DPP lane moves.  The camera-major pass runs one workgroup per chunk
