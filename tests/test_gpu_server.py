@@ -143,3 +143,27 @@ def test_blocked_problems_in_a_mix_equal_single_solves(ctx, prec):
         np.testing.assert_array_equal(cams, cams_a)
         np.testing.assert_array_equal(pts, pts_a)
         assert rep["cost_final"] == rep_a["cost_final"]
+
+
+def test_mixed_precisions_in_one_server(ctx):
+    """FP32-bulk and FP64 requests interleaved on one server (one batch per
+    precision, both advanced every round): each result equals the same
+    request solved alone in its precision, bitwise."""
+    probs = requests()[:6]
+    precs = ["fp32_bulk", "fp64"] * 3
+    print("[case] server mixed precisions", flush=True)
+    alone = []
+    for p, prec in zip(probs, precs):
+        gp = povar.Problem.from_synth(ctx, p, **dict(OPTS, precision=prec))
+        rep = gp.solve()
+        alone.append((rep, gp.cameras(), gp.points()))
+        gp.close()
+    sv = povar.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=4)
+    tickets = [sv.submit(p, **dict(OPTS, precision=prec)) for p, prec in zip(probs, precs)]
+    res, _ = drain(sv, tickets)
+    for t, (rep_a, cams_a, pts_a) in zip(tickets, alone):
+        rep, cams, pts, _ = res[t]
+        np.testing.assert_array_equal(cams, cams_a)
+        np.testing.assert_array_equal(pts, pts_a)
+        assert rep["cost_final"] == rep_a["cost_final"]
+    sv.close()
