@@ -53,8 +53,10 @@ CASES = [
     # 70,000 landmarks: 64-byte (z, X) records above 4 MB, so the camera pass
     # runs over landmark-blocked camera slots and adds each camera's runs
     dict(n_cams=40, n_pts=70000, seed=23, track=("uniform", 2, 3)),
+    # blocked, with heavy-tailed views per camera (Zipf): cameras with many runs
+    dict(n_cams=300, n_pts=70000, seed=24, track=("uniform", 2, 3), cam_choice="zipf"),
 ]
-IDS = ["small", "7-cameras", "ragged", "long-tracks", "3-chunk-cameras", "blocked"]
+IDS = ["small", "7-cameras", "ragged", "long-tracks", "3-chunk-cameras", "blocked", "blocked-zipf"]
 
 
 @pytest.mark.parametrize("lam", [1e-3, 1.0])
