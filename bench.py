@@ -400,7 +400,7 @@ def main():
                            os.path.join(ROOT, "profiles", "hbm_traffic.json"))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the library runs on one GPU here; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
