@@ -124,6 +124,34 @@ def test_refine_series_early_stop(ctx, lam):
         gp.close()
 
 
+def test_refine_landmarks_at_infinity(ctx):
+    """Homogeneous landmarks with w = 0 (points at infinity, which the unit
+    sphere of R^4 represents like any other point): blocks and a step as the
+    oracle computes them; nothing on the path divides by w."""
+    prob = synth.make_problem(**CASES[2])
+    P, X = start(prob, 11)
+    X = X.copy()
+    X[:10, 3] = 0.0
+    X[:10] /= np.linalg.norm(X[:10], axis=1, keepdims=True)
+    say("refine landmarks at infinity")
+    gp = refine(ctx, prob, P, X)
+    try:
+        d = gp.refine_blocks(1e-2)
+        lin = R.linearize(P, X, prob)
+        assert rel(d["U"], lin.U) < 1e-10
+        assert rel(d["bl"], lin.bl) < 1e-10
+        dp, pt, xt, ct = gp.refine_step(1e-2, 10)
+        dP, dX = R.step(P, X, lin, 1e-2, 10)
+        assert rel(dp, dP) < 1e-8
+        # the landmark update is -G_j (b_l + sum W^T dp): the camera step's
+        # rounding (<= 1e-8) comes through G_j, which is badly conditioned for
+        # these landmarks (measured 1.0e-8)
+        assert rel(xt, R.retract(X, dX)) < 1e-7
+        np.testing.assert_allclose(gp.points_h()[:10, 3], 0.0, atol=0)
+    finally:
+        gp.close()
+
+
 def test_refine_trajectory_matches_oracle(ctx):
     prob = synth.make_problem(**CASES[2])
     P, X = start(prob, 9)
