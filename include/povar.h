@@ -229,8 +229,9 @@ povar_status povar_debug_layout_check(int32_t n_cams, int32_t n_pts, int64_t n_o
    follows from the terms taken); the other fields as for
    povar_problem_create.  The handle works with povar_solve,
    povar_step, povar_enqueue, povar_get_report, povar_get_cameras,
-   povar_get_trace, povar_get_state, povar_kernel_timing / _times,
-   povar_problem_info / _layout and povar_problem_destroy; povar_get_points
+   povar_get_trace, povar_get_state, povar_problem_info / _layout and
+   povar_problem_destroy (povar_kernel_times counts no launches for it: the
+   timing hooks bracket the first stage's series kernels); povar_get_points
    returns X / w per landmark, povar_get_points_h the unit 4-vectors.  The
    server does not take second-stage problems.  Errors: POVAR_EINVAL for
    invalid sizes, indices, options or non-finite / zero inputs, POVAR_ENOMEM,
