@@ -27,8 +27,9 @@ Everything here is FP64, written for a reader checking it against the paper:
 
 parity pinned: see tests/test_ripoba_pins.py (worked example of (7), central
 finite differences, degree-0 homogeneity of the residual, the dense joint
-Riemannian system, Lemma 2's spectrum, the zero minimum of noise-free data,
-projective gauge invariance).
+Riemannian system and its Neumann partial sums with and without the early
+stop, Lemma 2's spectrum, the zero minimum of noise-free data, projective
+gauge invariance, the hand-over from the first stage).
 """
 from __future__ import annotations
 
