@@ -117,14 +117,15 @@ def run_stream(ctx, probs, arrivals, budget, slots, opts):
     return [lat[i] for i in range(len(probs))], wall, max_res
 
 
-def refine_leg(ctx, prob, P1, X1, steps: int):
+def refine_leg(ctx, prob, P1, X1, steps: int, eta_handover: bool = True):
     """The second stage (projective refinement, RiPoBA, FP64) on the same
     problem.  The rate: `steps` graph-replayed LM iterations from the first
     stage's FP64 solution (the stratified pipeline).  The costs: before and
     after, against the noise floor of the measurements, from that solution and
     from the ground truth perturbed by N(0, 0.02^2) per coordinate (cameras
-    and homogeneous landmarks, each then put back on its sphere), and from a
-    first stage run at eta = 0.3.  From random cameras the first stage at the
+    and homogeneous landmarks, each then put back on its sphere), and (with
+    eta_handover) from a first stage run at eta = 0.3.  From random cameras
+    the first stage at the
     workload's eta = 0.01 can stop in a poor basin of its own objective, and
     the refinement then only improves the start it was given."""
     def unit(a):
@@ -148,6 +149,16 @@ def refine_leg(ctx, prob, P1, X1, steps: int):
     gp.step(steps)
     grep_ = gp.report()
     gp.close()
+    out = {"iters_per_s": round(steps / secs, 2), "steps": steps, "precision": "fp64", "order": prob.order,
+           # sigma^2 per coordinate of every observation: reachable only
+           # without outliers (the 1,800-camera workload holds 1%)
+           "noise_floor": synth.SIGMA ** 2 * 2 * prob.n_obs,
+           "outlier_frac": next(w["outlier_frac"] for w in synth.WORKLOADS.values() if w["name"] == prob.name),
+           "from_first_stage": {"cost_initial": c0, "cost_after": rep["cost_final"], "iters": rep["iters"]},
+           "from_perturbed_truth": {"sigma": 0.02, "cost_initial": g0, "cost_after": grep_["cost_final"],
+                                    "iters": grep_["iters"]}}
+    if not eta_handover:
+        return out
     # the stratified pipeline with the first stage at eta = 0.3 (one of the
     # paper's ablation values): FP32-bulk, the workload's iteration count
     s1 = povar.Problem.from_synth(ctx, prob, precision="fp32_bulk", eta=0.3, ftol=0.0, max_iters=prob.iters)
@@ -159,17 +170,9 @@ def refine_leg(ctx, prob, P1, X1, steps: int):
     gp.step(steps)
     erep = gp.report()
     gp.close()
-    return {"iters_per_s": round(steps / secs, 2), "steps": steps, "precision": "fp64", "order": prob.order,
-            # sigma^2 per coordinate of every observation: reachable only
-            # without outliers (the 1,800-camera workload holds 1%)
-            "noise_floor": synth.SIGMA ** 2 * 2 * prob.n_obs,
-            "outlier_frac": next(w["outlier_frac"] for w in synth.WORKLOADS.values() if w["name"] == prob.name),
-            "from_first_stage": {"cost_initial": c0, "cost_after": rep["cost_final"], "iters": rep["iters"]},
-            "from_perturbed_truth": {"sigma": 0.02, "cost_initial": g0, "cost_after": grep_["cost_final"],
-                                     "iters": grep_["iters"]},
-            "from_first_stage_eta_0.3": {"first_stage_iters": r1["iters"], "first_stage_cost": r1["cost_final"],
-                                         "cost_initial": e0, "cost_after": erep["cost_final"],
-                                         "iters": erep["iters"]}}
+    out["from_first_stage_eta_0.3"] = {"first_stage_iters": r1["iters"], "first_stage_cost": r1["cost_final"],
+                                       "cost_initial": e0, "cost_after": erep["cost_final"], "iters": erep["iters"]}
+    return out
 
 
 def eta_sweep(ctx, prob, iters: int):
@@ -525,7 +528,7 @@ def main():
             "fp32_seconds_to_match_median": (med / r32) if med else None,
             "speedup_at_matched_cost": (prob.iters / r64) / (med / r32) if med else None}
     if not args.no_refine:
-        out["refine"] = refine_leg(ctx, prob, *stage1, min(args.steps, 50))
+        out["refine"] = refine_leg(ctx, prob, *stage1, min(args.steps, 50), eta_handover=args.workload == WORKLOAD)
         print(f"[bench] refinement: {out['refine']['iters_per_s']} iters/s", file=sys.stderr, flush=True)
     if not args.no_eta_sweep:
         out["eta_sweep"] = eta_sweep(ctx, prob, min(args.steps, prob.iters))
