@@ -103,13 +103,40 @@ typedef struct {
                             ||x_0 + ... + x_t|| (2-norms over all cameras,
                             FP64 sums of the stored terms).  0 (default) runs
                             all series_order terms. */
+  uint64_t init_seed;    /* seed of the initial cameras when cams0 is NULL
+                            (Sec. 5.2 "Dataset": cameras drawn from an
+                            isotropic Gaussian).  Camera c (caller's index)
+                            takes 12 standard normals from three blocks of the
+                            counter-based generator Philox4x64-10 (Salmon et
+                            al., SC 2011) with key (init_seed, 0) and counters
+                            (c, b, 0, 0), b = 0, 1, 2; each 64-bit output w
+                            gives u = ((w >> 11) + 0.5) 2^-53 in (0, 1), and
+                            the outputs (w0, w1), (w2, w3) of a block give two
+                            normals each by the Box-Muller transform
+                            (sqrt(-2 ln u0) cos(2 pi u1), then sin), in that
+                            order; the 12-vector is then scaled to unit norm.
+                            Default 0. */
 } povar_options;
 
 typedef struct {
   double cost_initial;   /* f* at the initial cameras */
   double cost_final;     /* f* at the current cameras */
-  double lambda_final;
-  double seconds;        /* wall time of the call */
+  double lambda_final;   /* damping for the next step */
+  double grad_norm_final;/* 2-norm over all cameras of the Riemannian gradient
+                            of f* at the current cameras: 2 Pi_i b_p,i with
+                            b_p,i = sum_k J_p,k^T r_k at X*(P) (the gradient of
+                            the reduced cost (9) by the envelope theorem, Eq.
+                            (10)), Pi_i the tangent projector of the unit sphere
+                            at p_i (identity in Euclidean mode); computed by
+                            povar_solve, povar_step and povar_get_report (one
+                            linearisation pass when the current one is stale),
+                            NaN in server reports */
+  double seconds_total;  /* wall time of the call (0 for povar_get_report) */
+  double seconds_series; /* device time of the power series (Eq. (17)) summed
+                            over every iteration of the problem so far: from
+                            the start of the first series pass of a step to
+                            the start of the landmark re-solve, read from the
+                            GPU's constant-rate clock */
   int32_t iters;         /* LM iterations taken so far (rejected ones count) */
   int32_t accepted;      /* accepted iterations so far */
   int32_t stop_reason;   /* 0 running / max_iters, 1 ftol reached */
@@ -140,7 +167,8 @@ povar_status povar_problem_footprint(int32_t n_cams, int32_t n_pts, int64_t n_ob
 /* Create a problem from observations (Sec. 3.2): cam_idx[k] in [0,n_cams),
    pt_idx[k] in [0,n_pts), meas[2k..2k+1] finite.  Every camera and every
    point needs at least one observation.  cams0 (n_cams x 12, required) is the
-   initial camera set; on the sphere manifold each camera is normalised to
+   initial camera set, or NULL: cameras drawn from opts->init_seed as
+   described there; on the sphere manifold each camera is normalised to
    unit norm.  The landmarks are then solved in closed form (8) and the
    initial cost is evaluated (POVAR_ENUMERIC if it is not finite).
    Errors: POVAR_EINVAL for any violated precondition, POVAR_ENOMEM,
@@ -150,7 +178,7 @@ povar_status povar_problem_create(povar_ctx ctx, int32_t n_cams, int32_t n_pts, 
                                   const double* meas, const double* cams0,
                                   const povar_options* opts, povar_problem* out);
 /* Same, with cam_idx, pt_idx, meas and cams0 in device memory of ctx's
-   device (e.g. torch tensors). */
+   device (e.g. torch tensors); cams0 may be NULL as above. */
 povar_status povar_problem_create_device(povar_ctx ctx, int32_t n_cams, int32_t n_pts, int64_t n_obs,
                                          const int32_t* cam_idx, const int32_t* pt_idx,
                                          const double* meas, const double* cams0,
@@ -175,6 +203,14 @@ povar_status povar_get_points(povar_problem pb, double* pts_out);
    first min(n, iters) iterations.  Any output pointer may be NULL. */
 povar_status povar_get_trace(povar_problem pb, int32_t n, double* trial_cost,
                              double* lambda_used, int32_t* accepted);
+/* Per-iteration diagnostics of the first stage, for the first min(n, iters)
+   iterations (either pointer may be NULL): bl_norm, the 2-norm over all
+   landmarks of b_l = sum_k J_l,k^T r_k at the trial cameras and their
+   re-solved landmarks (zero up to rounding, since X* solves (8): the
+   eliminated landmarks have zero gradient); series_seconds, the device time
+   of that iteration's power series as in povar_report.seconds_series.
+   Second-stage problems: POVAR_ESTATE. */
+povar_status povar_get_trace_diag(povar_problem pb, int32_t n, double* bl_norm, double* series_seconds);
 
 /* Checkpoint / resume: the state is (cameras, lambda, iteration count); the
    landmarks follow from the cameras by (8).  set_state re-solves them,
@@ -199,6 +235,18 @@ povar_status povar_debug_linearize(povar_problem pb, double* U, double* bp, doub
    cameras, cost_trial the cost after re-solving the landmarks there. */
 povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, double* dp,
                               double* p_trial, double* cost_trial);
+/* The truncated power series of Eq. (17) from a caller-supplied start, at
+   the current linearisation and damping (the problem's lambda for its next
+   step): x_out = sum_{t=0..order} M^t x0 with M = K W V^+ W^T, K the damped
+   camera block inverse in the tangent space of each camera (Sec. 4.3; K =
+   U_lambda^-1 in Euclidean mode).  x0 and x_out: n_cams x 12 ambient camera
+   vectors (host, caller's order); x0 is used as given (the terms t >= 1 are
+   tangent on the sphere).  The series precision is the problem's (an
+   FP32-bulk problem rounds x0 to FP32 for its first term; x_out sums the
+   terms in FP64); no early stop.  The solver state is kept.  POVAR_ESTATE on
+   a finished or second-stage problem, POVAR_ENUMERIC if a damped camera
+   block could not be factored. */
+povar_status povar_debug_series(povar_problem pb, const double* x0, int32_t order, double* x_out);
 /* Host only, no device needed: builds the device layout of a problem (same
    arguments as povar_problem_create) and checks it — every observation in
    exactly one packet entry, one camera-major position and, when the camera
@@ -339,8 +387,10 @@ povar_status povar_problem_layout(povar_problem pb, int32_t* blocked, int32_t* l
    independent of which other problems shared the launches. */
 povar_status povar_server_create(povar_ctx ctx, uint64_t hbm_budget_bytes, int32_t max_slots,
                                  povar_server* out);
-/* Copies the request; *ticket identifies it.  POVAR_ENOMEM if the request
-   alone exceeds the budget; POVAR_EINVAL as for povar_problem_create. */
+/* Copies the request; *ticket identifies it.  cams0 may be NULL (seeded
+   cameras from opts->init_seed, as for povar_problem_create).  POVAR_ENOMEM
+   if the request alone exceeds the budget; POVAR_EINVAL as for
+   povar_problem_create. */
 povar_status povar_server_submit(povar_server sv, int32_t n_cams, int32_t n_pts, int64_t n_obs,
                                  const int32_t* cam_idx, const int32_t* pt_idx, const double* meas,
                                  const double* cams0, const povar_options* opts, uint64_t* ticket);

@@ -260,6 +260,35 @@ def power_series(rs: ReducedSystem, order: int, rtol: float = 0.0):
     return acc, used
 
 
+def series_from(P: np.ndarray, lin: Linearization, lam: float, x0: np.ndarray, order: int,
+                manifold: str = "sphere") -> np.ndarray:
+    """The truncated series of (17) started from a given ambient camera vector:
+    sum_{t=0..m} x_t with x_0 = x0 (n_cams, 12) as given and
+    x_t = B U~^-1 B^T W V^+ W^T x_{t-1}, i.e. the operator of Lemma 1 mapped
+    to ambient coordinates by each camera's tangent basis B (identity in
+    Euclidean mode).  For x0 = B x~ the partial sums are B times those of
+    (17) from x~."""
+    rs = reduced_system(P, lin, lam, manifold)
+    Bs = block_diag_sparse(rs.B)
+    x = np.asarray(x0, dtype=np.float64).reshape(-1).copy()
+    acc = x.copy()
+    for _ in range(order):
+        z = rs.Vp_blk @ (lin.W.T @ x)          # V^+ W^T x, per landmark
+        x = Bs @ rs.apply_Uinv(rs.Wt @ z)      # B U~^-1 B^T W z, per camera
+        acc = acc + x
+    return acc.reshape(P.shape[0], 12)
+
+
+def riemannian_gradient(P: np.ndarray, lin: Linearization, manifold: str = "sphere") -> np.ndarray:
+    """Gradient of the reduced cost f* (9) at P, projected onto each camera's
+    tangent space: by the envelope theorem the Euclidean gradient is
+    2 J_p^T r = 2 b_p when the landmarks are at X*(P)."""
+    g = 2.0 * lin.bp
+    if manifold == "sphere":
+        g = g - np.sum(g * P, axis=1, keepdims=True) * P
+    return g
+
+
 def back_project(rs: ReducedSystem, xt: np.ndarray) -> np.ndarray:
     """Ambient camera update dx~_p = x~_p^perp dx_p, (n_cams, 12)."""
     n, _, k = rs.B.shape

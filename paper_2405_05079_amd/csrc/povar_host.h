@@ -17,6 +17,7 @@ struct povar_ctx_s {
   std::mutex err_mu;
   std::string err, err_copy;
   int live_problems = 0;   // problems created on this context and not destroyed
+  double clock_hz = 0.0;   // rate of the device clock kernels read (wall_clock64)
 };
 
 namespace povar {
@@ -62,8 +63,8 @@ struct ArenaOffsets {
   size_t pk_hdr, pk_code, pk_m32, pk_m64, cm_lm, cm_m32, cm_m64, ch_meta, cam_ch, mc_cam;
   size_t cs_hdr, cs_lane, cs_lm, cs_m32, cs_m64, run_off, smc, t_run;
   size_t P64[2], S32[2], S64[2], rec64[2], rec32[2], xs64[2], xs32[2], Vp64[2];
-  size_t lin_part, K64, g64, U40, acc, zx, t_part, cost_part, cost_group;
-  size_t tr_cost, tr_lambda, tr_acc, rec, tables;
+  size_t lin_part, K64, g64, U40, acc, zx, t_part, cost_part, cost_group, bl_part, bl_group;
+  size_t tr_cost, tr_lambda, tr_acc, tr_bl, tr_series, rec, tables;
   size_t init_end;   // buffers with initial values lie below this offset
 };
 
@@ -123,5 +124,9 @@ hipError_t read_ctl(povar_problem_s* pb, Ctl* out);
 hipError_t write_ctl(povar_problem_s* pb, const Ctl* in);
 hipError_t enqueue_iteration(povar_problem_s* pb, bool timed);
 hipError_t enqueue_iterations(povar_problem_s* pb, int n);
-void fill_report(const povar_problem_s* pb, const Ctl& c, double seconds, povar_report* r);
+// grad_norm: the report's grad_norm_final (NaN when not computed)
+void fill_report(const povar_problem_s* pb, const Ctl& c, double seconds, double grad_norm, povar_report* r);
+// Seeded initial cameras (the init_seed field of povar_options): n x 12,
+// caller's order, unit norm.
+void seeded_cameras(uint64_t seed, int32_t n, double* out);
 }  // namespace povar

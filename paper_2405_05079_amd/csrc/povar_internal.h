@@ -69,6 +69,11 @@ struct Ctl {
   int32_t status;       // bit 0: a damped camera block of this step could not be factored
   int32_t stop_at;      // last series term of the current step (order, or earlier on an early stop)
   int32_t stopped;      // 1: the series of the current step stopped early (retraction still to do)
+  double grad_norm;     // |2 Pi b_p| at the current cameras (k_grad_norm; report only)
+  // device clock (wall_clock64 ticks) of the power series: start of the
+  // current step's first series pass (0: none yet), that step's duration, and
+  // the sum over all steps
+  uint64_t series_t0, series_last, series_ticks;
 };
 
 struct DevProblem {
@@ -149,9 +154,13 @@ struct DevProblem {
   void POVAR_GMEM* ser_part;           // 12 values per partial, series precision
   double POVAR_GMEM* cost_part;        // n_pk landmark-solve cost partials (one per packet)
   double POVAR_GMEM* cost_group;       // n_cg sums of kCostGroup consecutive packet partials
+  double POVAR_GMEM* bl_part;          // n_pk partials of |b_l|^2 (landmark solve), and
+  double POVAR_GMEM* bl_group;         // their n_cg group sums
   double POVAR_GMEM* tr_cost;          // trace_cap entries
   double POVAR_GMEM* tr_lambda;
   int32_t POVAR_GMEM* tr_acc;
+  double POVAR_GMEM* tr_bl;            // |b_l| at the trial point
+  double POVAR_GMEM* tr_series;        // series device clock ticks of the iteration
 
   // Second stage (projective refinement, Eq. (7), RiPoBA of Sec. 4.3), FP64:
   // landmarks are unit 4-vectors in rec64[b] (first 4 of each record).
@@ -229,5 +238,8 @@ hipError_t launch_refine_cameras(const Batch& b, hipStream_t s);
 hipError_t launch_refine_step(const Batch& b, int order, bool check, hipStream_t s);
 hipError_t launch_retract(const Batch& b, bool fp32, hipStream_t s);
 hipError_t launch_decide(const Batch& b, hipStream_t s);
+// |2 Pi_i b_p,i| over all cameras from the linearisation partials (which must
+// be those of the current cameras) into Ctl::grad_norm
+hipError_t launch_grad_norm(const Batch& b, hipStream_t s);
 
 }  // namespace povar

@@ -541,7 +541,7 @@ __global__ void __launch_bounds__(kBlock) k_landmark_solve(Batch B, int mode) {
   const double2 mraw = D.pk_m64[off + lane];
   const int2 hdr = D.pk_hdr[q];
   const int n = hdr.x, lm0 = hdr.y;
-  double ftot = 0.0;
+  double ftot = 0.0, bl2 = 0.0;   // cost and |b_l|^2 of the slot's landmarks
   if (n == 0) {
     // continuation slot of a landmark with more than 64 observations
   } else if (n <= kWave) {
@@ -589,6 +589,7 @@ __global__ void __launch_bounds__(kBlock) k_landmark_solve(Batch B, int mode) {
     }
     seg_sum(b, links);
     ftot = wave_sum(f);
+    bl2 = wave_sum(tail ? b[0] * b[0] + b[1] * b[1] + b[2] * b[2] : 0.0);
     if (tail) store_landmark(D, lc, lm0 + key, vp, X0, X1, X2, b);
   } else {
     // a single landmark with more than 64 observations: lanes stride over it
@@ -626,9 +627,15 @@ __global__ void __launch_bounds__(kBlock) k_landmark_solve(Batch B, int mode) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) b[k] = wave_sum(b[k]);
     ftot = wave_sum(f);
+    bl2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
     if (lane == 0) store_landmark(D, lc, lm0, vp, X0, X1, X2, b);
   }
-  if (lane == 0) D.cost_part[q] = ftot;
+  if (lane == 0) {
+    D.cost_part[q] = ftot;
+    D.bl_part[q] = bl2;
+    // the trial landmark solve starts when the step's power series has ended
+    if (trial && q == 0 && D.ctl.series_t0 != 0) D.ctl.series_last = wall_clock64() - D.ctl.series_t0;
+  }
 }
 
 // Cost reduction in two fixed-order levels: k_cost_groups adds kCostGroup
@@ -648,22 +655,31 @@ __global__ void __launch_bounds__(kBlock) k_cost_groups(Batch B, int trial) {
   DevProblem& D = B.probs[p];
   if (trial && D.ctl.done) return;
   const int q0 = g * kCostGroup, q1 = min(q0 + kCostGroup, D.n_pk);
-  double a = 0.0;
+  double a = 0.0, b = 0.0;
 #pragma unroll
   for (int r = 0; r < kCostGroup / kBlock; ++r) {
     const int q = q0 + r * kBlock + (int)threadIdx.x;
-    if (q < q1) a += D.cost_part[q];
+    if (q < q1) {
+      a += D.cost_part[q];
+      b += D.bl_part[q];
+    }
   }
   const double s = block_sum(a);
-  if (threadIdx.x == 0) D.cost_group[g] = s;
+  __syncthreads();   // block_sum's LDS is reused
+  const double sb = block_sum(b);
+  if (threadIdx.x == 0) {
+    D.cost_group[g] = s;
+    D.bl_group[g] = sb;
+  }
 }
 
 // Cost of all packets: from the group sums, or, for problems with few
 // packets (no groups), from the packet partials directly.
-__device__ __forceinline__ double packet_cost_sum(const DevProblem& D) {
+__device__ __forceinline__ double packet_sum(const DevProblem& D, const double POVAR_GMEM* part,
+                                             const double POVAR_GMEM* group) {
   double a = 0.0;
   if (D.n_cg > 0) {
-    for (int q = threadIdx.x; q < D.n_cg; q += kBlock) a += D.cost_group[q];
+    for (int q = threadIdx.x; q < D.n_cg; q += kBlock) a += group[q];
   } else {
     // eight independent loads per thread per round, added in a fixed order
     for (int q0 = 0; q0 < D.n_pk; q0 += kBlock * 8) {
@@ -671,13 +687,17 @@ __device__ __forceinline__ double packet_cost_sum(const DevProblem& D) {
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int q = q0 + r * kBlock + (int)threadIdx.x;
-        v[r] = q < D.n_pk ? D.cost_part[q] : 0.0;
+        v[r] = q < D.n_pk ? part[q] : 0.0;
       }
 #pragma unroll
       for (int r = 0; r < 8; ++r) a += v[r];
     }
   }
   return block_sum(a);
+}
+
+__device__ __forceinline__ double packet_cost_sum(const DevProblem& D) {
+  return packet_sum(D, D.cost_part, D.cost_group);
 }
 
 // cost of a landmark solve outside the LM loop, one workgroup per problem:
@@ -709,8 +729,10 @@ __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
   int p, ch;
   if (!map_block(B, kUnitChunk, p, ch)) return;
   DevProblem& D = B.probs[p];
-  if (D.ctl.done) return;
-  if (!force && !D.ctl.need_lin) return;
+  // force 0: a running problem after an accept; 1: any running problem;
+  // 2: after an accept, also once the problem has finished (report)
+  if (force != 2 && D.ctl.done) return;
+  if (force != 1 && !D.ctl.need_lin) return;
   const int lc = D.ctl.lcur, pc = D.ctl.pcur;
   const int4 meta = D.ch_meta[ch];
   const int cam = meta.x, beg = meta.y, end = meta.z;
@@ -804,6 +826,8 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
   if (i == 0) {
     D.ctl.stop_at = D.ctl.order;
     D.ctl.stopped = 0;
+    D.ctl.series_t0 = 0;
+    D.ctl.series_last = 0;
   }
   if (i >= D.n_p) return;
   const double lam = D.ctl.lambda;
@@ -960,6 +984,12 @@ __device__ __forceinline__ void store_z(const double (&v)[8], int j, T y0, T y1,
   store4(zx + (size_t)j * kRec + 4, X0, X1, X2, (T)1);
 }
 
+// The step's power series starts with the first wave of its first landmark
+// pass (device clock; k_landmark_solve of the trial point reads the end).
+__device__ __forceinline__ void series_clock_start(DevProblem& D, int t, int q) {
+  if (t == 1 && q == 0 && lane_id() == 0) D.ctl.series_t0 = wall_clock64();
+}
+
 // Camera series data of the landmark pass: x_i (12 values) and the rows of
 // Pbar_i, from the series records in global memory ...
 template <typename T>
@@ -1104,6 +1134,7 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
   if (!map_wave(B, kUnitPacket, p, q)) return;
   DevProblem& D = B.probs[p];
   if (D.ctl.done || t > D.ctl.stop_at) return;
+  series_clock_start(D, t, q);
   const CamFromRecords<T> cam{Prec<T>::S(D, D.ctl.pcur), D.s_stride};
   landmark_slot<T>(D, q, slot_head<T>(D, q), D.ctl.lcur, cam);
 }
@@ -1116,6 +1147,7 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark_coop(Batch B, int t)
   if (!map_wave(B, kUnitPacket, p, q)) return;
   DevProblem& D = B.probs[p];
   if (D.ctl.done || t > D.ctl.stop_at) return;
+  series_clock_start(D, t, q);
   const CamFromRecords<float> cam{Prec<float>::S(D, D.ctl.pcur), D.s_stride};
   if (D.s_stride == kSerLine) {
     extern __shared__ f4v coop_lds[];
@@ -1134,6 +1166,7 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark_coop64(Batch B, int 
   if (!map_wave(B, kUnitPacket, p, q)) return;
   DevProblem& D = B.probs[p];
   if (D.ctl.done || t > D.ctl.stop_at) return;
+  series_clock_start(D, t, q);
   const CamFromRecords<double> cam{Prec<double>::S(D, D.ctl.pcur), D.s_stride};
   if (D.s_stride == kSerLine) {
     __shared__ f4v cbuf[kWavesPerBlock][kCoopPieces * kWave];
@@ -1499,6 +1532,42 @@ __global__ void __launch_bounds__(kWave) k_retract(Batch B) {
   }
 }
 
+// ------------------------------------------------------------- k_grad_norm
+// Riemannian gradient of the reduced cost at the current cameras: by the
+// envelope theorem the gradient of f* is 2 b_p (b_p = sum_k J_p,k^T r_k at
+// X*(P), Eq. (9)-(10)); on the sphere it is projected onto each camera's
+// tangent space.  b_p from the linearisation partials of the current cameras
+// (chunks added in order, as in k_camera_prep); one workgroup per problem,
+// FP64 sum in a fixed order.
+__global__ void __launch_bounds__(kBlock) k_grad_norm(Batch B) {
+  int p, w;
+  if (!map_block(B, kUnitOne, p, w)) return;
+  DevProblem& D = B.probs[p];
+  const int pc = D.ctl.pcur;
+  double s = 0.0;
+  for (int i = (int)threadIdx.x; i < D.n_p; i += kBlock) {
+    double b[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) b[k] = 0.0;
+    for (int q = D.cam_ch[i]; q < D.cam_ch[i + 1]; ++q) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) b[k] += D.lin_part[(size_t)q * kLinVals + 40 + k];
+    }
+    if (D.manifold == 0) {
+      double pv[12], pb = 0.0;
+      load12((pc ? D.P64[1] : D.P64[0]) + (size_t)i * kCam, pv);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) pb += pv[k] * b[k];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) b[k] -= pb * pv[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) s += b[k] * b[k];
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) D.ctl.grad_norm = 2.0 * sqrt(s);
+}
+
 // ---------------------------------------------------------------- k_decide
 // Adds the trial cost partials (packet order), then: strict decrease accepts
 // (NaN rejects, and so does a step whose damped camera block could not be
@@ -1511,6 +1580,8 @@ __global__ void __launch_bounds__(kBlock) k_decide(Batch B) {
   DevProblem& D = B.probs[p];
   if (D.ctl.done) return;
   const double fn = packet_cost_sum(D);
+  __syncthreads();   // block_sum's LDS is reused
+  const double bl2 = packet_sum(D, D.bl_part, D.bl_group);
   if (threadIdx.x != 0) return;
   Ctl& c = D.ctl;
   const double f = c.cost;
@@ -1524,7 +1595,10 @@ __global__ void __launch_bounds__(kBlock) k_decide(Batch B) {
     D.tr_cost[it] = c.cost_trial;
     D.tr_lambda[it] = c.lambda;
     D.tr_acc[it] = accept ? 1 : 0;
+    D.tr_bl[it] = factored ? sqrt(bl2) : NAN;
+    D.tr_series[it] = (double)c.series_last;
   }
+  c.series_ticks += c.series_last;
   if (accept) {
     const double rel = (f - fn) / f;
     c.cost = fn;
@@ -1831,6 +1905,8 @@ __global__ void __launch_bounds__(kWave) k_refine_prep(Batch B) {
   if (i == 0) {
     D.ctl.stop_at = D.ctl.order;
     D.ctl.stopped = 0;
+    D.ctl.series_t0 = 0;
+    D.ctl.series_last = 0;
   }
   if (i >= D.n_p) return;
   const double lam = D.ctl.lambda;
@@ -2425,6 +2501,12 @@ hipError_t launch_refine_iteration(const Batch& b, int order, bool check, hipStr
   if ((e = launch_refine_step(b, order, check, s)) != hipSuccess) return e;
   if ((e = launch_cost_groups(b, 1, s)) != hipSuccess) return e;
   return launch_decide(b, s);
+}
+
+hipError_t launch_grad_norm(const Batch& b, hipStream_t s) {
+  if (b.total[kUnitOne] == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_grad_norm, blocks_for(b.total[kUnitOne], 1), dim3(kBlock), 0, s, b);
+  return hipGetLastError();
 }
 
 hipError_t launch_decide(const Batch& b, hipStream_t s) {

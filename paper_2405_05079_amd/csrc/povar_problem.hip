@@ -109,9 +109,13 @@ size_t arena_bytes(const LayoutSizes& z, bool fp32, int64_t trace_cap, ArenaOffs
   r.t_part = a.take(n_ch * kCam * ts);
   r.cost_part = a.take(n_pk * 8);
   r.cost_group = a.take((n_pk + kCostGroup - 1) / kCostGroup * 8);
+  r.bl_part = a.take(n_pk * 8);
+  r.bl_group = a.take((n_pk + kCostGroup - 1) / kCostGroup * 8);
   r.tr_cost = a.take(trace_cap * 8);
   r.tr_lambda = a.take(trace_cap * 8);
   r.tr_acc = a.take(trace_cap * 4);
+  r.tr_bl = a.take(trace_cap * 8);
+  r.tr_series = a.take(trace_cap * 8);
   return a.total;
 }
 
@@ -826,9 +830,13 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.ser_part = H.blocked ? dp(A.t_run) : dp(A.t_part);
   R.cost_part = (double*)dp(A.cost_part);
   R.cost_group = (double*)dp(A.cost_group);
+  R.bl_part = (double*)dp(A.bl_part);
+  R.bl_group = (double*)dp(A.bl_group);
   R.tr_cost = (double*)dp(A.tr_cost);
   R.tr_lambda = (double*)dp(A.tr_lambda);
   R.tr_acc = (int32_t*)dp(A.tr_acc);
+  R.tr_bl = (double*)dp(A.tr_bl);
+  R.tr_series = (double*)dp(A.tr_series);
 
   // second stage: initial landmarks (unit 4-vectors) and its own buffers
   R.stage = pts0 ? 2 : 1;
@@ -1100,13 +1108,66 @@ hipError_t povar_problem_s::drain_timing() {
 
 namespace povar {
 
-void fill_report(const povar_problem_s* pb, const Ctl& c, double seconds, povar_report* r) {
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as
+// easy as 1, 2, 3", SC 2011): ten rounds of two 64x64 -> 128-bit products
+// with the published multipliers, the key bumped by the published Weyl
+// constants between rounds.
+static void philox4x64(const uint64_t (&ctr_in)[4], const uint64_t (&key_in)[2], uint64_t (&out)[4]) {
+  constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
+  constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
+  uint64_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+  uint64_t k0 = key_in[0], k1 = key_in[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += kW0;
+      k1 += kW1;
+    }
+    const unsigned __int128 p0 = (unsigned __int128)kM0 * c[0];
+    const unsigned __int128 p1 = (unsigned __int128)kM1 * c[2];
+    const uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+    const uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    c[0] = hi1 ^ c[1] ^ k0;
+    c[1] = lo1;
+    c[2] = hi0 ^ c[3] ^ k1;
+    c[3] = lo0;
+  }
+  for (int i = 0; i < 4; ++i) out[i] = c[i];
+}
+
+void seeded_cameras(uint64_t seed, int32_t n, double* out) {
+  constexpr double kTwoPi = 6.283185307179586476925286766559;
+  const uint64_t key[2] = {seed, 0};
+  for (int32_t cam = 0; cam < n; ++cam) {
+    double* v = out + (size_t)cam * kCam;
+    for (uint64_t b = 0; b < 3; ++b) {
+      const uint64_t ctr[4] = {(uint64_t)cam, b, 0, 0};
+      uint64_t w[4];
+      philox4x64(ctr, key, w);
+      for (int h = 0; h < 2; ++h) {
+        // uniforms in (0, 1): the top 53 bits, offset by half a unit
+        const double u0 = ((double)(w[2 * h] >> 11) + 0.5) * 0x1p-53;
+        const double u1 = ((double)(w[2 * h + 1] >> 11) + 0.5) * 0x1p-53;
+        const double rho = std::sqrt(-2.0 * std::log(u0));   // Box-Muller
+        v[4 * b + 2 * h] = rho * std::cos(kTwoPi * u1);
+        v[4 * b + 2 * h + 1] = rho * std::sin(kTwoPi * u1);
+      }
+    }
+    double nrm = 0.0;
+    for (int r = 0; r < kCam; ++r) nrm += v[r] * v[r];
+    const double inv = 1.0 / std::sqrt(nrm);
+    for (int r = 0; r < kCam; ++r) v[r] *= inv;
+  }
+}
+
+void fill_report(const povar_problem_s* pb, const Ctl& c, double seconds, double grad_norm, povar_report* r) {
   if (!r) return;
   std::memset(r, 0, sizeof(*r));
   r->cost_initial = c.cost0;
   r->cost_final = c.cost;
   r->lambda_final = c.lambda;
-  r->seconds = seconds;
+  r->grad_norm_final = grad_norm;
+  r->seconds_total = seconds;
+  r->seconds_series = pb->ctx->clock_hz > 0.0 ? (double)c.series_ticks / pb->ctx->clock_hz : NAN;
   r->iters = c.iter;
   r->accepted = c.n_accept;
   r->stop_reason = c.stop_reason;
@@ -1172,6 +1233,9 @@ povar_status povar_ctx_create(int device, void* hip_stream, povar_ctx* out) {
   }
   auto* c = new povar_ctx_s();
   c->device = device;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+    c->clock_hz = 1e3 * khz;
   if (hip_stream) {
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->own_stream = false;
@@ -1243,9 +1307,15 @@ povar_status povar_problem_create(povar_ctx ctx, int32_t n_cams, int32_t n_pts, 
   *out = nullptr;
   povar_status st = check_options(ctx, opts);
   if (st != POVAR_OK) return st;
-  if (!cams0) {
-    set_error(ctx, "cams0 must not be NULL");
+  if (n_cams <= 0) {
+    set_error(ctx, "n_cams must be positive");
     return POVAR_EINVAL;
+  }
+  std::vector<double> seeded;
+  if (!cams0) {   // seeded unit-norm Gaussian cameras
+    seeded.resize((size_t)n_cams * kCam);
+    seeded_cameras(opts->init_seed, n_cams, seeded.data());
+    cams0 = seeded.data();
   }
   (void)hipSetDevice(ctx->device);
   HostLayout L;
@@ -1269,19 +1339,20 @@ povar_status povar_problem_create_device(povar_ctx ctx, int32_t n_cams, int32_t 
                                          const int32_t* cam_idx, const int32_t* pt_idx, const double* meas,
                                          const double* cams0, const povar_options* opts, povar_problem* out) {
   if (!ctx || !out) return POVAR_EINVAL;
-  if (n_cams <= 0 || n_pts <= 0 || n_obs <= 0 || !cam_idx || !pt_idx || !meas || !cams0) {
+  if (n_cams <= 0 || n_pts <= 0 || n_obs <= 0 || !cam_idx || !pt_idx || !meas) {
     set_error(ctx, "invalid sizes or NULL device pointers");
     return POVAR_EINVAL;
   }
   (void)hipSetDevice(ctx->device);
   std::vector<int32_t> c(n_obs), p(n_obs);
-  std::vector<double> m(2 * n_obs), q((size_t)n_cams * kCam);
+  std::vector<double> m(2 * n_obs), q(cams0 ? (size_t)n_cams * kCam : 0);
   HIP_TRY(ctx, hipMemcpyAsync(c.data(), cam_idx, n_obs * 4, hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipMemcpyAsync(p.data(), pt_idx, n_obs * 4, hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipMemcpyAsync(m.data(), meas, n_obs * 16, hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(ctx, hipMemcpyAsync(q.data(), cams0, q.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+  if (cams0) HIP_TRY(ctx, hipMemcpyAsync(q.data(), cams0, q.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  return povar_problem_create(ctx, n_cams, n_pts, n_obs, c.data(), p.data(), m.data(), q.data(), opts, out);
+  return povar_problem_create(ctx, n_cams, n_pts, n_obs, c.data(), p.data(), m.data(),
+                              cams0 ? q.data() : nullptr, opts, out);
 }
 
 povar_status povar_problem_destroy(povar_problem pb) {
@@ -1295,6 +1366,21 @@ povar_status povar_problem_destroy(povar_problem pb) {
   if (pb->arena2) (void)hipFree(pb->arena2);
   if (pb->ctx && pb->owned_by_ctx) pb->ctx->live_problems -= 1;
   delete pb;
+  return POVAR_OK;
+}
+
+// Gradient norm of the report at the current cameras: the linearisation
+// partials are those of the current cameras unless an accepted step has made
+// them stale (then one linearisation pass refreshes them; the next step
+// linearises again as it would have).  First stage only.
+static povar_status report_grad_norm(povar_problem pb, double* out) {
+  *out = NAN;
+  if (pb->rec.stage != 1) return POVAR_OK;
+  HIP_TRY(pb->ctx, launch_linearize(pb->batch, pb->fp32, 2, pb->stream));
+  HIP_TRY(pb->ctx, launch_grad_norm(pb->batch, pb->stream));
+  Ctl c;
+  HIP_TRY(pb->ctx, read_ctl(pb, &c));
+  *out = c.grad_norm;
   return POVAR_OK;
 }
 
@@ -1312,7 +1398,11 @@ static povar_status run_iters(povar_problem pb, int32_t n, bool check_done, pova
     HIP_TRY(ctx, read_ctl(pb, &c));
   }
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  fill_report(pb, c, secs, report);
+  if (!report) return POVAR_OK;
+  double gn;
+  const povar_status st = report_grad_norm(pb, &gn);
+  if (st != POVAR_OK) return st;
+  fill_report(pb, c, secs, gn, report);
   return POVAR_OK;
 }
 
@@ -1338,9 +1428,13 @@ povar_status povar_enqueue(povar_problem pb, int32_t n_iters) {
 
 povar_status povar_get_report(povar_problem pb, povar_report* report) {
   if (!pb || !report) return POVAR_EINVAL;
+  (void)hipSetDevice(pb->ctx->device);
+  double gn;
+  const povar_status st = report_grad_norm(pb, &gn);
+  if (st != POVAR_OK) return st;
   Ctl c;
   HIP_TRY(pb->ctx, read_ctl(pb, &c));
-  fill_report(pb, c, 0.0, report);
+  fill_report(pb, c, 0.0, gn, report);
   return POVAR_OK;
 }
 
@@ -1422,6 +1516,26 @@ povar_status povar_get_trace(povar_problem pb, int32_t n, double* cost, double* 
   if (lam) HIP_TRY(pb->ctx, hipMemcpyAsync(lam, pb->rec.tr_lambda, m * 8, hipMemcpyDeviceToHost, pb->stream));
   if (acc) HIP_TRY(pb->ctx, hipMemcpyAsync(acc, pb->rec.tr_acc, m * 4, hipMemcpyDeviceToHost, pb->stream));
   HIP_TRY(pb->ctx, hipStreamSynchronize(pb->stream));
+  return POVAR_OK;
+}
+
+povar_status povar_get_trace_diag(povar_problem pb, int32_t n, double* bl_norm, double* series_seconds) {
+  if (!pb || n < 0) return POVAR_EINVAL;
+  if (pb->rec.stage != 1) {
+    set_error(pb->ctx, "povar_get_trace_diag is for first-stage problems");
+    return POVAR_ESTATE;
+  }
+  Ctl c;
+  HIP_TRY(pb->ctx, read_ctl(pb, &c));
+  const int m = std::min(std::min(n, c.iter), pb->trace_cap);
+  if (m == 0) return POVAR_OK;
+  if (bl_norm) HIP_TRY(pb->ctx, hipMemcpyAsync(bl_norm, pb->rec.tr_bl, m * 8, hipMemcpyDeviceToHost, pb->stream));
+  std::vector<double> ticks(m);
+  HIP_TRY(pb->ctx, hipMemcpyAsync(ticks.data(), pb->rec.tr_series, m * 8, hipMemcpyDeviceToHost, pb->stream));
+  HIP_TRY(pb->ctx, hipStreamSynchronize(pb->stream));
+  if (series_seconds)
+    for (int i = 0; i < m; ++i)
+      series_seconds[i] = pb->ctx->clock_hz > 0.0 ? ticks[i] / pb->ctx->clock_hz : NAN;
   return POVAR_OK;
 }
 
@@ -1612,7 +1726,72 @@ povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, do
   Ctl restore = saved;
   restore.need_lin = 0;   // the linearisation at the current cameras is now in place
   restore.cost_trial = after.cost_trial;
-  restore.status = after.status;
+  restore.status = saved.status;   // a failed hook step does not reject the next real step
+  HIP_TRY(ctx, write_ctl(pb, &restore));
+  if (after.status & 1) {
+    set_error(ctx, "a damped camera block could not be factored at this damping");
+    return POVAR_ENUMERIC;
+  }
+  return POVAR_OK;
+}
+
+povar_status povar_debug_series(povar_problem pb, const double* x0, int32_t order, double* x_out) {
+  if (!pb || !x0 || !x_out || order < 0) return POVAR_EINVAL;
+  if (pb->rec.stage == 2) {
+    set_error(pb->ctx, "povar_debug_series is for first-stage problems");
+    return POVAR_ESTATE;
+  }
+  povar_ctx ctx = pb->ctx;
+  (void)hipSetDevice(ctx->device);
+  Ctl c;
+  HIP_TRY(ctx, read_ctl(pb, &c));
+  if (c.done) {
+    set_error(ctx, "problem has finished; series hooks need a running problem");
+    return POVAR_ESTATE;
+  }
+  const int32_t n_p = pb->L.n_p;
+  for (size_t k = 0; k < (size_t)n_p * kCam; ++k)
+    if (!std::isfinite(x0[k])) {
+      set_error(ctx, "x0 is not finite");
+      return POVAR_EINVAL;
+    }
+  const Ctl saved = c;
+  c.order = order;
+  c.status = 0;
+  HIP_TRY(ctx, write_ctl(pb, &c));
+  const Batch& B = pb->batch;
+  // the camera blocks K_i at the problem's damping (x_0 = -K g is replaced below)
+  HIP_TRY(ctx, launch_linearize(B, pb->fp32, 0, pb->stream));
+  HIP_TRY(ctx, launch_camera_prep(B, pb->fp32, pb->stream));
+  // term 0: the caller's x0, in internal camera order, into the series
+  // records (series precision) and the FP64 partial sum
+  std::vector<double> xin((size_t)n_p * kCam);
+  for (int32_t i = 0; i < n_p; ++i)
+    std::memcpy(&xin[(size_t)i * kCam], x0 + (size_t)pb->L.cam_int2ext[i] * kCam, sizeof(double) * kCam);
+  const size_t ss = (size_t)ser_stride(n_p);
+  if (pb->fp32) {
+    std::vector<float> xf(xin.size());
+    for (size_t k = 0; k < xin.size(); ++k) xf[k] = (float)xin[k];
+    HIP_TRY(ctx, hipMemcpy2DAsync(pb->rec.S32[c.pcur] + kSerX, ss * 4, xf.data(), kCam * 4, kCam * 4, n_p,
+                                  hipMemcpyHostToDevice, pb->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(pb->stream));   // xf is freed at the end of this block
+  } else {
+    HIP_TRY(ctx, hipMemcpy2DAsync(pb->rec.S64[c.pcur] + kSerX, ss * 8, xin.data(), kCam * 8, kCam * 8, n_p,
+                                  hipMemcpyHostToDevice, pb->stream));
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(pb->rec.acc, xin.data(), xin.size() * 8, hipMemcpyHostToDevice, pb->stream));
+  for (int t = 1; t <= order; ++t) {
+    HIP_TRY(ctx, launch_series_landmark(B, pb->fp32, t, pb->stream));
+    HIP_TRY(ctx, launch_series_camera(B, pb->fp32, t, pb->stream));
+  }
+  Ctl after;
+  HIP_TRY(ctx, read_ctl(pb, &after));   // synchronises: xin may go
+  std::vector<double> acc((size_t)n_p * kCam);
+  HIP_TRY(ctx, hipMemcpyAsync(acc.data(), pb->rec.acc, acc.size() * 8, hipMemcpyDeviceToHost, pb->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(pb->stream));
+  cams_to_caller(pb->L, acc.data(), x_out, kCam);
+  Ctl restore = saved;
+  restore.need_lin = 0;   // the linearisation at the current cameras is in place
   HIP_TRY(ctx, write_ctl(pb, &restore));
   if (after.status & 1) {
     set_error(ctx, "a damped camera block could not be factored at this damping");
@@ -1737,7 +1916,7 @@ povar_status povar_refine_debug_step(povar_problem pb, double lambda, int32_t or
   if (cost_trial) *cost_trial = after.cost_trial;
   Ctl restore = c;
   restore.cost_trial = after.cost_trial;
-  restore.status = after.status;
+  restore.status = c.status;   // a failed hook step does not reject the next real step
   HIP_TRY(ctx, write_ctl(pb, &restore));
   if (after.status & 1) {
     set_error(ctx, "a damped block could not be factored at this damping");

@@ -191,7 +191,7 @@ hipError_t retire(povar_server_s* sv, Group& G, int idx, const Ctl& c) {
   if (e == hipSuccess) cams_to_caller(pb->L, cin.data(), cams.data(), kCam);
   povar_status st = e == hipSuccess ? copy_points(pb, c.lcur, pts.data()) : POVAR_EDEVICE;
   povar_report rep;
-  fill_report(pb, c, 0.0, &rep);
+  fill_report(pb, c, 0.0, NAN, &rep);
   povar_problem_destroy(pb);
   const int last = (int)G.res.size() - 1;
   if (idx != last) {
@@ -204,7 +204,7 @@ hipError_t retire(povar_server_s* sv, Group& G, int idx, const Ctl& c) {
   G.res.pop_back();
   G.dirty = true;
   std::lock_guard<std::mutex> g(sv->mu);
-  rep.seconds = sv->now() - r->t_admit;
+  rep.seconds_total = sv->now() - r->t_admit;
   r->report = rep;
   r->cams = std::move(cams);
   r->pts = std::move(pts);
@@ -328,8 +328,8 @@ povar_status povar_server_submit(povar_server sv, int32_t n_cams, int32_t n_pts,
   povar_ctx ctx = sv->ctx;
   povar_status st = check_options(ctx, opts);
   if (st != POVAR_OK) return st;
-  if (!cams0) {
-    set_error(ctx, "cams0 must not be NULL");
+  if (n_cams <= 0) {
+    set_error(ctx, "n_cams must be positive");
     return POVAR_EINVAL;
   }
   auto r = std::make_shared<Request>();
@@ -345,7 +345,12 @@ povar_status povar_server_submit(povar_server sv, int32_t n_cams, int32_t n_pts,
   }
   r->n_p = n_cams;
   r->n_l = n_pts;
-  r->cams0.assign(cams0, cams0 + (size_t)n_cams * kCam);
+  if (cams0) {
+    r->cams0.assign(cams0, cams0 + (size_t)n_cams * kCam);
+  } else {   // seeded unit-norm Gaussian cameras, as for povar_problem_create
+    r->cams0.resize((size_t)n_cams * kCam);
+    seeded_cameras(opts->init_seed, n_cams, r->cams0.data());
+  }
   {
     std::lock_guard<std::mutex> g(sv->mu);
     r->ticket = sv->next_ticket++;

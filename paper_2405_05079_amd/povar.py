@@ -33,6 +33,7 @@ EXPORTS = [
     "povar_problem_info", "povar_problem_layout", "povar_server_create", "povar_server_submit", "povar_server_poll",
     "povar_server_stats", "povar_server_destroy", "povar_refine_create", "povar_get_points_h",
     "povar_refine_debug_blocks", "povar_refine_debug_step", "povar_metric_upgrade", "povar_metric_debug_reduced",
+    "povar_get_trace_diag", "povar_debug_series",
 ]
 
 
@@ -52,13 +53,13 @@ class Options(C.Structure):
                 ("max_iters", C.c_int32), ("ftol", C.c_double), ("lambda0", C.c_double),
                 ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("precision", C.c_int32),
                 ("manifold", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32),
-                ("series_rtol", C.c_double)]
+                ("series_rtol", C.c_double), ("init_seed", C.c_uint64)]
 
 
 class Report(C.Structure):
     _fields_ = [("cost_initial", C.c_double), ("cost_final", C.c_double), ("lambda_final", C.c_double),
-                ("seconds", C.c_double), ("iters", C.c_int32), ("accepted", C.c_int32),
-                ("stop_reason", C.c_int32), ("reserved", C.c_int32)]
+                ("grad_norm_final", C.c_double), ("seconds_total", C.c_double), ("seconds_series", C.c_double),
+                ("iters", C.c_int32), ("accepted", C.c_int32), ("stop_reason", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -99,6 +100,8 @@ def lib() -> C.CDLL:
         "povar_get_cameras": (C.c_int, [_P, _P]),
         "povar_get_points": (C.c_int, [_P, _P]),
         "povar_get_trace": (C.c_int, [_P, C.c_int32, _P, _P, _P]),
+        "povar_get_trace_diag": (C.c_int, [_P, C.c_int32, _P, _P]),
+        "povar_debug_series": (C.c_int, [_P, _P, C.c_int32, _P]),
         "povar_get_state": (C.c_int, [_P, _P, _DP, _I32P, _DP]),
         "povar_set_state": (C.c_int, [_P, _P, C.c_double, C.c_int32]),
         "povar_debug_linearize": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _DP]),
@@ -137,7 +140,7 @@ def _ptr(a: np.ndarray) -> C.c_void_p:
 
 def make_options(eta=0.01, order=20, max_iters=50, ftol=1e-6, lambda0=1e-4, lambda_min=1e-12,
                  lambda_max=1e12, precision="fp64", manifold="sphere", use_graph=True,
-                 series_rtol=0.0) -> Options:
+                 series_rtol=0.0, init_seed=0) -> Options:
     o = Options()
     lib().povar_options_default(C.byref(o))
     o.eta, o.series_order, o.max_iters, o.ftol = eta, order, max_iters, ftol
@@ -146,6 +149,7 @@ def make_options(eta=0.01, order=20, max_iters=50, ftol=1e-6, lambda0=1e-4, lamb
     o.manifold = MANIFOLD[manifold] if isinstance(manifold, str) else int(manifold)
     o.use_graph = 1 if use_graph else 0
     o.series_rtol = series_rtol
+    o.init_seed = int(init_seed)
     return o
 
 
@@ -262,14 +266,17 @@ class Problem:
             st = lib().povar_problem_create_device(
                 ctx.handle, self.n_cams, self.n_pts, int(cam_idx.shape[0]),
                 C.c_void_p(cam_idx.data_ptr()), C.c_void_p(pt_idx.data_ptr()), C.c_void_p(meas.data_ptr()),
-                C.c_void_p(cams0.data_ptr()), C.byref(self.options), C.byref(self.handle))
+                C.c_void_p(cams0.data_ptr()) if cams0 is not None else None, C.byref(self.options),
+                C.byref(self.handle))
         else:
             self._cam = np.ascontiguousarray(cam_idx, dtype=np.int32)
             self._pt = np.ascontiguousarray(pt_idx, dtype=np.int32)
             self._meas = np.ascontiguousarray(meas, dtype=np.float64).reshape(-1, 2)
-            c0 = np.ascontiguousarray(cams0, dtype=np.float64).reshape(self.n_cams, 12)
+            # cams0 None: the library draws seeded cameras (options init_seed)
+            c0 = None if cams0 is None else np.ascontiguousarray(cams0, dtype=np.float64).reshape(self.n_cams, 12)
             st = lib().povar_problem_create(ctx.handle, self.n_cams, self.n_pts, int(self._cam.shape[0]),
-                                            _ptr(self._cam), _ptr(self._pt), _ptr(self._meas), _ptr(c0),
+                                            _ptr(self._cam), _ptr(self._pt), _ptr(self._meas),
+                                            _ptr(c0) if c0 is not None else None,
                                             C.byref(self.options), C.byref(self.handle))
             del self._cam, self._pt, self._meas
         ctx.check(st, "povar_problem_create")
@@ -363,6 +370,21 @@ class Problem:
         if n:
             self._chk(lib().povar_get_trace(self.handle, n, _ptr(cost), _ptr(lam), _ptr(acc)), "povar_get_trace")
         return cost, lam, acc.astype(bool)
+
+    def trace_diag(self, n: int = 4096):
+        """Per-iteration |b_l| at the trial point and series seconds."""
+        n = min(n, self.report()["iters"])
+        bl, ss = np.empty(n), np.empty(n)
+        if n:
+            self._chk(lib().povar_get_trace_diag(self.handle, n, _ptr(bl), _ptr(ss)), "povar_get_trace_diag")
+        return bl, ss
+
+    def debug_series(self, x0, order: int) -> np.ndarray:
+        """sum_{t=0..order} M^t x0 at the current linearisation and damping."""
+        x = np.ascontiguousarray(x0, dtype=np.float64).reshape(self.n_cams, 12)
+        out = np.empty((self.n_cams, 12))
+        self._chk(lib().povar_debug_series(self.handle, _ptr(x), int(order), _ptr(out)), "povar_debug_series")
+        return out
 
     def state(self):
         cams = np.empty((self.n_cams, 12))

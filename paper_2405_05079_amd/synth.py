@@ -214,6 +214,45 @@ def init_cameras(n_cams: int, init_seed: int) -> np.ndarray:
     return c / np.linalg.norm(c, axis=1, keepdims=True)
 
 
+# Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+# as 1, 2, 3", SC 2011): the published round multipliers and Weyl key bumps.
+_PHILOX_M = (0xD2E7470EE14C6C93, 0xCA5A826395121157)
+_PHILOX_W = (0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B)
+_MASK64 = (1 << 64) - 1
+
+
+def philox4x64(ctr, key, rounds: int = 10):
+    """One Philox4x64 block: four 64-bit outputs for a 4-word counter and a
+    2-word key (Python integers)."""
+    c, k = list(ctr), list(key)
+    for r in range(rounds):
+        if r:
+            k = [(k[0] + _PHILOX_W[0]) & _MASK64, (k[1] + _PHILOX_W[1]) & _MASK64]
+        p0, p1 = _PHILOX_M[0] * c[0], _PHILOX_M[1] * c[2]
+        c = [(p1 >> 64) ^ c[1] ^ k[0], p1 & _MASK64, (p0 >> 64) ^ c[3] ^ k[1], p0 & _MASK64]
+    return c
+
+
+def seeded_cameras(n_cams: int, seed: int) -> np.ndarray:
+    """Initial cameras the library draws itself when it is given none
+    (povar_options.init_seed): camera c takes the Philox4x64-10 blocks with key
+    (seed, 0) and counters (c, b, 0, 0), b = 0, 1, 2; each output w gives the
+    uniform ((w >> 11) + 0.5) 2^-53, each output pair (u0, u1) two normals by
+    the Box-Muller transform (Box and Muller, 1958), and the 12 normals are
+    scaled to unit norm."""
+    out = np.empty((n_cams, 12))
+    for cam in range(n_cams):
+        for b in range(3):
+            w = philox4x64([cam, b, 0, 0], [seed & _MASK64, 0])
+            for h in range(2):
+                u0 = ((w[2 * h] >> 11) + 0.5) * 2.0 ** -53
+                u1 = ((w[2 * h + 1] >> 11) + 0.5) * 2.0 ** -53
+                rho = math.sqrt(-2.0 * math.log(u0))
+                out[cam, 4 * b + 2 * h] = rho * math.cos(2.0 * math.pi * u1)
+                out[cam, 4 * b + 2 * h + 1] = rho * math.sin(2.0 * math.pi * u1)
+    return out / np.linalg.norm(out, axis=1, keepdims=True)
+
+
 def workload(number: int, k: int = 0, **overrides) -> Problem:
     """Problem number `k` of workload `number`; data seed = 1000*number + k,
     initial-camera seed = data seed + 1."""

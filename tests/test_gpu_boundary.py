@@ -1,0 +1,167 @@
+"""The C ABI calls added for the hot-path boundary (needs an MI355X):
+
+* povar_debug_series: the truncated series (17) from a caller's start x0 at
+  the current linearisation and damping, against the oracle's series_from;
+* cams0 = NULL: cameras drawn by the library from init_seed (Philox4x64-10,
+  Box-Muller), against the seeded generator's independent implementation;
+* the report's grad_norm_final (the Riemannian gradient of the reduced cost)
+  against the oracle's, seconds_series, and the per-iteration trace of
+  |b_l| (zero gradient of the eliminated landmarks) and series time;
+* R12: a damped camera block with no Cholesky factor rejects the step.
+"""
+import numpy as np
+import pytest
+
+from oracle import povar_oracle as O
+from paper_2405_05079_amd import povar, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = povar.Context(0)
+    yield c
+    c.close()
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def rel_rows(a, b):
+    a, b = a.reshape(len(a), -1), b.reshape(len(b), -1)
+    return (np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)).max()
+
+
+SERIES_CASES = [
+    dict(n_cams=7, n_pts=1000, seed=6, track=("uniform", 3, 6)),          # cameras over several chunks
+    dict(n_cams=400, n_pts=8000, seed=36, track=("uniform", 3, 6)),        # 128-byte records, cooperative gathers
+    dict(n_cams=300, n_pts=140000, seed=33, track=("uniform", 2, 3), cam_choice="zipf"),   # landmark-blocked
+]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32_bulk", 1e-4)])
+@pytest.mark.parametrize("kw", SERIES_CASES)
+def test_debug_series_matches_oracle(ctx, kw, prec, tol):
+    prob = synth.make_problem(**kw)
+    say("debug_series", kw, prec)
+    gp = povar.Problem.from_synth(ctx, prob, precision=prec)
+    try:
+        lam = gp.state()[1]
+        P, X, f = O.initial_state(prob, prob.cams0)
+        lin = O.linearize(P, X, prob)
+        rng = np.random.default_rng(kw["seed"])
+        x_amb = rng.standard_normal((prob.n_cams, 12))
+        x_tan = x_amb - np.sum(x_amb * P, axis=1, keepdims=True) * P
+        for x0 in (x_amb, x_tan):
+            for order in (0, 1, 6, 20):
+                got = gp.debug_series(x0, order)
+                if order == 0:   # the start itself, summed in FP64
+                    np.testing.assert_array_equal(got, x0)
+                    continue
+                ref = O.series_from(P, lin, lam, x0, order)
+                # per camera, with a floor at 1e-2 of the tolerance times the
+                # largest camera term: a random start makes each camera's sums
+                # cancel to different degrees, and FP32 rounding is relative to
+                # the summands, not to the sum
+                err = np.linalg.norm(got - ref, axis=1)
+                bound = tol * np.linalg.norm(ref, axis=1) + 1e-2 * tol * np.linalg.norm(ref, axis=1).max()
+                assert np.all(err <= bound), (order, (err / bound).max())
+        # the hook keeps the solver state: a step afterwards equals one on a fresh problem
+        gp.step(2)
+        fresh = povar.Problem.from_synth(ctx, prob, precision=prec)
+        fresh.step(2)
+        np.testing.assert_array_equal(gp.cameras(), fresh.cameras())
+        fresh.close()
+    finally:
+        gp.close()
+
+
+@pytest.mark.parametrize("manifold", ["sphere", "euclidean"])
+def test_seeded_initial_cameras(ctx, manifold):
+    prob = synth.make_problem(40, 2000, track=("uniform", 3, 6), seed=71)
+    say("seeded cameras", manifold)
+    for seed in (0, 12345, 2 ** 64 - 1):
+        gp = povar.Problem(ctx, prob.n_cams, prob.n_pts, prob.cam_idx, prob.pt_idx, prob.meas, None,
+                           init_seed=seed, manifold=manifold, eta=prob.eta)
+        C = synth.seeded_cameras(prob.n_cams, seed)
+        got = gp.cameras()
+        np.testing.assert_allclose(got, C, rtol=0, atol=1e-15)
+        P, X, f = O.initial_state(prob, C, manifold)
+        assert abs(gp.report()["cost_initial"] - f) <= 1e-11 * f
+        gp.close()
+
+
+def test_report_gradient_norm_series_time_and_trace_diagnostics(ctx):
+    prob = synth.workload(1)
+    say("report fields, workload 1")
+    gp = povar.Problem.from_synth(ctx, prob, precision="fp64", max_iters=50, ftol=0.0)
+    try:
+        # at the initial cameras
+        P, X, f = O.initial_state(prob, prob.cams0)
+        g0 = np.linalg.norm(O.riemannian_gradient(P, O.linearize(P, X, prob)))
+        r0 = gp.report()
+        assert abs(r0["grad_norm_final"] - g0) <= 1e-9 * g0
+        assert r0["seconds_series"] == 0.0
+        # after the solve (the FP64 trajectory follows the oracle's)
+        rep = gp.solve()
+        ref = O.lm_solve(prob, opts=O.Options(order=prob.order, max_iters=50, ftol=0.0))
+        gref = np.linalg.norm(O.riemannian_gradient(ref.P, O.linearize(ref.P, ref.X, prob)))
+        assert abs(rep["grad_norm_final"] - gref) <= 1e-6 * gref, (rep["grad_norm_final"], gref)
+        assert rep["grad_norm_final"] < g0
+        bl, ss = gp.trace_diag()
+        cost, lam, acc = gp.trace()
+        assert len(bl) == len(ss) == 50
+        assert np.all(ss > 0) and rep["seconds_series"] > 0
+        assert abs(ss.sum() - rep["seconds_series"]) <= 1e-9 * rep["seconds_series"]
+        assert rep["seconds_series"] <= rep["seconds_total"]
+        # the eliminated landmarks have zero gradient: |b_l| at rounding level
+        assert np.all(np.isfinite(bl))
+        assert np.all(bl <= 1e-11 * np.sqrt(cost)), (bl.max(), np.sqrt(cost).min())
+        # a second report does not change the state
+        assert gp.report()["grad_norm_final"] == rep["grad_norm_final"]
+    finally:
+        gp.close()
+
+
+def _camera_without_measurement_signal(seed=61):
+    prob = synth.make_problem(5, 60, track=("uniform", 3, 5), seed=seed)
+    meas = prob.meas.copy()
+    meas[prob.cam_idx == 0] = 0.0
+    return synth.Problem(prob.n_cams, prob.n_pts, prob.cam_idx, prob.pt_idx, meas, prob.cams0, prob.eta, 3)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_bulk"])
+def test_r12_block_without_cholesky_factor_rejects_the_step(ctx, prec):
+    """Camera 0 sees every point at m = 0, so its U block has four zero rows
+    and columns; at lambda = 1e-320 the damping of those entries underflows to
+    zero and the block is exactly singular: no Cholesky factor (R12)."""
+    prob = _camera_without_measurement_signal()
+    say("R12", prec)
+    lam = 1e-320
+    gp = povar.Problem.from_synth(ctx, prob, precision=prec, manifold="euclidean", lambda0=lam, lambda_min=lam,
+                                  lambda_max=lam, max_iters=4, ftol=0.0)
+    try:
+        cams0 = gp.cameras()
+        f0 = gp.report()["cost_initial"]
+        with pytest.raises(povar.PovarError) as e:
+            gp.debug_step(lam, 3)
+        assert e.value.status == povar.ENUMERIC
+        rep = gp.solve()
+        cost, lams, acc = gp.trace()
+        ref = O.lm_solve(prob, opts=O.Options(order=3, max_iters=4, ftol=0.0, lambda0=lam, lambda_min=lam,
+                                              lambda_max=lam, manifold="euclidean"))
+        assert list(acc) == ref.trace_accept == [False] * 4
+        assert np.all(np.isinf(cost)) and np.all(lams == lam)
+        np.testing.assert_array_equal(gp.cameras(), cams0)
+        assert rep["cost_final"] == f0 and rep["accepted"] == 0
+    finally:
+        gp.close()
+    # with ordinary damping the same camera block factors and the step matches the oracle
+    gp = povar.Problem.from_synth(ctx, prob, precision="fp64", manifold="euclidean")
+    P, X, f = O.initial_state(prob, prob.cams0, "euclidean")
+    dp, _, _ = gp.debug_step(1e-3, 3)
+    ref = O.camera_step(P, O.linearize(P, X, prob), 1e-3, 3, "euclidean")
+    assert rel_rows(dp, ref) < 1e-9
+    gp.close()

@@ -35,6 +35,22 @@ def rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
+def rel_rows(a, b):
+    """Largest per-camera relative error (2-norm of each camera's 12 values)."""
+    a, b = np.asarray(a).reshape(len(a), -1), np.asarray(b).reshape(len(b), -1)
+    return (np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)).max()
+
+
+# FP32-bulk steps: every camera's 12-vector within 1e-4 of the oracle's,
+# relative to that camera's own step (FP32 rounding of ~1e-7 in the series
+# terms, amplified by the damped camera inverse and up to m + 1 terms)
+FP32_STEP = 1e-4
+
+
+def step_err(prec, a, b):
+    return rel_rows(a, b) if prec == "fp32_bulk" else rel(a, b)
+
+
 # ragged sizes: several 64-landmark slices with a partial last slice, cameras
 # with several 256-observation chunks and a ragged last chunk
 CASES = [
@@ -114,7 +130,7 @@ def test_camera_step_fp32_bulk(ctx, lam, order, kw):
     dp, pt, ct = gp.debug_step(lam, order)
     P, X, f = O.initial_state(prob, prob.cams0)
     ref = O.camera_step(P, O.linearize(P, X, prob), lam, order)
-    assert rel(dp, ref) < 2e-3
+    assert rel_rows(dp, ref) < FP32_STEP
     gp.close()
 
 
@@ -136,7 +152,7 @@ def test_camera_step_fp64_cooperative(ctx, lam, order):
     gp.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32_bulk", 2e-3)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32_bulk", FP32_STEP)])
 def test_series_early_stop(ctx, prec, tol):
     """series_rtol = 0.01: the series stops after the first term t >= 1 with
     ||x_t|| <= 0.01 ||x_0 + ... + x_t|| and the step is retracted from there.
@@ -153,7 +169,7 @@ def test_series_early_stop(ctx, prec, tol):
         used.append(O.power_series(O.reduced_system(P, lin, lam), 20, 0.01)[1])
         dp, pt, ct = gp.debug_step(lam, 20)
         ref = O.camera_step(P, lin, lam, 20, rtol=0.01)
-        assert rel(dp, ref) < tol
+        assert step_err(prec, dp, ref) < tol
         np.testing.assert_allclose(np.linalg.norm(pt, axis=1), 1.0, rtol=1e-12)
         Pn = O.retract(P, ref)
         Xn, _ = O.solve_landmarks(Pn, prob)
@@ -201,11 +217,11 @@ BLOCKED = [
     # more cameras than the landmark pass stages in LDS: staged and global camera reads
     ("fp64", dict(n_cams=1200, n_pts=70000, track=("uniform", 2, 4), cam_choice="zipf", seed=34), 1e-9),
     # ~38k observations per camera: many runs per camera and block, runs split at slot ends
-    ("fp32_bulk", dict(n_cams=6, n_pts=140000, track=("uniform", 2, 2), seed=32), 2e-3),
+    ("fp32_bulk", dict(n_cams=6, n_pts=140000, track=("uniform", 2, 2), seed=32), FP32_STEP),
     # heavy-tailed views per camera
-    ("fp32_bulk", dict(n_cams=300, n_pts=140000, track=("uniform", 2, 3), cam_choice="zipf", seed=33), 2e-3),
+    ("fp32_bulk", dict(n_cams=300, n_pts=140000, track=("uniform", 2, 3), cam_choice="zipf", seed=33), FP32_STEP),
     # 128-byte camera records, gathered cooperatively by the landmark pass
-    ("fp32_bulk", dict(n_cams=400, n_pts=140000, track=("uniform", 2, 3), seed=35), 2e-3),
+    ("fp32_bulk", dict(n_cams=400, n_pts=140000, track=("uniform", 2, 3), seed=35), FP32_STEP),
 ]
 
 
@@ -223,7 +239,7 @@ def test_blocked_camera_pass(ctx, prec, kw, tol):
     lin = O.linearize(P, X, prob)
     for lam, order in ((1e-3, 1), (1e-3, 8)):
         dp, pt, ct = gp.debug_step(lam, order)
-        assert rel(dp, O.camera_step(P, lin, lam, order)) < tol
+        assert step_err(prec, dp, O.camera_step(P, lin, lam, order)) < tol
     gp.close()
 
 
@@ -267,7 +283,10 @@ def test_graph_replay_equals_direct_launches(ctx):
         b.step(5)
         np.testing.assert_array_equal(a.cameras(), b.cameras())
         np.testing.assert_array_equal(a.points(), b.points())
-        assert a.report() == b.report() or a.report()["cost_final"] == b.report()["cost_final"]
+        ra, rb = a.report(), b.report()
+        for key in ("cost_initial", "cost_final", "lambda_final", "grad_norm_final", "iters", "accepted",
+                    "stop_reason"):
+            assert ra[key] == rb[key], key   # wall and device times differ by nature
     a.close()
     b.close()
 
@@ -317,11 +336,11 @@ def test_paper_eta_values(ctx, eta):
     say("eta", eta)
     P, X, f = O.initial_state(prob, prob.cams0)
     ref = O.camera_step(P, O.linearize(P, X, prob), 1e-3, 10)
-    for prec, tol in (("fp64", 1e-9), ("fp32_bulk", 2e-3)):
+    for prec, tol in (("fp64", 1e-9), ("fp32_bulk", FP32_STEP)):
         gp = povar.Problem.from_synth(ctx, prob, precision=prec, eta=eta)
         dp, _, _ = gp.debug_step(1e-3, 10)
         gp.close()
-        assert rel(dp, ref) < tol
+        assert step_err(prec, dp, ref) < tol
 
 
 def test_edge_cases(ctx):

@@ -352,3 +352,149 @@ def test_lm_reaches_known_zero_minimum_on_noise_free_affine_problem():
     assert res.cost < 1e-12 * res.cost0
     res = O.lm_solve(prob, opts=O.Options(order=20, max_iters=50, ftol=0.0, manifold="sphere"))
     assert res.cost < 1e-3 * res.cost0
+
+
+# --------------------------------------------------------------------------- series from a given start
+def test_series_from_a_given_start_matches_dense_closed_form():
+    """The series of (17) from an arbitrary ambient start x0 (the operator
+    povar_debug_series exposes).  With the dense tangent-space matrix
+    M = U~^-1 W~ V^+ W~^T and M0 = U~^-1 B^T W V^+ W^T (the first application,
+    from ambient coordinates), the order-m sum is
+    x0 + Bd (I - M^m)(I - M)^-1 M0 x0; a tangent start x0 = Bd u gives
+    Bd (I - M^{m+1})(I - M)^-1 u, and the start -Bd U~^-1 g gives the camera
+    step itself."""
+    prob = tiny(n_cams=4, n_pts=30, seed=41)
+    P = synth.init_cameras(prob.n_cams, 42)
+    lam = 0.3
+    D = _dense_problem(prob, P, lam)
+    Ut, W, V, Bd = D["Ut"], D["W"], D["V"], D["Bd"]
+    Vp = np.linalg.pinv(V, rcond=1e-12, hermitian=True)
+    M = np.linalg.solve(Ut, W @ Vp @ W.T)
+    X, _ = O.solve_landmarks(P, prob)
+    lin = O.linearize(P, X, prob)
+    # ambient W from the dense literal Jacobians, not from the oracle's assembly
+    Jp, Jl = O.pose_jacobians(P, X, prob.cam_idx, prob.pt_idx, prob.meas, prob.eta)
+    JPa = np.zeros((4 * prob.n_obs, 12 * prob.n_cams))
+    for o in range(prob.n_obs):
+        i = prob.cam_idx[o]
+        JPa[4 * o:4 * o + 4, 12 * i:12 * i + 12] = Jp[o]
+    Wamb = JPa.T @ D["JL"]
+    Mt = np.linalg.solve(Ut, Bd.T @ Wamb @ Vp @ Wamb.T)     # ambient start -> tangent coordinates
+    I = np.eye(M.shape[0])
+    rng = np.random.default_rng(43)
+    x0 = rng.standard_normal((prob.n_cams, 12))              # not tangent
+    u = rng.standard_normal(M.shape[0])
+    for m in (0, 1, 3, 12):
+        got = O.series_from(P, lin, lam, x0, m)
+        if m == 0:
+            closed = x0.ravel()
+        else:
+            closed = x0.ravel() + Bd @ ((I - np.linalg.matrix_power(M, m)) @ np.linalg.solve(I - M, Mt @ x0.ravel()))
+        np.testing.assert_allclose(got.ravel(), closed, rtol=1e-9, atol=1e-11 * np.abs(closed).max())
+        # the terms after the first are tangent
+        assert np.abs(np.sum((got - x0) * P, axis=1)).max() <= 1e-12 * np.abs(got - x0).max() + 1e-300
+        got_t = O.series_from(P, lin, lam, (Bd @ u).reshape(-1, 12), m)
+        closed_t = Bd @ ((I - np.linalg.matrix_power(M, m + 1)) @ np.linalg.solve(I - M, u))
+        np.testing.assert_allclose(got_t.ravel(), closed_t, rtol=1e-9, atol=1e-11 * np.abs(closed_t).max())
+    # the camera step is the series from -U~^-1 g
+    g = D["bp"] - W @ Vp @ D["bl"]
+    start = (Bd @ -np.linalg.solve(Ut, g)).reshape(-1, 12)
+    np.testing.assert_allclose(O.series_from(P, lin, lam, start, 7), O.camera_step(P, lin, lam, 7),
+                               rtol=1e-9, atol=1e-12)
+
+
+def test_riemannian_gradient_matches_tangent_finite_differences():
+    """grad f* (the report's gradient norm): orthogonal to each camera and,
+    along tangent directions v, equal to the central difference of the
+    reduced cost (landmarks re-solved), which the envelope theorem predicts."""
+    prob = tiny(n_cams=4, n_pts=40, seed=51)
+    P = synth.init_cameras(prob.n_cams, 52)
+    X, _ = O.solve_landmarks(P, prob)
+    lin = O.linearize(P, X, prob)
+    g = O.riemannian_gradient(P, lin)
+    assert np.abs(np.sum(g * P, axis=1)).max() <= 1e-12 * np.abs(g).max()
+    rng = np.random.default_rng(53)
+    for _ in range(3):
+        v = rng.standard_normal(P.shape)
+        v -= np.sum(v * P, axis=1, keepdims=True) * P
+        h = 1e-6
+        fd = (O.reduced_cost(P + h * v, prob) - O.reduced_cost(P - h * v, prob)) / (2 * h)
+        assert abs(fd - np.sum(g * v)) <= 1e-6 * max(1.0, abs(fd))
+    ge = O.riemannian_gradient(P, lin, "euclidean")
+    np.testing.assert_allclose(ge, 2 * lin.bp, rtol=0, atol=0)
+
+
+# --------------------------------------------------------------------------- R12: no Cholesky factor
+def _camera_without_measurement_signal(seed=61):
+    """A problem whose camera 0 sees every point at m = (0, 0): the columns of
+    J_p for the third camera row are -sqrt(1-eta) m x~ = 0, so U_0 has four
+    exactly zero rows and columns (the row P^3 of that camera does not enter
+    its residuals)."""
+    prob = tiny(n_cams=5, n_pts=60, seed=seed)
+    meas = prob.meas.copy()
+    meas[prob.cam_idx == 0] = 0.0
+    return synth.Problem(prob.n_cams, prob.n_pts, prob.cam_idx, prob.pt_idx, meas, prob.cams0, prob.eta,
+                         prob.order)
+
+
+def test_r12_a_damped_block_without_cholesky_factor_is_rejected():
+    """R12.  Mathematically, U + lambda D (D = the floored diagonal of U,
+    positive) is positive definite for every lambda > 0, so a Cholesky factor
+    exists.  It fails only where lambda D underflows: with the damping floor
+    1e-12 of the largest diagonal entry and lambda = 1e-320, the zero diagonal
+    entries of U_0 stay exactly zero in FP64, the damped block is exactly
+    singular (four zero rows), and no Cholesky factor exists.  The oracle then
+    rejects the step: the trial cost is +inf, the cameras stay, and lambda
+    goes to min(10 lambda, lambda_max)."""
+    prob = _camera_without_measurement_signal()
+    P, X, f = O.initial_state(prob, prob.cams0, "euclidean")
+    lin = O.linearize(P, X, prob)
+    assert np.all(lin.U[0][8:, :] == 0.0) and np.all(lin.U[0][:, 8:] == 0.0)
+    tiny_lam = 1e-320
+    rs = O.reduced_system(P, lin, tiny_lam, "euclidean")
+    assert np.all(rs.Ut[0][8:, 8:] == 0.0)          # lambda * floor underflowed to zero
+    assert np.linalg.matrix_rank(rs.Ut[0]) == 8      # singular: no Cholesky factor exists
+    assert not O.factorizable(rs)
+    assert O.factorizable(O.reduced_system(P, lin, 1e-4, "euclidean"))
+    # the branch is not only reachable through underflow: on the sphere at the
+    # default smallest damping (1e-12) this camera's tangent block has
+    # eigenvalues of the order of 1e-24 of its largest, far below FP64
+    # rounding of the block's entries, so whether a factor is found is decided
+    # by rounding (the oracle and the GPU may then both reject, by R12 or by
+    # a non-finite or larger trial cost)
+    Ps, Xs, _ = O.initial_state(prob, prob.cams0)
+    ev = np.linalg.eigvalsh(O.reduced_system(Ps, O.linearize(Ps, Xs, prob), 1e-12).Ut[0])
+    assert abs(ev[0]) <= 1e-15 * ev[-1]
+    # the LM loop: every step rejected, nothing moves
+    res = O.lm_solve(prob, opts=O.Options(order=3, max_iters=4, ftol=0.0, lambda0=tiny_lam, lambda_min=tiny_lam,
+                                          lambda_max=tiny_lam, manifold="euclidean"))
+    assert res.trace_accept == [False] * 4
+    assert all(np.isinf(c) for c in res.trace_cost)
+    assert res.trace_lambda == [tiny_lam] * 4
+    np.testing.assert_array_equal(res.P, P)
+    assert res.cost == f
+    # with room to grow, lambda rises x10 per rejected step
+    res = O.lm_solve(prob, opts=O.Options(order=3, max_iters=3, ftol=0.0, lambda0=tiny_lam, lambda_min=tiny_lam,
+                                          lambda_max=1.0, manifold="euclidean"))
+    assert res.trace_lambda[1] == min(10 * tiny_lam, 1.0) and not res.trace_accept[0]
+
+
+# --------------------------------------------------------------------------- seeded initial cameras
+def test_philox_matches_numpy_bit_generator():
+    """synth's Philox4x64-10 (written from its published definition) against
+    numpy's Philox bit generator: numpy's n-th block is counter n + 1."""
+    for key in (0, 7, 2 ** 63 + 12345):
+        bg = np.random.Philox(key=np.array([key, 0], dtype=np.uint64), counter=np.zeros(4, dtype=np.uint64))
+        raw = bg.random_raw(12)
+        mine = [w for c in (1, 2, 3) for w in synth.philox4x64([c, 0, 0, 0], [key, 0])]
+        assert [int(x) for x in raw] == mine
+
+
+def test_seeded_cameras_are_unit_gaussian_directions():
+    C = synth.seeded_cameras(3000, 11)
+    np.testing.assert_allclose(np.linalg.norm(C, axis=1), 1.0, rtol=1e-15)
+    # the normals behind them: mean 0, variance 1 (36,000 draws: 5 sigma bounds)
+    w = C * np.sqrt(12.0)
+    assert abs(w.mean()) < 5 / np.sqrt(w.size)
+    assert abs((w * w).mean() - 1.0) < 0.05
+    assert not np.array_equal(C, synth.seeded_cameras(3000, 12))
