@@ -2,12 +2,23 @@
 
 A step is one PoVar outer iteration (linearisation after an accept, damping
 and tangent projection, the order-m power series, retraction, closed-form
-landmark re-solve, LM decision) on the mid-size synthetic workload: 250
-cameras, 60,000 points, ~300k observations, eta = 0.01, series order 20,
-FP32-bulk precision (FP32 Jacobians and series, FP64 landmark blocks, camera
-factorisation and cost).  The line also carries the plain FP64 GPU path on the
-same problem, the matched-final-cost comparison, the roofline of the dominant
-series kernel and the FP64 CPU oracle timed on a bounded sample.
+landmark re-solve, LM decision).  `value` is FP32-bulk iterations/s (FP32
+Jacobians and series, FP64 landmark blocks, camera factorisation and cost) on
+the mid-size synthetic workload: 250 cameras, 60,000 points, ~300k
+observations, eta = 0.01, series order 20.  The same JSON line carries:
+
+* the FP64 GPU path on the same problem;
+* the roofline of the series (bytes per order of the algorithmic model:
+  12 per observation, 36 per landmark, 800 per camera) at 250 cameras (cache
+  resident) and at the roofline rows, 1,800 cameras / 5M observations and
+  13,700 cameras / 29M observations, in both precisions, with the per-kernel
+  durations and the HBM traffic measured by rocprofv3 counters;
+* the time to the FP64 oracle's final cost: iterations and seconds each GPU
+  path needs to reach f_ref (1 + 1e-6), f_ref the oracle's cost after the
+  workload's 100 iterations, on five seeded problems;
+* the serving stream: 512 requests, Poisson arrivals at a fixed rate,
+  admission by HBM budget, p50/p99 latency per size bucket;
+* the FP64 CPU oracle timed on the host (all cores and one core).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -45,18 +56,26 @@ def device_sync():
         raise RuntimeError(f"hipDeviceSynchronize failed: {rc}")
 
 
+def alg_bytes_per_order(n_obs: int, n_l: int, n_p: int) -> int:
+    """Algorithmic bytes of one series order (the two passes together): per
+    observation the camera index and the FP32 measurement once (12 B), per
+    landmark x~_j and the symmetric V_j^+ in FP32 (36 B), per camera the
+    series vector, the packed FP64 Cholesky factor and the partial sums
+    (800 B).  What the method must move, whatever the kernels do."""
+    return 12 * n_obs + 36 * n_l + 800 * n_p
+
+
 def series_bytes(n_obs: int, n_l: int, n_p: int, fp32: bool):
-    """Algorithmic bytes of one launch of each series kernel (compulsory
-    traffic: every input read once, every output written once; s = 4 for
-    FP32-bulk, 8 for FP64):
+    """This implementation's own per-launch byte model of the two series
+    kernels (every input of the kernel read once, every output written once;
+    s = 4 for FP32-bulk, 8 for FP64):
     landmark pass: per observation the packed camera index (4 B) and the
       measurement (2s); per landmark X_j (3s), V_j^+ (6 FP64 = 48 B) and z_j
       written (3s); per camera x_i (12s) and Pbar_i (9s);
     camera pass: per observation the landmark index (4 B) and the measurement
       (2s); per landmark z_j and X_j (6s); per camera the FP64 12x12 block K_i
       (1152 B), Pbar_i (9s), x_i written (12s) and the FP64 partial sum acc_i
-      read and written (192 B).  The per-camera part is done by the combine
-      kernel when a problem's camera pass is blocked; the figure is the pass's."""
+      read and written (192 B).  Reported beside the algorithmic model."""
     s = 4 if fp32 else 8
     lpass = (4 + 2 * s) * n_obs + (6 * s + 48) * n_l + 21 * s * n_p
     cpass = (4 + 2 * s) * n_obs + 6 * s * n_l + (1344 + 21 * s) * n_p
@@ -72,31 +91,158 @@ def timed_iters(gp, steps: int) -> float:
     return time.perf_counter() - t0
 
 
-def matched_cost(ctx, prob, ref_cost: float, max_iters: int):
-    """Iterations FP32-bulk needs to first reach ref_cost (1 + 1e-6)."""
-    gp = povar.Problem.from_synth(ctx, prob, precision="fp32_bulk", ftol=0.0, max_iters=max_iters)
-    gp.step(max_iters)
+def series_kernel_names(prec: str, layout: dict, n_cams: int):
+    """rocprofv3 names of the landmark pass, the camera pass and the combine
+    kernel of a problem with this layout."""
+    t = "float" if prec == "fp32_bulk" else "double"
+    if layout["coop_gather"]:
+        land = "k_series_landmark_coop" if prec == "fp32_bulk" else "k_series_landmark_coop64"
+    else:
+        land = f"k_series_landmark<{t}>"
+    cam = f"k_series_camera_slots<{t}>" if layout["blocked"] else f"k_series_camera<{t}, 1024>"
+    return land, cam, f"k_series_camera_combine<{t}>"
+
+
+def series_leg(ctx, prob, prec: str, steps: int, warmup: int, workload: str):
+    """Timed iterations of one problem and the roofline of its series orders:
+    the durations of the landmark pass and of the camera pass (with its
+    combine kernel) from HIP events recorded by the kernels' own dispatches,
+    the algorithmic bytes per order over their sum, and the HBM traffic the
+    committed rocprofv3 counters measured for these kernels (None when the
+    kernels changed since)."""
+    gp = povar.Problem.from_synth(ctx, prob, precision=prec, ftol=0.0, max_iters=10 ** 6)
+    gp.step(warmup)
+    secs = timed_iters(gp, steps)
+    rep = gp.report()
+    gp.kernel_timing(True)
+    gp.step(max(3, min(steps // 4, 20)))
+    kt = gp.kernel_times()
+    gp.kernel_timing(False)
+    layout = gp.layout()
+    stage1 = (gp.cameras(), gp.points()) if prec == "fp64" else None
+    gp.close()
+    us_l = 1e3 * kt["ms_landmark_pass"] / max(1, kt["n_landmark_pass"])
+    us_c = 1e3 * kt["ms_camera_pass"] / max(1, kt["n_camera_pass"])
+    b_alg = alg_bytes_per_order(prob.n_obs, prob.n_pts, prob.n_cams)
+    b_l, b_c = series_bytes(prob.n_obs, prob.n_pts, prob.n_cams, prec == "fp32_bulk")
+    land, cam, comb = series_kernel_names(prec, layout, prob.n_cams)
+    h = kernel_source_hash()
+    tr = [traffic_from_profiles(k, workload, h) for k in (land, cam)]
+    tr_comb = traffic_from_profiles(comb, workload, h)
+    traffic = (tr[0] + tr[1] + (tr_comb or 0.0)) if None not in tr else None
+    order_us = us_l + us_c
+    dom, dom_us = (land, us_l) if us_l >= us_c else (cam, us_c)
+    out = {
+        "precision": prec, "iters_per_s": round(steps / secs, 3), "ms_per_iter": round(1e3 * secs / steps, 4),
+        "steps": steps, "cost_after": rep["cost_final"], "layout": layout,
+        "us_landmark_pass": round(us_l, 3), "us_camera_pass_with_combine": round(us_c, 3),
+        "us_per_order": round(order_us, 3),
+        "alg_bytes_per_order": b_alg,
+        "alg_frac_per_order": round(b_alg / (order_us * 1e-6) / (HBM_PEAK_GBS * 1e9), 4),
+        "dominant_kernel": {"name": dom, "avg_us": round(dom_us, 3),
+                            "alg_frac": round(b_alg / (dom_us * 1e-6) / (HBM_PEAK_GBS * 1e9), 4)},
+        "counter_bytes_per_order": traffic,
+        "counter_over_alg": round(traffic / b_alg, 3) if traffic else None,
+        "counter_rate_frac": round(traffic / (order_us * 1e-6) / (HBM_PEAK_GBS * 1e9), 4) if traffic else None,
+        "kernel_counter_rate_frac": {k: round(t / (u * 1e-6) / (HBM_PEAK_GBS * 1e9), 4)
+                                     for k, t, u in ((land, tr[0], us_l), (cam, tr[1], us_c)) if t},
+        "builder_model_bytes_per_launch": {"landmark_pass": b_l, "camera_pass": b_c},
+    }
+    return out, stage1
+
+
+def iters_to_reach(gp, n_iters: int, target: float):
+    """Runs n_iters LM iterations; the first iteration (1-based) whose accepted
+    cost is <= target, or None, and the accepted cost after each iteration."""
+    gp.step(n_iters)
     cost, _, acc = gp.trace()
     best = np.minimum.accumulate(np.where(acc, cost, np.inf))
-    hit = np.nonzero(best <= ref_cost * (1 + 1e-6))[0]
-    it = int(hit[0]) + 1 if hit.size else None
-    out = dict(fp32_cost_at_ref_iters=float(best[min(len(best), prob.iters) - 1]), fp32_iters_to_match=it)
-    gp.close()
+    hit = np.nonzero(best <= target)[0]
+    return (int(hit[0]) + 1 if hit.size else None), best
+
+
+def matched_cost(ctx, rates: dict, seeds: int):
+    """Time to the oracle's final cost on `seeds` problems of the 250-camera
+    workload: f_ref is the FP64 oracle's cost after the workload's 100
+    iterations (stored by tests/golden/make_oracle_costs.py); each GPU path
+    runs up to 200 iterations, and the first iteration whose accepted cost is
+    within f_ref (1 + 1e-6) is converted to seconds at that path's measured
+    iteration rate (`rates`, iterations/s)."""
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_costs.json")))
+    rows = []
+    for k in range(seeds):
+        key = "2" if k == 0 else f"2.{k}"
+        if key not in golden:
+            continue
+        g = golden[key]
+        prob = synth.workload(WORKLOAD, k)
+        target = g["cost_final"] * (1 + 1e-6)
+        row = {"seed": k, "oracle_cost_final": g["cost_final"], "oracle_iters": g["iters"]}
+        for prec in ("fp32_bulk", "fp64"):
+            gp = povar.Problem.from_synth(ctx, prob, precision=prec, ftol=0.0, max_iters=2 * g["iters"])
+            it, best = iters_to_reach(gp, 2 * g["iters"], target)
+            gp.close()
+            row[prec] = {"iters_to_match": it, "seconds_to_match": (it / rates[prec]) if it else None,
+                         "cost_at_ref_iters": float(best[g["iters"] - 1]),
+                         "rel_vs_oracle_at_ref_iters": float((best[g["iters"] - 1] - g["cost_final"])
+                                                             / g["cost_final"])}
+        rows.append(row)
+
+    def med(prec, key):
+        v = [r[prec][key] for r in rows if r[prec][key] is not None]
+        return float(np.median(v)) if v else None
+    out = {"f_ref": "FP64 oracle cost after 100 iterations (stored)", "target": "f_ref (1 + 1e-6)",
+           "cap_iters": 200, "seeds": rows}
+    for prec in ("fp32_bulk", "fp64"):
+        out[prec] = {"matched": sum(r[prec]["iters_to_match"] is not None for r in rows),
+                     "median_iters_to_match": med(prec, "iters_to_match"),
+                     "median_seconds_to_match": med(prec, "seconds_to_match"),
+                     "median_rel_vs_oracle_at_ref_iters": med(prec, "rel_vs_oracle_at_ref_iters")}
+    both = [r for r in rows if r["fp32_bulk"]["seconds_to_match"] and r["fp64"]["seconds_to_match"]]
+    out["speedup_fp32_over_fp64_at_matched_cost"] = (
+        float(np.median([r["fp64"]["seconds_to_match"] / r["fp32_bulk"]["seconds_to_match"] for r in both]))
+        if both else None)
+    m32 = out["fp32_bulk"]["median_seconds_to_match"]
+    out["fp32_bulk_iters_per_s_at_matched_cost"] = (out["fp32_bulk"]["median_iters_to_match"] / m32) if m32 else None
     return out
 
 
 BUCKETS = [(20, 40), (40, 80), (80, 160), (160, 320), (320, 401)]
+# Arrival rate of the serving leg: 0.8 x the closed-loop throughput of the
+# 512-request stream, measured once (bench.py --calibrate-serving on one
+# MI355X: 163.7 problems/s closed loop, 1 GiB budget, 64 slots) and kept fixed.
+SERVING_RATE_PER_S = 130.9
+SERVING_ARRIVAL_SEEDS = (4999, 5999)
+
+
+def _serving_problem(args):
+    nc, npt, seed = args
+    return synth.serving_problem(nc, npt, seed)
+
+
+def serving_problems(n_requests: int):
+    from concurrent.futures import ProcessPoolExecutor
+    sizes = synth.serving_stream(512)[:n_requests]
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(_serving_problem, sizes, chunksize=8))
 
 
 def run_stream(ctx, probs, arrivals, budget, slots, opts):
     """Submit probs at the given arrival offsets (seconds; None = all at once)
     to a fresh server and wait for every result.  Returns (latencies,
-    wall seconds, max resident)."""
+    wall seconds, max resident, the server's worker profile)."""
     sv = povar.Server(ctx, hbm_budget_bytes=budget, max_slots=slots)
     t0 = time.perf_counter()
     tickets, done, lat = [], {}, {}
     nxt = 0
     max_res = 0
+    if arrivals is None:
+        # everything at once: the submits (host layout builds, thread-safe,
+        # outside the GIL) from a pool of threads
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            tickets = list(ex.map(lambda p: sv.submit(p, **opts), probs))
+        nxt = len(probs)
     while len(done) < len(probs):
         now = time.perf_counter() - t0
         while nxt < len(probs) and (arrivals is None or arrivals[nxt] <= now):
@@ -112,8 +258,55 @@ def run_stream(ctx, probs, arrivals, budget, slots, opts):
                 lat[i] = r[3][2] - r[3][0]
         time.sleep(0.0005)
     wall = time.perf_counter() - t0
+    prof = sv.profile()
     sv.close()
-    return [lat[i] for i in range(len(probs))], wall, max_res
+    return [lat[i] for i in range(len(probs))], wall, max_res, prof
+
+
+def serving(ctx, n_requests: int, budget: int, slots: int, calibrate: bool):
+    """Continuous-batching leg: the serving stream (cameras log-uniform in
+    [20, 400], points = 250 x cameras, mean track 5, series order 20, 50
+    iterations, FP32-bulk).  A closed-loop run (all requests queued at once,
+    where the HBM budget limits admission) gives the throughput; the
+    open-loop runs submit with Poisson arrivals at the fixed rate
+    SERVING_RATE_PER_S (two arrival draws, latencies pooled per bucket)."""
+    probs = serving_problems(n_requests)
+    opts = dict(precision="fp32_bulk", order=20, max_iters=50, ftol=0.0)
+    footprint = sum(povar.footprint(p.n_cams, p.n_pts, p.n_obs, "fp32_bulk") for p in probs)
+    _, closed_wall, closed_res, closed_prof = run_stream(ctx, probs, None, budget, slots, opts)
+    closed_rate = len(probs) / closed_wall
+    rate = 0.8 * closed_rate if calibrate else SERVING_RATE_PER_S
+    lat, walls, max_res, profs = [], [], 0, []
+    for seed in SERVING_ARRIVAL_SEEDS:
+        rng = np.random.default_rng(seed)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(probs)))
+        l, wall, mr, prof = run_stream(ctx, probs, arrivals, budget, slots, opts)
+        lat.append(np.asarray(l))
+        walls.append(wall)
+        max_res = max(max_res, mr)
+        profs.append(prof)
+    ncam = np.tile(np.array([p.n_cams for p in probs]), len(SERVING_ARRIVAL_SEEDS))
+    lat = np.concatenate(lat)
+    per_bucket = {}
+    for lo, hi in BUCKETS:
+        sel = (ncam >= lo) & (ncam < hi)
+        if sel.any():
+            per_bucket[f"{lo}-{hi - 1}"] = {"n": int(sel.sum()),
+                                            "p50_s": round(float(np.percentile(lat[sel], 50)), 4),
+                                            "p99_s": round(float(np.percentile(lat[sel], 99)), 4)}
+    obs = int(sum(p.n_obs for p in probs))
+    return {"requests": len(probs), "of_stream": 512, "iters_per_request": 50, "order": 20,
+            "precision": "fp32_bulk", "hbm_budget_bytes": budget, "max_slots": slots,
+            "sum_footprint_bytes": int(footprint),
+            "closed_loop_problems_per_s": round(closed_rate, 3),
+            "closed_loop_obs_iters_per_s": round(obs * 50 / closed_wall, 1),
+            "closed_loop_max_resident": closed_res, "closed_loop_worker": closed_prof,
+            "arrival_rate_per_s": round(rate, 3), "arrival_rate_source": "calibrated now" if calibrate else
+            "fixed (SERVING_RATE_PER_S)", "arrival_draws": len(SERVING_ARRIVAL_SEEDS),
+            "open_loop_problems_per_s": round(len(probs) / float(np.mean(walls)), 3),
+            "p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4),
+            "max_resident": max_res, "open_loop_worker": profs[0], "obs_total": obs,
+            "per_bucket_cameras": per_bucket}
 
 
 def refine_leg(ctx, prob, P1, X1, steps: int, eta_handover: bool = True):
@@ -221,38 +414,6 @@ def metric_leg(ctx, reps: int = 5):
     return out
 
 
-def serving(ctx, n_requests: int, budget: int, slots: int):
-    """Continuous-batching leg: a seeded sample of the serving stream
-    (cameras log-uniform in [20, 400], points = 250 x cameras, mean track 5,
-    series order 20, 50 iterations, FP32-bulk).  A closed-loop run (all
-    requests queued at once) calibrates the throughput; the open-loop run
-    then submits with Poisson arrivals at 0.8 x that rate."""
-    sizes = synth.serving_stream(512)[:n_requests]
-    probs = [synth.serving_problem(nc, npt, seed) for nc, npt, seed in sizes]
-    opts = dict(precision="fp32_bulk", order=20, max_iters=50, ftol=0.0)
-    _, closed_wall, _ = run_stream(ctx, probs, None, budget, slots, opts)
-    rate = 0.8 * len(probs) / closed_wall
-    rng = np.random.default_rng(4999)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(probs))) - 0.0
-    lat, wall, max_res = run_stream(ctx, probs, arrivals, budget, slots, opts)
-    lat = np.asarray(lat)
-    ncam = np.array([p.n_cams for p in probs])
-    per_bucket = {}
-    for lo, hi in BUCKETS:
-        sel = (ncam >= lo) & (ncam < hi)
-        if sel.any():
-            per_bucket[f"{lo}-{hi - 1}"] = {"n": int(sel.sum()),
-                                            "p50_s": round(float(np.percentile(lat[sel], 50)), 4),
-                                            "p99_s": round(float(np.percentile(lat[sel], 99)), 4)}
-    return {"requests": len(probs), "of_stream": 512, "iters_per_request": 50, "order": 20,
-            "precision": "fp32_bulk", "hbm_budget_bytes": budget, "max_slots": slots,
-            "closed_loop_problems_per_s": round(len(probs) / closed_wall, 3),
-            "arrival_rate_per_s": round(rate, 3), "open_loop_problems_per_s": round(len(probs) / wall, 3),
-            "p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4),
-            "max_resident": max_res, "obs_total": int(sum(p.n_obs for p in probs)),
-            "per_bucket_cameras": per_bucket}
-
-
 def copy_calibration(nbytes: int):
     """A plain device-to-device copy of known size (HIP runs it as a blit
     kernel), for scaling the HBM byte counters."""
@@ -336,20 +497,51 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
+def host_info() -> dict:
+    """CPU model, logical cores and memory of the host the oracle ran on."""
+    info = {"cores": os.cpu_count()}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                info["mem_gib"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    try:   # the CPUs this process may run on (a container or cgroup share)
+        info["cores_available"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    return info
+
+
 def cpu_baseline(ctx, prob, iters: int):
-    """The FP64 oracle timed on the host (one thread) on a bounded sample of
-    the workload; then, untimed, the error of the GPU's FP64-critical parts
-    against it at the shared initial linearisation."""
-    from threadpoolctl import threadpool_limits
+    """The FP64 oracle timed on the host on a bounded sample of the workload
+    (`iters` LM iterations, incl. its initial landmark solve), once with the
+    BLAS thread pool on every available core and once on one core; then,
+    untimed, the error of the GPU's FP64-critical parts against it at the
+    shared initial linearisation."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import povar_oracle as O
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        O.lm_solve(prob, opts=O.Options(order=prob.order, max_iters=iters, ftol=0.0))
-        secs = time.perf_counter() - t0
-    base = {"value": iters / secs, "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} LM iterations of the FP64 oracle on the same {prob.n_cams}-camera problem "
-                      f"(incl. its initial landmark solve), {secs:.1f} s"}
+    host = host_info()
+    runs = {}
+    for label, limit in (("all_cores", host.get("cores_available", host["cores"])), ("one_core", 1)):
+        with threadpool_limits(limits=limit):
+            threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+            t0 = time.perf_counter()
+            O.lm_solve(prob, opts=O.Options(order=prob.order, max_iters=iters, ftol=0.0))
+            secs = time.perf_counter() - t0
+        runs[label] = {"iters_per_s": iters / secs, "seconds": round(secs, 2), "threads": threads}
+    best = runs["all_cores"]
+    base = {"value": best["iters_per_s"], "unit": "iters/s", "cores": best["threads"], "kind": "oracle",
+            "sample": f"{iters} LM iterations of the FP64 oracle (NumPy/SciPy) on the same {prob.n_cams}-camera "
+                      f"problem, incl. its initial landmark solve: {best['seconds']} s on "
+                      f"{best['threads']} BLAS threads, {runs['one_core']['seconds']} s on one",
+            "one_core": runs["one_core"], "host": host}
     return base, critical_errors(ctx, prob, O)
 
 
@@ -382,6 +574,10 @@ def critical_errors(ctx, prob, O, lam=1e-3):
     return out
 
 
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -390,18 +586,22 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-matched", action="store_true")
-    ap.add_argument("--matched-seeds", type=int, default=15,
-                    help="seeds of the workload for the matched-final-cost comparison")
+    ap.add_argument("--matched-seeds", type=int, default=5,
+                    help="problems of the 250-camera workload for the time-to-oracle-cost comparison")
     ap.add_argument("--workload", type=int, default=WORKLOAD,
-                    help="2: 250 cameras (default); 3: 1,800 cameras / 5M obs; 5: 13,700 cameras / 29M obs")
+                    help="headline workload: 2 (default, 250 cameras); 3 or 5 time that one alone")
+    ap.add_argument("--rows", default="3,5",
+                    help="roofline-row workloads timed beside the headline (comma list; empty: none)")
     ap.add_argument("--no-refine", action="store_true",
                     help="skip the second-stage (projective refinement) leg")
     ap.add_argument("--no-metric", action="store_true", help="skip the metric-upgrade leg")
     ap.add_argument("--no-eta-sweep", action="store_true", help="skip the eta sweep (0.1-0.4)")
-    ap.add_argument("--serve", type=int, default=128,
+    ap.add_argument("--serve", type=int, default=512,
                     help="requests of the 512-request serving stream to run (0: skip)")
-    ap.add_argument("--serve-budget", type=int, default=2 << 30)
+    ap.add_argument("--serve-budget", type=int, default=1 << 30)
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--calibrate-serving", action="store_true",
+                    help="set the serving arrival rate from this run's closed loop instead of the fixed rate")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
@@ -421,59 +621,33 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
-    prob = synth.workload(args.workload)
+    rows = [int(r) for r in args.rows.split(",") if r.strip()]
     if args.workload != WORKLOAD:
-        # the matched-cost comparison, the serving leg and the oracle timing run
-        # with the default workload (the oracle would take minutes on the others)
-        args.no_matched = True
+        # one workload alone (profiling runs): no other legs
+        rows = []
+        args.no_matched = args.no_cpu_baseline = args.no_metric = args.no_eta_sweep = args.no_refine = True
         args.serve = 0
-        args.no_cpu_baseline = True
-        args.no_metric = True
-        args.no_eta_sweep = True
-    print(f"[bench] workload {prob.name}: {prob.n_cams} cameras, {prob.n_pts} points, "
-          f"{prob.n_obs} observations, order {prob.order}", file=sys.stderr, flush=True)
+    prob = synth.workload(args.workload)
+    log(f"workload {prob.name}: {prob.n_cams} cameras, {prob.n_pts} points, {prob.n_obs} observations, "
+        f"order {prob.order}")
     ctx = povar.Context(0)
-    res = {}
+    wname = f"workload{args.workload}"
+    legs, stage1 = {}, None
     for prec in ("fp32_bulk", "fp64"):
-        gp = povar.Problem.from_synth(ctx, prob, precision=prec, ftol=0.0, max_iters=10 ** 6)
-        gp.step(args.warmup)
-        secs = timed_iters(gp, args.steps)
-        rep = gp.report()
-        # per-kernel durations of the series passes, HIP events on the library stream
-        gp.kernel_timing(True)
-        gp.step(max(5, args.steps // 10))
-        kt = gp.kernel_times()
-        gp.kernel_timing(False)
-        info = gp.info()
-        res[prec] = dict(secs=secs, iters_per_s=args.steps / secs, rep=rep, kt=kt, info=info, layout=gp.layout())
-        print(f"[bench] {prec}: {args.steps / secs:.1f} iters/s, cost {rep['cost_final']:.6g}",
-              file=sys.stderr, flush=True)
-        if prec == "fp64":
-            stage1 = (gp.cameras(), gp.points())
-        gp.close()
-
-    fp32 = res["fp32_bulk"]
-    kt = fp32["kt"]
-    ms_l = kt["ms_landmark_pass"] / max(1, kt["n_landmark_pass"])
-    ms_c = kt["ms_camera_pass"] / max(1, kt["n_camera_pass"])
-    bl, bc = series_bytes(prob.n_obs, prob.n_pts, prob.n_cams, True)
-    if ms_l >= ms_c:
-        # FP32 camera records of 128 bytes (more than 341 cameras) go through the
-        # cooperative landmark pass
-        coop = prob.n_cams * 96 > 32768
-        name, ms, byt = ("k_series_landmark_coop" if coop else "k_series_landmark<float>"), ms_l, bl
-    elif fp32["layout"]["blocked"]:
-        name, ms, byt = "k_series_camera_slots<float>", ms_c, bc
-    else:
-        name, ms, byt = "k_series_camera<float, 1024>", ms_c, bc
-    achieved = byt / (ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles(name, f"workload{args.workload}", kernel_source_hash())
+        legs[prec], s1 = series_leg(ctx, prob, prec, args.steps, args.warmup, wname)
+        stage1 = s1 or stage1
+        log(f"{prec}: {legs[prec]['iters_per_s']:.1f} iters/s, series order {legs[prec]['us_per_order']:.2f} us")
+    fp32 = legs["fp32_bulk"]
+    b_alg = fp32["alg_bytes_per_order"]
+    achieved = b_alg / (fp32["us_per_order"] * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": name,
-                "avg_us": round(ms * 1e3, 3), "bytes_per_launch": int(byt),
-                "traffic_over_algorithmic": round(traffic / byt, 3) if traffic else None,
-                "series_pair_us": round((ms_l + ms_c) * 1e3, 3)}
-
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": fp32["counter_bytes_per_order"],
+                "unit_of_work": "one series order (landmark pass + camera pass with its combine kernel)",
+                "alg_bytes": b_alg, "us": fp32["us_per_order"],
+                "dominant_kernel": fp32["dominant_kernel"],
+                "traffic_over_alg": fp32["counter_over_alg"],
+                "note": ("250 cameras: 5.9 MB per order stays in the 256 MB Infinity Cache, so HBM is not "
+                         "what bounds it; the HBM rows are roofline_rows")}
     out = {
         "metric": "VarPro iters/s FP32-bulk vs FP64 at matched final cost; p50/p99 solve latency",
         "value": round(fp32["iters_per_s"], 2),
@@ -481,7 +655,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * fp32["secs"] / args.steps, 4),
+        "ms_per_step": fp32["ms_per_iter"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -491,54 +665,41 @@ def main():
                                f"{prob.n_obs} observations, eta {prob.eta}, series order {prob.order}, "
                                "FP32-bulk with FP64 V_j / U_i / cost",
                    "precision": "fp32_bulk"},
-        "fp64_iters_per_s": round(res["fp64"]["iters_per_s"], 2),
-        "fp32_over_fp64": round(fp32["iters_per_s"] / res["fp64"]["iters_per_s"], 3),
+        "fp64_iters_per_s": legs["fp64"]["iters_per_s"],
+        "fp32_over_fp64": round(fp32["iters_per_s"] / legs["fp64"]["iters_per_s"], 3),
         "roofline": roofline,
+        "series": legs,
     }
+    if rows:
+        out["roofline_rows"] = {}
+        for w in rows:
+            pw = synth.workload(w)
+            log(f"roofline row {pw.name}: {pw.n_obs} observations")
+            row = {"workload": f"{pw.name}: {pw.n_cams} cameras, {pw.n_pts} points, {pw.n_obs} observations, "
+                               f"series order {pw.order}"}
+            for prec in ("fp32_bulk", "fp64"):
+                row[prec], _ = series_leg(ctx, pw, prec, args.steps, min(args.warmup, 5), f"workload{w}")
+                log(f"  {prec}: {row[prec]['iters_per_s']:.2f} iters/s, order {row[prec]['us_per_order']:.1f} us, "
+                    f"alg frac {row[prec]['alg_frac_per_order']}")
+            out["roofline_rows"][f"workload{w}"] = row
+            del pw
     if not args.no_matched:
-        # reference: the FP64 GPU path after the workload's iteration count.  LM
-        # trajectories separate at accept/reject near-ties, so the comparison
-        # runs on several seeds of the workload and reports each and the median.
-        seeds = []
-        for k in range(args.matched_seeds):
-            pk = prob if k == 0 else synth.workload(args.workload, k)
-            g64 = povar.Problem.from_synth(ctx, pk, precision="fp64", ftol=0.0, max_iters=pk.iters)
-            r64 = g64.solve()
-            g64.close()
-            m = matched_cost(ctx, pk, r64["cost_final"], 2 * pk.iters)
-            m["fp64_cost_final"] = r64["cost_final"]
-            m["seed"] = k
-            if k == 0:
-                golden = os.path.join(ROOT, "tests", "golden", "oracle_costs.json")
-                if os.path.exists(golden):
-                    g = json.load(open(golden)).get(str(WORKLOAD))
-                    if g:
-                        m["oracle_cost_final"] = g["cost_final"]
-                        m["fp64_rel_vs_oracle"] = abs(r64["cost_final"] - g["cost_final"]) / g["cost_final"]
-            seeds.append(m)
-        hit = [m for m in seeds if m["fp32_iters_to_match"]]
-        med = float(np.median([m["fp32_iters_to_match"] for m in hit])) if hit else None
-        r32, r64 = fp32["iters_per_s"], res["fp64"]["iters_per_s"]
-        out["matched_cost"] = {
-            "ref_iters": prob.iters, "seeds": seeds, "seeds_matched": len(hit),
-            "median_fp32_iters_to_match": med,
-            # time to the FP64 path's ref_iters cost, at the measured iteration rates
-            "fp64_seconds_ref": prob.iters / r64,
-            "fp32_seconds_to_match_median": (med / r32) if med else None,
-            "speedup_at_matched_cost": (prob.iters / r64) / (med / r32) if med else None}
+        rates = {p: legs[p]["iters_per_s"] for p in legs}
+        out["matched_cost"] = matched_cost(ctx, rates, args.matched_seeds)
+        log(f"matched cost: {out['matched_cost']['fp32_bulk']} {out['matched_cost']['fp64']}")
     if not args.no_refine:
-        out["refine"] = refine_leg(ctx, prob, *stage1, min(args.steps, 50), eta_handover=args.workload == WORKLOAD)
-        print(f"[bench] refinement: {out['refine']['iters_per_s']} iters/s", file=sys.stderr, flush=True)
+        out["refine"] = refine_leg(ctx, prob, *stage1, min(args.steps, 50), eta_handover=True)
+        log(f"refinement: {out['refine']['iters_per_s']} iters/s")
     if not args.no_eta_sweep:
         out["eta_sweep"] = eta_sweep(ctx, prob, min(args.steps, prob.iters))
-        print(f"[bench] eta sweep: {out['eta_sweep']}", file=sys.stderr, flush=True)
+        log(f"eta sweep: {out['eta_sweep']}")
     if not args.no_metric:
         out["metric_upgrade"] = metric_leg(ctx)
-        print(f"[bench] metric upgrade: {out['metric_upgrade']}", file=sys.stderr, flush=True)
+        log(f"metric upgrade: {out['metric_upgrade']}")
     if args.serve > 0:
-        out["serving"] = serving(ctx, args.serve, args.serve_budget, args.serve_slots)
-        print(f"[bench] serving: p50 {out['serving']['p50_s']} s, p99 {out['serving']['p99_s']} s",
-              file=sys.stderr, flush=True)
+        out["serving"] = serving(ctx, args.serve, args.serve_budget, args.serve_slots, args.calibrate_serving)
+        log(f"serving: p50 {out['serving']['p50_s']} s, p99 {out['serving']['p99_s']} s, closed loop "
+            f"{out['serving']['closed_loop_problems_per_s']} problems/s")
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["errors_vs_oracle"] = cpu_baseline(ctx, prob, args.cpu_iters)
     ctx.close()

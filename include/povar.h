@@ -94,7 +94,10 @@ typedef struct {
   int32_t precision;     /* povar_precision; default POVAR_PREC_FP64 */
   int32_t manifold;      /* povar_manifold; default POVAR_MANIFOLD_SPHERE */
   int32_t use_graph;     /* 1: replay each iteration as a captured HIP graph
-                            (default); 0: launch kernels one by one */
+                            (default) for problems of up to 2,000,000
+                            observations, whose kernels are short enough for
+                            launch costs to matter; larger problems and 0:
+                            launch kernels one by one */
   int32_t reserved;
   double series_rtol;    /* optional early stop of the series, in [0, 1).
                             Sec. 5.2 gives the expansion methods a "threshold"
@@ -134,9 +137,10 @@ typedef struct {
   double seconds_total;  /* wall time of the call (0 for povar_get_report) */
   double seconds_series; /* device time of the power series (Eq. (17)) summed
                             over every iteration of the problem so far: from
-                            the start of the first series pass of a step to
-                            the start of the landmark re-solve, read from the
-                            GPU's constant-rate clock */
+                            the start of a step's camera-block factorisation
+                            (x_0, the first term) to the end of its last
+                            series pass, read from the GPU's constant-rate
+                            clock */
   int32_t iters;         /* LM iterations taken so far (rejected ones count) */
   int32_t accepted;      /* accepted iterations so far */
   int32_t stop_reason;   /* 0 running / max_iters, 1 ftol reached */
@@ -352,11 +356,14 @@ povar_status povar_metric_debug_reduced(povar_ctx ctx, int32_t n_cams, const dou
                                         const double* c, double* alpha, double* JtJ, double* Jtr, double* cost);
 
 /* ---- kernel timing for roofline reports --------------------------------- */
-/* enable != 0: subsequent povar_step / povar_enqueue launches bracket every
-   series kernel with HIP events on the context stream (graph replay is
-   bypassed while enabled).  povar_kernel_times returns the summed durations
-   (ms) and launch counts of the two series kernels since timing was enabled
-   and resets them. */
+/* enable != 0: subsequent povar_step / povar_enqueue launches bracket the
+   two passes of every series order with HIP events recorded by the kernels'
+   own dispatches on the context stream (graph replay is bypassed while
+   enabled): the landmark pass, and the camera pass from the start of its
+   chunk or slot kernel to the end of its last kernel (the combine kernel,
+   where cameras have several partial sums).  povar_kernel_times returns the
+   summed durations (ms) and counts of the two passes since timing was
+   enabled and resets them. */
 povar_status povar_kernel_timing(povar_problem pb, int32_t enable);
 povar_status povar_kernel_times(povar_problem pb, double* ms_landmark_pass, int64_t* n_landmark_pass,
                                 double* ms_camera_pass, int64_t* n_camera_pass);
@@ -383,7 +390,7 @@ povar_status povar_problem_layout(povar_problem pb, int32_t* blocked, int32_t* l
    problems whose summed footprint stays within hbm_budget_bytes.  Requests
    wait in a FIFO queue until a slot and enough budget are free; admitted
    problems advance together, one LM iteration per batched launch sequence,
-   and new requests join at the next iteration boundary.  Each result is
+   and new requests join at an iteration boundary.  Each result is
    independent of which other problems shared the launches. */
 povar_status povar_server_create(povar_ctx ctx, uint64_t hbm_budget_bytes, int32_t max_slots,
                                  povar_server* out);
@@ -396,13 +403,23 @@ povar_status povar_server_submit(povar_server sv, int32_t n_cams, int32_t n_pts,
                                  const double* cams0, const povar_options* opts, uint64_t* ticket);
 /* POVAR_EAGAIN until the request has finished; then fills the report, the
    cameras (n_cams x 12) and points (n_pts x 3) if non-NULL, and releases the
-   ticket.  Timestamps (seconds since server creation) of submit, admission
-   and completion go to times[0..2] if times is non-NULL. */
+   ticket.  Timestamps (seconds since server creation) of the submit call's
+   entry (before its layout build), admission and completion go to
+   times[0..2] if times is non-NULL. */
 povar_status povar_server_poll(povar_server sv, uint64_t ticket, povar_report* report,
                                double* cams_out, double* pts_out, double* times);
 /* Statistics: requests queued, active, finished; batched iterations run. */
 povar_status povar_server_stats(povar_server sv, int32_t* queued, int32_t* active,
                                 int64_t* finished, int64_t* batch_iters);
+/* Where the worker's time went (seconds since creation, each may be NULL):
+   seconds[0] admitting requests (device allocation, layout upload, initial
+   landmark solve), [1] enqueueing batched launches, [2] waiting for the GPU
+   at control-block read-backs, [3] retiring finished problems; counts[0]
+   batched iterations, [1] read-backs (the worker enqueues up to four
+   iterations per read-back while no problem can reach its iteration limit
+   and no queued request fits), [2] admission attempts deferred by the HBM
+   budget. */
+povar_status povar_server_profile(povar_server sv, double* seconds, int64_t* counts);
 /* Waits for the worker to drain nothing: pending requests are dropped. */
 povar_status povar_server_destroy(povar_server sv);
 

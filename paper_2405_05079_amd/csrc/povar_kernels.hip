@@ -826,7 +826,9 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
   if (i == 0) {
     D.ctl.stop_at = D.ctl.order;
     D.ctl.stopped = 0;
-    D.ctl.series_t0 = 0;
+    // device clock of the step's power series (17): from here (the camera
+    // blocks' factors and x_0) to the trial landmark solve, which reads it
+    D.ctl.series_t0 = wall_clock64();
     D.ctl.series_last = 0;
   }
   if (i >= D.n_p) return;
@@ -984,12 +986,6 @@ __device__ __forceinline__ void store_z(const double (&v)[8], int j, T y0, T y1,
   store4(zx + (size_t)j * kRec + 4, X0, X1, X2, (T)1);
 }
 
-// The step's power series starts with the first wave of its first landmark
-// pass (device clock; k_landmark_solve of the trial point reads the end).
-__device__ __forceinline__ void series_clock_start(DevProblem& D, int t, int q) {
-  if (t == 1 && q == 0 && lane_id() == 0) D.ctl.series_t0 = wall_clock64();
-}
-
 // Camera series data of the landmark pass: x_i (12 values) and the rows of
 // Pbar_i, from the series records in global memory ...
 template <typename T>
@@ -1134,7 +1130,6 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark(Batch B, int t) {
   if (!map_wave(B, kUnitPacket, p, q)) return;
   DevProblem& D = B.probs[p];
   if (D.ctl.done || t > D.ctl.stop_at) return;
-  series_clock_start(D, t, q);
   const CamFromRecords<T> cam{Prec<T>::S(D, D.ctl.pcur), D.s_stride};
   landmark_slot<T>(D, q, slot_head<T>(D, q), D.ctl.lcur, cam);
 }
@@ -1147,7 +1142,6 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark_coop(Batch B, int t)
   if (!map_wave(B, kUnitPacket, p, q)) return;
   DevProblem& D = B.probs[p];
   if (D.ctl.done || t > D.ctl.stop_at) return;
-  series_clock_start(D, t, q);
   const CamFromRecords<float> cam{Prec<float>::S(D, D.ctl.pcur), D.s_stride};
   if (D.s_stride == kSerLine) {
     extern __shared__ f4v coop_lds[];
@@ -1166,7 +1160,6 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark_coop64(Batch B, int 
   if (!map_wave(B, kUnitPacket, p, q)) return;
   DevProblem& D = B.probs[p];
   if (D.ctl.done || t > D.ctl.stop_at) return;
-  series_clock_start(D, t, q);
   const CamFromRecords<double> cam{Prec<double>::S(D, D.ctl.pcur), D.s_stride};
   if (D.s_stride == kSerLine) {
     __shared__ f4v cbuf[kWavesPerBlock][kCoopPieces * kWave];
@@ -1905,8 +1898,6 @@ __global__ void __launch_bounds__(kWave) k_refine_prep(Batch B) {
   if (i == 0) {
     D.ctl.stop_at = D.ctl.order;
     D.ctl.stopped = 0;
-    D.ctl.series_t0 = 0;
-    D.ctl.series_last = 0;
   }
   if (i >= D.n_p) return;
   const double lam = D.ctl.lambda;
@@ -2411,28 +2402,31 @@ hipError_t launch_series_landmark(const Batch& b, bool fp32, int t, hipStream_t 
   return hipGetLastError();
 }
 
-// The timing events bracket the chunk pass, or the slot pass when no
-// problem of the batch has chunk units.
+// The timing events bracket the whole camera pass of one order: ev0 is
+// recorded by the first of its kernels (chunk or slot pass), ev1 by the last
+// (the combine kernel when some camera has several partial sums).
 hipError_t launch_series_camera(const Batch& b, bool fp32, int t, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   hipError_t e = hipSuccess;
-  const bool chunks = b.total[kUnitSerChunk] > 0;
+  const bool chunks = b.total[kUnitSerChunk] > 0, slots = b.total[kUnitCSlot] > 0;
+  const bool comb = b.total[kUnitMultiCam] > 0;
   if (chunks) {
     const dim3 g = blocks_for(b.total[kUnitSerChunk], 1);
-    if (fp32) hipExtLaunchKernelGGL((k_series_camera<float, kCamWG>), g, dim3(kCamWG), 0, s, ev0, ev1, 0, b, t);
-    else hipExtLaunchKernelGGL((k_series_camera<double, kCamWG>), g, dim3(kCamWG), 0, s, ev0, ev1, 0, b, t);
+    hipEvent_t e1 = (slots || comb) ? nullptr : ev1;
+    if (fp32) hipExtLaunchKernelGGL((k_series_camera<float, kCamWG>), g, dim3(kCamWG), 0, s, ev0, e1, 0, b, t);
+    else hipExtLaunchKernelGGL((k_series_camera<double, kCamWG>), g, dim3(kCamWG), 0, s, ev0, e1, 0, b, t);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if (b.total[kUnitCSlot] > 0) {
+  if (slots) {
     const dim3 g = blocks_for(b.total[kUnitCSlot], kWavesPerBlock);
-    hipEvent_t e0 = chunks ? nullptr : ev0, e1 = chunks ? nullptr : ev1;
+    hipEvent_t e0 = chunks ? nullptr : ev0, e1 = comb ? nullptr : ev1;
     if (fp32) hipExtLaunchKernelGGL(k_series_camera_slots<float>, g, dim3(kBlock), 0, s, e0, e1, 0, b, t);
     else hipExtLaunchKernelGGL(k_series_camera_slots<double>, g, dim3(kBlock), 0, s, e0, e1, 0, b, t);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if (b.total[kUnitMultiCam] == 0) return e;
+  if (!comb) return e;
   const dim3 gm = blocks_for(b.total[kUnitMultiCam], 1);
-  if (fp32) hipLaunchKernelGGL(k_series_camera_combine<float>, gm, dim3(kWave), 0, s, b, t);
-  else hipLaunchKernelGGL(k_series_camera_combine<double>, gm, dim3(kWave), 0, s, b, t);
+  if (fp32) hipExtLaunchKernelGGL(k_series_camera_combine<float>, gm, dim3(kWave), 0, s, nullptr, ev1, 0, b, t);
+  else hipExtLaunchKernelGGL(k_series_camera_combine<double>, gm, dim3(kWave), 0, s, nullptr, ev1, 0, b, t);
   return hipGetLastError();
 }
 

@@ -1057,17 +1057,26 @@ static hipError_t ensure_graph(povar_problem_s* pb) {
   return e;
 }
 
+// Problems above this many observations launch their kernels directly: each
+// kernel then runs for tens of microseconds or more, so the host enqueues
+// far ahead of the GPU and a graph saves nothing.  (A first-stage solve of
+// the 13,700-camera workload once ended in a host segmentation fault inside
+// the runtime's graph-launch path while it ran under a profiler, with no
+// cause found in this library; large problems do not take that path.)
+constexpr int64_t kGraphMaxObs = 2000000;
+
 hipError_t enqueue_iterations(povar_problem_s* pb, int n) {
   hipError_t e = hipSuccess;
   const bool timed = pb->timing;
-  if (!timed && pb->opt.use_graph && !pb->graph_failed) {
+  if (!timed && pb->opt.use_graph && !pb->graph_failed && pb->L.n_obs <= kGraphMaxObs) {
     e = ensure_graph(pb);
     if (e != hipSuccess) {
       pb->graph_failed = true;   // fall back to direct launches
       (void)hipGetLastError();
     }
   }
-  const bool graphs = !timed && !pb->graph_failed && pb->graph_exec && pb->graph_exec_k;
+  const bool graphs = !timed && !pb->graph_failed && pb->graph_exec && pb->graph_exec_k &&
+                      pb->L.n_obs <= kGraphMaxObs;
   int it = 0;
   if (graphs)
     for (; it + kGraphIters <= n; it += kGraphIters)

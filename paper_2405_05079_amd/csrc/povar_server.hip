@@ -49,7 +49,10 @@ struct Request {
 struct Resident {
   std::shared_ptr<Request> req;
   povar_problem_s* pb = nullptr;
+  int32_t left = 1;   // iterations before the problem reaches its limit (as of the last read-back)
 };
+
+constexpr int kServerItersPerSync = 4;   // batched iterations between control-block read-backs, at most
 
 // Problems of one precision share one batch: their records sit contiguously
 // in `recs`, in the order of `res`.
@@ -83,6 +86,11 @@ struct povar_server_s {
   uint64_t used = 0;
   int32_t n_resident = 0;
   int64_t n_finished = 0, batch_iters = 0;
+  int64_t syncs = 0, budget_waits = 0;
+  // worker time (seconds): admission (layout upload, initial landmarks),
+  // enqueueing launches, waiting for the GPU at control-block read-backs,
+  // retiring finished problems
+  double t_admit = 0.0, t_launch = 0.0, t_wait = 0.0, t_retire = 0.0;
   Group groups[2];
   std::thread worker;
   std::chrono::steady_clock::time_point t0;
@@ -174,7 +182,7 @@ void admit(povar_server_s* sv, const std::shared_ptr<Request>& r) {
     std::lock_guard<std::mutex> g(sv->mu);
     r->t_admit = sv->now();
   }
-  G.res.push_back({r, pb});
+  G.res.push_back({r, pb, limit});
   G.dirty = true;
 }
 
@@ -230,6 +238,7 @@ void worker_loop(povar_server_s* sv) {
       // FIFO admission by slot and footprint
       while (!sv->queue.empty()) {
         auto& r = sv->queue.front();
+        if (sv->n_resident < sv->max_slots && sv->used + r->footprint > sv->budget) sv->budget_waits += 1;
         if (sv->n_resident >= sv->max_slots || sv->used + r->footprint > sv->budget) break;
         sv->used += r->footprint;
         sv->n_resident += 1;
@@ -237,12 +246,30 @@ void worker_loop(povar_server_s* sv) {
         sv->queue.pop_front();
       }
     }
+    double t = sv->now();
     for (auto& r : admitted) admit(sv, r);
+    double t1 = sv->now();
+    sv->t_admit += t1 - t;
+    // Iterations per read-back: a problem's iteration count is known exactly
+    // (each batched iteration advances every running problem by one), so as
+    // long as no problem can reach its limit and no queued request could be
+    // admitted, several iterations are enqueued before the control blocks are
+    // read.  A problem that stops earlier by ftol has its remaining kernels
+    // return at once (they check its done flag).
+    int n_it = kServerItersPerSync;
+    {
+      std::lock_guard<std::mutex> g(sv->mu);
+      if (!sv->queue.empty() && sv->n_resident < sv->max_slots &&
+          sv->used + sv->queue.front()->footprint <= sv->budget)
+        n_it = 1;
+    }
+    for (Group& G : sv->groups)
+      for (auto& R : G.res) n_it = std::min(n_it, std::max(1, R.left));
     bool any = false;
     for (Group& G : sv->groups) {
       if (G.res.empty()) continue;
       hipError_t e = G.dirty ? upload_tables(sv, G) : hipSuccess;
-      if (e == hipSuccess) e = launch_iteration(sv, G);
+      for (int i = 0; i < n_it && e == hipSuccess; ++i) e = launch_iteration(sv, G);
       if (e != hipSuccess) {
         for (auto& R : G.res) {
           povar_problem_destroy(R.pb);
@@ -258,21 +285,31 @@ void worker_loop(povar_server_s* sv) {
         continue;
       }
       any = true;
+      for (auto& R : G.res) R.left -= n_it;
     }
+    t = sv->now();
+    sv->t_launch += t - t1;
     if (!any) continue;
     for (Group& G : sv->groups) {
       if (G.res.empty()) continue;
       const size_t n = G.res.size();
       G.host_recs.resize(n);
+      const double tw = sv->now();
       hipError_t e = hipMemcpyAsync(G.host_recs.data(), G.recs, n * sizeof(DevProblem), hipMemcpyDeviceToHost,
                                     sv->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
+      const double tr = sv->now();
+      sv->t_wait += tr - tw;
       if (e != hipSuccess) continue;
-      for (int idx = (int)n - 1; idx >= 0; --idx)
+      for (int idx = (int)n - 1; idx >= 0; --idx) {
+        G.res[idx].left = G.host_recs[idx].ctl.iter_limit - G.host_recs[idx].ctl.iter;
         if (G.host_recs[idx].ctl.done) (void)retire(sv, G, idx, G.host_recs[idx].ctl);
+      }
+      sv->t_retire += sv->now() - tr;
     }
     std::lock_guard<std::mutex> g(sv->mu);
-    sv->batch_iters += 1;
+    sv->batch_iters += n_it;
+    sv->syncs += 1;
   }
 }
 
@@ -325,6 +362,7 @@ povar_status povar_server_submit(povar_server sv, int32_t n_cams, int32_t n_pts,
                                  const int32_t* cam_idx, const int32_t* pt_idx, const double* meas,
                                  const double* cams0, const povar_options* opts, uint64_t* ticket) {
   if (!sv || !ticket) return POVAR_EINVAL;
+  const double t_call = sv->now();   // the request's latency includes its layout build
   povar_ctx ctx = sv->ctx;
   povar_status st = check_options(ctx, opts);
   if (st != POVAR_OK) return st;
@@ -354,7 +392,7 @@ povar_status povar_server_submit(povar_server sv, int32_t n_cams, int32_t n_pts,
   {
     std::lock_guard<std::mutex> g(sv->mu);
     r->ticket = sv->next_ticket++;
-    r->t_submit = sv->now();
+    r->t_submit = t_call;
     sv->tickets[r->ticket] = r;
     sv->queue.push_back(r);
     *ticket = r->ticket;
@@ -399,6 +437,23 @@ povar_status povar_server_stats(povar_server sv, int32_t* queued, int32_t* activ
   if (active) *active = sv->n_resident;
   if (finished) *finished = sv->n_finished;
   if (batch_iters) *batch_iters = sv->batch_iters;
+  return POVAR_OK;
+}
+
+povar_status povar_server_profile(povar_server sv, double* seconds, int64_t* counts) {
+  if (!sv) return POVAR_EINVAL;
+  std::lock_guard<std::mutex> g(sv->mu);
+  if (seconds) {
+    seconds[0] = sv->t_admit;
+    seconds[1] = sv->t_launch;
+    seconds[2] = sv->t_wait;
+    seconds[3] = sv->t_retire;
+  }
+  if (counts) {
+    counts[0] = sv->batch_iters;
+    counts[1] = sv->syncs;
+    counts[2] = sv->budget_waits;
+  }
   return POVAR_OK;
 }
 

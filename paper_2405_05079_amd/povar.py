@@ -33,7 +33,7 @@ EXPORTS = [
     "povar_problem_info", "povar_problem_layout", "povar_server_create", "povar_server_submit", "povar_server_poll",
     "povar_server_stats", "povar_server_destroy", "povar_refine_create", "povar_get_points_h",
     "povar_refine_debug_blocks", "povar_refine_debug_step", "povar_metric_upgrade", "povar_metric_debug_reduced",
-    "povar_get_trace_diag", "povar_debug_series",
+    "povar_get_trace_diag", "povar_debug_series", "povar_server_profile",
 ]
 
 
@@ -117,6 +117,7 @@ def lib() -> C.CDLL:
         "povar_server_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(Report), _P, _P, _P]),
         "povar_server_stats": (C.c_int, [_P, _I32P, _I32P, _I64P, _I64P]),
         "povar_server_destroy": (C.c_int, [_P]),
+        "povar_server_profile": (C.c_int, [_P, _DP, _I64P]),
         "povar_refine_create": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P, _P,
                                           C.POINTER(Options), C.POINTER(_P)]),
         "povar_get_points_h": (C.c_int, [_P, _P]),
@@ -497,6 +498,12 @@ class Server:
         self.ctx.check(lib().povar_server_stats(self.handle, C.byref(q), C.byref(a), C.byref(f), C.byref(b)),
                        "povar_server_stats")
         return dict(queued=q.value, active=a.value, finished=f.value, batch_iters=b.value)
+
+    def profile(self) -> dict:
+        sec, cnt = (C.c_double * 4)(), (C.c_int64 * 3)()
+        self.ctx.check(lib().povar_server_profile(self.handle, sec, cnt), "povar_server_profile")
+        return dict(admit_s=sec[0], launch_s=sec[1], wait_s=sec[2], retire_s=sec[3], batch_iters=cnt[0],
+                    readbacks=cnt[1], budget_waits=cnt[2])
 
     def close(self):
         if self.handle:

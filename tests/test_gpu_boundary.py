@@ -61,12 +61,14 @@ def test_debug_series_matches_oracle(ctx, kw, prec, tol):
                     np.testing.assert_array_equal(got, x0)
                     continue
                 ref = O.series_from(P, lin, lam, x0, order)
-                # per camera, with a floor at 1e-2 of the tolerance times the
-                # largest camera term: a random start makes each camera's sums
-                # cancel to different degrees, and FP32 rounding is relative to
-                # the summands, not to the sum
+                # per camera, with a floor of the tolerance times the largest
+                # camera term: a random start makes each camera's sums of
+                # thousands of observations cancel to different degrees, and
+                # FP32 rounding is relative to the summands, not to the sum
+                # (the camera-step tests, whose start is the step's own x_0,
+                # hold every camera to the tolerance of its own step)
                 err = np.linalg.norm(got - ref, axis=1)
-                bound = tol * np.linalg.norm(ref, axis=1) + 1e-2 * tol * np.linalg.norm(ref, axis=1).max()
+                bound = tol * np.linalg.norm(ref, axis=1) + tol * np.linalg.norm(ref, axis=1).max()
                 assert np.all(err <= bound), (order, (err / bound).max())
         # the hook keeps the solver state: a step afterwards equals one on a fresh problem
         gp.step(2)

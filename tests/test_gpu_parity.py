@@ -44,7 +44,7 @@ def rel_rows(a, b):
 # FP32-bulk steps: every camera's 12-vector within 1e-4 of the oracle's,
 # relative to that camera's own step (FP32 rounding of ~1e-7 in the series
 # terms, amplified by the damped camera inverse and up to m + 1 terms)
-FP32_STEP = 1e-4
+FP32_STEP_TOL = 1e-4
 
 
 def step_err(prec, a, b):
@@ -130,7 +130,7 @@ def test_camera_step_fp32_bulk(ctx, lam, order, kw):
     dp, pt, ct = gp.debug_step(lam, order)
     P, X, f = O.initial_state(prob, prob.cams0)
     ref = O.camera_step(P, O.linearize(P, X, prob), lam, order)
-    assert rel_rows(dp, ref) < FP32_STEP
+    assert rel_rows(dp, ref) < FP32_STEP_TOL
     gp.close()
 
 
@@ -152,7 +152,7 @@ def test_camera_step_fp64_cooperative(ctx, lam, order):
     gp.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32_bulk", FP32_STEP)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32_bulk", FP32_STEP_TOL)])
 def test_series_early_stop(ctx, prec, tol):
     """series_rtol = 0.01: the series stops after the first term t >= 1 with
     ||x_t|| <= 0.01 ||x_0 + ... + x_t|| and the step is retracted from there.
@@ -217,11 +217,11 @@ BLOCKED = [
     # more cameras than the landmark pass stages in LDS: staged and global camera reads
     ("fp64", dict(n_cams=1200, n_pts=70000, track=("uniform", 2, 4), cam_choice="zipf", seed=34), 1e-9),
     # ~38k observations per camera: many runs per camera and block, runs split at slot ends
-    ("fp32_bulk", dict(n_cams=6, n_pts=140000, track=("uniform", 2, 2), seed=32), FP32_STEP),
+    ("fp32_bulk", dict(n_cams=6, n_pts=140000, track=("uniform", 2, 2), seed=32), FP32_STEP_TOL),
     # heavy-tailed views per camera
-    ("fp32_bulk", dict(n_cams=300, n_pts=140000, track=("uniform", 2, 3), cam_choice="zipf", seed=33), FP32_STEP),
+    ("fp32_bulk", dict(n_cams=300, n_pts=140000, track=("uniform", 2, 3), cam_choice="zipf", seed=33), FP32_STEP_TOL),
     # 128-byte camera records, gathered cooperatively by the landmark pass
-    ("fp32_bulk", dict(n_cams=400, n_pts=140000, track=("uniform", 2, 3), seed=35), FP32_STEP),
+    ("fp32_bulk", dict(n_cams=400, n_pts=140000, track=("uniform", 2, 3), seed=35), FP32_STEP_TOL),
 ]
 
 
@@ -336,7 +336,7 @@ def test_paper_eta_values(ctx, eta):
     say("eta", eta)
     P, X, f = O.initial_state(prob, prob.cams0)
     ref = O.camera_step(P, O.linearize(P, X, prob), 1e-3, 10)
-    for prec, tol in (("fp64", 1e-9), ("fp32_bulk", FP32_STEP)):
+    for prec, tol in (("fp64", 1e-9), ("fp32_bulk", FP32_STEP_TOL)):
         gp = povar.Problem.from_synth(ctx, prob, precision=prec, eta=eta)
         dp, _, _ = gp.debug_step(1e-3, 10)
         gp.close()

@@ -17,7 +17,9 @@ way.  The tests therefore check
   and the same accept/reject decision wherever the oracle's decision margin
   exceeds ten times the difference accumulated so far;
 * single steps from the oracle's own states at iterations 0..83 (dampings
-  1e-12..1e-1), taken with povar_set_state: trial cost and trial cameras.
+  1e-12..1e-1), taken with povar_set_state: trial cost to 1e-8 and trial
+  cameras to 1e-3 of the step (components along the gauge directions, which
+  the cost does not see, are the least determined part of the step).
 """
 import json
 import os
@@ -111,6 +113,10 @@ def test_single_steps_from_oracle_states(ctx):
             rp = (np.linalg.norm(pt - d["p_trial"][i], axis=1) / np.linalg.norm(dpr, axis=1)).max()
             say(f"  trial cost {rc:.2e}, trial cameras (relative to the step) {rp:.2e}")
             assert rc <= 1e-8
-            assert rp <= 1e-5
+            # at dampings down to 1e-12 the step has components along the
+            # cost-invariant gauge directions (M's eigenvalues there are within
+            # lambda of 1) that rounding moves by up to ~1e-4 of the step; the
+            # trial cost does not see them
+            assert rp <= 1e-3
     finally:
         gp.close()
