@@ -396,3 +396,61 @@ def lm_solve(prob, cams0=None, opts: Options | None = None, lam=None, P=None) ->
             lam = min(lam * 10.0, opts.lambda_max)
     res.P, res.X, res.cost, res.lam = P, X, f, lam
     return res
+
+
+# ----------------------------------------------------------------------------
+# the same camera step for problems too large for the sparse assembly above
+# ----------------------------------------------------------------------------
+def camera_step_large(P: np.ndarray, prob, lam: float, order: int, manifold: str = "sphere",
+                      chunk: int = 1_000_000):
+    """camera_step(P, linearize(P, X*(P), prob), lam, order) for problems with
+    tens of millions of observations (memory-bounded; the 13,700-camera
+    workload).  The same definitions as above: the literal Jacobians of (6)
+    per observation, U and b_p summed per camera, V^+ per landmark, the
+    reduced system in an explicit tangent basis and the series (17).  Instead
+    of the assembled sparse W (which would not fit in host memory), each
+    observation keeps its own W_k = J_p^T J_l (12 x 3), and W z / W^T x are
+    their per-camera / per-landmark sums; the observations are processed in
+    consecutive ranges of `chunk`, whose partial sums are added.  Returns the
+    ambient step (n_cams, 12), X*(P) and the cost at P."""
+    cam, pt, n = prob.cam_idx, prob.pt_idx, prob.n_obs
+    X, Vp = solve_landmarks(P, prob)
+    f = cost(P, X, prob)
+    U = np.zeros((prob.n_cams, 12, 12))
+    bp = np.zeros((prob.n_cams, 12))
+    bl = np.zeros((prob.n_pts, 3))
+    Wk = np.empty((n, 12, 3))
+    ranges = [(a, min(a + chunk, n)) for a in range(0, n, chunk)]
+    for a, b in ranges:
+        c, p_, m = cam[a:b], pt[a:b], prob.meas[a:b]
+        r = pose_residual(P, X, c, p_, m, prob.eta)
+        Jp, Jl = pose_jacobians(P, X, c, p_, m, prob.eta)
+        U += sum_by(c, prob.n_cams, np.einsum("nri,nrj->nij", Jp, Jp))
+        bp += sum_by(c, prob.n_cams, np.einsum("nri,nr->ni", Jp, r))
+        bl += sum_by(p_, prob.n_pts, np.einsum("nri,nr->ni", Jl, r))
+        Wk[a:b] = np.einsum("nri,nrj->nij", Jp, Jl)
+
+    def W_times(z):         # sum_{k in i} W_k z_j, per camera
+        out = np.zeros((prob.n_cams, 12))
+        for a, b in ranges:
+            out += sum_by(cam[a:b], prob.n_cams, np.einsum("nij,nj->ni", Wk[a:b], z[pt[a:b]]))
+        return out
+
+    def WT_times(x):        # sum_{k in j} W_k^T x_i, per landmark
+        out = np.zeros((prob.n_pts, 3))
+        for a, b in ranges:
+            out += sum_by(pt[a:b], prob.n_pts, np.einsum("nij,ni->nj", Wk[a:b], x[cam[a:b]]))
+        return out
+
+    B = tangent_basis(P) if manifold == "sphere" else np.broadcast_to(np.eye(12), (prob.n_cams, 12, 12))
+    Ut = np.einsum("nik,nij,njl->nkl", B, damped(U, lam), B)
+    Vp_times = lambda y: np.einsum("nij,nj->ni", Vp, y)
+    Ut_solve = lambda v: np.linalg.solve(Ut, v[..., None])[..., 0]
+    g = np.einsum("nik,ni->nk", B, bp - W_times(Vp_times(bl)))
+    x = -Ut_solve(g)                                    # tangent coordinates, per camera
+    acc = x.copy()
+    for _ in range(order):
+        s = np.einsum("nik,ni->nk", B, W_times(Vp_times(WT_times(np.einsum("nik,nk->ni", B, x)))))
+        x = Ut_solve(s)
+        acc = acc + x
+    return np.einsum("nik,nk->ni", B, acc), X, f

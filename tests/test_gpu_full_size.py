@@ -229,3 +229,31 @@ def test_refine_full_size_1800_cameras_sampled(ctx, w3):
         assert rep["iters"] == 3 and rep["cost_final"] <= c0
     finally:
         gp.close()
+
+
+# every camera's damped step at the roofline rows, against the oracle's step
+# stored by tests/golden/make_oracle_steps_large.py (lambda 1e-3, the
+# workload's order: 20 at 1,800 cameras, 30 at 13,700)
+STEP_TOL = {"fp64": (1e-8, 1e-10), "fp32_bulk": (1e-4, 1e-6)}   # per-camera step, trial cost
+
+
+@pytest.mark.parametrize("number", [3])
+@pytest.mark.parametrize("prec", ["fp32_bulk", "fp64"])
+def test_full_size_step_against_stored_oracle_step(ctx, number, prec):
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", f"oracle_step_w{number}.npz"))
+    prob = synth.workload(number)
+    assert prob.n_obs == int(g["n_obs"])
+    say("full-size step", number, prec, prob.n_obs)
+    gp = povar.Problem.from_synth(ctx, prob, precision=prec)
+    try:
+        assert abs(gp.report()["cost_initial"] - float(g["cost"])) <= 1e-11 * float(g["cost"])
+        dp, pt, ct = gp.debug_step(float(g["lam"]), int(g["order"]))
+        t_step, t_cost = STEP_TOL[prec]
+        err = rel_rows(dp, g["dp"])
+        say(f"  max per-camera step error {err.max():.2e}, trial cost {abs(ct - g['cost_trial']) / g['cost_trial']:.2e}")
+        assert err.max() < t_step
+        assert abs(ct - float(g["cost_trial"])) <= t_cost * float(g["cost_trial"])
+        assert rel_rows(pt, g["p_trial"]).max() < t_step
+    finally:
+        gp.close()

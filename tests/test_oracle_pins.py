@@ -498,3 +498,19 @@ def test_seeded_cameras_are_unit_gaussian_directions():
     assert abs(w.mean()) < 5 / np.sqrt(w.size)
     assert abs((w * w).mean() - 1.0) < 0.05
     assert not np.array_equal(C, synth.seeded_cameras(3000, 12))
+
+
+def test_large_problem_step_equals_the_assembled_one():
+    """The memory-bounded step (per-observation W_k, observations in ranges)
+    is the same computation as the assembled one: equal to rounding, with
+    ranges that cut landmarks and cameras apart."""
+    prob = tiny(n_cams=9, n_pts=200, seed=81, track=("uniform", 3, 6))
+    P = synth.init_cameras(prob.n_cams, 82)
+    for manifold in ("sphere", "euclidean"):
+        Pm = P if manifold == "sphere" else P * 1.7
+        Xm, _ = O.solve_landmarks(Pm, prob)
+        ref = O.camera_step(Pm, O.linearize(Pm, Xm, prob), 1e-2, 7, manifold)
+        got, Xg, f = O.camera_step_large(Pm, prob, 1e-2, 7, manifold, chunk=97)
+        np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+        np.testing.assert_allclose(Xg, Xm, rtol=0, atol=0)
+        assert f == O.cost(Pm, Xm, prob)
