@@ -31,7 +31,7 @@
 // Second stage, objective (7) with both blocks on their spheres (Sec. 4.3):
 //   k_refine_landmarks     V_j, b_l, G_j (projected damped inverse), z0, cost
 //   k_refine_cameras       U_i, b_p, sum W z0 per camera chunk
-//   k_refine_prep          damping, Cholesky, K_i (KKT form), x_0
+//   k_refine_prep          damping, K_i in a Householder tangent basis, x_0
 //   k_refine_series_landmark / _camera / _camera_slots / _combine / _check
 //                          the series (29) and its optional early stop
 //   k_refine_landmark_update  back-substitution and landmark retraction
@@ -1616,9 +1616,12 @@ __global__ void __launch_bounds__(kBlock) k_decide(Batch B) {
 // both retracted (Sec. 4.3).  FP64.  With y = P X, iw = 1 / y2 and
 // u = (y0 iw, y1 iw):  d pi / d y = iw [[1, 0, -u0], [0, 1, -u1]],
 // J_l = (d pi / d y) P (2 x 4) and J_p[r][4a + c] = (d pi / d y)[r][a] X_c.
-// Tangent projections are applied in the KKT form (ambient coordinates):
-// K_i = U_l^-1 - w w^T / (p^T w), w = U_l^-1 p, and likewise
-// G_j = V_l^-1 - v v^T / (x^T v), v = V_l^-1 x, for the landmark blocks.
+// Tangent projections in an explicit orthonormal basis of each tangent
+// space (the last columns of the Householder reflection that maps the point
+// to a coordinate axis): K_i = B (B^T U_l B)^-1 B^T and G_j likewise, applied
+// in ambient coordinates.  Both blocks are singular along their own point up
+// to the damping, so the constrained (KKT) form through U_l^-1 would cancel
+// terms of size 1 / lambda.
 struct Proj2 {
   double iw, u0, u1;
   double jl0[4], jl1[4];   // rows of J_l
@@ -1725,19 +1728,43 @@ __device__ __forceinline__ void refine_lm_finish(DevProblem& D, int j, const dou
   v[4] += lam * fmax(v[4], 1e-12 * dmax);
   v[7] += lam * fmax(v[7], 1e-12 * dmax);
   v[9] += lam * fmax(v[9], 1e-12 * dmax);
+  // G = B (B^T V_l B)^-1 B^T with B the last three columns of the
+  // Householder reflection H = I - beta h h^T that maps X to -+e_0 (an
+  // orthonormal basis of the tangent space at X): A = H V_l H, whose lower
+  // right 3 x 3 block is inverted (row and column 0 replaced by those of the
+  // identity), then G = H diag(0, A_33^-1) H.  V_l is singular along X up to
+  // the damping (the landmark's scale does not change the residual), so the
+  // inverse of V_l itself would carry 1 / lambda along X; the 3 x 3 block
+  // has no such direction.
+  double hv[4] = {X[0] + (X[0] >= 0.0 ? 1.0 : -1.0), X[1], X[2], X[3]};
+  const double beta = 2.0 / (hv[0] * hv[0] + hv[1] * hv[1] + hv[2] * hv[2] + hv[3] * hv[3]);
+  double u[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+    u[a] = v[sym4(a, 0)] * hv[0] + v[sym4(a, 1)] * hv[1] + v[sym4(a, 2)] * hv[2] + v[sym4(a, 3)] * hv[3];
+  const double hu = hv[0] * u[0] + hv[1] * u[1] + hv[2] * u[2] + hv[3] * u[3];
+  double A[10];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = a; b < 4; ++b)
+      A[sym4(a, b)] = v[sym4(a, b)] - beta * (hv[a] * u[b] + u[a] * hv[b]) + beta * beta * hu * hv[a] * hv[b];
+  A[sym4(0, 0)] = 1.0;
+  A[sym4(0, 1)] = A[sym4(0, 2)] = A[sym4(0, 3)] = 0.0;
   double vi[10];
-  const bool ok = sym4_inv(v, vi);
+  const bool ok = sym4_inv(A, vi);
+  vi[sym4(0, 0)] = 0.0;   // diag(0, A_33^-1)
   double w[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
-    w[a] = vi[sym4(a, 0)] * X[0] + vi[sym4(a, 1)] * X[1] + vi[sym4(a, 2)] * X[2] + vi[sym4(a, 3)] * X[3];
-  const double xw = X[0] * w[0] + X[1] * w[1] + X[2] * w[2] + X[3] * w[3];
-  const double ixw = 1.0 / xw;
+    w[a] = vi[sym4(a, 0)] * hv[0] + vi[sym4(a, 1)] * hv[1] + vi[sym4(a, 2)] * hv[2] + vi[sym4(a, 3)] * hv[3];
+  const double hw = hv[0] * w[0] + hv[1] * w[1] + hv[2] * w[2] + hv[3] * w[3];
   double G[10];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = a; b < 4; ++b) G[sym4(a, b)] = vi[sym4(a, b)] - w[a] * w[b] * ixw;
+    for (int b = a; b < 4; ++b)
+      G[sym4(a, b)] = vi[sym4(a, b)] - beta * (hv[a] * w[b] + w[a] * hv[b]) + beta * beta * hw * hv[a] * hv[b];
   double* go = D.g2 + (size_t)j * kG2;
 #pragma unroll
   for (int k = 0; k < 10; ++k) go[k] = G[k];
@@ -1750,7 +1777,7 @@ __device__ __forceinline__ void refine_lm_finish(DevProblem& D, int j, const dou
   double* zo = static_cast<double*>(D.zx) + (size_t)j * kRec;
   store4(zo, z0[0], z0[1], z0[2], z0[3]);
   store4(zo + 4, X[0], X[1], X[2], X[3]);
-  if (!(ok && xw > 0.0)) atomicOr(&D.ctl.status, 1);
+  if (!ok) atomicOr(&D.ctl.status, 1);
 }
 
 // k_refine_landmarks: per landmark V_j, b_l, G_j and z0 at the current point,
@@ -1886,8 +1913,8 @@ __device__ __forceinline__ int refine_gsel(int a, int a2) {
 }
 
 // k_refine_prep: one lane per camera.  U_i from the chunk sums, Marquardt
-// damping, Cholesky, the tangent inverse K_i (KKT form), g_i = b_p - sum W z0,
-// x0 = acc = -K_i g_i.
+// damping, the tangent inverse K_i (Householder basis, Cholesky of the 11 x 11
+// block), g_i = b_p - sum W z0, x0 = acc = -K_i g_i.
 __global__ void __launch_bounds__(kWave) k_refine_prep(Batch B) {
   int p, w;
   if (!map_wave<kWave>(B, kUnitCamWave, p, w)) return;
@@ -1922,8 +1949,40 @@ __global__ void __launch_bounds__(kWave) k_refine_prep(Batch B) {
   for (int r = 0; r < 12; ++r) dmax = fmax(dmax, L[tri(r, r)]);
 #pragma unroll
   for (int r = 0; r < 12; ++r) L[tri(r, r)] += lam * fmax(L[tri(r, r)], 1e-12 * dmax);
+  // K = B (B^T U_l B)^-1 B^T with B the last eleven columns of the
+  // Householder reflection H = I - beta h h^T mapping p to -+e_0: A = H U_l H
+  // (a rank-two update of U_l), its lower right 11 x 11 block factored with
+  // row and column 0 replaced by those of the identity, then
+  // K = H diag(0, A_11^-1) H.  U_l is singular along p up to the damping (a
+  // camera's scale does not change the residual), so the inverse of U_l
+  // itself would carry 1 / lambda along p; the 11 x 11 block has no such
+  // direction.
   double pv[12];
   load12((D.ctl.pcur ? D.P64[1] : D.P64[0]) + (size_t)i * kCam, pv);
+  pv[0] += pv[0] >= 0.0 ? 1.0 : -1.0;   // pv is now h (p has unit norm)
+  double beta;
+  {
+    double hh = 0.0;
+#pragma unroll
+    for (int r = 0; r < 12; ++r) hh += pv[r] * pv[r];
+    beta = 2.0 / hh;
+    double u[12], hu = 0.0;
+#pragma unroll
+    for (int r = 0; r < 12; ++r) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) t += L[r >= k ? tri(r, k) : tri(k, r)] * pv[k];
+      u[r] = t;
+      hu += pv[r] * t;
+    }
+#pragma unroll
+    for (int r = 0; r < 12; ++r)
+#pragma unroll
+      for (int c = 0; c <= r; ++c)
+        L[tri(r, c)] += -beta * (pv[r] * u[c] + u[r] * pv[c]) + beta * beta * hu * pv[r] * pv[c];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) L[tri(c, 0)] = c == 0 ? 1.0 : 0.0;
+  }
   bool ok = true;
   double rd[12];
 #pragma unroll
@@ -1954,7 +2013,8 @@ __global__ void __launch_bounds__(kWave) k_refine_prep(Batch B) {
       L[tri(r, j)] = -v * rd[r];
     }
   }
-  double wp[12], h = 0.0;
+  // w = diag(0, A_11^-1) h = L^-T L^-1 h - h_0 e_0 (the inverse holds 1 at (0, 0))
+  double wp[12], hw = 0.0;
   {
     double u[12];
 #pragma unroll
@@ -1963,7 +2023,6 @@ __global__ void __launch_bounds__(kWave) k_refine_prep(Batch B) {
 #pragma unroll
       for (int k = 0; k <= r; ++k) v += L[tri(r, k)] * pv[k];
       u[r] = v;
-      h += v * v;
     }
 #pragma unroll
     for (int r = 0; r < 12; ++r) {
@@ -1972,8 +2031,10 @@ __global__ void __launch_bounds__(kWave) k_refine_prep(Batch B) {
       for (int k = r; k < 12; ++k) v += L[tri(k, r)] * u[k];
       wp[r] = v;
     }
+    wp[0] -= pv[0];
+#pragma unroll
+    for (int r = 0; r < 12; ++r) hw += pv[r] * wp[r];
   }
-  const double ih = 1.0 / h;
   double gv[12], x0[12];
 #pragma unroll
   for (int r = 0; r < 12; ++r) {
@@ -1986,10 +2047,10 @@ __global__ void __launch_bounds__(kWave) k_refine_prep(Batch B) {
   for (int r = 0; r < 12; ++r) {
 #pragma unroll
     for (int c = 0; c <= r; ++c) {
-      double v = 0.0;
+      double v = (r == 0 && c == 0) ? -1.0 : 0.0;   // the (0, 0) entry of diag(0, A_11^-1)
 #pragma unroll
       for (int k = r; k < 12; ++k) v += L[tri(k, r)] * L[tri(k, c)];
-      v -= wp[r] * wp[c] * ih;
+      v += -beta * (pv[r] * wp[c] + wp[r] * pv[c]) + beta * beta * hw * pv[r] * pv[c];
       if (!ok) v = 0.0;
       K64[r * 12 + c] = v;
       K64[c * 12 + r] = v;

@@ -234,3 +234,37 @@ def test_refine_rejects_invalid_use(ctx):
         np.testing.assert_allclose(s1.points_h()[:, 3], 1.0)
     finally:
         s1.close()
+
+
+def rel_rows(a, b):
+    a, b = np.asarray(a).reshape(len(a), -1), np.asarray(b).reshape(len(b), -1)
+    return (np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)).max()
+
+
+@pytest.mark.parametrize("lam", [1e-8, 1e-10, 1e-12])
+@pytest.mark.parametrize("kw", [CASES[0], CASES[1], CASES[5]], ids=["small", "7-cameras", "blocked"])
+def test_refine_blocks_and_steps_at_small_damping(ctx, kw, lam):
+    """The damped landmark and camera blocks are singular along their own
+    point up to lambda; their tangent-space inverses, formed in an explicit
+    basis, must keep rounding-level agreement with the oracle's (which inverts
+    B^T V B in an explicit basis too) down to the smallest damping: every
+    landmark's G_j and every camera's step."""
+    prob = synth.make_problem(**kw)
+    P, X = start(prob, 9)
+    say("refine small damping", kw, lam)
+    gp = refine(ctx, prob, P, X)
+    try:
+        d = gp.refine_blocks(lam)
+        lin = R.linearize(P, X, prob)
+        rs = R.riemannian_system(P, X, lin, lam)
+        G = np.einsum("nai,nij,nbj->nab", rs.Bl, np.linalg.inv(rs.Vt), rs.Bl)
+        assert rel_rows(d["G"], G) < 1e-9, rel_rows(d["G"], G)
+        for order in (0, 10):
+            dp, pt, xt, ct = gp.refine_step(lam, order)
+            dP, dX = R.step(P, X, lin, lam, order)
+            Pn, Xn = R.retract(P, dP), R.retract(X, dX)
+            assert rel(dp, dP) < 1e-8, (order, rel(dp, dP))
+            assert rel(xt, Xn) < 1e-9
+            assert abs(ct - R.cost(Pn, Xn, prob)) / R.cost(Pn, Xn, prob) < 1e-8
+    finally:
+        gp.close()
