@@ -350,6 +350,24 @@ povar_status povar_metric_upgrade(povar_ctx ctx, int32_t n_cams, const double* c
                                   int32_t max_iters, double ftol, double* H, double* c, double* alpha,
                                   double* R, double* t, double* trace_cost, int32_t* trace_accept,
                                   povar_metric_report* report);
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   call as povar_metric_upgrade, with the same arguments, results and errors,
+   but every device buffer of the call is carved from a static scratch array
+   of 8 MiB per GPU instead of being allocated; it calls no hipMalloc or
+   hipFree (nor any other allocating routine).  The call needs about
+   n_cams x 368 + max_iters x 12 bytes (plus 80 bytes of partial sums per
+   256 cameras and 256-byte alignment of each buffer), at most 8 MiB: up to
+   22,700 cameras at 1,000 iterations; larger calls return POVAR_EINVAL with
+   the bytes needed.
+   The array of a GPU is shared by every call on it and keeps the last call's
+   contents (each call initialises what it reads): calls that overlap on one
+   GPU (two threads, or two contexts on one device) race and must not be
+   issued.  POVAR_ESTATE if ctx was not made by povar_ctx_create. */
+povar_status povar_metric_upgrade_noalloc(povar_ctx ctx, int32_t n_cams, const double* cams, const double* K,
+                                          int32_t max_iters, double ftol, double* H, double* c, double* alpha,
+                                          double* R, double* t, double* trace_cost, int32_t* trace_accept,
+                                          povar_metric_report* report);
 /* Test hook: the reduced problem at a given c (3 values): alpha (n_cams),
    J^T J (9, row-major 3 x 3), J^T r (3) and the cost. */
 povar_status povar_metric_debug_reduced(povar_ctx ctx, int32_t n_cams, const double* cams, const double* K,

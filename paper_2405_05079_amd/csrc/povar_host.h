@@ -126,6 +126,10 @@ hipError_t enqueue_iteration(povar_problem_s* pb, bool timed);
 hipError_t enqueue_iterations(povar_problem_s* pb, int n);
 // grad_norm: the report's grad_norm_final (NaN when not computed)
 void fill_report(const povar_problem_s* pb, const Ctl& c, double seconds, double grad_norm, povar_report* r);
+// Device address of the no-allocation metric upgrade's scratch array on
+// ctx's device, looked up once per device (povar_ctx_create calls it with
+// that device current).
+povar_status metric_scratch_init(povar_ctx ctx);
 // Seeded initial cameras (the init_seed field of povar_options): n x 12,
 // caller's order, unit norm.
 void seeded_cameras(uint64_t seed, int32_t n, double* out);

@@ -31,10 +31,49 @@
 #include <cstring>
 #include <vector>
 
+#include <map>
+#include <mutex>
+
 #include "povar.h"
 #include "povar_host.h"
 
+// Device scratch of povar_metric_upgrade_noalloc: every buffer of one call
+// (control block, camera copies, per-block partials, outputs, traces) is
+// carved from this array instead of being allocated.  Each GPU the library
+// runs on holds its own copy until the process ends; calls that overlap on
+// one GPU share it and race.  In host code `scratch` names a host-side
+// stand-in: its device address comes from hipGetSymbolAddress, once per
+// device (metric_scratch_init), and only that address is used.
+static constexpr size_t kMetricScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kMetricScratchBytes];
+
 namespace povar {
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_addr;   // device -> address of `scratch` there
+
+// The scratch address of a device (nullptr until metric_scratch_init ran on it).
+char* metric_scratch(int device) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  return it == g_scratch_addr.end() ? nullptr : it->second;
+}
+}  // namespace
+
+povar_status metric_scratch_init(povar_ctx ctx) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_addr.count(ctx->device)) return POVAR_OK;
+  void* ptr = nullptr;   // ctx->device is current (povar_ctx_create)
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    set_error(ctx, "hipGetSymbolAddress of the metric-upgrade scratch failed: %s", hipGetErrorString(e));
+    return POVAR_EDEVICE;
+  }
+  g_scratch_addr[ctx->device] = static_cast<char*>(ptr);
+  return POVAR_OK;
+}
+
 namespace {
 
 constexpr int kMBlock = 256;
@@ -397,17 +436,28 @@ __global__ void __launch_bounds__(kMBlock) k_metric_finish(MetricArgs a) {
 
 size_t align_256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Device buffers of one call, freed by the destructor.
+// Device buffers of one call: allocated per call (owned, freed by the
+// destructor), or carved from the device's scratch array (not owned).
 struct MetricRun {
   void* mem = nullptr;
+  bool owned = false;
   MetricArgs a{};
   ~MetricRun() {
-    if (mem) (void)hipFree(mem);
+    if (mem && owned) (void)hipFree(mem);
   }
 };
 
+// Bytes of device memory a call needs for n cameras and max_iters iterations.
+size_t metric_bytes(int32_t n, int32_t max_iters) {
+  const int32_t blocks = (n + kMBlock - 1) / kMBlock;
+  const int32_t tr = max_iters > 0 ? max_iters : 1;
+  return align_256(sizeof(MetricCtl)) + 2 * align_256((size_t)n * 12 * 8) + align_256((size_t)n * 9 * 8) +
+         align_256((size_t)blocks * kMVals * 8) + align_256((size_t)n * 8) + align_256((size_t)n * 9 * 8) +
+         align_256((size_t)n * 3 * 8) + align_256((size_t)tr * 8) + align_256((size_t)tr * 4);
+}
+
 povar_status metric_setup(povar_ctx ctx, int32_t n, const double* cams, const double* K, int32_t max_iters,
-                          double ftol, MetricRun& run) {
+                          double ftol, MetricRun& run, char* scratch_base) {
   if (n < 2) {
     set_error(ctx, "the metric upgrade needs at least two cameras (got %d)", n);
     return POVAR_EINVAL;
@@ -447,10 +497,21 @@ povar_status metric_setup(povar_ctx ctx, int32_t n, const double* cams, const do
                b_a = align_256((size_t)n * 8), b_R = align_256((size_t)n * 9 * 8), b_t = align_256((size_t)n * 3 * 8),
                b_tc = align_256((size_t)tr * 8), b_ta = align_256((size_t)tr * 4);
   const size_t total = b_ctl + 2 * b_P + b_K + b_part + b_a + b_R + b_t + b_tc + b_ta;
-  if (hipMalloc(&run.mem, total) != hipSuccess) {
-    run.mem = nullptr;
-    set_error(ctx, "hipMalloc of %zu bytes for the metric upgrade failed", total);
-    return POVAR_ENOMEM;
+  if (scratch_base) {
+    if (total > kMetricScratchBytes) {
+      set_error(ctx, "%d cameras and %d iterations need %zu bytes of device memory; the no-allocation metric "
+                "upgrade has %zu bytes of scratch per device", n, max_iters, total, kMetricScratchBytes);
+      return POVAR_EINVAL;
+    }
+    run.mem = scratch_base;
+    run.owned = false;
+  } else {
+    if (hipMalloc(&run.mem, total) != hipSuccess) {
+      run.mem = nullptr;
+      set_error(ctx, "hipMalloc of %zu bytes for the metric upgrade failed", total);
+      return POVAR_ENOMEM;
+    }
+    run.owned = true;
   }
   char* p = static_cast<char*>(run.mem);
   MetricArgs& a = run.a;
@@ -494,19 +555,11 @@ povar_status metric_setup(povar_ctx ctx, int32_t n, const double* cams, const do
   return POVAR_OK;
 }
 
-}  // namespace
-}  // namespace povar
-
-using namespace povar;
-
-extern "C" povar_status povar_metric_upgrade(povar_ctx ctx, int32_t n_cams, const double* cams, const double* K,
-                                             int32_t max_iters, double ftol, double* H, double* c, double* alpha,
-                                             double* R, double* t, double* trace_cost, int32_t* trace_accept,
-                                             povar_metric_report* rep) {
-  if (!ctx) return POVAR_EINVAL;
-  MetricRun run;
-  povar_status st = metric_setup(ctx, n_cams, cams, K, max_iters, ftol, run);
-  if (st != POVAR_OK) return st;
+// The LM iterations, the final pass and the copies of the results into the
+// caller's host buffers, for a run set up by metric_setup.
+povar_status metric_solve(povar_ctx ctx, MetricRun& run, int32_t n_cams, int32_t max_iters, double* H, double* c,
+                          double* alpha, double* R, double* t, double* trace_cost, int32_t* trace_accept,
+                          povar_metric_report* rep) {
   MetricArgs& a = run.a;
   hipStream_t s = ctx->stream;
   // iterations in groups of 8 between reads of the stop flag; every kernel
@@ -543,17 +596,15 @@ extern "C" povar_status povar_metric_upgrade(povar_ctx ctx, int32_t n_cams, cons
   if (alpha) M_TRY(ctx, hipMemcpyAsync(alpha, a.alpha, n * 8, hipMemcpyDeviceToHost, s));
   if (R) M_TRY(ctx, hipMemcpyAsync(R, a.R, n * 9 * 8, hipMemcpyDeviceToHost, s));
   if (t) M_TRY(ctx, hipMemcpyAsync(t, a.t, n * 3 * 8, hipMemcpyDeviceToHost, s));
-  std::vector<double> tc(max_iters > 0 ? max_iters : 1);
-  std::vector<int32_t> ta(tc.size());
-  M_TRY(ctx, hipMemcpyAsync(tc.data(), a.tr_cost, tc.size() * 8, hipMemcpyDeviceToHost, s));
-  M_TRY(ctx, hipMemcpyAsync(ta.data(), a.tr_acc, ta.size() * 4, hipMemcpyDeviceToHost, s));
+  M_TRY(ctx, hipStreamSynchronize(s));
+  // the first C.iters trace entries (C.iters <= max_iters, the buffers' size)
+  if (C.iters > 0 && trace_cost)
+    M_TRY(ctx, hipMemcpyAsync(trace_cost, a.tr_cost, (size_t)C.iters * 8, hipMemcpyDeviceToHost, s));
+  if (C.iters > 0 && trace_accept)
+    M_TRY(ctx, hipMemcpyAsync(trace_accept, a.tr_acc, (size_t)C.iters * 4, hipMemcpyDeviceToHost, s));
   M_TRY(ctx, hipStreamSynchronize(s));
   if (H) std::memcpy(H, C.H, sizeof(C.H));
   if (c) std::memcpy(c, C.c, sizeof(C.c));
-  if (trace_cost)
-    for (int32_t k = 0; k < C.iters; ++k) trace_cost[k] = tc[k];
-  if (trace_accept)
-    for (int32_t k = 0; k < C.iters; ++k) trace_accept[k] = ta[k];
   if (rep) {
     rep->cost_initial = C.have_cost0 ? C.cost0 : C.cost;
     rep->cost_final = C.cost;
@@ -562,6 +613,40 @@ extern "C" povar_status povar_metric_upgrade(povar_ctx ctx, int32_t n_cams, cons
     rep->stop = C.stop;
   }
   return POVAR_OK;
+}
+
+}  // namespace
+}  // namespace povar
+
+using namespace povar;
+
+extern "C" povar_status povar_metric_upgrade(povar_ctx ctx, int32_t n_cams, const double* cams, const double* K,
+                                             int32_t max_iters, double ftol, double* H, double* c, double* alpha,
+                                             double* R, double* t, double* trace_cost, int32_t* trace_accept,
+                                             povar_metric_report* rep) {
+  if (!ctx) return POVAR_EINVAL;
+  MetricRun run;
+  povar_status st = metric_setup(ctx, n_cams, cams, K, max_iters, ftol, run, nullptr);
+  if (st != POVAR_OK) return st;
+  return metric_solve(ctx, run, n_cams, max_iters, H, c, alpha, R, t, trace_cost, trace_accept, rep);
+}
+
+extern "C" povar_status povar_metric_upgrade_noalloc(povar_ctx ctx, int32_t n_cams, const double* cams,
+                                                     const double* K, int32_t max_iters, double ftol, double* H,
+                                                     double* c, double* alpha, double* R, double* t,
+                                                     double* trace_cost, int32_t* trace_accept,
+                                                     povar_metric_report* rep) {
+  if (!ctx) return POVAR_EINVAL;
+  char* base = metric_scratch(ctx->device);
+  if (!base) {
+    set_error(ctx, "no scratch address for device %d (the context was not created through povar_ctx_create)",
+              ctx->device);
+    return POVAR_ESTATE;
+  }
+  MetricRun run;
+  povar_status st = metric_setup(ctx, n_cams, cams, K, max_iters, ftol, run, base);
+  if (st != POVAR_OK) return st;
+  return metric_solve(ctx, run, n_cams, max_iters, H, c, alpha, R, t, trace_cost, trace_accept, rep);
 }
 
 extern "C" povar_status povar_metric_debug_reduced(povar_ctx ctx, int32_t n_cams, const double* cams,
@@ -573,7 +658,7 @@ extern "C" povar_status povar_metric_debug_reduced(povar_ctx ctx, int32_t n_cams
     return POVAR_EINVAL;
   }
   MetricRun run;
-  povar_status st = metric_setup(ctx, n_cams, cams, K, 1, 0.0, run);
+  povar_status st = metric_setup(ctx, n_cams, cams, K, 1, 0.0, run, nullptr);
   if (st != POVAR_OK) return st;
   MetricArgs& a = run.a;
   hipStream_t s = ctx->stream;

@@ -1257,6 +1257,13 @@ povar_status povar_ctx_create(int device, void* hip_stream, povar_ctx* out) {
     }
     c->own_stream = true;
   }
+  const povar_status st = metric_scratch_init(c);
+  if (st != POVAR_OK) {
+    set_error(nullptr, "%s", povar_last_error(c));
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return st;
+  }
   *out = c;
   return POVAR_OK;
 }

@@ -33,7 +33,7 @@ EXPORTS = [
     "povar_problem_info", "povar_problem_layout", "povar_server_create", "povar_server_submit", "povar_server_poll",
     "povar_server_stats", "povar_server_destroy", "povar_refine_create", "povar_get_points_h",
     "povar_refine_debug_blocks", "povar_refine_debug_step", "povar_metric_upgrade", "povar_metric_debug_reduced",
-    "povar_get_trace_diag", "povar_debug_series", "povar_server_profile",
+    "povar_get_trace_diag", "povar_debug_series", "povar_server_profile", "povar_metric_upgrade_noalloc",
 ]
 
 
@@ -126,6 +126,8 @@ def lib() -> C.CDLL:
         "povar_metric_upgrade": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int32, C.c_double, _P, _P, _P, _P, _P, _P, _P,
                                            C.POINTER(MetricReport)]),
         "povar_metric_debug_reduced": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, _P, _DP]),
+        "povar_metric_upgrade_noalloc": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int32, C.c_double, _P, _P, _P, _P,
+                                                   _P, _P, _P, C.POINTER(MetricReport)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -189,19 +191,21 @@ def _metric_inputs(cams, K):
 
 
 def metric_upgrade(ctx: "Context", cams: np.ndarray, K: np.ndarray, max_iters: int = 100,
-                   ftol: float = 1e-14) -> dict:
-    """Metric upgrade (``povar_metric_upgrade``): cams (n, 12) or (n, 3, 4)
-    projective cameras, K (n, 3, 3) intrinsics.  Returns H (4, 4), c, alpha,
-    R (n, 3, 3), t (n, 3), the trace and the report."""
+                   ftol: float = 1e-14, noalloc: bool = False) -> dict:
+    """Metric upgrade (``povar_metric_upgrade``, or with noalloc
+    ``povar_metric_upgrade_noalloc``): cams (n, 12) or (n, 3, 4) projective
+    cameras, K (n, 3, 3) intrinsics.  Returns H (4, 4), c, alpha, R (n, 3, 3),
+    t (n, 3), the trace and the report."""
     P, Km = _metric_inputs(cams, K)
     n = P.shape[0]
     out = dict(H=np.empty(16), c=np.empty(3), alpha=np.empty(n), R=np.empty((n, 9)), t=np.empty((n, 3)))
     tc, ta = np.empty(max(max_iters, 1)), np.empty(max(max_iters, 1), dtype=np.int32)
     rep = MetricReport()
-    ctx.check(lib().povar_metric_upgrade(ctx.handle, n, _ptr(P), _ptr(Km), int(max_iters), float(ftol),
-                                         _ptr(out["H"]), _ptr(out["c"]), _ptr(out["alpha"]), _ptr(out["R"]),
-                                         _ptr(out["t"]), _ptr(tc), _ptr(ta), C.byref(rep)),
-              "povar_metric_upgrade")
+    fn = lib().povar_metric_upgrade_noalloc if noalloc else lib().povar_metric_upgrade
+    ctx.check(fn(ctx.handle, n, _ptr(P), _ptr(Km), int(max_iters), float(ftol),
+                 _ptr(out["H"]), _ptr(out["c"]), _ptr(out["alpha"]), _ptr(out["R"]),
+                 _ptr(out["t"]), _ptr(tc), _ptr(ta), C.byref(rep)),
+              "povar_metric_upgrade_noalloc" if noalloc else "povar_metric_upgrade")
     out["H"] = out["H"].reshape(4, 4)
     out["R"] = out["R"].reshape(n, 3, 3)
     out.update(trace_cost=tc[:rep.iters].copy(), trace_accept=ta[:rep.iters].astype(bool), iters=rep.iters,
