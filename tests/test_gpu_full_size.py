@@ -237,7 +237,7 @@ def test_refine_full_size_1800_cameras_sampled(ctx, w3):
 STEP_TOL = {"fp64": (1e-8, 1e-10), "fp32_bulk": (1e-4, 1e-6)}   # per-camera step, trial cost
 
 
-@pytest.mark.parametrize("number", [3])
+@pytest.mark.parametrize("number", [3, 5])
 @pytest.mark.parametrize("prec", ["fp32_bulk", "fp64"])
 def test_full_size_step_against_stored_oracle_step(ctx, number, prec):
     import os
