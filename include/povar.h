@@ -393,8 +393,9 @@ povar_status povar_problem_info(povar_problem pb, int64_t* n_obs, int64_t* n_pac
 /* Series camera pass of the problem.  *blocked = 0: one workgroup per camera
    chunk, landmark records gathered from anywhere (the records fit in L2).
    *blocked = 1 (records of the series precision above 4 MiB): landmarks in
-   blocks of *lm_block internal ids (2 MiB of records), *n_slots 64-lane slots of 4 observations
-   per lane, each block's slots run on one XCD, and *n_runs per-(camera, block
+   blocks of *lm_block internal ids (2 MiB of records), *n_slots 64-lane
+   slots of 8 (FP32-bulk) or 4 (FP64) observations per lane, each block's
+   slots run on one XCD, and *n_runs per-(camera, block
    part) partial sums added per camera afterwards.  *coop_gather = 1 when the
    cameras' series records are a full stride apart (more than 341 cameras:
    128 bytes in FP32, 256 in FP64) and the landmark pass gathers them

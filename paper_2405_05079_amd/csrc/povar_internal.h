@@ -192,8 +192,11 @@ constexpr int kCostGroup = 2048;
 constexpr int kCostDirect = 8192;    // up to this many packets, k_decide adds the packet partials itself
 
 // Blocked series camera pass.
-constexpr int kCsPerLane = 4;                    // observations per lane of a camera slot
-constexpr int kCsObs = kWave * kCsPerLane;       // observations per slot
+// Observations per lane of a camera slot, by series precision: FP32 slots
+// hold eight (more loads in flight per lane, and fewer runs split at slot
+// ends), FP64 slots four (the same registers).
+__host__ __device__ constexpr int cs_per_lane(bool fp32) { return fp32 ? 8 : 4; }
+__host__ __device__ constexpr int cs_obs(bool fp32) { return kWave * cs_per_lane(fp32); }
 constexpr long long kLmBlockBytes = 2ll << 20;   // landmark records per block (half of one XCD's L2)
 constexpr long long kL2Bytes = 4ll << 20;        // L2 of one XCD
 constexpr int kXcds = 8;

@@ -41,8 +41,9 @@
 // scan of DPP lane moves.  The camera-major pass runs one workgroup per chunk
 // of <= 2048 observations of one camera while the landmark records fit one
 // XCD's L2; larger problems use landmark blocks pinned to XCDs, with 64-lane
-// slots of 4 observations per lane and one partial per (camera, block part),
-// which the combine kernel adds per camera in a fixed order.
+// slots of 8 (FP32) or 4 (FP64) observations per lane and one partial per
+// (camera, block part), which the combine kernel adds per camera in a fixed
+// order.
 #include <hip/hip_ext.h>
 
 #include <mutex>
@@ -1349,12 +1350,13 @@ __global__ void __launch_bounds__(kWave) k_series_camera_combine(Batch B, int t)
 }
 
 // --------------------------------------------------- k_series_camera_slots
-// Blocked problems: one wave per camera slot, kCsPerLane observations per
+// Blocked problems: one wave per camera slot, cs_per_lane observations per
 // lane, all of one run.  t_run = sum_k vec((N_k Pbar_i z_j) x~_j^T) over the
 // run's observations; the (z, X) records gathered here belong to the slot's
 // landmark block, which the slot order keeps in one XCD's L2.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_series_camera_slots(Batch B, int t) {
+  constexpr int kCsPerLane = cs_per_lane(sizeof(T) == 4);
   int p, q;
   if (!map_wave(B, kUnitCSlot, p, q)) return;
   DevProblem& D = B.probs[p];
@@ -2272,6 +2274,7 @@ __global__ void __launch_bounds__(kCamWG) k_refine_series_camera(Batch B, int t)
 // kCsPerLane observations of one run per lane, a partial sum per run; the
 // (z, X) records of the slot's landmark block stay in one XCD's L2.
 __global__ void __launch_bounds__(kBlock) k_refine_series_camera_slots(Batch B, int t) {
+  constexpr int kCsPerLane = cs_per_lane(false);
   int p, q;
   if (!map_wave(B, kUnitCSlot, p, q)) return;
   DevProblem& D = B.probs[p];

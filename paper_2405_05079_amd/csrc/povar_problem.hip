@@ -71,9 +71,9 @@ size_t arena_bytes(const LayoutSizes& z, bool fp32, int64_t trace_cap, ArenaOffs
   const int64_t n_cs = z.blocked ? z.n_cs : 0, n_runs = z.blocked ? z.n_runs : 0;
   r.cs_hdr = a.take(n_cs * 4);
   r.cs_lane = a.take(n_cs * kWave * 8);
-  r.cs_lm = a.take(n_cs * kCsObs * 4);
-  r.cs_m32 = fp32 ? a.take(n_cs * kCsObs * 8) : SIZE_MAX;
-  r.cs_m64 = fp32 ? SIZE_MAX : a.take(n_cs * kCsObs * 16);
+  r.cs_lm = a.take(n_cs * cs_obs(fp32) * 4);
+  r.cs_m32 = fp32 ? a.take(n_cs * cs_obs(fp32) * 8) : SIZE_MAX;
+  r.cs_m64 = fp32 ? SIZE_MAX : a.take(n_cs * cs_obs(fp32) * 16);
   r.run_off = a.take((n_p + 1) * 4);
   r.smc = a.take((z.blocked ? n_p : n_mc) * 4);
   // the other buffers with initial values (current cameras and series
@@ -160,6 +160,7 @@ static int xcd_of_block(int64_t b) {
 // (camera, then internal landmark) already in L.cm_lm / L.cm_m*.
 static povar_status build_camera_slots(povar_ctx ctx, HostLayout& L, const std::vector<int64_t>& cstart,
                                        bool fp32) {
+  const int kCsPerLane = cs_per_lane(fp32), kCsObs = cs_obs(fp32);
   const int32_t n_p = L.n_p, n_l = L.n_l;
   const int64_t nb = landmark_blocks(n_l, fp32);
   const int64_t lb = (n_l + nb - 1) / nb;
@@ -198,7 +199,7 @@ static povar_status build_camera_slots(povar_ctx ctx, HostLayout& L, const std::
           used = 0;
           key = 0;
         }
-        const int64_t want = (end - beg + kCsPerLane - 1) / kCsPerLane;
+        const int64_t want = (end - beg + kCsPerLane - 1) / kCsPerLane;   // lanes
         const int32_t nl = (int32_t)std::min<int64_t>(kWave - used, want);
         const int64_t cnt = std::min<int64_t>(end - beg, (int64_t)nl * kCsPerLane);
         runs[b].push_back(Run{(int32_t)segs_cam[b][k].first, nslots[b] - 1, used, nl, key, beg, cnt});
@@ -498,6 +499,7 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
 // properties are listed with povar_debug_layout_check).
 static povar_status check_layout(const HostLayout& L, const int32_t* cam, const int32_t* pt, const double* meas,
                                  bool fp32, int64_t* out) {
+  const int kCsPerLane = cs_per_lane(fp32);
   auto fail = [](const char* what, long long a, long long b) {
     set_error(nullptr, "layout check: %s (%lld, %lld)", what, a, b);
     return POVAR_EINVAL;
@@ -1309,7 +1311,7 @@ povar_status povar_problem_footprint(int32_t n_cams, int32_t n_pts, int64_t n_ob
     // at most one run; plus one partial slot per block and the dispatch padding
     const int64_t nb = landmark_blocks(n_pts, fp32);
     const int64_t segs = std::min<int64_t>(n_obs, (int64_t)n_cams * nb);
-    z.n_cs = (n_obs / kCsPerLane + segs) / (kWave - 1) + 2 * nb + 2 * kXcds * kWavesPerBlock;
+    z.n_cs = (n_obs / cs_per_lane(fp32) + segs) / (kWave - 1) + 2 * nb + 2 * kXcds * kWavesPerBlock;
     z.n_runs = segs + z.n_cs;
   }
   *bytes = arena_bytes(z, fp32, kTraceCapacity, nullptr);
