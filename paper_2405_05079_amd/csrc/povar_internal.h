@@ -219,7 +219,8 @@ struct Batch {
   int32_t coop_cams, pad;
 };
 constexpr int kCoopPieces = 6;   // 16-byte pieces of P and x (FP32), or of each of them (FP64)
-constexpr int kCoopLdsBytes = kBlock / kWave * kCoopPieces * kWave * 16;
+constexpr int kCoopHalves = 2;   // FP32 exchange rounds (half the wave each): 3 KB of LDS per wave
+constexpr int kCoopLdsBytes = kBlock / kWave * kCoopPieces * kWave * 16 / kCoopHalves;
 
 // Launchers (defined with the kernels).  `fp32` selects the series /
 // Jacobian precision; the critical kernels are FP64 in both modes.

@@ -124,10 +124,15 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // serves several lanes) instead of one piece of 64 records (up to 64 lines,
 // each one lookup in the vector L1).  All loads are issued first; the pieces
 // then go to their lanes through `buf` (64 NP pieces of this wave), one r at
-// a time.  All 64 lanes call it.
-template <int NP, int R = 1>
+// a time.  With Halves = 2 the exchange takes two rounds through half the
+// buffer (64 NP / 2 pieces): the first NP / 2 load instructions hold exactly
+// the pieces of lanes 0-31, the others those of lanes 32-63, so each round
+// delivers all pieces of one half of the wave; the loads and the number of
+// cache lines they touch do not change.  All 64 lanes call it.
+template <int NP, int R = 1, int Halves = 1>
 __device__ __forceinline__ void coop_fetch(const char POVAR_GMEM* base, size_t stride, const int (&src)[R],
                                            f4v POVAR_LDS* buf, f4v (&out)[R][NP]) {
+  static_assert(Halves == 1 || (Halves == 2 && NP % 2 == 0), "one round, or two for an even piece count");
   const int lane = lane_id();
   f4v piece[R][NP];
 #pragma unroll
@@ -140,12 +145,26 @@ __device__ __forceinline__ void coop_fetch(const char POVAR_GMEM* base, size_t s
     }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
+    if constexpr (Halves == 1) {
 #pragma unroll
-    for (int i = 0; i < NP; ++i) buf[i * kWave + lane] = piece[r][i];
-    wave_sync();
+      for (int i = 0; i < NP; ++i) buf[i * kWave + lane] = piece[r][i];
+      wave_sync();
 #pragma unroll
-    for (int k = 0; k < NP; ++k) out[r][k] = buf[lane * NP + k];
-    wave_sync();
+      for (int k = 0; k < NP; ++k) out[r][k] = buf[lane * NP + k];
+      wave_sync();
+    } else {
+      constexpr int H = NP / 2;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int i = 0; i < H; ++i) buf[i * kWave + lane] = piece[r][h * H + i];
+        wave_sync();
+        if ((lane >> 5) == h)
+#pragma unroll
+          for (int k = 0; k < NP; ++k) out[r][k] = buf[(lane & 31) * NP + k];
+        wave_sync();
+      }
+    }
   }
 }
 
@@ -1050,7 +1069,8 @@ __device__ __forceinline__ void landmark_slot(const DevProblem& D, int q, const 
       const int src[1] = {act ? (int)(code & kCamMask) : -1};
       if constexpr (sizeof(T) == 4) {
         f4v pc[1][kCoopPieces];
-        coop_fetch<kCoopPieces>((const char POVAR_GMEM*)cam.S, (size_t)cam.stride * sizeof(T), src, cbuf, pc);
+        coop_fetch<kCoopPieces, 1, kCoopHalves>((const char POVAR_GMEM*)cam.S, (size_t)cam.stride * sizeof(T), src,
+                                                cbuf, pc);
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -1146,7 +1166,7 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark_coop(Batch B, int t)
   const CamFromRecords<float> cam{Prec<float>::S(D, D.ctl.pcur), D.s_stride};
   if (D.s_stride == kSerLine) {
     extern __shared__ f4v coop_lds[];
-    f4v POVAR_LDS* buf = (f4v POVAR_LDS*)coop_lds + (threadIdx.x >> 6) * (kCoopPieces * kWave);
+    f4v POVAR_LDS* buf = (f4v POVAR_LDS*)coop_lds + (threadIdx.x >> 6) * (kCoopPieces * kWave / kCoopHalves);
     landmark_slot<float, CamFromRecords<float>, true>(D, q, slot_head<float>(D, q), D.ctl.lcur, cam, buf);
   } else {
     landmark_slot<float>(D, q, slot_head<float>(D, q), D.ctl.lcur, cam);
