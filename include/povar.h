@@ -387,7 +387,10 @@ povar_status povar_kernel_times(povar_problem pb, double* ms_landmark_pass, int6
                                 double* ms_camera_pass, int64_t* n_camera_pass);
 /* Problem shape after layout: landmark-major packets (runs of whole
    landmarks of at most 64 observations), camera-major chunks (at most 2048
-   observations of one camera), device bytes. */
+   observations of one camera), device bytes.  In a problem with a camera of
+   more than 8 chunks, each accepted step adds every camera's chunk partials
+   of the linearisation with one wave per camera (one more kernel) instead of
+   one lane per camera, in the same order: the same sums, bit for bit. */
 povar_status povar_problem_info(povar_problem pb, int64_t* n_obs, int64_t* n_packets,
                                 int32_t* n_chunks, uint64_t* device_bytes);
 /* Series camera pass of the problem.  *blocked = 0: one workgroup per camera

@@ -30,6 +30,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kPerLane = 8;               // camera-major observations per lane
 constexpr int kChunk = kBlock * kPerLane; // camera-major observations per workgroup
 constexpr int kLinVals = 64;              // per-camera linearisation accumulators
+constexpr int kWaveSumChunks = 8;         // above this many chunks per camera, a wave adds a camera's partials
 constexpr int kCamBits = 26;              // packet entry: camera index bits
 constexpr uint32_t kCamMask = (1u << kCamBits) - 1u;
 
@@ -82,7 +83,8 @@ struct DevProblem {
   int32_t manifold;     // 0 sphere, 1 euclidean
   int32_t trace_cap;
   int32_t s_stride;     // series record stride, ser_stride(n_p)
-  int32_t pad1;
+  int32_t wave_sums;    // 1: a camera spans more than kWaveSumChunks chunks; k_camera_sums adds the
+                        // linearisation partials (one wave per camera), else k_camera_prep (one lane)
   double eta, ftol, lambda_min, lambda_max;
   double series_rtol;   // early stop of the series (0: off)
 
@@ -216,7 +218,9 @@ struct Batch {
   // 1: problems of the batch whose camera series records are kSerLine
   // values apart (128 bytes in FP32, 256 in FP64) gather them cooperatively in
   // the landmark pass (kCoopLdsBytes of LDS per workgroup)
-  int32_t coop_cams, pad;
+  int32_t coop_cams;
+  // 1: some problem of the batch has wave_sums set (k_camera_sums is launched)
+  int32_t wave_sums;
 };
 constexpr int kCoopPieces = 6;   // 16-byte pieces of P and x (FP32), or of each of them (FP64)
 constexpr int kCoopHalves = 2;   // FP32 exchange rounds (half the wave each): 3 KB of LDS per wave

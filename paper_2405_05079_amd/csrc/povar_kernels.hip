@@ -835,6 +835,36 @@ __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
 // x_0 = acc = -K g with g = b_p - sum W_k V^+ b_l.
 __host__ __device__ constexpr int tri(int r, int c) { return r * (r + 1) / 2 + c; }
 
+// -------------------------------------------------------- k_camera_sums
+// After an accept, for problems with wave_sums set: each camera's 64
+// linearisation sums (the 40 distinct entries of U_i, then the two 12-vectors
+// whose difference is the reduced gradient g_i), its chunk partials added in
+// chunk order.  One wave per camera, lane k adds value k: a camera seen
+// hundreds of thousands of times (hundreds of chunks) costs that many
+// coalesced loads of one wave instead of one lane's serial walk over 64
+// values per chunk.  The sums are those k_camera_prep forms for the other
+// problems, bit for bit.  One workgroup per 64 cameras, each wave a quarter
+// of them.
+static_assert(kLinVals == kWave, "one linearisation value per lane");
+__global__ void __launch_bounds__(kBlock) k_camera_sums(Batch B) {
+  int p, w;
+  if (!map_block(B, kUnitCamWave, p, w)) return;
+  DevProblem& D = B.probs[p];
+  if (D.ctl.done || !D.ctl.need_lin || !D.wave_sums) return;
+  const int lane = lane_id();
+  for (int c = (int)(threadIdx.x >> 6); c < kWave; c += kWavesPerBlock) {
+    const int i = w * kWave + c;
+    if (i >= D.n_p) break;
+    const int q1 = D.cam_ch[i + 1];
+    double s = 0.0;
+#pragma unroll 8
+    for (int q = D.cam_ch[i]; q < q1; ++q) s += D.lin_part[(size_t)q * kLinVals + lane];
+    const double other = __shfl(s, (lane + 12) & (kWave - 1));   // lane 40 + k receives value 52 + k
+    if (lane < 40) D.U40[(size_t)i * 40 + lane] = s;
+    else if (lane < 52) D.g64[(size_t)i * kCam + lane - 40] = s - other;
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
   int p, w;
@@ -857,8 +887,10 @@ __global__ void __launch_bounds__(kWave) k_camera_prep(Batch B) {
   const bool sphere = D.manifold == 0;
   const double a = 1.0 - D.eta;
 
+  // U_i and g_i: after an accept the sums of the chunk partials (here, or in
+  // k_camera_sums for problems with wave_sums), else those in place
   double u40[40], g[12];
-  if (D.ctl.need_lin) {
+  if (D.ctl.need_lin && !D.wave_sums) {
     double s[kLinVals];
 #pragma unroll
     for (int k = 0; k < kLinVals; ++k) s[k] = 0.0;
@@ -2467,6 +2499,7 @@ hipError_t launch_linearize(const Batch& b, bool fp32, int force, hipStream_t s)
 hipError_t launch_camera_prep(const Batch& b, bool fp32, hipStream_t s) {
   if (b.total[kUnitCamWave] == 0) return hipSuccess;
   const dim3 g = blocks_for(b.total[kUnitCamWave], 1);
+  if (b.wave_sums) hipLaunchKernelGGL(k_camera_sums, g, dim3(kBlock), 0, s, b);
   if (fp32) hipLaunchKernelGGL(k_camera_prep<float>, g, dim3(kWave), 0, s, b);
   else hipLaunchKernelGGL(k_camera_prep<double>, g, dim3(kWave), 0, s, b);
   return hipGetLastError();

@@ -785,6 +785,9 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   R.n_ch = H.n_ch;
   R.manifold = o->manifold;
   R.s_stride = ser_stride(H.n_p);
+  R.wave_sums = 0;
+  for (int32_t i = 0; i < H.n_p; ++i)
+    if (H.cam_ch[i + 1] - H.cam_ch[i] > kWaveSumChunks) R.wave_sums = 1;
   R.trace_cap = pb->trace_cap;
   R.eta = o->eta;
   R.ftol = o->ftol;
@@ -941,7 +944,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   for (int k = 0; k < kNumUnitKinds; ++k) B.total[k] = units[k];
   B.n_prob = 1;
   B.coop_cams = R.s_stride == kSerLine ? 1 : 0;
-  B.pad = 0;
+  B.wave_sums = R.wave_sums;
   if (pts0) {
     // second stage: the cost (7) at the given cameras and landmarks
     HIP_TRY(ctx, launch_refine_landmarks(B, stream));

@@ -130,9 +130,11 @@ hipError_t upload_tables(povar_server_s* sv, Group& G) {
   G.batch.probs = G.recs;
   G.batch.n_prob = n;
   G.batch.coop_cams = 0;
-  G.batch.pad = 0;
-  for (int p = 0; p < n; ++p)
+  G.batch.wave_sums = 0;
+  for (int p = 0; p < n; ++p) {
     if (G.res[p].pb->rec.s_stride == kSerLine) G.batch.coop_cams = 1;
+    if (G.res[p].pb->rec.wave_sums) G.batch.wave_sums = 1;
+  }
   G.batch.tables = G.tables;
   G.batch.tab_stride = stride;
   for (int k = 0; k < kNumUnitKinds; ++k) G.batch.total[k] = tab[(size_t)k * stride + n];

@@ -243,6 +243,34 @@ def test_blocked_camera_pass(ctx, prec, kw, tol):
     gp.close()
 
 
+# Cameras spanning more than 8 chunks of 2048 observations (Zipf views; 100k
+# observations, the heaviest camera 22k): each camera's linearisation
+# partials are added by one wave per camera, for every camera of the
+# problem.  One step against the oracle's, then (FP64) six LM iterations,
+# each relinearising after its accept, against the oracle's trajectory.
+WAVE_SUMS = dict(n_cams=12, n_pts=40000, track=("uniform", 2, 3), cam_choice="zipf", seed=36)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_bulk"])
+def test_linearisation_sums_by_wave(ctx, prec):
+    prob = synth.make_problem(**WAVE_SUMS)
+    chunks = -(-np.bincount(prob.cam_idx, minlength=prob.n_cams) // 2048)
+    assert chunks.max() > 8 and chunks.min() <= 8
+    say("wave sums", prec, WAVE_SUMS, "chunks per camera", chunks.tolist())
+    gp = povar.Problem.from_synth(ctx, prob, precision=prec, order=8, max_iters=6, ftol=0.0)
+    P, X, f = O.initial_state(prob, prob.cams0)
+    lin = O.linearize(P, X, prob)
+    dp, pt, ct = gp.debug_step(1e-3, 8)
+    assert step_err(prec, dp, O.camera_step(P, lin, 1e-3, 8)) < (1e-9 if prec == "fp64" else FP32_STEP_TOL)
+    if prec == "fp64":
+        gp.solve()
+        cost, lam, acc = gp.trace()
+        ref = O.lm_solve(prob, opts=O.Options(order=8, max_iters=6, ftol=0.0))
+        assert list(acc) == ref.trace_accept and all(ref.trace_accept)
+        np.testing.assert_allclose(cost, ref.trace_cost, rtol=1e-9)
+    gp.close()
+
+
 def test_trajectory_fp64_matches_oracle(ctx):
     prob = synth.workload(1)
     say("trajectory fp64 workload 1")
