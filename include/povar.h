@@ -170,8 +170,9 @@ povar_status povar_problem_footprint(int32_t n_cams, int32_t n_pts, int64_t n_ob
 
 /* Create a problem from observations (Sec. 3.2): cam_idx[k] in [0,n_cams),
    pt_idx[k] in [0,n_pts), meas[2k..2k+1] finite.  Every camera and every
-   point needs at least one observation.  cams0 (n_cams x 12, required) is the
-   initial camera set, or NULL: cameras drawn from opts->init_seed as
+   point needs at least one observation.  Sizes up to 67,108,863 cameras and
+   1,073,741,822 observations.  cams0 (n_cams x 12) is the initial camera
+   set, or NULL: cameras drawn from opts->init_seed as
    described there; on the sphere manifold each camera is normalised to
    unit norm.  The landmarks are then solved in closed form (8) and the
    initial cost is evaluated (POVAR_ENUMERIC if it is not finite).
