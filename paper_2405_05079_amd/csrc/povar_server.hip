@@ -248,10 +248,11 @@ void worker_loop(povar_server_s* sv) {
         sv->queue.pop_front();
       }
     }
+    // phase times of this pass, published under the lock at its end
     double t = sv->now();
     for (auto& r : admitted) admit(sv, r);
     double t1 = sv->now();
-    sv->t_admit += t1 - t;
+    const double d_admit = t1 - t;
     // Iterations per read-back: a problem's iteration count is known exactly
     // (each batched iteration advances every running problem by one), so as
     // long as no problem can reach its limit and no queued request could be
@@ -290,8 +291,14 @@ void worker_loop(povar_server_s* sv) {
       for (auto& R : G.res) R.left -= n_it;
     }
     t = sv->now();
-    sv->t_launch += t - t1;
-    if (!any) continue;
+    const double d_launch = t - t1;
+    if (!any) {
+      std::lock_guard<std::mutex> g(sv->mu);
+      sv->t_admit += d_admit;
+      sv->t_launch += d_launch;
+      continue;
+    }
+    double d_wait = 0.0, d_retire = 0.0;
     for (Group& G : sv->groups) {
       if (G.res.empty()) continue;
       const size_t n = G.res.size();
@@ -301,15 +308,19 @@ void worker_loop(povar_server_s* sv) {
                                     sv->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
       const double tr = sv->now();
-      sv->t_wait += tr - tw;
+      d_wait += tr - tw;
       if (e != hipSuccess) continue;
       for (int idx = (int)n - 1; idx >= 0; --idx) {
         G.res[idx].left = G.host_recs[idx].ctl.iter_limit - G.host_recs[idx].ctl.iter;
         if (G.host_recs[idx].ctl.done) (void)retire(sv, G, idx, G.host_recs[idx].ctl);
       }
-      sv->t_retire += sv->now() - tr;
+      d_retire += sv->now() - tr;
     }
     std::lock_guard<std::mutex> g(sv->mu);
+    sv->t_admit += d_admit;
+    sv->t_launch += d_launch;
+    sv->t_wait += d_wait;
+    sv->t_retire += d_retire;
     sv->batch_iters += n_it;
     sv->syncs += 1;
   }

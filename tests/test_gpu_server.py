@@ -93,6 +93,13 @@ def test_admission_respects_budget_and_late_arrivals_join(ctx):
     assert any(admits[t] >= min(finishes.values()) for t in later)
     for t, p in zip(first + later, probs):
         assert res[t][0]["iters"] == OPTS["max_iters"]
+    # the worker's own account: the budget deferred an admission, every
+    # batched iteration was counted once, read-backs cover up to four of them
+    prof = sv.profile()
+    assert prof["budget_waits"] >= 1
+    assert prof["batch_iters"] == sv.stats()["batch_iters"] >= OPTS["max_iters"]
+    assert 1 <= prof["readbacks"] <= prof["batch_iters"] <= 4 * prof["readbacks"]
+    assert min(prof["admit_s"], prof["launch_s"], prof["retire_s"]) >= 0.0 and prof["wait_s"] > 0.0
     sv.close()
 
 
