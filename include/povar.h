@@ -413,8 +413,10 @@ povar_status povar_problem_layout(povar_problem pb, int32_t* blocked, int32_t* l
    problems whose summed footprint stays within hbm_budget_bytes.  Requests
    wait in a FIFO queue until a slot and enough budget are free; admitted
    problems advance together, one LM iteration per batched launch sequence,
-   and new requests join at an iteration boundary.  Each result is
-   independent of which other problems shared the launches. */
+   and new requests join at an iteration boundary: a request is initialised
+   on a stream of its own while the residents' iterations of that pass run,
+   and enters the batch at the next pass.  Each result is independent of
+   which other problems shared the launches. */
 povar_status povar_server_create(povar_ctx ctx, uint64_t hbm_budget_bytes, int32_t max_slots,
                                  povar_server* out);
 /* Copies the request; *ticket identifies it.  cams0 may be NULL (seeded
@@ -439,9 +441,9 @@ povar_status povar_server_stats(povar_server sv, int32_t* queued, int32_t* activ
    landmark solve), [1] enqueueing batched launches, [2] waiting for the GPU
    at control-block read-backs, [3] retiring finished problems; counts[0]
    batched iterations, [1] read-backs (the worker enqueues up to four
-   iterations per read-back while no problem can reach its iteration limit
-   and no queued request fits), [2] admission attempts deferred by the HBM
-   budget. */
+   iterations per read-back while no problem can reach its iteration limit,
+   nothing was admitted in the pass and no queued request fits), [2]
+   admission attempts deferred by the HBM budget. */
 povar_status povar_server_profile(povar_server sv, double* seconds, int64_t* counts);
 /* Waits for the worker to drain nothing: pending requests are dropped. */
 povar_status povar_server_destroy(povar_server sv);

@@ -74,7 +74,8 @@ using namespace povar;
 
 struct povar_server_s {
   povar_ctx ctx = nullptr;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;         // batched iterations, read-backs, retirement
+  hipStream_t admit_stream = nullptr;   // admissions, while the residents' iterations run
   uint64_t budget = 0;
   int32_t max_slots = 0;
   std::mutex mu;
@@ -165,7 +166,7 @@ void admit(povar_server_s* sv, const std::shared_ptr<Request>& r) {
   auto* pb = new povar_problem_s();
   const int pos = (int)G.res.size();
   const int32_t limit = r->opt.max_iters;
-  povar_status st = problem_init(sv->ctx, std::move(r->layout), r->cams0.data(), &r->opt, sv->stream, pb,
+  povar_status st = problem_init(sv->ctx, std::move(r->layout), r->cams0.data(), &r->opt, sv->admit_stream, pb,
                                  G.recs + pos, limit);
   r->cams0.clear();
   r->cams0.shrink_to_fit();
@@ -248,24 +249,26 @@ void worker_loop(povar_server_s* sv) {
         sv->queue.pop_front();
       }
     }
-    // phase times of this pass, published under the lock at its end
-    double t = sv->now();
-    for (auto& r : admitted) admit(sv, r);
-    double t1 = sv->now();
-    const double d_admit = t1 - t;
+    // The residents' iterations are enqueued first; the requests admitted in
+    // this pass are initialised on the admission stream while those run (the
+    // record of a new problem lies past the batch's, which its tables cover)
+    // and join the batch from the next pass.
+    //
     // Iterations per read-back: a problem's iteration count is known exactly
     // (each batched iteration advances every running problem by one), so as
-    // long as no problem can reach its limit and no queued request could be
-    // admitted, several iterations are enqueued before the control blocks are
-    // read.  A problem that stops earlier by ftol has its remaining kernels
-    // return at once (they check its done flag).
-    int n_it = kServerItersPerSync;
+    // long as no problem can reach its limit, nothing was admitted and no
+    // queued request could be, several iterations are enqueued before the
+    // control blocks are read.  A problem that stops earlier by ftol has its
+    // remaining kernels return at once (they check its done flag).
+    int n_it = admitted.empty() ? kServerItersPerSync : 1;
     {
       std::lock_guard<std::mutex> g(sv->mu);
       if (!sv->queue.empty() && sv->n_resident < sv->max_slots &&
           sv->used + sv->queue.front()->footprint <= sv->budget)
         n_it = 1;
     }
+    // phase times of this pass, published under the lock at its end
+    double t1 = sv->now();
     for (Group& G : sv->groups)
       for (auto& R : G.res) n_it = std::min(n_it, std::max(1, R.left));
     bool any = false;
@@ -290,8 +293,11 @@ void worker_loop(povar_server_s* sv) {
       any = true;
       for (auto& R : G.res) R.left -= n_it;
     }
-    t = sv->now();
+    double t = sv->now();
     const double d_launch = t - t1;
+    for (auto& r : admitted) admit(sv, r);
+    t1 = sv->now();
+    const double d_admit = t1 - t;
     if (!any) {
       std::lock_guard<std::mutex> g(sv->mu);
       sv->t_admit += d_admit;
@@ -334,6 +340,7 @@ void free_server(povar_server_s* sv) {
     if (G.tables) (void)hipFree(G.tables);
   }
   if (sv->stream) (void)hipStreamDestroy(sv->stream);
+  if (sv->admit_stream) (void)hipStreamDestroy(sv->admit_stream);
 }
 
 }  // namespace
@@ -354,6 +361,7 @@ povar_status povar_server_create(povar_ctx ctx, uint64_t hbm_budget_bytes, int32
   sv->max_slots = max_slots;
   sv->t0 = std::chrono::steady_clock::now();
   hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->admit_stream, hipStreamNonBlocking);
   for (int g = 0; g < 2 && e == hipSuccess; ++g) {
     sv->groups[g].fp32 = g == 0;
     e = hipMalloc(&sv->groups[g].recs, sizeof(DevProblem) * max_slots);
