@@ -843,22 +843,26 @@ __host__ __device__ constexpr int tri(int r, int c) { return r * (r + 1) / 2 + c
 // hundreds of thousands of times (hundreds of chunks) costs that many
 // coalesced loads of one wave instead of one lane's serial walk over 64
 // values per chunk.  The sums are those k_camera_prep forms for the other
-// problems, bit for bit.  One workgroup per 64 cameras, each wave a quarter
-// of them.
-static_assert(kLinVals == kWave, "one linearisation value per lane");
+// problems, bit for bit.  The second stage (whose partials, recomputed every
+// iteration, have the same 40 + 12 + 12 layout) takes its sums from here on
+// every iteration for k_refine_prep.  One workgroup per 64 cameras, each
+// wave a quarter of them.
+static_assert(kLinVals == kWave && kLin2 == kWave, "one linearisation value per lane");
 __global__ void __launch_bounds__(kBlock) k_camera_sums(Batch B) {
   int p, w;
   if (!map_block(B, kUnitCamWave, p, w)) return;
   DevProblem& D = B.probs[p];
-  if (D.ctl.done || !D.ctl.need_lin || !D.wave_sums) return;
+  const bool stage2 = D.stage == 2;
+  if (D.ctl.done || !D.wave_sums || !(stage2 || D.ctl.need_lin)) return;
   const int lane = lane_id();
+  const double* __restrict__ part = stage2 ? D.lin2 : D.lin_part;
   for (int c = (int)(threadIdx.x >> 6); c < kWave; c += kWavesPerBlock) {
     const int i = w * kWave + c;
     if (i >= D.n_p) break;
     const int q1 = D.cam_ch[i + 1];
     double s = 0.0;
 #pragma unroll 8
-    for (int q = D.cam_ch[i]; q < q1; ++q) s += D.lin_part[(size_t)q * kLinVals + lane];
+    for (int q = D.cam_ch[i]; q < q1; ++q) s += part[(size_t)q * kLinVals + lane];
     const double other = __shfl(s, (lane + 12) & (kWave - 1));   // lane 40 + k receives value 52 + k
     if (lane < 40) D.U40[(size_t)i * 40 + lane] = s;
     else if (lane < 52) D.g64[(size_t)i * kCam + lane - 40] = s - other;
@@ -1982,13 +1986,25 @@ __global__ void __launch_bounds__(kWave) k_refine_prep(Batch B) {
   }
   if (i >= D.n_p) return;
   const double lam = D.ctl.lambda;
+  // the chunk partials' sums, here or (problems with wave_sums) from
+  // k_camera_sums: s[0..39] in U40, s[40 + k] - s[52 + k] in g64
   double s[kLin2];
+  if (D.wave_sums) {
 #pragma unroll
-  for (int k = 0; k < kLin2; ++k) s[k] = 0.0;
-  for (int q = D.cam_ch[i]; q < D.cam_ch[i + 1]; ++q) {
-    const double* part = D.lin2 + (size_t)q * kLin2;
+    for (int k = 0; k < 40; ++k) s[k] = D.U40[(size_t)i * 40 + k];
 #pragma unroll
-    for (int k = 0; k < kLin2; ++k) s[k] += part[k];
+    for (int k = 0; k < 12; ++k) {
+      s[40 + k] = D.g64[(size_t)i * kCam + k];
+      s[52 + k] = 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kLin2; ++k) s[k] = 0.0;
+    for (int q = D.cam_ch[i]; q < D.cam_ch[i + 1]; ++q) {
+      const double* part = D.lin2 + (size_t)q * kLin2;
+#pragma unroll
+      for (int k = 0; k < kLin2; ++k) s[k] += part[k];
+    }
   }
   double L[78];
 #pragma unroll
@@ -2586,6 +2602,7 @@ hipError_t launch_refine_cameras(const Batch& b, hipStream_t s) {
 hipError_t launch_refine_step(const Batch& b, int order, bool check, hipStream_t s) {
   const dim3 gp = blocks_for(b.total[kUnitPacket], kWavesPerBlock);
   const dim3 gw = blocks_for(b.total[kUnitCamWave], 1);
+  if (b.wave_sums) hipLaunchKernelGGL(k_camera_sums, gw, dim3(kBlock), 0, s, b);
   hipLaunchKernelGGL(k_refine_prep, gw, dim3(kWave), 0, s, b);
   for (int t = 1; t <= order; ++t) {
     hipLaunchKernelGGL(k_refine_series_landmark, gp, dim3(kBlock), 0, s, b, t);

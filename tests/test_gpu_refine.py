@@ -55,8 +55,11 @@ CASES = [
     dict(n_cams=40, n_pts=70000, seed=23, track=("uniform", 2, 3)),
     # blocked, with heavy-tailed views per camera (Zipf): cameras with many runs
     dict(n_cams=300, n_pts=70000, seed=24, track=("uniform", 2, 3), cam_choice="zipf"),
+    # cameras of up to 11 chunks (Zipf views, 100k observations): each
+    # camera's linearisation partials added by one wave per camera
+    dict(n_cams=12, n_pts=40000, seed=36, track=("uniform", 2, 3), cam_choice="zipf"),
 ]
-IDS = ["small", "7-cameras", "ragged", "long-tracks", "3-chunk-cameras", "blocked", "blocked-zipf"]
+IDS = ["small", "7-cameras", "ragged", "long-tracks", "3-chunk-cameras", "blocked", "blocked-zipf", "wave-sums"]
 
 
 @pytest.mark.parametrize("lam", [1e-3, 1.0])
