@@ -205,11 +205,12 @@ povar_status povar_get_report(povar_problem pb, povar_report* report);
 povar_status povar_get_cameras(povar_problem pb, double* cams_out);
 povar_status povar_get_points(povar_problem pb, double* pts_out);
 /* Per-iteration trace: trial cost, damping used, accepted flag, for the
-   first min(n, iters) iterations.  Any output pointer may be NULL. */
+   first min(n, iters, 4096) iterations (the trace keeps the first 4096; the
+   rest of each output is left untouched).  Any output pointer may be NULL. */
 povar_status povar_get_trace(povar_problem pb, int32_t n, double* trial_cost,
                              double* lambda_used, int32_t* accepted);
-/* Per-iteration diagnostics of the first stage, for the first min(n, iters)
-   iterations (either pointer may be NULL): bl_norm, the 2-norm over all
+/* Per-iteration diagnostics of the first stage, for the first
+   min(n, iters, 4096) iterations (either pointer may be NULL): bl_norm, the 2-norm over all
    landmarks of b_l = sum_k J_l,k^T r_k at the trial cameras and their
    re-solved landmarks (zero up to rounding, since X* solves (8): the
    eliminated landmarks have zero gradient); series_seconds, the device time
