@@ -40,7 +40,12 @@ notes of the repository):
 
 parity pinned: see tests/test_oracle_pins.py (finite differences, lstsq,
 envelope theorem, dense joint solve, Neumann closed form and bound, Lemma 1,
-tangency and basis invariance, gauge invariance, known zero minimum).
+tangency and basis invariance, gauge invariance, known zero minimum, the R12
+branch on a block without a Cholesky factor, the series from a given start
+against its dense closed form, the Riemannian gradient against central
+differences, the memory-bounded step against the assembled one).  lm_solve:
+each step and the accept rule R8 are pinned; the trajectory over many
+iterations has no closed form of its own: parity unpinned beyond those pins.
 """
 from __future__ import annotations
 
