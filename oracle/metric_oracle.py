@@ -44,7 +44,9 @@ parity pinned: see tests/test_metric_pins.py (exact calibrated scenes seen
 through a random projective frame are recovered, the closed-form scale is
 the least-squares one, the derivative theorem and the Jacobian against
 central differences, the reference camera's term vanishes, invariance to the
-projective frame and to camera scales).
+projective frame and to camera scales).  lm_solve is pinned by its end point
+(exact recovery on noise-free scenes); its iterates in between are parity
+unpinned.
 """
 from __future__ import annotations
 

@@ -29,7 +29,9 @@ parity pinned: see tests/test_ripoba_pins.py (worked example of (7), central
 finite differences, degree-0 homogeneity of the residual, the dense joint
 Riemannian system and its Neumann partial sums with and without the early
 stop, Lemma 2's spectrum, the zero minimum of noise-free data, projective
-gauge invariance, the hand-over from the first stage).
+gauge invariance, the hand-over from the first stage).  lm_solve: its steps
+and the accept rule (R8) are pinned; the many-iteration trajectory has no
+closed form of its own: parity unpinned beyond those pins.
 """
 from __future__ import annotations
 
