@@ -402,9 +402,10 @@ povar_status povar_problem_info(povar_problem pb, int64_t* n_obs, int64_t* n_pac
    slots of 8 (FP32-bulk) or 4 (FP64) observations per lane, each block's
    slots run on one XCD, and *n_runs per-(camera, block
    part) partial sums added per camera afterwards.  *coop_gather = 1 when the
-   cameras' series records are a full stride apart (more than 341 cameras:
-   128 bytes in FP32, 256 in FP64) and the landmark pass gathers them
-   cooperatively, whole waves reading consecutive pieces of a few records.
+   landmark pass gathers the cameras' series records cooperatively, whole
+   waves reading consecutive pieces of a few records: every FP64 problem, and
+   FP32-bulk problems whose records are a full 128-byte line apart (more
+   than 341 cameras).
    NULL outputs are skipped. */
 povar_status povar_problem_layout(povar_problem pb, int32_t* blocked, int32_t* lm_block, int64_t* n_slots,
                                   int64_t* n_runs, int32_t* coop_gather);

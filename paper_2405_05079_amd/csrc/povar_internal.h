@@ -215,9 +215,9 @@ struct Batch {
   const int32_t POVAR_GMEM* tables;
   int32_t n_prob, tab_stride;
   int32_t total[kNumUnitKinds];
-  // 1: problems of the batch whose camera series records are kSerLine
-  // values apart (128 bytes in FP32, 256 in FP64) gather them cooperatively in
-  // the landmark pass (kCoopLdsBytes of LDS per workgroup)
+  // 1: the landmark pass gathers camera series records cooperatively: every
+  // FP64 batch; an FP32 batch holding problems whose records are kSerLine
+  // values (128 bytes) apart (kCoopLdsBytes of LDS per workgroup)
   int32_t coop_cams;
   // 1: some problem of the batch has wave_sums set (k_camera_sums is launched)
   int32_t wave_sums;

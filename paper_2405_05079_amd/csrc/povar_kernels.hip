@@ -20,7 +20,8 @@
 //   k_series_landmark      z_j = V_j^+ sum_k W_k^T x_i                      (17)
 //   k_series_landmark_coop the same, FP32 problems with many cameras, camera
 //                          records fetched by whole waves
-//   k_series_landmark_coop64  the same in FP64 (two gathers per record)
+//   k_series_landmark_coop64  the same for every FP64 problem (two gathers per
+//                          record)
 //   k_series_camera        x_i = K_i sum_k W_k z_j, acc_i += x_i             (17)
 //   k_series_camera_slots  the same sums for landmark-blocked problems, per run
 //   k_series_camera_combine  adds a camera's partial sums, applies K_i
@@ -1209,22 +1210,19 @@ __global__ void __launch_bounds__(kBlock) k_series_landmark_coop(Batch B, int t)
   }
 }
 
-// FP64 landmark pass of batches holding problems with 256-byte camera
-// records (stride kSerLine): P and x gathered cooperatively, through a 6 KB
-// LDS buffer per wave; the other problems per lane.
+// FP64 landmark pass (every FP64 problem): P and x gathered cooperatively,
+// through a 6 KB LDS buffer per wave.  Even 250 cameras' FP64 records (48 KB)
+// overflow the vector L1, so per-lane gathers would go to L2 one line per
+// lane and piece.
 __global__ void __launch_bounds__(kBlock) k_series_landmark_coop64(Batch B, int t) {
   int p, q;
   if (!map_wave(B, kUnitPacket, p, q)) return;
   DevProblem& D = B.probs[p];
   if (D.ctl.done || t > D.ctl.stop_at) return;
   const CamFromRecords<double> cam{Prec<double>::S(D, D.ctl.pcur), D.s_stride};
-  if (D.s_stride == kSerLine) {
-    __shared__ f4v cbuf[kWavesPerBlock][kCoopPieces * kWave];
-    landmark_slot<double, CamFromRecords<double>, true>(D, q, slot_head<double>(D, q), D.ctl.lcur, cam,
-                                                        (f4v POVAR_LDS*)cbuf[threadIdx.x >> 6]);
-  } else {
-    landmark_slot<double>(D, q, slot_head<double>(D, q), D.ctl.lcur, cam);
-  }
+  __shared__ f4v cbuf[kWavesPerBlock][kCoopPieces * kWave];
+  landmark_slot<double, CamFromRecords<double>, true>(D, q, slot_head<double>(D, q), D.ctl.lcur, cam,
+                                                      (f4v POVAR_LDS*)cbuf[threadIdx.x >> 6]);
 }
 
 // --------------------------------------------------------- k_series_camera
@@ -2526,12 +2524,10 @@ hipError_t launch_camera_prep(const Batch& b, bool fp32, hipStream_t s) {
 hipError_t launch_series_landmark(const Batch& b, bool fp32, int t, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (b.total[kUnitPacket] == 0) return hipSuccess;
   const dim3 g = blocks_for(b.total[kUnitPacket], kWavesPerBlock);
-  if (fp32 && b.coop_cams)
-    hipExtLaunchKernelGGL(k_series_landmark_coop, g, dim3(kBlock), kCoopLdsBytes, s, ev0, ev1, 0, b, t);
+  if (!fp32) hipExtLaunchKernelGGL(k_series_landmark_coop64, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
   else if (b.coop_cams)
-    hipExtLaunchKernelGGL(k_series_landmark_coop64, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
-  else if (fp32) hipExtLaunchKernelGGL(k_series_landmark<float>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
-  else hipExtLaunchKernelGGL(k_series_landmark<double>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
+    hipExtLaunchKernelGGL(k_series_landmark_coop, g, dim3(kBlock), kCoopLdsBytes, s, ev0, ev1, 0, b, t);
+  else hipExtLaunchKernelGGL(k_series_landmark<float>, g, dim3(kBlock), 0, s, ev0, ev1, 0, b, t);
   return hipGetLastError();
 }
 

@@ -943,7 +943,7 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
   B.tab_stride = 2;
   for (int k = 0; k < kNumUnitKinds; ++k) B.total[k] = units[k];
   B.n_prob = 1;
-  B.coop_cams = R.s_stride == kSerLine ? 1 : 0;
+  B.coop_cams = (!pb->fp32 || R.s_stride == kSerLine) ? 1 : 0;
   B.wave_sums = R.wave_sums;
   if (pts0) {
     // second stage: the cost (7) at the given cameras and landmarks

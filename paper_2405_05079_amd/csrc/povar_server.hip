@@ -130,7 +130,7 @@ hipError_t upload_tables(povar_server_s* sv, Group& G) {
   if (e != hipSuccess) return e;
   G.batch.probs = G.recs;
   G.batch.n_prob = n;
-  G.batch.coop_cams = 0;
+  G.batch.coop_cams = G.fp32 ? 0 : 1;   // FP64: always cooperative
   G.batch.wave_sums = 0;
   for (int p = 0; p < n; ++p) {
     if (G.res[p].pb->rec.s_stride == kSerLine) G.batch.coop_cams = 1;
