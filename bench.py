@@ -207,6 +207,36 @@ def matched_cost(ctx, rates: dict, seeds: int):
     return out
 
 
+def matched_cost_row(ctx, prob, rates: dict):
+    """Time to a matched final cost at a size the oracle cannot run for a
+    whole trajectory: f_ref is the FP64 GPU path's accepted cost after the
+    workload's iteration count (that path's steps match the stored oracle
+    steps at this size to 1e-12, tests/test_gpu_full_size.py); FP32-bulk runs
+    up to twice as many iterations, and the first whose accepted cost is
+    within f_ref (1 + 1e-6) is converted to seconds at its measured rate."""
+    n = prob.iters
+    gp = povar.Problem.from_synth(ctx, prob, precision="fp64", ftol=0.0, max_iters=n)
+    _, best64 = iters_to_reach(gp, n, -np.inf)
+    gp.close()
+    f_ref = float(best64[n - 1])
+    if not np.isfinite(f_ref):
+        return {"f_ref": f"FP64 GPU path's cost after {n} iterations", "f_ref_value": None,
+                "note": "no accepted FP64 step"}
+    target = f_ref * (1 + 1e-6)
+    it64 = int(np.nonzero(best64 <= target)[0][0]) + 1
+    gp = povar.Problem.from_synth(ctx, prob, precision="fp32_bulk", ftol=0.0, max_iters=2 * n)
+    it32, best32 = iters_to_reach(gp, 2 * n, target)
+    gp.close()
+    out = {"f_ref": f"FP64 GPU path's cost after {n} iterations", "f_ref_value": f_ref,
+           "target": "f_ref (1 + 1e-6)", "cap_iters": 2 * n,
+           "fp64": {"iters_to_match": it64, "seconds_to_match": it64 / rates["fp64"]},
+           "fp32_bulk": {"iters_to_match": it32, "seconds_to_match": (it32 / rates["fp32_bulk"]) if it32 else None,
+                         "rel_vs_ref_at_ref_iters": float((best32[n - 1] - f_ref) / f_ref)}}
+    s32 = out["fp32_bulk"]["seconds_to_match"]
+    out["speedup_fp32_over_fp64_at_matched_cost"] = (out["fp64"]["seconds_to_match"] / s32) if s32 else None
+    return out
+
+
 BUCKETS = [(20, 40), (40, 80), (80, 160), (160, 320), (320, 401)]
 # Arrival rate of the serving leg: 0.8 x the closed-loop throughput of the
 # 512-request stream, measured once (bench.py --calibrate-serving on one
@@ -682,6 +712,12 @@ def main():
                 row[prec], _ = series_leg(ctx, pw, prec, args.steps, min(args.warmup, 5), f"workload{w}")
                 log(f"  {prec}: {row[prec]['iters_per_s']:.2f} iters/s, order {row[prec]['us_per_order']:.1f} us, "
                     f"alg frac {row[prec]['alg_frac_per_order']}")
+            if not args.no_matched:
+                row["matched_cost"] = matched_cost_row(
+                    ctx, pw, {p: row[p]["iters_per_s"] for p in ("fp32_bulk", "fp64")})
+                mc = row["matched_cost"]
+                log(f"  matched cost: FP64 {mc['fp64']['iters_to_match']} iterations, FP32-bulk "
+                    f"{mc['fp32_bulk']['iters_to_match']}, speedup {mc['speedup_fp32_over_fp64_at_matched_cost']}")
             out["roofline_rows"][f"workload{w}"] = row
             del pw
     if not args.no_matched:
