@@ -119,3 +119,16 @@ def test_layout_check_rejects_invalid_problems():
     with pytest.raises(povar.PovarError, match="non-finite"):
         povar.layout_check(cam, pt, bad, 2, 2, "fp64")
     assert povar.layout_check(cam, pt, meas, 2, 2, "fp64")["n_packets"] == 1
+
+
+def test_layout_on_edge_shapes():
+    """Cameras of exactly 2048, 2049 and 4096 observations and landmarks of
+    exactly 64, 65 and 63: the host layout passes its invariant checks in
+    both precisions, with one, two and two chunks for the first three
+    cameras and one for each of the other 77."""
+    from edge_shapes import boundary_problem
+    p = boundary_problem()
+    for prec in ("fp64", "fp32_bulk"):
+        info = povar.layout_check(p.cam_idx, p.pt_idx, p.meas, p.n_cams, p.n_pts, prec)
+        assert info["n_chunks"] == 1 + 2 + 2 + 77
+        assert not info["blocked"]

@@ -12,6 +12,8 @@ import pytest
 from oracle import povar_oracle as O
 from paper_2405_05079_amd import povar, synth
 
+from edge_shapes import boundary_problem
+
 pytestmark = pytest.mark.gpu
 
 
@@ -240,6 +242,29 @@ def test_blocked_camera_pass(ctx, prec, kw, tol):
     for lam, order in ((1e-3, 1), (1e-3, 8)):
         dp, pt, ct = gp.debug_step(lam, order)
         assert step_err(prec, dp, O.camera_step(P, lin, lam, order)) < tol
+    gp.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_bulk"])
+def test_layout_edge_shapes(ctx, prec):
+    prob = boundary_problem()
+    counts = np.bincount(prob.cam_idx, minlength=prob.n_cams)
+    tracks = np.bincount(prob.pt_idx, minlength=prob.n_pts)
+    assert counts[:3].tolist() == [2048, 2049, 4096] and tracks[-3:].tolist() == [64, 65, 63]
+    say("layout edges", prec)
+    gp = povar.Problem.from_synth(ctx, prob, precision=prec)
+    P, X, f = O.initial_state(prob, prob.cams0)
+    np.testing.assert_allclose(gp.points(), X, rtol=1e-9, atol=1e-9 * np.abs(X).max())
+    assert abs(gp.report()["cost_initial"] - f) <= 1e-11 * f
+    d = gp.debug_linearize()
+    lin = O.linearize(P, X, prob)
+    tol = 1e-10 if prec == "fp64" else 2e-5
+    assert rel_rows(d["U"].reshape(-1, 144), lin.U.reshape(-1, 144)) < tol
+    assert rel(d["Vp"], lin.Vp) < 1e-9
+    for lam, order in ((1e-3, 0), (1e-3, 8)):
+        dp, pt, ct = gp.debug_step(lam, order)
+        ref = O.camera_step(P, lin, lam, order)
+        assert step_err(prec, dp, ref) < (1e-9 if prec == "fp64" else FP32_STEP_TOL)
     gp.close()
 
 
