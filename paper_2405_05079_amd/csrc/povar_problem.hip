@@ -365,11 +365,20 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
     }
     for (int64_t k = 0; k < n_obs; ++k) sig[pt[k]] |= cmask[cam[k]];
   }
+  // (the order of a stable sort by (sig, minc), built as two stable counting
+  // sorts: by minc, then by sig)
   L.int2ext.resize(n_l);
-  std::iota(L.int2ext.begin(), L.int2ext.end(), 0);
-  std::stable_sort(L.int2ext.begin(), L.int2ext.end(), [&](int32_t a, int32_t b) {
-    return sig[a] != sig[b] ? sig[a] < sig[b] : minc[a] < minc[b];
-  });
+  {
+    std::vector<int32_t> by_minc(n_l);
+    std::vector<int64_t> start((size_t)n_p + 1, 0);
+    for (int32_t j = 0; j < n_l; ++j) ++start[(size_t)minc[j] + 1];
+    for (int32_t i = 0; i < n_p; ++i) start[i + 1] += start[i];
+    for (int32_t j = 0; j < n_l; ++j) by_minc[start[minc[j]]++] = j;
+    int64_t sstart[(1 << kXcds) + 1] = {0};
+    for (int32_t j = 0; j < n_l; ++j) ++sstart[sig[j] + 1];
+    for (int s = 0; s < (1 << kXcds); ++s) sstart[s + 1] += sstart[s];
+    for (int32_t j : by_minc) L.int2ext[sstart[sig[j]]++] = j;
+  }
   // observations grouped by caller's landmark, then sorted by camera
   std::vector<int64_t> lstart(n_l + 1, 0);
   for (int32_t j = 0; j < n_l; ++j) lstart[j + 1] = lstart[j] + cnt_l[j];
@@ -378,9 +387,23 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
     std::vector<int64_t> fill(lstart.begin(), lstart.end() - 1);
     for (int64_t k = 0; k < n_obs; ++k) lobs[fill[pt[k]]++] = k;
   }
-  for (int32_t j = 0; j < n_l; ++j)
-    std::stable_sort(lobs.begin() + lstart[j], lobs.begin() + lstart[j + 1],
-                     [&](int64_t a, int64_t b) { return cam[a] < cam[b]; });
+  // each landmark's observations by camera, stable (insertion sort for the
+  // usual short tracks, merge sort for long ones)
+  for (int32_t j = 0; j < n_l; ++j) {
+    int64_t* o = lobs.data() + lstart[j];
+    const int64_t m = lstart[j + 1] - lstart[j];
+    if (m > 32) {
+      std::stable_sort(o, o + m, [&](int64_t a, int64_t b) { return cam[a] < cam[b]; });
+      continue;
+    }
+    for (int64_t u = 1; u < m; ++u) {
+      const int64_t x = o[u];
+      const int32_t cx = cam[x];
+      int64_t v = u;
+      for (; v > 0 && cam[o[v - 1]] > cx; --v) o[v] = o[v - 1];
+      o[v] = x;
+    }
+  }
   if (n_p > (int32_t)kCamMask) {
     set_error(ctx, "n_cams exceeds the supported maximum");
     return POVAR_EINVAL;
