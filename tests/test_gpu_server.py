@@ -103,6 +103,48 @@ def test_admission_respects_budget_and_late_arrivals_join(ctx):
     sv.close()
 
 
+def test_budget_frees_a_large_problem_while_small_ones_run(ctx):
+    """A large problem (above 250,000 observations: the large class, on a
+    stream of its own) finishes while small ones are still iterating; the next
+    large request fits only once that problem's memory is freed, which the
+    worker does after the small group's iterations in flight (freeing
+    synchronises the device), without waiting for the small problems to
+    finish.  Every result equals its problem solved alone, bitwise."""
+    large = [synth.make_problem(60, 60000, track=("geom", 0.25), seed=901 + i) for i in range(2)]
+    small = requests()[:3]
+    assert min(p.n_obs for p in large) > 250000 >= max(p.n_obs for p in small)
+    o_large, o_small = dict(OPTS, max_iters=3), dict(OPTS, max_iters=60)
+    print("[case] server budget across size classes", flush=True)
+    fps, alone = [], []
+    for p, o in [(large[0], o_large), (small[0], o_small), (small[1], o_small), (large[1], o_large),
+                 (small[2], o_small)]:
+        gp = povar.Problem.from_synth(ctx, p, **o)
+        fps.append(gp.info()["device_bytes"])
+        alone.append((gp.solve(), gp.cameras(), gp.points()))
+        gp.close()
+    budget = fps[0] + fps[1] + fps[2] + fps[4] + (1 << 20)
+    assert fps[3] > fps[1] + fps[2] + fps[4] + (1 << 20)   # the second large one waits for the first
+    sv = povar.Server(ctx, hbm_budget_bytes=budget, max_slots=8)
+    try:
+        order = [(large[0], o_large), (small[0], o_small), (small[1], o_small), (large[1], o_large),
+                 (small[2], o_small)]
+        tickets = [sv.submit(p, **o) for p, o in order]
+        res, _ = drain(sv, tickets)
+        prof = sv.profile()
+    finally:
+        sv.close()
+    for t, (rep_a, cams_a, pts_a) in zip(tickets, alone):
+        rep, cams, pts, _ = res[t]
+        np.testing.assert_array_equal(cams, cams_a)
+        np.testing.assert_array_equal(pts, pts_a)
+        assert rep["cost_final"] == rep_a["cost_final"]
+    times = [res[t][3] for t in tickets]
+    assert prof["budget_waits"] >= 1
+    # the second large request entered after the first finished, while the
+    # small ones admitted with the first were still running
+    assert times[0][2] <= times[3][1] < min(times[1][2], times[2][2])
+
+
 def test_oversized_and_invalid_requests_are_rejected(ctx):
     prob = requests()[0]
     print("[case] server rejects", flush=True)
@@ -153,9 +195,9 @@ def test_blocked_problems_in_a_mix_equal_single_solves(ctx, prec):
 
 
 def test_mixed_precisions_in_one_server(ctx):
-    """FP32-bulk and FP64 requests interleaved on one server (one batch per
-    precision, both advanced every round): each result equals the same
-    request solved alone in its precision, bitwise."""
+    """FP32-bulk and FP64 requests interleaved on one server (one group, and
+    stream, per precision): each result equals the same request solved alone
+    in its precision, bitwise."""
     probs = requests()[:6]
     precs = ["fp32_bulk", "fp64"] * 3
     print("[case] server mixed precisions", flush=True)
