@@ -239,9 +239,10 @@ def matched_cost_row(ctx, prob, rates: dict):
 
 BUCKETS = [(20, 40), (40, 80), (80, 160), (160, 320), (320, 401)]
 # Arrival rate of the serving leg: 0.8 x the closed-loop throughput of the
-# 512-request stream, measured once (bench.py --calibrate-serving on one
-# MI355X: 163.7 problems/s closed loop, 1 GiB budget, 64 slots) and kept fixed.
-SERVING_RATE_PER_S = 130.9
+# 512-request stream (1 GiB budget, 64 slots), measured on one MI355X with the
+# server that groups problems by size: 205.6 problems/s, the mean of seven
+# runs (194-213), and kept fixed.
+SERVING_RATE_PER_S = 164.5
 SERVING_ARRIVAL_SEEDS = (4999, 5999)
 
 

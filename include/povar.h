@@ -417,8 +417,10 @@ povar_status povar_problem_layout(povar_problem pb, int32_t* blocked, int32_t* l
    problems form groups by precision and by size (up to 250,000 observations,
    or more); each group advances one LM iteration per batched launch sequence
    on a stream of its own, so small problems are not held to the pace of large
-   ones.  A request is initialised on a stream of its own while the groups'
-   iterations run and joins its group at the group's next launch.  A finished
+   ones.  An admission thread initialises admitted requests (device
+   allocation, upload, initial landmark solve) on a stream of its own while
+   the groups' iterations run; an initialised problem joins its group before
+   the group's next launch.  A finished
    problem's result is copied out at once; its device memory (still counted
    against the budget) is freed when no group has work in flight, or, when a
    queued request needs that memory, after the groups in flight finish their
@@ -445,8 +447,8 @@ povar_status povar_server_poll(povar_server sv, uint64_t ticket, povar_report* r
 povar_status povar_server_stats(povar_server sv, int32_t* queued, int32_t* active,
                                 int64_t* finished, int64_t* batch_iters);
 /* Where the worker's time went (seconds since creation, each may be NULL):
-   seconds[0] admitting requests (device allocation, layout upload, initial
-   landmark solve), [1] enqueueing batched launches, [2] waiting for the GPU
+   seconds[0] the admission thread initialising requests (device allocation,
+   layout upload, initial landmark solve), [1] enqueueing batched launches, [2] waiting for the GPU
    while no group's read-back had arrived, [3] retiring finished problems and
    freeing their memory; counts[0] batched iterations summed over the groups,
    [1] control-block read-backs (a group enqueues up to four iterations per

@@ -3,9 +3,13 @@
 //
 // submit() validates a request and builds its observation layout on the
 // caller's thread, so its exact device footprint is known before admission.
-// One worker thread owns the device.  It admits queued requests in FIFO order
-// whenever a slot is free and the summed footprint of resident problems stays
-// within the budget.  Resident problems form groups by precision and by size
+// One worker thread runs the batched iterations.  It admits queued requests
+// in FIFO order whenever a slot is free and the summed footprint of resident
+// problems stays within the budget; an admission thread initialises them
+// (device allocation, upload, initial landmark solve) on a stream of its own
+// into staging records, so the worker keeps relaunching groups meanwhile, and
+// an initialised problem's record is copied into its group while the group
+// is idle, before its next launch.  Resident problems form groups by precision and by size
 // (up to kLargeObs observations, or more).  A group advances with one batched
 // launch sequence per LM iteration (each kernel's grid covers the work units
 // of all its problems) on a stream of its own, so the small problems iterate
@@ -14,8 +18,8 @@
 // copied back (an event marks their arrival), and finished problems are
 // retired: their results are copied to the host at once, their device memory
 // is freed later, when no group has work in flight (freeing memory
-// synchronises the whole device).  New requests join their group at its next
-// launch while others are mid-solve.  Every reduction stays inside one
+// synchronises the whole device).  New requests thus join their group while
+// others are mid-solve.  Every reduction stays inside one
 // problem's own units in a fixed order, so a problem's result does not depend
 // on which others shared the launches.
 #include <chrono>
@@ -60,6 +64,13 @@ struct Resident {
   int32_t left = 1;   // iterations before the problem reaches its limit (as of the last read-back)
 };
 
+// An initialised problem waiting to join its group.
+struct Ready {
+  std::shared_ptr<Request> req;
+  povar_problem_s* pb = nullptr;
+  int stage = 0;   // its staging record
+};
+
 constexpr int kServerItersPerSync = 4;   // batched iterations between control-block read-backs, at most
 // Problems of more than this many observations form the large class of their
 // precision: each precision's small problems iterate beside its large ones on
@@ -94,7 +105,7 @@ using namespace povar;
 
 struct povar_server_s {
   povar_ctx ctx = nullptr;
-  hipStream_t admit_stream = nullptr;   // admissions, while the groups' iterations run
+  hipStream_t admit_stream = nullptr;   // the admission thread's initialisations
   uint64_t budget = 0;
   int32_t max_slots = 0;
   std::mutex mu;
@@ -107,15 +118,24 @@ struct povar_server_s {
   int32_t n_resident = 0;
   int64_t n_finished = 0, batch_iters = 0;
   int64_t syncs = 0, budget_waits = 0;
-  // worker time (seconds): admission (layout upload, initial landmarks),
-  // enqueueing launches, waiting for the GPU while no read-back has arrived,
-  // retiring finished problems and freeing their memory
+  // time (seconds) of the admission thread initialising requests, and of the
+  // worker enqueueing launches, waiting for the GPU while no read-back has
+  // arrived, retiring finished problems and freeing their memory
   double t_admit = 0.0, t_launch = 0.0, t_wait = 0.0, t_retire = 0.0;
+  // admission: requests admitted and waiting for initialisation, problems
+  // initialised and waiting to join their group, admitted problems not yet in
+  // their group (per group), and the staging records not in use
+  std::condition_variable admit_cv;
+  std::deque<std::shared_ptr<Request>> to_init;
+  std::vector<Ready> ready;
+  int pending[kNumGroups] = {};
+  std::vector<int> free_stage;
+  DevProblem* stage_recs = nullptr;     // device, max_slots records
   Group groups[kNumGroups];
   // worker only: finished problems whose device memory is not yet freed
   std::vector<std::pair<povar_problem_s*, size_t>> retired;
   uint64_t retired_bytes = 0;
-  std::thread worker;
+  std::thread worker, admitter;
   std::chrono::steady_clock::time_point t0;
 
   double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
@@ -183,34 +203,115 @@ hipError_t launch_iteration(Group& G) {
   return launch_decide(B, s);
 }
 
-void admit(povar_server_s* sv, const std::shared_ptr<Request>& r) {
-  Group& G = sv->groups[group_index(r->fp32, r->n_obs)];
-  auto* pb = new povar_problem_s();
-  // the record lies past those of the group's batch in flight, which does not
-  // reach it; the problem joins the batch at the group's next launch
-  const int pos = (int)G.res.size();
-  const int32_t limit = r->opt.max_iters;
-  povar_status st = problem_init(sv->ctx, std::move(r->layout), r->cams0.data(), &r->opt, sv->admit_stream, pb,
-                                 G.recs + pos, limit);
-  r->cams0.clear();
-  r->cams0.shrink_to_fit();
-  if (st != POVAR_OK) {
-    std::string msg = povar_last_error(sv->ctx);
-    povar_problem_destroy(pb);
+// Every resident of the group fails with the device error.
+void fail_group(povar_server_s* sv, Group& G, hipError_t e) {
+  for (auto& R : G.res) {
+    povar_problem_destroy(R.pb);
     {
       std::lock_guard<std::mutex> g(sv->mu);
-      sv->used -= r->footprint;
+      sv->used -= R.req->footprint;
       sv->n_resident -= 1;
     }
-    fail_request(sv, r, st, msg);
-    return;
+    fail_request(sv, R.req, POVAR_EDEVICE, hipGetErrorString(e));
   }
-  {
-    std::lock_guard<std::mutex> g(sv->mu);
-    r->t_admit = sv->now();
-  }
-  G.res.push_back({r, pb, limit});
+  G.res.clear();
   G.dirty = true;
+  G.n_flight = 0;
+}
+
+std::string error_text(povar_ctx ctx) {
+  std::lock_guard<std::mutex> g(ctx->err_mu);
+  return ctx->err;
+}
+
+// Initialises admitted requests, in admission order, into staging records.
+// Every admitted request holds a slot until it finishes, and a staging record
+// only until it joins its group, so a staging record is free for each.
+void admitter_loop(povar_server_s* sv) {
+  (void)hipSetDevice(sv->ctx->device);
+  for (;;) {
+    std::shared_ptr<Request> r;
+    int k = -1;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      sv->admit_cv.wait(lk, [&] { return sv->stop || !sv->to_init.empty(); });
+      if (sv->stop) return;
+      r = sv->to_init.front();
+      sv->to_init.pop_front();
+      if (!sv->free_stage.empty()) {
+        k = sv->free_stage.back();
+        sv->free_stage.pop_back();
+      }
+    }
+    const double t0 = sv->now();
+    const int g = group_index(r->fp32, r->n_obs);
+    auto* pb = new povar_problem_s();
+    povar_status st = POVAR_ESTATE;
+    std::string msg = "no staging record free";
+    if (k >= 0) {
+      st = problem_init(sv->ctx, std::move(r->layout), r->cams0.data(), &r->opt, sv->admit_stream, pb,
+                        sv->stage_recs + k, r->opt.max_iters);
+      if (st != POVAR_OK) msg = error_text(sv->ctx);
+    }
+    r->cams0.clear();
+    r->cams0.shrink_to_fit();
+    if (st != POVAR_OK) {
+      povar_problem_destroy(pb);
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->used -= r->footprint;
+        sv->n_resident -= 1;
+        sv->pending[g] -= 1;
+        if (k >= 0) sv->free_stage.push_back(k);
+        sv->t_admit += sv->now() - t0;
+      }
+      fail_request(sv, r, st, msg);
+      continue;
+    }
+    std::lock_guard<std::mutex> lk(sv->mu);
+    r->t_admit = sv->now();
+    sv->ready.push_back({r, pb, k});
+    sv->t_admit += r->t_admit - t0;
+  }
+}
+
+// Initialised problems whose group is idle join it: the staging record is
+// copied behind the group's records, and released once the copy is done.
+// Returns whether any joined.
+bool join_ready(povar_server_s* sv) {
+  std::vector<Ready> joining;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    std::vector<Ready> keep;
+    for (auto& x : sv->ready) {
+      if (sv->groups[group_index(x.req->fp32, x.req->n_obs)].n_flight == 0) joining.push_back(x);
+      else keep.push_back(x);
+    }
+    sv->ready.swap(keep);
+  }
+  if (joining.empty()) return false;
+  bool copied[kNumGroups] = {};
+  for (auto& x : joining) {
+    const int g = group_index(x.req->fp32, x.req->n_obs);
+    Group& G = sv->groups[g];
+    const int pos = (int)G.res.size();
+    const hipError_t e = hipMemcpyAsync(G.recs + pos, sv->stage_recs + x.stage, sizeof(DevProblem),
+                                        hipMemcpyDeviceToDevice, G.stream);
+    x.pb->batch.probs = G.recs + pos;
+    x.pb->stream = G.stream;
+    G.res.push_back({x.req, x.pb, x.req->opt.max_iters});
+    G.dirty = true;
+    copied[g] = true;
+    if (e != hipSuccess) fail_group(sv, G, e);
+  }
+  for (int g = 0; g < kNumGroups; ++g)
+    if (copied[g]) (void)hipStreamSynchronize(sv->groups[g].stream);
+  std::lock_guard<std::mutex> lk(sv->mu);
+  for (auto& x : joining) {
+    sv->free_stage.push_back(x.stage);
+    sv->pending[group_index(x.req->fp32, x.req->n_obs)] -= 1;
+  }
+  return true;
 }
 
 // Copies the result of resident problem `idx` out, moves the last record into
@@ -264,22 +365,6 @@ void free_retired(povar_server_s* sv) {
   sv->retired_bytes = 0;
 }
 
-// Every resident of the group fails with the device error.
-void fail_group(povar_server_s* sv, Group& G, hipError_t e) {
-  for (auto& R : G.res) {
-    povar_problem_destroy(R.pb);
-    {
-      std::lock_guard<std::mutex> g(sv->mu);
-      sv->used -= R.req->footprint;
-      sv->n_resident -= 1;
-    }
-    fail_request(sv, R.req, POVAR_EDEVICE, hipGetErrorString(e));
-  }
-  G.res.clear();
-  G.dirty = true;
-  G.n_flight = 0;
-}
-
 void worker_loop(povar_server_s* sv) {
   (void)hipSetDevice(sv->ctx->device);
   bool drain = false;   // launches held until no group is in flight, to free retired problems' memory
@@ -293,13 +378,13 @@ void worker_loop(povar_server_s* sv) {
       d_retire += sv->now() - t_pass;
     }
     if (idle) drain = false;
-    std::vector<std::shared_ptr<Request>> admitted;
-    bool joins[kNumGroups] = {};
+    bool progressed = false;
     {
       std::unique_lock<std::mutex> lk(sv->mu);
       if (sv->n_resident == 0 && idle) sv->cv.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
       if (sv->stop) return;
-      // FIFO admission by slot and footprint
+      // FIFO admission by slot and footprint; the admission thread
+      // initialises the admitted requests
       while (!sv->queue.empty()) {
         auto& r = sv->queue.front();
         const bool slot = sv->n_resident < sv->max_slots;
@@ -316,26 +401,33 @@ void worker_loop(povar_server_s* sv) {
         if (!slot || !fits) break;
         sv->used += r->footprint;
         sv->n_resident += 1;
-        joins[group_index(r->fp32, r->n_obs)] = true;
-        admitted.push_back(r);
+        sv->pending[group_index(r->fp32, r->n_obs)] += 1;
+        sv->to_init.push_back(r);
         sv->queue.pop_front();
+        progressed = true;
       }
     }
-    // Idle groups launch their next iterations first; the requests admitted
-    // in this pass are initialised on the admission stream meanwhile.
+    if (progressed) sv->admit_cv.notify_one();
+    // Idle groups take in their initialised newcomers and launch their next
+    // iterations.
     //
     // Iterations per read-back: a problem's iteration count is known exactly
     // (each batched iteration advances every running problem of the group by
-    // one), so as long as no problem can reach its limit and nothing joins
-    // the group, several iterations are enqueued before the control blocks
-    // are read.  A problem that stops earlier by ftol has its remaining
-    // kernels return at once (they check its done flag).
+    // one), so as long as no problem can reach its limit and no admitted
+    // request waits to join the group, several iterations are enqueued before
+    // the control blocks are read.  A problem that stops earlier by ftol has
+    // its remaining kernels return at once (they check its done flag).
     const double t1 = sv->now();
-    bool progressed = !admitted.empty();
+    if (!drain && join_ready(sv)) progressed = true;
+    int pending[kNumGroups];
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      for (int g = 0; g < kNumGroups; ++g) pending[g] = sv->pending[g];
+    }
     for (int g = 0; g < kNumGroups && !drain; ++g) {
       Group& G = sv->groups[g];
       if (G.n_flight > 0 || G.res.empty()) continue;
-      int n_it = joins[g] ? 1 : kServerItersPerSync;
+      int n_it = pending[g] > 0 ? 1 : kServerItersPerSync;
       for (auto& R : G.res) n_it = std::min(n_it, std::max(1, R.left));
       hipError_t e = G.dirty ? upload_tables(sv, G) : hipSuccess;
       for (int i = 0; i < n_it && e == hipSuccess; ++i) e = launch_iteration(G);
@@ -352,9 +444,8 @@ void worker_loop(povar_server_s* sv) {
       progressed = true;
     }
     const double t2 = sv->now();
-    for (auto& r : admitted) admit(sv, r);
-    const double t3 = sv->now();
-    // read-backs that have arrived
+    // read-backs that have arrived (nothing joins a group in flight, so the
+    // read-back covers all of its residents)
     int64_t iters = 0, readbacks = 0;
     for (Group& G : sv->groups) {
       if (G.n_flight == 0) continue;
@@ -378,16 +469,11 @@ void worker_loop(povar_server_s* sv) {
       d_retire += sv->now() - tr;
     }
     if (!progressed) std::this_thread::yield();
-    const double t4 = sv->now();
+    const double t3 = sv->now();
     std::lock_guard<std::mutex> g(sv->mu);
-    if (progressed) {
-      sv->t_launch += t2 - t1;
-      sv->t_admit += t3 - t2;
-      sv->t_retire += d_retire;
-    } else {
-      sv->t_wait += t4 - t_pass - d_retire;
-      sv->t_retire += d_retire;
-    }
+    if (progressed) sv->t_launch += t2 - t1;
+    else sv->t_wait += t3 - t_pass - d_retire;
+    sv->t_retire += d_retire;
     sv->batch_iters += iters;
     sv->syncs += readbacks;
   }
@@ -401,6 +487,9 @@ void free_server(povar_server_s* sv) {
   }
   for (auto& pr : sv->retired) povar_problem_destroy(pr.first);
   sv->retired.clear();
+  for (auto& x : sv->ready) povar_problem_destroy(x.pb);
+  sv->ready.clear();
+  if (sv->stage_recs) (void)hipFree(sv->stage_recs);
   for (Group& G : sv->groups) {
     if (G.recs) (void)hipFree(G.recs);
     if (G.tables) (void)hipFree(G.tables);
@@ -441,6 +530,8 @@ povar_status povar_server_create(povar_ctx ctx, uint64_t hbm_budget_bytes, int32
     if (e == hipSuccess) e = hipMalloc(&G.tables, sizeof(int32_t) * kNumUnitKinds * (max_slots + 1));
     if (e == hipSuccess) e = hipHostMalloc(&G.host_recs, sizeof(DevProblem) * max_slots, hipHostMallocDefault);
   }
+  if (e == hipSuccess) e = hipMalloc(&sv->stage_recs, sizeof(DevProblem) * max_slots);
+  for (int k = max_slots - 1; k >= 0; --k) sv->free_stage.push_back(k);
   if (e != hipSuccess) {
     set_error(ctx, "server allocation failed: %s", hipGetErrorString(e));
     free_server(sv);
@@ -449,6 +540,7 @@ povar_status povar_server_create(povar_ctx ctx, uint64_t hbm_budget_bytes, int32
   }
   ctx->live_problems += 1;
   sv->worker = std::thread(worker_loop, sv);
+  sv->admitter = std::thread(admitter_loop, sv);
   *out = sv;
   return POVAR_OK;
 }
@@ -560,7 +652,9 @@ povar_status povar_server_destroy(povar_server sv) {
     sv->stop = true;
   }
   sv->cv.notify_all();
+  sv->admit_cv.notify_all();
   if (sv->worker.joinable()) sv->worker.join();
+  if (sv->admitter.joinable()) sv->admitter.join();
   (void)hipSetDevice(sv->ctx->device);
   free_server(sv);
   sv->ctx->live_problems -= 1;
