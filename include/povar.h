@@ -411,7 +411,7 @@ povar_status povar_problem_layout(povar_problem pb, int32_t* blocked, int32_t* l
                                   int64_t* n_runs, int32_t* coop_gather);
 
 /* ---- serving: continuous batching of many problems on one GPU ----------- */
-/* A server owns a worker thread and the device state of up to max_slots
+/* A server owns a worker thread, an admission thread and the device state of up to max_slots
    problems whose summed footprint stays within hbm_budget_bytes.  Requests
    wait in a FIFO queue until a slot and enough budget are free.  Admitted
    problems form groups by precision and by size (up to 250,000 observations,
