@@ -411,21 +411,21 @@ povar_status povar_problem_layout(povar_problem pb, int32_t* blocked, int32_t* l
                                   int64_t* n_runs, int32_t* coop_gather);
 
 /* ---- serving: continuous batching of many problems on one GPU ----------- */
-/* A server owns a worker thread, an admission thread and the device state of up to max_slots
-   problems whose summed footprint stays within hbm_budget_bytes.  Requests
-   wait in a FIFO queue until a slot and enough budget are free.  Admitted
-   problems form groups by precision and by size (up to 250,000 observations,
-   or more); each group advances one LM iteration per batched launch sequence
-   on a stream of its own, so small problems are not held to the pace of large
-   ones.  An admission thread initialises admitted requests (device
-   allocation, upload, initial landmark solve) on a stream of its own while
-   the groups' iterations run; an initialised problem joins its group before
-   the group's next launch.  A finished
-   problem's result is copied out at once; its device memory (still counted
-   against the budget) is freed when no group has work in flight, or, when a
-   queued request needs that memory, after the groups in flight finish their
-   current iterations.  Each result is independent of which other problems
-   shared the launches. */
+/* A server owns a worker thread, an admission thread and the device state of
+   up to max_slots problems whose summed footprint stays within
+   hbm_budget_bytes. Requests wait in a FIFO queue until a slot and enough
+   budget are free. Admitted problems form groups by precision and by size
+   (up to 250,000 observations, or more); each group advances one LM
+   iteration per batched launch sequence on a stream of its own, so small
+   problems are not held to the pace of large ones. An admission thread
+   initialises admitted requests (device allocation, upload, initial landmark
+   solve) on a stream of its own while the groups' iterations run; an
+   initialised problem joins its group before the group's next launch. A
+   finished problem's result is copied out at once; its device memory (still
+   counted against the budget) is freed when no group has work in flight, or,
+   when a queued request needs that memory, after the groups in flight finish
+   their current iterations. Each result is independent of which other
+   problems shared the launches. */
 povar_status povar_server_create(povar_ctx ctx, uint64_t hbm_budget_bytes, int32_t max_slots,
                                  povar_server* out);
 /* Copies the request; *ticket identifies it.  cams0 may be NULL (seeded

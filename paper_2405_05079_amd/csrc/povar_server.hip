@@ -368,6 +368,7 @@ void free_retired(povar_server_s* sv) {
 void worker_loop(povar_server_s* sv) {
   (void)hipSetDevice(sv->ctx->device);
   bool drain = false;   // launches held until no group is in flight, to free retired problems' memory
+  double quiet_since = -1.0;   // start of the current run of passes without progress
   for (;;) {
     const double t_pass = sv->now();
     bool idle = true;
@@ -468,7 +469,17 @@ void worker_loop(povar_server_s* sv) {
       }
       d_retire += sv->now() - tr;
     }
-    if (!progressed) std::this_thread::yield();
+    // Without progress the worker polls again at once for 2 ms (batches of
+    // serving-sized problems come back every millisecond or so, and a sleep
+    // between polls measured 3-5% longer median latency), then at 20 us
+    // intervals, so that long batches do not keep a core spinning.
+    if (progressed) {
+      quiet_since = -1.0;
+    } else {
+      if (quiet_since < 0.0) quiet_since = t_pass;
+      if (t_pass - quiet_since < 2e-3) std::this_thread::yield();
+      else std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
     const double t3 = sv->now();
     std::lock_guard<std::mutex> g(sv->mu);
     if (progressed) sv->t_launch += t2 - t1;
