@@ -145,6 +145,40 @@ def test_budget_frees_a_large_problem_while_small_ones_run(ctx):
     assert times[0][2] <= times[3][1] < min(times[1][2], times[2][2])
 
 
+def test_early_stops_in_the_mix_equal_single_solves(ctx):
+    """Problems that stop before their iteration limit by ftol (inside a batch
+    of up to four iterations, whose remaining kernels then return at once for
+    them) and problems whose series stops early by series_rtol, in both size
+    groups: each result equals the same request solved alone, bitwise, with
+    the same iteration count."""
+    probs = [synth.make_problem(52, 52000, track=("geom", 0.25), seed=911),
+             synth.make_problem(20, 2500, track=("geom", 0.25), seed=912),
+             synth.make_problem(45, 6000, track=("geom", 0.25), seed=913),
+             synth.make_problem(30, 4000, track=("geom", 0.25), seed=914)]
+    assert probs[0].n_obs > 250000 >= max(p.n_obs for p in probs[1:])
+    opts = [dict(OPTS, max_iters=40, ftol=0.05), dict(OPTS, max_iters=40, ftol=0.05),
+            dict(OPTS, max_iters=12, series_rtol=0.01), dict(OPTS, max_iters=40, ftol=0.02, series_rtol=0.01)]
+    print("[case] server early stops", flush=True)
+    alone = []
+    for p, o in zip(probs, opts):
+        gp = povar.Problem.from_synth(ctx, p, **o)
+        alone.append((gp.solve(), gp.cameras(), gp.points()))
+        gp.close()
+    iters = [a[0]["iters"] for a in alone]
+    assert [n < o["max_iters"] for n, o in zip(iters, opts)] == [True, True, False, True], iters
+    sv = povar.Server(ctx, hbm_budget_bytes=8 << 30, max_slots=4)
+    try:
+        tickets = [sv.submit(p, **o) for p, o in zip(probs, opts)]
+        res, _ = drain(sv, tickets)
+    finally:
+        sv.close()
+    for t, (rep_a, cams_a, pts_a) in zip(tickets, alone):
+        rep, cams, pts, _ = res[t]
+        np.testing.assert_array_equal(cams, cams_a)
+        np.testing.assert_array_equal(pts, pts_a)
+        assert rep["cost_final"] == rep_a["cost_final"] and rep["iters"] == rep_a["iters"]
+
+
 def test_oversized_and_invalid_requests_are_rejected(ctx):
     prob = requests()[0]
     print("[case] server rejects", flush=True)
