@@ -43,7 +43,9 @@ envelope theorem, dense joint solve, Neumann closed form and bound, Lemma 1,
 tangency and basis invariance, gauge invariance, known zero minimum, the R12
 branch on a block without a Cholesky factor, the series from a given start
 against its dense closed form, the Riemannian gradient against central
-differences, the memory-bounded step against the assembled one).  lm_solve:
+differences, the memory-bounded step against the assembled one, mu_max by
+power iteration against the dense spectrum and the decay of the series
+terms).  lm_solve:
 each step and the accept rule R8 are pinned; the trajectory over many
 iterations has no closed form of its own: parity unpinned beyond those pins.
 """
@@ -265,6 +267,35 @@ def power_series(rs: ReducedSystem, order: int, rtol: float = 0.0):
     return acc, used
 
 
+def spectral_radius(rs: ReducedSystem, iters: int = 20000, tol: float = 1e-10, seed: int = 0) -> float:
+    """mu_max, the largest eigenvalue of M = U~^-1 W~ V^+ W~^T, by power
+    iteration: the series (17) converges when it is below 1 (Lemma 1 /
+    Prop. 1), and its terms shrink like mu_max^t.  M is self-adjoint in the
+    inner product <x, y> = x^T U~ y (U~ M = W~ V^+ W~^T is symmetric), so its
+    eigenvalues are real and non-negative and the Rayleigh quotient
+    mu = x^T W~ V^+ W~^T x / x^T U~ x of the iterate converges to the largest.
+    Stops when the residual |M x - mu x|_U is below tol |x|_U (then mu is
+    within tol^2 / gap of mu_max) or after `iters` steps: the quotient never
+    exceeds mu_max, and with eigenvalues clustered near it (little damping)
+    it approaches it at the rate of their ratio.  A diagnostic for small
+    problems."""
+    n, k = rs.Ut.shape[0], rs.Ut.shape[1]
+    x = np.random.default_rng(seed).standard_normal(n * k)
+    mu = 0.0
+    for _ in range(iters):
+        wvw = rs.Wt @ (rs.Vp_blk @ (rs.Wt.T @ x))            # W~ V^+ W~^T x = U~ M x
+        ux = np.einsum("nkl,nl->nk", rs.Ut, x.reshape(n, k)).reshape(-1)
+        xux = float(x @ ux)
+        mu = float(x @ wvw) / xux
+        y = rs.apply_Uinv(wvw)                             # M x
+        d = y - mu * x
+        res2 = float(d @ np.einsum("nkl,nl->nk", rs.Ut, d.reshape(n, k)).reshape(-1))
+        if res2 <= tol * tol * xux:
+            break
+        x = y / np.linalg.norm(y)
+    return mu
+
+
 def series_from(P: np.ndarray, lin: Linearization, lam: float, x0: np.ndarray, order: int,
                 manifold: str = "sphere") -> np.ndarray:
     """The truncated series of (17) started from a given ambient camera vector:
@@ -337,6 +368,8 @@ class Options:
     lambda_max: float = 1e12
     manifold: str = "sphere"
     rtol: float = 0.0
+    diag: bool = False        # record |b_l|, mu_max per step and the final gradient norm (small problems)
+    mu_iters: int = 2000      # power iterations for each step's mu_max (a lower bound when not converged)
 
 
 @dataclass
@@ -350,6 +383,11 @@ class Result:
     trace_cost: list = field(default_factory=list)      # trial cost of each iteration
     trace_accept: list = field(default_factory=list)
     trace_lambda: list = field(default_factory=list)    # lambda used by each iteration
+    # with Options.diag: |b_l| at each trial point's landmarks, mu_max of each
+    # step's system, |Riemannian gradient| at the final cameras
+    trace_bl: list = field(default_factory=list)
+    trace_mu: list = field(default_factory=list)
+    grad_norm: float = float("nan")
     stop: str = "max_iters"
 
 
@@ -380,11 +418,18 @@ def lm_solve(prob, cams0=None, opts: Options | None = None, lam=None, P=None) ->
         if not factorizable(rs):
             # R12: a step whose damped camera block has no Cholesky factor is rejected
             fn, accepted = np.inf, False
+            if opts.diag:
+                res.trace_bl.append(float("nan"))
+                res.trace_mu.append(float("nan"))
         else:
+            if opts.diag:
+                res.trace_mu.append(spectral_radius(rs, iters=opts.mu_iters))
             xt, _ = power_series(rs, opts.order, opts.rtol)
             Pn = retract(P, back_project(rs, xt), opts.manifold)
             Xn, _ = solve_landmarks(Pn, prob)
             fn = cost(Pn, Xn, prob)
+            if opts.diag:
+                res.trace_bl.append(float(np.linalg.norm(linearize(Pn, Xn, prob).bl)))
             accepted = bool(np.isfinite(fn) and fn < f)
         res.trace_cost.append(fn)
         res.trace_accept.append(accepted)
@@ -400,6 +445,8 @@ def lm_solve(prob, cams0=None, opts: Options | None = None, lam=None, P=None) ->
         else:
             lam = min(lam * 10.0, opts.lambda_max)
     res.P, res.X, res.cost, res.lam = P, X, f, lam
+    if opts.diag:
+        res.grad_norm = float(np.linalg.norm(riemannian_gradient(P, linearize(P, X, prob), opts.manifold)))
     return res
 
 

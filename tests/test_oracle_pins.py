@@ -276,6 +276,56 @@ def test_lemma1_spectrum_in_unit_interval(manifold, lam):
     assert ev.real.min() > -1e-10 and ev.real.max() < 1.0
 
 
+@pytest.mark.parametrize("manifold,lam", [("sphere", 1.0), ("sphere", 0.1), ("euclidean", 1.0)])
+def test_mu_max_by_power_iteration_matches_dense_spectrum(manifold, lam):
+    """The oracle's mu_max (power iteration in the U~ inner product) equals the
+    largest eigenvalue of the densely assembled M (in another tangent basis),
+    and the terms of the series (17) shrink at that rate.  With little damping
+    (eigenvalues clustered below 1) the iteration gives a lower bound."""
+    prob = tiny(n_cams=5, n_pts=40, seed=41)
+    P = synth.init_cameras(prob.n_cams, 42)
+    D = _dense_problem(prob, P, lam, manifold)
+    Vp = np.linalg.pinv(D["V"], rcond=1e-12, hermitian=True)
+    M = np.linalg.solve(D["Ut"], D["W"] @ Vp @ D["W"].T)
+    ev = np.sort(np.linalg.eigvals(M).real)
+    X, _ = O.solve_landmarks(P, prob)
+    rs = O.reduced_system(P, O.linearize(P, X, prob), lam, manifold)
+    mu = O.spectral_radius(rs)
+    assert abs(mu - ev[-1]) <= 1e-8 * ev[-1], (mu, ev[-1])
+    # |x_{t+1}|_U / |x_t|_U of the series terms from x_0 = -U~^-1 g tends to
+    # mu_max at the rate (second eigenvalue / mu_max)^t
+    n, k = rs.Ut.shape[0], rs.Ut.shape[1]
+    unorm = lambda v: np.sqrt(v @ np.einsum("nkl,nl->nk", rs.Ut, v.reshape(n, k)).reshape(-1))
+    x = -rs.apply_Uinv(rs.g)
+    t_end = 400
+    for _ in range(t_end):
+        x_prev, x = x, rs.apply_M(x)
+    ratio = unorm(x) / unorm(x_prev)
+    assert abs(ratio - mu) <= 2 * mu * (ev[-2] / ev[-1]) ** t_end + 1e-9 * mu, (ratio, mu, ev[-2])
+    # clustered spectrum (lambda = 1e-4): a lower bound within the iteration's reach
+    rs4 = O.reduced_system(P, O.linearize(P, X, prob), 1e-4, manifold)
+    D4 = _dense_problem(prob, P, 1e-4, manifold)
+    Vp4 = np.linalg.pinv(D4["V"], rcond=1e-12, hermitian=True)
+    top4 = np.linalg.eigvals(np.linalg.solve(D4["Ut"], D4["W"] @ Vp4 @ D4["W"].T)).real.max()
+    mu4 = O.spectral_radius(rs4, iters=2000)
+    assert top4 - 1e-3 <= mu4 <= top4 + 1e-12
+
+
+def test_lm_diagnostics_mu_bl_and_gradient():
+    """lm_solve's diagnostics: mu_max of every step's system is in [0, 1)
+    (Lemma 1 with damping), |b_l| at each trial point's closed-form landmarks
+    is zero to rounding (they minimise over X), and the final gradient norm is
+    that of riemannian_gradient at the returned cameras."""
+    prob = tiny(n_cams=5, n_pts=40, seed=43)
+    res = O.lm_solve(prob, opts=O.Options(order=10, max_iters=6, ftol=0.0, diag=True))
+    assert len(res.trace_mu) == len(res.trace_bl) == res.iters == 6
+    assert all(0.0 <= m < 1.0 for m in res.trace_mu)
+    for P_scale_bl in res.trace_bl:
+        assert P_scale_bl < 1e-8
+    g = O.riemannian_gradient(res.P, O.linearize(res.P, res.X, prob))
+    assert res.grad_norm == float(np.linalg.norm(g)) and res.grad_norm > 0.0
+
+
 # --------------------------------------------------------------------------- tangent space
 def test_update_is_tangent_and_retraction_normalises():
     prob = tiny(seed=51)
