@@ -452,41 +452,51 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
   L.pk_code.assign(n_ent, 0u);
   L.pk_m64.assign(2 * n_ent, 0.0);
   if (fp32) L.pk_m32.assign(2 * n_ent, 0.0f);
-  for (int32_t jj = 0; jj < n_l; ++jj) {
-    const int32_t j = L.int2ext[jj];
-    const int32_t slot = slot_of[jj];
-    const int32_t local = jj - L.pk_hdr[2 * slot + 1];
-    int64_t e = (int64_t)slot * kWave + pos_in_slot[jj];
-    for (int64_t q = lstart[j]; q < lstart[j + 1]; ++q, ++e) {
-      const int64_t k = lobs[q];
-      L.pk_code[e] = (uint32_t)cam[k] | ((uint32_t)local << kCamBits);
-      L.pk_m64[2 * e] = meas[2 * k];
-      L.pk_m64[2 * e + 1] = meas[2 * k + 1];
-      if (fp32) {
-        L.pk_m32[2 * e] = (float)meas[2 * k];
-        L.pk_m32[2 * e + 1] = (float)meas[2 * k + 1];
+  // filled in the caller's landmark order, so that the observation data are
+  // read in (usually) their own order and each landmark's entries written
+  // where its slot puts them
+  {
+    std::vector<int32_t> lm_ext2int(n_l);
+    for (int32_t jj = 0; jj < n_l; ++jj) lm_ext2int[L.int2ext[jj]] = jj;
+    for (int32_t j = 0; j < n_l; ++j) {
+      const int32_t jj = lm_ext2int[j];
+      const int32_t slot = slot_of[jj];
+      const int32_t local = jj - L.pk_hdr[2 * slot + 1];
+      int64_t e = (int64_t)slot * kWave + pos_in_slot[jj];
+      for (int64_t q = lstart[j]; q < lstart[j + 1]; ++q, ++e) {
+        const int64_t k = lobs[q];
+        L.pk_code[e] = (uint32_t)cam[k] | ((uint32_t)local << kCamBits);
+        L.pk_m64[2 * e] = meas[2 * k];
+        L.pk_m64[2 * e + 1] = meas[2 * k + 1];
+        if (fp32) {
+          L.pk_m32[2 * e] = (float)meas[2 * k];
+          L.pk_m32[2 * e + 1] = (float)meas[2 * k + 1];
+        }
       }
     }
   }
-  // camera-major order: by camera, then internal landmark
+  // camera-major order: by camera, then internal landmark, then the order
+  // within the landmark, which is the order of the packet entries (read
+  // from them in sequence)
   std::vector<int64_t> cstart(n_p + 1, 0);
   for (int32_t i = 0; i < n_p; ++i) cstart[i + 1] = cstart[i] + cnt_c[i];
   L.cm_lm.resize(n_obs);
   if (fp32) L.cm_m32.resize(2 * n_obs); else L.cm_m64.resize(2 * n_obs);
   {
     std::vector<int64_t> fill(cstart.begin(), cstart.end() - 1);
-    for (int32_t jj = 0; jj < n_l; ++jj) {
-      const int32_t j = L.int2ext[jj];
-      for (int64_t q = lstart[j]; q < lstart[j + 1]; ++q) {
-        const int64_t k = lobs[q];
-        const int64_t pos = fill[cam[k]]++;
-        L.cm_lm[pos] = jj;
+    for (int32_t q = 0; q < L.n_pk; ++q) {
+      const int32_t n = L.pk_hdr[2 * q], lm0 = L.pk_hdr[2 * q + 1];
+      // continuation slots (n = 0) hold the tail of the landmark started before
+      for (int64_t e = (int64_t)q * kWave; e < (int64_t)q * kWave + n; ++e) {
+        const uint32_t code = L.pk_code[e];
+        const int64_t pos = fill[code & kCamMask]++;
+        L.cm_lm[pos] = lm0 + (int32_t)(code >> kCamBits);
         if (fp32) {
-          L.cm_m32[2 * pos] = (float)meas[2 * k];
-          L.cm_m32[2 * pos + 1] = (float)meas[2 * k + 1];
+          L.cm_m32[2 * pos] = L.pk_m32[2 * e];
+          L.cm_m32[2 * pos + 1] = L.pk_m32[2 * e + 1];
         } else {
-          L.cm_m64[2 * pos] = meas[2 * k];
-          L.cm_m64[2 * pos + 1] = meas[2 * k + 1];
+          L.cm_m64[2 * pos] = L.pk_m64[2 * e];
+          L.cm_m64[2 * pos + 1] = L.pk_m64[2 * e + 1];
         }
       }
     }
