@@ -12,6 +12,7 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -283,6 +284,27 @@ static povar_status build_camera_slots(povar_ctx ctx, HostLayout& L, const std::
   return POVAR_OK;
 }
 
+// Runs fn(t, begin, end) over T contiguous parts of [0, n) on T threads (the
+// caller's included).  Large layouts use up to four: the parts write
+// disjoint entries, so the result does not depend on T.
+template <typename F>
+static void parallel_parts(int T, int64_t n, F fn) {
+  if (T <= 1) {
+    fn(0, (int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 1; t < T; ++t) th.emplace_back(fn, t, n * t / T, n * (t + 1) / T);
+  fn(0, (int64_t)0, n / T);
+  for (auto& x : th) x.join();
+}
+
+static int layout_threads(int64_t n_obs) {
+  if (n_obs < (1 << 17)) return 1;
+  const unsigned hw = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(4u, hw));
+}
+
 povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs, const int32_t* cam,
                           const int32_t* pt, const double* meas, bool fp32, HostLayout& L) {
   if (n_p <= 0 || n_l <= 0 || n_obs <= 0) {
@@ -389,21 +411,24 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
   }
   // each landmark's observations by camera, stable (insertion sort for the
   // usual short tracks, merge sort for long ones)
-  for (int32_t j = 0; j < n_l; ++j) {
-    int64_t* o = lobs.data() + lstart[j];
-    const int64_t m = lstart[j + 1] - lstart[j];
-    if (m > 32) {
-      std::stable_sort(o, o + m, [&](int64_t a, int64_t b) { return cam[a] < cam[b]; });
-      continue;
+  const int T = layout_threads(n_obs);
+  parallel_parts(T, n_l, [&](int, int64_t j0, int64_t j1) {
+    for (int64_t j = j0; j < j1; ++j) {
+      int64_t* o = lobs.data() + lstart[j];
+      const int64_t m = lstart[j + 1] - lstart[j];
+      if (m > 32) {
+        std::stable_sort(o, o + m, [&](int64_t a, int64_t b) { return cam[a] < cam[b]; });
+        continue;
+      }
+      for (int64_t u = 1; u < m; ++u) {
+        const int64_t x = o[u];
+        const int32_t cx = cam[x];
+        int64_t v = u;
+        for (; v > 0 && cam[o[v - 1]] > cx; --v) o[v] = o[v - 1];
+        o[v] = x;
+      }
     }
-    for (int64_t u = 1; u < m; ++u) {
-      const int64_t x = o[u];
-      const int32_t cx = cam[x];
-      int64_t v = u;
-      for (; v > 0 && cam[o[v - 1]] > cx; --v) o[v] = o[v - 1];
-      o[v] = x;
-    }
-  }
+  });
   if (n_p > (int32_t)kCamMask) {
     set_error(ctx, "n_cams exceeds the supported maximum");
     return POVAR_EINVAL;
@@ -458,22 +483,24 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
   {
     std::vector<int32_t> lm_ext2int(n_l);
     for (int32_t jj = 0; jj < n_l; ++jj) lm_ext2int[L.int2ext[jj]] = jj;
-    for (int32_t j = 0; j < n_l; ++j) {
-      const int32_t jj = lm_ext2int[j];
-      const int32_t slot = slot_of[jj];
-      const int32_t local = jj - L.pk_hdr[2 * slot + 1];
-      int64_t e = (int64_t)slot * kWave + pos_in_slot[jj];
-      for (int64_t q = lstart[j]; q < lstart[j + 1]; ++q, ++e) {
-        const int64_t k = lobs[q];
-        L.pk_code[e] = (uint32_t)cam[k] | ((uint32_t)local << kCamBits);
-        L.pk_m64[2 * e] = meas[2 * k];
-        L.pk_m64[2 * e + 1] = meas[2 * k + 1];
-        if (fp32) {
-          L.pk_m32[2 * e] = (float)meas[2 * k];
-          L.pk_m32[2 * e + 1] = (float)meas[2 * k + 1];
+    parallel_parts(T, n_l, [&](int, int64_t j0, int64_t j1) {
+      for (int64_t j = j0; j < j1; ++j) {
+        const int32_t jj = lm_ext2int[j];
+        const int32_t slot = slot_of[jj];
+        const int32_t local = jj - L.pk_hdr[2 * slot + 1];
+        int64_t e = (int64_t)slot * kWave + pos_in_slot[jj];
+        for (int64_t q = lstart[j]; q < lstart[j + 1]; ++q, ++e) {
+          const int64_t k = lobs[q];
+          L.pk_code[e] = (uint32_t)cam[k] | ((uint32_t)local << kCamBits);
+          L.pk_m64[2 * e] = meas[2 * k];
+          L.pk_m64[2 * e + 1] = meas[2 * k + 1];
+          if (fp32) {
+            L.pk_m32[2 * e] = (float)meas[2 * k];
+            L.pk_m32[2 * e + 1] = (float)meas[2 * k + 1];
+          }
         }
       }
-    }
+    });
   }
   // camera-major order: by camera, then internal landmark, then the order
   // within the landmark, which is the order of the packet entries (read
@@ -483,13 +510,39 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
   L.cm_lm.resize(n_obs);
   if (fp32) L.cm_m32.resize(2 * n_obs); else L.cm_m64.resize(2 * n_obs);
   {
-    std::vector<int64_t> fill(cstart.begin(), cstart.end() - 1);
-    for (int32_t q = 0; q < L.n_pk; ++q) {
-      const int32_t n = L.pk_hdr[2 * q], lm0 = L.pk_hdr[2 * q + 1];
-      // continuation slots (n = 0) hold the tail of the landmark started before
-      for (int64_t e = (int64_t)q * kWave; e < (int64_t)q * kWave + n; ++e) {
+    // with several threads, each takes a contiguous range of slots and
+    // starts each camera after the entries the earlier ranges put there
+    // (counted first), so the order is the sequential one
+    const int Tc = (int64_t)n_p * 64 <= n_obs ? T : 1;
+    std::vector<int64_t> fill((size_t)Tc * n_p);
+    auto walk = [&](int64_t q0, int64_t q1, auto&& visit) {
+      for (int64_t q = q0; q < q1; ++q) {
+        const int32_t n = L.pk_hdr[2 * q], lm0 = L.pk_hdr[2 * q + 1];
+        // continuation slots (n = 0) hold the tail of the landmark started before
+        for (int64_t e = q * kWave; e < q * kWave + n; ++e) visit(e, lm0);
+      }
+    };
+    if (Tc > 1) {
+      std::vector<int64_t> cnt((size_t)Tc * n_p, 0);
+      parallel_parts(Tc, L.n_pk, [&](int t, int64_t q0, int64_t q1) {
+        int64_t* c = cnt.data() + (size_t)t * n_p;
+        walk(q0, q1, [&](int64_t e, int32_t) { ++c[L.pk_code[e] & kCamMask]; });
+      });
+      for (int32_t i = 0; i < n_p; ++i) {
+        int64_t at = cstart[i];
+        for (int t = 0; t < Tc; ++t) {
+          fill[(size_t)t * n_p + i] = at;
+          at += cnt[(size_t)t * n_p + i];
+        }
+      }
+    } else {
+      for (int32_t i = 0; i < n_p; ++i) fill[i] = cstart[i];
+    }
+    parallel_parts(Tc, L.n_pk, [&](int t, int64_t q0, int64_t q1) {
+      int64_t* f = fill.data() + (size_t)t * n_p;
+      walk(q0, q1, [&](int64_t e, int32_t lm0) {
         const uint32_t code = L.pk_code[e];
-        const int64_t pos = fill[code & kCamMask]++;
+        const int64_t pos = f[code & kCamMask]++;
         L.cm_lm[pos] = lm0 + (int32_t)(code >> kCamBits);
         if (fp32) {
           L.cm_m32[2 * pos] = L.pk_m32[2 * e];
@@ -498,8 +551,8 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
           L.cm_m64[2 * pos] = L.pk_m64[2 * e];
           L.cm_m64[2 * pos + 1] = L.pk_m64[2 * e + 1];
         }
-      }
-    }
+      });
+    });
   }
   // chunks of <= kChunk observations, never spanning two cameras
   L.cam_ch.resize(n_p + 1);
