@@ -234,8 +234,23 @@ def matched_cost_row(ctx, prob, rates: dict):
                          "rel_vs_ref_at_ref_iters": float((best32[n - 1] - f_ref) / f_ref)}}
     s32 = out["fp32_bulk"]["seconds_to_match"]
     out["speedup_fp32_over_fp64_at_matched_cost"] = (out["fp64"]["seconds_to_match"] / s32) if s32 else None
+    # the same target with both paths damped no lower than 1e-6 (the default
+    # floor is 1e-12): below it the FP32 series' rounding makes steps fail
+    floor = {"lambda_min": DAMPING_FLOOR_ALT}
+    for prec in ("fp64", "fp32_bulk"):
+        gp = povar.Problem.from_synth(ctx, prob, precision=prec, ftol=0.0, max_iters=2 * n,
+                                      lambda_min=DAMPING_FLOOR_ALT)
+        it, _ = iters_to_reach(gp, 2 * n, target)
+        gp.close()
+        floor[prec] = {"iters_to_match": it, "seconds_to_match": (it / rates[prec]) if it else None}
+    a, b = floor["fp64"]["seconds_to_match"], floor["fp32_bulk"]["seconds_to_match"]
+    floor["speedup_fp32_over_fp64_at_matched_cost"] = (a / b) if a and b else None
+    out["both_with_lambda_min_1e-6"] = floor
     return out
 
+
+# damping floor of the second matched-cost comparison at the large workloads
+DAMPING_FLOOR_ALT = 1e-6
 
 BUCKETS = [(20, 40), (40, 80), (80, 160), (160, 320), (320, 401)]
 # Arrival rate of the serving leg: 0.8 x the closed-loop throughput of the
@@ -737,6 +752,9 @@ def main():
                 mc = row["matched_cost"]
                 log(f"  matched cost: FP64 {mc['fp64']['iters_to_match']} iterations, FP32-bulk "
                     f"{mc['fp32_bulk']['iters_to_match']}, speedup {mc['speedup_fp32_over_fp64_at_matched_cost']}")
+                fl = mc["both_with_lambda_min_1e-6"]
+                log(f"  both with lambda_min 1e-6: FP64 {fl['fp64']['iters_to_match']}, FP32-bulk "
+                    f"{fl['fp32_bulk']['iters_to_match']}, speedup {fl['speedup_fp32_over_fp64_at_matched_cost']}")
             out["roofline_rows"][f"workload{w}"] = row
             del pw
     if not args.no_matched:
