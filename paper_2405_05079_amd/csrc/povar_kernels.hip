@@ -743,8 +743,12 @@ __global__ void __launch_bounds__(kBlock) k_cost_finalize(Batch B, int mode) {
 // values of U_i = sum N_k (x) x~x~^T (N has fixed entries 1 and 0 in its
 // top-left 2x2 block, so U_i is made of sum x~x~^T, sum m1 x~x~^T, sum m2 x~x~^T
 // and sum |m|^2 x~x~^T), b_p = sum vec((N y - eta (m,0)) x~^T) and
-// sum_k W_k z0_j = sum vec((N Pbar z0) x~^T); products in T.  Writes one
-// 64-value partial per chunk; k_camera_prep adds a camera's chunks in order.
+// sum_k W_k z0_j = sum vec((N Pbar z0) x~^T).  U_i is formed from the FP64
+// landmark copy with FP64 products in both precisions: the damped camera
+// block is factored in FP64, and at small damping its weakest directions
+// turn the rounding of an FP32-formed U_i into steps that fail.  The other
+// products are in T.  Writes one 64-value partial per chunk; k_camera_prep
+// adds a camera's chunks in order.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
   int p, ch;
@@ -791,16 +795,24 @@ __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
     apply_N(am1, am2, amsq, q[0], q[1], q[2], vq[0], vq[1], vq[2]);
     nv[0] -= eta * m.x;
     nv[1] -= eta * m.y;
+    double X64[4];
+    if constexpr (sizeof(T) == 4) {
+      load4((lc ? D.rec64[1] : D.rec64[0]) + (size_t)j * kRec + 4, X64[0], X64[1], X64[2], X64[3]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) X64[c] = x[c];
+    }
+    const double mx = m.x, my = m.y, ms = mx * mx + my * my;
     int o = 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
 #pragma unroll
       for (int d = c; d < 4; ++d) {
-        const T xx = x[c] * x[d];
-        acc[o] += (double)xx;
-        acc[10 + o] += (double)(m.x * xx);
-        acc[20 + o] += (double)(m.y * xx);
-        acc[30 + o] += (double)(msq * xx);
+        const double xx = X64[c] * X64[d];
+        acc[o] += xx;
+        acc[10 + o] += mx * xx;
+        acc[20 + o] += my * xx;
+        acc[30 + o] += ms * xx;
         ++o;
       }
     }
