@@ -744,10 +744,10 @@ __global__ void __launch_bounds__(kBlock) k_cost_finalize(Batch B, int mode) {
 // top-left 2x2 block, so U_i is made of sum x~x~^T, sum m1 x~x~^T, sum m2 x~x~^T
 // and sum |m|^2 x~x~^T), b_p = sum vec((N y - eta (m,0)) x~^T) and
 // sum_k W_k z0_j = sum vec((N Pbar z0) x~^T).  U_i is formed from the FP64
-// landmark copy with FP64 products in both precisions: the damped camera
-// block is factored in FP64, and at small damping its weakest directions
-// turn the rounding of an FP32-formed U_i into steps that fail.  The other
-// products are in T.  Writes one 64-value partial per chunk; k_camera_prep
+// landmark copy and the FP64 measurements with FP64 products in both
+// precisions: the damped camera block is factored in FP64, and at small
+// damping its weakest directions turn the rounding of an FP32-formed U_i
+// into steps that fail.  The other products are in T.  Writes one 64-value partial per chunk; k_camera_prep
 // adds a camera's chunks in order.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
@@ -802,7 +802,13 @@ __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) X64[c] = x[c];
     }
-    const double mx = m.x, my = m.y, ms = mx * mx + my * my;
+    double mx = m.x, my = m.y;
+    if constexpr (sizeof(T) == 4) {
+      const double2 m64 = D.cm_m64[e];
+      mx = m64.x;
+      my = m64.y;
+    }
+    const double ms = mx * mx + my * my;
     int o = 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {

@@ -65,7 +65,7 @@ size_t arena_bytes(const LayoutSizes& z, bool fp32, int64_t trace_cap, ArenaOffs
   r.pk_m64 = a.take(n_ent * 16);
   r.cm_lm = a.take(n_obs * 4);
   r.cm_m32 = fp32 ? a.take(n_obs * 8) : SIZE_MAX;
-  r.cm_m64 = fp32 ? SIZE_MAX : a.take(n_obs * 16);
+  r.cm_m64 = a.take(n_obs * 16);   // FP32-bulk too: its linearisation forms U_i in FP64
   r.ch_meta = a.take(n_ch * 16);
   r.cam_ch = a.take((n_p + 1) * 4);
   r.mc_cam = a.take(n_mc * 4);
@@ -508,7 +508,8 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
   std::vector<int64_t> cstart(n_p + 1, 0);
   for (int32_t i = 0; i < n_p; ++i) cstart[i + 1] = cstart[i] + cnt_c[i];
   L.cm_lm.resize(n_obs);
-  if (fp32) L.cm_m32.resize(2 * n_obs); else L.cm_m64.resize(2 * n_obs);
+  if (fp32) L.cm_m32.resize(2 * n_obs);
+  L.cm_m64.resize(2 * n_obs);
   {
     // with several threads, each takes a contiguous range of slots and
     // starts each camera after the entries the earlier ranges put there
@@ -547,10 +548,9 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
         if (fp32) {
           L.cm_m32[2 * pos] = L.pk_m32[2 * e];
           L.cm_m32[2 * pos + 1] = L.pk_m32[2 * e + 1];
-        } else {
-          L.cm_m64[2 * pos] = L.pk_m64[2 * e];
-          L.cm_m64[2 * pos + 1] = L.pk_m64[2 * e + 1];
         }
+        L.cm_m64[2 * pos] = L.pk_m64[2 * e];
+        L.cm_m64[2 * pos + 1] = L.pk_m64[2 * e + 1];
       });
     });
   }
@@ -640,7 +640,8 @@ static povar_status check_layout(const HostLayout& L, const int32_t* cam, const 
   // camera-major chunks: consecutive, at most kChunk observations, one camera each
   {
     if ((int64_t)L.cm_lm.size() != n_obs) return fail("camera-major size", L.cm_lm.size(), n_obs);
-    std::vector<Obs> got;
+    if ((int64_t)L.cm_m64.size() != 2 * n_obs) return fail("camera-major FP64 size", L.cm_m64.size(), n_obs);
+    std::vector<Obs> got, got64;
     int64_t pos = 0;
     for (int32_t i = 0; i < n_p; ++i) {
       if (L.cam_ch[i + 1] <= L.cam_ch[i]) return fail("camera without a chunk", i, L.cam_ch[i]);
@@ -654,6 +655,10 @@ static povar_status check_layout(const HostLayout& L, const int32_t* cam, const 
           prev = L.cm_lm[e];
           got.push_back(Obs(i, L.cm_lm[e], fp32 ? L.cm_m32[2 * e] : L.cm_m64[2 * e],
                             fp32 ? L.cm_m32[2 * e + 1] : L.cm_m64[2 * e + 1]));
+          // the FP64 measurements beside the bulk ones (FP32-bulk forms U_i from them)
+          if (fp32 && ((float)L.cm_m64[2 * e] != L.cm_m32[2 * e] || (float)L.cm_m64[2 * e + 1] != L.cm_m32[2 * e + 1]))
+            return fail("camera-major FP64 measurement", i, e);
+          if (fp32) got64.push_back(Obs(i, L.cm_lm[e], L.cm_m64[2 * e], L.cm_m64[2 * e + 1]));
         }
         pos = m[2];
       }
@@ -661,6 +666,8 @@ static povar_status check_layout(const HostLayout& L, const int32_t* cam, const 
     if (pos != n_obs) return fail("chunks end early", pos, n_obs);
     std::sort(got.begin(), got.end());
     if (got != want) return fail("chunks do not hold every observation once", (long long)got.size(), n_obs);
+    std::sort(got64.begin(), got64.end());
+    if (fp32 && got64 != want64) return fail("camera-major FP64 measurements", (long long)got64.size(), n_obs);
     int32_t n_mc = 0;
     for (int32_t i = 0; i < n_p; ++i)
       if (L.cam_ch[i + 1] - L.cam_ch[i] > 1 && (n_mc >= L.n_mc || L.mc_cam[n_mc++] != i))
