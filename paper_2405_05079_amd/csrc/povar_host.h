@@ -62,7 +62,7 @@ inline LayoutSizes sizes_of(const HostLayout& L) {
 struct ArenaOffsets {
   size_t pk_hdr, pk_code, pk_m32, pk_m64, cm_lm, cm_m32, cm_m64, ch_meta, cam_ch, mc_cam;
   size_t cs_hdr, cs_lane, cs_lm, cs_m32, cs_m64, run_off, smc, t_run;
-  size_t P64[2], S32[2], S64[2], rec64[2], rec32[2], xs64[2], xs32[2], Vp64[2];
+  size_t P64[2], S32[2], S64[2], rec64[2], xs64[2], xs32[2], Vp64[2];
   size_t lin_part, K64, g64, U40, acc, zx, t_part, cost_part, cost_group, bl_part, bl_group;
   size_t tr_cost, tr_lambda, tr_acc, tr_bl, tr_series, rec, tables;
   size_t init_end;   // buffers with initial values lie below this offset

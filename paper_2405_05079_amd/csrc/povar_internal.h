@@ -116,7 +116,6 @@ struct DevProblem {
   // landmarks of the current linearisation / trial point, internal order:
   // record (z0 = V^+ b_l, X) per landmark, and V^+
   double POVAR_GMEM* rec64[2];         // n_l x 8
-  float POVAR_GMEM* rec32[2];
   // (X, 1) of the same records, compact (n_l x 4): what the landmark series
   // pass reads, half the bytes of the full records
   double POVAR_GMEM* xs64[2];

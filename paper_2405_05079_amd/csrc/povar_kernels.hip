@@ -338,7 +338,6 @@ template <> struct Prec<float> {
   __device__ static const float2 POVAR_GMEM* cs_m(const DevProblem& D) { return D.cs_m32; }
   // series record of buffer b: P at 0, x at kSerX (stride s_stride)
   __device__ static float POVAR_GMEM* S(const DevProblem& D, int b) { return b ? D.S32[1] : D.S32[0]; }
-  __device__ static const float POVAR_GMEM* rec(const DevProblem& D, int b) { return b ? D.rec32[1] : D.rec32[0]; }
   __device__ static const float POVAR_GMEM* xs(const DevProblem& D, int b) { return b ? D.xs32[1] : D.xs32[0]; }
 };
 template <> struct Prec<double> {
@@ -347,7 +346,6 @@ template <> struct Prec<double> {
   __device__ static const double2 POVAR_GMEM* pk_m(const DevProblem& D) { return D.pk_m64; }
   __device__ static const double2 POVAR_GMEM* cs_m(const DevProblem& D) { return D.cs_m64; }
   __device__ static double POVAR_GMEM* S(const DevProblem& D, int b) { return b ? D.S64[1] : D.S64[0]; }
-  __device__ static const double POVAR_GMEM* rec(const DevProblem& D, int b) { return b ? D.rec64[1] : D.rec64[0]; }
   __device__ static const double POVAR_GMEM* xs(const DevProblem& D, int b) { return b ? D.xs64[1] : D.xs64[0]; }
 };
 
@@ -532,12 +530,9 @@ __device__ __forceinline__ void store_landmark(DevProblem& D, int lc, int j, con
   const double z1 = vp[1] * bl[0] + vp[3] * bl[1] + vp[4] * bl[2];
   const double z2 = vp[2] * bl[0] + vp[4] * bl[1] + vp[5] * bl[2];
   double* r64 = (lc ? D.rec64[1] : D.rec64[0]) + (size_t)j * kRec;
-  float* r32 = (lc ? D.rec32[1] : D.rec32[0]) + (size_t)j * kRec;
   double* v64 = (lc ? D.Vp64[1] : D.Vp64[0]) + (size_t)j * kLmSym;
   store4(r64, z0, z1, z2, 0.0);
   store4(r64 + 4, X0, X1, X2, 1.0);
-  store4(r32, (float)z0, (float)z1, (float)z2, 0.0f);
-  store4(r32 + 4, (float)X0, (float)X1, (float)X2, 1.0f);
   store4((lc ? D.xs64[1] : D.xs64[0]) + (size_t)j * 4, X0, X1, X2, 1.0);
   store4((lc ? D.xs32[1] : D.xs32[0]) + (size_t)j * 4, (float)X0, (float)X1, (float)X2, 1.0f);
   store4(v64, vp[0], vp[1], vp[2], vp[3]);
@@ -763,8 +758,11 @@ __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
   const int cam = meta.x, beg = meta.y, end = meta.z;
   T Pc[12];
   load12(Prec<T>::S(D, pc) + (size_t)cam * D.s_stride, Pc);
-  const T* __restrict__ rec = Prec<T>::rec(D, lc);
-  const typename Prec<T>::T2* __restrict__ M = Prec<T>::cm_m(D);
+  // landmarks and measurements are read in FP64 in both precisions (U_i is
+  // formed from them) and rounded to T for the other sums: the rounded values
+  // are the FP32 copies the series passes use
+  const double* __restrict__ rec = lc ? D.rec64[1] : D.rec64[0];
+  const double2* __restrict__ M = D.cm_m64;
   const int32_t* __restrict__ lm = D.cm_lm;
   const T eta = (T)D.eta, a = (T)(1.0 - D.eta);
 
@@ -779,10 +777,19 @@ __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
     const int e = beg + r * kBlock + (int)threadIdx.x;
     if (e >= end) break;
     const int j = lm[e];
-    const auto m = M[e];
+    const double2 m64 = M[e];
+    double z64[4], X64[4];
+    load4(rec + (size_t)j * kRec, z64[0], z64[1], z64[2], z64[3]);
+    load4(rec + (size_t)j * kRec + 4, X64[0], X64[1], X64[2], X64[3]);
     T z[4], x[4];
-    load4(rec + (size_t)j * kRec, z[0], z[1], z[2], z[3]);
-    load4(rec + (size_t)j * kRec + 4, x[0], x[1], x[2], x[3]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      z[c] = (T)z64[c];
+      x[c] = (T)X64[c];
+    }
+    struct {
+      T x, y;
+    } const m = {(T)m64.x, (T)m64.y};
     const T am1 = a * m.x, am2 = a * m.y, msq = m.x * m.x + m.y * m.y, amsq = a * msq;
     T y[3], q[3];
 #pragma unroll
@@ -795,20 +802,7 @@ __global__ void __launch_bounds__(kBlock) k_linearize(Batch B, int force) {
     apply_N(am1, am2, amsq, q[0], q[1], q[2], vq[0], vq[1], vq[2]);
     nv[0] -= eta * m.x;
     nv[1] -= eta * m.y;
-    double X64[4];
-    if constexpr (sizeof(T) == 4) {
-      load4((lc ? D.rec64[1] : D.rec64[0]) + (size_t)j * kRec + 4, X64[0], X64[1], X64[2], X64[3]);
-    } else {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) X64[c] = x[c];
-    }
-    double mx = m.x, my = m.y;
-    if constexpr (sizeof(T) == 4) {
-      const double2 m64 = D.cm_m64[e];
-      mx = m64.x;
-      my = m64.y;
-    }
-    const double ms = mx * mx + my * my;
+    const double mx = m64.x, my = m64.y, ms = mx * mx + my * my;
     int o = 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {

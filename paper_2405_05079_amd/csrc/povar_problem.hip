@@ -96,7 +96,6 @@ size_t arena_bytes(const LayoutSizes& z, bool fp32, int64_t trace_cap, ArenaOffs
       r.S64[b] = fp32 ? SIZE_MAX : a.take(n_p * ser_stride((int)n_p) * 8);
       r.rec64[b] = a.take(n_l * kRec * 8);
     }
-    r.rec32[b] = a.take(n_l * kRec * 4);
     r.xs64[b] = a.take(n_l * 4 * 8);
     r.xs32[b] = a.take(n_l * 4 * 4);
     r.Vp64[b] = a.take(n_l * kLmSym * 8);
@@ -913,7 +912,6 @@ povar_status problem_init(povar_ctx ctx, HostLayout&& L, const double* cams0, co
     R.S32[b] = (float*)dp(A.S32[b]);
     R.S64[b] = (double*)dp(A.S64[b]);
     R.rec64[b] = (double*)dp(A.rec64[b]);
-    R.rec32[b] = (float*)dp(A.rec32[b]);
     R.xs64[b] = (double*)dp(A.xs64[b]);
     R.xs32[b] = (float*)dp(A.xs32[b]);
     R.Vp64[b] = (double*)dp(A.Vp64[b]);
