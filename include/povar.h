@@ -69,7 +69,9 @@ typedef enum {
      accumulation (the per-observation products and their per-landmark and
      per-camera sums); the V_j pseudo-inverse, the U_i factorisation (and
      their application to those sums inside the series) and the cost in FP64.
-     U_i and b_p are FP32 products accumulated in FP64. */
+     U_i is formed in FP64 from FP64 landmarks and measurements (its FP64
+     factorisation needs an FP64 input at small damping); b_p is FP32
+     products accumulated in FP64. */
   POVAR_PREC_FP32_BULK = 1
 } povar_precision;
 
