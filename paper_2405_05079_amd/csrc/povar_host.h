@@ -3,6 +3,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <exception>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -73,6 +74,19 @@ povar_status build_layout(povar_ctx ctx, int32_t n_p, int32_t n_l, int64_t n_obs
                           const int32_t* pt, const double* meas, bool fp32, HostLayout& L);
 povar_status check_options(povar_ctx ctx, const povar_options* o);
 void set_error(povar_ctx ctx, const char* fmt, ...);
+
+// Turns a host exception (host memory or threads exhausted) into an error
+// status.  The C entry points that allocate host memory end with it as the
+// handler of a function-try-block, so that no exception leaves the C ABI.
+#define POVAR_HOST_CATCH(ctxexpr)                                                \
+  catch (const std::exception& povar_ex_) {                                     \
+    povar::set_error((ctxexpr), "host resources exhausted: %s", povar_ex_.what()); \
+    return POVAR_ENOMEM;                                                        \
+  }                                                                             \
+  catch (...) {                                                                 \
+    povar::set_error((ctxexpr), "unexpected host exception");                   \
+    return POVAR_EDEVICE;                                                       \
+  }
 
 struct TimedPair {
   hipEvent_t start, stop;

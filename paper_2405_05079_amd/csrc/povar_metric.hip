@@ -623,19 +623,19 @@ using namespace povar;
 extern "C" povar_status povar_metric_upgrade(povar_ctx ctx, int32_t n_cams, const double* cams, const double* K,
                                              int32_t max_iters, double ftol, double* H, double* c, double* alpha,
                                              double* R, double* t, double* trace_cost, int32_t* trace_accept,
-                                             povar_metric_report* rep) {
+                                             povar_metric_report* rep) try {
   if (!ctx) return POVAR_EINVAL;
   MetricRun run;
   povar_status st = metric_setup(ctx, n_cams, cams, K, max_iters, ftol, run, nullptr);
   if (st != POVAR_OK) return st;
   return metric_solve(ctx, run, n_cams, max_iters, H, c, alpha, R, t, trace_cost, trace_accept, rep);
-}
+} POVAR_HOST_CATCH(ctx)
 
 extern "C" povar_status povar_metric_upgrade_noalloc(povar_ctx ctx, int32_t n_cams, const double* cams,
                                                      const double* K, int32_t max_iters, double ftol, double* H,
                                                      double* c, double* alpha, double* R, double* t,
                                                      double* trace_cost, int32_t* trace_accept,
-                                                     povar_metric_report* rep) {
+                                                     povar_metric_report* rep) try {
   if (!ctx) return POVAR_EINVAL;
   char* base = metric_scratch(ctx->device);
   if (!base) {
@@ -647,11 +647,11 @@ extern "C" povar_status povar_metric_upgrade_noalloc(povar_ctx ctx, int32_t n_ca
   povar_status st = metric_setup(ctx, n_cams, cams, K, max_iters, ftol, run, base);
   if (st != POVAR_OK) return st;
   return metric_solve(ctx, run, n_cams, max_iters, H, c, alpha, R, t, trace_cost, trace_accept, rep);
-}
+} POVAR_HOST_CATCH(ctx)
 
 extern "C" povar_status povar_metric_debug_reduced(povar_ctx ctx, int32_t n_cams, const double* cams,
                                                    const double* K, const double* c, double* alpha, double* JtJ,
-                                                   double* Jtr, double* cost) {
+                                                   double* Jtr, double* cost) try {
   if (!ctx) return POVAR_EINVAL;
   if (!c || !std::isfinite(c[0]) || !std::isfinite(c[1]) || !std::isfinite(c[2])) {
     set_error(ctx, "c must be three finite values");
@@ -686,4 +686,4 @@ extern "C" povar_status povar_metric_debug_reduced(povar_ctx ctx, int32_t n_cams
     for (int k = 0; k < 3; ++k) Jtr[k] = C.g[k];
   if (cost) *cost = C.cost;
   return POVAR_OK;
-}
+} POVAR_HOST_CATCH(ctx)

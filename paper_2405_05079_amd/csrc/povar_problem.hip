@@ -12,6 +12,7 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <tuple>
 #include <vector>
@@ -293,7 +294,13 @@ static void parallel_parts(int T, int64_t n, F fn) {
     return;
   }
   std::vector<std::thread> th;
-  for (int t = 1; t < T; ++t) th.emplace_back(fn, t, n * t / T, n * (t + 1) / T);
+  int t = 1;
+  try {
+    for (; t < T; ++t) th.emplace_back(fn, t, n * t / T, n * (t + 1) / T);
+  } catch (const std::system_error&) {
+    // no thread to be had: the caller takes the parts left over
+  }
+  for (int u = t; u < T; ++u) fn(u, n * u / T, n * (u + 1) / T);
   fn(0, (int64_t)0, n / T);
   for (auto& x : th) x.join();
 }
@@ -1318,7 +1325,7 @@ povar_status povar_options_default(povar_options* o) {
   return POVAR_OK;
 }
 
-povar_status povar_ctx_create(int device, void* hip_stream, povar_ctx* out) {
+povar_status povar_ctx_create(int device, void* hip_stream, povar_ctx* out) try {
   if (!out) return POVAR_EINVAL;
   *out = nullptr;
   int n = 0;
@@ -1362,7 +1369,7 @@ povar_status povar_ctx_create(int device, void* hip_stream, povar_ctx* out) {
   }
   *out = c;
   return POVAR_OK;
-}
+} POVAR_HOST_CATCH(nullptr)
 
 povar_status povar_ctx_destroy(povar_ctx ctx) {
   if (!ctx) return POVAR_EINVAL;
@@ -1414,7 +1421,7 @@ povar_status povar_problem_footprint(int32_t n_cams, int32_t n_pts, int64_t n_ob
 
 povar_status povar_problem_create(povar_ctx ctx, int32_t n_cams, int32_t n_pts, int64_t n_obs,
                                   const int32_t* cam_idx, const int32_t* pt_idx, const double* meas,
-                                  const double* cams0, const povar_options* opts, povar_problem* out) {
+                                  const double* cams0, const povar_options* opts, povar_problem* out) try {
   if (!ctx || !out) return POVAR_EINVAL;
   *out = nullptr;
   povar_status st = check_options(ctx, opts);
@@ -1445,11 +1452,11 @@ povar_status povar_problem_create(povar_ctx ctx, int32_t n_cams, int32_t n_pts, 
   }
   *out = pb;
   return POVAR_OK;
-}
+} POVAR_HOST_CATCH(ctx)
 
 povar_status povar_problem_create_device(povar_ctx ctx, int32_t n_cams, int32_t n_pts, int64_t n_obs,
                                          const int32_t* cam_idx, const int32_t* pt_idx, const double* meas,
-                                         const double* cams0, const povar_options* opts, povar_problem* out) {
+                                         const double* cams0, const povar_options* opts, povar_problem* out) try {
   if (!ctx || !out) return POVAR_EINVAL;
   if (n_cams <= 0 || n_pts <= 0 || n_obs <= 0 || !cam_idx || !pt_idx || !meas) {
     set_error(ctx, "invalid sizes or NULL device pointers");
@@ -1465,7 +1472,7 @@ povar_status povar_problem_create_device(povar_ctx ctx, int32_t n_cams, int32_t 
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   return povar_problem_create(ctx, n_cams, n_pts, n_obs, c.data(), p.data(), m.data(),
                               cams0 ? q.data() : nullptr, opts, out);
-}
+} POVAR_HOST_CATCH(ctx)
 
 povar_status povar_problem_destroy(povar_problem pb) {
   if (!pb) return POVAR_EINVAL;
@@ -1550,7 +1557,7 @@ povar_status povar_get_report(povar_problem pb, povar_report* report) {
   return POVAR_OK;
 }
 
-povar_status povar_get_cameras(povar_problem pb, double* out) {
+povar_status povar_get_cameras(povar_problem pb, double* out) try {
   if (!pb || !out) return POVAR_EINVAL;
   Ctl c;
   HIP_TRY(pb->ctx, read_ctl(pb, &c));
@@ -1560,9 +1567,9 @@ povar_status povar_get_cameras(povar_problem pb, double* out) {
   HIP_TRY(pb->ctx, hipStreamSynchronize(pb->stream));
   cams_to_caller(pb->L, tmp.data(), out, kCam);
   return POVAR_OK;
-}
+} POVAR_HOST_CATCH(pb ? pb->ctx : nullptr)
 
-povar_status povar_get_points(povar_problem pb, double* out) {
+povar_status povar_get_points(povar_problem pb, double* out) try {
   if (!pb || !out) return POVAR_EINVAL;
   Ctl c;
   HIP_TRY(pb->ctx, read_ctl(pb, &c));
@@ -1573,20 +1580,20 @@ povar_status povar_get_points(povar_problem pb, double* out) {
   for (int32_t j = 0; j < pb->L.n_l; ++j)
     for (int k = 0; k < 3; ++k) out[(size_t)j * 3 + k] = h[(size_t)j * 4 + k] / h[(size_t)j * 4 + 3];
   return POVAR_OK;
-}
+} POVAR_HOST_CATCH(pb ? pb->ctx : nullptr)
 
-povar_status povar_get_points_h(povar_problem pb, double* out) {
+povar_status povar_get_points_h(povar_problem pb, double* out) try {
   if (!pb || !out) return POVAR_EINVAL;
   Ctl c;
   HIP_TRY(pb->ctx, read_ctl(pb, &c));
   if (pb->rec.stage == 2) return copy_landmark_vec(pb, pb->rec.rec64[c.lcur], kX2, 0, 4, out);
   return copy_landmark_vec(pb, pb->rec.rec64[c.lcur], kRec, 4, 4, out);
-}
+} POVAR_HOST_CATCH(pb ? pb->ctx : nullptr)
 
 povar_status povar_refine_create(povar_ctx ctx, int32_t n_cams, int32_t n_pts, int64_t n_obs,
                                  const int32_t* cam_idx, const int32_t* pt_idx, const double* meas,
                                  const double* cams0, const double* pts0, const povar_options* opts,
-                                 povar_problem* out) {
+                                 povar_problem* out) try {
   if (!ctx || !out) return POVAR_EINVAL;
   *out = nullptr;
   povar_status st = check_options(ctx, opts);
@@ -1614,7 +1621,7 @@ povar_status povar_refine_create(povar_ctx ctx, int32_t n_cams, int32_t n_pts, i
   }
   *out = pb;
   return POVAR_OK;
-}
+} POVAR_HOST_CATCH(ctx)
 
 
 
@@ -1651,7 +1658,7 @@ povar_status povar_get_trace_diag(povar_problem pb, int32_t n, double* bl_norm, 
   return POVAR_OK;
 }
 
-povar_status povar_get_state(povar_problem pb, double* cams, double* lambda, int32_t* iter, double* cost) {
+povar_status povar_get_state(povar_problem pb, double* cams, double* lambda, int32_t* iter, double* cost) try {
   if (!pb) return POVAR_EINVAL;
   Ctl c;
   HIP_TRY(pb->ctx, read_ctl(pb, &c));
@@ -1663,9 +1670,9 @@ povar_status povar_get_state(povar_problem pb, double* cams, double* lambda, int
   if (iter) *iter = c.iter;
   if (cost) *cost = c.cost;
   return POVAR_OK;
-}
+} POVAR_HOST_CATCH(pb ? pb->ctx : nullptr)
 
-povar_status povar_set_state(povar_problem pb, const double* cams, double lambda, int32_t iter) {
+povar_status povar_set_state(povar_problem pb, const double* cams, double lambda, int32_t iter) try {
   if (!pb || !cams || !(lambda > 0.0) || iter < 0) return POVAR_EINVAL;
   if (pb->rec.stage == 2) {
     set_error(pb->ctx, "povar_set_state restores first-stage problems (their landmarks follow from the cameras)");
@@ -1721,10 +1728,10 @@ povar_status povar_set_state(povar_problem pb, const double* cams, double lambda
     return POVAR_ENUMERIC;
   }
   return POVAR_OK;
-}
+} POVAR_HOST_CATCH(pb ? pb->ctx : nullptr)
 
 povar_status povar_debug_linearize(povar_problem pb, double* U, double* bp, double* g, double* Vp, double* X,
-                                   double* z0, double* cost) {
+                                   double* z0, double* cost) try {
   if (!pb) return POVAR_EINVAL;
   if (pb->rec.stage == 2) {
     set_error(pb->ctx, "povar_debug_linearize is for first-stage problems; use povar_refine_debug_blocks");
@@ -1790,10 +1797,10 @@ povar_status povar_debug_linearize(povar_problem pb, double* U, double* bp, doub
   }
   if (cost) *cost = c.cost;
   return POVAR_OK;
-}
+} POVAR_HOST_CATCH(pb ? pb->ctx : nullptr)
 
 povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, double* dp, double* p_trial,
-                              double* cost_trial) {
+                              double* cost_trial) try {
   if (!pb || !(lambda > 0.0) || order < 0) return POVAR_EINVAL;
   if (pb->rec.stage == 2) {
     set_error(pb->ctx, "povar_debug_step is for first-stage problems; use povar_refine_debug_step");
@@ -1845,9 +1852,9 @@ povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, do
     return POVAR_ENUMERIC;
   }
   return POVAR_OK;
-}
+} POVAR_HOST_CATCH(pb ? pb->ctx : nullptr)
 
-povar_status povar_debug_series(povar_problem pb, const double* x0, int32_t order, double* x_out) {
+povar_status povar_debug_series(povar_problem pb, const double* x0, int32_t order, double* x_out) try {
   if (!pb || !x0 || !x_out || order < 0) return POVAR_EINVAL;
   if (pb->rec.stage == 2) {
     set_error(pb->ctx, "povar_debug_series is for first-stage problems");
@@ -1910,11 +1917,11 @@ povar_status povar_debug_series(povar_problem pb, const double* x0, int32_t orde
     return POVAR_ENUMERIC;
   }
   return POVAR_OK;
-}
+} POVAR_HOST_CATCH(pb ? pb->ctx : nullptr)
 
 // Second stage: the blocks at the current point for damping lambda.
 povar_status povar_refine_debug_blocks(povar_problem pb, double lambda, double* U, double* bp, double* G,
-                                       double* bl, double* cost) {
+                                       double* bl, double* cost) try {
   if (!pb || !(lambda > 0.0)) return POVAR_EINVAL;
   if (pb->rec.stage != 2) {
     set_error(pb->ctx, "povar_refine_debug_blocks needs a second-stage problem");
@@ -1982,11 +1989,11 @@ povar_status povar_refine_debug_blocks(povar_problem pb, double lambda, double* 
   Ctl restore = c;
   HIP_TRY(ctx, write_ctl(pb, &restore));
   return POVAR_OK;
-}
+} POVAR_HOST_CATCH(pb ? pb->ctx : nullptr)
 
 // Second stage: one step at damping lambda and series order `order`.
 povar_status povar_refine_debug_step(povar_problem pb, double lambda, int32_t order, double* dp, double* p_trial,
-                                     double* x_trial, double* cost_trial) {
+                                     double* x_trial, double* cost_trial) try {
   if (!pb || !(lambda > 0.0) || order < 0) return POVAR_EINVAL;
   if (pb->rec.stage != 2) {
     set_error(pb->ctx, "povar_refine_debug_step needs a second-stage problem");
@@ -2035,7 +2042,7 @@ povar_status povar_refine_debug_step(povar_problem pb, double lambda, int32_t or
     return POVAR_ENUMERIC;
   }
   return POVAR_OK;
-}
+} POVAR_HOST_CATCH(pb ? pb->ctx : nullptr)
 
 povar_status povar_kernel_timing(povar_problem pb, int32_t enable) {
   if (!pb) return POVAR_EINVAL;
@@ -2070,7 +2077,7 @@ povar_status povar_problem_info(povar_problem pb, int64_t* n_obs, int64_t* n_pac
 
 povar_status povar_debug_layout_check(int32_t n_cams, int32_t n_pts, int64_t n_obs, const int32_t* cam_idx,
                                       const int32_t* pt_idx, const double* meas, int32_t precision,
-                                      int64_t* out) {
+                                      int64_t* out) try {
   if (precision != POVAR_PREC_FP64 && precision != POVAR_PREC_FP32_BULK) {
     set_error(nullptr, "precision must be POVAR_PREC_FP64 or POVAR_PREC_FP32_BULK");
     return POVAR_EINVAL;
@@ -2080,7 +2087,7 @@ povar_status povar_debug_layout_check(int32_t n_cams, int32_t n_pts, int64_t n_o
   const povar_status st = build_layout(nullptr, n_cams, n_pts, n_obs, cam_idx, pt_idx, meas, fp32, L);
   if (st != POVAR_OK) return st;
   return check_layout(L, cam_idx, pt_idx, meas, fp32, out);
-}
+} POVAR_HOST_CATCH(nullptr)
 
 povar_status povar_problem_layout(povar_problem pb, int32_t* blocked, int32_t* lm_block, int64_t* n_slots,
                                   int64_t* n_runs, int32_t* coop_gather) {

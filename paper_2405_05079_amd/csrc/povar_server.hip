@@ -31,6 +31,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <utility>
 #include <vector>
@@ -249,9 +250,14 @@ void admitter_loop(povar_server_s* sv) {
     povar_status st = POVAR_ESTATE;
     std::string msg = "no staging record free";
     if (k >= 0) {
-      st = problem_init(sv->ctx, std::move(r->layout), r->cams0.data(), &r->opt, sv->admit_stream, pb,
-                        sv->stage_recs + k, r->opt.max_iters);
-      if (st != POVAR_OK) msg = error_text(sv->ctx);
+      try {
+        st = problem_init(sv->ctx, std::move(r->layout), r->cams0.data(), &r->opt, sv->admit_stream, pb,
+                          sv->stage_recs + k, r->opt.max_iters);
+        if (st != POVAR_OK) msg = error_text(sv->ctx);
+      } catch (const std::exception& ex) {
+        st = POVAR_ENOMEM;
+        msg = std::string("host resources exhausted: ") + ex.what();
+      }
     }
     r->cams0.clear();
     r->cams0.shrink_to_fit();
@@ -321,12 +327,22 @@ hipError_t retire(povar_server_s* sv, Group& G, int idx, const Ctl& c) {
   Resident R = G.res[idx];
   auto& r = R.req;
   povar_problem_s* pb = R.pb;
-  std::vector<double> cams((size_t)r->n_p * kCam), pts((size_t)r->n_l * 3), cin((size_t)r->n_p * kCam);
-  hipError_t e = hipMemcpyAsync(cin.data(), pb->rec.P64[c.pcur], cin.size() * 8, hipMemcpyDeviceToHost,
-                                G.stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(G.stream);
-  if (e == hipSuccess) cams_to_caller(pb->L, cin.data(), cams.data(), kCam);
-  povar_status st = e == hipSuccess ? copy_points(pb, c.lcur, pts.data()) : POVAR_EDEVICE;
+  std::vector<double> cams, pts, cin;
+  hipError_t e = hipSuccess;
+  povar_status st = POVAR_OK;
+  try {
+    cams.resize((size_t)r->n_p * kCam);
+    pts.resize((size_t)r->n_l * 3);
+    cin.resize((size_t)r->n_p * kCam);
+  } catch (const std::exception&) {
+    st = POVAR_ENOMEM;   // the request fails; the problem still leaves its group
+  }
+  if (st == POVAR_OK) {
+    e = hipMemcpyAsync(cin.data(), pb->rec.P64[c.pcur], cin.size() * 8, hipMemcpyDeviceToHost, G.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(G.stream);
+    if (e == hipSuccess) cams_to_caller(pb->L, cin.data(), cams.data(), kCam);
+    st = e == hipSuccess ? copy_points(pb, c.lcur, pts.data()) : POVAR_EDEVICE;
+  }
   povar_report rep;
   fill_report(pb, c, 0.0, NAN, &rep);
   const int last = (int)G.res.size() - 1;
@@ -346,8 +362,11 @@ hipError_t retire(povar_server_s* sv, Group& G, int idx, const Ctl& c) {
   r->report = rep;
   r->cams = std::move(cams);
   r->pts = std::move(pts);
-  r->status = (e != hipSuccess || st != POVAR_OK) ? POVAR_EDEVICE : POVAR_OK;
-  if (r->status != POVAR_OK) r->error = e != hipSuccess ? hipGetErrorString(e) : "result copy failed";
+  r->status = st == POVAR_ENOMEM ? POVAR_ENOMEM : (e != hipSuccess || st != POVAR_OK) ? POVAR_EDEVICE : POVAR_OK;
+  if (r->status != POVAR_OK)
+    r->error = st == POVAR_ENOMEM ? "host memory for the result exhausted"
+               : e != hipSuccess  ? hipGetErrorString(e)
+                                  : "result copy failed";
   r->finished = true;
   r->t_finish = sv->now();
   sv->n_resident -= 1;
@@ -515,7 +534,7 @@ void free_server(povar_server_s* sv) {
 
 extern "C" {
 
-povar_status povar_server_create(povar_ctx ctx, uint64_t hbm_budget_bytes, int32_t max_slots, povar_server* out) {
+povar_status povar_server_create(povar_ctx ctx, uint64_t hbm_budget_bytes, int32_t max_slots, povar_server* out) try {
   if (!out) return POVAR_EINVAL;
   *out = nullptr;
   if (!ctx || max_slots <= 0 || hbm_budget_bytes == 0) {
@@ -549,16 +568,30 @@ povar_status povar_server_create(povar_ctx ctx, uint64_t hbm_budget_bytes, int32
     delete sv;
     return POVAR_ENOMEM;
   }
+  try {
+    sv->worker = std::thread(worker_loop, sv);
+    sv->admitter = std::thread(admitter_loop, sv);
+  } catch (const std::system_error& ex) {
+    {
+      std::lock_guard<std::mutex> g(sv->mu);
+      sv->stop = true;
+    }
+    sv->cv.notify_all();
+    sv->admit_cv.notify_all();
+    if (sv->worker.joinable()) sv->worker.join();
+    free_server(sv);
+    delete sv;
+    set_error(ctx, "server threads could not start: %s", ex.what());
+    return POVAR_ENOMEM;
+  }
   ctx->live_problems += 1;
-  sv->worker = std::thread(worker_loop, sv);
-  sv->admitter = std::thread(admitter_loop, sv);
   *out = sv;
   return POVAR_OK;
-}
+} POVAR_HOST_CATCH(ctx)
 
 povar_status povar_server_submit(povar_server sv, int32_t n_cams, int32_t n_pts, int64_t n_obs,
                                  const int32_t* cam_idx, const int32_t* pt_idx, const double* meas,
-                                 const double* cams0, const povar_options* opts, uint64_t* ticket) {
+                                 const double* cams0, const povar_options* opts, uint64_t* ticket) try {
   if (!sv || !ticket) return POVAR_EINVAL;
   const double t_call = sv->now();   // the request's latency includes its layout build
   povar_ctx ctx = sv->ctx;
@@ -598,7 +631,7 @@ povar_status povar_server_submit(povar_server sv, int32_t n_cams, int32_t n_pts,
   }
   sv->cv.notify_one();
   return POVAR_OK;
-}
+} POVAR_HOST_CATCH(sv ? sv->ctx : nullptr)
 
 povar_status povar_server_poll(povar_server sv, uint64_t ticket, povar_report* report, double* cams_out,
                                double* pts_out, double* times) {
