@@ -120,3 +120,43 @@ def test_single_steps_from_oracle_states(ctx):
             assert rp <= 1e-3
     finally:
         gp.close()
+
+
+@pytest.mark.parametrize("key", sorted(golden_traces()))
+def test_fp32_bulk_reaches_the_oracle_final_cost(ctx, key):
+    """FP32-bulk (FP32 series, FP64 landmark and camera blocks and cost)
+    reaches the FP64 oracle's cost after 100 iterations to 1e-6 relative
+    within twice as many iterations, on each of the five 250-camera problems
+    (it takes 95-122 of them)."""
+    g = golden_traces()[key]
+    seed = 0 if key == "2" else int(key.split(".")[1])
+    prob = synth.workload(2, seed)
+    say("FP32-bulk to the oracle's final cost", key)
+    gp = povar.Problem.from_synth(ctx, prob, precision="fp32_bulk", ftol=0.0, max_iters=2 * g["iters"])
+    try:
+        gp.step(2 * g["iters"])
+        cost, _, acc = gp.trace()
+    finally:
+        gp.close()
+    best = np.minimum.accumulate(np.where(acc, cost, np.inf))
+    hit = np.nonzero(best <= g["cost_final"] * (1 + 1e-6))[0]
+    say(f"  reached at iteration {hit[0] + 1 if hit.size else None}")
+    assert hit.size > 0
+
+
+def test_fp32_bulk_steps_hold_at_small_damping(ctx):
+    """At 1,800 cameras (1% outliers) the damping reaches its floor of 1e-12
+    after eight accepted steps.  With U_i formed in FP64 the FP32-bulk steps
+    keep being accepted there as FP64's do (both first reject a step at
+    iteration 29); with U_i formed from FP32 products they failed from
+    iteration 9 on, every other step."""
+    prob = synth.workload(3)
+    say("FP32-bulk at small damping, 1800 cameras")
+    gp = povar.Problem.from_synth(ctx, prob, precision="fp32_bulk", ftol=0.0, max_iters=24)
+    try:
+        gp.step(24)
+        _, lam, acc = gp.trace()
+    finally:
+        gp.close()
+    assert lam.min() == 1e-12          # the floor was reached
+    assert acc.all(), np.nonzero(~acc)[0]
