@@ -494,6 +494,35 @@ def copy_calibration(nbytes: int):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}))
 
 
+def stream_copy_gbps(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Achievable HBM rate of a plain device-to-device copy (HIP's blit
+    kernel): bytes read plus bytes written per second, timed with HIP events
+    over `reps` copies of `nbytes` after three untimed ones."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    e0, e1 = ctypes.c_void_p(), ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(a), ctypes.c_size_t(nbytes)) == 0
+    assert hip.hipMalloc(ctypes.byref(b), ctypes.c_size_t(nbytes)) == 0
+    assert hip.hipEventCreate(ctypes.byref(e0)) == 0 and hip.hipEventCreate(ctypes.byref(e1)) == 0
+    try:
+        for _ in range(3):
+            assert hip.hipMemcpyAsync(b, a, ctypes.c_size_t(nbytes), 3, None) == 0
+        assert hip.hipEventRecord(e0, None) == 0
+        for _ in range(reps):
+            assert hip.hipMemcpyAsync(b, a, ctypes.c_size_t(nbytes), 3, None) == 0
+        assert hip.hipEventRecord(e1, None) == 0
+        assert hip.hipEventSynchronize(e1) == 0
+        ms = ctypes.c_float()
+        assert hip.hipEventElapsedTime(ctypes.byref(ms), e0, e1) == 0
+        return 2.0 * nbytes * reps / (ms.value * 1e-3) / 1e9
+    finally:
+        hip.hipEventDestroy(e0)
+        hip.hipEventDestroy(e1)
+        hip.hipFree(a)
+        hip.hipFree(b)
+
+
 def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, workload, out_path):
     """Per-launch HBM bytes of the series kernels from rocprofv3 counter CSVs:
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) averaged over the kernel's
@@ -705,7 +734,10 @@ def main():
     fp32 = legs["fp32_bulk"]
     b_alg = fp32["alg_bytes_per_order"]
     achieved = b_alg / (fp32["us_per_order"] * 1e-6) / 1e9
+    copy_gbps = stream_copy_gbps()
+    log(f"plain device copy: {copy_gbps:.0f} GB/s (read + write)")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "achievable_copy_GBps": round(copy_gbps, 1),
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": fp32["counter_bytes_per_order"],
                 "unit_of_work": "one series order (landmark pass + camera pass with its combine kernel)",
                 "alg_bytes": b_alg, "us": fp32["us_per_order"],
@@ -744,6 +776,9 @@ def main():
                                f"series order {pw.order}"}
             for prec in ("fp32_bulk", "fp64"):
                 row[prec], _ = series_leg(ctx, pw, prec, args.steps, min(args.warmup, 5), f"workload{w}")
+                cb = row[prec]["counter_bytes_per_order"]
+                row[prec]["counter_rate_of_copy"] = (
+                    round(cb / (row[prec]["us_per_order"] * 1e-6) / (copy_gbps * 1e9), 4) if cb else None)
                 log(f"  {prec}: {row[prec]['iters_per_s']:.2f} iters/s, order {row[prec]['us_per_order']:.1f} us, "
                     f"alg frac {row[prec]['alg_frac_per_order']}")
             if not args.no_matched:
