@@ -676,7 +676,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    # about 12 s of oracle work per timing on the GPU machine's host (all cores, then one)
+    # about 12 s of oracle work per timing on the host of the GPU (all cores, then one)
     ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-matched", action="store_true")
