@@ -448,15 +448,15 @@ povar_status povar_server_poll(povar_server sv, uint64_t ticket, povar_report* r
    (summed over the groups). */
 povar_status povar_server_stats(povar_server sv, int32_t* queued, int32_t* active,
                                 int64_t* finished, int64_t* batch_iters);
-/* Where the worker's time went (seconds since creation, each may be NULL):
+/* Where the server's time went (seconds since creation, each may be NULL):
    seconds[0] the admission thread initialising requests (device allocation,
-   layout upload, initial landmark solve), [1] enqueueing batched launches, [2] waiting for the GPU
-   while no group's read-back had arrived, [3] retiring finished problems and
-   freeing their memory; counts[0] batched iterations summed over the groups,
-   [1] control-block read-backs (a group enqueues up to four iterations per
-   read-back while none of its problems can reach its iteration limit and
-   nothing joined it), [2] requests whose admission the HBM budget
-   deferred. */
+   layout upload, initial landmark solve), [1] the worker enqueueing batched
+   launches, [2] waiting for the GPU while no group's read-back had arrived,
+   [3] retiring finished problems and freeing their memory; counts[0] batched
+   iterations summed over the groups, [1] control-block read-backs (a group
+   enqueues up to four iterations per read-back while none of its problems
+   can reach its iteration limit and no admitted request waits to join it),
+   [2] requests whose admission the HBM budget deferred. */
 povar_status povar_server_profile(povar_server sv, double* seconds, int64_t* counts);
 /* Waits for the worker to drain nothing: pending requests are dropped. */
 povar_status povar_server_destroy(povar_server sv);
