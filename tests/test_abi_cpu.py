@@ -132,3 +132,27 @@ def test_layout_on_edge_shapes():
         info = povar.layout_check(p.cam_idx, p.pt_idx, p.meas, p.n_cams, p.n_pts, prec)
         assert info["n_chunks"] == 1 + 2 + 2 + 77
         assert not info["blocked"]
+
+
+def test_host_memory_exhaustion_is_an_error_status():
+    """A host allocation that fails inside the library comes back as
+    POVAR_ENOMEM with a message, not as an exception through the C ABI: a
+    layout of two billion points under a 6 GiB address-space limit (in a
+    child process)."""
+    import subprocess
+    import sys
+    code = (
+        "import resource, sys, ctypes\n"
+        "resource.setrlimit(resource.RLIMIT_AS, (6 << 30, 6 << 30))\n"
+        f"sys.path.insert(0, {ROOT!r})\n"
+        "import numpy as np\n"
+        "from paper_2405_05079_amd import povar\n"
+        "L = povar.lib()\n"
+        "cam = np.zeros(1, np.int32); pt = np.zeros(1, np.int32); m = np.zeros(2)\n"
+        "out = (ctypes.c_int64 * 8)()\n"
+        "st = L.povar_debug_layout_check(1, 2_000_000_000, 1, cam.ctypes.data, pt.ctypes.data, m.ctypes.data, 1, out)\n"
+        "print(st, L.povar_last_error(None).decode())\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    st, msg = r.stdout.strip().split(" ", 1)
+    assert int(st) == povar.ENOMEM and "host resources exhausted" in msg
