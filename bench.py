@@ -640,12 +640,15 @@ def cpu_baseline(ctx, prob, iters: int):
 
 def critical_errors(ctx, prob, O, lam=1e-3):
     """Relative errors of the GPU against the oracle at the initial state:
-    V_j^+ (per landmark, Frobenius), U_i (per camera, Frobenius), the cost,
+    V_j^+ (per landmark, Frobenius), U_i and the damped camera block inverse
+    K_i = B_i (B_i^T U_i,lambda B_i)^-1 B_i^T (per camera, Frobenius), the cost,
     one damped camera step of the workload's order (per camera, 2-norm) and
     the cost at its trial cameras; max and median over landmarks / cameras."""
     P, X, f = O.initial_state(prob, prob.cams0)
     lin = O.linearize(P, X, prob)
     ref_step = O.camera_step(P, lin, lam, prob.order)
+    rs = O.reduced_system(P, lin, lam)
+    ref_K = np.einsum("nik,nkl,njl->nij", rs.B, np.linalg.inv(rs.Ut), rs.B)
     Pn = O.retract(P, ref_step)
     Xn, _ = O.solve_landmarks(Pn, prob)
     f_trial = O.cost(Pn, Xn, prob)
@@ -659,11 +662,12 @@ def critical_errors(ctx, prob, O, lam=1e-3):
     for prec in ("fp32_bulk", "fp64"):
         gp = povar.Problem.from_synth(ctx, prob, precision=prec)
         d = gp.debug_linearize()
+        K = gp.debug_camera_blocks(lam)
         dp, _, ct = gp.debug_step(lam, prob.order)
         gp.close()
         out[prec] = {"V_pinv": rel_rows(d["Vp"], lin.Vp), "U": rel_rows(d["U"], lin.U),
-                     "cost": abs(d["cost"] - lin.cost) / lin.cost, "step": rel_rows(dp, ref_step),
-                     "trial_cost": abs(ct - f_trial) / f_trial}
+                     "K": rel_rows(K, ref_K), "cost": abs(d["cost"] - lin.cost) / lin.cost,
+                     "step": rel_rows(dp, ref_step), "trial_cost": abs(ct - f_trial) / f_trial}
     return out
 
 

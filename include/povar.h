@@ -243,6 +243,17 @@ povar_status povar_debug_linearize(povar_problem pb, double* U, double* bp, doub
    cameras, cost_trial the cost after re-solving the landmarks there. */
 povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, double* dp,
                               double* p_trial, double* cost_trial);
+/* The damped camera block inverses at the current linearisation and damping
+   `lambda`, without changing the solver state: K (n_cams x 144, host, caller's
+   order, each block 12 x 12 row-major) receives K_i = B_i (B_i^T U_i,lambda
+   B_i)^-1 B_i^T with B_i an orthonormal basis of the tangent space of camera
+   i's unit sphere, i.e. the inverse of the camera block of Eq. (22) mapped
+   back to the ambient space (Sec. 4.3); U_i,lambda = U_i + lambda diag(U_i)
+   (Sec. 5.2), its diagonal floored at 1e-12 of its largest entry.  K_i =
+   U_i,lambda^-1 in Euclidean mode.  Formed in FP64 in both precisions.
+   POVAR_ESTATE on a finished or second-stage problem, POVAR_ENUMERIC (K of
+   that camera zero) if a damped block could not be factored. */
+povar_status povar_debug_camera_blocks(povar_problem pb, double lambda, double* K);
 /* The truncated power series of Eq. (17) from a caller-supplied start, at
    the current linearisation and damping (the problem's lambda for its next
    step): x_out = sum_{t=0..order} M^t x0 with M = K W V^+ W^T, K the damped

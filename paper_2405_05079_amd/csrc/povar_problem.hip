@@ -1854,6 +1854,42 @@ povar_status povar_debug_step(povar_problem pb, double lambda, int32_t order, do
   return POVAR_OK;
 } POVAR_HOST_CATCH(pb ? pb->ctx : nullptr)
 
+povar_status povar_debug_camera_blocks(povar_problem pb, double lambda, double* K) try {
+  if (!pb || !K || !(lambda > 0.0)) return POVAR_EINVAL;
+  if (pb->rec.stage == 2) {
+    set_error(pb->ctx, "povar_debug_camera_blocks is for first-stage problems; use povar_refine_debug_blocks");
+    return POVAR_ESTATE;
+  }
+  povar_ctx ctx = pb->ctx;
+  (void)hipSetDevice(ctx->device);
+  Ctl c;
+  HIP_TRY(ctx, read_ctl(pb, &c));
+  if (c.done) {
+    set_error(ctx, "problem has finished; camera-block hooks need a running problem");
+    return POVAR_ESTATE;
+  }
+  const Ctl saved = c;
+  c.lambda = lambda;
+  c.status = 0;
+  HIP_TRY(ctx, write_ctl(pb, &c));
+  HIP_TRY(ctx, launch_linearize(pb->batch, pb->fp32, 0, pb->stream));
+  HIP_TRY(ctx, launch_camera_prep(pb->batch, pb->fp32, pb->stream));
+  Ctl after;
+  HIP_TRY(ctx, read_ctl(pb, &after));
+  std::vector<double> k((size_t)pb->L.n_p * kCamMat);
+  HIP_TRY(ctx, hipMemcpyAsync(k.data(), pb->rec.K64, k.size() * 8, hipMemcpyDeviceToHost, pb->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(pb->stream));
+  cams_to_caller(pb->L, k.data(), K, kCamMat);
+  Ctl restore = saved;
+  restore.need_lin = 0;   // the linearisation at the current cameras is in place
+  HIP_TRY(ctx, write_ctl(pb, &restore));
+  if (after.status & 1) {
+    set_error(ctx, "a damped camera block could not be factored at this damping");
+    return POVAR_ENUMERIC;
+  }
+  return POVAR_OK;
+} POVAR_HOST_CATCH(pb ? pb->ctx : nullptr)
+
 povar_status povar_debug_series(povar_problem pb, const double* x0, int32_t order, double* x_out) try {
   if (!pb || !x0 || !x_out || order < 0) return POVAR_EINVAL;
   if (pb->rec.stage == 2) {

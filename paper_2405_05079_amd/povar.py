@@ -29,7 +29,8 @@ EXPORTS = [
     "povar_problem_footprint", "povar_problem_create", "povar_problem_create_device",
     "povar_problem_destroy", "povar_solve", "povar_step", "povar_enqueue", "povar_get_report",
     "povar_get_cameras", "povar_get_points", "povar_get_trace", "povar_get_state", "povar_set_state",
-    "povar_debug_linearize", "povar_debug_step", "povar_debug_layout_check", "povar_kernel_timing", "povar_kernel_times",
+    "povar_debug_linearize", "povar_debug_step", "povar_debug_camera_blocks", "povar_debug_layout_check",
+    "povar_kernel_timing", "povar_kernel_times",
     "povar_problem_info", "povar_problem_layout", "povar_server_create", "povar_server_submit", "povar_server_poll",
     "povar_server_stats", "povar_server_destroy", "povar_refine_create", "povar_get_points_h",
     "povar_refine_debug_blocks", "povar_refine_debug_step", "povar_metric_upgrade", "povar_metric_debug_reduced",
@@ -106,6 +107,7 @@ def lib() -> C.CDLL:
         "povar_set_state": (C.c_int, [_P, _P, C.c_double, C.c_int32]),
         "povar_debug_linearize": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _DP]),
         "povar_debug_step": (C.c_int, [_P, C.c_double, C.c_int32, _P, _P, _DP]),
+        "povar_debug_camera_blocks": (C.c_int, [_P, C.c_double, _P]),
         "povar_debug_layout_check": (C.c_int, [C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, C.c_int32, _I64P]),
         "povar_kernel_timing": (C.c_int, [_P, C.c_int32]),
         "povar_kernel_times": (C.c_int, [_P, _DP, _I64P, _DP, _I64P]),
@@ -419,6 +421,12 @@ class Problem:
         self._chk(lib().povar_debug_step(self.handle, float(lam), int(order), _ptr(dp), _ptr(pt), C.byref(ct)),
                   "povar_debug_step")
         return dp, pt, ct.value
+
+    def debug_camera_blocks(self, lam: float) -> np.ndarray:
+        """The damped camera block inverses K_i (n_cams, 12, 12) at damping `lam`."""
+        K = np.empty((self.n_cams, 12, 12))
+        self._chk(lib().povar_debug_camera_blocks(self.handle, float(lam), _ptr(K)), "povar_debug_camera_blocks")
+        return K
 
     def kernel_timing(self, enable: bool):
         self._chk(lib().povar_kernel_timing(self.handle, 1 if enable else 0), "povar_kernel_timing")

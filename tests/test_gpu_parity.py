@@ -118,6 +118,57 @@ def test_camera_step_fp64(ctx, kw, lam, order, manifold):
     gp.close()
 
 
+def oracle_K(P, lin, lam, manifold):
+    """K_i = B_i (B_i^T U_i,lambda B_i)^-1 B_i^T from the oracle's tangent basis."""
+    rs = O.reduced_system(P, lin, lam, manifold)
+    return np.einsum("nik,nkl,njl->nij", rs.B, np.linalg.inv(rs.Ut), rs.B)
+
+
+@pytest.mark.parametrize("manifold", ["sphere", "euclidean"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_bulk"])
+@pytest.mark.parametrize("lam", [1e-4, 1e-2, 1.0])
+@pytest.mark.parametrize("kw", CASES[:3])
+def test_camera_block_inverses(ctx, kw, lam, prec, manifold):
+    """The FP64 damped camera block inverses (Sec. 4.3, Eq. (22)) of both
+    precisions against the oracle's, camera by camera, within the first-order
+    perturbation bound of an inverse: |dK|_2 <= 2 |K|_2^2 ((1 + lam) |dU|_F +
+    2 n^2 eps |U_lam|_2), dU the GPU's U_i minus the oracle's (itself held to
+    rounding level by the linearisation tests) and the second term the
+    backward error of a 12 x 12 Cholesky factorisation and inversion."""
+    prob = case(**kw)
+    say("camera blocks", kw, lam, prec, manifold)
+    gp = povar.Problem.from_synth(ctx, prob, precision=prec, manifold=manifold)
+    U = gp.debug_linearize()["U"]
+    K = gp.debug_camera_blocks(lam)
+    gp.close()
+    P, X, f = O.initial_state(prob, prob.cams0, manifold)
+    lin = O.linearize(P, X, prob)
+    Kr = oracle_K(P, lin, lam, manifold)
+    nK = np.linalg.norm(Kr, 2, axis=(1, 2))
+    dU = np.linalg.norm((U - lin.U).reshape(len(U), -1), axis=1)
+    nUl = np.linalg.norm(O.damped(lin.U, lam), 2, axis=(1, 2))
+    bound = 2 * nK ** 2 * ((1 + lam) * dU + 2 * 144 * np.finfo(float).eps * nUl)
+    assert rel_rows(U.reshape(-1, 144), lin.U.reshape(-1, 144)) < 1e-10   # so the bound stays tight
+    err = np.linalg.norm(K - Kr, 2, axis=(1, 2))
+    assert (err <= bound).all(), (err / bound).max()
+    np.testing.assert_array_equal(K, K.transpose(0, 2, 1))      # stored from one triangle
+    if manifold == "sphere":                                     # K_i maps into the tangent space of p_i
+        assert (np.abs(np.einsum("ni,nij->nj", P, K)).max(axis=1) <= 1e-12 * nK).all()
+
+
+def test_camera_block_hook_keeps_the_solver_state(ctx):
+    prob = case(**CASES[0])
+    say("camera-block hook then solve")
+    gp = povar.Problem.from_synth(ctx, prob, precision="fp64", max_iters=6, ftol=0.0)
+    gp.debug_camera_blocks(0.5)
+    gp.solve()
+    cost, lam, acc = gp.trace()
+    gp.close()
+    ref = O.lm_solve(prob, opts=O.Options(order=prob.order, max_iters=6, ftol=0.0))
+    assert list(acc) == ref.trace_accept
+    np.testing.assert_allclose(cost, ref.trace_cost, rtol=1e-9)
+
+
 # 400 cameras: camera records of 128 bytes (more than the vector L1 holds
 # packed), which the landmark pass gathers cooperatively
 FP32_STEP = [CASES[1], dict(n_cams=400, n_pts=8000, track=("uniform", 3, 6), seed=36)]
