@@ -24,6 +24,8 @@ from oracle import povar_oracle as O
 from oracle import ripoba_oracle as R
 from paper_2405_05079_amd import povar, synth
 
+from camera_blocks import err_over_bound, oracle_K
+
 pytestmark = pytest.mark.gpu
 
 # (V^+, U, cost, step, trial cost) relative-error bounds: FP64 at rounding
@@ -71,6 +73,9 @@ def test_full_size_250_cameras(ctx, w2, prec):
         assert rel_rows(d["X"], X).max() < t_vp
         assert rel_rows(d["U"], lin.U).max() < t_u
         assert abs(d["cost"] - lin.cost) / lin.cost < t_f
+        P = prob.cams0 / np.linalg.norm(prob.cams0, axis=1, keepdims=True)   # the initial cameras
+        K = gp.debug_camera_blocks(1e-3)
+        assert err_over_bound(K, oracle_K(P, lin.U, 1e-3), d["U"], lin.U, 1e-3).max() <= 1.0
         dp, pt, ct = gp.debug_step(1e-3, prob.order)
         assert rel_rows(dp, step).max() < t_step
         assert abs(ct - f_trial) / f_trial < t_trial
@@ -125,6 +130,10 @@ def test_full_size_1800_cameras_sampled(ctx, w3, prec):
         Xs, _ = O.solve_landmarks(P, sub)
         lin_s = O.linearize(P, Xs, sub)
         assert rel_rows(d["U"][cams], lin_s.U[cams]).max() < t_u
+        # their damped block inverses (the landmark-blocked camera sums)
+        K = gp.debug_camera_blocks(1e-3)[cams]
+        Kr = oracle_K(P[cams], lin_s.U[cams], 1e-3)
+        assert err_over_bound(K, Kr, d["U"][cams], lin_s.U[cams], 1e-3).max() <= 1.0
         # properties at any size: the step lies in each camera's tangent space
         # and the trial cameras have unit norm; iterations never raise the cost
         dp, pt, ct = gp.debug_step(1e-3, prob.order)
