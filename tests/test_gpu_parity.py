@@ -121,7 +121,7 @@ def test_camera_step_fp64(ctx, kw, lam, order, manifold):
 
 @pytest.mark.parametrize("manifold", ["sphere", "euclidean"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32_bulk"])
-@pytest.mark.parametrize("lam", [1e-4, 1e-2, 1.0])
+@pytest.mark.parametrize("lam", [1e-12, 1e-4, 1e-2, 1.0])
 @pytest.mark.parametrize("kw", CASES[:3])
 def test_camera_block_inverses(ctx, kw, lam, prec, manifold):
     """The FP64 damped camera block inverses (Sec. 4.3, Eq. (22)) of both
