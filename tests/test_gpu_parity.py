@@ -511,3 +511,21 @@ def test_invalid_inputs_are_rejected(ctx):
     for r in (-0.1, 1.0, float("nan")):
         with pytest.raises(povar.PovarError):
             povar.Problem.from_synth(ctx, prob, series_rtol=r)
+
+
+def test_camera_block_hook_rejects_bad_calls(ctx):
+    prob = case(**CASES[0])
+    say("camera-block hook errors")
+    gp = povar.Problem.from_synth(ctx, prob, precision="fp64", max_iters=2, ftol=0.0)
+    try:
+        for lam in (0.0, -1.0, float("nan")):
+            with pytest.raises(povar.PovarError) as e:
+                gp.debug_camera_blocks(lam)
+            assert e.value.status == povar.EINVAL
+        # a spent iteration budget does not finish a problem (only a stop
+        # test does): the hook still answers, at the new cameras
+        gp.solve()
+        K = gp.debug_camera_blocks(1e-3)
+        assert np.isfinite(K).all() and np.abs(K).max() > 0.0
+    finally:
+        gp.close()
